@@ -1,0 +1,161 @@
+/*
+ * ilt.h -- C ABI of the MI355X (gfx950) level-set ILT hot path.
+ *
+ * The operations follow DevelSet (Chen et al., arXiv 2303.12529):
+ *   forward lithography   Sec. II-B (Hopkins / truncated SOCS sum
+ *                         I = sum_k w_k |M (*) h_k|^2, N_k = 24 kernels);
+ *   resist and loss       Sec. III-A (sigmoid resist, L_ilt, L_pvb, L_DSO)
+ *                         and Sec. II-C (binary print, squared L2, PVBand);
+ *   adjoint gradient      Sec. III-A (dL_ilt/dM through the rotated and
+ *                         conjugated kernels; dL_pvb/dM likewise);
+ *   level-set step        Sec. II-A (explicit update of phi), Sec. III-A
+ *                         (velocity = the ILT gradient, curvature term,
+ *                         central differences and numeric curvature),
+ *                         Sec. III-C (CFL time step eta / max|v|);
+ *   re-initialisation     Sec. II-A (signed distance function), Sec. III-A
+ *                         (TSDF clip to [D_l, D_u]) and Alg. 1 (CUDA_TSDF);
+ *   the loop              Sec. III-A/B (DSO) and Fig. "DevelSet flow".
+ *
+ * Conventions shared by every call
+ *   - Images are N x N, row-major [y][x], contiguous, 4-byte floats unless
+ *     stated; every device pointer must be 16-byte aligned (torch tensors are).
+ *   - "d_" pointers are device memory on the context's device; "h_" pointers
+ *     are host memory.  The caller owns all of them; the library never frees
+ *     or retains them beyond the call.
+ *   - Work is enqueued on the context's stream and is asynchronous unless a
+ *     call says otherwise.  One context must not be used from two host
+ *     threads at once; calls on one context are ordered by its stream.
+ *   - Frequency convention: forward DFT unnormalised, inverse with 1/N^2.
+ *     A kernel is given by its frequency samples Hhat[a][b] on a P x P
+ *     window, P odd, with (f_y, f_x) = (a - c, b - c), c = (P-1)/2, in units
+ *     of 1/(N pitch).  The clear-field intensity is sum_k w_k |Hhat_k[c][c]|^2.
+ *   - Return value: ILT_OK or a negative ILT_E* code; arguments are checked
+ *     before anything is launched.  ilt_last_error() gives a message.
+ */
+#ifndef ILT_H
+#define ILT_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ilt_ctx ilt_ctx;
+
+enum {
+    ILT_OK = 0,
+    ILT_EINVAL = -1,       /* bad argument (null, size, range, alignment)     */
+    ILT_ENOMEM = -2,       /* device allocation at create time failed         */
+    ILT_EDEVICE = -3,      /* a HIP runtime call failed                       */
+    ILT_ENUMERIC = -4,     /* non-finite loss or gradient detected            */
+    ILT_EUNSUPPORTED = -5  /* valid but not built for (e.g. P too large)      */
+};
+
+enum { ILT_FP32 = 0 };
+
+/* Optical model, read at create time and copied to the device. */
+typedef struct {
+    int N;                  /* grid side, 16 <= N <= 4096                     */
+    int P;                  /* odd window side, 1 <= P <= 35, 2P-1 <= N       */
+    int K;                  /* kernels per set, 1 <= K <= 64                  */
+    int n_sets;             /* focus conditions (kernel sets), 1 <= n <= 4    */
+    int precision;          /* ILT_FP32                                       */
+    const double *h_kernels;/* host [n_sets][K][P][P][2] (re, im)             */
+    const double *h_weights;/* host [n_sets][K], each >= 0                    */
+} ilt_optics;
+
+/* A process corner: resist sees dose * I_set; loss weight omega. */
+typedef struct { int set; float dose; float omega; } ilt_corner;
+
+typedef struct {
+    int iters;              /* DSO iterations T                               */
+    int reinit_every;       /* R: TSDF re-initialisation after steps i with
+                               (i+1) % R == 0; 0 = never                      */
+    int dt_mode;            /* 0: dt = eta / max|g| (CFL), 1: dt = eta        */
+    int init_mode;          /* ilt_solve: 0 = phi0 = TSDF(target), 1 = use the
+                               caller's phi as phi0                           */
+    float eta;              /* CFL number (dt_mode 0) or fixed dt (1)         */
+    float dt_max;           /* cap on dt in CFL mode; <= 0: no cap            */
+    float lambda;           /* curvature weight                               */
+    float sigma_z;          /* sigmoid steepness                              */
+    float i_th;             /* resist threshold                               */
+    float eps_kappa;        /* added to |grad phi|^2 in the curvature ratio   */
+    float d_lower;          /* TSDF clip bounds, pixels (D_l < 0 < D_u)       */
+    float d_upper;
+    int n_corners;          /* 1..4; corner 0 = nominal (L2 metric); with 3
+                               corners, 1 and 2 are the PVBand extremes       */
+    ilt_corner corners[4];
+} ilt_params;
+
+typedef struct {
+    int iters_done;
+    int status;
+    double loss;            /* L_DSO of the final mask                        */
+    long long l2;           /* squared L2 (pixels) of the final nominal print */
+    long long pvb;          /* PVBand (pixels) of the final mask              */
+    long long flips;        /* mask pixels flipped by the last step           */
+} ilt_report;
+
+/* Create a context on the current HIP device.  Copies the kernels, builds
+ * the DFT tables (FP64 on the host, rounded once to FP32) and allocates all
+ * workspaces; nothing is allocated after this.  stream: a hipStream_t
+ * (NULL = the default stream).  max_batch: reserved, pass 1. */
+int ilt_create(ilt_ctx **out, const ilt_optics *optics, int max_batch, void *stream);
+int ilt_destroy(ilt_ctx *ctx);
+/* Thread-local message for the last non-OK status of this thread. */
+const char *ilt_last_error(void);
+/* Grid side and window of a context (for bindings). */
+int ilt_get_dims(const ilt_ctx *ctx, int *N, int *P, int *K, int *n_sets);
+
+/* Sec. II-B: aerial image of kernel set `set` for a real-valued mask.
+ * d_mask [N][N] (any real values), d_aerial [N][N] out.  Async. */
+int litho_forward(ilt_ctx *ctx, const float *d_mask, int set, float *d_aerial);
+
+/* Sec. III-A (ILT gradient): dL/dM = 2 sum_k w_k Re T_k^H (G . T_k M) for a
+ * loss with dL/dI = G on kernel set `set` (T_k M = field of kernel k).
+ * d_mask, d_dL_dI [N][N] in; d_dL_dM [N][N] out (overwritten).  Async. */
+int litho_adjoint(ilt_ctx *ctx, const float *d_mask, const float *d_dL_dI, int set,
+                  float *d_dL_dM);
+
+/* Sec. III-A: sigmoid resist per corner, L_DSO = sum_c omega_c sum (Z_c - Z_t)^2,
+ * G_s = dL/dI_s, and the binary-print L2 / PVBand counts.
+ * d_aerial [n_sets][N][N] in (only sets used by a corner are read);
+ * d_target [N][N] bytes (0/1); d_G [n_sets][N][N] out (sets not used by any
+ * corner are zero-filled); d_stats: NULL or device double[4] =
+ * {loss, l2, pvb, non-finite count}.  Async. */
+int resist_loss(ilt_ctx *ctx, const float *d_aerial, const unsigned char *d_target,
+                const ilt_params *params, float *d_G, double *d_stats);
+
+/* Sec. II-A / III-A / III-C: one DSO evolution step, in place on d_phi:
+ *   phi += dt * (v |grad phi| + lambda * m * K),
+ * K = (phi_xx phi_y^2 - 2 phi_x phi_y phi_xy + phi_yy phi_x^2)/(phi_x^2+phi_y^2+eps),
+ * central differences with replicated borders, v = d_vel = dL/dM (descent
+ * sign), m = d_mod or 1 if NULL, dt from params (CFL uses max|v|, computed on
+ * the device).  d_stats: NULL or device double[4] = {max|v|, dt, flips, 0}.
+ * Async. */
+int levelset_step(ilt_ctx *ctx, float *d_phi, const float *d_vel, const float *d_mod,
+                  const ilt_params *params, double *d_stats);
+
+/* Sec. II-A, III-A (TSDF), Alg. 1: truncated signed distance of a mask.
+ * Exactly one of d_phi (mask = [phi <= 0]) and d_mask (bytes, nonzero = 1)
+ * is non-NULL.  Squared distances between pixel centres are exact integers:
+ * phi = sqrt(D_in) - 1/2 outside, 1/2 - sqrt(D_out) inside, correctly rounded
+ * to FP32, clipped to [d_lower, d_upper] from params.  d_phi_out [N][N] out
+ * (may equal d_phi).  d_sqdist: NULL or device int32 [2][N][N] = {D_in, D_out}
+ * (squared distance to the nearest inside / outside pixel; INT32_MAX when
+ * that class is absent).  Async. */
+int edt_reinit(ilt_ctx *ctx, const float *d_phi, const unsigned char *d_mask,
+               float *d_phi_out, int *d_sqdist, const ilt_params *params);
+
+/* Sec. III-A/B: the plain DSO loop, params->iters iterations, entirely on the
+ * device.  d_target [N][N] bytes; d_phi [N][N] in (used when init_mode = 1)
+ * and out (final phi).  h_report: final loss / L2 / PVB of [phi_T <= 0].
+ * d_trace: NULL or device double [iters][8] rows
+ *   {i, loss, l2, pvb, flips, max|g|, dt, device time (ns)}.
+ * Synchronous: waits for the stream once at the end. */
+int ilt_solve(ilt_ctx *ctx, const unsigned char *d_target, float *d_phi,
+              const ilt_params *params, ilt_report *h_report, double *d_trace);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ILT_H */

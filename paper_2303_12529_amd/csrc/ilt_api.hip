@@ -1,0 +1,418 @@
+// Host side of the C ABI declared in include/ilt.h: context creation (DFT
+// tables built in FP64 and rounded once to FP32, kernels copied to the
+// device, all workspaces allocated up front), argument checks, and the
+// stream-ordered sequences behind each entry point.
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdint>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "ilt_internal.h"
+
+void set_ns_per_tick(double v);
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+int fail(int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIPCHK(expr)                                                                             \
+    do {                                                                                         \
+        hipError_t e_ = (expr);                                                                  \
+        if (e_ != hipSuccess) return fail(ILT_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+int pick_kp(int P) {
+    if (2 * P <= 8) return 8;
+    if (2 * P <= 24) return 24;
+    if (2 * P <= 40) return 40;
+    return 72;
+}
+int round_up(int v, int m) { return (v + m - 1) / m * m; }
+
+bool aligned(const void *p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
+
+template <typename T>
+hipError_t dalloc(T **p, size_t n) {
+    void *v = nullptr;
+    hipError_t e = hipMalloc(&v, std::max<size_t>(n, 1) * sizeof(T));
+    if (e != hipSuccess) return e;
+    e = hipMemset(v, 0, std::max<size_t>(n, 1) * sizeof(T));
+    *p = static_cast<T *>(v);
+    return e;
+}
+
+void free_ctx(ilt_ctx *c) {
+    if (!c) return;
+    void *ptrs[] = {c->tl, c->tb, c->ta4, c->ar, c->ai, c->H, c->sw, c->coef, c->t1, c->S, c->Y, c->Tg,
+                    c->I, c->G, c->g, c->phi2, c->Wpart, c->W, c->edtg, c->part, c->scal};
+    for (void *p : ptrs)
+        if (p) (void)hipFree(p);
+    delete c;
+}
+
+int check_ctx(const ilt_ctx *c) {
+    if (!c) return fail(ILT_EINVAL, "null context");
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev != c->device)
+        return fail(ILT_EINVAL, "context belongs to device %d, current device is %d", c->device, dev);
+    return ILT_OK;
+}
+
+int check_ptr(const void *p, const char *name, size_t align = 4) {
+    if (!p) return fail(ILT_EINVAL, "%s is null", name);
+    if (!aligned(p, align)) return fail(ILT_EINVAL, "%s is not %zu-byte aligned", name, align);
+    return ILT_OK;
+}
+
+int check_params(const ilt_ctx *c, const ilt_params *p, bool need_loop) {
+    if (!p) return fail(ILT_EINVAL, "params is null");
+    if (p->n_corners < 1 || p->n_corners > 4) return fail(ILT_EINVAL, "n_corners must be 1..4");
+    for (int i = 0; i < p->n_corners; ++i) {
+        const ilt_corner &k = p->corners[i];
+        if (k.set < 0 || k.set >= c->n_sets) return fail(ILT_EINVAL, "corner %d uses set %d", i, k.set);
+        if (!(k.dose > 0.f) || !std::isfinite(k.dose) || !(k.omega >= 0.f) || !std::isfinite(k.omega))
+            return fail(ILT_EINVAL, "corner %d has a bad dose or weight", i);
+    }
+    if (!(p->sigma_z > 0.f) || !std::isfinite(p->i_th)) return fail(ILT_EINVAL, "bad resist parameters");
+    if (need_loop) {
+        if (p->iters < 0) return fail(ILT_EINVAL, "iters < 0");
+        if (p->reinit_every < 0) return fail(ILT_EINVAL, "reinit_every < 0");
+    }
+    if (p->dt_mode != 0 && p->dt_mode != 1) return fail(ILT_EINVAL, "dt_mode must be 0 or 1");
+    if (!std::isfinite(p->eta) || p->eta < 0.f) return fail(ILT_EINVAL, "eta must be finite and >= 0");
+    if (!std::isfinite(p->lambda) || !(p->eps_kappa >= 0.f)) return fail(ILT_EINVAL, "bad lambda / eps_kappa");
+    if (!(p->d_lower < 0.f) || !(p->d_upper > 0.f)) return fail(ILT_EINVAL, "need d_lower < 0 < d_upper");
+    return ILT_OK;
+}
+
+resist_args make_resist_args(const ilt_params *p) {
+    resist_args ra{};
+    ra.n_corners = p->n_corners;
+    for (int i = 0; i < 4; ++i) {
+        ra.cset[i] = i < p->n_corners ? p->corners[i].set : 0;
+        ra.dose[i] = i < p->n_corners ? p->corners[i].dose : 1.f;
+        ra.omega[i] = i < p->n_corners ? p->corners[i].omega : 0.f;
+    }
+    for (int s = 0; s < ILT_MAX_SETS; ++s) ra.set_used[s] = 0;
+    for (int i = 0; i < p->n_corners; ++i) ra.set_used[p->corners[i].set] = 1;
+    ra.sigma_z = p->sigma_z;
+    ra.i_th = p->i_th;
+    return ra;
+}
+
+void used_set_range(const ilt_params *p, int *lo, int *hi) {
+    int a = 1 << 30, b = -1;
+    for (int i = 0; i < p->n_corners; ++i) {
+        a = std::min(a, p->corners[i].set);
+        b = std::max(b, p->corners[i].set);
+    }
+    *lo = a;
+    *hi = b + 1;
+}
+
+// partial-buffer regions (doubles)
+size_t part_resist_off(const ilt_ctx *) { return 0; }
+size_t part_max_off(const ilt_ctx *c) { return 4 * (size_t)resist_blocks(c); }
+size_t n_image_blocks(const ilt_ctx *c) { return (size_t)(c->Np / 64) * (c->Np / 128); }
+size_t part_step_off(const ilt_ctx *c) {
+    return part_max_off(c) + std::max<size_t>(n_image_blocks(c), (size_t)gradmax_blocks(c));
+}
+size_t part_total(const ilt_ctx *c) { return part_step_off(c) + (size_t)step_blocks(c); }
+
+}  // namespace
+
+// ------------------------------------------------------------------ C ABI
+
+extern "C" const char *ilt_last_error(void) { return g_err.c_str(); }
+
+extern "C" int ilt_get_dims(const ilt_ctx *c, int *N, int *P, int *K, int *n_sets) {
+    if (!c) return fail(ILT_EINVAL, "null context");
+    if (N) *N = c->N;
+    if (P) *P = c->P;
+    if (K) *K = c->K;
+    if (n_sets) *n_sets = c->n_sets;
+    return ILT_OK;
+}
+
+extern "C" int ilt_create(ilt_ctx **out, const ilt_optics *o, int max_batch, void *stream) {
+    if (!out) return fail(ILT_EINVAL, "out is null");
+    *out = nullptr;
+    if (!o) return fail(ILT_EINVAL, "optics is null");
+    if (max_batch != 1) return fail(ILT_EUNSUPPORTED, "max_batch must be 1");
+    const int N = o->N, P = o->P, K = o->K, ns = o->n_sets;
+    if (N < 16 || N > ILT_MAX_N) return fail(ILT_EINVAL, "N=%d outside [16, %d]", N, ILT_MAX_N);
+    if (P < 1 || P % 2 == 0) return fail(ILT_EINVAL, "P=%d must be odd and positive", P);
+    if (P > ILT_MAX_P) return fail(ILT_EUNSUPPORTED, "P=%d above the built maximum %d", P, ILT_MAX_P);
+    if (2 * P - 1 > N) return fail(ILT_EINVAL, "window 2P-1=%d exceeds N=%d", 2 * P - 1, N);
+    if (K < 1 || K > ILT_MAX_K) return fail(ILT_EINVAL, "K=%d outside [1, %d]", K, ILT_MAX_K);
+    if (ns < 1 || ns > ILT_MAX_SETS) return fail(ILT_EINVAL, "n_sets=%d outside [1, %d]", ns, ILT_MAX_SETS);
+    if (o->precision != ILT_FP32) return fail(ILT_EUNSUPPORTED, "precision %d not built", o->precision);
+    if (!o->h_kernels || !o->h_weights) return fail(ILT_EINVAL, "kernels or weights are null");
+    for (int i = 0; i < ns * K; ++i)
+        if (!(o->h_weights[i] >= 0.0) || !std::isfinite(o->h_weights[i]))
+            return fail(ILT_EINVAL, "weight %d is negative or not finite", i);
+    for (size_t i = 0; i < (size_t)ns * K * P * P * 2; ++i)
+        if (!std::isfinite(o->h_kernels[i])) return fail(ILT_EINVAL, "kernel entry %zu is not finite", i);
+
+    ilt_ctx *c = new ilt_ctx();
+    std::memset(c, 0, sizeof *c);
+    c->N = N; c->P = P; c->K = K; c->n_sets = ns; c->precision = o->precision;
+    c->Np = round_up(N, 128);
+    c->KP = pick_kp(P);
+    c->ZO = round_up(P, 16);
+    c->NZ = 2 * c->ZO;
+    c->AP = c->ZO;
+    c->stream = static_cast<hipStream_t>(stream);
+    if (hipGetDevice(&c->device) != hipSuccess) { free_ctx(c); return fail(ILT_EDEVICE, "hipGetDevice failed"); }
+    const int Np = c->Np, KP = c->KP, NZ = c->NZ, ZO = c->ZO, AP = c->AP;
+
+    // DFT window matrix A[a][x] = exp(-2 pi i ((f_a x) mod N)/N), FP64 then rounded
+    std::vector<float> ar((size_t)P * Np, 0.f), ai((size_t)P * Np, 0.f);
+    const int cc = (P - 1) / 2;
+    for (int a = 0; a < P; ++a) {
+        const long long f = a - cc;
+        for (int x = 0; x < N; ++x) {
+            long long ph = (f * x) % N;
+            if (ph < 0) ph += N;
+            const double ang = -2.0 * M_PI * (double)ph / (double)N;
+            ar[(size_t)a * Np + x] = (float)std::cos(ang);
+            ai[(size_t)a * Np + x] = (float)std::sin(ang);
+        }
+    }
+    std::vector<float> tl((size_t)2 * KP * Np, 0.f), tb((size_t)2 * Np * NZ, 0.f), ta4((size_t)2 * Np * AP, 0.f);
+    for (int r = 0; r < P; ++r)
+        for (int y = 0; y < Np; ++y) {
+            const float c_ = ar[(size_t)r * Np + y], s_ = ai[(size_t)r * Np + y];
+            tl[(size_t)r * Np + y] = c_;                       // L1, real rows
+            tl[(size_t)(P + r) * Np + y] = s_;                 // L1, imaginary rows
+            tl[(size_t)(KP + r) * Np + y] = -s_;               // L2, real rows
+            tl[(size_t)(KP + P + r) * Np + y] = c_;            // L2, imaginary rows
+            tb[(size_t)y * NZ + r] = c_;                       // part 0: Re -> (Re, Im)
+            tb[(size_t)y * NZ + ZO + r] = s_;
+            tb[((size_t)Np + y) * NZ + r] = -s_;               // part 1: Im -> (Re, Im)
+            tb[((size_t)Np + y) * NZ + ZO + r] = c_;
+            ta4[(size_t)y * AP + r] = c_;
+            ta4[((size_t)Np + y) * AP + r] = s_;
+        }
+    std::vector<float2> H((size_t)ns * K * P * P), coef((size_t)ns * K * P * P);
+    std::vector<float> sw((size_t)ns * K);
+    for (int s = 0; s < ns; ++s)
+        for (int k = 0; k < K; ++k) {
+            const double scale = std::sqrt(o->h_weights[s * K + k]) / ((double)N * (double)N);
+            sw[(size_t)s * K + k] = (float)scale;
+            for (int e = 0; e < P * P; ++e) {
+                const size_t i = ((size_t)(s * K + k) * P * P + e);
+                const double hr = o->h_kernels[2 * i], hi = o->h_kernels[2 * i + 1];
+                H[i] = make_float2((float)hr, (float)hi);
+                coef[i] = make_float2((float)(scale * hr), (float)(-scale * hi));
+            }
+        }
+
+    hipError_t e = hipSuccess;
+#define ALLOC(ptr, n) \
+    if (e == hipSuccess) e = dalloc(&c->ptr, (n))
+    ALLOC(tl, tl.size());
+    ALLOC(tb, tb.size());
+    ALLOC(ta4, ta4.size());
+    ALLOC(ar, ar.size());
+    ALLOC(ai, ai.size());
+    ALLOC(H, H.size());
+    ALLOC(coef, coef.size());
+    ALLOC(sw, sw.size());
+    ALLOC(t1, (size_t)Np * NZ);
+    ALLOC(S, (size_t)P * P);
+    ALLOC(W, (size_t)P * P);
+    ALLOC(Y, (size_t)ns * K * KP * Np);
+    ALLOC(Tg, (size_t)KP * Np);
+    ALLOC(I, (size_t)ns * N * N);
+    ALLOC(G, (size_t)ns * N * N);
+    ALLOC(g, (size_t)N * N);
+    ALLOC(phi2, (size_t)N * N);
+    c->n_wpart = ns * ((N + 31) / 32) * ((K + 3) / 4) * P * P * 2;
+    ALLOC(Wpart, (size_t)c->n_wpart);
+    ALLOC(edtg, (size_t)N * N);
+    c->n_part = (int)part_total(c);
+    ALLOC(part, (size_t)c->n_part);
+    ALLOC(scal, (size_t)SC_COUNT);
+#undef ALLOC
+    if (e != hipSuccess) {
+        free_ctx(c);
+        return fail(ILT_ENOMEM, "device allocation failed: %s", hipGetErrorString(e));
+    }
+    if (e == hipSuccess) e = hipMemcpy(c->tl, tl.data(), tl.size() * 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(c->tb, tb.data(), tb.size() * 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(c->ta4, ta4.data(), ta4.size() * 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(c->ar, ar.data(), ar.size() * 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(c->ai, ai.data(), ai.size() * 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(c->H, H.data(), H.size() * 8, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(c->coef, coef.data(), coef.size() * 8, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(c->sw, sw.data(), sw.size() * 4, hipMemcpyHostToDevice);
+    int rate_khz = 0;
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, c->device);
+    if (e != hipSuccess) {
+        free_ctx(c);
+        return fail(ILT_EDEVICE, "context set-up failed: %s", hipGetErrorString(e));
+    }
+    set_ns_per_tick(rate_khz > 0 ? 1.0e6 / rate_khz : 10.0);
+    *out = c;
+    return ILT_OK;
+}
+
+extern "C" int ilt_destroy(ilt_ctx *c) {
+    if (!c) return ILT_OK;
+    (void)hipStreamSynchronize(c->stream);
+    free_ctx(c);
+    return ILT_OK;
+}
+
+extern "C" int litho_forward(ilt_ctx *c, const float *d_mask, int set, float *d_aerial) {
+    int r;
+    if ((r = check_ctx(c))) return r;
+    if ((r = check_ptr(d_mask, "d_mask"))) return r;
+    if ((r = check_ptr(d_aerial, "d_aerial"))) return r;
+    if (set < 0 || set >= c->n_sets) return fail(ILT_EINVAL, "set %d outside [0, %d)", set, c->n_sets);
+    HIPCHK(launch_spectrum(c, d_mask, 0));
+    HIPCHK(launch_make_Y(c, set, set + 1));
+    HIPCHK(launch_image_to(c, set, set + 1, d_aerial));
+    return ILT_OK;
+}
+
+extern "C" int litho_adjoint(ilt_ctx *c, const float *d_mask, const float *d_G, int set, float *d_out) {
+    int r;
+    if ((r = check_ctx(c))) return r;
+    if ((r = check_ptr(d_mask, "d_mask"))) return r;
+    if ((r = check_ptr(d_G, "d_dL_dI"))) return r;
+    if ((r = check_ptr(d_out, "d_dL_dM"))) return r;
+    if (set < 0 || set >= c->n_sets) return fail(ILT_EINVAL, "set %d outside [0, %d)", set, c->n_sets);
+    HIPCHK(launch_spectrum(c, d_mask, 0));
+    HIPCHK(launch_make_Y(c, set, set + 1));
+    HIPCHK(launch_adjoint(c, d_G, 0, set, set + 1));
+    HIPCHK(launch_window_sum(c, set, set + 1));
+    HIPCHK(launch_gradient(c, d_out, c->part + part_max_off(c)));
+    return ILT_OK;
+}
+
+extern "C" int resist_loss(ilt_ctx *c, const float *d_aerial, const unsigned char *d_target,
+                           const ilt_params *p, float *d_G, double *d_stats) {
+    int r;
+    if ((r = check_ctx(c))) return r;
+    if ((r = check_ptr(d_aerial, "d_aerial"))) return r;
+    if ((r = check_ptr(d_target, "d_target", 1))) return r;
+    if ((r = check_ptr(d_G, "d_G"))) return r;
+    if (d_stats && !aligned(d_stats, 8)) return fail(ILT_EINVAL, "d_stats is not 8-byte aligned");
+    if ((r = check_params(c, p, false))) return r;
+    const resist_args ra = make_resist_args(p);
+    const size_t npix = (size_t)c->N * c->N;
+    for (int s = 0; s < c->n_sets; ++s)
+        if (!ra.set_used[s]) HIPCHK(launch_fill(c, d_G + s * npix, 0.f, npix));
+    HIPCHK(launch_resist(c, d_aerial, d_target, ra, d_G, c->part + part_resist_off(c)));
+    HIPCHK(launch_finish_resist(c, c->part + part_resist_off(c), resist_blocks(c), c->scal, d_stats));
+    return ILT_OK;
+}
+
+extern "C" int levelset_step(ilt_ctx *c, float *d_phi, const float *d_vel, const float *d_mod,
+                             const ilt_params *p, double *d_stats) {
+    int r;
+    if ((r = check_ctx(c))) return r;
+    if ((r = check_ptr(d_phi, "d_phi"))) return r;
+    if ((r = check_ptr(d_vel, "d_vel"))) return r;
+    if (d_mod && !aligned(d_mod, 4)) return fail(ILT_EINVAL, "d_mod is not 4-byte aligned");
+    if (d_stats && !aligned(d_stats, 8)) return fail(ILT_EINVAL, "d_stats is not 8-byte aligned");
+    if ((r = check_params(c, p, false))) return r;
+    const size_t npix = (size_t)c->N * c->N;
+    HIPCHK(launch_absmax(c, d_vel, c->part + part_max_off(c)));
+    HIPCHK(launch_finish_dt(c, c->part + part_max_off(c), gradmax_blocks(c), p->dt_mode, p->eta, p->dt_max,
+                            c->scal));
+    HIPCHK(launch_levelset(c, d_phi, d_vel, d_mod, p->lambda, p->eps_kappa, c->scal, c->phi2,
+                           c->part + part_step_off(c)));
+    HIPCHK(launch_copy(c, d_phi, c->phi2, npix));
+    HIPCHK(launch_finish_step(c, c->part + part_step_off(c), step_blocks(c), c->scal, d_stats, nullptr, 0));
+    return ILT_OK;
+}
+
+extern "C" int edt_reinit(ilt_ctx *c, const float *d_phi, const unsigned char *d_mask, float *d_phi_out,
+                          int *d_sqdist, const ilt_params *p) {
+    int r;
+    if ((r = check_ctx(c))) return r;
+    if ((d_phi == nullptr) == (d_mask == nullptr))
+        return fail(ILT_EINVAL, "exactly one of d_phi and d_mask must be given");
+    if (d_phi && (r = check_ptr(d_phi, "d_phi"))) return r;
+    if ((r = check_ptr(d_phi_out, "d_phi_out"))) return r;
+    if (d_sqdist && !aligned(d_sqdist, 4)) return fail(ILT_EINVAL, "d_sqdist is not 4-byte aligned");
+    if (!p) return fail(ILT_EINVAL, "params is null");
+    if (!(p->d_lower < 0.f) || !(p->d_upper > 0.f)) return fail(ILT_EINVAL, "need d_lower < 0 < d_upper");
+    HIPCHK(launch_edt(c, d_phi, d_mask, d_phi_out, d_sqdist, p->d_lower, p->d_upper));
+    return ILT_OK;
+}
+
+extern "C" int ilt_solve(ilt_ctx *c, const unsigned char *d_target, float *d_phi, const ilt_params *p,
+                         ilt_report *h_report, double *d_trace) {
+    int r;
+    if ((r = check_ctx(c))) return r;
+    if ((r = check_ptr(d_target, "d_target", 1))) return r;
+    if ((r = check_ptr(d_phi, "d_phi"))) return r;
+    if (d_trace && !aligned(d_trace, 8)) return fail(ILT_EINVAL, "d_trace is not 8-byte aligned");
+    if ((r = check_params(c, p, true))) return r;
+    if (p->init_mode != 0 && p->init_mode != 1) return fail(ILT_EINVAL, "init_mode must be 0 or 1");
+    const resist_args ra = make_resist_args(p);
+    int slo, shi;
+    used_set_range(p, &slo, &shi);
+    const size_t npix = (size_t)c->N * c->N;
+    double *pr = c->part + part_resist_off(c), *pm = c->part + part_max_off(c), *ps = c->part + part_step_off(c);
+
+    if (p->init_mode == 0) HIPCHK(launch_edt(c, nullptr, d_target, d_phi, nullptr, p->d_lower, p->d_upper));
+    float *cur = d_phi, *nxt = c->phi2;
+    for (int i = 0; i < p->iters; ++i) {
+        HIPCHK(launch_spectrum(c, cur, 1));
+        HIPCHK(launch_make_Y(c, slo, shi));
+        HIPCHK(launch_image_to(c, slo, shi, c->I + (size_t)slo * npix));
+        HIPCHK(launch_resist(c, c->I, d_target, ra, c->G, pr));
+        HIPCHK(launch_finish_resist(c, pr, resist_blocks(c), c->scal, nullptr));
+        HIPCHK(launch_adjoint(c, c->G, npix, slo, shi));
+        HIPCHK(launch_window_sum(c, slo, shi));
+        HIPCHK(launch_gradient(c, c->g, pm));
+        HIPCHK(launch_finish_dt(c, pm, (int)n_image_blocks(c), p->dt_mode, p->eta, p->dt_max, c->scal));
+        HIPCHK(launch_levelset(c, cur, c->g, nullptr, p->lambda, p->eps_kappa, c->scal, nxt, ps));
+        HIPCHK(launch_finish_step(c, ps, step_blocks(c), c->scal, nullptr,
+                                  d_trace ? d_trace + (size_t)i * ILT_TRACE_W : nullptr, i));
+        if (p->reinit_every > 0 && (i + 1) % p->reinit_every == 0)
+            HIPCHK(launch_edt(c, nxt, nullptr, nxt, nullptr, p->d_lower, p->d_upper));
+        std::swap(cur, nxt);
+    }
+    if (cur != d_phi) HIPCHK(launch_copy(c, d_phi, cur, npix));
+    // final metrics of [phi_T <= 0]
+    HIPCHK(launch_spectrum(c, d_phi, 1));
+    HIPCHK(launch_make_Y(c, slo, shi));
+    HIPCHK(launch_image_to(c, slo, shi, c->I + (size_t)slo * npix));
+    HIPCHK(launch_resist(c, c->I, d_target, ra, c->G, pr));
+    HIPCHK(launch_finish_resist(c, pr, resist_blocks(c), c->scal, nullptr));
+    double sc[SC_COUNT];
+    HIPCHK(hipMemcpyAsync(sc, c->scal, sizeof sc, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    if (h_report) {
+        h_report->iters_done = p->iters;
+        h_report->loss = sc[SC_LOSS];
+        h_report->l2 = (long long)sc[SC_L2];
+        h_report->pvb = (long long)sc[SC_PVB];
+        h_report->flips = (long long)sc[SC_FLIPS];
+        h_report->status = (sc[SC_NONFIN] > 0.0 || !std::isfinite(sc[SC_LOSS])) ? ILT_ENUMERIC : ILT_OK;
+    }
+    if (sc[SC_NONFIN] > 0.0 || !std::isfinite(sc[SC_LOSS]))
+        return fail(ILT_ENUMERIC, "non-finite loss or gradient in the loop");
+    return ILT_OK;
+}

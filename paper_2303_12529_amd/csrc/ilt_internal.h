@@ -1,0 +1,122 @@
+// Internal declarations of the gfx950 level-set ILT library.
+//
+// Device data layout (all FP32 unless noted; Np = N rounded up to 128, and
+// every padded row/column of a table is zero so that GEMMs over padded
+// indices add nothing):
+//
+//   KP  = 2P rounded up to a multiple of 8 (real inner dimension of the
+//         window transforms: rows [0,P) real parts, [P,2P) imaginary parts)
+//   ZO  = P rounded up to 16; NZ = 2 ZO (window columns of the adjoint's
+//         row transform: [0,P) real, [ZO, ZO+P) imaginary)
+//   AP  = P rounded up to 16
+//
+//   tl   [2][KP][Np]   L1^T, L2^T: rows r of the image-side transform
+//                      L1[y][r] = Ar[r][y] (r<P), Ai[r-P][y] (P<=r<2P)
+//                      L2[y][r] = -Ai[r][y] (r<P), Ar[r-P][y] (P<=r<2P)
+//                      so that for a window array Y (rows r as above)
+//                      Re(A^H Y) = L1 Y and Im(A^H Y) = L2 Y.
+//   tb   [2][Np][NZ]   image -> window row transform for a real (part 0)
+//                      or imaginary (part 1) input column
+//   ta4  [2][Np][AP]   Ar[a][y], Ai[a][y] stored [y][a]
+//   ar, ai [P][Np]     A = exp(-2 pi i ((f_a x) mod N) / N)
+//   Y    [n_sets][K][KP][Np]  window -> image operands, scaled sqrt(w_k)/N^2
+//
+// A is computed on the host in FP64 from the integer-reduced phase and
+// rounded once.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/ilt.h"
+
+#define ILT_MAX_N 4096
+#define ILT_MAX_P 35
+#define ILT_MAX_K 64
+#define ILT_MAX_SETS 4
+#define ILT_TRACE_W 8
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+// 16x16x4 FP32 matrix-core step.  Lane l supplies A[m = l%16][k = l/16] and
+// B[k = l/16][n = l%16]; accumulator register i of lane l is
+// C[m = 4*(l/16) + i][n = l%16].
+__device__ __forceinline__ f4 mfma4(float a, float b, f4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+struct ilt_ctx {
+    int N, P, K, n_sets, precision;
+    int Np, KP, ZO, NZ, AP;
+    int device;
+    hipStream_t stream;
+
+    // tables
+    float *tl;         // [2][KP][Np]
+    float *tb;         // [2][Np][NZ]
+    float *ta4;        // [2][Np][AP]
+    float *ar, *ai;    // [P][Np]
+    float2 *H;         // [n_sets][K][P][P]   kernels (FP32)
+    float *sw;         // [n_sets][K]         sqrt(w_k) / N^2
+    float2 *coef;      // [n_sets][K][P][P]   sqrt(w_k)/N^2 conj(H)
+
+    // workspaces
+    float *t1;         // spectrum row transform [N/16 blocks][16][NZ]
+    float2 *S;         // [P][P]
+    float *Y;          // [n_sets][K][KP][Np]
+    float *Tg;         // [KP][Np]
+    float *I;          // [n_sets][N][N]
+    float *G;          // [n_sets][N][N]
+    float *g;          // [N][N]
+    float *phi2;       // [N][N]
+    float *Wpart;      // adjoint partials
+    float2 *W;         // [P][P]
+    uint32_t *edtg;    // [N][N] packed column distances
+    double *part;      // reduction partials (doubles)
+    double *scal;      // device scalars (see SC_* below)
+    int n_part;        // capacity of part (doubles)
+    int n_wpart;       // capacity of Wpart (floats)
+};
+
+// device scalar slots
+enum {
+    SC_LOSS = 0, SC_L2 = 1, SC_PVB = 2, SC_NONFIN = 3,
+    SC_MV = 4, SC_DT = 5, SC_FLIPS = 6, SC_ITER = 7,
+    SC_COUNT = 16
+};
+
+struct resist_args {
+    int n_corners;
+    int cset[4];
+    float dose[4];
+    float omega[4];
+    float sigma_z, i_th;
+    int set_used[ILT_MAX_SETS];
+};
+
+// ---- launchers (k_litho.hip) ----
+hipError_t launch_spectrum(ilt_ctx *c, const float *src, int src_is_phi);
+hipError_t launch_make_Y(ilt_ctx *c, int set_lo, int set_hi);
+hipError_t launch_image_to(ilt_ctx *c, int set_lo, int set_hi, float *out);
+hipError_t launch_adjoint(ilt_ctx *c, const float *G, size_t g_set_stride, int set_lo, int set_hi);
+hipError_t launch_window_sum(ilt_ctx *c, int set_lo, int set_hi);
+hipError_t launch_gradient(ilt_ctx *c, float *g_out, double *maxpart);
+
+// ---- launchers (k_pixel.hip) ----
+int resist_blocks(const ilt_ctx *c);
+hipError_t launch_resist(ilt_ctx *c, const float *I, const uint8_t *target, const resist_args &ra,
+                         float *G, double *part);
+hipError_t launch_finish_resist(ilt_ctx *c, const double *part, int nblk, double *scal, double *stats4);
+int gradmax_blocks(const ilt_ctx *c);
+hipError_t launch_absmax(ilt_ctx *c, const float *v, double *part);
+hipError_t launch_finish_dt(ilt_ctx *c, const double *part, int nblk, int dt_mode, float eta,
+                            float dt_max, double *scal);
+int step_blocks(const ilt_ctx *c);
+hipError_t launch_levelset(ilt_ctx *c, const float *phi, const float *vel, const float *mod,
+                           float lam, float eps_kappa, const double *scal, float *phi_out,
+                           double *part);
+hipError_t launch_finish_step(ilt_ctx *c, const double *part, int nblk, double *scal, double *stats4,
+                              double *trace_row, int iter);
+hipError_t launch_edt(ilt_ctx *c, const float *phi, const uint8_t *mask, float *phi_out, int *sqdist,
+                      float d_lower, float d_upper);
+hipError_t launch_copy(ilt_ctx *c, float *dst, const float *src, size_t n);
+hipError_t launch_fill(ilt_ctx *c, float *dst, float v, size_t n);

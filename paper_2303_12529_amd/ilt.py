@@ -1,0 +1,272 @@
+"""Python binding of the gfx950 level-set ILT library (ctypes, marshalling only).
+
+Every function here checks tensor shapes, dtypes and devices, packs the C
+structs declared in ``include/ilt.h`` and calls the library; all arithmetic
+happens in the HIP kernels.  Importing this module loads ``libilt.so`` built
+in-tree by ``paper_2303_12529_amd/build.py`` and fails loudly if it is
+missing: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libilt.so")
+
+ILT_OK, ILT_EINVAL, ILT_ENOMEM, ILT_EDEVICE, ILT_ENUMERIC, ILT_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+ILT_FP32 = 0
+TRACE_W = 8
+TRACE_COLUMNS = ("i", "loss", "l2", "pvb", "flips", "max_g", "dt", "t_ns")
+
+
+class IltError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("ILT error %d: %s" % (code, msg))
+        self.code = code
+
+
+class _Optics(ctypes.Structure):
+    _fields_ = [("N", ctypes.c_int), ("P", ctypes.c_int), ("K", ctypes.c_int), ("n_sets", ctypes.c_int),
+                ("precision", ctypes.c_int), ("h_kernels", ctypes.c_void_p), ("h_weights", ctypes.c_void_p)]
+
+
+class _Corner(ctypes.Structure):
+    _fields_ = [("set", ctypes.c_int), ("dose", ctypes.c_float), ("omega", ctypes.c_float)]
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int), ("reinit_every", ctypes.c_int), ("dt_mode", ctypes.c_int),
+                ("init_mode", ctypes.c_int), ("eta", ctypes.c_float), ("dt_max", ctypes.c_float),
+                ("lambda_", ctypes.c_float), ("sigma_z", ctypes.c_float), ("i_th", ctypes.c_float),
+                ("eps_kappa", ctypes.c_float), ("d_lower", ctypes.c_float), ("d_upper", ctypes.c_float),
+                ("n_corners", ctypes.c_int), ("corners", _Corner * 4)]
+
+
+class _Report(ctypes.Structure):
+    _fields_ = [("iters_done", ctypes.c_int), ("status", ctypes.c_int), ("loss", ctypes.c_double),
+                ("l2", ctypes.c_longlong), ("pvb", ctypes.c_longlong), ("flips", ctypes.c_longlong)]
+
+
+_lib = None
+_VP = ctypes.c_void_p
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libilt.so and declare the C signatures (no GPU work)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError("libilt.so is not built (%s); run paper_2303_12529_amd/build.py" % path)
+    lib = ctypes.CDLL(path)
+    sig = {
+        "ilt_create": [ctypes.POINTER(_VP), ctypes.POINTER(_Optics), ctypes.c_int, _VP],
+        "ilt_destroy": [_VP],
+        "ilt_get_dims": [_VP, ctypes.POINTER(ctypes.c_int)] + [ctypes.POINTER(ctypes.c_int)] * 3,
+        "litho_forward": [_VP, _VP, ctypes.c_int, _VP],
+        "litho_adjoint": [_VP, _VP, _VP, ctypes.c_int, _VP],
+        "resist_loss": [_VP, _VP, _VP, ctypes.POINTER(_Params), _VP, _VP],
+        "levelset_step": [_VP, _VP, _VP, _VP, ctypes.POINTER(_Params), _VP],
+        "edt_reinit": [_VP, _VP, _VP, _VP, _VP, ctypes.POINTER(_Params)],
+        "ilt_solve": [_VP, _VP, _VP, ctypes.POINTER(_Params), ctypes.POINTER(_Report), _VP],
+    }
+    for name, args in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = ctypes.c_int
+    lib.ilt_last_error.argtypes = []
+    lib.ilt_last_error.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def _check(rc):
+    if rc != ILT_OK:
+        raise IltError(rc, load_library().ilt_last_error().decode(errors="replace"))
+
+
+@dataclasses.dataclass
+class Params:
+    """Method settings (see ilt_params in include/ilt.h)."""
+    iters: int = 20
+    reinit_every: int = 5
+    dt_mode: int = 0
+    init_mode: int = 0
+    eta: float = 0.85
+    dt_max: float = 5.0
+    lam: float = 0.05
+    sigma_z: float = 50.0
+    i_th: float = 0.225
+    eps_kappa: float = 1e-12
+    d_lower: float = -100.0
+    d_upper: float = 900.0
+    corners: tuple = ((0, 1.0, 1.0),)
+
+    @classmethod
+    def from_dict(cls, d: dict, **over):
+        kw = {f.name: d[f.name] for f in dataclasses.fields(cls) if f.name in d}
+        kw.update(over)
+        kw["corners"] = tuple(tuple(c) for c in kw.get("corners", ((0, 1.0, 1.0),)))
+        return cls(**kw)
+
+    def to_c(self) -> _Params:
+        p = _Params()
+        p.iters, p.reinit_every, p.dt_mode, p.init_mode = self.iters, self.reinit_every, self.dt_mode, self.init_mode
+        p.eta, p.dt_max, p.lambda_, p.sigma_z = self.eta, self.dt_max, self.lam, self.sigma_z
+        p.i_th, p.eps_kappa, p.d_lower, p.d_upper = self.i_th, self.eps_kappa, self.d_lower, self.d_upper
+        if not 1 <= len(self.corners) <= 4:
+            raise ValueError("1..4 corners")
+        p.n_corners = len(self.corners)
+        for i, (s, d, w) in enumerate(self.corners):
+            p.corners[i].set, p.corners[i].dose, p.corners[i].omega = int(s), float(d), float(w)
+        return p
+
+
+def _ptr(t, dtype, shape, name, device):
+    import torch
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("%s must be a torch tensor" % name)
+    if t.device != device:
+        raise ValueError("%s is on %s, context is on %s" % (name, t.device, device))
+    if t.dtype != dtype:
+        raise TypeError("%s must be %s, got %s" % (name, dtype, t.dtype))
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError("%s must have shape %s, got %s" % (name, tuple(shape), tuple(t.shape)))
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Context:
+    """A library context on the current torch CUDA (HIP) device and stream."""
+
+    def __init__(self, kernels: np.ndarray, weights: np.ndarray, N: int, precision: int = ILT_FP32):
+        import torch
+        lib = load_library()
+        kernels = np.asarray(kernels)
+        weights = np.asarray(weights, dtype=np.float64)
+        if kernels.ndim == 3:
+            kernels = kernels[None]
+            weights = weights[None]
+        ns, K, P, P2 = kernels.shape
+        if P != P2 or weights.shape != (ns, K):
+            raise ValueError("kernels must be [n_sets, K, P, P] and weights [n_sets, K]")
+        kr = np.ascontiguousarray(np.stack([kernels.real, kernels.imag], axis=-1), dtype=np.float64)
+        wr = np.ascontiguousarray(weights)
+        o = _Optics(N=int(N), P=int(P), K=int(K), n_sets=int(ns), precision=int(precision),
+                    h_kernels=kr.ctypes.data, h_weights=wr.ctypes.data)
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        self.stream = torch.cuda.current_stream(self.device)
+        h = _VP()
+        _check(lib.ilt_create(ctypes.byref(h), ctypes.byref(o), 1, _VP(self.stream.cuda_stream)))
+        self._h = h
+        self.N, self.P, self.K, self.n_sets = int(N), int(P), int(K), int(ns)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load_library().ilt_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _img(self, t, name, dtype=None):
+        import torch
+        return _ptr(t, dtype or torch.float32, (self.N, self.N), name, self.device)
+
+    def litho_forward(self, mask, set_: int = 0, out=None):
+        import torch
+        if out is None:
+            out = torch.empty((self.N, self.N), dtype=torch.float32, device=self.device)
+        _check(load_library().litho_forward(self._h, self._img(mask, "mask"), int(set_), self._img(out, "out")))
+        return out
+
+    def litho_adjoint(self, mask, dL_dI, set_: int = 0, out=None):
+        import torch
+        if out is None:
+            out = torch.empty((self.N, self.N), dtype=torch.float32, device=self.device)
+        _check(load_library().litho_adjoint(self._h, self._img(mask, "mask"), self._img(dL_dI, "dL_dI"),
+                                            int(set_), self._img(out, "out")))
+        return out
+
+    def resist_loss(self, aerial, target, params: Params, G=None, stats=None):
+        import torch
+        shp = (self.n_sets, self.N, self.N)
+        if G is None:
+            G = torch.empty(shp, dtype=torch.float32, device=self.device)
+        if stats is None:
+            stats = torch.zeros(4, dtype=torch.float64, device=self.device)
+        pc = params.to_c()
+        _check(load_library().resist_loss(self._h, _ptr(aerial, torch.float32, shp, "aerial", self.device),
+                                          self._img(target, "target", torch.uint8), ctypes.byref(pc),
+                                          _ptr(G, torch.float32, shp, "G", self.device),
+                                          _ptr(stats, torch.float64, (4,), "stats", self.device)))
+        return G, stats
+
+    def levelset_step(self, phi, vel, params: Params, mod=None, stats=None):
+        import torch
+        if stats is None:
+            stats = torch.zeros(4, dtype=torch.float64, device=self.device)
+        pc = params.to_c()
+        _check(load_library().levelset_step(self._h, self._img(phi, "phi"), self._img(vel, "vel"),
+                                            self._img(mod, "mod"), ctypes.byref(pc),
+                                            _ptr(stats, torch.float64, (4,), "stats", self.device)))
+        return phi, stats
+
+    def edt_reinit(self, params: Params, phi=None, mask=None, phi_out=None, sqdist=None):
+        import torch
+        if phi_out is None:
+            phi_out = torch.empty((self.N, self.N), dtype=torch.float32, device=self.device)
+        pc = params.to_c()
+        _check(load_library().edt_reinit(self._h, self._img(phi, "phi"), self._img(mask, "mask", torch.uint8),
+                                         self._img(phi_out, "phi_out"),
+                                         _ptr(sqdist, torch.int32, (2, self.N, self.N), "sqdist", self.device),
+                                         ctypes.byref(pc)))
+        return phi_out
+
+    def ilt_solve(self, target, phi, params: Params, trace=None):
+        import torch
+        pc = params.to_c()
+        rep = _Report()
+        tr = None
+        if trace is not None:
+            tr = _ptr(trace, torch.float64, (params.iters, TRACE_W), "trace", self.device)
+        rc = load_library().ilt_solve(self._h, self._img(target, "target", torch.uint8), self._img(phi, "phi"),
+                                      ctypes.byref(pc), ctypes.byref(rep), tr)
+        _check(rc)
+        return dict(iters_done=rep.iters_done, status=rep.status, loss=rep.loss, l2=rep.l2, pvb=rep.pvb,
+                    flips=rep.flips)
+
+
+# module-level names matching the C ABI
+def litho_forward(ctx: Context, mask, set_=0, out=None):
+    return ctx.litho_forward(mask, set_, out)
+
+
+def litho_adjoint(ctx: Context, mask, dL_dI, set_=0, out=None):
+    return ctx.litho_adjoint(mask, dL_dI, set_, out)
+
+
+def resist_loss(ctx: Context, aerial, target, params, G=None, stats=None):
+    return ctx.resist_loss(aerial, target, params, G, stats)
+
+
+def levelset_step(ctx: Context, phi, vel, params, mod=None, stats=None):
+    return ctx.levelset_step(phi, vel, params, mod, stats)
+
+
+def edt_reinit(ctx: Context, params, phi=None, mask=None, phi_out=None, sqdist=None):
+    return ctx.edt_reinit(params, phi, mask, phi_out, sqdist)
+
+
+def ilt_solve(ctx: Context, target, phi, params, trace=None):
+    return ctx.ilt_solve(target, phi, params, trace)

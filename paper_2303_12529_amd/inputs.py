@@ -264,3 +264,39 @@ def optics_checksum(kernels: np.ndarray, weights: np.ndarray) -> str:
     h.update(np.ascontiguousarray(kernels, dtype=np.complex128).tobytes())
     h.update(np.ascontiguousarray(weights, dtype=np.float64).tobytes())
     return h.hexdigest()[:16]
+
+
+# --------------------------------------------------------------------------
+# Workload presets (inputs and method settings; plain data only)
+# --------------------------------------------------------------------------
+
+def _params(pitch_nm, corners, iters, eta=0.85, lam=0.05, dt_mode=0, reinit_every=5):
+    return dict(
+        iters=iters, reinit_every=reinit_every, dt_mode=dt_mode, eta=eta,
+        dt_max=(0.25 / lam if lam > 0 else 0.0), lam=lam, sigma_z=50.0, i_th=0.225,
+        eps_kappa=1e-12, d_lower=-100.0 / pitch_nm, d_upper=900.0 / pitch_nm,
+        corners=corners,
+    )
+
+
+NOMINAL_ONLY = [(0, 1.0, 1.0)]
+# nominal (alpha = 1), outer (+2 % dose, nominal focus, beta = 7.5),
+# inner (-2 % dose, 25 nm defocus, beta = 7.5)
+THREE_CORNERS = [(0, 1.0, 1.0), (0, 1.02, 7.5), (1, 0.98, 7.5)]
+
+WORKLOADS = {
+    # 256^2 at 8 nm, K = 8, P = 9, nominal only, 20 iterations
+    "c0": dict(clip=C0_CLIP, optics=dict(N=256, pitch_nm=8.0, P=9, K=8, defocus_sets=(0.0,)),
+               params=_params(8.0, NOMINAL_ONLY, 20)),
+    # 2048^2 at 1 nm, K = 24, P = 35, nominal + 25 nm defocus sets, 3 corners, 50 iterations
+    "c1": dict(clip=C1_CLIP, optics=dict(N=2048, pitch_nm=1.0, P=35, K=24, defocus_sets=(0.0, 25.0)),
+               params=_params(1.0, THREE_CORNERS, 50)),
+}
+
+
+def workload_inputs(name: str, seed: int = 0):
+    """(target uint8 [N,N], kernels [n_sets,K,P,P], weights [n_sets,K], params dict)."""
+    w = WORKLOADS[name]
+    Z = gen_clip(w["clip"], seed)
+    k, wt = build_optics(**w["optics"])
+    return Z, k, wt, dict(w["params"])

@@ -1,0 +1,261 @@
+"""GPU-vs-oracle parity of every C-ABI entry point (needs an MI355X).
+
+Inputs are seeded and synthetic; the oracle (FP64) runs on the same values
+the GPU receives (FP32 inputs widened to FP64).  Tolerances:
+
+* aerial image: max|I_gpu - I_ref| / max|I_ref| <= 1e-5 (FP32 bar);
+* adjoint gradient: max|g_gpu - g_ref| / max|g_ref| <= 1e-4;
+* EDT: squared distances bit-exact; phi bit-exact against the FP64 value
+  rounded to FP32;
+* level-set step: |phi'_gpu - phi'_ref| <= 4 ulp(|phi'_ref|) + 1e-5 px;
+* resist: loss relative 1e-6, G normwise 1e-5, L2 / PVB exact except pixels
+  whose print decision is within 1e-6 of the threshold.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import edt as o_edt  # noqa: E402
+from oracle import levelset as o_ls  # noqa: E402
+from oracle import litho as o_litho  # noqa: E402
+from oracle import resist as o_resist  # noqa: E402
+from paper_2303_12529_amd.inputs import (build_optics, gen_clip, C0_CLIP, C1_CLIP,  # noqa: E402
+                                         random_mask, random_phi)
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def ilt():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2303_12529_amd import ilt as mod
+    mod.load_library()
+    return mod
+
+
+def _dev(a, dtype=torch.float32):
+    return torch.as_tensor(np.ascontiguousarray(a)).to(device="cuda", dtype=dtype)
+
+
+def _rand_kernels(ns, K, P, seed):
+    rng = np.random.default_rng(seed)
+    H = rng.normal(size=(ns, K, P, P)) + 1j * rng.normal(size=(ns, K, P, P))
+    H /= np.sqrt(P * P)
+    w = rng.uniform(0.1, 1.0, size=(ns, K))
+    return H, w
+
+
+FWD_CASES = [
+    # (N, P, K, kind)
+    (64, 3, 2, "rand"),
+    (64, 9, 4, "rand"),
+    (100, 9, 5, "binary"),
+    (256, 9, 8, "optics"),
+    (200, 35, 6, "rand"),
+    (300, 21, 7, "binary"),
+    (512, 35, 24, "optics"),
+]
+
+
+@pytest.mark.parametrize("N,P,K,kind", FWD_CASES)
+def test_litho_forward_parity(ilt, N, P, K, kind):
+    _say("forward", N, P, K, kind)
+    if kind == "optics":
+        H, w = build_optics(N, 2048.0 / N, P, K)
+    else:
+        H, w = _rand_kernels(1, K, P, seed=N + P)
+    rng = np.random.default_rng(N * 7 + K)
+    if kind == "rand":
+        M = rng.uniform(size=(N, N)).astype(np.float32)
+    else:
+        M = random_mask(N, 0.3, seed=N).astype(np.float32)
+    ctx = ilt.Context(H, w, N)
+    out = ctx.litho_forward(_dev(M), 0).cpu().numpy()
+    torch.cuda.synchronize()
+    ref = o_litho.aerial_image(M.astype(np.float64), H[0], w[0])
+    err = np.abs(out - ref).max() / np.abs(ref).max()
+    _say("  rel err", err)
+    assert err <= 1e-5
+
+
+def test_clear_field_gpu(ilt):
+    N, P, K = 256, 9, 8
+    H, w = build_optics(N, 8.0, P, K)
+    ctx = ilt.Context(H, w, N)
+    out = ctx.litho_forward(torch.ones((N, N), device="cuda"), 0).cpu().numpy()
+    expect = float(np.sum(w[0] * np.abs(H[0, :, 4, 4]) ** 2))
+    assert np.abs(out - expect).max() <= 1e-5 * expect
+
+
+def test_litho_forward_two_sets_select(ilt):
+    N, P, K = 128, 9, 4
+    H, w = _rand_kernels(2, K, P, seed=3)
+    M = random_mask(N, 0.4, seed=5).astype(np.float32)
+    ctx = ilt.Context(H, w, N)
+    for s in range(2):
+        out = ctx.litho_forward(_dev(M), s).cpu().numpy()
+        ref = o_litho.aerial_image(M.astype(np.float64), H[s], w[s])
+        assert np.abs(out - ref).max() <= 1e-5 * np.abs(ref).max()
+
+
+ADJ_CASES = [(64, 3, 2), (64, 9, 4), (100, 9, 5), (200, 35, 6), (256, 21, 9), (384, 35, 24)]
+
+
+@pytest.mark.parametrize("N,P,K", ADJ_CASES)
+def test_litho_adjoint_parity(ilt, N, P, K):
+    _say("adjoint", N, P, K)
+    H, w = _rand_kernels(1, K, P, seed=N * 3 + P)
+    rng = np.random.default_rng(N + K)
+    M = random_mask(N, 0.3, seed=N + 1).astype(np.float32)
+    G = rng.normal(size=(N, N)).astype(np.float32)
+    ctx = ilt.Context(H, w, N)
+    out = ctx.litho_adjoint(_dev(M), _dev(G), 0).cpu().numpy()
+    ref = o_litho.litho_adjoint(M.astype(np.float64), G.astype(np.float64), H[0], w[0])
+    err = np.abs(out - ref).max() / np.abs(ref).max()
+    _say("  rel err", err)
+    assert err <= 1e-4
+
+
+def test_resist_loss_parity(ilt):
+    N = 256
+    H, w = _rand_kernels(2, 2, 5, seed=1)
+    rng = np.random.default_rng(11)
+    I = rng.uniform(0.0, 0.5, size=(2, N, N)).astype(np.float32)
+    Zt = random_mask(N, 0.3, seed=12)
+    corners = ((0, 1.0, 1.0), (0, 1.02, 7.5), (1, 0.98, 7.5))
+    p = ilt.Params(corners=corners)
+    ctx = ilt.Context(H, w, N)
+    G, st = ctx.resist_loss(_dev(I), _dev(Zt, torch.uint8), p)
+    G = G.cpu().numpy()
+    st = st.cpu().numpy()
+    L, Gr = o_resist.dso_loss_and_grad([I[0].astype(np.float64), I[1].astype(np.float64)], Zt, corners,
+                                       50.0, 0.225)
+    assert abs(st[0] - L) <= 1e-6 * abs(L)
+    for s in range(2):
+        assert np.abs(G[s] - Gr[s]).max() <= 1e-5 * np.abs(Gr[s]).max()
+    # binary decisions taken in FP32 on both sides
+    f32 = np.float32
+    pr = [(f32(d) * I[s] >= f32(0.225)) for (s, d, _) in corners]
+    l2 = int(np.sum(pr[0] != (Zt == 1)))
+    pvb = int(np.sum(pr[1] != pr[2]))
+    assert st[1] == l2 and st[2] == pvb and st[3] == 0
+
+
+def test_resist_unused_set_zero(ilt):
+    N = 64
+    H, w = _rand_kernels(2, 2, 5, seed=2)
+    I = np.full((2, N, N), 0.2, dtype=np.float32)
+    Zt = random_mask(N, 0.5, seed=1)
+    ctx = ilt.Context(H, w, N)
+    G, st = ctx.resist_loss(_dev(I), _dev(Zt, torch.uint8), ilt.Params(corners=((0, 1.0, 1.0),)))
+    assert torch.count_nonzero(G[1]).item() == 0
+    assert torch.count_nonzero(G[0]).item() > 0
+
+
+EDT_CASES = [(16, 0.5), (64, 0.02), (64, 0.5), (64, 0.97), (100, 0.1), (257, 0.3), (256, "clip0"),
+             (1000, 0.001), (2048, "clip1")]
+
+
+@pytest.mark.parametrize("N,dens", EDT_CASES)
+def test_edt_bit_exact(ilt, N, dens):
+    _say("edt", N, dens)
+    if dens == "clip0":
+        m = gen_clip(C0_CLIP, 1)
+    elif dens == "clip1":
+        m = gen_clip(C1_CLIP, 2)
+    else:
+        m = random_mask(N, dens, seed=N)
+    lo, hi = (-12.5, 112.5) if N <= 300 else (-100.0, 900.0)
+    H, w = _rand_kernels(1, 1, 3, seed=0)
+    ctx = ilt.Context(H, w, N)
+    p = ilt.Params(d_lower=lo, d_upper=hi)
+    sq = torch.empty((2, N, N), dtype=torch.int32, device="cuda")
+    phi = ctx.edt_reinit(p, mask=_dev(m, torch.uint8), sqdist=sq).cpu().numpy()
+    sq = sq.cpu().numpy()
+    ref_phi, d_in, d_out = o_edt.tsdf_from_mask(m, lo, hi)
+    big = np.iinfo(np.int32).max
+    np.testing.assert_array_equal(sq[0], np.where(d_in < 0, big, d_in))
+    np.testing.assert_array_equal(sq[1], np.where(d_out < 0, big, d_out))
+    np.testing.assert_array_equal(phi, ref_phi.astype(np.float32))
+
+
+def test_edt_from_phi_and_in_place(ilt):
+    N = 192
+    phi0 = random_phi(N, seed=3).astype(np.float32)
+    H, w = _rand_kernels(1, 1, 3, seed=0)
+    ctx = ilt.Context(H, w, N)
+    p = ilt.Params(d_lower=-12.5, d_upper=112.5)
+    t = _dev(phi0)
+    ctx.edt_reinit(p, phi=t, phi_out=t)
+    ref, _, _ = o_edt.tsdf_from_phi(phi0, -12.5, 112.5)
+    np.testing.assert_array_equal(t.cpu().numpy(), ref.astype(np.float32))
+
+
+def test_edt_empty_and_full(ilt):
+    N = 48
+    H, w = _rand_kernels(1, 1, 3, seed=0)
+    ctx = ilt.Context(H, w, N)
+    p = ilt.Params(d_lower=-12.5, d_upper=112.5)
+    for val, expect in ((0, 112.5), (1, -12.5)):
+        m = np.full((N, N), val, dtype=np.uint8)
+        sq = torch.empty((2, N, N), dtype=torch.int32, device="cuda")
+        phi = ctx.edt_reinit(p, mask=_dev(m, torch.uint8), sqdist=sq).cpu().numpy()
+        assert (phi == expect).all()
+        none = sq[0] if val == 0 else sq[1]
+        assert (none.cpu().numpy() == np.iinfo(np.int32).max).all()
+
+
+def test_sqrt_rounding_all_small_distances(ilt):
+    """phi of a single inside pixel covers every squared distance up to
+    2 (N-1)^2; each must equal the FP64 value rounded once to FP32."""
+    N = 1024
+    m = np.zeros((N, N), dtype=np.uint8)
+    m[0, 0] = 1
+    H, w = _rand_kernels(1, 1, 3, seed=0)
+    ctx = ilt.Context(H, w, N)
+    p = ilt.Params(d_lower=-1e6, d_upper=1e6)
+    phi = ctx.edt_reinit(p, mask=_dev(m, torch.uint8)).cpu().numpy()
+    yy, xx = np.mgrid[0:N, 0:N]
+    D = (yy ** 2 + xx ** 2).astype(np.float64)
+    ref = (np.sqrt(D) - 0.5).astype(np.float32)
+    ref[0, 0] = np.float32(0.5 - 1.0)   # the pixel itself: nearest outside pixel at distance 1
+    np.testing.assert_array_equal(phi, ref)
+
+
+STEP_CASES = [(64, 0.05, 0), (200, 0.05, 0), (256, 0.9, 0), (130, 0.05, 1), (2048, 0.05, 0)]
+
+
+@pytest.mark.parametrize("N,lam,dt_mode", STEP_CASES)
+def test_levelset_step_parity(ilt, N, lam, dt_mode):
+    _say("step", N, lam, dt_mode)
+    phi = random_phi(N, seed=N).astype(np.float32) * (1.0 if N < 1000 else 20.0)
+    rng = np.random.default_rng(N)
+    vel = (rng.normal(size=(N, N)) * 3.0).astype(np.float32)
+    mod = rng.uniform(size=(N, N)).astype(np.float32) if N == 200 else None
+    H, w = _rand_kernels(1, 1, 3, seed=0)
+    ctx = ilt.Context(H, w, N)
+    p = ilt.Params(eta=0.85 if dt_mode == 0 else 0.1, lam=lam, dt_mode=dt_mode, dt_max=0.25 / lam)
+    t = _dev(phi)
+    _, st = ctx.levelset_step(t, _dev(vel), p, mod=None if mod is None else _dev(mod))
+    out = t.cpu().numpy().astype(np.float64)
+    st = st.cpu().numpy()
+    ref, dt, m_v, flips = o_ls.levelset_step(phi.astype(np.float64), vel.astype(np.float64),
+                                             None if mod is None else mod.astype(np.float64),
+                                             p.eta, lam, 1e-12, dt_mode, p.dt_max)
+    assert st[0] == m_v
+    assert abs(st[1] - dt) <= 2e-7 * dt
+    ulp = np.spacing(np.abs(ref).astype(np.float32)).astype(np.float64)
+    tol = 4 * ulp + 1e-5
+    bad = np.abs(out - ref) > tol
+    _say("  max err", np.abs(out - ref).max(), "bad", bad.sum())
+    assert not bad.any()
+    near = np.abs(ref) <= tol
+    assert abs(st[2] - flips) <= near.sum()
