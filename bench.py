@@ -1,0 +1,164 @@
+#!/usr/bin/env python3
+"""Throughput of the level-set ILT loop on one MI355X.
+
+A step is one DSO iteration over one synthetic 2048 x 2048 clip (1 nm
+pixels): mask spectrum, SOCS forward imaging with K = 24 kernels for two
+focus conditions, resist and L_DSO over three process corners, the SOCS
+adjoint, the gradient back-transform, the curvature-regularised level-set
+step, and TSDF re-initialisation every 5 steps.  Inputs are resident in HBM
+before timing starts.
+
+Output: one JSON line (rank 0) with the metric, a roofline entry for the
+dominant kernel (timed with HIP events on the library's stream inside the
+timed region) and the CPU FP64 oracle timed on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+METRIC = "level-set ILT iterations/s per 2048² clip (K=24); time-to-L2 target vs plain"
+FP32_MFMA_PEAK_TFLOPS = 157.3
+HBM_PEAK_GBS = 8000.0
+
+
+def algorithmic_work(N, P, K, n_sets):
+    """Per-phase algorithmic flops (dense phases) and bytes (pixel phases)
+    of one iteration; complex multiply-add = 8 flops."""
+    N2 = float(N) * N
+    return {
+        "spectrum": dict(flops=4 * P * N2 + 8 * P * P * N),
+        "window_rows": dict(flops=n_sets * K * 8.0 * P * P * N),
+        "image": dict(flops=n_sets * K * 8.0 * P * N2),
+        "adjoint": dict(flops=n_sets * K * (8.0 * P * N2 + 8.0 * P * P * N)),
+        "gradient": dict(flops=4 * P * N2 + 8 * P * P * N),
+        "resist": dict(bytes=N2 * (4 * n_sets + 1 + 4 * n_sets)),
+        "levelset_step": dict(bytes=N2 * 12),
+        "reinit": dict(bytes=N2 * 16),
+    }
+
+
+def cpu_baseline(workload, seed, iters):
+    """Time the FP64 oracle on `iters` iterations of the same workload."""
+    import numpy as np
+    from threadpoolctl import threadpool_info
+    from oracle import edt as o_edt
+    from oracle import solve as o_solve
+    from paper_2303_12529_amd.inputs import workload_inputs
+    Z, H, w, prm = workload_inputs(workload, seed)
+    phi, _, _ = o_edt.tsdf_from_mask(Z, prm["d_lower"], prm["d_upper"])
+    threads = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
+    t0 = time.perf_counter()
+    for _ in range(iters):
+        phi, _ = o_solve.iteration(phi, Z, H, w, prm)
+    dt = time.perf_counter() - t0
+    return {"value": iters / dt, "unit": "it/s", "cores": int(threads), "kind": "oracle",
+            "sample": "%d DSO iterations of the same %s clip (seed %d), FP64 numpy/BLAS, %.1f s"
+                      % (iters, workload, seed, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="c1")
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--cpu-iters", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: the path runs on a single MI355X "
+              "(see the design notes on sharding); --gpus must be 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2303_12529_amd import ilt
+    from paper_2303_12529_amd.inputs import WORKLOADS, workload_inputs
+
+    Z, H, w, prm = workload_inputs(args.workload, args.seed)
+    N = Z.shape[0]
+    n_sets, K, P, _ = H.shape
+    torch.cuda.set_device(0)
+    ctx = ilt.Context(H, w, N)
+    target = torch.as_tensor(Z).to("cuda")
+    phi = torch.empty((N, N), dtype=torch.float32, device="cuda")
+
+    # warm-up: TSDF init + W iterations (also compiles/loads every kernel)
+    ctx.ilt_solve(target, phi, ilt.Params.from_dict(prm, iters=max(args.warmup, 1), init_mode=0))
+    torch.cuda.synchronize()
+
+    p = ilt.Params.from_dict(prm, iters=args.steps, init_mode=1)
+    trace = torch.zeros((args.steps, ilt.TRACE_W), dtype=torch.float64, device="cuda")
+    ctx.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rep = ctx.ilt_solve(target, phi, p, trace=trace)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    prof = ctx.profile_read()
+    ctx.profile(False)
+
+    ms_per_step = 1e3 * wall / args.steps
+    value = args.steps / wall
+    work = algorithmic_work(N, P, K, n_sets)
+    phase_ms = {k: v[0] for k, v in prof.items()}
+    dominant = max(phase_ms, key=lambda k: phase_ms[k])
+    launches = prof[dominant][1]
+    avg_ms = phase_ms[dominant] / max(launches, 1)
+    wd = work[dominant]
+    if "flops" in wd:
+        achieved = wd["flops"] / (avg_ms * 1e-3) / 1e12
+        roof = {"bound": "mfma", "achieved": round(achieved, 2), "peak": FP32_MFMA_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(achieved / FP32_MFMA_PEAK_TFLOPS, 4), "traffic": None}
+    else:
+        achieved = wd["bytes"] / (avg_ms * 1e-3) / 1e9
+        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None}
+    roof["kernel"] = dominant
+    roof["avg_launch_ms"] = round(avg_ms, 4)
+    total_flops = sum(v.get("flops", 0.0) for v in work.values())
+    tr = trace.cpu().numpy()
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(args.workload, args.seed, args.cpu_iters)
+
+    desc = WORKLOADS[args.workload]
+    line = {
+        "metric": METRIC,
+        "value": round(value, 3),
+        "unit": "it/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "%s: %dx%d clip at %.0f nm/px, K=%d kernels on a %dx%d window, %d kernel sets, "
+                        "%d corners, TSDF reinit every %d" % (
+                            args.workload, N, N, desc["optics"]["pitch_nm"], K, P, P, n_sets,
+                            len(prm["corners"]), prm["reinit_every"]),
+            "N": N, "P": P, "K": K, "n_sets": n_sets, "corners": len(prm["corners"]), "seed": args.seed,
+        },
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "whole_loop_tflops": round(total_flops * value / 1e12, 2),
+        "whole_loop_frac_fp32_mfma": round(total_flops * value / 1e12 / FP32_MFMA_PEAK_TFLOPS, 4),
+        "phases_ms_per_step": {k: round(v / args.steps, 4) for k, v in phase_ms.items()},
+        "final": {"l2": rep["l2"], "pvb": rep["pvb"], "loss": rep["loss"],
+                  "l2_first": int(tr[0, 2]), "l2_last_iter": int(tr[-1, 2])},
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

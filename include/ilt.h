@@ -155,6 +155,18 @@ int edt_reinit(ilt_ctx *ctx, const float *d_phi, const unsigned char *d_mask,
 int ilt_solve(ilt_ctx *ctx, const unsigned char *d_target, float *d_phi,
               const ilt_params *params, ilt_report *h_report, double *d_trace);
 
+/* Measurement hook.  ilt_profile(ctx, 1) makes later ilt_solve calls record
+ * a HIP event pair on the context's stream around every launch of each
+ * phase of the loop; ilt_profile_read() then returns, per phase, the summed
+ * device time in ms and the launch count of the most recent ilt_solve:
+ * h_out[2*p] = ms, h_out[2*p+1] = launches, for p in
+ *   0 spectrum, 1 window->rows, 2 image (forward), 3 resist, 4 adjoint,
+ *   5 window sum + gradient, 6 level-set step, 7 re-initialisation.
+ * n = number of doubles available at h_out (>= 16).  Synchronous. */
+#define ILT_N_PHASES 8
+int ilt_profile(ilt_ctx *ctx, int enable);
+int ilt_profile_read(ilt_ctx *ctx, double *h_out, int n);
+
 #ifdef __cplusplus
 }
 #endif

@@ -35,8 +35,10 @@ def build(verbose: bool = False) -> str:
     failed = []
     for cmd, p in procs:
         out, _ = p.communicate()
-        if out:
-            sys.stdout.write(out.decode(errors="replace"))
+        text = "".join(line for line in out.decode(errors="replace").splitlines(True)
+                       if "packed-fp32-ops" not in line)
+        if text.strip():
+            sys.stdout.write(text)
         if p.returncode != 0:
             failed.append(cmd[-3])
     if failed:

@@ -56,8 +56,20 @@ hipError_t dalloc(T **p, size_t n) {
     return e;
 }
 
+void free_events(ilt_ctx *c) {
+    for (int i = 0; i < 2 * c->ev_cap; ++i)
+        if (c->ev && c->ev[i]) (void)hipEventDestroy(c->ev[i]);
+    delete[] c->ev;
+    delete[] c->ev_phase;
+    c->ev = nullptr;
+    c->ev_phase = nullptr;
+    c->ev_cap = 0;
+    c->n_ev = 0;
+}
+
 void free_ctx(ilt_ctx *c) {
     if (!c) return;
+    free_events(c);
     void *ptrs[] = {c->tl, c->tb, c->ta4, c->ar, c->ai, c->H, c->sw, c->coef, c->t1, c->S, c->Y, c->Tg,
                     c->I, c->G, c->g, c->phi2, c->Wpart, c->W, c->edtg, c->part, c->scal};
     for (void *p : ptrs)
@@ -124,6 +136,23 @@ void used_set_range(const ilt_params *p, int *lo, int *hi) {
     *lo = a;
     *hi = b + 1;
 }
+
+// Record the launches of one loop phase between an event pair when the
+// measurement hook is on (no-op otherwise).
+struct PhaseTimer {
+    ilt_ctx *c;
+    int slot;
+    PhaseTimer(ilt_ctx *c_, int phase) : c(c_), slot(-1) {
+        if (c->profiling && c->n_ev < c->ev_cap) {
+            slot = c->n_ev++;
+            c->ev_phase[slot] = phase;
+            (void)hipEventRecord(c->ev[2 * slot], c->stream);
+        }
+    }
+    ~PhaseTimer() {
+        if (slot >= 0) (void)hipEventRecord(c->ev[2 * slot + 1], c->stream);
+    }
+};
 
 // partial-buffer regions (doubles)
 size_t part_resist_off(const ilt_ctx *) { return 0; }
@@ -375,23 +404,50 @@ extern "C" int ilt_solve(ilt_ctx *c, const unsigned char *d_target, float *d_phi
     const size_t npix = (size_t)c->N * c->N;
     double *pr = c->part + part_resist_off(c), *pm = c->part + part_max_off(c), *ps = c->part + part_step_off(c);
 
-    if (p->init_mode == 0) HIPCHK(launch_edt(c, nullptr, d_target, d_phi, nullptr, p->d_lower, p->d_upper));
+    c->n_ev = 0;
+    if (p->init_mode == 0) {
+        PhaseTimer t(c, 7);
+        HIPCHK(launch_edt(c, nullptr, d_target, d_phi, nullptr, p->d_lower, p->d_upper));
+    }
     float *cur = d_phi, *nxt = c->phi2;
     for (int i = 0; i < p->iters; ++i) {
-        HIPCHK(launch_spectrum(c, cur, 1));
-        HIPCHK(launch_make_Y(c, slo, shi));
-        HIPCHK(launch_image_to(c, slo, shi, c->I + (size_t)slo * npix));
-        HIPCHK(launch_resist(c, c->I, d_target, ra, c->G, pr));
-        HIPCHK(launch_finish_resist(c, pr, resist_blocks(c), c->scal, nullptr));
-        HIPCHK(launch_adjoint(c, c->G, npix, slo, shi));
-        HIPCHK(launch_window_sum(c, slo, shi));
-        HIPCHK(launch_gradient(c, c->g, pm));
-        HIPCHK(launch_finish_dt(c, pm, (int)n_image_blocks(c), p->dt_mode, p->eta, p->dt_max, c->scal));
-        HIPCHK(launch_levelset(c, cur, c->g, nullptr, p->lambda, p->eps_kappa, c->scal, nxt, ps));
-        HIPCHK(launch_finish_step(c, ps, step_blocks(c), c->scal, nullptr,
-                                  d_trace ? d_trace + (size_t)i * ILT_TRACE_W : nullptr, i));
-        if (p->reinit_every > 0 && (i + 1) % p->reinit_every == 0)
+        {
+            PhaseTimer t(c, 0);
+            HIPCHK(launch_spectrum(c, cur, 1));
+        }
+        {
+            PhaseTimer t(c, 1);
+            HIPCHK(launch_make_Y(c, slo, shi));
+        }
+        {
+            PhaseTimer t(c, 2);
+            HIPCHK(launch_image_to(c, slo, shi, c->I + (size_t)slo * npix));
+        }
+        {
+            PhaseTimer t(c, 3);
+            HIPCHK(launch_resist(c, c->I, d_target, ra, c->G, pr));
+            HIPCHK(launch_finish_resist(c, pr, resist_blocks(c), c->scal, nullptr));
+        }
+        {
+            PhaseTimer t(c, 4);
+            HIPCHK(launch_adjoint(c, c->G, npix, slo, shi));
+        }
+        {
+            PhaseTimer t(c, 5);
+            HIPCHK(launch_window_sum(c, slo, shi));
+            HIPCHK(launch_gradient(c, c->g, pm));
+            HIPCHK(launch_finish_dt(c, pm, (int)n_image_blocks(c), p->dt_mode, p->eta, p->dt_max, c->scal));
+        }
+        {
+            PhaseTimer t(c, 6);
+            HIPCHK(launch_levelset(c, cur, c->g, nullptr, p->lambda, p->eps_kappa, c->scal, nxt, ps));
+            HIPCHK(launch_finish_step(c, ps, step_blocks(c), c->scal, nullptr,
+                                      d_trace ? d_trace + (size_t)i * ILT_TRACE_W : nullptr, i));
+        }
+        if (p->reinit_every > 0 && (i + 1) % p->reinit_every == 0) {
+            PhaseTimer t(c, 7);
             HIPCHK(launch_edt(c, nxt, nullptr, nxt, nullptr, p->d_lower, p->d_upper));
+        }
         std::swap(cur, nxt);
     }
     if (cur != d_phi) HIPCHK(launch_copy(c, d_phi, cur, npix));
@@ -414,5 +470,43 @@ extern "C" int ilt_solve(ilt_ctx *c, const unsigned char *d_target, float *d_phi
     }
     if (sc[SC_NONFIN] > 0.0 || !std::isfinite(sc[SC_LOSS]))
         return fail(ILT_ENUMERIC, "non-finite loss or gradient in the loop");
+    return ILT_OK;
+}
+
+extern "C" int ilt_profile(ilt_ctx *c, int enable) {
+    int r;
+    if ((r = check_ctx(c))) return r;
+    if (!enable) {
+        c->profiling = 0;
+        return ILT_OK;
+    }
+    if (!c->ev) {
+        const int cap = 4096;
+        c->ev = new hipEvent_t[2 * cap]();
+        c->ev_phase = new int[cap]();
+        c->ev_cap = cap;
+        for (int i = 0; i < 2 * cap; ++i)
+            if (hipEventCreate(&c->ev[i]) != hipSuccess) {
+                free_events(c);
+                return fail(ILT_EDEVICE, "hipEventCreate failed");
+            }
+    }
+    c->n_ev = 0;
+    c->profiling = 1;
+    return ILT_OK;
+}
+
+extern "C" int ilt_profile_read(ilt_ctx *c, double *h_out, int n) {
+    int r;
+    if ((r = check_ctx(c))) return r;
+    if (!h_out || n < 2 * ILT_N_PHASES) return fail(ILT_EINVAL, "h_out needs %d doubles", 2 * ILT_N_PHASES);
+    for (int i = 0; i < 2 * ILT_N_PHASES; ++i) h_out[i] = 0.0;
+    HIPCHK(hipStreamSynchronize(c->stream));
+    for (int i = 0; i < c->n_ev; ++i) {
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, c->ev[2 * i], c->ev[2 * i + 1]));
+        h_out[2 * c->ev_phase[i]] += ms;
+        h_out[2 * c->ev_phase[i] + 1] += 1.0;
+    }
     return ILT_OK;
 }

@@ -75,6 +75,13 @@ struct ilt_ctx {
     double *scal;      // device scalars (see SC_* below)
     int n_part;        // capacity of part (doubles)
     int n_wpart;       // capacity of Wpart (floats)
+
+    // measurement hook: event pairs per recorded launch
+    int profiling;
+    int n_ev;                 // events recorded in the current solve
+    int ev_cap;
+    hipEvent_t *ev;           // [ev_cap][2]
+    int *ev_phase;            // [ev_cap]
 };
 
 // device scalar slots

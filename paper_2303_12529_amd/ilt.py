@@ -21,6 +21,7 @@ ILT_OK, ILT_EINVAL, ILT_ENOMEM, ILT_EDEVICE, ILT_ENUMERIC, ILT_EUNSUPPORTED = 0,
 ILT_FP32 = 0
 TRACE_W = 8
 TRACE_COLUMNS = ("i", "loss", "l2", "pvb", "flips", "max_g", "dt", "t_ns")
+PHASES = ("spectrum", "window_rows", "image", "resist", "adjoint", "gradient", "levelset_step", "reinit")
 
 
 class IltError(RuntimeError):
@@ -73,6 +74,8 @@ def load_library(path: str = LIB_PATH):
         "levelset_step": [_VP, _VP, _VP, _VP, ctypes.POINTER(_Params), _VP],
         "edt_reinit": [_VP, _VP, _VP, _VP, _VP, ctypes.POINTER(_Params)],
         "ilt_solve": [_VP, _VP, _VP, ctypes.POINTER(_Params), ctypes.POINTER(_Report), _VP],
+        "ilt_profile": [_VP, ctypes.c_int],
+        "ilt_profile_read": [_VP, ctypes.POINTER(ctypes.c_double), ctypes.c_int],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -245,6 +248,17 @@ class Context:
         _check(rc)
         return dict(iters_done=rep.iters_done, status=rep.status, loss=rep.loss, l2=rep.l2, pvb=rep.pvb,
                     flips=rep.flips)
+
+
+    def profile(self, enable: bool = True):
+        """Turn the per-phase HIP-event timing of ilt_solve on or off."""
+        _check(load_library().ilt_profile(self._h, 1 if enable else 0))
+
+    def profile_read(self):
+        """{phase: (ms summed over the last ilt_solve, launches)}."""
+        buf = (ctypes.c_double * (2 * len(PHASES)))()
+        _check(load_library().ilt_profile_read(self._h, buf, len(buf)))
+        return {name: (buf[2 * i], int(buf[2 * i + 1])) for i, name in enumerate(PHASES)}
 
 
 # module-level names matching the C ABI
