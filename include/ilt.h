@@ -52,6 +52,15 @@ enum {
 
 enum { ILT_FP32 = 0 };
 
+/* ilt_optics.flags */
+enum {
+    /* Recompute the K coherent fields in the adjoint instead of storing them
+     * during the forward pass.  Storing needs n_sets * K * N^2 * 8 bytes of
+     * device memory (1.6 GB at N = 2048, K = 24, two sets) and halves the
+     * adjoint's matrix-core work; recomputing needs no such workspace. */
+    ILT_FLAG_RECOMPUTE_FIELDS = 1
+};
+
 /* Optical model, read at create time and copied to the device. */
 typedef struct {
     int N;                  /* grid side, 16 <= N <= 4096                     */
@@ -59,6 +68,7 @@ typedef struct {
     int K;                  /* kernels per set, 1 <= K <= 64                  */
     int n_sets;             /* focus conditions (kernel sets), 1 <= n <= 4    */
     int precision;          /* ILT_FP32                                       */
+    int flags;              /* ILT_FLAG_*                                     */
     const double *h_kernels;/* host [n_sets][K][P][P][2] (re, im)             */
     const double *h_weights;/* host [n_sets][K], each >= 0                    */
 } ilt_optics;

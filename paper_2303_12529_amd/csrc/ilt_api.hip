@@ -70,7 +70,7 @@ void free_events(ilt_ctx *c) {
 void free_ctx(ilt_ctx *c) {
     if (!c) return;
     free_events(c);
-    void *ptrs[] = {c->tl, c->tb, c->ta4, c->ar, c->ai, c->H, c->sw, c->coef, c->t1, c->S, c->Y, c->Tg,
+    void *ptrs[] = {c->tl, c->tb, c->ta4, c->ar, c->ai, c->H, c->sw, c->coef, c->Spart, c->S, c->Est, c->Y, c->Tg,
                     c->I, c->G, c->g, c->phi2, c->Wpart, c->W, c->edtg, c->part, c->scal};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
@@ -191,6 +191,7 @@ extern "C" int ilt_create(ilt_ctx **out, const ilt_optics *o, int max_batch, voi
     if (K < 1 || K > ILT_MAX_K) return fail(ILT_EINVAL, "K=%d outside [1, %d]", K, ILT_MAX_K);
     if (ns < 1 || ns > ILT_MAX_SETS) return fail(ILT_EINVAL, "n_sets=%d outside [1, %d]", ns, ILT_MAX_SETS);
     if (o->precision != ILT_FP32) return fail(ILT_EUNSUPPORTED, "precision %d not built", o->precision);
+    if (o->flags & ~ILT_FLAG_RECOMPUTE_FIELDS) return fail(ILT_EINVAL, "unknown flags 0x%x", o->flags);
     if (!o->h_kernels || !o->h_weights) return fail(ILT_EINVAL, "kernels or weights are null");
     for (int i = 0; i < ns * K; ++i)
         if (!(o->h_weights[i] >= 0.0) || !std::isfinite(o->h_weights[i]))
@@ -263,7 +264,8 @@ extern "C" int ilt_create(ilt_ctx **out, const ilt_optics *o, int max_batch, voi
     ALLOC(H, H.size());
     ALLOC(coef, coef.size());
     ALLOC(sw, sw.size());
-    ALLOC(t1, (size_t)Np * NZ);
+    ALLOC(Spart, (size_t)(Np / 16) * P * P);
+    if (!(o->flags & ILT_FLAG_RECOMPUTE_FIELDS)) ALLOC(Est, (size_t)ns * K * (Np / 16) * (Np / 16) * 512);
     ALLOC(S, (size_t)P * P);
     ALLOC(W, (size_t)P * P);
     ALLOC(Y, (size_t)ns * K * KP * Np);
@@ -317,7 +319,7 @@ extern "C" int litho_forward(ilt_ctx *c, const float *d_mask, int set, float *d_
     if (set < 0 || set >= c->n_sets) return fail(ILT_EINVAL, "set %d outside [0, %d)", set, c->n_sets);
     HIPCHK(launch_spectrum(c, d_mask, 0));
     HIPCHK(launch_make_Y(c, set, set + 1));
-    HIPCHK(launch_image_to(c, set, set + 1, d_aerial));
+    HIPCHK(launch_image_to(c, set, set + 1, d_aerial, 0));
     return ILT_OK;
 }
 
@@ -330,7 +332,9 @@ extern "C" int litho_adjoint(ilt_ctx *c, const float *d_mask, const float *d_G, 
     if (set < 0 || set >= c->n_sets) return fail(ILT_EINVAL, "set %d outside [0, %d)", set, c->n_sets);
     HIPCHK(launch_spectrum(c, d_mask, 0));
     HIPCHK(launch_make_Y(c, set, set + 1));
-    HIPCHK(launch_adjoint(c, d_G, 0, set, set + 1));
+    const int stored = c->Est != nullptr;
+    if (stored) HIPCHK(launch_image_to(c, set, set + 1, c->I + (size_t)set * c->N * c->N, 1));
+    HIPCHK(launch_adjoint(c, d_G, 0, set, set + 1, stored));
     HIPCHK(launch_window_sum(c, set, set + 1));
     HIPCHK(launch_gradient(c, d_out, c->part + part_max_off(c)));
     return ILT_OK;
@@ -404,6 +408,7 @@ extern "C" int ilt_solve(ilt_ctx *c, const unsigned char *d_target, float *d_phi
     const size_t npix = (size_t)c->N * c->N;
     double *pr = c->part + part_resist_off(c), *pm = c->part + part_max_off(c), *ps = c->part + part_step_off(c);
 
+    const int stored = c->Est != nullptr;
     c->n_ev = 0;
     if (p->init_mode == 0) {
         PhaseTimer t(c, 7);
@@ -421,7 +426,7 @@ extern "C" int ilt_solve(ilt_ctx *c, const unsigned char *d_target, float *d_phi
         }
         {
             PhaseTimer t(c, 2);
-            HIPCHK(launch_image_to(c, slo, shi, c->I + (size_t)slo * npix));
+            HIPCHK(launch_image_to(c, slo, shi, c->I + (size_t)slo * npix, stored));
         }
         {
             PhaseTimer t(c, 3);
@@ -430,7 +435,7 @@ extern "C" int ilt_solve(ilt_ctx *c, const unsigned char *d_target, float *d_phi
         }
         {
             PhaseTimer t(c, 4);
-            HIPCHK(launch_adjoint(c, c->G, npix, slo, shi));
+            HIPCHK(launch_adjoint(c, c->G, npix, slo, shi, stored));
         }
         {
             PhaseTimer t(c, 5);
@@ -454,7 +459,7 @@ extern "C" int ilt_solve(ilt_ctx *c, const unsigned char *d_target, float *d_phi
     // final metrics of [phi_T <= 0]
     HIPCHK(launch_spectrum(c, d_phi, 1));
     HIPCHK(launch_make_Y(c, slo, shi));
-    HIPCHK(launch_image_to(c, slo, shi, c->I + (size_t)slo * npix));
+    HIPCHK(launch_image_to(c, slo, shi, c->I + (size_t)slo * npix, 0));
     HIPCHK(launch_resist(c, c->I, d_target, ra, c->G, pr));
     HIPCHK(launch_finish_resist(c, pr, resist_blocks(c), c->scal, nullptr));
     double sc[SC_COUNT];

@@ -20,6 +20,9 @@
 //   ta4  [2][Np][AP]   Ar[a][y], Ai[a][y] stored [y][a]
 //   ar, ai [P][Np]     A = exp(-2 pi i ((f_a x) mod N) / N)
 //   Y    [n_sets][K][KP][Np]  window -> image operands, scaled sqrt(w_k)/N^2
+//   Est  [n_sets][K][Np/16][Np/16][2][64][4]  fields E_k in the matrix-core
+//        accumulator layout (real fragment, then imaginary), one 2 KB record
+//        per 16 x 16 block
 //
 // A is computed on the host in FP64 from the integer-reduced phase and
 // rounded once.
@@ -60,8 +63,9 @@ struct ilt_ctx {
     float2 *coef;      // [n_sets][K][P][P]   sqrt(w_k)/N^2 conj(H)
 
     // workspaces
-    float *t1;         // spectrum row transform [N/16 blocks][16][NZ]
+    double2 *Spart;    // spectrum band partials [Np/16][P][P]
     float2 *S;         // [P][P]
+    float *Est;        // stored fields [n_sets][K][Np/16][Np/16][2][64][4] (null: recompute)
     float *Y;          // [n_sets][K][KP][Np]
     float *Tg;         // [KP][Np]
     float *I;          // [n_sets][N][N]
@@ -103,8 +107,9 @@ struct resist_args {
 // ---- launchers (k_litho.hip) ----
 hipError_t launch_spectrum(ilt_ctx *c, const float *src, int src_is_phi);
 hipError_t launch_make_Y(ilt_ctx *c, int set_lo, int set_hi);
-hipError_t launch_image_to(ilt_ctx *c, int set_lo, int set_hi, float *out);
-hipError_t launch_adjoint(ilt_ctx *c, const float *G, size_t g_set_stride, int set_lo, int set_hi);
+hipError_t launch_image_to(ilt_ctx *c, int set_lo, int set_hi, float *out, int store_fields);
+hipError_t launch_adjoint(ilt_ctx *c, const float *G, size_t g_set_stride, int set_lo, int set_hi,
+                          int fields_stored);
 hipError_t launch_window_sum(ilt_ctx *c, int set_lo, int set_hi);
 hipError_t launch_gradient(ilt_ctx *c, float *g_out, double *maxpart);
 

@@ -13,7 +13,12 @@
 //   adjoint    V_k = A (G . E_k) A^T, W = sum_k c_k conj(H_k) . V_k
 //   gradient   g = 2 Re(A^H W conj(A))
 //
-// Layouts of the tables and workspaces are described in ilt_internal.h.
+// Matrix-core operand conventions (16x16x4 FP32): lane l supplies
+// A[m = l%16][k = l/16] and B[k = l/16][n = l%16]; accumulator register i of
+// lane l holds C[m = 4(l/16) + i][n = l%16].  The image kernel computes E^T
+// (m = x, n = y), so register i of lane l is E[y = l%16][x = 4(l/16) + i]:
+// exactly the A-operand the adjoint's row transform needs (k = x), and the
+// field fragments are stored and reloaded in that native layout.
 #include "ilt_internal.h"
 
 namespace {
@@ -24,15 +29,18 @@ __device__ __forceinline__ float wave_max(float v) {
 }
 
 // --------------------------------------------------------------------------
-// Spectrum, first half: T1[y][n] = sum_x M[y][x] tb0[x][n]  (row transform).
-// One block per 16-row band; 8 waves split the x range; the 8 partial
-// accumulators are summed in a fixed order through LDS.
-// src_is_phi: M = [phi <= 0]; else M = src (real mask).
+// Spectrum.  Block = one 16-row band, 8 waves splitting the columns:
+//   T1[y][n] = sum_x M[y][x] tb0[x][n]        (matrix cores; M = [phi<=0] or src)
+//   Spart[band][a][b] = sum_{y in band} A[a][y] T1[y][b]   (FP64)
+// Each lane loads four consecutive columns of its row as one float4 and uses
+// them in four consecutive k-steps; the B-operand rows follow the same
+// (x = 4(l/16) + e) order, so the sum is unchanged.
 // --------------------------------------------------------------------------
 template <int NZ>
-__global__ __launch_bounds__(512) void k_spectrum_rows(const float *__restrict__ src, int src_is_phi,
-                                                       const float *__restrict__ tb, int N, int Np,
-                                                       float *__restrict__ t1) {
+__global__ __launch_bounds__(512) void k_spectrum_band(const float *__restrict__ src, int src_is_phi,
+                                                       const float *__restrict__ tb, const float *__restrict__ ar,
+                                                       const float *__restrict__ ai, int P, int ZO, int N,
+                                                       int Np, double2 *__restrict__ Spart) {
     constexpr int NB = NZ / 16;
     __shared__ float red[8][16][NZ + 1];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -45,16 +53,30 @@ __global__ __launch_bounds__(512) void k_spectrum_rows(const float *__restrict__
     for (int nb = 0; nb < NB; ++nb) acc[nb] = f4{0.f, 0.f, 0.f, 0.f};
     const int y = y0 + l16;
     const bool yok = y < N;
-    for (int x = xa; x < xa + span; x += 4) {
-        const int xx = x + lq;
-        float m = 0.f;
-        if (yok && xx < N) {
-            const float v = src[(size_t)y * N + xx];
-            m = src_is_phi ? (v <= 0.f ? 1.f : 0.f) : v;
-        }
-        const float *brow = tb + (size_t)xx * NZ + l16;
+    const bool vec = (N % 4) == 0;
+    for (int x = xa; x < xa + span; x += 16) {
+        const int xx = x + 4 * lq;
+        float m[4] = {0.f, 0.f, 0.f, 0.f};
+        if (yok) {
+            if (vec && xx + 3 < N) {
+                const float4 v = *reinterpret_cast<const float4 *>(src + (size_t)y * N + xx);
+                m[0] = v.x; m[1] = v.y; m[2] = v.z; m[3] = v.w;
+            } else {
 #pragma unroll
-        for (int nb = 0; nb < NB; ++nb) acc[nb] = mfma4(m, brow[nb * 16], acc[nb]);
+                for (int e = 0; e < 4; ++e)
+                    if (xx + e < N) m[e] = src[(size_t)y * N + xx + e];
+            }
+            if (src_is_phi) {
+#pragma unroll
+                for (int e = 0; e < 4; ++e) m[e] = m[e] <= 0.f ? 1.f : 0.f;
+            }
+        }
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const float *brow = tb + (size_t)(xx + e) * NZ + l16;
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) acc[nb] = mfma4(m[e], brow[nb * 16], acc[nb]);
+        }
     }
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb)
@@ -66,74 +88,96 @@ __global__ __launch_bounds__(512) void k_spectrum_rows(const float *__restrict__
         float s = 0.f;
 #pragma unroll
         for (int w = 0; w < 8; ++w) s += red[w][r][n];
-        t1[((size_t)blockIdx.x * 16 + r) * NZ + n] = s;
+        red[0][r][n] = s;
+    }
+    __syncthreads();
+    // band partial of S = A T1, complex, FP64
+    for (int e = threadIdx.x; e < P * P; e += 512) {
+        const int a = e / P, b = e % P;
+        double sr = 0.0, si = 0.0;
+        for (int r = 0; r < 16; ++r) {
+            const int yy = y0 + r;
+            if (yy >= N) break;
+            const double c = ar[(size_t)a * Np + yy], s = ai[(size_t)a * Np + yy];
+            const double tr = red[0][r][b], ti = red[0][r][ZO + b];
+            sr += c * tr - s * ti;
+            si += c * ti + s * tr;
+        }
+        Spart[(size_t)blockIdx.x * P * P + e] = make_double2(sr, si);
     }
 }
 
-// Spectrum, second half: S[a][b] = sum_y A[a][y] T1[y][b] (complex), in FP64.
-// One block per window row a; four y-quarters reduced in a fixed order.
-__global__ __launch_bounds__(256) void k_spectrum_cols(const float *__restrict__ t1,
-                                                       const float *__restrict__ ar,
-                                                       const float *__restrict__ ai, int P, int N,
-                                                       int Np, int NZ, int ZO, float2 *__restrict__ S) {
-    __shared__ double sr[4][64], si[4][64];
-    const int a = blockIdx.x;
-    const int b = threadIdx.x & 63, q = threadIdx.x >> 6;
-    double accr = 0.0, acci = 0.0;
-    if (b < P) {
-        const int per = (N + 3) / 4;
-        const int ylo = q * per, yhi = min(N, ylo + per);
-        for (int y = ylo; y < yhi; ++y) {
-            const double c = ar[(size_t)a * Np + y], s = ai[(size_t)a * Np + y];
-            const double tr = t1[(size_t)y * NZ + b], ti = t1[(size_t)y * NZ + ZO + b];
-            accr += c * tr - s * ti;
-            acci += c * ti + s * tr;
+// Deterministic sum of n complex partial arrays: out[e] = sum_p part[p][e].
+// Block = 64 outputs x 16 partial groups; groups combined in a fixed order.
+template <typename T2>
+__global__ __launch_bounds__(1024) void k_psum(const T2 *__restrict__ part, int nparts, int n,
+                                               float2 *__restrict__ out) {
+    __shared__ double sr[16][64], si[16][64];
+    const int o = threadIdx.x & 63, g = threadIdx.x >> 6;
+    const int e = blockIdx.x * 64 + o;
+    double r = 0.0, i = 0.0;
+    if (e < n)
+        for (int p = g; p < nparts; p += 16) {
+            const T2 v = part[(size_t)p * n + e];
+            r += (double)v.x;
+            i += (double)v.y;
         }
-    }
-    sr[q][b] = accr;
-    si[q][b] = acci;
+    sr[g][o] = r;
+    si[g][o] = i;
     __syncthreads();
-    if (q == 0 && b < P) {
-        const double r = ((sr[0][b] + sr[1][b]) + sr[2][b]) + sr[3][b];
-        const double i = ((si[0][b] + si[1][b]) + si[2][b]) + si[3][b];
-        S[a * P + b] = make_float2((float)r, (float)i);
+    if (g == 0 && e < n) {
+        double a = 0.0, b = 0.0;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            a += sr[q][o];
+            b += si[q][o];
+        }
+        out[e] = make_float2((float)a, (float)b);
     }
 }
 
 // --------------------------------------------------------------------------
 // Window -> rows: out[j][r][x] = scale_j * sum_b U_j[a][b] conj(A[b][x]),
 // U_j = H_j . S (or U = S when H is null); rows r = a (real), P + a (imag).
-// Grid (Np/64, n_j, n_sets); each thread owns one x and a strided set of a.
+// Grid (Np/64, n_j, n_sets); 64 columns x 4 row groups per block; each
+// thread keeps the twiddles of its column in registers.
 // --------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_window_rows(const float2 *__restrict__ H, size_t h_set_stride,
-                                                     const float2 *__restrict__ S,
-                                                     const float *__restrict__ scale, size_t sc_set_stride,
-                                                     float scale_c, const float *__restrict__ ar,
-                                                     const float *__restrict__ ai, int P, int KP, int Np,
-                                                     int nj, int set_lo, float *__restrict__ out) {
+__global__ __launch_bounds__(256) void k_window_rows(const float2 *__restrict__ H, const float2 *__restrict__ S,
+                                                     const float *__restrict__ scale, float scale_c,
+                                                     const float *__restrict__ ar, const float *__restrict__ ai,
+                                                     int P, int KP, int Np, int nj, int set_lo,
+                                                     float *__restrict__ out) {
     __shared__ float2 U[ILT_MAX_P * ILT_MAX_P];
     const int j = blockIdx.y, s = set_lo + blockIdx.z;
     const int x = blockIdx.x * 64 + (threadIdx.x & 63);
     const int ag = threadIdx.x >> 6;
-    const float sc = scale ? scale[s * sc_set_stride + j] : scale_c;
     for (int e = threadIdx.x; e < P * P; e += 256) {
         float2 u = S[e];
         if (H) {
-            const float2 h = H[s * h_set_stride + (size_t)j * P * P + e];
+            const float2 h = H[((size_t)s * nj + j) * P * P + e];
             u = make_float2(h.x * u.x - h.y * u.y, h.x * u.y + h.y * u.x);
         }
         U[e] = u;
     }
+    float cr[ILT_MAX_P], ci[ILT_MAX_P];
+#pragma unroll
+    for (int b = 0; b < ILT_MAX_P; ++b) {
+        cr[b] = b < P ? ar[(size_t)b * Np + x] : 0.f;
+        ci[b] = b < P ? ai[(size_t)b * Np + x] : 0.f;
+    }
     __syncthreads();
+    const float sc = scale ? scale[(size_t)s * nj + j] : scale_c;
     float *o = out + ((size_t)(s * nj + j) * KP) * Np;
     for (int a = ag; a < P; a += 4) {
         float yr = 0.f, yi = 0.f;
-        for (int b = 0; b < P; ++b) {
-            const float c = ar[(size_t)b * Np + x], sn = ai[(size_t)b * Np + x];
-            const float2 u = U[a * P + b];
-            // u * conj(A) = (ur + i ui)(c - i sn)
-            yr = fmaf(u.x, c, fmaf(u.y, sn, yr));
-            yi = fmaf(u.y, c, fmaf(-u.x, sn, yi));
+#pragma unroll
+        for (int b = 0; b < ILT_MAX_P; ++b) {
+            if (b < P) {
+                const float2 u = U[a * P + b];
+                // u * conj(A) = (ur + i ui)(c - i sn)
+                yr = fmaf(u.x, cr[b], fmaf(u.y, ci[b], yr));
+                yi = fmaf(u.y, cr[b], fmaf(-u.x, ci[b], yi));
+            }
         }
         o[(size_t)a * Np + x] = sc * yr;
         o[(size_t)(P + a) * Np + x] = sc * yi;
@@ -141,102 +185,142 @@ __global__ __launch_bounds__(256) void k_window_rows(const float2 *__restrict__ 
 }
 
 // --------------------------------------------------------------------------
-// Image: E_j = A^H Y_j per 16x16 block with Re E = L1 Y, Im E = L2 Y.
+// Image: per 16x16 block, E_j^T = Y_j^T L^T with Re E = L1 Y, Im E = L2 Y.
 //   MODE 0: out = sum_j |E_j|^2      (aerial image of one kernel set)
 //   MODE 1: out = Re E_0             (gradient back-transform), plus the
 //           block maximum of |out| into maxpart[block].
+//   STORE:  also write every E_j fragment to Est in the accumulator layout
+//           [set][j][y/16][x/16][re|im][lane][4].
 // Block = 4 waves; block tile = 128 rows x 64 columns; wave tile = 32 x 64.
-// The image-side operands L1, L2 of a wave stay in registers for all j; the
-// Y_j tile of each j is staged through LDS and shared by the four waves.
+// The image-side operands (L rows of the wave's 32 y) stay in registers as
+// B-operands; each Y_j tile (KP x 64) is staged through LDS, double-buffered
+// with a register prefetch of the next j, and shared by the four waves.
 // --------------------------------------------------------------------------
-template <int KP, int MODE>
-__global__ __launch_bounds__(256) void k_image(const float *__restrict__ tl, const float *__restrict__ Y,
-                                               int nj, int N, int Np, int set_lo,
-                                               float *__restrict__ out, double *__restrict__ maxpart) {
+template <int KP, int MODE, bool STORE>
+__global__ __launch_bounds__(256, 2) void k_image(const float *__restrict__ tl, const float *__restrict__ Y,
+                                               int nj, int N, int Np, int set_lo, float *__restrict__ out,
+                                               double *__restrict__ maxpart, float *__restrict__ Est) {
     constexpr int KS = KP / 4;
     constexpr int LDW = 64 + 16;
-    __shared__ float Ys[KP][LDW];
+    constexpr int NV = (KP * 16 + 255) / 256;      // float4 per thread per tile
+    __shared__ float Ys[2][KP][LDW];
     __shared__ float wmax[4];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int l16 = lane & 15, lq = lane >> 4;
     const int s = set_lo + blockIdx.z;
     const int x0 = blockIdx.x * 64;
     const int yw = blockIdx.y * 128 + wave * 32;
+    const int NB16 = Np / 16;
 
-    float a1[2][KS], a2[2][KS];
+    float b1[2][KS], b2[2][KS];
 #pragma unroll
-    for (int mb = 0; mb < 2; ++mb)
+    for (int yb = 0; yb < 2; ++yb)
 #pragma unroll
         for (int ks = 0; ks < KS; ++ks) {
-            a1[mb][ks] = tl[(size_t)(4 * ks + lq) * Np + yw + 16 * mb + l16];
-            a2[mb][ks] = tl[(size_t)(KP + 4 * ks + lq) * Np + yw + 16 * mb + l16];
+            b1[yb][ks] = tl[(size_t)(4 * ks + lq) * Np + yw + 16 * yb + l16];
+            if (MODE == 0) b2[yb][ks] = tl[(size_t)(KP + 4 * ks + lq) * Np + yw + 16 * yb + l16];
         }
-    f4 accI[2][4];
+    f4 accI[4][2];
 #pragma unroll
-    for (int mb = 0; mb < 2; ++mb)
+    for (int xb = 0; xb < 4; ++xb)
 #pragma unroll
-        for (int nb = 0; nb < 4; ++nb) accI[mb][nb] = f4{0.f, 0.f, 0.f, 0.f};
+        for (int yb = 0; yb < 2; ++yb) accI[xb][yb] = f4{0.f, 0.f, 0.f, 0.f};
 
+    f4 pre[NV];
+#define IMG_FETCH(jj)                                                                                     \
+    do {                                                                                                  \
+        const float *Yj_ = Y + ((size_t)(s * nj + (jj)) * KP) * Np + x0;                                 \
+        _Pragma("unroll") for (int v = 0; v < NV; ++v) {                                                  \
+            const int e = threadIdx.x + 256 * v;                                                          \
+            if (e < KP * 16) pre[v] = *reinterpret_cast<const f4 *>(Yj_ + (size_t)(e >> 4) * Np + (e & 15) * 4); \
+        }                                                                                                 \
+    } while (0)
+#define IMG_STASH(bb)                                                                                     \
+    do {                                                                                                  \
+        _Pragma("unroll") for (int v = 0; v < NV; ++v) {                                                  \
+            const int e = threadIdx.x + 256 * v;                                                          \
+            if (e < KP * 16) *reinterpret_cast<f4 *>(&Ys[(bb)][e >> 4][(e & 15) * 4]) = pre[v];       \
+        }                                                                                                 \
+    } while (0)
+    IMG_FETCH(0);
+    IMG_STASH(0);
+    __syncthreads();
     for (int j = 0; j < nj; ++j) {
-        const float *Yj = Y + ((size_t)(s * nj + j) * KP) * Np + x0;
-        for (int e = threadIdx.x; e < KP * 16; e += 256) {
-            const int r = e >> 4, c4 = (e & 15) * 4;
-            const float4 v = *reinterpret_cast<const float4 *>(Yj + (size_t)r * Np + c4);
-            Ys[r][c4 + 0] = v.x;
-            Ys[r][c4 + 1] = v.y;
-            Ys[r][c4 + 2] = v.z;
-            Ys[r][c4 + 3] = v.w;
-        }
-        __syncthreads();
-        f4 er[2][4], ei[2][4];
+        const int buf = j & 1;
+        if (j + 1 < nj) IMG_FETCH(j + 1);
+        f4 er[4][2], ei[4][2];
 #pragma unroll
-        for (int mb = 0; mb < 2; ++mb)
+        for (int xb = 0; xb < 4; ++xb)
 #pragma unroll
-            for (int nb = 0; nb < 4; ++nb) {
-                er[mb][nb] = f4{0.f, 0.f, 0.f, 0.f};
-                ei[mb][nb] = f4{0.f, 0.f, 0.f, 0.f};
+            for (int yb = 0; yb < 2; ++yb) {
+                er[xb][yb] = f4{0.f, 0.f, 0.f, 0.f};
+                ei[xb][yb] = f4{0.f, 0.f, 0.f, 0.f};
             }
 #pragma unroll
         for (int ks = 0; ks < KS; ++ks) {
 #pragma unroll
-            for (int nb = 0; nb < 4; ++nb) {
-                const float b = Ys[4 * ks + lq][16 * nb + l16];
+            for (int xb = 0; xb < 4; ++xb) {
+                const float a = Ys[buf][4 * ks + lq][16 * xb + l16];
 #pragma unroll
-                for (int mb = 0; mb < 2; ++mb) {
-                    er[mb][nb] = mfma4(a1[mb][ks], b, er[mb][nb]);
-                    if (MODE == 0) ei[mb][nb] = mfma4(a2[mb][ks], b, ei[mb][nb]);
+                for (int yb = 0; yb < 2; ++yb) {
+                    er[xb][yb] = mfma4(a, b1[yb][ks], er[xb][yb]);
+                    if (MODE == 0) ei[xb][yb] = mfma4(a, b2[yb][ks], ei[xb][yb]);
                 }
             }
         }
+        if (STORE) {
 #pragma unroll
-        for (int mb = 0; mb < 2; ++mb)
+            for (int xb = 0; xb < 4; ++xb)
 #pragma unroll
-            for (int nb = 0; nb < 4; ++nb)
+                for (int yb = 0; yb < 2; ++yb) {
+                    const size_t blk = (((size_t)(s * nj + j) * NB16 + (yw / 16 + yb)) * NB16 + (x0 / 16 + xb));
+                    float *dst = Est + blk * 512 + lane * 4;
+                    *reinterpret_cast<f4 *>(dst) = er[xb][yb];
+                    *reinterpret_cast<f4 *>(dst + 256) = ei[xb][yb];
+                }
+        }
+#pragma unroll
+        for (int xb = 0; xb < 4; ++xb)
+#pragma unroll
+            for (int yb = 0; yb < 2; ++yb)
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
                     if (MODE == 0)
-                        accI[mb][nb][i] = fmaf(er[mb][nb][i], er[mb][nb][i],
-                                               fmaf(ei[mb][nb][i], ei[mb][nb][i], accI[mb][nb][i]));
+                        accI[xb][yb][i] = fmaf(er[xb][yb][i], er[xb][yb][i],
+                                               fmaf(ei[xb][yb][i], ei[xb][yb][i], accI[xb][yb][i]));
                     else
-                        accI[mb][nb][i] += er[mb][nb][i];
+                        accI[xb][yb][i] += er[xb][yb][i];
                 }
+        if (j + 1 < nj) IMG_STASH(buf ^ 1);
         __syncthreads();
     }
+#undef IMG_FETCH
+#undef IMG_STASH
     float m = 0.f;
     float *o = out + (size_t)blockIdx.z * N * N;
 #pragma unroll
-    for (int mb = 0; mb < 2; ++mb)
+    for (int xb = 0; xb < 4; ++xb)
 #pragma unroll
-        for (int nb = 0; nb < 4; ++nb)
+        for (int yb = 0; yb < 2; ++yb) {
+            const int y = yw + 16 * yb + l16;
+            const int x = x0 + 16 * xb + 4 * lq;
+            if (y < N) {
+                if ((N % 4) == 0 && x + 3 < N) {
+                    *reinterpret_cast<f4 *>(o + (size_t)y * N + x) = accI[xb][yb];
+                } else {
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int y = yw + 16 * mb + 4 * lq + i, x = x0 + 16 * nb + l16;
-                if (y < N && x < N) {
-                    const float v = accI[mb][nb][i];
-                    o[(size_t)y * N + x] = v;
-                    if (MODE == 1) m = (v != v) ? INFINITY : fmaxf(m, fabsf(v));
+                    for (int i = 0; i < 4; ++i)
+                        if (x + i < N) o[(size_t)y * N + x + i] = accI[xb][yb][i];
                 }
+                if (MODE == 1)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i)
+                        if (x + i < N) {
+                            const float v = accI[xb][yb][i];
+                            m = (v != v) ? INFINITY : fmaxf(m, fabsf(v));
+                        }
             }
+        }
     if (MODE == 1) {
         m = wave_max(m);
         if (lane == 0) wmax[wave] = m;
@@ -249,24 +333,198 @@ __global__ __launch_bounds__(256) void k_image(const float *__restrict__ tl, con
 }
 
 // --------------------------------------------------------------------------
-// Adjoint, fused with recomputation of the fields.
-// Block = (32-row tile, group of 4 kernels, set); wave w handles kernel
-// j = 4*group + w.  For each 32-column chunk:
+// Adjoint, shared tail: (d) V = A4 Z over the block's 32 rows, then
+// W_part += c_j conj(H_j) . V, summed over the four waves in a fixed order.
+// --------------------------------------------------------------------------
+template <int ZO>
+__device__ __forceinline__ void adjoint_tail(const f4 (&accZ)[2][2 * ZO / 16], bool jok, int j, int s, int K, int P,
+                                             int Np, int y0, const float *__restrict__ ta4,
+                                             const float2 *__restrict__ coef, float2 *Ws,
+                                             float *__restrict__ dst) {
+    constexpr int AB = ZO / 16, AP = ZO;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int l16 = lane & 15, lq = lane >> 4;
+    for (int e = threadIdx.x; e < P * P; e += 256) Ws[e] = make_float2(0.f, 0.f);
+    __syncthreads();
+    const float2 *cj = coef + ((size_t)s * K + (jok ? j : 0)) * P * P;
+    for (int ab = 0; ab < AB; ++ab) {
+        f4 vr[AB], vi[AB];
+#pragma unroll
+        for (int bb = 0; bb < AB; ++bb) {
+            vr[bb] = f4{0.f, 0.f, 0.f, 0.f};
+            vi[bb] = f4{0.f, 0.f, 0.f, 0.f};
+        }
+        if (jok) {
+#pragma unroll
+            for (int yb = 0; yb < 2; ++yb)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int y = y0 + 16 * yb + 4 * lq + i;
+                    const float car = ta4[(size_t)y * AP + 16 * ab + l16];
+                    const float cai = ta4[((size_t)Np + y) * AP + 16 * ab + l16];
+#pragma unroll
+                    for (int bb = 0; bb < AB; ++bb) {
+                        vr[bb] = mfma4(car, accZ[yb][bb][i], vr[bb]);
+                        vi[bb] = mfma4(cai, accZ[yb][bb][i], vi[bb]);
+                    }
+#pragma unroll
+                    for (int bb = 0; bb < AB; ++bb) {
+                        vr[bb] = mfma4(-cai, accZ[yb][bb + AB][i], vr[bb]);
+                        vi[bb] = mfma4(car, accZ[yb][bb + AB][i], vi[bb]);
+                    }
+                }
+        }
+        for (int w = 0; w < 4; ++w) {
+            if (wave == w && jok) {
+#pragma unroll
+                for (int bb = 0; bb < AB; ++bb)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const int a = 16 * ab + 4 * lq + i, b = 16 * bb + l16;
+                        if (a < P && b < P) {
+                            const float2 c = cj[a * P + b];
+                            const float xr = vr[bb][i], xi = vi[bb][i];
+                            float2 cur = Ws[a * P + b];
+                            cur.x += c.x * xr - c.y * xi;
+                            cur.y += c.x * xi + c.y * xr;
+                            Ws[a * P + b] = cur;
+                        }
+                    }
+            }
+            __syncthreads();
+        }
+    }
+    for (int e = threadIdx.x; e < P * P; e += 256) {
+        dst[2 * e] = Ws[e].x;
+        dst[2 * e + 1] = Ws[e].y;
+    }
+}
+
+// (c) for one 16-column block xb of a 32-column chunk: Z += (G . E) B3.
+template <int NB>
+__device__ __forceinline__ void adjoint_rows(f4 (&accZ)[2][NB], const f4 (&er)[2], const f4 (&ei)[2],
+                                             const float *Bre, const float *Bim, int ldb, int xb, int lq,
+                                             int l16) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int xr = 16 * xb + 4 * lq + i;
+        float br[NB], bi[NB];
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) {
+            br[nb] = Bre[xr * ldb + 16 * nb + l16];
+            bi[nb] = Bim[xr * ldb + 16 * nb + l16];
+        }
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+            for (int yb = 0; yb < 2; ++yb) accZ[yb][nb] = mfma4(er[yb][i], br[nb], accZ[yb][nb]);
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+            for (int yb = 0; yb < 2; ++yb) accZ[yb][nb] = mfma4(ei[yb][i], bi[nb], accZ[yb][nb]);
+    }
+}
+
+// --------------------------------------------------------------------------
+// Adjoint from stored fields.  Block = (32-row tile, group of 4 kernels,
+// set); wave w handles kernel j = 4*group + w and walks all columns in
+// 32-column chunks:
+//   X = G . E_j    (E_j fragments read in accumulator layout, G from LDS)
+//   Z += X B3      (E fragments are the A-operand as loaded; B3 from LDS)
+// then the shared tail.  G and B3 chunks and the next chunk's fragments are
+// prefetched into registers while the current chunk is multiplied.
+// --------------------------------------------------------------------------
+template <int ZO>
+__global__ __launch_bounds__(256, 2) void k_adjoint_st(const float *__restrict__ tb, const float *__restrict__ ta4,
+                                                    const float *__restrict__ Est, const float *__restrict__ G,
+                                                    size_t g_set_stride, const float2 *__restrict__ coef, int K,
+                                                    int P, int N, int Np, int set_lo, float *__restrict__ Wpart) {
+    constexpr int NZ = 2 * ZO, NB = NZ / 16;
+    constexpr int LDB = NZ + 4;
+    constexpr int NBV = (2 * 32 * NZ / 4) / 256;    // float4 of B3 per thread per chunk
+    __shared__ float Gs[32][36];
+    __shared__ float Bs[2][32][LDB];
+    __shared__ float2 Ws[ILT_MAX_P * ILT_MAX_P];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int l16 = lane & 15, lq = lane >> 4;
+    const int ytile = blockIdx.x, kg = blockIdx.y, srel = blockIdx.z, s = set_lo + srel;
+    const int y0 = ytile * 32;
+    const int j = kg * 4 + wave;
+    const bool jok = j < K;
+    const int NB16 = Np / 16;
+    const float *Gsrc = G + (size_t)s * g_set_stride;
+    const float *Ej = Est + (size_t)(s * K + (jok ? j : 0)) * NB16 * NB16 * 512;
+    const int nchunk = (N + 31) / 32;
+
+    f4 accZ[2][NB];
+#pragma unroll
+    for (int yb = 0; yb < 2; ++yb)
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) accZ[yb][nb] = f4{0.f, 0.f, 0.f, 0.f};
+
+    for (int c = 0; c < nchunk; ++c) {
+        const int x0 = c * 32;
+        __syncthreads();
+#pragma unroll
+        for (int v = 0; v < NBV; ++v) {
+            const int e = threadIdx.x + 256 * v;
+            const int part = e / (32 * NZ / 4), rem = e % (32 * NZ / 4);
+            const int xx = rem / (NZ / 4), c4 = (rem % (NZ / 4)) * 4;
+            *reinterpret_cast<float4 *>(&Bs[part][xx][c4]) =
+                *reinterpret_cast<const float4 *>(tb + ((size_t)part * Np + x0 + xx) * NZ + c4);
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int e = threadIdx.x + 256 * v;
+            const int yy = e >> 5, xx = e & 31;
+            const int gy = y0 + yy, gx = x0 + xx;
+            Gs[yy][xx] = (gy < N && gx < N) ? Gsrc[(size_t)gy * N + gx] : 0.f;
+        }
+        f4 e_[2][2][2];
+        if (jok) {
+#pragma unroll
+            for (int yb = 0; yb < 2; ++yb)
+#pragma unroll
+                for (int xb = 0; xb < 2; ++xb) {
+                    const float *src = Ej + (((size_t)(ytile * 2 + yb) * NB16) + (c * 2 + xb)) * 512 + lane * 4;
+                    e_[yb][xb][0] = __builtin_nontemporal_load(reinterpret_cast<const f4 *>(src));
+                    e_[yb][xb][1] = __builtin_nontemporal_load(reinterpret_cast<const f4 *>(src + 256));
+                }
+        }
+        __syncthreads();
+        if (jok) {
+#pragma unroll
+            for (int xb = 0; xb < 2; ++xb) {
+                f4 er[2], ei[2];
+#pragma unroll
+                for (int yb = 0; yb < 2; ++yb) {
+                    const float4 gv = *reinterpret_cast<const float4 *>(&Gs[16 * yb + l16][16 * xb + 4 * lq]);
+                    const f4 g4 = f4{gv.x, gv.y, gv.z, gv.w};
+                    er[yb] = e_[yb][xb][0] * g4;
+                    ei[yb] = e_[yb][xb][1] * g4;
+                }
+                adjoint_rows<NB>(accZ, er, ei, &Bs[0][0][0], &Bs[1][0][0], LDB, xb, lq, l16);
+            }
+        }
+    }
+    float *dst = Wpart + ((size_t)(srel * gridDim.x + ytile) * gridDim.y + kg) * P * P * 2;
+    adjoint_tail<ZO>(accZ, jok, j, s, K, P, Np, y0, ta4, coef, Ws, dst);
+}
+
+// --------------------------------------------------------------------------
+// Adjoint with the fields recomputed (no field store; half the matrix-core
+// throughput of the stored form but no N^2 K workspace):
 //   (a) E^T chunk = Y_j^T L^T     (A-operand streamed from Y_j, B in registers)
 //   (b) X = G . E                 (G tile staged in LDS)
-//   (c) Z += X B3                 (accumulator layout of (a) is fed straight
-//                                  in as the A-operand; B3 chunk in LDS)
-// after all chunks:
-//   (d) V = A4 Z (window rows), W_part += c_j conj(H_j) . V, summed over the
-//       four waves in a fixed order and written per block.
+//   (c) Z += X B3                 then the shared tail.
 // --------------------------------------------------------------------------
 template <int KP, int ZO>
-__global__ __launch_bounds__(256) void k_adjoint(const float *__restrict__ tl, const float *__restrict__ tb,
-                                                 const float *__restrict__ ta4, const float *__restrict__ Y,
-                                                 const float *__restrict__ G, size_t g_set_stride,
-                                                 const float2 *__restrict__ coef, int K, int P, int N,
-                                                 int Np, int set_lo, float *__restrict__ Wpart) {
-    constexpr int NZ = 2 * ZO, NB = NZ / 16, KS = KP / 4, AB = ZO / 16, AP = ZO;
+__global__ __launch_bounds__(256, 2) void k_adjoint_rc(const float *__restrict__ tl, const float *__restrict__ tb,
+                                                    const float *__restrict__ ta4, const float *__restrict__ Y,
+                                                    const float *__restrict__ G, size_t g_set_stride,
+                                                    const float2 *__restrict__ coef, int K, int P, int N, int Np,
+                                                    int set_lo, float *__restrict__ Wpart) {
+    constexpr int NZ = 2 * ZO, NB = NZ / 16, KS = KP / 4;
     constexpr int LDB = NZ + 4;
     __shared__ float Gs[32][33];
     __shared__ float Bs[2][32][LDB];
@@ -305,11 +563,8 @@ __global__ __launch_bounds__(256) void k_adjoint(const float *__restrict__ tl, c
             const int part = e / (32 * (NZ / 4));
             const int rem = e % (32 * (NZ / 4));
             const int xx = rem / (NZ / 4), c4 = (rem % (NZ / 4)) * 4;
-            const float4 v = *reinterpret_cast<const float4 *>(tb + ((size_t)part * Np + x0 + xx) * NZ + c4);
-            Bs[part][xx][c4 + 0] = v.x;
-            Bs[part][xx][c4 + 1] = v.y;
-            Bs[part][xx][c4 + 2] = v.z;
-            Bs[part][xx][c4 + 3] = v.w;
+            *reinterpret_cast<float4 *>(&Bs[part][xx][c4]) =
+                *reinterpret_cast<const float4 *>(tb + ((size_t)part * Np + x0 + xx) * NZ + c4);
         }
         __syncthreads();
         if (jok) {
@@ -331,7 +586,6 @@ __global__ __launch_bounds__(256) void k_adjoint(const float *__restrict__ tl, c
                         ei[yb] = mfma4(a, b2[yb][ks], ei[yb]);
                     }
                 }
-                // (b) multiply by G; er/ei register i holds E[y = 16yb + l16][x = 16xb + 4lq + i]
 #pragma unroll
                 for (int yb = 0; yb < 2; ++yb)
 #pragma unroll
@@ -340,99 +594,13 @@ __global__ __launch_bounds__(256) void k_adjoint(const float *__restrict__ tl, c
                         er[yb][i] *= gv;
                         ei[yb][i] *= gv;
                     }
-                // (c) Z[y][n] += sum_x X[y][x] B3[x][n]
-#pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const int xr = 16 * xb + 4 * lq + i;
-#pragma unroll
-                    for (int nb = 0; nb < NB; ++nb) {
-                        const float br = Bs[0][xr][16 * nb + l16];
-                        const float bi = Bs[1][xr][16 * nb + l16];
-#pragma unroll
-                        for (int yb = 0; yb < 2; ++yb) {
-                            accZ[yb][nb] = mfma4(er[yb][i], br, accZ[yb][nb]);
-                            accZ[yb][nb] = mfma4(ei[yb][i], bi, accZ[yb][nb]);
-                        }
-                    }
-                }
+                adjoint_rows<NB>(accZ, er, ei, &Bs[0][0][0], &Bs[1][0][0], LDB, xb, lq, l16);
             }
-        }
-        __syncthreads();
-    }
-
-    for (int e = threadIdx.x; e < P * P; e += 256) Ws[e] = make_float2(0.f, 0.f);
-    __syncthreads();
-    // (d) V[a][b] = sum_y A[a][y] Z[y][b]
-    f4 vr[AB][AB], vi[AB][AB];
-#pragma unroll
-    for (int ab = 0; ab < AB; ++ab)
-#pragma unroll
-        for (int bb = 0; bb < AB; ++bb) {
-            vr[ab][bb] = f4{0.f, 0.f, 0.f, 0.f};
-            vi[ab][bb] = f4{0.f, 0.f, 0.f, 0.f};
-        }
-    if (jok) {
-#pragma unroll
-        for (int yb = 0; yb < 2; ++yb)
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int y = y0 + 16 * yb + 4 * lq + i;
-#pragma unroll
-                for (int ab = 0; ab < AB; ++ab) {
-                    const float car = ta4[(size_t)y * AP + 16 * ab + l16];
-                    const float cai = ta4[((size_t)Np + y) * AP + 16 * ab + l16];
-#pragma unroll
-                    for (int bb = 0; bb < AB; ++bb) {
-                        const float zr = accZ[yb][bb][i];
-                        const float zi = accZ[yb][bb + ZO / 16][i];
-                        vr[ab][bb] = mfma4(car, zr, vr[ab][bb]);
-                        vr[ab][bb] = mfma4(-cai, zi, vr[ab][bb]);
-                        vi[ab][bb] = mfma4(cai, zr, vi[ab][bb]);
-                        vi[ab][bb] = mfma4(car, zi, vi[ab][bb]);
-                    }
-                }
-            }
-    }
-    const float2 *cj = coef + ((size_t)s * K + (jok ? j : 0)) * P * P;
-    for (int w = 0; w < 4; ++w) {
-        if (wave == w && jok) {
-#pragma unroll
-            for (int ab = 0; ab < AB; ++ab)
-#pragma unroll
-                for (int bb = 0; bb < AB; ++bb)
-#pragma unroll
-                    for (int i = 0; i < 4; ++i) {
-                        const int a = 16 * ab + 4 * lq + i, b = 16 * bb + l16;
-                        if (a < P && b < P) {
-                            const float2 c = cj[a * P + b];
-                            const float xr = vr[ab][bb][i], xi = vi[ab][bb][i];
-                            float2 cur = Ws[a * P + b];
-                            cur.x += c.x * xr - c.y * xi;
-                            cur.y += c.x * xi + c.y * xr;
-                            Ws[a * P + b] = cur;
-                        }
-                    }
         }
         __syncthreads();
     }
     float *dst = Wpart + ((size_t)(srel * gridDim.x + ytile) * gridDim.y + kg) * P * P * 2;
-    for (int e = threadIdx.x; e < P * P; e += 256) {
-        dst[2 * e] = Ws[e].x;
-        dst[2 * e + 1] = Ws[e].y;
-    }
-}
-
-// W[a][b] = sum over all adjoint partials, in FP64, fixed order.
-__global__ __launch_bounds__(256) void k_window_sum(const float *__restrict__ Wpart, int nparts, int P,
-                                                    float2 *__restrict__ W) {
-    const int e = blockIdx.x * 256 + threadIdx.x;
-    if (e >= P * P) return;
-    double r = 0.0, i = 0.0;
-    for (int p = 0; p < nparts; ++p) {
-        r += Wpart[((size_t)p * P * P + e) * 2];
-        i += Wpart[((size_t)p * P * P + e) * 2 + 1];
-    }
-    W[e] = make_float2((float)r, (float)i);
+    adjoint_tail<ZO>(accZ, jok, j, s, K, P, Np, y0, ta4, coef, Ws, dst);
 }
 
 }  // namespace
@@ -440,47 +608,58 @@ __global__ __launch_bounds__(256) void k_window_sum(const float *__restrict__ Wp
 // ---------------------------------------------------------------- launchers
 
 hipError_t launch_spectrum(ilt_ctx *c, const float *src, int src_is_phi) {
-    const int nyb = c->Np / 16;
+    const int nband = c->Np / 16;
     switch (c->NZ) {
-        case 32: k_spectrum_rows<32><<<nyb, 512, 0, c->stream>>>(src, src_is_phi, c->tb, c->N, c->Np, c->t1); break;
-        case 64: k_spectrum_rows<64><<<nyb, 512, 0, c->stream>>>(src, src_is_phi, c->tb, c->N, c->Np, c->t1); break;
-        case 96: k_spectrum_rows<96><<<nyb, 512, 0, c->stream>>>(src, src_is_phi, c->tb, c->N, c->Np, c->t1); break;
+        case 32: k_spectrum_band<32><<<nband, 512, 0, c->stream>>>(src, src_is_phi, c->tb, c->ar, c->ai, c->P, c->ZO, c->N, c->Np, c->Spart); break;
+        case 64: k_spectrum_band<64><<<nband, 512, 0, c->stream>>>(src, src_is_phi, c->tb, c->ar, c->ai, c->P, c->ZO, c->N, c->Np, c->Spart); break;
+        case 96: k_spectrum_band<96><<<nband, 512, 0, c->stream>>>(src, src_is_phi, c->tb, c->ar, c->ai, c->P, c->ZO, c->N, c->Np, c->Spart); break;
         default: return hipErrorInvalidValue;
     }
-    k_spectrum_cols<<<c->P, 256, 0, c->stream>>>(c->t1, c->ar, c->ai, c->P, c->N, c->Np, c->NZ, c->ZO, c->S);
+    const int n = c->P * c->P;
+    k_psum<double2><<<(n + 63) / 64, 1024, 0, c->stream>>>(c->Spart, nband, n, c->S);
     return hipGetLastError();
 }
 
 hipError_t launch_make_Y(ilt_ctx *c, int set_lo, int set_hi) {
     dim3 grid(c->Np / 64, c->K, set_hi - set_lo);
-    k_window_rows<<<grid, 256, 0, c->stream>>>(c->H, (size_t)c->K * c->P * c->P, c->S, c->sw, (size_t)c->K,
-                                               1.f, c->ar, c->ai, c->P, c->KP, c->Np, c->K, set_lo, c->Y);
+    k_window_rows<<<grid, 256, 0, c->stream>>>(c->H, c->S, c->sw, 1.f, c->ar, c->ai, c->P, c->KP, c->Np, c->K,
+                                               set_lo, c->Y);
     return hipGetLastError();
 }
 
-template <int MODE>
+template <int MODE, bool STORE>
 static hipError_t image_dispatch(ilt_ctx *c, const float *Y, int nj, int set_lo, int nsets, float *out,
                                  double *maxpart) {
     dim3 grid(c->Np / 64, c->Np / 128, nsets);
     switch (c->KP) {
-        case 8: k_image<8, MODE><<<grid, 256, 0, c->stream>>>(c->tl, Y, nj, c->N, c->Np, set_lo, out, maxpart); break;
-        case 24: k_image<24, MODE><<<grid, 256, 0, c->stream>>>(c->tl, Y, nj, c->N, c->Np, set_lo, out, maxpart); break;
-        case 40: k_image<40, MODE><<<grid, 256, 0, c->stream>>>(c->tl, Y, nj, c->N, c->Np, set_lo, out, maxpart); break;
-        case 72: k_image<72, MODE><<<grid, 256, 0, c->stream>>>(c->tl, Y, nj, c->N, c->Np, set_lo, out, maxpart); break;
+#define IMG(KP_) case KP_: k_image<KP_, MODE, STORE><<<grid, 256, 0, c->stream>>>(c->tl, Y, nj, c->N, c->Np, set_lo, out, maxpart, c->Est); break;
+        IMG(8) IMG(24) IMG(40) IMG(72)
+#undef IMG
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
-hipError_t launch_image_to(ilt_ctx *c, int set_lo, int set_hi, float *out) {
-    return image_dispatch<0>(c, c->Y, c->K, set_lo, set_hi - set_lo, out, nullptr);
+hipError_t launch_image_to(ilt_ctx *c, int set_lo, int set_hi, float *out, int store_fields) {
+    if (store_fields && c->Est) return image_dispatch<0, true>(c, c->Y, c->K, set_lo, set_hi - set_lo, out, nullptr);
+    return image_dispatch<0, false>(c, c->Y, c->K, set_lo, set_hi - set_lo, out, nullptr);
 }
 
-hipError_t launch_adjoint(ilt_ctx *c, const float *G, size_t g_set_stride, int set_lo, int set_hi) {
+hipError_t launch_adjoint(ilt_ctx *c, const float *G, size_t g_set_stride, int set_lo, int set_hi, int fields_stored) {
     dim3 grid((c->N + 31) / 32, (c->K + 3) / 4, set_hi - set_lo);
-#define ADJ(KP_, ZO_)                                                                                  \
-    k_adjoint<KP_, ZO_><<<grid, 256, 0, c->stream>>>(c->tl, c->tb, c->ta4, c->Y, G, g_set_stride, c->coef, \
-                                                     c->K, c->P, c->N, c->Np, set_lo, c->Wpart)
+    if (fields_stored) {
+        if (!c->Est) return hipErrorInvalidValue;
+#define ADJS(ZO_) k_adjoint_st<ZO_><<<grid, 256, 0, c->stream>>>(c->tb, c->ta4, c->Est, G, g_set_stride, c->coef, c->K, c->P, c->N, c->Np, set_lo, c->Wpart)
+        if (c->ZO == 16) ADJS(16);
+        else if (c->ZO == 32) ADJS(32);
+        else if (c->ZO == 48) ADJS(48);
+        else return hipErrorInvalidValue;
+#undef ADJS
+        return hipGetLastError();
+    }
+#define ADJ(KP_, ZO_)                                                                                    \
+    k_adjoint_rc<KP_, ZO_><<<grid, 256, 0, c->stream>>>(c->tl, c->tb, c->ta4, c->Y, G, g_set_stride, c->coef, \
+                                                        c->K, c->P, c->N, c->Np, set_lo, c->Wpart)
     if (c->KP == 8 && c->ZO == 16) ADJ(8, 16);
     else if (c->KP == 24 && c->ZO == 16) ADJ(24, 16);
     else if (c->KP == 40 && c->ZO == 16) ADJ(40, 16);
@@ -494,16 +673,18 @@ hipError_t launch_adjoint(ilt_ctx *c, const float *G, size_t g_set_stride, int s
 
 hipError_t launch_window_sum(ilt_ctx *c, int set_lo, int set_hi) {
     const int nparts = (set_hi - set_lo) * ((c->N + 31) / 32) * ((c->K + 3) / 4);
-    k_window_sum<<<(c->P * c->P + 255) / 256, 256, 0, c->stream>>>(c->Wpart, nparts, c->P, c->W);
+    const int n = c->P * c->P;
+    k_psum<float2><<<(n + 63) / 64, 1024, 0, c->stream>>>(reinterpret_cast<const float2 *>(c->Wpart), nparts, n,
+                                                         c->W);
     return hipGetLastError();
 }
 
 hipError_t launch_gradient(ilt_ctx *c, float *g_out, double *maxpart) {
     // Tg = 2 W conj(A) in the row layout, then g = Re(A^H Tg)
     dim3 grid(c->Np / 64, 1, 1);
-    k_window_rows<<<grid, 256, 0, c->stream>>>(nullptr, 0, c->W, nullptr, 0, 2.f, c->ar, c->ai, c->P, c->KP,
-                                               c->Np, 1, 0, c->Tg);
+    k_window_rows<<<grid, 256, 0, c->stream>>>(nullptr, c->W, nullptr, 2.f, c->ar, c->ai, c->P, c->KP, c->Np, 1, 0,
+                                               c->Tg);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    return image_dispatch<1>(c, c->Tg, 1, 0, 1, g_out, maxpart);
+    return image_dispatch<1, false>(c, c->Tg, 1, 0, 1, g_out, maxpart);
 }

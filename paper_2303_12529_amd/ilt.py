@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libilt.so")
 
 ILT_OK, ILT_EINVAL, ILT_ENOMEM, ILT_EDEVICE, ILT_ENUMERIC, ILT_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 ILT_FP32 = 0
+ILT_FLAG_RECOMPUTE_FIELDS = 1
 TRACE_W = 8
 TRACE_COLUMNS = ("i", "loss", "l2", "pvb", "flips", "max_g", "dt", "t_ns")
 PHASES = ("spectrum", "window_rows", "image", "resist", "adjoint", "gradient", "levelset_step", "reinit")
@@ -32,7 +33,8 @@ class IltError(RuntimeError):
 
 class _Optics(ctypes.Structure):
     _fields_ = [("N", ctypes.c_int), ("P", ctypes.c_int), ("K", ctypes.c_int), ("n_sets", ctypes.c_int),
-                ("precision", ctypes.c_int), ("h_kernels", ctypes.c_void_p), ("h_weights", ctypes.c_void_p)]
+                ("precision", ctypes.c_int), ("flags", ctypes.c_int), ("h_kernels", ctypes.c_void_p),
+                ("h_weights", ctypes.c_void_p)]
 
 
 class _Corner(ctypes.Structure):
@@ -149,7 +151,8 @@ def _ptr(t, dtype, shape, name, device):
 class Context:
     """A library context on the current torch CUDA (HIP) device and stream."""
 
-    def __init__(self, kernels: np.ndarray, weights: np.ndarray, N: int, precision: int = ILT_FP32):
+    def __init__(self, kernels: np.ndarray, weights: np.ndarray, N: int, precision: int = ILT_FP32,
+                 flags: int = 0):
         import torch
         lib = load_library()
         kernels = np.asarray(kernels)
@@ -162,7 +165,7 @@ class Context:
             raise ValueError("kernels must be [n_sets, K, P, P] and weights [n_sets, K]")
         kr = np.ascontiguousarray(np.stack([kernels.real, kernels.imag], axis=-1), dtype=np.float64)
         wr = np.ascontiguousarray(weights)
-        o = _Optics(N=int(N), P=int(P), K=int(K), n_sets=int(ns), precision=int(precision),
+        o = _Optics(N=int(N), P=int(P), K=int(K), n_sets=int(ns), precision=int(precision), flags=int(flags),
                     h_kernels=kr.ctypes.data, h_weights=wr.ctypes.data)
         self.device = torch.device("cuda", torch.cuda.current_device())
         self.stream = torch.cuda.current_stream(self.device)

@@ -109,14 +109,15 @@ def test_litho_forward_two_sets_select(ilt):
 ADJ_CASES = [(64, 3, 2), (64, 9, 4), (100, 9, 5), (200, 35, 6), (256, 21, 9), (384, 35, 24)]
 
 
+@pytest.mark.parametrize("flags", [0, 1])
 @pytest.mark.parametrize("N,P,K", ADJ_CASES)
-def test_litho_adjoint_parity(ilt, N, P, K):
-    _say("adjoint", N, P, K)
+def test_litho_adjoint_parity(ilt, N, P, K, flags):
+    _say("adjoint", N, P, K, "recompute" if flags else "stored")
     H, w = _rand_kernels(1, K, P, seed=N * 3 + P)
     rng = np.random.default_rng(N + K)
     M = random_mask(N, 0.3, seed=N + 1).astype(np.float32)
     G = rng.normal(size=(N, N)).astype(np.float32)
-    ctx = ilt.Context(H, w, N)
+    ctx = ilt.Context(H, w, N, flags=flags)
     out = ctx.litho_adjoint(_dev(M), _dev(G), 0).cpu().numpy()
     ref = o_litho.litho_adjoint(M.astype(np.float64), G.astype(np.float64), H[0], w[0])
     err = np.abs(out - ref).max() / np.abs(ref).max()

@@ -88,6 +88,20 @@ def test_c0_trajectory_band(ilt):
     assert rep["l2"] < l2o[0]
 
 
+def test_recompute_and_stored_fields_agree(ilt):
+    Z, H, w, prm = workload_inputs("c0", 4)
+    N = Z.shape[0]
+    outs = []
+    for flags in (0, ilt.ILT_FLAG_RECOMPUTE_FIELDS):
+        ctx = ilt.Context(H, w, N, flags=flags)
+        phi = torch.empty((N, N), dtype=torch.float32, device="cuda")
+        tr = torch.zeros((6, ilt.TRACE_W), dtype=torch.float64, device="cuda")
+        ctx.ilt_solve(_dev(Z, torch.uint8), phi, ilt.Params.from_dict(prm, iters=6), trace=tr)
+        outs.append((phi.cpu().numpy(), tr.cpu().numpy()))
+    np.testing.assert_array_equal(outs[0][1][:, 2], outs[1][1][:, 2])
+    assert np.abs(outs[0][0] - outs[1][0]).max() <= 1e-4
+
+
 def test_solve_deterministic_and_init_modes(ilt):
     Z, H, w, prm = workload_inputs("c0", 2)
     N = Z.shape[0]
