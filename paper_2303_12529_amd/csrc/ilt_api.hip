@@ -71,7 +71,7 @@ void free_ctx(ilt_ctx *c) {
     if (!c) return;
     free_events(c);
     void *ptrs[] = {c->tl, c->tb, c->ta4, c->ar, c->ai, c->H, c->sw, c->coef, c->Spart, c->S, c->Est, c->Y, c->Tg,
-                    c->I, c->G, c->g, c->phi2, c->Wpart, c->W, c->edtg, c->part, c->scal};
+                    c->I, c->G, c->g, c->phi2, c->Wpart, c->W, c->edtg, c->colbits, c->part, c->scal};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     delete c;
@@ -277,6 +277,7 @@ extern "C" int ilt_create(ilt_ctx **out, const ilt_optics *o, int max_batch, voi
     c->n_wpart = ns * ((N + 31) / 32) * ((K + 3) / 4) * P * P * 2;
     ALLOC(Wpart, (size_t)c->n_wpart);
     ALLOC(edtg, (size_t)N * N);
+    ALLOC(colbits, (size_t)((N + 31) / 32) * N);
     c->n_part = (int)part_total(c);
     ALLOC(part, (size_t)c->n_part);
     ALLOC(scal, (size_t)SC_COUNT);

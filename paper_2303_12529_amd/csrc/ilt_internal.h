@@ -75,6 +75,7 @@ struct ilt_ctx {
     float *Wpart;      // adjoint partials
     float2 *W;         // [P][P]
     uint32_t *edtg;    // [N][N] packed column distances
+    uint32_t *colbits; // [ceil(N/32)][N] class bits, 32 rows per word
     double *part;      // reduction partials (doubles)
     double *scal;      // device scalars (see SC_* below)
     int n_part;        // capacity of part (doubles)

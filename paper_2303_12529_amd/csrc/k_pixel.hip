@@ -2,6 +2,7 @@
 // exact squared EDT.  All reductions are two-stage with a fixed order (block
 // partials, then one block), so results are bitwise reproducible.
 #include <algorithm>
+#include <cmath>
 
 #include "ilt_internal.h"
 
@@ -227,68 +228,81 @@ __global__ __launch_bounds__(RB) void k_finish_step(const double *__restrict__ p
 // --------------------------------------------------------------------------
 // Exact squared EDT (Sec. II-A SDF, Sec. III-A TSDF, Alg. 1 CUDA_TSDF).
 //
-// Column pass: for every pixel, the distance along its column to the nearest
-// pixel of each class (0 = outside, 1 = inside), packed as two 16-bit fields
-// (0xFFFF = none).  One block per 64-column strip; its 16 waves split the
-// rows; class bits live in LDS.
+// Column pass, step 1: pack the class bits of every column, 32 rows per word:
+// colbits[w][x] bit b = [pixel (32w + b, x) is inside].
 // --------------------------------------------------------------------------
 constexpr uint32_t NONE16 = 0xFFFFu;
 
-__global__ __launch_bounds__(1024) void k_edt_cols(const float *__restrict__ phi, const uint8_t *__restrict__ mask,
-                                                   int N, uint32_t *__restrict__ gout) {
-    __shared__ uint32_t bits[ILT_MAX_N / 32][64];
-    __shared__ int fl[16][64][4];   // first0, last0, first1, last1 per segment
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int x = blockIdx.x * 64 + lane;
-    const bool xok = x < N;
-    const int seg = (N + 15) / 16;
-    const int ylo = w * seg, yhi = min(N, ylo + seg);
-    // class bits, 32 rows per word; each wave owns whole words when seg % 32 == 0,
-    // otherwise words are assembled after a barrier from per-row bytes below.
-    for (int e = threadIdx.x; e < (ILT_MAX_N / 32) * 64; e += 1024) (&bits[0][0])[e] = 0u;
-    __syncthreads();
-    int f0 = -1, l0 = -1, f1 = -1, l1 = -1;
-    for (int y = ylo; y < yhi; ++y) {
-        int cls = 0;
-        if (xok) cls = phi ? (phi[(size_t)y * N + x] <= 0.f) : (mask[(size_t)y * N + x] != 0);
-        if (cls) { if (f1 < 0) f1 = y; l1 = y; }
-        else { if (f0 < 0) f0 = y; l0 = y; }
-        // set bit y of this lane's column (atomics on LDS keep words shared by
-        // two segments correct)
-        if (cls) atomicOr(&bits[y >> 5][lane], 1u << (y & 31));
+__global__ __launch_bounds__(256) void k_edt_pack(const float *__restrict__ phi, const uint8_t *__restrict__ mask,
+                                                  int N, uint32_t *__restrict__ colbits) {
+    const int x = blockIdx.x * 256 + threadIdx.x;
+    const int w = blockIdx.y;
+    if (x >= N) return;
+    uint32_t bits = 0u;
+#pragma unroll 8
+    for (int b = 0; b < 32; ++b) {
+        const int y = 32 * w + b;
+        if (y < N) {
+            const bool in = phi ? (phi[(size_t)y * N + x] <= 0.f) : (mask[(size_t)y * N + x] != 0);
+            bits |= (in ? 1u : 0u) << b;
+        }
     }
-    fl[w][lane][0] = f0; fl[w][lane][1] = l0; fl[w][lane][2] = f1; fl[w][lane][3] = l1;
-    __syncthreads();
-    if (!xok || ylo >= yhi) return;
-    // nearest pixel of each class above / below this segment
-    int up0 = -1, up1 = -1, dn0 = -1, dn1 = -1;
-    for (int v = w - 1; v >= 0 && (up0 < 0 || up1 < 0); --v) {
-        if (up0 < 0 && fl[v][lane][1] >= 0) up0 = fl[v][lane][1];
-        if (up1 < 0 && fl[v][lane][3] >= 0) up1 = fl[v][lane][3];
+    colbits[(size_t)w * N + x] = bits;
+}
+
+// Column pass, step 2: for each pixel, the distance along its column to the
+// nearest pixel of each class (0 = outside, 1 = inside), packed as two 16-bit
+// fields (0xFFFF = none).  One thread per (column, 32-row word): the nearest
+// class pixels above and below the word come from a scan over whole words,
+// the rest from clz / ctz of the word itself.
+__device__ __forceinline__ uint32_t valid_bits(int w, int N) {
+    const int rows = N - 32 * w;
+    return rows >= 32 ? 0xFFFFFFFFu : ((1u << rows) - 1u);
+}
+
+__global__ __launch_bounds__(256) void k_edt_coldist(const uint32_t *__restrict__ colbits, int N,
+                                                     uint32_t *__restrict__ gout) {
+    const int x = blockIdx.x * 256 + threadIdx.x;
+    const int w = blockIdx.y;
+    if (x >= N) return;
+    const int W = (N + 31) / 32;
+    const uint32_t vm = valid_bits(w, N);
+    const uint32_t w1 = colbits[(size_t)w * N + x];
+    const uint32_t w0 = ~w1 & vm;
+    // nearest rows of each class strictly above this word / strictly below it
+    int up1 = -1, up0 = -1, dn1 = -1, dn0 = -1;
+    for (int v = w - 1; v >= 0 && (up1 < 0 || up0 < 0); --v) {
+        const uint32_t b1 = colbits[(size_t)v * N + x];
+        const uint32_t b0 = ~b1;                      // words above are full
+        if (up1 < 0 && b1) up1 = 32 * v + 31 - __clz(b1);
+        if (up0 < 0 && b0) up0 = 32 * v + 31 - __clz(b0);
     }
-    for (int v = w + 1; v < 16 && (dn0 < 0 || dn1 < 0); ++v) {
-        if (dn0 < 0 && fl[v][lane][0] >= 0) dn0 = fl[v][lane][0];
-        if (dn1 < 0 && fl[v][lane][2] >= 0) dn1 = fl[v][lane][2];
+    for (int v = w + 1; v < W && (dn1 < 0 || dn0 < 0); ++v) {
+        const uint32_t b1 = colbits[(size_t)v * N + x];
+        const uint32_t b0 = ~b1 & valid_bits(v, N);
+        if (dn1 < 0 && b1) dn1 = 32 * v + __ffs(b1) - 1;
+        if (dn0 < 0 && b0) dn0 = 32 * v + __ffs(b0) - 1;
     }
-    // downward sweep: distance to the nearest pixel above (or at) y
-    int p0 = up0, p1 = up1;
-    for (int y = ylo; y < yhi; ++y) {
-        const int cls = (bits[y >> 5][lane] >> (y & 31)) & 1;
-        if (cls) p1 = y; else p0 = y;
-        const uint32_t d0 = p0 >= 0 ? (uint32_t)(y - p0) : NONE16;
-        const uint32_t d1 = p1 >= 0 ? (uint32_t)(y - p1) : NONE16;
-        gout[(size_t)y * N + x] = d0 | (d1 << 16);
-    }
-    // upward sweep: merge with the nearest pixel below
-    int n0 = dn0, n1 = dn1;
-    for (int y = yhi - 1; y >= ylo; --y) {
-        const int cls = (bits[y >> 5][lane] >> (y & 31)) & 1;
-        if (cls) n1 = y; else n0 = y;
-        uint32_t v = gout[(size_t)y * N + x];
-        uint32_t d0 = v & 0xFFFFu, d1 = v >> 16;
-        if (n0 >= 0) d0 = min(d0, (uint32_t)(n0 - y));
-        if (n1 >= 0) d1 = min(d1, (uint32_t)(n1 - y));
-        gout[(size_t)y * N + x] = d0 | (d1 << 16);
+#pragma unroll 4
+    for (int b = 0; b < 32; ++b) {
+        const int y = 32 * w + b;
+        if (y >= N) break;
+        const uint32_t le = (b == 31) ? 0xFFFFFFFFu : ((2u << b) - 1u);   // bits <= b
+        uint32_t d[2];
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            const uint32_t word = c ? w1 : w0;
+            const int up = c ? up1 : up0, dn = c ? dn1 : dn0;
+            const uint32_t a = word & le;
+            const uint32_t bl = word & ~le;
+            int best = 0x7FFFFFFF;
+            if (a) best = min(best, b - (31 - __clz(a)));
+            else if (up >= 0) best = min(best, y - up);
+            if (bl) best = min(best, (__ffs(bl) - 1) - b);
+            else if (dn >= 0) best = min(best, dn - y);
+            d[c] = best == 0x7FFFFFFF ? NONE16 : (uint32_t)best;
+        }
+        gout[(size_t)y * N + x] = d[0] | (d[1] << 16);
     }
 }
 
@@ -310,102 +324,217 @@ __device__ float sqrt_minus_half(int D) {
 }
 
 // Row pass: for each row and class c, D_c(x) = min_x' f(x') + (x - x')^2,
-// f = g_c^2 (2^30 stand-in where the column has no class-c pixel).  The
-// cost matrix is Monge, so the leftmost minimiser is non-decreasing in x;
-// minimisers are found by bisection levels over x, each query scanning only
-// the candidate range between its neighbours' minimisers.  One wave per row.
+// f = g_c^2 (2^30 stand-in where the column has no class-c pixel).  The cost
+// matrix is Monge, so the leftmost minimiser is non-decreasing in x; the
+// minimisers are found level by level over x (stride halving), each query
+// searching only between its neighbours' minimisers.  The candidates of all
+// queries of a level are laid end to end and split evenly over the 64 lanes
+// of the row's wave; partial minima meet in LDS through a 64-bit atomic
+// minimum of (value, index), which keeps the leftmost minimiser.
 constexpr int FBIG = 1 << 30;
 
-__device__ __forceinline__ void argmin_combine(int &bv, int &bi, int ov, int oi) {
-    if (ov < bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
+struct RowLevel {
+    int s;      // stride (0: the two end points)
+    int N;
+    int nq;     // queries per class
+};
+
+// Query q of a level covers class q / nq; returns its pixel, candidate range
+// and the class arrays it reads.
+// arg and f hold both classes back to back: class c at [c * N, (c + 1) * N).
+__device__ __forceinline__ void query_of(const RowLevel &L, const int16_t *arg, int q, int &cls, int &xq,
+                                         int &lo, int &hi) {
+    cls = q >= L.nq;
+    const int qq = q - cls * L.nq;
+    if (L.s == 0) {
+        xq = qq ? L.N - 1 : 0;
+        lo = 0;
+        hi = L.N - 1;
+    } else {
+        xq = L.s * (2 * qq + 1);
+        lo = arg[cls * L.N + xq - L.s];
+        hi = arg[cls * L.N + min(xq + L.s, L.N - 1)];
+    }
 }
 
-__device__ void row_transform(const int *f, int16_t *arg, int N, int lane) {
-    // full scans for x = 0 and x = N-1
-    for (int q = 0; q < 2; ++q) {
-        const int x = q ? N - 1 : 0;
-        int bv = 0x7FFFFFFF, bi = 0x7FFFFFFF;
-        for (int c = lane; c < N; c += 64) {
-            const int v = f[c] + (x - c) * (x - c);
-            argmin_combine(bv, bi, v, c);
-        }
-        for (int o = 32; o > 0; o >>= 1) {
-            const int ov = __shfl_xor(bv, o), oi = __shfl_xor(bi, o);
-            argmin_combine(bv, bi, ov, oi);
-        }
-        if (lane == 0) arg[x] = (int16_t)bi;
-        __syncthreads();
+__device__ __forceinline__ void row_level(const RowLevel &L, const int *f, int16_t *arg, int *off,
+                                          unsigned long long *key, int lane) {
+    const int nq = 2 * L.nq;                  // both classes
+    const int qb = (nq + 63) / 64;
+    const int qlo = min(nq, lane * qb), qhi = min(nq, qlo + qb);
+    int sum = 0;
+    for (int q = qlo; q < qhi; ++q) {
+        int cls, xq, lo, hi;
+        query_of(L, arg, q, cls, xq, lo, hi);
+        sum += hi - lo + 1;
     }
-    int L = 1;
-    while (L < N - 1) L <<= 1;
-    for (int s = L >> 1; s >= 1; s >>= 1) {
-        // queries x = s, 3s, 5s, ... < N-1
+    int incl = sum;
+    for (int o = 1; o < 64; o <<= 1) {
+        const int t = __shfl_up(incl, o);
+        if (lane >= o) incl += t;
+    }
+    const int T = __shfl(incl, 63);
+    int run = incl - sum;
+    for (int q = qlo; q < qhi; ++q) {
+        int cls, xq, lo, hi;
+        query_of(L, arg, q, cls, xq, lo, hi);
+        off[q] = run;
+        run += hi - lo + 1;
+        key[q] = ~0ull;
+    }
+    __syncthreads();
+    const int C = (T + 63) / 64;
+    const int i0 = lane * C, i1 = min(T, i0 + C);
+    if (i0 < i1) {
+        int a = 0, b = nq - 1;                  // largest q with off[q] <= i0
+        while (a < b) {
+            const int m = (a + b + 1) >> 1;
+            if (off[m] <= i0) a = m; else b = m - 1;
+        }
+        int q = a, i = i0;
+        while (i < i1) {
+            int cls, xq, lo, hi;
+            query_of(L, arg, q, cls, xq, lo, hi);
+            const int *fc = f + cls * L.N;
+            const int cs = lo + (i - off[q]);
+            const int ce = min(hi, lo + (i1 - off[q]) - 1);
+            int bv = 0x7FFFFFFF, bi = 0;
+            int cnd = cs;
+            for (; cnd + 3 <= ce; cnd += 4) {
+                const int f0 = fc[cnd], f1 = fc[cnd + 1], f2 = fc[cnd + 2], f3 = fc[cnd + 3];
+                const int d0 = xq - cnd;
+                const int v0 = f0 + d0 * d0;
+                const int v1 = f1 + (d0 - 1) * (d0 - 1);
+                const int v2 = f2 + (d0 - 2) * (d0 - 2);
+                const int v3 = f3 + (d0 - 3) * (d0 - 3);
+                if (v0 < bv) { bv = v0; bi = cnd; }
+                if (v1 < bv) { bv = v1; bi = cnd + 1; }
+                if (v2 < bv) { bv = v2; bi = cnd + 2; }
+                if (v3 < bv) { bv = v3; bi = cnd + 3; }
+            }
+            for (; cnd <= ce; ++cnd) {
+                const int v = fc[cnd] + (xq - cnd) * (xq - cnd);
+                if (v < bv) { bv = v; bi = cnd; }
+            }
+            atomicMin(&key[q], ((unsigned long long)(unsigned)bv << 32) | (unsigned)bi);
+            i = off[q] + (hi - lo + 1);
+            ++q;
+        }
+    }
+    __syncthreads();
+    for (int q = lane; q < nq; q += 64) {
+        int cls, xq, lo, hi;
+        query_of(L, arg, q, cls, xq, lo, hi);
+        arg[cls * L.N + xq] = (int16_t)(key[q] & 0xFFFFFFFFull);
+    }
+    __syncthreads();
+}
+
+__device__ __forceinline__ void row_transform(const int *f, int16_t *arg, int *off, unsigned long long *key,
+                                              int N, int lane) {
+    row_level(RowLevel{0, N, N > 1 ? 2 : 1}, f, arg, off, key, lane);
+    int Lp = 1;
+    while (Lp < N - 1) Lp <<= 1;
+    for (int s = Lp >> 1; s >= 1; s >>= 1) {
         const int nq = (N - 1 > s) ? ((N - 1 - s + 2 * s - 1) / (2 * s)) : 0;
-        if (nq <= 0) continue;
-        int gq = 1;                       // lanes per query (power of two)
-        while (gq * 2 * nq <= 64 && gq < 64) gq <<= 1;
-        const int per_pass = 64 / gq;
-        for (int q0 = 0; q0 < nq; q0 += per_pass) {
-            const int qi = q0 + lane / gq;
-            const int sub = lane % gq;
-            int bv = 0x7FFFFFFF, bi = 0x7FFFFFFF;
-            int x = -1;
-            if (qi < nq) {
-                x = s * (2 * qi + 1);
-                const int lo = arg[x - s];
-                const int hi = arg[min(x + s, N - 1)];
-                for (int c = lo + sub; c <= hi; c += gq) {
-                    const int v = f[c] + (x - c) * (x - c);
-                    argmin_combine(bv, bi, v, c);
-                }
-            }
-            for (int o = gq >> 1; o > 0; o >>= 1) {
-                const int ov = __shfl_xor(bv, o), oi = __shfl_xor(bi, o);
-                argmin_combine(bv, bi, ov, oi);
-            }
-            if (qi < nq && sub == 0) arg[x] = (int16_t)bi;
-        }
-        __syncthreads();
+        if (nq > 0) row_level(RowLevel{s, N, nq}, f, arg, off, key, lane);
     }
 }
 
+// Both classes of one row per 64-lane block.  LDS: packed column distances,
+// f and minimisers for each class, and the level's query offsets and keys.
 __global__ __launch_bounds__(64) void k_edt_rows(const uint32_t *__restrict__ gin, int N, float d_lower,
                                                  float d_upper, float *__restrict__ phi_out,
                                                  int *__restrict__ sqdist) {
-    extern __shared__ unsigned char smem[];
-    uint32_t *gr = reinterpret_cast<uint32_t *>(smem);            // [N]
-    int *f = reinterpret_cast<int *>(gr + N);                     // [N]
-    int16_t *arg = reinterpret_cast<int16_t *>(f + N);            // [N]
+    extern __shared__ unsigned long long smem_u64[];
+    const int nqmax = 2 * (N / 2 + 2);
+    unsigned long long *key = smem_u64;                           // [nqmax]
+    uint32_t *gr = reinterpret_cast<uint32_t *>(key + nqmax);     // [N]
+    int *f0 = reinterpret_cast<int *>(gr + N);                    // [N]
+    int *f1 = f0 + N;                                             // [N]
+    int *off = f1 + N;                                            // [nqmax]
+    int16_t *a0 = reinterpret_cast<int16_t *>(off + nqmax);       // [N]
+    int16_t *a1 = a0 + N;                                         // [N]
     const int y = blockIdx.x, lane = threadIdx.x;
-    for (int x = lane; x < N; x += 64) gr[x] = gin[(size_t)y * N + x];
+    const uint32_t *grow = gin + (size_t)y * N;
+    for (int x = lane; x < N; x += 64) {
+        const uint32_t g = grow[x];
+        gr[x] = g;
+        const uint32_t g0 = g & 0xFFFFu, g1 = g >> 16;
+        f0[x] = (g0 == NONE16) ? FBIG : (int)(g0 * g0);
+        f1[x] = (g1 == NONE16) ? FBIG : (int)(g1 * g1);
+    }
     __syncthreads();
-    for (int c = 0; c < 2; ++c) {
-        for (int x = lane; x < N; x += 64) {
-            const uint32_t g = c ? (gr[x] >> 16) : (gr[x] & 0xFFFFu);
-            f[x] = (g == NONE16) ? FBIG : (int)(g * g);
+    row_transform(f0, a0, off, key, N, lane);
+    for (int x = lane; x < N; x += 64) {
+        const bool inside = (gr[x] >> 16) == 0;        // distance 0 to class 1
+        // inside pixels need the distance to class 0 (D_out), outside to class 1 (D_in)
+        const int c0 = a0[x], c1 = a1[x];
+        const int D0 = f0[c0] + (x - c0) * (x - c0);
+        const int D1 = f1[c1] + (x - c1) * (x - c1);
+        if (sqdist) {
+            sqdist[(size_t)y * N + x] = D1 >= FBIG ? 0x7FFFFFFF : D1;
+            sqdist[(size_t)N * N + (size_t)y * N + x] = D0 >= FBIG ? 0x7FFFFFFF : D0;
         }
-        __syncthreads();
-        row_transform(f, arg, N, lane);
-        for (int x = lane; x < N; x += 64) {
-            const int a = arg[x];
-            const int D = f[a] + (x - a) * (x - a);
-            const bool none = D >= FBIG;
-            const bool inside = (gr[x] >> 16) == 0;        // distance 0 to class 1
-            if (sqdist) {
-                // c = 1: distance to inside pixels (D_in); c = 0: to outside (D_out)
-                int *dst = sqdist + (size_t)(1 - c) * N * N;
-                dst[(size_t)y * N + x] = none ? 0x7FFFFFFF : D;
-            }
-            if (c == 0 && inside) {          // inside pixel: 1/2 - sqrt(D_out)
-                const float v = none ? d_lower : -sqrt_minus_half(D);
-                phi_out[(size_t)y * N + x] = fminf(fmaxf(v, d_lower), d_upper);
-            }
-            if (c == 1 && !inside) {         // outside pixel: sqrt(D_in) - 1/2
-                const float v = none ? d_upper : sqrt_minus_half(D);
-                phi_out[(size_t)y * N + x] = fminf(fmaxf(v, d_lower), d_upper);
+        float v;
+        if (inside) v = D0 >= FBIG ? d_lower : -sqrt_minus_half(D0);
+        else v = D1 >= FBIG ? d_upper : sqrt_minus_half(D1);
+        phi_out[(size_t)y * N + x] = fminf(fmaxf(v, d_lower), d_upper);
+    }
+}
+
+// Row pass for a clipped TSDF only (no squared-distance output).  A pixel
+// needs its exact D only while sqrt(D) - 1/2 stays inside the clip bound B,
+// i.e. D <= Rb^2 with Rb = bound + 1/2.  Each pixel scans candidate columns
+// outward from its own, x' = x +- d: every scanned candidate is an upper
+// bound of D, and the scan stops once d^2 >= best (nothing farther can beat
+// it) or d passes floor(Rb) (a minimiser with D <= Rb^2 lies within that
+// window).  So the result is exact whenever it is at most Rb^2, and above
+// Rb^2 only when D is; such pixels take the clip value.  One block per row.
+__global__ __launch_bounds__(256) void k_edt_rows_clip(const uint32_t *__restrict__ gin, int N, int pad,
+                                                       float d_lower, float d_upper, float *__restrict__ phi_out) {
+    // each class row is stored with `pad` sentinel entries on both sides, so
+    // the scan needs no bounds checks (sentinels never win: FBIG >= any bound)
+    extern __shared__ int fsh[];
+    const int W = N + 2 * pad;
+    int *f0 = fsh + pad;          // squared column distance to class 0 (FBIG: none)
+    int *f1 = fsh + W + pad;      // ... to class 1
+    const int y = blockIdx.x;
+    const uint32_t *grow = gin + (size_t)y * N;
+    for (int i = threadIdx.x; i < 2 * W; i += 256) fsh[i] = FBIG;
+    __syncthreads();
+    for (int x = threadIdx.x; x < N; x += 256) {
+        const uint32_t g = grow[x];
+        const uint32_t g0 = g & 0xFFFFu, g1 = g >> 16;
+        f0[x] = (g0 == NONE16) ? FBIG : (int)(g0 * g0);
+        f1[x] = (g1 == NONE16) ? FBIG : (int)(g1 * g1);
+    }
+    __syncthreads();
+    const int r_out = (int)floorf(d_upper + 0.5f);     // outside pixels: bound d_upper
+    const int r_in = (int)floorf(-d_lower + 0.5f);     // inside pixels: bound |d_lower|
+    for (int x = threadIdx.x; x < N; x += 256) {
+        const bool inside = f1[x] == 0;
+        const int *fc = inside ? f0 : f1;
+        const int R = min(inside ? r_in : r_out, pad - 8);
+        int best = fc[x];
+        int d = 1, q = 1;                               // q = d^2
+        while (d <= R && q < best) {
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                best = min(best, min(fc[x - d], fc[x + d]) + q);
+                q += 2 * d + 1;
+                ++d;
             }
         }
-        __syncthreads();
+        const float rb = inside ? (-d_lower + 0.5f) : (d_upper + 0.5f);
+        float v;
+        if ((double)best > (double)rb * (double)rb) {
+            v = inside ? d_lower : d_upper;
+        } else {
+            const float t = sqrt_minus_half(best);
+            v = inside ? -t : t;
+        }
+        phi_out[(size_t)y * N + x] = fminf(fmaxf(v, d_lower), d_upper);
     }
 }
 
@@ -480,10 +609,23 @@ hipError_t launch_finish_step(ilt_ctx *c, const double *part, int nblk, double *
 hipError_t launch_edt(ilt_ctx *c, const float *phi, const uint8_t *mask, float *phi_out, int *sqdist,
                       float d_lower, float d_upper) {
     const int N = c->N;
-    k_edt_cols<<<(N + 63) / 64, 1024, 0, c->stream>>>(phi, mask, N, c->edtg);
+    const dim3 grid((N + 255) / 256, (N + 31) / 32);
+    k_edt_pack<<<grid, 256, 0, c->stream>>>(phi, mask, N, c->colbits);
+    k_edt_coldist<<<grid, 256, 0, c->stream>>>(c->colbits, N, c->edtg);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const size_t sm = (size_t)N * (4 + 4 + 2);
+    if (!sqdist) {
+        // sentinel padding covers the largest clip radius plus one unrolled step
+        const int r = (int)std::ceil(std::max(d_upper, -d_lower) + 0.5f);
+        const int pad = std::min(r, N) + 8;
+        const size_t sm = (size_t)(N + 2 * pad) * 2 * sizeof(int);
+        if (sm <= 160 * 1024) {
+            k_edt_rows_clip<<<N, 256, sm, c->stream>>>(c->edtg, N, pad, d_lower, d_upper, phi_out);
+            return hipGetLastError();
+        }
+    }
+    const int nqmax = 2 * (N / 2 + 2);
+    const size_t sm = (size_t)nqmax * 8 + (size_t)N * 4 * 3 + (size_t)nqmax * 4 + (size_t)N * 2 * 2;
     k_edt_rows<<<N, 64, sm, c->stream>>>(c->edtg, N, d_lower, d_upper, phi_out, sqdist);
     return hipGetLastError();
 }

@@ -186,6 +186,9 @@ def test_edt_bit_exact(ilt, N, dens):
     np.testing.assert_array_equal(sq[0], np.where(d_in < 0, big, d_in))
     np.testing.assert_array_equal(sq[1], np.where(d_out < 0, big, d_out))
     np.testing.assert_array_equal(phi, ref_phi.astype(np.float32))
+    # the clip-bounded row pass (no squared-distance output) gives the same phi
+    phi2 = ctx.edt_reinit(p, mask=_dev(m, torch.uint8)).cpu().numpy()
+    np.testing.assert_array_equal(phi2, ref_phi.astype(np.float32))
 
 
 def test_edt_from_phi_and_in_place(ilt):
@@ -223,12 +226,17 @@ def test_sqrt_rounding_all_small_distances(ilt):
     H, w = _rand_kernels(1, 1, 3, seed=0)
     ctx = ilt.Context(H, w, N)
     p = ilt.Params(d_lower=-1e6, d_upper=1e6)
-    phi = ctx.edt_reinit(p, mask=_dev(m, torch.uint8)).cpu().numpy()
+    sq = torch.empty((2, N, N), dtype=torch.int32, device="cuda")
+    phi = ctx.edt_reinit(p, mask=_dev(m, torch.uint8), sqdist=sq).cpu().numpy()
     yy, xx = np.mgrid[0:N, 0:N]
     D = (yy ** 2 + xx ** 2).astype(np.float64)
     ref = (np.sqrt(D) - 0.5).astype(np.float32)
     ref[0, 0] = np.float32(0.5 - 1.0)   # the pixel itself: nearest outside pixel at distance 1
     np.testing.assert_array_equal(phi, ref)
+    # clip-bounded path with a tight bound: exact inside the bound, clipped outside
+    p2 = ilt.Params(d_lower=-3.0, d_upper=700.25)
+    phi2 = ctx.edt_reinit(p2, mask=_dev(m, torch.uint8)).cpu().numpy()
+    np.testing.assert_array_equal(phi2, np.clip(ref, np.float32(-3.0), np.float32(700.25)))
 
 
 STEP_CASES = [(64, 0.05, 0), (200, 0.05, 0), (256, 0.9, 0), (130, 0.05, 1), (2048, 0.05, 0)]
