@@ -204,12 +204,14 @@ extern "C" int ilt_create(ilt_ctx **out, const ilt_optics *o, int max_batch, voi
     c->N = N; c->P = P; c->K = K; c->n_sets = ns; c->precision = o->precision;
     c->Np = round_up(N, 128);
     c->KP = pick_kp(P);
-    c->ZO = round_up(P, 16);
-    c->NZ = 2 * c->ZO;
-    c->AP = c->ZO;
+    c->FB = P / 16;
+    c->MIX = (P % 16) != 0 && (P % 16) <= 8;
+    if ((P % 16) > 8) c->FB += 1;
+    c->NZ = 32 * c->FB + 16 * c->MIX;
+    c->AP = round_up(P, 16);
     c->stream = static_cast<hipStream_t>(stream);
     if (hipGetDevice(&c->device) != hipSuccess) { free_ctx(c); return fail(ILT_EDEVICE, "hipGetDevice failed"); }
-    const int Np = c->Np, KP = c->KP, NZ = c->NZ, ZO = c->ZO, AP = c->AP;
+    const int Np = c->Np, KP = c->KP, NZ = c->NZ, FB = c->FB, AP = c->AP;
 
     // DFT window matrix A[a][x] = exp(-2 pi i ((f_a x) mod N)/N), FP64 then rounded
     std::vector<float> ar((size_t)P * Np, 0.f), ai((size_t)P * Np, 0.f);
@@ -232,10 +234,10 @@ extern "C" int ilt_create(ilt_ctx **out, const ilt_optics *o, int max_batch, voi
             tl[(size_t)(P + r) * Np + y] = s_;                 // L1, imaginary rows
             tl[(size_t)(KP + r) * Np + y] = -s_;               // L2, real rows
             tl[(size_t)(KP + P + r) * Np + y] = c_;            // L2, imaginary rows
-            tb[(size_t)y * NZ + r] = c_;                       // part 0: Re -> (Re, Im)
-            tb[(size_t)y * NZ + ZO + r] = s_;
-            tb[((size_t)Np + y) * NZ + r] = -s_;               // part 1: Im -> (Re, Im)
-            tb[((size_t)Np + y) * NZ + ZO + r] = c_;
+            tb[(size_t)y * NZ + win_re(r, FB)] = c_;           // part 0: Re -> (Re, Im)
+            tb[(size_t)y * NZ + win_im(r, FB)] = s_;
+            tb[((size_t)Np + y) * NZ + win_re(r, FB)] = -s_;   // part 1: Im -> (Re, Im)
+            tb[((size_t)Np + y) * NZ + win_im(r, FB)] = c_;
             ta4[(size_t)y * AP + r] = c_;
             ta4[((size_t)Np + y) * AP + r] = s_;
         }

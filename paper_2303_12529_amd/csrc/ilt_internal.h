@@ -6,8 +6,13 @@
 //
 //   KP  = 2P rounded up to a multiple of 8 (real inner dimension of the
 //         window transforms: rows [0,P) real parts, [P,2P) imaginary parts)
-//   ZO  = P rounded up to 16; NZ = 2 ZO (window columns of the adjoint's
-//         row transform: [0,P) real, [ZO, ZO+P) imaginary)
+//   window columns of the row transform (spectrum and adjoint), NZ of them:
+//         FB = P / 16 full 16-column blocks of real parts followed by FB
+//         blocks of imaginary parts; when 0 < P % 16 <= 8 the leftover real
+//         and imaginary columns share one more block (real at lanes 0..7,
+//         imaginary at lanes 8..15: MIX = 1); when P % 16 > 8 they get a
+//         padded pair of blocks (FB rounded up, MIX = 0).
+//         NZ = 32 FB + 16 MIX; column of (b, real) = win_re(b), (b, imag) = win_im(b).
 //   AP  = P rounded up to 16
 //
 //   tl   [2][KP][Np]   L1^T, L2^T: rows r of the image-side transform
@@ -40,6 +45,11 @@
 
 typedef float f4 __attribute__((ext_vector_type(4)));
 
+__host__ __device__ __forceinline__ int win_re(int b, int FB) { return b < 16 * FB ? b : 32 * FB + (b - 16 * FB); }
+__host__ __device__ __forceinline__ int win_im(int b, int FB) {
+    return b < 16 * FB ? 16 * FB + b : 32 * FB + 8 + (b - 16 * FB);
+}
+
 // 16x16x4 FP32 matrix-core step.  Lane l supplies A[m = l%16][k = l/16] and
 // B[k = l/16][n = l%16]; accumulator register i of lane l is
 // C[m = 4*(l/16) + i][n = l%16].
@@ -49,7 +59,7 @@ __device__ __forceinline__ f4 mfma4(float a, float b, f4 c) {
 
 struct ilt_ctx {
     int N, P, K, n_sets, precision;
-    int Np, KP, ZO, NZ, AP;
+    int Np, KP, FB, MIX, NZ, AP;
     int device;
     hipStream_t stream;
 

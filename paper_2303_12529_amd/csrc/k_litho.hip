@@ -36,11 +36,12 @@ __device__ __forceinline__ float wave_max(float v) {
 // them in four consecutive k-steps; the B-operand rows follow the same
 // (x = 4(l/16) + e) order, so the sum is unchanged.
 // --------------------------------------------------------------------------
-template <int NZ>
+template <int FB, int MIX>
 __global__ __launch_bounds__(512) void k_spectrum_band(const float *__restrict__ src, int src_is_phi,
                                                        const float *__restrict__ tb, const float *__restrict__ ar,
-                                                       const float *__restrict__ ai, int P, int ZO, int N,
+                                                       const float *__restrict__ ai, int P, int N,
                                                        int Np, double2 *__restrict__ Spart) {
+    constexpr int NZ = 32 * FB + 16 * MIX;
     constexpr int NB = NZ / 16;
     __shared__ float red[8][16][NZ + 1];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -99,7 +100,7 @@ __global__ __launch_bounds__(512) void k_spectrum_band(const float *__restrict__
             const int yy = y0 + r;
             if (yy >= N) break;
             const double c = ar[(size_t)a * Np + yy], s = ai[(size_t)a * Np + yy];
-            const double tr = red[0][r][b], ti = red[0][r][ZO + b];
+            const double tr = red[0][r][win_re(b, FB)], ti = red[0][r][win_im(b, FB)];
             sr += c * tr - s * ti;
             si += c * ti + s * tr;
         }
@@ -336,21 +337,22 @@ __global__ __launch_bounds__(256, 2) void k_image(const float *__restrict__ tl, 
 // Adjoint, shared tail: (d) V = A4 Z over the block's 32 rows, then
 // W_part += c_j conj(H_j) . V, summed over the four waves in a fixed order.
 // --------------------------------------------------------------------------
-template <int ZO>
-__device__ __forceinline__ void adjoint_tail(const f4 (&accZ)[2][2 * ZO / 16], bool jok, int j, int s, int K, int P,
-                                             int Np, int y0, const float *__restrict__ ta4,
+template <int FB, int MIX>
+__device__ __forceinline__ void adjoint_tail(const f4 (&accZ)[2][2 * FB + MIX], bool jok, int j, int s, int K, int P,
+                                             int Np, int AP, int y0, const float *__restrict__ ta4,
                                              const float2 *__restrict__ coef, float2 *Ws,
                                              float *__restrict__ dst) {
-    constexpr int AB = ZO / 16, AP = ZO;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int l16 = lane & 15, lq = lane >> 4;
+    const int AB = AP / 16;
     for (int e = threadIdx.x; e < P * P; e += 256) Ws[e] = make_float2(0.f, 0.f);
     __syncthreads();
     const float2 *cj = coef + ((size_t)s * K + (jok ? j : 0)) * P * P;
     for (int ab = 0; ab < AB; ++ab) {
-        f4 vr[AB], vi[AB];
+        // full column blocks: real in block bb, imaginary in block FB + bb
+        f4 vr[FB + MIX], vi[FB + MIX];
 #pragma unroll
-        for (int bb = 0; bb < AB; ++bb) {
+        for (int bb = 0; bb < FB + MIX; ++bb) {
             vr[bb] = f4{0.f, 0.f, 0.f, 0.f};
             vi[bb] = f4{0.f, 0.f, 0.f, 0.f};
         }
@@ -363,24 +365,41 @@ __device__ __forceinline__ void adjoint_tail(const f4 (&accZ)[2][2 * ZO / 16], b
                     const float car = ta4[(size_t)y * AP + 16 * ab + l16];
                     const float cai = ta4[((size_t)Np + y) * AP + 16 * ab + l16];
 #pragma unroll
-                    for (int bb = 0; bb < AB; ++bb) {
+                    for (int bb = 0; bb < FB; ++bb) {
                         vr[bb] = mfma4(car, accZ[yb][bb][i], vr[bb]);
                         vi[bb] = mfma4(cai, accZ[yb][bb][i], vi[bb]);
                     }
 #pragma unroll
-                    for (int bb = 0; bb < AB; ++bb) {
-                        vr[bb] = mfma4(-cai, accZ[yb][bb + AB][i], vr[bb]);
-                        vi[bb] = mfma4(car, accZ[yb][bb + AB][i], vi[bb]);
+                    for (int bb = 0; bb < FB; ++bb) {
+                        vr[bb] = mfma4(-cai, accZ[yb][bb + FB][i], vr[bb]);
+                        vi[bb] = mfma4(car, accZ[yb][bb + FB][i], vi[bb]);
+                    }
+                    if (MIX) {
+                        // shared block: vr <- Ar Z, vi <- Ai Z (combined across lanes below)
+                        vr[FB] = mfma4(car, accZ[yb][2 * FB][i], vr[FB]);
+                        vi[FB] = mfma4(cai, accZ[yb][2 * FB][i], vi[FB]);
                     }
                 }
+            if (MIX) {
+                // lanes l16 < 8 hold real columns, l16 >= 8 the imaginary ones:
+                // V_re = (Ar Z_re) - (Ai Z_im), V_im = (Ar Z_im) + (Ai Z_re)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const float q1 = vr[FB][i], q2 = vi[FB][i];
+                    const float q1o = __shfl_xor(q1, 8), q2o = __shfl_xor(q2, 8);
+                    vr[FB][i] = q1 - q2o;
+                    vi[FB][i] = q1o + q2;
+                }
+            }
         }
         for (int w = 0; w < 4; ++w) {
             if (wave == w && jok) {
 #pragma unroll
-                for (int bb = 0; bb < AB; ++bb)
+                for (int bb = 0; bb < FB + MIX; ++bb)
 #pragma unroll
                     for (int i = 0; i < 4; ++i) {
-                        const int a = 16 * ab + 4 * lq + i, b = 16 * bb + l16;
+                        const int a = 16 * ab + 4 * lq + i;
+                        const int b = bb < FB ? 16 * bb + l16 : (l16 < 8 ? 16 * FB + l16 : P);
                         if (a < P && b < P) {
                             const float2 c = cj[a * P + b];
                             const float xr = vr[bb][i], xi = vi[bb][i];
@@ -434,14 +453,15 @@ __device__ __forceinline__ void adjoint_rows(f4 (&accZ)[2][NB], const f4 (&er)[2
 // then the shared tail.  G and B3 chunks and the next chunk's fragments are
 // prefetched into registers while the current chunk is multiplied.
 // --------------------------------------------------------------------------
-template <int ZO>
+template <int FB, int MIX>
 __global__ __launch_bounds__(256, 2) void k_adjoint_st(const float *__restrict__ tb, const float *__restrict__ ta4,
                                                     const float *__restrict__ Est, const float *__restrict__ G,
                                                     size_t g_set_stride, const float2 *__restrict__ coef, int K,
-                                                    int P, int N, int Np, int set_lo, float *__restrict__ Wpart) {
-    constexpr int NZ = 2 * ZO, NB = NZ / 16;
+                                                    int P, int N, int Np, int AP, int set_lo,
+                                                    float *__restrict__ Wpart) {
+    constexpr int NZ = 32 * FB + 16 * MIX, NB = NZ / 16;
     constexpr int LDB = NZ + 4;
-    constexpr int NBV = (2 * 32 * NZ / 4) / 256;    // float4 of B3 per thread per chunk
+    constexpr int NBV = (2 * 32 * NZ / 4 + 255) / 256;    // float4 of B3 per thread per chunk
     __shared__ float Gs[32][36];
     __shared__ float Bs[2][32][LDB];
     __shared__ float2 Ws[ILT_MAX_P * ILT_MAX_P];
@@ -468,10 +488,12 @@ __global__ __launch_bounds__(256, 2) void k_adjoint_st(const float *__restrict__
 #pragma unroll
         for (int v = 0; v < NBV; ++v) {
             const int e = threadIdx.x + 256 * v;
-            const int part = e / (32 * NZ / 4), rem = e % (32 * NZ / 4);
-            const int xx = rem / (NZ / 4), c4 = (rem % (NZ / 4)) * 4;
-            *reinterpret_cast<float4 *>(&Bs[part][xx][c4]) =
-                *reinterpret_cast<const float4 *>(tb + ((size_t)part * Np + x0 + xx) * NZ + c4);
+            if (e < 2 * 32 * NZ / 4) {
+                const int part = e / (32 * NZ / 4), rem = e % (32 * NZ / 4);
+                const int xx = rem / (NZ / 4), c4 = (rem % (NZ / 4)) * 4;
+                *reinterpret_cast<float4 *>(&Bs[part][xx][c4]) =
+                    *reinterpret_cast<const float4 *>(tb + ((size_t)part * Np + x0 + xx) * NZ + c4);
+            }
         }
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
@@ -508,7 +530,7 @@ __global__ __launch_bounds__(256, 2) void k_adjoint_st(const float *__restrict__
         }
     }
     float *dst = Wpart + ((size_t)(srel * gridDim.x + ytile) * gridDim.y + kg) * P * P * 2;
-    adjoint_tail<ZO>(accZ, jok, j, s, K, P, Np, y0, ta4, coef, Ws, dst);
+    adjoint_tail<FB, MIX>(accZ, jok, j, s, K, P, Np, AP, y0, ta4, coef, Ws, dst);
 }
 
 // --------------------------------------------------------------------------
@@ -518,13 +540,13 @@ __global__ __launch_bounds__(256, 2) void k_adjoint_st(const float *__restrict__
 //   (b) X = G . E                 (G tile staged in LDS)
 //   (c) Z += X B3                 then the shared tail.
 // --------------------------------------------------------------------------
-template <int KP, int ZO>
+template <int KP, int FB, int MIX>
 __global__ __launch_bounds__(256, 2) void k_adjoint_rc(const float *__restrict__ tl, const float *__restrict__ tb,
                                                     const float *__restrict__ ta4, const float *__restrict__ Y,
                                                     const float *__restrict__ G, size_t g_set_stride,
                                                     const float2 *__restrict__ coef, int K, int P, int N, int Np,
-                                                    int set_lo, float *__restrict__ Wpart) {
-    constexpr int NZ = 2 * ZO, NB = NZ / 16, KS = KP / 4;
+                                                    int AP, int set_lo, float *__restrict__ Wpart) {
+    constexpr int NZ = 32 * FB + 16 * MIX, NB = NZ / 16, KS = KP / 4;
     constexpr int LDB = NZ + 4;
     __shared__ float Gs[32][33];
     __shared__ float Bs[2][32][LDB];
@@ -600,7 +622,7 @@ __global__ __launch_bounds__(256, 2) void k_adjoint_rc(const float *__restrict__
         __syncthreads();
     }
     float *dst = Wpart + ((size_t)(srel * gridDim.x + ytile) * gridDim.y + kg) * P * P * 2;
-    adjoint_tail<ZO>(accZ, jok, j, s, K, P, Np, y0, ta4, coef, Ws, dst);
+    adjoint_tail<FB, MIX>(accZ, jok, j, s, K, P, Np, AP, y0, ta4, coef, Ws, dst);
 }
 
 }  // namespace
@@ -609,12 +631,16 @@ __global__ __launch_bounds__(256, 2) void k_adjoint_rc(const float *__restrict__
 
 hipError_t launch_spectrum(ilt_ctx *c, const float *src, int src_is_phi) {
     const int nband = c->Np / 16;
-    switch (c->NZ) {
-        case 32: k_spectrum_band<32><<<nband, 512, 0, c->stream>>>(src, src_is_phi, c->tb, c->ar, c->ai, c->P, c->ZO, c->N, c->Np, c->Spart); break;
-        case 64: k_spectrum_band<64><<<nband, 512, 0, c->stream>>>(src, src_is_phi, c->tb, c->ar, c->ai, c->P, c->ZO, c->N, c->Np, c->Spart); break;
-        case 96: k_spectrum_band<96><<<nband, 512, 0, c->stream>>>(src, src_is_phi, c->tb, c->ar, c->ai, c->P, c->ZO, c->N, c->Np, c->Spart); break;
-        default: return hipErrorInvalidValue;
-    }
+#define SPEC(FB_, MIX_)                                                                                          \
+    k_spectrum_band<FB_, MIX_><<<nband, 512, 0, c->stream>>>(src, src_is_phi, c->tb, c->ar, c->ai, c->P, c->N, \
+                                                             c->Np, c->Spart)
+    if (c->FB == 0 && c->MIX == 1) SPEC(0, 1);
+    else if (c->FB == 1 && c->MIX == 0) SPEC(1, 0);
+    else if (c->FB == 1 && c->MIX == 1) SPEC(1, 1);
+    else if (c->FB == 2 && c->MIX == 0) SPEC(2, 0);
+    else if (c->FB == 2 && c->MIX == 1) SPEC(2, 1);
+    else return hipErrorInvalidValue;
+#undef SPEC
     const int n = c->P * c->P;
     k_psum<double2><<<(n + 63) / 64, 1024, 0, c->stream>>>(c->Spart, nband, n, c->S);
     return hipGetLastError();
@@ -649,23 +675,31 @@ hipError_t launch_adjoint(ilt_ctx *c, const float *G, size_t g_set_stride, int s
     dim3 grid((c->N + 31) / 32, (c->K + 3) / 4, set_hi - set_lo);
     if (fields_stored) {
         if (!c->Est) return hipErrorInvalidValue;
-#define ADJS(ZO_) k_adjoint_st<ZO_><<<grid, 256, 0, c->stream>>>(c->tb, c->ta4, c->Est, G, g_set_stride, c->coef, c->K, c->P, c->N, c->Np, set_lo, c->Wpart)
-        if (c->ZO == 16) ADJS(16);
-        else if (c->ZO == 32) ADJS(32);
-        else if (c->ZO == 48) ADJS(48);
+#define ADJS(FB_, MIX_)                                                                                       \
+    k_adjoint_st<FB_, MIX_><<<grid, 256, 0, c->stream>>>(c->tb, c->ta4, c->Est, G, g_set_stride, c->coef, c->K, \
+                                                         c->P, c->N, c->Np, c->AP, set_lo, c->Wpart)
+        if (c->FB == 0 && c->MIX == 1) ADJS(0, 1);
+        else if (c->FB == 1 && c->MIX == 0) ADJS(1, 0);
+        else if (c->FB == 1 && c->MIX == 1) ADJS(1, 1);
+        else if (c->FB == 2 && c->MIX == 0) ADJS(2, 0);
+        else if (c->FB == 2 && c->MIX == 1) ADJS(2, 1);
         else return hipErrorInvalidValue;
 #undef ADJS
         return hipGetLastError();
     }
-#define ADJ(KP_, ZO_)                                                                                    \
-    k_adjoint_rc<KP_, ZO_><<<grid, 256, 0, c->stream>>>(c->tl, c->tb, c->ta4, c->Y, G, g_set_stride, c->coef, \
-                                                        c->K, c->P, c->N, c->Np, set_lo, c->Wpart)
-    if (c->KP == 8 && c->ZO == 16) ADJ(8, 16);
-    else if (c->KP == 24 && c->ZO == 16) ADJ(24, 16);
-    else if (c->KP == 40 && c->ZO == 16) ADJ(40, 16);
-    else if (c->KP == 40 && c->ZO == 32) ADJ(40, 32);
-    else if (c->KP == 72 && c->ZO == 32) ADJ(72, 32);
-    else if (c->KP == 72 && c->ZO == 48) ADJ(72, 48);
+#define ADJ(KP_, FB_, MIX_)                                                                                 \
+    k_adjoint_rc<KP_, FB_, MIX_><<<grid, 256, 0, c->stream>>>(c->tl, c->tb, c->ta4, c->Y, G, g_set_stride,  \
+                                                              c->coef, c->K, c->P, c->N, c->Np, c->AP, set_lo, \
+                                                              c->Wpart)
+    const int KPv = c->KP, FBv = c->FB, MIXv = c->MIX;
+    if (KPv == 8 && FBv == 0 && MIXv == 1) ADJ(8, 0, 1);
+    else if (KPv == 24 && FBv == 0 && MIXv == 1) ADJ(24, 0, 1);
+    else if (KPv == 24 && FBv == 1 && MIXv == 0) ADJ(24, 1, 0);
+    else if (KPv == 40 && FBv == 1 && MIXv == 0) ADJ(40, 1, 0);
+    else if (KPv == 40 && FBv == 1 && MIXv == 1) ADJ(40, 1, 1);
+    else if (KPv == 72 && FBv == 1 && MIXv == 1) ADJ(72, 1, 1);
+    else if (KPv == 72 && FBv == 2 && MIXv == 0) ADJ(72, 2, 0);
+    else if (KPv == 72 && FBv == 2 && MIXv == 1) ADJ(72, 2, 1);
     else return hipErrorInvalidValue;
 #undef ADJ
     return hipGetLastError();

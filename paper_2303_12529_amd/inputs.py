@@ -4,7 +4,7 @@ This module holds none of the level-set ILT method's arithmetic.  It only
 produces the two kinds of input the method consumes:
 
 * a binary target layout Z_t (N x N, uint8), standing in for the ICCAD-2013
-  M1 clips the paper evaluates on (Sec. V, Table I), which are not available;
+  M1 clips the paper evaluates on (Sec. IV, Table I), which are not available;
 * a set of K coherent optical kernels H_k (frequency samples on a P x P
   pass-band window) and their weights w_k, standing in for the contest
   litho engine's 24 kernels (Sec. II-B, truncated SOCS with N_k = 24).

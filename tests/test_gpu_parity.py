@@ -61,6 +61,8 @@ FWD_CASES = [
     (256, 9, 8, "optics"),
     (200, 35, 6, "rand"),
     (300, 21, 7, "binary"),
+    (128, 27, 4, "rand"),
+    (160, 15, 3, "binary"),
     (512, 35, 24, "optics"),
 ]
 
@@ -106,7 +108,10 @@ def test_litho_forward_two_sets_select(ilt):
         assert np.abs(out - ref).max() <= 1e-5 * np.abs(ref).max()
 
 
-ADJ_CASES = [(64, 3, 2), (64, 9, 4), (100, 9, 5), (200, 35, 6), (256, 21, 9), (384, 35, 24)]
+# every (inner dimension, window-column layout) instantiation: P in 1-4, 5-8,
+# 9-12, 13-16, 17-20, 21-24, 25-32, 33-35
+ADJ_CASES = [(64, 3, 2), (96, 7, 3), (64, 9, 4), (100, 9, 5), (128, 15, 4), (160, 19, 5), (256, 21, 9),
+             (200, 27, 6), (200, 35, 6), (384, 35, 24)]
 
 
 @pytest.mark.parametrize("flags", [0, 1])
