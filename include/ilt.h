@@ -165,6 +165,15 @@ int edt_reinit(ilt_ctx *ctx, const float *d_phi, const unsigned char *d_mask,
 int ilt_solve(ilt_ctx *ctx, const unsigned char *d_target, float *d_phi,
               const ilt_params *params, ilt_report *h_report, double *d_trace);
 
+/* Sec. III-A/B, device-resident loop: by default ilt_solve captures its
+ * whole launch sequence (init, iterations, final metrics) into a hipGraph on
+ * an internal stream the first time it sees a set of arguments, and replays
+ * the graph on the context's stream while the arguments (pointers and
+ * params, measurement hook on or off) stay the same.  enable = 0 launches
+ * every kernel directly instead.  Not thread-safe (like every call on a
+ * context). */
+int ilt_set_graph(ilt_ctx *ctx, int enable);
+
 /* Measurement hook.  ilt_profile(ctx, 1) makes later ilt_solve calls record
  * a HIP event pair on the context's stream around every launch of each
  * phase of the loop; ilt_profile_read() then returns, per phase, the summed

@@ -67,9 +67,19 @@ void free_events(ilt_ctx *c) {
     c->n_ev = 0;
 }
 
+void free_graph(ilt_ctx *c) {
+    if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
+    if (c->graph) (void)hipGraphDestroy(c->graph);
+    c->graph_exec = nullptr;
+    c->graph = nullptr;
+    c->graph_key_len = 0;
+}
+
 void free_ctx(ilt_ctx *c) {
     if (!c) return;
     free_events(c);
+    free_graph(c);
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     void *ptrs[] = {c->tl, c->tb, c->ta4, c->ar, c->ai, c->H, c->sw, c->coef, c->Spart, c->S, c->Est, c->Y, c->Tg,
                     c->I, c->G, c->g, c->phi2, c->Wpart, c->W, c->edtg, c->colbits, c->part, c->scal};
     for (void *p : ptrs)
@@ -302,6 +312,12 @@ extern "C" int ilt_create(ilt_ctx **out, const ilt_optics *o, int max_batch, voi
         free_ctx(c);
         return fail(ILT_EDEVICE, "context set-up failed: %s", hipGetErrorString(e));
     }
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        free_ctx(c);
+        return fail(ILT_EDEVICE, "context set-up failed: %s", hipGetErrorString(e));
+    }
+    c->use_graph = 1;
     set_ns_per_tick(rate_khz > 0 ? 1.0e6 / rate_khz : 10.0);
     *out = c;
     return ILT_OK;
@@ -396,21 +412,15 @@ extern "C" int edt_reinit(ilt_ctx *c, const float *d_phi, const unsigned char *d
     return ILT_OK;
 }
 
-extern "C" int ilt_solve(ilt_ctx *c, const unsigned char *d_target, float *d_phi, const ilt_params *p,
-                         ilt_report *h_report, double *d_trace) {
-    int r;
-    if ((r = check_ctx(c))) return r;
-    if ((r = check_ptr(d_target, "d_target", 1))) return r;
-    if ((r = check_ptr(d_phi, "d_phi"))) return r;
-    if (d_trace && !aligned(d_trace, 8)) return fail(ILT_EINVAL, "d_trace is not 8-byte aligned");
-    if ((r = check_params(c, p, true))) return r;
-    if (p->init_mode != 0 && p->init_mode != 1) return fail(ILT_EINVAL, "init_mode must be 0 or 1");
+namespace {
+
+// Enqueue the whole solve (init, T iterations, final metrics) on c->stream.
+int enqueue_solve(ilt_ctx *c, const unsigned char *d_target, float *d_phi, const ilt_params *p, double *d_trace) {
     const resist_args ra = make_resist_args(p);
     int slo, shi;
     used_set_range(p, &slo, &shi);
     const size_t npix = (size_t)c->N * c->N;
     double *pr = c->part + part_resist_off(c), *pm = c->part + part_max_off(c), *ps = c->part + part_step_off(c);
-
     const int stored = c->Est != nullptr;
     c->n_ev = 0;
     if (p->init_mode == 0) {
@@ -465,6 +475,66 @@ extern "C" int ilt_solve(ilt_ctx *c, const unsigned char *d_target, float *d_phi
     HIPCHK(launch_image_to(c, slo, shi, c->I + (size_t)slo * npix, 0));
     HIPCHK(launch_resist(c, c->I, d_target, ra, c->G, pr));
     HIPCHK(launch_finish_resist(c, pr, resist_blocks(c), c->scal, nullptr));
+    return ILT_OK;
+}
+
+int graph_key(const unsigned char *d_target, const float *d_phi, const ilt_params *p, const double *d_trace,
+              unsigned char *key) {
+    int n = 0;
+    std::memcpy(key + n, &d_target, sizeof d_target); n += sizeof d_target;
+    std::memcpy(key + n, &d_phi, sizeof d_phi); n += sizeof d_phi;
+    std::memcpy(key + n, &d_trace, sizeof d_trace); n += sizeof d_trace;
+    std::memcpy(key + n, p, sizeof *p); n += sizeof *p;
+    return n;
+}
+
+}  // namespace
+
+extern "C" int ilt_solve(ilt_ctx *c, const unsigned char *d_target, float *d_phi, const ilt_params *p,
+                         ilt_report *h_report, double *d_trace) {
+    int r;
+    if ((r = check_ctx(c))) return r;
+    if ((r = check_ptr(d_target, "d_target", 1))) return r;
+    if ((r = check_ptr(d_phi, "d_phi"))) return r;
+    if (d_trace && !aligned(d_trace, 8)) return fail(ILT_EINVAL, "d_trace is not 8-byte aligned");
+    if ((r = check_params(c, p, true))) return r;
+    if (p->init_mode != 0 && p->init_mode != 1) return fail(ILT_EINVAL, "init_mode must be 0 or 1");
+
+    if (c->use_graph) {
+        unsigned char key[sizeof c->graph_key];
+        int klen = graph_key(d_target, d_phi, p, d_trace, key);
+        key[klen++] = (unsigned char)c->profiling;
+        if (!c->graph_exec || klen != c->graph_key_len || std::memcmp(key, c->graph_key, klen) != 0) {
+            free_graph(c);
+            hipStream_t user = c->stream;
+            c->stream = c->cap_stream;
+            hipError_t e = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeRelaxed);
+            if (e != hipSuccess) {
+                c->stream = user;
+                return fail(ILT_EDEVICE, "hipStreamBeginCapture: %s", hipGetErrorString(e));
+            }
+            const int rc = enqueue_solve(c, d_target, d_phi, p, d_trace);
+            hipGraph_t g = nullptr;
+            e = hipStreamEndCapture(c->cap_stream, &g);
+            c->stream = user;
+            if (rc != ILT_OK) {
+                if (g) (void)hipGraphDestroy(g);
+                return rc;
+            }
+            if (e != hipSuccess) return fail(ILT_EDEVICE, "hipStreamEndCapture: %s", hipGetErrorString(e));
+            c->graph = g;
+            e = hipGraphInstantiate(&c->graph_exec, g, nullptr, nullptr, 0);
+            if (e != hipSuccess) {
+                free_graph(c);
+                return fail(ILT_EDEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e));
+            }
+            std::memcpy(c->graph_key, key, klen);
+            c->graph_key_len = klen;
+        }
+        HIPCHK(hipGraphLaunch(c->graph_exec, c->stream));
+    } else {
+        if ((r = enqueue_solve(c, d_target, d_phi, p, d_trace))) return r;
+    }
     double sc[SC_COUNT];
     HIPCHK(hipMemcpyAsync(sc, c->scal, sizeof sc, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
@@ -478,6 +548,14 @@ extern "C" int ilt_solve(ilt_ctx *c, const unsigned char *d_target, float *d_phi
     }
     if (sc[SC_NONFIN] > 0.0 || !std::isfinite(sc[SC_LOSS]))
         return fail(ILT_ENUMERIC, "non-finite loss or gradient in the loop");
+    return ILT_OK;
+}
+
+extern "C" int ilt_set_graph(ilt_ctx *c, int enable) {
+    int r;
+    if ((r = check_ctx(c))) return r;
+    c->use_graph = enable ? 1 : 0;
+    if (!enable) free_graph(c);
     return ILT_OK;
 }
 

@@ -91,6 +91,15 @@ struct ilt_ctx {
     int n_part;        // capacity of part (doubles)
     int n_wpart;       // capacity of Wpart (floats)
 
+    // whole-solve hipGraph, captured on an internal stream and replayed on
+    // `stream`; reused while the solve's arguments are unchanged
+    int use_graph;
+    hipStream_t cap_stream;
+    hipGraph_t graph;
+    hipGraphExec_t graph_exec;
+    unsigned char graph_key[160];
+    int graph_key_len;
+
     // measurement hook: event pairs per recorded launch
     int profiling;
     int n_ev;                 // events recorded in the current solve

@@ -77,6 +77,7 @@ def load_library(path: str = LIB_PATH):
         "edt_reinit": [_VP, _VP, _VP, _VP, _VP, ctypes.POINTER(_Params)],
         "ilt_solve": [_VP, _VP, _VP, ctypes.POINTER(_Params), ctypes.POINTER(_Report), _VP],
         "ilt_profile": [_VP, ctypes.c_int],
+        "ilt_set_graph": [_VP, ctypes.c_int],
         "ilt_profile_read": [_VP, ctypes.POINTER(ctypes.c_double), ctypes.c_int],
     }
     for name, args in sig.items():
@@ -252,6 +253,10 @@ class Context:
         return dict(iters_done=rep.iters_done, status=rep.status, loss=rep.loss, l2=rep.l2, pvb=rep.pvb,
                     flips=rep.flips)
 
+
+    def set_graph(self, enable: bool = True):
+        """Capture ilt_solve into a reusable hipGraph (default) or launch directly."""
+        _check(load_library().ilt_set_graph(self._h, 1 if enable else 0))
 
     def profile(self, enable: bool = True):
         """Turn the per-phase HIP-event timing of ilt_solve on or off."""
