@@ -50,7 +50,12 @@ enum {
     ILT_EUNSUPPORTED = -5  /* valid but not built for (e.g. P too large)      */
 };
 
-enum { ILT_FP32 = 0 };
+/* Arithmetic of the two dense contractions (forward image, adjoint).
+ * ILT_BF16X3: each FP32 operand is split into BF16 hi + lo and products are
+ * taken as hi*hi + hi*lo + lo*hi with FP32 accumulation on the BF16 matrix
+ * cores; the adjoint then recomputes the fields (no field store).  Every
+ * other step is FP32/FP64 as in ILT_FP32. */
+enum { ILT_FP32 = 0, ILT_BF16X3 = 1 };
 
 /* ilt_optics.flags */
 enum {
@@ -67,7 +72,7 @@ typedef struct {
     int P;                  /* odd window side, 1 <= P <= 35, 2P-1 <= N       */
     int K;                  /* kernels per set, 1 <= K <= 64                  */
     int n_sets;             /* focus conditions (kernel sets), 1 <= n <= 4    */
-    int precision;          /* ILT_FP32                                       */
+    int precision;          /* ILT_FP32 or ILT_BF16X3                         */
     int flags;              /* ILT_FLAG_*                                     */
     const double *h_kernels;/* host [n_sets][K][P][P][2] (re, im)             */
     const double *h_weights;/* host [n_sets][K], each >= 0                    */
@@ -169,9 +174,8 @@ int ilt_solve(ilt_ctx *ctx, const unsigned char *d_target, float *d_phi,
  * whole launch sequence (init, iterations, final metrics) into a hipGraph on
  * an internal stream the first time it sees a set of arguments, and replays
  * the graph on the context's stream while the arguments (pointers and
- * params, measurement hook on or off) stay the same.  enable = 0 launches
- * every kernel directly instead.  Not thread-safe (like every call on a
- * context). */
+ * params) stay the same.  enable = 0 launches every kernel directly
+ * instead; solves with the measurement hook on always launch directly. */
 int ilt_set_graph(ilt_ctx *ctx, int enable);
 
 /* Measurement hook.  ilt_profile(ctx, 1) makes later ilt_solve calls record

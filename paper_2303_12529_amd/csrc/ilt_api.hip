@@ -44,6 +44,24 @@ int pick_kp(int P) {
 }
 int round_up(int v, int m) { return (v + m - 1) / m * m; }
 
+// BF16 round-to-nearest-even of an FP32 value, and back.
+uint16_t f2bf(float f) {
+    uint32_t u;
+    std::memcpy(&u, &f, 4);
+    if ((u & 0x7FFFFFFFu) > 0x7F800000u) return 0x7FC0u;
+    return (uint16_t)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+}
+float bf2f(uint16_t h) {
+    const uint32_t u = (uint32_t)h << 16;
+    float f;
+    std::memcpy(&f, &u, 4);
+    return f;
+}
+void split_bf(float x, uint16_t &hi, uint16_t &lo) {
+    hi = f2bf(x);
+    lo = f2bf(x - bf2f(hi));
+}
+
 bool aligned(const void *p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
 
 template <typename T>
@@ -80,7 +98,7 @@ void free_ctx(ilt_ctx *c) {
     free_events(c);
     free_graph(c);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
-    void *ptrs[] = {c->tl, c->tb, c->ta4, c->ar, c->ai, c->H, c->sw, c->coef, c->Spart, c->S, c->Est, c->Y, c->Tg,
+    void *ptrs[] = {c->tl, c->tb, c->ta4, c->ar, c->ai, c->H, c->sw, c->coef, c->tlhl, c->tbhl, c->Yhl, c->Spart, c->S, c->Est, c->Y, c->Tg,
                     c->I, c->G, c->g, c->phi2, c->Wpart, c->W, c->edtg, c->colbits, c->part, c->scal};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
@@ -200,7 +218,8 @@ extern "C" int ilt_create(ilt_ctx **out, const ilt_optics *o, int max_batch, voi
     if (2 * P - 1 > N) return fail(ILT_EINVAL, "window 2P-1=%d exceeds N=%d", 2 * P - 1, N);
     if (K < 1 || K > ILT_MAX_K) return fail(ILT_EINVAL, "K=%d outside [1, %d]", K, ILT_MAX_K);
     if (ns < 1 || ns > ILT_MAX_SETS) return fail(ILT_EINVAL, "n_sets=%d outside [1, %d]", ns, ILT_MAX_SETS);
-    if (o->precision != ILT_FP32) return fail(ILT_EUNSUPPORTED, "precision %d not built", o->precision);
+    if (o->precision != ILT_FP32 && o->precision != ILT_BF16X3)
+        return fail(ILT_EUNSUPPORTED, "precision %d not built", o->precision);
     if (o->flags & ~ILT_FLAG_RECOMPUTE_FIELDS) return fail(ILT_EINVAL, "unknown flags 0x%x", o->flags);
     if (!o->h_kernels || !o->h_weights) return fail(ILT_EINVAL, "kernels or weights are null");
     for (int i = 0; i < ns * K; ++i)
@@ -277,7 +296,13 @@ extern "C" int ilt_create(ilt_ctx **out, const ilt_optics *o, int max_batch, voi
     ALLOC(coef, coef.size());
     ALLOC(sw, sw.size());
     ALLOC(Spart, (size_t)(Np / 16) * P * P);
-    if (!(o->flags & ILT_FLAG_RECOMPUTE_FIELDS)) ALLOC(Est, (size_t)ns * K * (Np / 16) * (Np / 16) * 512);
+    const bool b3 = o->precision == ILT_BF16X3;
+    if (!b3 && !(o->flags & ILT_FLAG_RECOMPUTE_FIELDS)) ALLOC(Est, (size_t)ns * K * (Np / 16) * (Np / 16) * 512);
+    if (b3) {
+        ALLOC(tlhl, (size_t)2 * Np * 2 * KP);
+        ALLOC(tbhl, (size_t)2 * 2 * NZ * Np);
+        ALLOC(Yhl, (size_t)ns * K * Np * 2 * KP);
+    }
     ALLOC(S, (size_t)P * P);
     ALLOC(W, (size_t)P * P);
     ALLOC(Y, (size_t)ns * K * KP * Np);
@@ -306,6 +331,27 @@ extern "C" int ilt_create(ilt_ctx **out, const ilt_optics *o, int max_batch, voi
     if (e == hipSuccess) e = hipMemcpy(c->H, H.data(), H.size() * 8, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(c->coef, coef.data(), coef.size() * 8, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(c->sw, sw.data(), sw.size() * 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess && b3) {
+        std::vector<uint16_t> lh((size_t)2 * Np * 2 * KP), bh((size_t)2 * 2 * NZ * Np);
+        for (int part = 0; part < 2; ++part)
+            for (int y = 0; y < Np; ++y)
+                for (int r = 0; r < KP; ++r) {
+                    uint16_t h, l;
+                    split_bf(tl[((size_t)part * KP + r) * Np + y], h, l);
+                    lh[(((size_t)part * Np + y) * 2 + 0) * KP + r] = h;
+                    lh[(((size_t)part * Np + y) * 2 + 1) * KP + r] = l;
+                }
+        for (int part = 0; part < 2; ++part)
+            for (int x = 0; x < Np; ++x)
+                for (int n = 0; n < NZ; ++n) {
+                    uint16_t h, l;
+                    split_bf(tb[((size_t)part * Np + x) * NZ + n], h, l);
+                    bh[(((size_t)part * 2 + 0) * NZ + n) * Np + x] = h;
+                    bh[(((size_t)part * 2 + 1) * NZ + n) * Np + x] = l;
+                }
+        e = hipMemcpy(c->tlhl, lh.data(), lh.size() * 2, hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(c->tbhl, bh.data(), bh.size() * 2, hipMemcpyHostToDevice);
+    }
     int rate_khz = 0;
     if (e == hipSuccess) e = hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, c->device);
     if (e != hipSuccess) {
@@ -338,7 +384,12 @@ extern "C" int litho_forward(ilt_ctx *c, const float *d_mask, int set, float *d_
     if (set < 0 || set >= c->n_sets) return fail(ILT_EINVAL, "set %d outside [0, %d)", set, c->n_sets);
     HIPCHK(launch_spectrum(c, d_mask, 0));
     HIPCHK(launch_make_Y(c, set, set + 1));
-    HIPCHK(launch_image_to(c, set, set + 1, d_aerial, 0));
+    if (c->precision == ILT_BF16X3) {
+        HIPCHK(launch_split_rows(c, set, set + 1));
+        HIPCHK(launch_image_b3(c, set, set + 1, d_aerial));
+    } else {
+        HIPCHK(launch_image_to(c, set, set + 1, d_aerial, 0));
+    }
     return ILT_OK;
 }
 
@@ -351,9 +402,14 @@ extern "C" int litho_adjoint(ilt_ctx *c, const float *d_mask, const float *d_G, 
     if (set < 0 || set >= c->n_sets) return fail(ILT_EINVAL, "set %d outside [0, %d)", set, c->n_sets);
     HIPCHK(launch_spectrum(c, d_mask, 0));
     HIPCHK(launch_make_Y(c, set, set + 1));
-    const int stored = c->Est != nullptr;
-    if (stored) HIPCHK(launch_image_to(c, set, set + 1, c->I + (size_t)set * c->N * c->N, 1));
-    HIPCHK(launch_adjoint(c, d_G, 0, set, set + 1, stored));
+    if (c->precision == ILT_BF16X3) {
+        HIPCHK(launch_split_rows(c, set, set + 1));
+        HIPCHK(launch_adjoint_b3(c, d_G, 0, set, set + 1));
+    } else {
+        const int stored = c->Est != nullptr;
+        if (stored) HIPCHK(launch_image_to(c, set, set + 1, c->I + (size_t)set * c->N * c->N, 1));
+        HIPCHK(launch_adjoint(c, d_G, 0, set, set + 1, stored));
+    }
     HIPCHK(launch_window_sum(c, set, set + 1));
     HIPCHK(launch_gradient(c, d_out, c->part + part_max_off(c)));
     return ILT_OK;
@@ -422,6 +478,7 @@ int enqueue_solve(ilt_ctx *c, const unsigned char *d_target, float *d_phi, const
     const size_t npix = (size_t)c->N * c->N;
     double *pr = c->part + part_resist_off(c), *pm = c->part + part_max_off(c), *ps = c->part + part_step_off(c);
     const int stored = c->Est != nullptr;
+    const bool b3 = c->precision == ILT_BF16X3;
     c->n_ev = 0;
     if (p->init_mode == 0) {
         PhaseTimer t(c, 7);
@@ -436,10 +493,12 @@ int enqueue_solve(ilt_ctx *c, const unsigned char *d_target, float *d_phi, const
         {
             PhaseTimer t(c, 1);
             HIPCHK(launch_make_Y(c, slo, shi));
+            if (b3) HIPCHK(launch_split_rows(c, slo, shi));
         }
         {
             PhaseTimer t(c, 2);
-            HIPCHK(launch_image_to(c, slo, shi, c->I + (size_t)slo * npix, stored));
+            if (b3) HIPCHK(launch_image_b3(c, slo, shi, c->I + (size_t)slo * npix));
+            else HIPCHK(launch_image_to(c, slo, shi, c->I + (size_t)slo * npix, stored));
         }
         {
             PhaseTimer t(c, 3);
@@ -448,7 +507,8 @@ int enqueue_solve(ilt_ctx *c, const unsigned char *d_target, float *d_phi, const
         }
         {
             PhaseTimer t(c, 4);
-            HIPCHK(launch_adjoint(c, c->G, npix, slo, shi, stored));
+            if (b3) HIPCHK(launch_adjoint_b3(c, c->G, npix, slo, shi));
+            else HIPCHK(launch_adjoint(c, c->G, npix, slo, shi, stored));
         }
         {
             PhaseTimer t(c, 5);
@@ -472,7 +532,12 @@ int enqueue_solve(ilt_ctx *c, const unsigned char *d_target, float *d_phi, const
     // final metrics of [phi_T <= 0]
     HIPCHK(launch_spectrum(c, d_phi, 1));
     HIPCHK(launch_make_Y(c, slo, shi));
-    HIPCHK(launch_image_to(c, slo, shi, c->I + (size_t)slo * npix, 0));
+    if (b3) {
+        HIPCHK(launch_split_rows(c, slo, shi));
+        HIPCHK(launch_image_b3(c, slo, shi, c->I + (size_t)slo * npix));
+    } else {
+        HIPCHK(launch_image_to(c, slo, shi, c->I + (size_t)slo * npix, 0));
+    }
     HIPCHK(launch_resist(c, c->I, d_target, ra, c->G, pr));
     HIPCHK(launch_finish_resist(c, pr, resist_blocks(c), c->scal, nullptr));
     return ILT_OK;
@@ -500,10 +565,11 @@ extern "C" int ilt_solve(ilt_ctx *c, const unsigned char *d_target, float *d_phi
     if ((r = check_params(c, p, true))) return r;
     if (p->init_mode != 0 && p->init_mode != 1) return fail(ILT_EINVAL, "init_mode must be 0 or 1");
 
-    if (c->use_graph) {
+    // event pairs recorded inside a graph carry no usable timestamps, so a
+    // solve with the measurement hook on launches directly
+    if (c->use_graph && !c->profiling) {
         unsigned char key[sizeof c->graph_key];
-        int klen = graph_key(d_target, d_phi, p, d_trace, key);
-        key[klen++] = (unsigned char)c->profiling;
+        const int klen = graph_key(d_target, d_phi, p, d_trace, key);
         if (!c->graph_exec || klen != c->graph_key_len || std::memcmp(key, c->graph_key, klen) != 0) {
             free_graph(c);
             hipStream_t user = c->stream;

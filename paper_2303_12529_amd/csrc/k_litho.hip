@@ -20,6 +20,7 @@
 // exactly the A-operand the adjoint's row transform needs (k = x), and the
 // field fragments are stored and reloaded in that native layout.
 #include "ilt_internal.h"
+#include "ilt_device.h"
 
 namespace {
 
@@ -334,117 +335,6 @@ __global__ __launch_bounds__(256, 2) void k_image(const float *__restrict__ tl, 
 }
 
 // --------------------------------------------------------------------------
-// Adjoint, shared tail: (d) V = A4 Z over the block's 32 rows, then
-// W_part += c_j conj(H_j) . V, summed over the four waves in a fixed order.
-// --------------------------------------------------------------------------
-template <int FB, int MIX>
-__device__ __forceinline__ void adjoint_tail(const f4 (&accZ)[2][2 * FB + MIX], bool jok, int j, int s, int K, int P,
-                                             int Np, int AP, int y0, const float *__restrict__ ta4,
-                                             const float2 *__restrict__ coef, float2 *Ws,
-                                             float *__restrict__ dst) {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int l16 = lane & 15, lq = lane >> 4;
-    const int AB = AP / 16;
-    for (int e = threadIdx.x; e < P * P; e += 256) Ws[e] = make_float2(0.f, 0.f);
-    __syncthreads();
-    const float2 *cj = coef + ((size_t)s * K + (jok ? j : 0)) * P * P;
-    for (int ab = 0; ab < AB; ++ab) {
-        // full column blocks: real in block bb, imaginary in block FB + bb
-        f4 vr[FB + MIX], vi[FB + MIX];
-#pragma unroll
-        for (int bb = 0; bb < FB + MIX; ++bb) {
-            vr[bb] = f4{0.f, 0.f, 0.f, 0.f};
-            vi[bb] = f4{0.f, 0.f, 0.f, 0.f};
-        }
-        if (jok) {
-#pragma unroll
-            for (int yb = 0; yb < 2; ++yb)
-#pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const int y = y0 + 16 * yb + 4 * lq + i;
-                    const float car = ta4[(size_t)y * AP + 16 * ab + l16];
-                    const float cai = ta4[((size_t)Np + y) * AP + 16 * ab + l16];
-#pragma unroll
-                    for (int bb = 0; bb < FB; ++bb) {
-                        vr[bb] = mfma4(car, accZ[yb][bb][i], vr[bb]);
-                        vi[bb] = mfma4(cai, accZ[yb][bb][i], vi[bb]);
-                    }
-#pragma unroll
-                    for (int bb = 0; bb < FB; ++bb) {
-                        vr[bb] = mfma4(-cai, accZ[yb][bb + FB][i], vr[bb]);
-                        vi[bb] = mfma4(car, accZ[yb][bb + FB][i], vi[bb]);
-                    }
-                    if (MIX) {
-                        // shared block: vr <- Ar Z, vi <- Ai Z (combined across lanes below)
-                        vr[FB] = mfma4(car, accZ[yb][2 * FB][i], vr[FB]);
-                        vi[FB] = mfma4(cai, accZ[yb][2 * FB][i], vi[FB]);
-                    }
-                }
-            if (MIX) {
-                // lanes l16 < 8 hold real columns, l16 >= 8 the imaginary ones:
-                // V_re = (Ar Z_re) - (Ai Z_im), V_im = (Ar Z_im) + (Ai Z_re)
-#pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const float q1 = vr[FB][i], q2 = vi[FB][i];
-                    const float q1o = __shfl_xor(q1, 8), q2o = __shfl_xor(q2, 8);
-                    vr[FB][i] = q1 - q2o;
-                    vi[FB][i] = q1o + q2;
-                }
-            }
-        }
-        for (int w = 0; w < 4; ++w) {
-            if (wave == w && jok) {
-#pragma unroll
-                for (int bb = 0; bb < FB + MIX; ++bb)
-#pragma unroll
-                    for (int i = 0; i < 4; ++i) {
-                        const int a = 16 * ab + 4 * lq + i;
-                        const int b = bb < FB ? 16 * bb + l16 : (l16 < 8 ? 16 * FB + l16 : P);
-                        if (a < P && b < P) {
-                            const float2 c = cj[a * P + b];
-                            const float xr = vr[bb][i], xi = vi[bb][i];
-                            float2 cur = Ws[a * P + b];
-                            cur.x += c.x * xr - c.y * xi;
-                            cur.y += c.x * xi + c.y * xr;
-                            Ws[a * P + b] = cur;
-                        }
-                    }
-            }
-            __syncthreads();
-        }
-    }
-    for (int e = threadIdx.x; e < P * P; e += 256) {
-        dst[2 * e] = Ws[e].x;
-        dst[2 * e + 1] = Ws[e].y;
-    }
-}
-
-// (c) for one 16-column block xb of a 32-column chunk: Z += (G . E) B3.
-template <int NB>
-__device__ __forceinline__ void adjoint_rows(f4 (&accZ)[2][NB], const f4 (&er)[2], const f4 (&ei)[2],
-                                             const float *Bre, const float *Bim, int ldb, int xb, int lq,
-                                             int l16) {
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const int xr = 16 * xb + 4 * lq + i;
-        float br[NB], bi[NB];
-#pragma unroll
-        for (int nb = 0; nb < NB; ++nb) {
-            br[nb] = Bre[xr * ldb + 16 * nb + l16];
-            bi[nb] = Bim[xr * ldb + 16 * nb + l16];
-        }
-#pragma unroll
-        for (int nb = 0; nb < NB; ++nb)
-#pragma unroll
-            for (int yb = 0; yb < 2; ++yb) accZ[yb][nb] = mfma4(er[yb][i], br[nb], accZ[yb][nb]);
-#pragma unroll
-        for (int nb = 0; nb < NB; ++nb)
-#pragma unroll
-            for (int yb = 0; yb < 2; ++yb) accZ[yb][nb] = mfma4(ei[yb][i], bi[nb], accZ[yb][nb]);
-    }
-}
-
-// --------------------------------------------------------------------------
 // Adjoint from stored fields.  Block = (32-row tile, group of 4 kernels,
 // set); wave w handles kernel j = 4*group + w and walks all columns in
 // 32-column chunks:
@@ -525,12 +415,12 @@ __global__ __launch_bounds__(256, 2) void k_adjoint_st(const float *__restrict__
                     er[yb] = e_[yb][xb][0] * g4;
                     ei[yb] = e_[yb][xb][1] * g4;
                 }
-                adjoint_rows<NB>(accZ, er, ei, &Bs[0][0][0], &Bs[1][0][0], LDB, xb, lq, l16);
+                ilt_dev::adjoint_rows<NB>(accZ, er, ei, &Bs[0][0][0], &Bs[1][0][0], LDB, xb, lq, l16);
             }
         }
     }
     float *dst = Wpart + ((size_t)(srel * gridDim.x + ytile) * gridDim.y + kg) * P * P * 2;
-    adjoint_tail<FB, MIX>(accZ, jok, j, s, K, P, Np, AP, y0, ta4, coef, Ws, dst);
+    ilt_dev::adjoint_tail<FB, MIX>(accZ, jok, j, s, K, P, Np, AP, y0, ta4, coef, Ws, dst);
 }
 
 // --------------------------------------------------------------------------
@@ -616,13 +506,13 @@ __global__ __launch_bounds__(256, 2) void k_adjoint_rc(const float *__restrict__
                         er[yb][i] *= gv;
                         ei[yb][i] *= gv;
                     }
-                adjoint_rows<NB>(accZ, er, ei, &Bs[0][0][0], &Bs[1][0][0], LDB, xb, lq, l16);
+                ilt_dev::adjoint_rows<NB>(accZ, er, ei, &Bs[0][0][0], &Bs[1][0][0], LDB, xb, lq, l16);
             }
         }
         __syncthreads();
     }
     float *dst = Wpart + ((size_t)(srel * gridDim.x + ytile) * gridDim.y + kg) * P * P * 2;
-    adjoint_tail<FB, MIX>(accZ, jok, j, s, K, P, Np, AP, y0, ta4, coef, Ws, dst);
+    ilt_dev::adjoint_tail<FB, MIX>(accZ, jok, j, s, K, P, Np, AP, y0, ta4, coef, Ws, dst);
 }
 
 }  // namespace

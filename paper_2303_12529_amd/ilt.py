@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libilt.so")
 
 ILT_OK, ILT_EINVAL, ILT_ENOMEM, ILT_EDEVICE, ILT_ENUMERIC, ILT_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 ILT_FP32 = 0
+ILT_BF16X3 = 1
 ILT_FLAG_RECOMPUTE_FIELDS = 1
 TRACE_W = 8
 TRACE_COLUMNS = ("i", "loss", "l2", "pvb", "flips", "max_g", "dt", "t_ns")
