@@ -61,6 +61,94 @@ def cpu_baseline(workload, seed, iters):
                       % (iters, workload, seed, dt)}
 
 
+def time_to_target(ctxs, workload, seeds, extra_iters=10):
+    """Time for each form to reach the L2 that the plain FP32 loop reaches
+    after its configured number of iterations from TSDF(target), per seed.
+
+    A form's time is the wall time of one solve (TSDF init included) that
+    stops at the first iteration whose printed mask has L2 <= the target;
+    that iteration count is read from a longer traced run of the same form.
+    """
+    import numpy as np
+    import torch
+    from paper_2303_12529_amd import ilt
+    from paper_2303_12529_amd.inputs import workload_inputs
+    per_seed = []
+    for seed in seeds:
+        Z, _, _, prm = workload_inputs(workload, seed)
+        N = Z.shape[0]
+        T = prm["iters"]
+        tgt = torch.as_tensor(Z).to("cuda")
+        phi = torch.empty((N, N), dtype=torch.float32, device="cuda")
+        target_l2 = ctxs["fp32"].ilt_solve(tgt, phi, ilt.Params.from_dict(prm, iters=T, init_mode=0))["l2"]
+        row = {"seed": seed, "target_l2": int(target_l2)}
+        for name, ctx in ctxs.items():
+            tmax = T + extra_iters
+            tr = torch.zeros((tmax, ilt.TRACE_W), dtype=torch.float64, device="cuda")
+            ctx.ilt_solve(tgt, phi, ilt.Params.from_dict(prm, iters=tmax, init_mode=0), trace=tr)
+            l2 = tr[:, 2].cpu().numpy()
+            hits = np.nonzero(l2 <= target_l2)[0]
+            hits = hits[hits > 0]
+            if len(hits) == 0:
+                row[name] = None
+                continue
+            n_it = int(hits[0])
+            p = ilt.Params.from_dict(prm, iters=n_it, init_mode=0)
+            ctx.ilt_solve(tgt, phi, p)          # captures this solve's graph
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ctx.ilt_solve(tgt, phi, p)
+            torch.cuda.synchronize()
+            row[name] = {"iters": n_it, "ms": round(1e3 * (time.perf_counter() - t0), 3),
+                         "l2_at_T": int(l2[T]) if T < tmax else None}
+        per_seed.append(row)
+    out = {"target": "L2 of the plain FP32 loop after its configured iterations from TSDF(target)",
+           "seeds": list(seeds), "per_seed": per_seed, "median_ms": {}}
+    for name in ctxs:
+        ms = [r[name]["ms"] for r in per_seed if r.get(name)]
+        out["median_ms"][name] = round(float(np.median(ms)), 3) if len(ms) == len(per_seed) else None
+    if out["median_ms"].get("fp32") and out["median_ms"].get("bf16x3"):
+        out["bf16x3_speedup_vs_plain"] = round(out["median_ms"]["fp32"] / out["median_ms"]["bf16x3"], 3)
+    return out
+
+
+def batched(n_clips, lanes, precision):
+    """Batched form on n_clips synthetic clips (N uniform over 512/1024/2048,
+    one 2048 nm field): one ilt_solve_batch of the full 50-iteration loop per
+    clip (TSDF init included) on `lanes` streams, against the same clips on
+    one lane (clips strictly one after another)."""
+    import torch
+    from paper_2303_12529_amd import ilt
+    from paper_2303_12529_amd.inputs import BATCH_SIZES, batch_inputs
+    clips, H, w = batch_inputs(n_clips)
+    data = []
+    flops = 0.0
+    for Z, prm in clips:
+        N = Z.shape[0]
+        data.append((torch.as_tensor(Z).to("cuda"), torch.empty((N, N), dtype=torch.float32, device="cuda"),
+                     ilt.Params.from_dict(prm, init_mode=0), None))
+        flops += sum(v.get("flops", 0.0) for v in algorithmic_work(N, H.shape[2], H.shape[1], H.shape[0]).values()) \
+            * prm["iters"]
+    out = {"clips": n_clips, "sizes": {str(n): sum(1 for z, _ in clips if z.shape[0] == n) for n in BATCH_SIZES},
+           "iters_per_clip": clips[0][1]["iters"], "dtype": "f32" if precision == ilt.ILT_FP32 else "bf16x3"}
+    for nl in sorted({lanes, 1}, reverse=True):
+        b = ilt.Batch(H, w, BATCH_SIZES, max_clips=n_clips, n_lanes=nl, precision=precision)
+        b.solve(data)                      # captures the lanes' graphs
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        reps = b.solve(data)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        b.close()
+        out["lanes_%d" % nl] = {"s_per_batch": round(dt, 4),
+                                "clip_iters_per_s": round(n_clips * clips[0][1]["iters"] / dt, 1),
+                                "algorithmic_tflops": round(flops / dt / 1e12, 2),
+                                "l2_sum": int(sum(r["l2"] for r in reps))}
+    if lanes > 1:
+        out["speedup_vs_one_lane"] = round(out["lanes_1"]["s_per_batch"] / out["lanes_%d" % lanes]["s_per_batch"], 3)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -72,6 +160,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--precision", choices=("fp32", "bf16x3"), default="fp32",
                     help="arithmetic of the dense contractions (default: the plain FP32 loop)")
+    ap.add_argument("--batch-clips", type=int, default=64,
+                    help="clips in the batched-form measurement (0: skip)")
+    ap.add_argument("--batch-lanes", type=int, default=4)
+    ap.add_argument("--ttt-seeds", type=int, default=10,
+                    help="seeds 0..n-1 for the time-to-L2-target comparison (0: skip)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the path runs on a single MI355X "
@@ -145,6 +238,16 @@ def main():
     total_flops = sum(v.get("flops", 0.0) for v in work.values())
     tr = trace.cpu().numpy()
 
+    ttt = None
+    if args.ttt_seeds > 0:
+        ctxs = {"fp32": ctx if prec == ilt.ILT_FP32 else ilt.Context(H, w, N, precision=ilt.ILT_FP32),
+                "bf16x3": ctx if prec == ilt.ILT_BF16X3 else ilt.Context(H, w, N, precision=ilt.ILT_BF16X3)}
+        ttt = time_to_target(ctxs, args.workload, range(args.ttt_seeds))
+
+    bat = None
+    if args.batch_clips > 0:
+        bat = batched(args.batch_clips, args.batch_lanes, prec)
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(args.workload, args.seed, args.cpu_iters)
@@ -179,6 +282,8 @@ def main():
                          % (args.steps, 1e3 * wall_direct / args.steps),
         "final": {"l2": rep["l2"], "pvb": rep["pvb"], "loss": rep["loss"],
                   "l2_first": int(tr[0, 2]), "l2_last_iter": int(tr[-1, 2])},
+        "time_to_target": ttt,
+        "batched": bat,
     }
     print(json.dumps(line), flush=True)
 

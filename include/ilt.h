@@ -190,6 +190,53 @@ int ilt_set_graph(ilt_ctx *ctx, int enable);
 int ilt_profile(ilt_ctx *ctx, int enable);
 int ilt_profile_read(ilt_ctx *ctx, double *h_out, int n);
 
+/* ------------------------------------------------------------------------
+ * Batched form (many clips per call).  The paper solves one clip at a time
+ * (Sec. IV reports per-clip turnaround); this form runs the same DSO loop of
+ * ilt_solve on a list of clips, possibly of different sizes, in one call.
+ * Every clip's result is bitwise identical to ilt_solve on that clip alone.
+ *
+ * ilt_batch_create: one batch object on the current device.  optics->N is
+ * ignored; sizes[0..n_sizes) lists the clip sides the batch accepts (each in
+ * [16, 4096], distinct).  The same kernels are used at every size, so the
+ * caller passes kernels whose frequency samples suit all of them (clips of
+ * one physical field width at different pixel pitches).  n_lanes in
+ * [1, ILT_BATCH_MAX_LANES]: clips are spread over that many internal streams
+ * and run side by side; device memory grows with n_sizes x n_lanes contexts.
+ * max_clips: largest n accepted by ilt_solve_batch.  stream: the caller's
+ * stream (NULL = default); ilt_solve_batch orders its work after what is
+ * already queued there and returns when every clip is done.
+ *
+ * ilt_solve_batch: clips[i] names a listed size N, its device target
+ * [N][N] bytes, its phi [N][N] (in when params.init_mode = 1, out always;
+ * no two clips may share phi), an optional device trace [iters][8] (rows as
+ * for ilt_solve) and its own parameters (the TSDF bounds depend on the
+ * pixel pitch).  h_reports: NULL or host [n].  The first call with a given
+ * clip list captures each lane's sequence of solves into a hipGraph; later
+ * calls with an identical list (byte for byte, including struct padding)
+ * replay it.  Returns ILT_ENUMERIC if any clip's loss or gradient went
+ * non-finite (its report says which). */
+#define ILT_BATCH_MAX_SIZES 8
+#define ILT_BATCH_MAX_LANES 4
+#define ILT_BATCH_MAX_CLIPS 1024
+
+typedef struct ilt_batch ilt_batch;
+
+typedef struct {
+    int N;                            /* clip side: one of the listed sizes  */
+    const unsigned char *d_target;    /* device [N][N], nonzero = metal      */
+    float *d_phi;                     /* device [N][N], in/out               */
+    double *d_trace;                  /* NULL or device [params.iters][8]    */
+    ilt_params params;                /* this clip's loop parameters         */
+} ilt_clip;
+
+int ilt_batch_create(ilt_batch **out, const ilt_optics *optics, const int *sizes, int n_sizes,
+                     int max_clips, int n_lanes, void *stream);
+int ilt_batch_destroy(ilt_batch *batch);
+/* Capture and replay hipGraphs (1, default) or launch directly (0). */
+int ilt_batch_set_graph(ilt_batch *batch, int enable);
+int ilt_solve_batch(ilt_batch *batch, int n, const ilt_clip *clips, ilt_report *h_reports);
+
 #ifdef __cplusplus
 }
 #endif

@@ -311,7 +311,7 @@ extern "C" int ilt_create(ilt_ctx **out, const ilt_optics *o, int max_batch, voi
     ALLOC(G, (size_t)ns * N * N);
     ALLOC(g, (size_t)N * N);
     ALLOC(phi2, (size_t)N * N);
-    c->n_wpart = ns * ((N + 31) / 32) * ((K + 3) / 4) * P * P * 2;
+    c->n_wpart = ns * std::max(((N + 31) / 32) * ((K + 3) / 4), ((N + 127) / 128) * K) * P * P * 2;
     ALLOC(Wpart, (size_t)c->n_wpart);
     ALLOC(edtg, (size_t)N * N);
     ALLOC(colbits, (size_t)((N + 31) / 32) * N);
@@ -341,14 +341,24 @@ extern "C" int ilt_create(ilt_ctx **out, const ilt_optics *o, int max_batch, voi
                     lh[(((size_t)part * Np + y) * 2 + 0) * KP + r] = h;
                     lh[(((size_t)part * Np + y) * 2 + 1) * KP + r] = l;
                 }
-        for (int part = 0; part < 2; ++part)
-            for (int x = 0; x < Np; ++x)
-                for (int n = 0; n < NZ; ++n) {
-                    uint16_t h, l;
-                    split_bf(tb[((size_t)part * Np + x) * NZ + n], h, l);
-                    bh[(((size_t)part * 2 + 0) * NZ + n) * Np + x] = h;
-                    bh[(((size_t)part * 2 + 1) * NZ + n) * Np + x] = l;
-                }
+        // B3 table in matrix-core fragment order, per 32-column chunk:
+        // [chunk][part][n-block][hi|lo][lane][8]; lane l, element e holds
+        // column n = 16 nb + l % 16, row x = 32 chunk + 4 (l / 16) + e for
+        // e < 4 and 32 chunk + 16 + 4 (l / 16) + e - 4 otherwise
+        const int NB = NZ / 16;
+        for (int ch = 0; ch < Np / 32; ++ch)
+            for (int part = 0; part < 2; ++part)
+                for (int nb = 0; nb < NB; ++nb)
+                    for (int l = 0; l < 64; ++l)
+                        for (int el = 0; el < 8; ++el) {
+                            const int n = 16 * nb + l % 16;
+                            const int x = 32 * ch + (el < 4 ? 4 * (l / 16) + el : 16 + 4 * (l / 16) + el - 4);
+                            uint16_t h, lo;
+                            split_bf(tb[((size_t)part * Np + x) * NZ + n], h, lo);
+                            const size_t base = ((((size_t)ch * 2 + part) * NB + nb) * 2) * 64 + l;
+                            bh[base * 8 + el] = h;
+                            bh[(base + 64) * 8 + el] = lo;
+                        }
         e = hipMemcpy(c->tlhl, lh.data(), lh.size() * 2, hipMemcpyHostToDevice);
         if (e == hipSuccess) e = hipMemcpy(c->tbhl, bh.data(), bh.size() * 2, hipMemcpyHostToDevice);
     }
@@ -660,5 +670,257 @@ extern "C" int ilt_profile_read(ilt_ctx *c, double *h_out, int n) {
         h_out[2 * c->ev_phase[i]] += ms;
         h_out[2 * c->ev_phase[i] + 1] += 1.0;
     }
+    return ILT_OK;
+}
+
+// ---------------------------------------------------------------- batched form
+//
+// Many clips, possibly of different sizes, solved in one call.  Clips of one
+// size share that size's DFT tables and kernel copies through per-(size,
+// lane) contexts; the clips are spread over n_lanes streams (longest clip
+// first onto the least-loaded lane), so that small clips, which cannot fill
+// the chip alone, run side by side.  Each lane's whole sequence of solves is
+// captured into one hipGraph the first time a clip list is seen and replayed
+// afterwards.  The final scalars of every clip are copied to a device report
+// slot at the end of its solve and read back once.
+
+struct ilt_batch {
+    int n_sizes = 0, n_lanes = 0, max_clips = 0;
+    int sizes[ILT_BATCH_MAX_SIZES] = {};
+    ilt_ctx *ctx[ILT_BATCH_MAX_SIZES][ILT_BATCH_MAX_LANES] = {};
+    hipStream_t user = nullptr;
+    hipStream_t lane[ILT_BATCH_MAX_LANES] = {};
+    hipStream_t cap[ILT_BATCH_MAX_LANES] = {};
+    hipEvent_t ev_start = nullptr;
+    hipEvent_t ev_lane[ILT_BATCH_MAX_LANES] = {};
+    double *d_reports = nullptr;            // [max_clips][SC_COUNT]
+    double *h_reports = nullptr;            // pinned mirror
+    hipGraph_t graph[ILT_BATCH_MAX_LANES] = {};
+    hipGraphExec_t exec[ILT_BATCH_MAX_LANES] = {};
+    std::vector<unsigned char> key;
+    std::vector<int> lane_of;               // clip -> lane of the captured plan
+    int use_graph = 1;
+};
+
+namespace {
+
+void batch_free_graphs(ilt_batch *b) {
+    for (int l = 0; l < ILT_BATCH_MAX_LANES; ++l) {
+        if (b->exec[l]) (void)hipGraphExecDestroy(b->exec[l]);
+        if (b->graph[l]) (void)hipGraphDestroy(b->graph[l]);
+        b->exec[l] = nullptr;
+        b->graph[l] = nullptr;
+    }
+    b->key.clear();
+}
+
+void batch_free(ilt_batch *b) {
+    if (!b) return;
+    batch_free_graphs(b);
+    for (int s = 0; s < ILT_BATCH_MAX_SIZES; ++s)
+        for (int l = 0; l < ILT_BATCH_MAX_LANES; ++l)
+            if (b->ctx[s][l]) {
+                free_ctx(b->ctx[s][l]);
+                b->ctx[s][l] = nullptr;
+            }
+    for (int l = 0; l < ILT_BATCH_MAX_LANES; ++l) {
+        if (b->lane[l]) (void)hipStreamDestroy(b->lane[l]);
+        if (b->cap[l]) (void)hipStreamDestroy(b->cap[l]);
+        if (b->ev_lane[l]) (void)hipEventDestroy(b->ev_lane[l]);
+    }
+    if (b->ev_start) (void)hipEventDestroy(b->ev_start);
+    if (b->d_reports) (void)hipFree(b->d_reports);
+    if (b->h_reports) (void)hipHostFree(b->h_reports);
+    delete b;
+}
+
+int size_index(const ilt_batch *b, int N) {
+    for (int s = 0; s < b->n_sizes; ++s)
+        if (b->sizes[s] == N) return s;
+    return -1;
+}
+
+// Longest-processing-time-first assignment of clips to lanes (cost ~ N^2);
+// ties keep the clip order, so the plan is a pure function of the clip list.
+void plan_lanes(const ilt_batch *b, int n, const ilt_clip *clips, std::vector<int> &lane_of) {
+    std::vector<int> order(n);
+    for (int i = 0; i < n; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a, int c) { return (long long)clips[a].N * clips[a].N > (long long)clips[c].N * clips[c].N; });
+    std::vector<double> load(b->n_lanes, 0.0);
+    lane_of.assign(n, 0);
+    for (int i : order) {
+        int best = 0;
+        for (int l = 1; l < b->n_lanes; ++l)
+            if (load[l] < load[best]) best = l;
+        lane_of[i] = best;
+        load[best] += (double)clips[i].N * clips[i].N * (clips[i].params.iters + 1);
+    }
+}
+
+// Enqueue the clips of lane l, in clip order, on each context's current stream.
+int enqueue_lane(ilt_batch *b, int l, int n, const ilt_clip *clips, const std::vector<int> &lane_of) {
+    for (int i = 0; i < n; ++i) {
+        if (lane_of[i] != l) continue;
+        ilt_ctx *c = b->ctx[size_index(b, clips[i].N)][l];
+        int r = enqueue_solve(c, clips[i].d_target, clips[i].d_phi, &clips[i].params, clips[i].d_trace);
+        if (r != ILT_OK) return r;
+        HIPCHK(launch_copy(c, reinterpret_cast<float *>(b->d_reports + (size_t)i * SC_COUNT),
+                           reinterpret_cast<const float *>(c->scal), 2 * SC_COUNT));
+    }
+    return ILT_OK;
+}
+
+void set_lane_streams(ilt_batch *b, int l, hipStream_t s) {
+    for (int z = 0; z < b->n_sizes; ++z) b->ctx[z][l]->stream = s;
+}
+
+}  // namespace
+
+extern "C" int ilt_batch_create(ilt_batch **out, const ilt_optics *o, const int *sizes, int n_sizes,
+                                int max_clips, int n_lanes, void *stream) {
+    if (!out) return fail(ILT_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!o) return fail(ILT_EINVAL, "optics is NULL");
+    if (!sizes || n_sizes < 1 || n_sizes > ILT_BATCH_MAX_SIZES)
+        return fail(ILT_EINVAL, "n_sizes must be in [1, %d]", ILT_BATCH_MAX_SIZES);
+    if (n_lanes < 1 || n_lanes > ILT_BATCH_MAX_LANES)
+        return fail(ILT_EINVAL, "n_lanes must be in [1, %d]", ILT_BATCH_MAX_LANES);
+    if (max_clips < 1 || max_clips > ILT_BATCH_MAX_CLIPS)
+        return fail(ILT_EINVAL, "max_clips must be in [1, %d]", ILT_BATCH_MAX_CLIPS);
+    for (int s = 0; s < n_sizes; ++s)
+        for (int t = 0; t < s; ++t)
+            if (sizes[s] == sizes[t]) return fail(ILT_EINVAL, "size %d listed twice", sizes[s]);
+    ilt_batch *b = new (std::nothrow) ilt_batch();
+    if (!b) return fail(ILT_ENOMEM, "out of host memory");
+    b->n_sizes = n_sizes;
+    b->n_lanes = n_lanes;
+    b->max_clips = max_clips;
+    b->user = static_cast<hipStream_t>(stream);
+    hipError_t e = hipSuccess;
+    for (int l = 0; l < n_lanes && e == hipSuccess; ++l) {
+        e = hipStreamCreateWithFlags(&b->lane[l], hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->cap[l], hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_lane[l], hipEventDisableTiming);
+    }
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_start, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipMalloc(&b->d_reports, (size_t)max_clips * SC_COUNT * sizeof(double));
+    if (e == hipSuccess) e = hipHostMalloc(&b->h_reports, (size_t)max_clips * SC_COUNT * sizeof(double));
+    if (e != hipSuccess) {
+        batch_free(b);
+        return fail(ILT_EDEVICE, "batch set-up failed: %s", hipGetErrorString(e));
+    }
+    for (int s = 0; s < n_sizes; ++s) {
+        b->sizes[s] = sizes[s];
+        ilt_optics os = *o;
+        os.N = sizes[s];
+        for (int l = 0; l < n_lanes; ++l) {
+            const int r = ilt_create(&b->ctx[s][l], &os, 1, b->lane[l]);
+            if (r != ILT_OK) {
+                batch_free(b);
+                return r;   // message set by ilt_create
+            }
+        }
+    }
+    *out = b;
+    return ILT_OK;
+}
+
+extern "C" int ilt_batch_destroy(ilt_batch *b) {
+    if (!b) return fail(ILT_EINVAL, "batch is NULL");
+    (void)hipDeviceSynchronize();
+    batch_free(b);
+    return ILT_OK;
+}
+
+extern "C" int ilt_batch_set_graph(ilt_batch *b, int enable) {
+    if (!b) return fail(ILT_EINVAL, "batch is NULL");
+    b->use_graph = enable ? 1 : 0;
+    if (!enable) batch_free_graphs(b);
+    return ILT_OK;
+}
+
+extern "C" int ilt_solve_batch(ilt_batch *b, int n, const ilt_clip *clips, ilt_report *h_reports) {
+    if (!b) return fail(ILT_EINVAL, "batch is NULL");
+    if (n < 1 || n > b->max_clips) return fail(ILT_EINVAL, "n must be in [1, %d]", b->max_clips);
+    if (!clips) return fail(ILT_EINVAL, "clips is NULL");
+    int r;
+    for (int i = 0; i < n; ++i) {
+        const ilt_clip &k = clips[i];
+        const int s = size_index(b, k.N);
+        if (s < 0) return fail(ILT_EINVAL, "clip %d: size %d was not listed at creation", i, k.N);
+        if ((r = check_ptr(k.d_target, "d_target", 1))) return r;
+        if ((r = check_ptr(k.d_phi, "d_phi"))) return r;
+        if (k.d_trace && !aligned(k.d_trace, 8)) return fail(ILT_EINVAL, "clip %d: d_trace not 8-byte aligned", i);
+        if ((r = check_params(b->ctx[s][0], &k.params, true))) return r;
+        if (k.params.init_mode != 0 && k.params.init_mode != 1) return fail(ILT_EINVAL, "clip %d: bad init_mode", i);
+        for (int t = 0; t < i; ++t)
+            if (clips[t].d_phi == k.d_phi) return fail(ILT_EINVAL, "clips %d and %d share d_phi", t, i);
+    }
+    std::vector<int> lane_of;
+    plan_lanes(b, n, clips, lane_of);
+    std::vector<unsigned char> key(sizeof n + (size_t)n * sizeof(ilt_clip));
+    std::memcpy(key.data(), &n, sizeof n);
+    std::memcpy(key.data() + sizeof n, clips, (size_t)n * sizeof(ilt_clip));
+
+    if (b->use_graph && key != b->key) {
+        batch_free_graphs(b);
+        for (int l = 0; l < b->n_lanes; ++l) {
+            if (std::find(lane_of.begin(), lane_of.end(), l) == lane_of.end()) continue;
+            set_lane_streams(b, l, b->cap[l]);
+            hipError_t e = hipStreamBeginCapture(b->cap[l], hipStreamCaptureModeRelaxed);
+            if (e != hipSuccess) {
+                set_lane_streams(b, l, b->lane[l]);
+                batch_free_graphs(b);
+                return fail(ILT_EDEVICE, "hipStreamBeginCapture: %s", hipGetErrorString(e));
+            }
+            const int rc = enqueue_lane(b, l, n, clips, lane_of);
+            hipGraph_t g = nullptr;
+            e = hipStreamEndCapture(b->cap[l], &g);
+            set_lane_streams(b, l, b->lane[l]);
+            b->graph[l] = g;
+            if (rc != ILT_OK || e != hipSuccess) {
+                batch_free_graphs(b);
+                return rc != ILT_OK ? rc : fail(ILT_EDEVICE, "hipStreamEndCapture: %s", hipGetErrorString(e));
+            }
+            e = hipGraphInstantiate(&b->exec[l], g, nullptr, nullptr, 0);
+            if (e != hipSuccess) {
+                batch_free_graphs(b);
+                return fail(ILT_EDEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e));
+            }
+        }
+        b->key = key;
+        b->lane_of = lane_of;
+    }
+    HIPCHK(hipEventRecord(b->ev_start, b->user));
+    for (int l = 0; l < b->n_lanes; ++l) {
+        if (std::find(lane_of.begin(), lane_of.end(), l) == lane_of.end()) continue;
+        HIPCHK(hipStreamWaitEvent(b->lane[l], b->ev_start, 0));
+        if (b->use_graph) {
+            HIPCHK(hipGraphLaunch(b->exec[l], b->lane[l]));
+        } else if ((r = enqueue_lane(b, l, n, clips, lane_of))) {
+            return r;
+        }
+        HIPCHK(hipEventRecord(b->ev_lane[l], b->lane[l]));
+        HIPCHK(hipStreamWaitEvent(b->user, b->ev_lane[l], 0));
+    }
+    HIPCHK(hipMemcpyAsync(b->h_reports, b->d_reports, (size_t)n * SC_COUNT * sizeof(double), hipMemcpyDeviceToHost,
+                          b->user));
+    HIPCHK(hipStreamSynchronize(b->user));
+    int status = ILT_OK;
+    for (int i = 0; i < n; ++i) {
+        const double *sc = b->h_reports + (size_t)i * SC_COUNT;
+        const bool bad = sc[SC_NONFIN] > 0.0 || !std::isfinite(sc[SC_LOSS]);
+        if (h_reports) {
+            h_reports[i].iters_done = clips[i].params.iters;
+            h_reports[i].loss = sc[SC_LOSS];
+            h_reports[i].l2 = (long long)sc[SC_L2];
+            h_reports[i].pvb = (long long)sc[SC_PVB];
+            h_reports[i].flips = (long long)sc[SC_FLIPS];
+            h_reports[i].status = bad ? ILT_ENUMERIC : ILT_OK;
+        }
+        if (bad) status = ILT_ENUMERIC;
+    }
+    if (status != ILT_OK) return fail(ILT_ENUMERIC, "non-finite loss or gradient in a clip of the batch");
     return ILT_OK;
 }

@@ -5,7 +5,7 @@
 namespace ilt_dev {
 
 // --------------------------------------------------------------------------
-// Adjoint, shared tail: (d) V = A4 Z over the block's 32 rows, then
+// Adjoint, shared tail: (d) V = A4 Z over each wave's 32 rows y0.., then
 // W_part += c_j conj(H_j) . V, summed over the four waves in a fixed order.
 // --------------------------------------------------------------------------
 template <int FB, int MIX>

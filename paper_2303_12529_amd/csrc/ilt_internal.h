@@ -72,7 +72,7 @@ struct ilt_ctx {
     float *sw;         // [n_sets][K]         sqrt(w_k) / N^2
     float2 *coef;      // [n_sets][K][P][P]   sqrt(w_k)/N^2 conj(H)
     __bf16 *tlhl;      // split-BF16 form: L operands [2][Np][hi|lo][KP]
-    __bf16 *tbhl;      // split-BF16 form: B3 [2][hi|lo][NZ][Np]
+    __bf16 *tbhl;      // split-BF16 form: B3 in fragment order [Np/32][2][NZ/16][hi|lo][64][8]
     __bf16 *Yhl;       // split-BF16 form: window rows [n_sets][K][Np][hi|lo][KP]
 
     // workspaces
@@ -133,13 +133,14 @@ hipError_t launch_make_Y(ilt_ctx *c, int set_lo, int set_hi);
 hipError_t launch_image_to(ilt_ctx *c, int set_lo, int set_hi, float *out, int store_fields);
 hipError_t launch_adjoint(ilt_ctx *c, const float *G, size_t g_set_stride, int set_lo, int set_hi,
                           int fields_stored);
-hipError_t launch_window_sum(ilt_ctx *c, int set_lo, int set_hi);
+hipError_t launch_window_sum(ilt_ctx *c, int set_lo, int set_hi);  // partial count follows c->precision
 hipError_t launch_gradient(ilt_ctx *c, float *g_out, double *maxpart);
 
 // ---- launchers (k_bf16.hip) ----
 hipError_t launch_split_rows(ilt_ctx *c, int set_lo, int set_hi);
 hipError_t launch_image_b3(ilt_ctx *c, int set_lo, int set_hi, float *out);
 hipError_t launch_adjoint_b3(ilt_ctx *c, const float *G, size_t g_set_stride, int set_lo, int set_hi);
+int adjoint_b3_parts(const ilt_ctx *c, int nsets);
 
 // ---- launchers (k_pixel.hip) ----
 int resist_blocks(const ilt_ctx *c);

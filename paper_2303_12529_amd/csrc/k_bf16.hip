@@ -41,14 +41,71 @@ __device__ __forceinline__ bf8 bf8_zero() {
     return z;
 }
 
-// k-group g (8 wide) of the concatenated inner dimension: segment p = g / (KP/8)
-// and first row r0.  A-side reads hi for p = 0, 1 and lo for p = 2; B-side
-// reads hi for p = 0, 2 and lo for p = 1; p >= 3 is zero padding.
+// Order of the 8-wide k-groups of the concatenated inner dimension.  Step st
+// of a contraction (32 wide) gives lane l the group of segment p, first row
+// r0; B-side operands live in registers, and slot() says which register
+// holds the B data of step st.  The first NF steps take hi rows of segment 0
+// and the next NF steps the same rows of segment 2, whose B-side data (hi) is
+// identical, so they share registers: NS - NF registers per operand instead
+// of NS.  The remaining groups (tails of segments 0 and 2, all of segment 1,
+// then zero padding, p = 3) fill the last steps in that order.
+// A-side reads hi for p = 0, 1 and lo for p = 2; B-side reads hi for p = 0, 2
+// and lo for p = 1.
 template <int KP>
-__device__ __forceinline__ void kgroup(int g, int &p, int &r0) {
-    constexpr int KP8 = KP / 8;
-    p = g / KP8;
-    r0 = (g - p * KP8) * 8;
+struct kmap {
+    static constexpr int KP8 = KP / 8;
+    static constexpr int NF = KP8 / 4;
+    static constexpr int NS = (3 * KP8 + 3) / 4;
+    static constexpr int NSL = NS - NF;
+    static constexpr int R = KP8 - 4 * NF;
+    __device__ static constexpr int slot(int st) { return st < NF ? st : st - NF; }
+    // step whose groups are loaded into register slot sl
+    __device__ static constexpr int load_step(int sl) { return sl < NF ? sl : sl + NF; }
+    __device__ static __forceinline__ void group(int st, int lq, int &p, int &r0) {
+        int rb;
+        if (st < NF) {
+            p = 0;
+            rb = 4 * st + lq;
+        } else if (st < 2 * NF) {
+            p = 2;
+            rb = 4 * (st - NF) + lq;
+        } else {
+            const int idx = 4 * (st - 2 * NF) + lq;
+            if (idx < R) {
+                p = 0;
+                rb = 4 * NF + idx;
+            } else if (idx < 2 * R) {
+                p = 2;
+                rb = 4 * NF + idx - R;
+            } else if (idx < 2 * R + KP8) {
+                p = 1;
+                rb = idx - 2 * R;
+            } else {
+                p = 3;
+                rb = 0;
+            }
+        }
+        r0 = 8 * rb;
+    }
+};
+
+// B-side (L) operands of one wave's 16-row block y..y+15 for both parts.
+template <int KP>
+__device__ __forceinline__ void load_l_operands(const __bf16 *__restrict__ tlhl, int Np, size_t y, int lq,
+                                                bf8 (&b1)[kmap<KP>::NSL], bf8 (&b2)[kmap<KP>::NSL]) {
+#pragma unroll
+    for (int sl = 0; sl < kmap<KP>::NSL; ++sl) {
+        int p, r0;
+        kmap<KP>::group(kmap<KP>::load_step(sl), lq, p, r0);
+        if (p >= 3) {
+            b1[sl] = bf8_zero();
+            b2[sl] = bf8_zero();
+        } else {
+            const int hl = (p == 1);
+            b1[sl] = *reinterpret_cast<const bf8 *>(tlhl + ((0 * (size_t)Np + y) * 2 + hl) * KP + r0);
+            b2[sl] = *reinterpret_cast<const bf8 *>(tlhl + ((1 * (size_t)Np + y) * 2 + hl) * KP + r0);
+        }
+    }
 }
 
 // --------------------------------------------------------------------------
@@ -97,11 +154,10 @@ __device__ __forceinline__ void xcd_tile(int b, int nblk, int NY, int NX, int &t
 // double-buffered, shared by the four waves.
 // --------------------------------------------------------------------------
 template <int KP>
-__global__ __launch_bounds__(256, KP > 40 ? 1 : 2) void k_image_b3(const __bf16 *__restrict__ tlhl, const __bf16 *__restrict__ Yhl,
+__global__ __launch_bounds__(256, 2) void k_image_b3(const __bf16 *__restrict__ tlhl, const __bf16 *__restrict__ Yhl,
                                                       int nj, int N, int Np, int set_lo, int nsets,
                                                       float *__restrict__ out) {
-    constexpr int KC = (3 * KP + 31) / 32 * 32;
-    constexpr int NS = KC / 32;
+    constexpr int NS = kmap<KP>::NS, NSL = kmap<KP>::NSL;
     constexpr int RW = 2 * KP + 8;                 // LDS row (one column x), bf16
     constexpr int NV = (64 * 2 * KP / 8 + 255) / 256;
     __shared__ __attribute__((aligned(16))) __bf16 Ys[2][64][RW];
@@ -114,23 +170,9 @@ __global__ __launch_bounds__(256, KP > 40 ? 1 : 2) void k_image_b3(const __bf16 
     const int x0 = tx * 64;
     const int yw = ty * 128 + wave * 32;
 
-    bf8 b1[2][NS], b2[2][NS];
+    bf8 b1[2][NSL], b2[2][NSL];
 #pragma unroll
-    for (int yb = 0; yb < 2; ++yb)
-#pragma unroll
-        for (int st = 0; st < NS; ++st) {
-            int p, r0;
-            kgroup<KP>(4 * st + lq, p, r0);
-            if (p >= 3) {
-                b1[yb][st] = bf8_zero();
-                b2[yb][st] = bf8_zero();
-            } else {
-                const int hl = (p == 1);
-                const size_t y = yw + 16 * yb + l16;
-                b1[yb][st] = *reinterpret_cast<const bf8 *>(tlhl + ((0 * (size_t)Np + y) * 2 + hl) * KP + r0);
-                b2[yb][st] = *reinterpret_cast<const bf8 *>(tlhl + ((1 * (size_t)Np + y) * 2 + hl) * KP + r0);
-            }
-        }
+    for (int yb = 0; yb < 2; ++yb) load_l_operands<KP>(tlhl, Np, (size_t)yw + 16 * yb + l16, lq, b1[yb], b2[yb]);
     f4 accI[4][2];
 #pragma unroll
     for (int xb = 0; xb < 4; ++xb)
@@ -176,7 +218,8 @@ __global__ __launch_bounds__(256, KP > 40 ? 1 : 2) void k_image_b3(const __bf16 
 #pragma unroll
             for (int st = 0; st < NS; ++st) {
                 int p, r0;
-                kgroup<KP>(4 * st + lq, p, r0);
+                kmap<KP>::group(st, lq, p, r0);
+                const int sl = kmap<KP>::slot(st);
                 const int off = (p == 2 ? KP : 0) + r0;
 #pragma unroll
                 for (int xl = 0; xl < 2; ++xl) {
@@ -184,8 +227,8 @@ __global__ __launch_bounds__(256, KP > 40 ? 1 : 2) void k_image_b3(const __bf16 
                     bf8 a = (p >= 3) ? bf8_zero() : *reinterpret_cast<const bf8 *>(&Ys[buf][16 * xb + l16][off]);
 #pragma unroll
                     for (int yb = 0; yb < 2; ++yb) {
-                        er[xl][yb] = mfma_b(a, b1[yb][st], er[xl][yb]);
-                        ei[xl][yb] = mfma_b(a, b2[yb][st], ei[xl][yb]);
+                        er[xl][yb] = mfma_b(a, b1[yb][sl], er[xl][yb]);
+                        ei[xl][yb] = mfma_b(a, b2[yb][sl], ei[xl][yb]);
                     }
                 }
             }
@@ -223,48 +266,97 @@ __global__ __launch_bounds__(256, KP > 40 ? 1 : 2) void k_image_b3(const __bf16 
 }
 
 // --------------------------------------------------------------------------
-// Adjoint, split-BF16, fields recomputed.  Block = (32-row tile, 4 kernels,
-// set); per 32-column chunk, each wave:
-//   (a) E^T = Y_j^T L^T                split-BF16 GEMM, K = 3 KP padded
-//   (b) X = G . E                       FP32, G tile from LDS
+// Adjoint, split-BF16, fields recomputed.  Block = (128-row tile, range of
+// 32-column chunks, kernel j, set); wave w owns rows 32w..32w+31 of the tile.
+// Per chunk the four waves share, through LDS, the Y_j chunk (hi|lo rows),
+// the B3 chunk (stored in matrix-core fragment order) and the G tile.  They
+// are copied global -> LDS by the memory unit without register staging; Y_j
+// and B3 are double-buffered so that chunk c+1 arrives while chunk c is
+// contracted, the G tile is read into registers first and then refilled.
+// Each wave:
+//   (a) E^T = Y_j^T L^T                split-BF16 GEMM, K = 3 KP padded; the
+//       L-side operands of the wave's rows stay in registers
+//   (b) X = G . E                       FP32
 //   (c) Z += X B3                       X split in registers; its 8 values per
 //       lane (columns 4(l/16)+i of both 16-column blocks) form one k-group,
-//       and the B3 rows are read in the same order
-// then the FP32 window contraction and W partial of the plain path.
+//       matching the fragment order of the B3 table
+// real part first, then imaginary part.  Then the FP32 window contraction;
+// the four waves' W contributions (same kernel j) are summed in a fixed
+// order into the block's partial.
+//
+// The copies are issued from inline assembly, so the compiler neither
+// counts them nor waits for them: every wave waits for its own copies
+// (vmcnt 0) and then meets the others at a barrier before reading them.
 // --------------------------------------------------------------------------
-template <int KP, int FB, int MIX>
+__device__ __forceinline__ unsigned lds_offset(const void *p) {
+    return (unsigned)(size_t)(const __attribute__((address_space(3))) void *)p;
+}
+
+// global -> LDS copy of 16 bytes per lane: lane l's bytes land at
+// lds + 16 l (lds wave-uniform); M0 is restored afterwards
+__device__ __forceinline__ void lds_dma16(const void *g, const void *lds) {
+    const unsigned base = __builtin_amdgcn_readfirstlane(lds_offset(lds));
+    unsigned saved;
+    asm volatile(
+        "s_mov_b32 %0, m0\n\t"
+        "s_mov_b32 m0, %2\n\t"
+        "global_load_lds_dwordx4 %1, off\n\t"
+        "s_mov_b32 m0, %0"
+        : "=&s"(saved)
+        : "v"(g), "s"(base)
+        : "memory");
+}
+
+// wait for every outstanding memory operation of this wave, the copies
+// included; as a compiler-visible wait it also retires the compiler's own
+// pending loads, so that none of its waits land inside the chunk loop
+__device__ __forceinline__ void wait_copies() { __builtin_amdgcn_s_waitcnt(0); }
+
+// G[y][x..x+3] (x a multiple of 4), zero outside the N x N image, for N % 4 != 0
+__device__ __forceinline__ f4 load_g4_any(const float *__restrict__ G, int N, int y, int x) {
+    const bool ok = y < N && x < N;
+    const int yc = ok ? y : 0, xc = ok ? x : 0;
+    f4 v;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int xi = xc + i < N ? xc + i : N - 1;
+        v[i] = (ok && x + i < N) ? G[(size_t)yc * N + xi] : 0.f;
+    }
+    return v;
+}
+
+template <int KP, int FB, int MIX, bool A4>
 __global__ __launch_bounds__(256, 2) void k_adjoint_b3(const __bf16 *__restrict__ tlhl,
-                                                        const __bf16 *__restrict__ tbhl,
+                                                        const __bf16 *__restrict__ tbf,
                                                         const float *__restrict__ ta4,
                                                         const __bf16 *__restrict__ Yhl, const float *__restrict__ G,
                                                         size_t g_set_stride, const float2 *__restrict__ coef, int K,
-                                                        int P, int N, int Np, int AP, int set_lo,
+                                                        int P, int N, int Np, int AP, int set_lo, int xsplit,
                                                         float *__restrict__ Wpart) {
-    constexpr int KC = (3 * KP + 31) / 32 * 32;
-    constexpr int NS = KC / 32;
-    constexpr int RW = 2 * KP + 8;
+    constexpr int NS = kmap<KP>::NS, NSL = kmap<KP>::NSL;
     constexpr int NZ = 32 * FB + 16 * MIX, NB = NZ / 16;
-    constexpr int BW = 32 + 8;                     // B3 chunk row (bf16)
-    constexpr int NBV = (2 * 2 * NZ * 4 + 255) / 256;
-    __shared__ __attribute__((aligned(16))) __bf16 Ls[2][32][RW];
-    __shared__ __attribute__((aligned(16))) __bf16 Bt[2][2][NZ][BW];
-    __shared__ __attribute__((aligned(16))) float Gs[32][36];
-    __shared__ float2 Ws[ILT_MAX_P * ILT_MAX_P];
+    constexpr int RWU = 2 * KP / 8 + 1;            // 16-byte units per LDS row of Y (one pad unit)
+    constexpr int NYI = (32 * RWU + 63) / 64;      // 64-unit copies per Y chunk
+    constexpr int NBI = 2 * NB * 2;                // 64-unit copies per B3 chunk
+    constexpr int GRU = 9;                         // 16-byte units per LDS row of G (one pad unit)
+    constexpr int NGI = 128 * GRU / 64;            // 64-unit copies per G tile
+    __shared__ u4 Yc[2][NYI * 64];
+    __shared__ u4 Bc[2][NBI * 64];
+    // G tile during the chunk loop, the window accumulator W afterwards
+    __shared__ u4 GWs[128 * GRU];
+    static_assert(sizeof(GWs) >= ILT_MAX_P * ILT_MAX_P * sizeof(float2), "W fits the G tile");
+    const float *Gs = reinterpret_cast<const float *>(GWs);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int l16 = lane & 15, lq = lane >> 4;
-    const int ytile = blockIdx.x, kg = blockIdx.y, srel = blockIdx.z, s = set_lo + srel;
-    const int y0 = ytile * 32;
-    const int j = kg * 4 + wave;
-    const bool jok = j < K;
+    const int ytile = blockIdx.x / xsplit, xs = blockIdx.x - ytile * xsplit;
+    const int j = blockIdx.y, srel = blockIdx.z, s = set_lo + srel;
+    const int yt0 = ytile * 128, y0 = yt0 + 32 * wave;
+    const int nchunk = (N + 31) / 32;
+    const int c_lo = xs * nchunk / xsplit, c_hi = (xs + 1) * nchunk / xsplit;
 
-    // L operands of the block's 32 rows (both parts, hi and lo)
-    for (int e = threadIdx.x; e < 2 * 32 * (2 * KP / 8); e += 256) {
-        const int part = e / (32 * (2 * KP / 8));
-        const int rem = e % (32 * (2 * KP / 8));
-        const int yy = rem / (2 * KP / 8), q = rem % (2 * KP / 8);
-        *reinterpret_cast<u4 *>(&Ls[part][yy][q * 8]) =
-            *reinterpret_cast<const u4 *>(tlhl + ((size_t)part * Np + y0 + yy) * 2 * KP + q * 8);
-    }
+    bf8 b1[2][NSL], b2[2][NSL];
+#pragma unroll
+    for (int yb = 0; yb < 2; ++yb) load_l_operands<KP>(tlhl, Np, (size_t)y0 + 16 * yb + l16, lq, b1[yb], b2[yb]);
 
     f4 accZ[2][NB];
 #pragma unroll
@@ -272,103 +364,110 @@ __global__ __launch_bounds__(256, 2) void k_adjoint_b3(const __bf16 *__restrict_
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb) accZ[yb][nb] = f4{0.f, 0.f, 0.f, 0.f};
 
-    const __bf16 *Yj = Yhl + (size_t)(s * K + (jok ? j : 0)) * Np * 2 * KP;
+    const __bf16 *Yj = Yhl + (size_t)(s * K + j) * Np * 2 * KP;
     const float *Gsrc = G + (size_t)s * g_set_stride;
-    const int nchunk = (N + 31) / 32;
-    for (int c = 0; c < nchunk; ++c) {
+    // Y_j and B3 of chunk c_ -> buffer bb; pad units and rows past the chunk
+    // copy a valid in-chunk unit (never read back)
+    auto copy_yb = [&](int c_, int bb) {
+        const int x0_ = c_ * 32;
+        for (int i = wave; i < NYI; i += 4) {
+            const int U = 64 * i + lane;
+            int row = U / RWU, col = U - row * RWU;
+            if (row > 31) row = 31;
+            if (col >= RWU - 1) col = 0;
+            lds_dma16(Yj + (size_t)(x0_ + row) * 2 * KP + col * 8, &Yc[bb][64 * i]);
+        }
+        for (int i = wave; i < NBI; i += 4)
+            lds_dma16(tbf + ((size_t)c_ * NBI * 64 + 64 * i + lane) * 8, &Bc[bb][64 * i]);
+    };
+    // G rows yt0.., columns 32 c_.. (clamped into the image; values outside it
+    // are masked when read)
+    auto copy_g = [&](int c_) {
+        const int x0_ = c_ * 32;
+        for (int i = wave; i < NGI; i += 4) {
+            const int U = 64 * i + lane;
+            const int row = U / GRU, col = U - row * GRU;
+            const int y = min(yt0 + row, N - 1);
+            const int x = min(x0_ + 4 * (col < GRU - 1 ? col : 0), N - 4);
+            lds_dma16(Gsrc + (size_t)y * N + x, &GWs[64 * i]);
+        }
+    };
+    if (c_lo < c_hi) {
+        copy_yb(c_lo, 0);
+        if (A4) copy_g(c_lo);
+    }
+    wait_copies();
+    __syncthreads();
+    for (int c = c_lo, it = 0; c < c_hi; ++c, ++it) {
+        const int bb = it & 1;
         const int x0 = c * 32;
-        __syncthreads();
-#pragma unroll
-        for (int v = 0; v < NBV; ++v) {
-            const int e = threadIdx.x + 256 * v;
-            if (e < 2 * 2 * NZ * 4) {
-                const int row = e >> 2, q = e & 3;        // row = (part, hl, n)
-                const int part = row / (2 * NZ), hl = (row / NZ) & 1, n = row % NZ;
-                *reinterpret_cast<u4 *>(&Bt[part][hl][n][q * 8]) =
-                    *reinterpret_cast<const u4 *>(tbhl + ((size_t)(part * 2 + hl) * NZ + n) * Np + x0 + q * 8);
-            }
-        }
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int e = threadIdx.x + 256 * v;
-            const int yy = e >> 5, xx = e & 31;
-            const int gy = y0 + yy, gx = x0 + xx;
-            Gs[yy][xx] = (gy < N && gx < N) ? Gsrc[(size_t)gy * N + gx] : 0.f;
-        }
-        __syncthreads();
-        if (!jok) continue;
-        // (a) fields of this chunk, E^T blocks (xb = 16-column block, yb = 16-row block)
-        f4 er[2][2], ei[2][2];
+        f4 gv[2][2];
 #pragma unroll
         for (int xb = 0; xb < 2; ++xb)
 #pragma unroll
             for (int yb = 0; yb < 2; ++yb) {
-                er[xb][yb] = f4{0.f, 0.f, 0.f, 0.f};
-                ei[xb][yb] = f4{0.f, 0.f, 0.f, 0.f};
-            }
-#pragma unroll
-        for (int st = 0; st < NS; ++st) {
-            int p, r0;
-            kgroup<KP>(4 * st + lq, p, r0);
-            // zero padding of the inner dimension (p >= 3) goes in as zero
-            // operands: the matrix instructions must run with every lane active
-            const bool pad = p >= 3;
-            const int offA = pad ? 0 : (p == 2 ? KP : 0) + r0;
-            const int offB = pad ? 0 : (p == 1 ? KP : 0) + r0;
-            bf8 bb1[2], bb2[2];
-#pragma unroll
-            for (int yb = 0; yb < 2; ++yb) {
-                bb1[yb] = pad ? bf8_zero() : *reinterpret_cast<const bf8 *>(&Ls[0][16 * yb + l16][offB]);
-                bb2[yb] = pad ? bf8_zero() : *reinterpret_cast<const bf8 *>(&Ls[1][16 * yb + l16][offB]);
-            }
-#pragma unroll
-            for (int xb = 0; xb < 2; ++xb) {
-                const bf8 a = pad ? bf8_zero()
-                                  : *reinterpret_cast<const bf8 *>(Yj + (size_t)(x0 + 16 * xb + l16) * 2 * KP + offA);
-#pragma unroll
-                for (int yb = 0; yb < 2; ++yb) {
-                    er[xb][yb] = mfma_b(a, bb1[yb], er[xb][yb]);
-                    ei[xb][yb] = mfma_b(a, bb2[yb], ei[xb][yb]);
+                const int yy = 32 * wave + 16 * yb + l16, xx = 16 * xb + 4 * lq;
+                if constexpr (A4) {
+                    const f4 v = *reinterpret_cast<const f4 *>(&Gs[yy * (4 * GRU) + xx]);
+                    gv[xb][yb] = (yt0 + yy < N && x0 + xx < N) ? v : f4{0.f, 0.f, 0.f, 0.f};
+                } else {
+                    gv[xb][yb] = load_g4_any(Gsrc, N, yt0 + yy, x0 + xx);
                 }
             }
-        }
-        // (b) X = G . E; register i of (xb, yb) is column 16 xb + 4 lq + i, row 16 yb + l16
-#pragma unroll
-        for (int xb = 0; xb < 2; ++xb)
-#pragma unroll
-            for (int yb = 0; yb < 2; ++yb) {
-                const f4 g4 = *reinterpret_cast<const f4 *>(&Gs[16 * yb + l16][16 * xb + 4 * lq]);
-                er[xb][yb] *= g4;
-                ei[xb][yb] *= g4;
+        if (c + 1 < c_hi) {
+            if (A4) {
+                __syncthreads();   // every wave holds its G values before the tile is refilled
+                copy_g(c + 1);
             }
-        // (c) Z[y][n] += sum_x X[y][x] B3[x][n]: one k-group per part = the
-        // lane's 8 columns {4lq+i} of block 0 then block 1
+            copy_yb(c + 1, bb ^ 1);
+        }
+        const u4 *Yb = Yc[bb];
+        const u4 *Bb = Bc[bb];
 #pragma unroll
         for (int part = 0; part < 2; ++part) {
+            // (a) E^T for this part; register i of e[xb][yb] is column
+            // 16 xb + 4 lq + i, row 16 yb + l16 of the wave's 32 x 32 block
+            f4 e[2][2];
+#pragma unroll
+            for (int xb = 0; xb < 2; ++xb)
+#pragma unroll
+                for (int yb = 0; yb < 2; ++yb) e[xb][yb] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int st = 0; st < NS; ++st) {
+                int p, r0;
+                kmap<KP>::group(st, lq, p, r0);
+                const int sl = kmap<KP>::slot(st);
+                // zero padding of the inner dimension (p = 3) goes in as zero
+                // operands: the matrix instructions must run with every lane active
+                const bool pad = p >= 3;
+                const int ua = pad ? 0 : ((p == 2 ? KP : 0) + r0) / 8;
+#pragma unroll
+                for (int xb = 0; xb < 2; ++xb) {
+                    const bf8 a = pad ? bf8_zero() : __builtin_bit_cast(bf8, Yb[(16 * xb + l16) * RWU + ua]);
+#pragma unroll
+                    for (int yb = 0; yb < 2; ++yb)
+                        e[xb][yb] = mfma_b(a, part ? b2[yb][sl] : b1[yb][sl], e[xb][yb]);
+                }
+            }
+            // (b) X = G . E, split
             bf8 xh[2], xl[2];
 #pragma unroll
             for (int yb = 0; yb < 2; ++yb)
 #pragma unroll
-                for (int e = 0; e < 8; ++e) {
-                    const float v = part ? ei[e >> 2][yb][e & 3] : er[e >> 2][yb][e & 3];
+                for (int i = 0; i < 4; ++i) {
                     __bf16 h, l;
-                    split(v, h, l);
-                    xh[yb][e] = h;
-                    xl[yb][e] = l;
+                    split(e[0][yb][i] * gv[0][yb][i], h, l);
+                    xh[yb][i] = h;
+                    xl[yb][i] = l;
+                    split(e[1][yb][i] * gv[1][yb][i], h, l);
+                    xh[yb][4 + i] = h;
+                    xl[yb][4 + i] = l;
                 }
+            // (c) Z[y][n] += sum_x X[y][x] B3[x][n]
 #pragma unroll
             for (int nb = 0; nb < NB; ++nb) {
-                const int n = 16 * nb + l16;
-                bf8 bh, bl;
-                {
-                    const uint2 h0 = *reinterpret_cast<const uint2 *>(&Bt[part][0][n][4 * lq]);
-                    const uint2 h1 = *reinterpret_cast<const uint2 *>(&Bt[part][0][n][16 + 4 * lq]);
-                    const uint2 l0 = *reinterpret_cast<const uint2 *>(&Bt[part][1][n][4 * lq]);
-                    const uint2 l1 = *reinterpret_cast<const uint2 *>(&Bt[part][1][n][16 + 4 * lq]);
-                    u4 th = {h0.x, h0.y, h1.x, h1.y}, tl = {l0.x, l0.y, l1.x, l1.y};
-                    bh = __builtin_bit_cast(bf8, th);
-                    bl = __builtin_bit_cast(bf8, tl);
-                }
+                const bf8 bh = __builtin_bit_cast(bf8, Bb[((part * NB + nb) * 2 + 0) * 64 + lane]);
+                const bf8 bl = __builtin_bit_cast(bf8, Bb[((part * NB + nb) * 2 + 1) * 64 + lane]);
 #pragma unroll
                 for (int yb = 0; yb < 2; ++yb) {
                     accZ[yb][nb] = mfma_b(xh[yb], bh, accZ[yb][nb]);
@@ -377,9 +476,14 @@ __global__ __launch_bounds__(256, 2) void k_adjoint_b3(const __bf16 *__restrict_
                 }
             }
         }
+        // the next chunk's copies have landed (this wave's), and every wave is
+        // done with buffer bb before it is refilled
+        wait_copies();
+        __syncthreads();
     }
-    float *dst = Wpart + ((size_t)(srel * gridDim.x + ytile) * gridDim.y + kg) * P * P * 2;
-    ilt_dev::adjoint_tail<FB, MIX>(accZ, jok, j, s, K, P, Np, AP, y0, ta4, coef, Ws, dst);
+    float *dst = Wpart + ((size_t)(srel * gridDim.x + blockIdx.x) * gridDim.y + j) * P * P * 2;
+    ilt_dev::adjoint_tail<FB, MIX>(accZ, true, j, s, K, P, Np, AP, y0, ta4, coef,
+                                   reinterpret_cast<float2 *>(GWs), dst);
 }
 
 }  // namespace
@@ -403,12 +507,28 @@ hipError_t launch_image_b3(ilt_ctx *c, int set_lo, int set_hi, float *out) {
     return hipGetLastError();
 }
 
+// Column chunks are split over two blocks once there are enough of them, so
+// that a 2048-pixel clip gives three full rounds of blocks on 256 CUs.
+static int adjoint_b3_xsplit(const ilt_ctx *c) { return (c->N + 31) / 32 >= 8 ? 2 : 1; }
+
+int adjoint_b3_parts(const ilt_ctx *c, int nsets) {
+    return nsets * ((c->N + 127) / 128) * adjoint_b3_xsplit(c) * c->K;
+}
+
 hipError_t launch_adjoint_b3(ilt_ctx *c, const float *G, size_t g_set_stride, int set_lo, int set_hi) {
-    dim3 grid((c->N + 31) / 32, (c->K + 3) / 4, set_hi - set_lo);
-#define ADJB(KP_, FB_, MIX_)                                                                                  \
-    k_adjoint_b3<KP_, FB_, MIX_><<<grid, 256, 0, c->stream>>>(c->tlhl, c->tbhl, c->ta4, c->Yhl, G, g_set_stride, \
-                                                              c->coef, c->K, c->P, c->N, c->Np, c->AP, set_lo,  \
-                                                              c->Wpart)
+    const int xsplit = adjoint_b3_xsplit(c);
+    dim3 grid((c->N + 127) / 128 * xsplit, c->K, set_hi - set_lo);
+#define ADJB(KP_, FB_, MIX_)                                                                                   \
+    do {                                                                                                       \
+        if ((c->N & 3) == 0)                                                                                   \
+            k_adjoint_b3<KP_, FB_, MIX_, true><<<grid, 256, 0, c->stream>>>(                                   \
+                c->tlhl, c->tbhl, c->ta4, c->Yhl, G, g_set_stride, c->coef, c->K, c->P, c->N, c->Np, c->AP,     \
+                set_lo, xsplit, c->Wpart);                                                                     \
+        else                                                                                                   \
+            k_adjoint_b3<KP_, FB_, MIX_, false><<<grid, 256, 0, c->stream>>>(                                  \
+                c->tlhl, c->tbhl, c->ta4, c->Yhl, G, g_set_stride, c->coef, c->K, c->P, c->N, c->Np, c->AP,     \
+                set_lo, xsplit, c->Wpart);                                                                     \
+    } while (0)
     const int KPv = c->KP, FBv = c->FB, MIXv = c->MIX;
     if (KPv == 8 && FBv == 0 && MIXv == 1) ADJB(8, 0, 1);
     else if (KPv == 24 && FBv == 0 && MIXv == 1) ADJB(24, 0, 1);

@@ -596,7 +596,8 @@ hipError_t launch_adjoint(ilt_ctx *c, const float *G, size_t g_set_stride, int s
 }
 
 hipError_t launch_window_sum(ilt_ctx *c, int set_lo, int set_hi) {
-    const int nparts = (set_hi - set_lo) * ((c->N + 31) / 32) * ((c->K + 3) / 4);
+    const int nparts = c->precision == ILT_BF16X3 ? adjoint_b3_parts(c, set_hi - set_lo)
+                                                  : (set_hi - set_lo) * ((c->N + 31) / 32) * ((c->K + 3) / 4);
     const int n = c->P * c->P;
     k_psum<float2><<<(n + 63) / 64, 1024, 0, c->stream>>>(reinterpret_cast<const float2 *>(c->Wpart), nparts, n,
                                                          c->W);

@@ -55,6 +55,13 @@ class _Report(ctypes.Structure):
                 ("l2", ctypes.c_longlong), ("pvb", ctypes.c_longlong), ("flips", ctypes.c_longlong)]
 
 
+class _Clip(ctypes.Structure):
+    _fields_ = [("N", ctypes.c_int), ("d_target", ctypes.c_void_p), ("d_phi", ctypes.c_void_p),
+                ("d_trace", ctypes.c_void_p), ("params", _Params)]
+
+
+ILT_BATCH_MAX_SIZES, ILT_BATCH_MAX_LANES, ILT_BATCH_MAX_CLIPS = 8, 4, 1024
+
 _lib = None
 _VP = ctypes.c_void_p
 
@@ -80,6 +87,11 @@ def load_library(path: str = LIB_PATH):
         "ilt_profile": [_VP, ctypes.c_int],
         "ilt_set_graph": [_VP, ctypes.c_int],
         "ilt_profile_read": [_VP, ctypes.POINTER(ctypes.c_double), ctypes.c_int],
+        "ilt_batch_create": [ctypes.POINTER(_VP), ctypes.POINTER(_Optics), ctypes.POINTER(ctypes.c_int),
+                             ctypes.c_int, ctypes.c_int, ctypes.c_int, _VP],
+        "ilt_batch_destroy": [_VP],
+        "ilt_batch_set_graph": [_VP, ctypes.c_int],
+        "ilt_solve_batch": [_VP, ctypes.c_int, ctypes.POINTER(_Clip), ctypes.POINTER(_Report)],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -150,6 +162,23 @@ def _ptr(t, dtype, shape, name, device):
     return ctypes.c_void_p(t.data_ptr())
 
 
+def _optics(kernels, weights, N, precision, flags):
+    """Pack ilt_optics; returns (struct, arrays that must outlive the call)."""
+    kernels = np.asarray(kernels)
+    weights = np.asarray(weights, dtype=np.float64)
+    if kernels.ndim == 3:
+        kernels = kernels[None]
+        weights = weights[None]
+    ns, K, P, P2 = kernels.shape
+    if P != P2 or weights.shape != (ns, K):
+        raise ValueError("kernels must be [n_sets, K, P, P] and weights [n_sets, K]")
+    kr = np.ascontiguousarray(np.stack([kernels.real, kernels.imag], axis=-1), dtype=np.float64)
+    wr = np.ascontiguousarray(weights)
+    o = _Optics(N=int(N), P=int(P), K=int(K), n_sets=int(ns), precision=int(precision), flags=int(flags),
+                h_kernels=kr.ctypes.data, h_weights=wr.ctypes.data)
+    return o, (kr, wr), (int(P), int(K), int(ns))
+
+
 class Context:
     """A library context on the current torch CUDA (HIP) device and stream."""
 
@@ -157,18 +186,7 @@ class Context:
                  flags: int = 0):
         import torch
         lib = load_library()
-        kernels = np.asarray(kernels)
-        weights = np.asarray(weights, dtype=np.float64)
-        if kernels.ndim == 3:
-            kernels = kernels[None]
-            weights = weights[None]
-        ns, K, P, P2 = kernels.shape
-        if P != P2 or weights.shape != (ns, K):
-            raise ValueError("kernels must be [n_sets, K, P, P] and weights [n_sets, K]")
-        kr = np.ascontiguousarray(np.stack([kernels.real, kernels.imag], axis=-1), dtype=np.float64)
-        wr = np.ascontiguousarray(weights)
-        o = _Optics(N=int(N), P=int(P), K=int(K), n_sets=int(ns), precision=int(precision), flags=int(flags),
-                    h_kernels=kr.ctypes.data, h_weights=wr.ctypes.data)
+        o, _keep, (P, K, ns) = _optics(kernels, weights, N, precision, flags)
         self.device = torch.device("cuda", torch.cuda.current_device())
         self.stream = torch.cuda.current_stream(self.device)
         h = _VP()
@@ -271,6 +289,63 @@ class Context:
 
 
 # module-level names matching the C ABI
+class Batch:
+    """Batched form: ilt_solve over a list of clips of the listed sizes.
+
+    Clip i is (target uint8 [N,N], phi float32 [N,N], Params, trace or None);
+    phi is in/out as for ilt_solve.  Results equal per-clip ilt_solve calls.
+    """
+
+    def __init__(self, kernels, weights, sizes, max_clips: int = 64, n_lanes: int = 4,
+                 precision: int = ILT_FP32, flags: int = 0):
+        import torch
+        lib = load_library()
+        sizes = [int(n) for n in sizes]
+        o, _keep, (P, K, ns) = _optics(kernels, weights, sizes[0], precision, flags)
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        self.stream = torch.cuda.current_stream(self.device)
+        arr = (ctypes.c_int * len(sizes))(*sizes)
+        h = _VP()
+        _check(lib.ilt_batch_create(ctypes.byref(h), ctypes.byref(o), arr, len(sizes), int(max_clips),
+                                    int(n_lanes), _VP(self.stream.cuda_stream)))
+        self._h = h
+        self.sizes, self.max_clips, self.n_lanes = sizes, int(max_clips), int(n_lanes)
+        self.P, self.K, self.n_sets = P, K, ns
+        self._clips = None
+        self._clip_key = None
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load_library().ilt_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_graph(self, enable: bool = True):
+        _check(load_library().ilt_batch_set_graph(self._h, 1 if enable else 0))
+
+    def solve(self, clips):
+        import torch
+        n = len(clips)
+        arr = (_Clip * n)()
+        for i, (target, phi, params, trace) in enumerate(clips):
+            N = int(target.shape[0])
+            arr[i].N = N
+            arr[i].d_target = _ptr(target, torch.uint8, (N, N), "target[%d]" % i, self.device)
+            arr[i].d_phi = _ptr(phi, torch.float32, (N, N), "phi[%d]" % i, self.device)
+            arr[i].d_trace = None if trace is None else _ptr(trace, torch.float64, (params.iters, TRACE_W),
+                                                             "trace[%d]" % i, self.device)
+            arr[i].params = params.to_c()
+        reps = (_Report * n)()
+        _check(load_library().ilt_solve_batch(self._h, n, arr, reps))
+        return [dict(iters_done=r.iters_done, status=r.status, loss=r.loss, l2=r.l2, pvb=r.pvb, flips=r.flips)
+                for r in reps]
+
+
 def litho_forward(ctx: Context, mask, set_=0, out=None):
     return ctx.litho_forward(mask, set_, out)
 

@@ -27,7 +27,7 @@ import hashlib
 import numpy as np
 
 __all__ = [
-    "ClipSpec", "C0_CLIP", "C1_CLIP", "gen_clip", "clip_density",
+    "ClipSpec", "C0_CLIP", "C1_CLIP", "gen_clip", "clip_density", "batch_inputs",
     "OpticsSpec", "build_kernels", "build_optics", "optics_checksum",
     "random_phi", "random_mask",
 ]
@@ -124,10 +124,16 @@ def gen_clip(spec: ClipSpec, seed: int) -> np.ndarray:
         n_target = 10 ** 9
         dens_target = float(rng.uniform(*spec.density))
     placed = 0
+    metal = 0
     attempts = 0
     max_attempts = 200 * max(1, min(n_target, 400))
+    misses = 0
     while placed < n_target and attempts < max_attempts:
         attempts += 1
+        # density mode: the frame counts as full after 1000 rejections in a row
+        if dens_target is not None and misses >= 1000:
+            break
+        misses += 1
         boxes = _draw_polygon(rng, spec)
         h = max(b[2] for b in boxes)
         w = max(b[3] for b in boxes)
@@ -143,11 +149,13 @@ def gen_clip(spec: ClipSpec, seed: int) -> np.ndarray:
         if not ok:
             continue
         for (a0, b0, a1, b1) in boxes:
+            metal += int((Z[oy + a0:oy + a1, ox + b0:ox + b1] == 0).sum())
             Z[oy + a0:oy + a1, ox + b0:ox + b1] = 1
             keep[max(0, oy + a0 - space):oy + a1 + space,
                  max(0, ox + b0 - space):ox + b1 + space] = True
         placed += 1
-        if dens_target is not None and Z.mean() >= dens_target:
+        misses = 0
+        if dens_target is not None and metal >= dens_target * N * N:
             break
     return Z
 
@@ -292,6 +300,30 @@ WORKLOADS = {
     "c1": dict(clip=C1_CLIP, optics=dict(N=2048, pitch_nm=1.0, P=35, K=24, defocus_sets=(0.0, 25.0)),
                params=_params(1.0, THREE_CORNERS, 50)),
 }
+
+
+# Batched workload: clips of one 2048 nm field at 512, 1024 or 2048 pixels
+# (pitch 4, 2 or 1 nm), so one 35 x 35, K = 24 kernel set pair serves all;
+# polygons are added until the metal density reaches U[5 %, 25 %].
+BATCH_SIZES = (512, 1024, 2048)
+BATCH_FIELD_NM = 2048.0
+
+
+def batch_inputs(n_clips: int = 64, seed: int = 1234, sizes=BATCH_SIZES):
+    """[(target uint8 [N,N], params dict)] for n_clips clips with N drawn
+    uniformly from `sizes`, plus (kernels, weights) shared by all."""
+    rng = np.random.default_rng(seed)
+    Ns = rng.choice(np.asarray(sizes), size=n_clips)
+    clips = []
+    for i, N in enumerate(Ns):
+        N = int(N)
+        pitch = BATCH_FIELD_NM / N
+        spec = ClipSpec(N=N, pitch_nm=pitch, n_min=1, n_max=1, width_nm=(40.0, 80.0),
+                        length_nm=(80.0, 400.0), spacing_nm=60.0, margin_nm=256.0, manhattan=True,
+                        density=(0.05, 0.25))
+        clips.append((gen_clip(spec, seed * 1000 + i), _params(pitch, THREE_CORNERS, 50)))
+    k, w = build_optics(N=2048, pitch_nm=1.0, P=35, K=24, defocus_sets=(0.0, 25.0))
+    return clips, k, w
 
 
 def workload_inputs(name: str, seed: int = 0):

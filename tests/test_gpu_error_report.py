@@ -1,0 +1,107 @@
+"""Per-step precision report of the split-BF16 (BF16x3) form.
+
+At sampled steps i of the plain FP32 trajectory of the 2048^2 clip (K = 24,
+two kernel sets, three corners) the mask M_i = [phi_i <= 0] is fed to both
+device forms and to the FP64 oracle (teacher forcing), and each computes the
+aerial images I_s and the whole-objective gradient g = sum_s dL/dM through
+its own chain (image -> resist -> G_s -> adjoint).  Errors are normwise:
+max|x - x_ref| / max|x_ref| per quantity, against (a) the plain FP32 form and
+(b) the oracle.  One JSON line per step is written to
+$ILT_REPORT_DIR/precision_report.jsonl when that directory exists.
+
+Bars (BF16x3 vs the oracle): I <= 1e-3, g <= 2e-2; FP32: I <= 1e-5, g <= 1e-3.
+"""
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import litho as o_litho  # noqa: E402
+from oracle import resist as o_resist  # noqa: E402
+from oracle import solve as o_solve  # noqa: E402
+from paper_2303_12529_amd.inputs import workload_inputs  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+STEPS = (0, 10, 25, 50)
+
+
+def _say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def ilt():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2303_12529_amd import ilt as mod
+    mod.load_library()
+    return mod
+
+
+def _rel(x, ref):
+    return float(np.abs(x - ref).max() / max(np.abs(ref).max(), 1e-300))
+
+
+def _device_chain(ctx, M, target, params, n_sets):
+    """I_s and g = sum_s adjoint(M, G_s, s) with the device form of ctx."""
+    N = M.shape[0]
+    m = torch.as_tensor(M).cuda()
+    I = torch.empty((n_sets, N, N), dtype=torch.float32, device="cuda")
+    for s in range(n_sets):
+        ctx.litho_forward(m, s, out=I[s])
+    G, _ = ctx.resist_loss(I, target, params)
+    g = torch.zeros((N, N), dtype=torch.float32, device="cuda")
+    for s in range(n_sets):
+        g += ctx.litho_adjoint(m, G[s].contiguous(), s)
+    return I.cpu().numpy().astype(np.float64), g.cpu().numpy().astype(np.float64)
+
+
+def test_precision_report_along_trajectory(ilt):
+    Z, H, w, prm = workload_inputs("c1", 0)
+    N = Z.shape[0]
+    n_sets = H.shape[0]
+    corners = prm["corners"]
+    target = torch.as_tensor(Z).cuda()
+    plain = ilt.Context(H, w, N, precision=ilt.ILT_FP32)
+    b3 = ilt.Context(H, w, N, precision=ilt.ILT_BF16X3)
+    params = ilt.Params.from_dict(prm)
+    out_dir = os.environ.get("ILT_REPORT_DIR", "gpurun_out")
+    rows = []
+    for i in STEPS:
+        phi = torch.empty((N, N), dtype=torch.float32, device="cuda")
+        if i == 0:
+            plain.edt_reinit(params, mask=target, phi_out=phi)
+        else:
+            plain.ilt_solve(target, phi, ilt.Params.from_dict(prm, iters=i, init_mode=0))
+        M = (phi <= 0).to(torch.float32).cpu().numpy()
+        I32, g32 = _device_chain(plain, M, target, params, n_sets)
+        Ib3, gb3 = _device_chain(b3, M, target, params, n_sets)
+        M64 = M.astype(np.float64)
+        Iref = o_solve.forward_all(M64, H, w, corners)
+        _, Gref = o_resist.dso_loss_and_grad(Iref, Z, corners, prm["sigma_z"], prm["i_th"])
+        gref = np.zeros((N, N))
+        for s in o_solve.sets_used(corners):
+            gref += o_litho.litho_adjoint(M64, Gref[s], H[s], w[s])
+        used = o_solve.sets_used(corners)
+        row = {
+            "step": i,
+            "I_bf16x3_vs_oracle": max(_rel(Ib3[s], Iref[s]) for s in used),
+            "I_fp32_vs_oracle": max(_rel(I32[s], Iref[s]) for s in used),
+            "I_bf16x3_vs_fp32": max(_rel(Ib3[s], I32[s]) for s in used),
+            "g_bf16x3_vs_oracle": _rel(gb3, gref),
+            "g_fp32_vs_oracle": _rel(g32, gref),
+            "g_bf16x3_vs_fp32": _rel(gb3, g32),
+        }
+        _say(json.dumps(row))
+        rows.append(row)
+        assert row["I_bf16x3_vs_oracle"] <= 1e-3 and row["g_bf16x3_vs_oracle"] <= 2e-2
+        assert row["I_fp32_vs_oracle"] <= 1e-5 and row["g_fp32_vs_oracle"] <= 1e-3
+    if os.path.isdir(out_dir):
+        with open(os.path.join(out_dir, "precision_report.jsonl"), "w") as f:
+            for r in rows:
+                f.write(json.dumps(r) + "\n")

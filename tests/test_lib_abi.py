@@ -45,6 +45,8 @@ int main(void) {
   printf("%zu %zu %zu %zu\n", sizeof(ilt_optics), sizeof(ilt_corner), sizeof(ilt_params), sizeof(ilt_report));
   printf("%zu %zu %zu\n", offsetof(ilt_params, eta), offsetof(ilt_params, n_corners), offsetof(ilt_params, corners));
   printf("%zu %zu\n", offsetof(ilt_optics, h_kernels), offsetof(ilt_report, loss));
+  printf("%zu %zu %zu %d %d %d\n", sizeof(ilt_clip), offsetof(ilt_clip, d_trace), offsetof(ilt_clip, params),
+         ILT_BATCH_MAX_SIZES, ILT_BATCH_MAX_LANES, ILT_BATCH_MAX_CLIPS);
   return 0;
 }
 '''
@@ -64,6 +66,10 @@ int main(void) {
     assert vals[6] == ilt._Params.corners.offset
     assert vals[7] == ilt._Optics.h_kernels.offset
     assert vals[8] == ilt._Report.loss.offset
+    assert vals[9] == ctypes.sizeof(ilt._Clip)
+    assert vals[10] == ilt._Clip.d_trace.offset
+    assert vals[11] == ilt._Clip.params.offset
+    assert tuple(vals[12:15]) == (ilt.ILT_BATCH_MAX_SIZES, ilt.ILT_BATCH_MAX_LANES, ilt.ILT_BATCH_MAX_CLIPS)
 
 
 def test_params_roundtrip_and_validation():
