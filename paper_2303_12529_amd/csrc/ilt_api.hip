@@ -311,7 +311,8 @@ extern "C" int ilt_create(ilt_ctx **out, const ilt_optics *o, int max_batch, voi
     ALLOC(G, (size_t)ns * N * N);
     ALLOC(g, (size_t)N * N);
     ALLOC(phi2, (size_t)N * N);
-    c->n_wpart = ns * std::max(((N + 31) / 32) * ((K + 3) / 4), ((N + 127) / 128) * K) * P * P * 2;
+    // W partials: one per block of the FP32 adjoint grid, or of the split-BF16 one
+    c->n_wpart = std::max(ns * ((N + 31) / 32) * ((K + 3) / 4), adjoint_b3_parts(c, ns)) * P * P * 2;
     ALLOC(Wpart, (size_t)c->n_wpart);
     ALLOC(edtg, (size_t)N * N);
     ALLOC(colbits, (size_t)((N + 31) / 32) * N);

@@ -517,6 +517,7 @@ int adjoint_b3_parts(const ilt_ctx *c, int nsets) {
 
 hipError_t launch_adjoint_b3(ilt_ctx *c, const float *G, size_t g_set_stride, int set_lo, int set_hi) {
     const int xsplit = adjoint_b3_xsplit(c);
+    if ((size_t)adjoint_b3_parts(c, set_hi - set_lo) * c->P * c->P * 2 > (size_t)c->n_wpart) return hipErrorInvalidValue;
     dim3 grid((c->N + 127) / 128 * xsplit, c->K, set_hi - set_lo);
 #define ADJB(KP_, FB_, MIX_)                                                                                   \
     do {                                                                                                       \
