@@ -42,6 +42,64 @@ def algorithmic_work(N, P, K, n_sets):
     }
 
 
+# Dominant-kernel names and the sources they are built from, per (phase, dtype);
+# the HBM traffic measured with hardware counters is used only while those
+# sources are unchanged since the measurement.
+KERNELS = {
+    ("adjoint", "f32"): ("k_adjoint_st", ("k_litho.hip", "ilt_device.h", "ilt_internal.h")),
+    ("adjoint", "bf16x3"): ("k_adjoint_b3", ("k_bf16.hip", "ilt_device.h", "ilt_internal.h")),
+    ("image", "f32"): ("k_image", ("k_litho.hip", "ilt_internal.h")),
+    ("image", "bf16x3"): ("k_image_b3", ("k_bf16.hip", "ilt_internal.h")),
+}
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def sources_digest(files):
+    import hashlib
+    h = hashlib.sha256()
+    for f in files:
+        with open(os.path.join(HERE, "paper_2303_12529_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel, dtype, files):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    profiles/<kernel>_<dtype>_traffic.md, or None if absent or stale."""
+    path = os.path.join(HERE, "profiles", "%s_%s_traffic.md" % (kernel, dtype))
+    if not os.path.exists(path):
+        return None, None
+    vals = {}
+    for line in open(path):
+        if ":" in line and line.startswith("- "):
+            k, v = line[2:].split(":", 1)
+            vals[k.strip()] = v.strip().strip("`")
+    if vals.get("sources sha256/16") != sources_digest(files):
+        return None, "stale"
+    try:
+        return float(vals["hbm bytes per launch"]), os.path.relpath(path, HERE)
+    except (KeyError, ValueError):
+        return None, None
+
+
+def issued_bf16_flops(N, P, K, n_sets, phase):
+    """Matrix-core flops the split-BF16 kernels issue per launch (padding and
+    the three hi/lo products included)."""
+    kp = 8 if 2 * P <= 8 else 24 if 2 * P <= 24 else 40 if 2 * P <= 40 else 72
+    kc = (3 * kp + 31) // 32 * 32
+    fb, mix = P // 16, int(P % 16 != 0 and P % 16 <= 8)
+    if P % 16 > 8:
+        fb += 1
+    nz = 32 * fb + 16 * mix
+    npad = (N + 127) // 128 * 128
+    pix = float(npad) * ((N + 31) // 32 * 32)
+    if phase == "adjoint":
+        return n_sets * K * pix * (2 * kc * 2 + 2 * nz * 3 * 2)
+    if phase == "image":
+        return n_sets * K * float(npad) * npad * 2 * kc * 2
+    return None
+
+
 def cpu_baseline(workload, seed, iters):
     """Time the FP64 oracle on `iters` iterations of the same workload."""
     import numpy as np
@@ -160,6 +218,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--precision", choices=("fp32", "bf16x3"), default="fp32",
                     help="arithmetic of the dense contractions (default: the plain FP32 loop)")
+    ap.add_argument("--traffic-probe", action="store_true",
+                    help="first copy 256 MiB device to device (the reference kernel for scaling HBM counters)")
     ap.add_argument("--batch-clips", type=int, default=64,
                     help="clips in the batched-form measurement (0: skip)")
     ap.add_argument("--batch-lanes", type=int, default=4)
@@ -180,6 +240,12 @@ def main():
     N = Z.shape[0]
     n_sets, K, P, _ = H.shape
     torch.cuda.set_device(0)
+    if args.traffic_probe:
+        a = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     prec = ilt.ILT_BF16X3 if args.precision == "bf16x3" else ilt.ILT_FP32
     ctx = ilt.Context(H, w, N, precision=prec)
     target = torch.as_tensor(Z).to("cuda")
@@ -233,8 +299,18 @@ def main():
         achieved = wd["bytes"] / (avg_ms * 1e-3) / 1e9
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None}
-    roof["kernel"] = dominant
+    dtype = "f32" if args.precision == "fp32" else "bf16x3"
+    kname, ksrc = KERNELS.get((dominant, dtype), (dominant, ()))
+    roof["kernel"] = kname
+    roof["phase"] = dominant
     roof["avg_launch_ms"] = round(avg_ms, 4)
+    if ksrc:
+        roof["traffic"], roof["traffic_source"] = measured_traffic(kname, dtype, ksrc)
+    if args.precision == "bf16x3":
+        iss = issued_bf16_flops(N, P, K, n_sets, dominant)
+        if iss:
+            roof["issued_bf16_tflops"] = round(iss / (avg_ms * 1e-3) / 1e12, 1)
+            roof["issued_bf16_frac"] = round(iss / (avg_ms * 1e-3) / 1e12 / BF16_MFMA_PEAK_TFLOPS, 4)
     total_flops = sum(v.get("flops", 0.0) for v in work.values())
     tr = trace.cpu().numpy()
 
