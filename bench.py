@@ -218,6 +218,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--precision", choices=("fp32", "bf16x3"), default="fp32",
                     help="arithmetic of the dense contractions (default: the plain FP32 loop)")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default launch settings instead of timing the tuning candidates first")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="first copy 256 MiB device to device (the reference kernel for scaling HBM counters)")
     ap.add_argument("--batch-clips", type=int, default=64,
@@ -248,6 +250,7 @@ def main():
         del a, b
     prec = ilt.ILT_BF16X3 if args.precision == "bf16x3" else ilt.ILT_FP32
     ctx = ilt.Context(H, w, N, precision=prec)
+    tuning = None if args.no_autotune else ctx.autotune()
     target = torch.as_tensor(Z).to("cuda")
     phi = torch.empty((N, N), dtype=torch.float32, device="cuda")
 
@@ -318,6 +321,10 @@ def main():
     if args.ttt_seeds > 0:
         ctxs = {"fp32": ctx if prec == ilt.ILT_FP32 else ilt.Context(H, w, N, precision=ilt.ILT_FP32),
                 "bf16x3": ctx if prec == ilt.ILT_BF16X3 else ilt.Context(H, w, N, precision=ilt.ILT_BF16X3)}
+        if not args.no_autotune:
+            for c in ctxs.values():
+                if c is not ctx:
+                    c.autotune()
         ttt = time_to_target(ctxs, args.workload, range(args.ttt_seeds))
 
     bat = None
@@ -358,6 +365,7 @@ def main():
                          % (args.steps, 1e3 * wall_direct / args.steps),
         "final": {"l2": rep["l2"], "pvb": rep["pvb"], "loss": rep["loss"],
                   "l2_first": int(tr[0, 2]), "l2_last_iter": int(tr[-1, 2])},
+        "tuning": tuning if tuning is not None else ctx.get_tuning(),
         "time_to_target": ttt,
         "batched": bat,
     }

@@ -191,6 +191,35 @@ int ilt_profile(ilt_ctx *ctx, int enable);
 int ilt_profile_read(ilt_ctx *ctx, double *h_out, int n);
 
 /* ------------------------------------------------------------------------
+ * Tuning (not in the paper: launch-level choices of this implementation).
+ * None changes what is computed beyond the order of rounding.
+ *   store_fields  FP32: the forward pass stores the coherent fields and the
+ *                 adjoint streams them (1), or the adjoint recomputes them
+ *                 (0).  1 needs a context created without
+ *                 ILT_FLAG_RECOMPUTE_FIELDS.
+ *   b3_xsplit     BF16x3 adjoint: column chunks split over this many blocks
+ *                 per row tile, 1..4 (0 = chosen by size).
+ *   xcd_remap     BF16x3 image: XCD-aware tile order (1) or plain (0).
+ * ilt_set_tuning drops a captured solve graph (it is re-captured).
+ * ilt_autotune: with cache_path non-NULL and a line for this device
+ * architecture and problem (N, P, K, n_sets, precision, field buffer) in that
+ * text file (one JSON object per line, written by this function), applies
+ * it and returns 1.  Otherwise times every candidate with HIP events on a
+ * synthetic clip (3-iteration solves on the context's stream; allocates and
+ * frees two N x N scratch buffers), applies the fastest, appends it to
+ * cache_path (if given) and returns 0.  h_best, h_ms_per_iter: NULL or out.
+ * Synchronous. */
+typedef struct {
+    int store_fields;
+    int b3_xsplit;
+    int xcd_remap;
+} ilt_tuning;
+
+int ilt_get_tuning(const ilt_ctx *ctx, ilt_tuning *h_tuning);
+int ilt_set_tuning(ilt_ctx *ctx, const ilt_tuning *h_tuning);
+int ilt_autotune(ilt_ctx *ctx, const char *cache_path, ilt_tuning *h_best, double *h_ms_per_iter);
+
+/* ------------------------------------------------------------------------
  * Batched form (many clips per call).  The paper solves one clip at a time
  * (Sec. IV reports per-clip turnaround); this form runs the same DSO loop of
  * ilt_solve on a list of clips, possibly of different sizes, in one call.

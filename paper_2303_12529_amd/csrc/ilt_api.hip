@@ -312,7 +312,7 @@ extern "C" int ilt_create(ilt_ctx **out, const ilt_optics *o, int max_batch, voi
     ALLOC(g, (size_t)N * N);
     ALLOC(phi2, (size_t)N * N);
     // W partials: one per block of the FP32 adjoint grid, or of the split-BF16 one
-    c->n_wpart = std::max(ns * ((N + 31) / 32) * ((K + 3) / 4), adjoint_b3_parts(c, ns)) * P * P * 2;
+    c->n_wpart = std::max(ns * ((N + 31) / 32) * ((K + 3) / 4), adjoint_b3_max_parts(c, ns)) * P * P * 2;
     ALLOC(Wpart, (size_t)c->n_wpart);
     ALLOC(edtg, (size_t)N * N);
     ALLOC(colbits, (size_t)((N + 31) / 32) * N);
@@ -375,6 +375,9 @@ extern "C" int ilt_create(ilt_ctx **out, const ilt_optics *o, int max_batch, voi
         return fail(ILT_EDEVICE, "context set-up failed: %s", hipGetErrorString(e));
     }
     c->use_graph = 1;
+    c->store_fields = c->Est != nullptr;
+    c->b3_xsplit = 0;
+    c->xcd_remap = 1;
     set_ns_per_tick(rate_khz > 0 ? 1.0e6 / rate_khz : 10.0);
     *out = c;
     return ILT_OK;
@@ -417,7 +420,7 @@ extern "C" int litho_adjoint(ilt_ctx *c, const float *d_mask, const float *d_G, 
         HIPCHK(launch_split_rows(c, set, set + 1));
         HIPCHK(launch_adjoint_b3(c, d_G, 0, set, set + 1));
     } else {
-        const int stored = c->Est != nullptr;
+        const int stored = c->Est != nullptr && c->store_fields;
         if (stored) HIPCHK(launch_image_to(c, set, set + 1, c->I + (size_t)set * c->N * c->N, 1));
         HIPCHK(launch_adjoint(c, d_G, 0, set, set + 1, stored));
     }
@@ -488,7 +491,7 @@ int enqueue_solve(ilt_ctx *c, const unsigned char *d_target, float *d_phi, const
     used_set_range(p, &slo, &shi);
     const size_t npix = (size_t)c->N * c->N;
     double *pr = c->part + part_resist_off(c), *pm = c->part + part_max_off(c), *ps = c->part + part_step_off(c);
-    const int stored = c->Est != nullptr;
+    const int stored = c->Est != nullptr && c->store_fields;
     const bool b3 = c->precision == ILT_BF16X3;
     c->n_ev = 0;
     if (p->init_mode == 0) {
@@ -671,6 +674,175 @@ extern "C" int ilt_profile_read(ilt_ctx *c, double *h_out, int n) {
         h_out[2 * c->ev_phase[i]] += ms;
         h_out[2 * c->ev_phase[i] + 1] += 1.0;
     }
+    return ILT_OK;
+}
+
+// ---------------------------------------------------------------- tuning
+
+extern "C" int ilt_get_tuning(const ilt_ctx *c, ilt_tuning *t) {
+    int r;
+    if ((r = check_ctx(c))) return r;
+    if (!t) return fail(ILT_EINVAL, "tuning is NULL");
+    t->store_fields = c->store_fields;
+    t->b3_xsplit = c->b3_xsplit;
+    t->xcd_remap = c->xcd_remap;
+    return ILT_OK;
+}
+
+extern "C" int ilt_set_tuning(ilt_ctx *c, const ilt_tuning *t) {
+    int r;
+    if ((r = check_ctx(c))) return r;
+    if (!t) return fail(ILT_EINVAL, "tuning is NULL");
+    if (t->store_fields != 0 && t->store_fields != 1) return fail(ILT_EINVAL, "store_fields must be 0 or 1");
+    if (t->store_fields && !c->Est)
+        return fail(ILT_EINVAL, "store_fields = 1 needs the field buffer (a context without ILT_FLAG_RECOMPUTE_FIELDS, FP32)");
+    if (t->b3_xsplit < 0 || t->b3_xsplit > ILT_B3_MAX_XSPLIT)
+        return fail(ILT_EINVAL, "b3_xsplit must be in [0, %d]", ILT_B3_MAX_XSPLIT);
+    if (t->xcd_remap != 0 && t->xcd_remap != 1) return fail(ILT_EINVAL, "xcd_remap must be 0 or 1");
+    c->store_fields = t->store_fields;
+    c->b3_xsplit = t->b3_xsplit;
+    c->xcd_remap = t->xcd_remap;
+    free_graph(c);   // a captured solve used the old settings
+    return ILT_OK;
+}
+
+namespace {
+
+// Cache line prefix identifying (device architecture, problem shape, form).
+std::string tune_key(const ilt_ctx *c) {
+    hipDeviceProp_t prop;
+    std::string arch = "unknown";
+    if (hipGetDeviceProperties(&prop, c->device) == hipSuccess) arch = prop.gcnArchName;
+    char buf[384];
+    std::snprintf(buf, sizeof buf,
+                  "{\"arch\": \"%s\", \"N\": %d, \"P\": %d, \"K\": %d, \"n_sets\": %d, \"precision\": %d, "
+                  "\"fields_buffer\": %d, ",
+                  arch.c_str(), c->N, c->P, c->K, c->n_sets, c->precision, c->Est != nullptr ? 1 : 0);
+    return buf;
+}
+
+bool tune_from_cache(const char *path, const std::string &key, ilt_tuning *t, double *ms) {
+    FILE *f = std::fopen(path, "r");
+    if (!f) return false;
+    char line[1024];
+    bool found = false;
+    while (std::fgets(line, sizeof line, f)) {
+        if (std::strncmp(line, key.c_str(), key.size()) != 0) continue;
+        ilt_tuning v;
+        double m = 0.0;
+        if (std::sscanf(line + key.size(), "\"store_fields\": %d, \"b3_xsplit\": %d, \"xcd_remap\": %d, \"ms_per_iter\": %lf",
+                        &v.store_fields, &v.b3_xsplit, &v.xcd_remap, &m) == 4) {
+            *t = v;      // the last matching line wins
+            *ms = m;
+            found = true;
+        }
+    }
+    std::fclose(f);
+    return found;
+}
+
+}  // namespace
+
+extern "C" int ilt_autotune(ilt_ctx *c, const char *cache_path, ilt_tuning *h_best, double *h_ms_per_iter) {
+    int r;
+    if ((r = check_ctx(c))) return r;
+    const std::string key = tune_key(c);
+    ilt_tuning best;
+    double best_ms = 0.0;
+    if (cache_path && tune_from_cache(cache_path, key, &best, &best_ms) && ilt_set_tuning(c, &best) == ILT_OK) {
+        if (h_best) *h_best = best;
+        if (h_ms_per_iter) *h_ms_per_iter = best_ms;
+        return 1;   // taken from the cache
+    }
+    // candidates
+    std::vector<ilt_tuning> cand;
+    if (c->precision == ILT_BF16X3) {
+        for (int xs : {1, 2, 4})
+            for (int rm : {0, 1}) cand.push_back(ilt_tuning{0, xs, rm});
+    } else {
+        if (c->Est) cand.push_back(ilt_tuning{1, 0, 1});
+        cand.push_back(ilt_tuning{0, 0, 1});
+    }
+    // a synthetic clip: bars of width N/32 on a pitch of N/8 in both
+    // directions inside a guard band, so every phase sees edges
+    const int N = c->N;
+    std::vector<unsigned char> h_t((size_t)N * N, 0);
+    const int w = std::max(1, N / 32), pitch = std::max(2, N / 8), m = N / 8;
+    for (int y = m; y < N - m; ++y)
+        for (int x = m; x < N - m; ++x)
+            h_t[(size_t)y * N + x] = ((y - m) % pitch < w) || ((x - m) % (2 * pitch) < w);
+    ilt_params p{};
+    p.iters = 3;
+    p.reinit_every = 5;
+    p.dt_mode = 0;
+    p.init_mode = 0;
+    p.eta = 0.85f;
+    p.dt_max = 5.0f;
+    p.lambda = 0.05f;
+    p.sigma_z = 50.0f;
+    p.i_th = 0.225f;
+    p.eps_kappa = 1e-12f;
+    p.d_lower = -100.0f;
+    p.d_upper = 900.0f;
+    p.n_corners = 1;
+    p.corners[0] = ilt_corner{0, 1.0f, 1.0f};
+    if (c->n_sets > 1) {
+        p.n_corners = 3;
+        p.corners[1] = ilt_corner{0, 1.02f, 7.5f};
+        p.corners[2] = ilt_corner{1, 0.98f, 7.5f};
+    }
+    unsigned char *d_t = nullptr;
+    float *d_phi = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipMalloc(&d_t, (size_t)N * N);
+    if (e == hipSuccess) e = hipMalloc(&d_phi, (size_t)N * N * sizeof(float));
+    if (e == hipSuccess) e = hipMemcpy(d_t, h_t.data(), h_t.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    ilt_tuning saved;
+    (void)ilt_get_tuning(c, &saved);
+    const int saved_prof = c->profiling;
+    c->profiling = 0;
+    int rc = e == hipSuccess ? ILT_OK : fail(ILT_EDEVICE, "autotune set-up: %s", hipGetErrorString(e));
+    best_ms = 1e30;
+    best = saved;
+    for (size_t i = 0; i < cand.size() && rc == ILT_OK; ++i) {
+        if ((rc = ilt_set_tuning(c, &cand[i])) != ILT_OK) break;
+        if ((rc = enqueue_solve(c, d_t, d_phi, &p, nullptr)) != ILT_OK) break;     // warm-up
+        if ((e = hipEventRecord(e0, c->stream)) != hipSuccess) break;
+        for (int rep = 0; rep < 2 && rc == ILT_OK; ++rep) rc = enqueue_solve(c, d_t, d_phi, &p, nullptr);
+        if (rc != ILT_OK) break;
+        if ((e = hipEventRecord(e1, c->stream)) != hipSuccess) break;
+        if ((e = hipEventSynchronize(e1)) != hipSuccess) break;
+        float ms = 0.f;
+        if ((e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) break;
+        const double per_iter = ms / (2.0 * p.iters);
+        if (per_iter < best_ms) {
+            best_ms = per_iter;
+            best = cand[i];
+        }
+    }
+    if (rc == ILT_OK && e != hipSuccess) rc = fail(ILT_EDEVICE, "autotune: %s", hipGetErrorString(e));
+    c->profiling = saved_prof;
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipStreamSynchronize(c->stream);
+    if (d_t) (void)hipFree(d_t);
+    if (d_phi) (void)hipFree(d_phi);
+    if (rc != ILT_OK) {
+        (void)ilt_set_tuning(c, &saved);
+        return rc;
+    }
+    if ((rc = ilt_set_tuning(c, &best)) != ILT_OK) return rc;
+    if (cache_path) {
+        FILE *f = std::fopen(cache_path, "a");
+        if (!f) return fail(ILT_EINVAL, "cannot append to the tuning cache %s", cache_path);
+        std::fprintf(f, "%s\"store_fields\": %d, \"b3_xsplit\": %d, \"xcd_remap\": %d, \"ms_per_iter\": %.6f}\n",
+                     key.c_str(), best.store_fields, best.b3_xsplit, best.xcd_remap, best_ms);
+        std::fclose(f);
+    }
+    if (h_best) *h_best = best;
+    if (h_ms_per_iter) *h_ms_per_iter = best_ms;
     return ILT_OK;
 }
 

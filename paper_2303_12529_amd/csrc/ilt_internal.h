@@ -97,6 +97,10 @@ struct ilt_ctx {
     // whole-solve hipGraph, captured on an internal stream and replayed on
     // `stream`; reused while the solve's arguments are unchanged
     int use_graph;
+    // tuning (ilt_set_tuning / ilt_autotune); none changes what is computed
+    // beyond rounding order
+    int store_fields;  // FP32: 1 = forward stores the fields, the adjoint streams them
+    int b3_xsplit;     // BF16x3 adjoint: column chunks split over this many blocks (0 = by size)
     hipStream_t cap_stream;
     hipGraph_t graph;
     hipGraphExec_t graph_exec;
@@ -105,6 +109,7 @@ struct ilt_ctx {
 
     // measurement hook: event pairs per recorded launch
     int profiling;
+    int xcd_remap;     // BF16x3 image: XCD-aware tile order
     int n_ev;                 // events recorded in the current solve
     int ev_cap;
     hipEvent_t *ev;           // [ev_cap][2]
@@ -141,6 +146,8 @@ hipError_t launch_split_rows(ilt_ctx *c, int set_lo, int set_hi);
 hipError_t launch_image_b3(ilt_ctx *c, int set_lo, int set_hi, float *out);
 hipError_t launch_adjoint_b3(ilt_ctx *c, const float *G, size_t g_set_stride, int set_lo, int set_hi);
 int adjoint_b3_parts(const ilt_ctx *c, int nsets);
+int adjoint_b3_max_parts(const ilt_ctx *c, int nsets);
+#define ILT_B3_MAX_XSPLIT 4
 
 // ---- launchers (k_pixel.hip) ----
 int resist_blocks(const ilt_ctx *c);

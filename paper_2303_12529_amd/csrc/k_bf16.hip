@@ -137,9 +137,9 @@ __global__ __launch_bounds__(256) void k_split_rows(const float *__restrict__ Y,
 // XCD-aware tile order: hardware places consecutive blocks round-robin on the
 // 8 XCDs; remap so that the blocks an XCD receives cover all row tiles of the
 // same column tiles, which then share that XCD's L2 for their Y_j tiles.
-__device__ __forceinline__ void xcd_tile(int b, int nblk, int NY, int NX, int &ty, int &tx, int &ts) {
+__device__ __forceinline__ void xcd_tile(int b, int nblk, int NY, int NX, int remap, int &ty, int &tx, int &ts) {
     int L = b;
-    if ((nblk & 7) == 0) L = (b & 7) * (nblk >> 3) + (b >> 3);
+    if (remap && (nblk & 7) == 0) L = (b & 7) * (nblk >> 3) + (b >> 3);
     ty = L % NY;
     const int rest = L / NY;
     tx = rest % NX;
@@ -155,7 +155,7 @@ __device__ __forceinline__ void xcd_tile(int b, int nblk, int NY, int NX, int &t
 // --------------------------------------------------------------------------
 template <int KP>
 __global__ __launch_bounds__(256, 2) void k_image_b3(const __bf16 *__restrict__ tlhl, const __bf16 *__restrict__ Yhl,
-                                                      int nj, int N, int Np, int set_lo, int nsets,
+                                                      int nj, int N, int Np, int set_lo, int nsets, int remap,
                                                       float *__restrict__ out) {
     constexpr int NS = kmap<KP>::NS, NSL = kmap<KP>::NSL;
     constexpr int RW = 2 * KP + 8;                 // LDS row (one column x), bf16
@@ -165,7 +165,7 @@ __global__ __launch_bounds__(256, 2) void k_image_b3(const __bf16 *__restrict__ 
     const int l16 = lane & 15, lq = lane >> 4;
     const int NX = Np / 64, NY = Np / 128;
     int ty, tx, ts;
-    xcd_tile(blockIdx.x, gridDim.x, NY, NX, ty, tx, ts);
+    xcd_tile(blockIdx.x, gridDim.x, NY, NX, remap, ty, tx, ts);
     const int s = set_lo + ts;
     const int x0 = tx * 64;
     const int yw = ty * 128 + wave * 32;
@@ -499,7 +499,7 @@ hipError_t launch_split_rows(ilt_ctx *c, int set_lo, int set_hi) {
 hipError_t launch_image_b3(ilt_ctx *c, int set_lo, int set_hi, float *out) {
     const int nblk = (c->Np / 64) * (c->Np / 128) * (set_hi - set_lo);
     switch (c->KP) {
-#define IMGB(KP_) case KP_: k_image_b3<KP_><<<nblk, 256, 0, c->stream>>>(c->tlhl, c->Yhl, c->K, c->N, c->Np, set_lo, set_hi - set_lo, out); break;
+#define IMGB(KP_) case KP_: k_image_b3<KP_><<<nblk, 256, 0, c->stream>>>(c->tlhl, c->Yhl, c->K, c->N, c->Np, set_lo, set_hi - set_lo, c->xcd_remap, out); break;
         IMGB(8) IMGB(24) IMGB(40) IMGB(72)
 #undef IMGB
         default: return hipErrorInvalidValue;
@@ -508,8 +508,16 @@ hipError_t launch_image_b3(ilt_ctx *c, int set_lo, int set_hi, float *out) {
 }
 
 // Column chunks are split over two blocks once there are enough of them, so
-// that a 2048-pixel clip gives three full rounds of blocks on 256 CUs.
-static int adjoint_b3_xsplit(const ilt_ctx *c) { return (c->N + 31) / 32 >= 8 ? 2 : 1; }
+// that a 2048-pixel clip gives three full rounds of blocks on 256 CUs; the
+// tuner may pick 1 to ILT_B3_MAX_XSPLIT instead.
+static int adjoint_b3_xsplit(const ilt_ctx *c) {
+    if (c->b3_xsplit > 0) return c->b3_xsplit;
+    return (c->N + 31) / 32 >= 8 ? 2 : 1;
+}
+
+int adjoint_b3_max_parts(const ilt_ctx *c, int nsets) {
+    return nsets * ((c->N + 127) / 128) * ILT_B3_MAX_XSPLIT * c->K;
+}
 
 int adjoint_b3_parts(const ilt_ctx *c, int nsets) {
     return nsets * ((c->N + 127) / 128) * adjoint_b3_xsplit(c) * c->K;

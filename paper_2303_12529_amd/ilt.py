@@ -55,6 +55,10 @@ class _Report(ctypes.Structure):
                 ("l2", ctypes.c_longlong), ("pvb", ctypes.c_longlong), ("flips", ctypes.c_longlong)]
 
 
+class _Tuning(ctypes.Structure):
+    _fields_ = [("store_fields", ctypes.c_int), ("b3_xsplit", ctypes.c_int), ("xcd_remap", ctypes.c_int)]
+
+
 class _Clip(ctypes.Structure):
     _fields_ = [("N", ctypes.c_int), ("d_target", ctypes.c_void_p), ("d_phi", ctypes.c_void_p),
                 ("d_trace", ctypes.c_void_p), ("params", _Params)]
@@ -87,6 +91,9 @@ def load_library(path: str = LIB_PATH):
         "ilt_profile": [_VP, ctypes.c_int],
         "ilt_set_graph": [_VP, ctypes.c_int],
         "ilt_profile_read": [_VP, ctypes.POINTER(ctypes.c_double), ctypes.c_int],
+        "ilt_get_tuning": [_VP, ctypes.POINTER(_Tuning)],
+        "ilt_set_tuning": [_VP, ctypes.POINTER(_Tuning)],
+        "ilt_autotune": [_VP, ctypes.c_char_p, ctypes.POINTER(_Tuning), ctypes.POINTER(ctypes.c_double)],
         "ilt_batch_create": [ctypes.POINTER(_VP), ctypes.POINTER(_Optics), ctypes.POINTER(ctypes.c_int),
                              ctypes.c_int, ctypes.c_int, ctypes.c_int, _VP],
         "ilt_batch_destroy": [_VP],
@@ -272,6 +279,31 @@ class Context:
         return dict(iters_done=rep.iters_done, status=rep.status, loss=rep.loss, l2=rep.l2, pvb=rep.pvb,
                     flips=rep.flips)
 
+
+    def get_tuning(self) -> dict:
+        t = _Tuning()
+        _check(load_library().ilt_get_tuning(self._h, ctypes.byref(t)))
+        return {f: getattr(t, f) for f, _ in _Tuning._fields_}
+
+    def set_tuning(self, **kw):
+        cur = self.get_tuning()
+        cur.update(kw)
+        t = _Tuning(**{k: int(v) for k, v in cur.items()})
+        _check(load_library().ilt_set_tuning(self._h, ctypes.byref(t)))
+
+    def autotune(self, cache_path: str | None = None) -> dict:
+        """Time the tuning candidates (or take them from cache_path) and apply
+        the fastest; returns the choice, its ms per iteration and whether it
+        came from the cache."""
+        t = _Tuning()
+        ms = ctypes.c_double()
+        rc = load_library().ilt_autotune(self._h, None if cache_path is None else cache_path.encode(),
+                                         ctypes.byref(t), ctypes.byref(ms))
+        if rc < 0:
+            _check(rc)
+        out = {f: getattr(t, f) for f, _ in _Tuning._fields_}
+        out.update(ms_per_iter=ms.value, from_cache=bool(rc == 1))
+        return out
 
     def set_graph(self, enable: bool = True):
         """Capture ilt_solve into a reusable hipGraph (default) or launch directly."""
