@@ -20,6 +20,9 @@ Modules, each following the paper's statement of the step it computes:
                   truncated signed distance function (TSDF equation, Alg. 1's
                   CUDA_TSDF role).
 * ``solve``    -- the plain DSO loop in the paper's order.
+* ``dsn``      -- the level-set branch of DevelSet-Net (Sec. III-B): a UNet
+                  forward and backward, the L_0 squared error, Adam, and the
+                  resampling between the 2048 grid and the network's 512 grid.
 
 Everything floating-point is float64.  Readings of passages the paper leaves
 open are listed in the design document; each function's docstring names the
