@@ -1,0 +1,106 @@
+/* C ABI of the DevelSet-Net level-set branch on one AMD MI355X (gfx950).
+ *
+ * Sec. III-B of Chen et al., "DevelSet: Deep Neural Level Set for Instant
+ * Mask Optimization" (arXiv 2303.12529): a UNet backbone predicts the initial
+ * level-set function phi_0 of DSO from the target image and is trained with
+ * the squared error L_0 = sum (phi_0,theta - phi_gt)^2 against level-set
+ * functions produced by DSO.  The paper leaves the layer sizes, resampling
+ * and optimiser open; this library fixes them as follows:
+ *   - network grid H x W (the 2048 clip's 4 x 4 means: 512 x 512); four
+ *     levels of width C, 2C, 4C, 8C (C = base, a multiple of 32); per level
+ *     two 3x3 convolutions (zero padding 1, bias, ReLU); 2x2 max-pooling
+ *     down; up: nearest 2x upsampling, a 3x3 convolution (bias, ReLU) to the
+ *     level's width, concatenation [up | skip], the level's two
+ *     convolutions; a 1x1 head (bias, no ReLU);
+ *   - input = 4 x 4 mean of the binary target; target = 4 x 4 mean of phi_gt
+ *     (pixels of the fine grid) / 100; phi_0 = clip(100 x bilinear 4x
+ *     upsample of the output) with half-pixel centres and clamped borders;
+ *   - loss L_0 per sample (a sum over pixels) averaged over the batch;
+ *     Adam on FP32 master weights; BF16 activations, weights and activation
+ *     gradients with FP32 accumulation; FP32 weight gradients.
+ * Parameters are one flat FP32 vector: for each layer in the order enc0_a,
+ * enc0_b, ..., enc3_a, enc3_b, dec2_up, dec2_a, dec2_b, dec1_*, dec0_*, head,
+ * the weights [C_out][3][3][C_in] (head: [1][1][1][C]) then the bias [C_out].
+ *
+ * Buffers are device pointers owned by the caller unless stated; every call
+ * is enqueued on the context's stream and returns without waiting.  Errors:
+ * DSN_EINVAL (bad argument, checked before any launch), DSN_EDEVICE (a HIP
+ * call failed; the message says which), DSN_ENOMEM.  No exception crosses
+ * the ABI.  One context per stream. */
+#ifndef DSN_H
+#define DSN_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { DSN_OK = 0, DSN_EINVAL = -1, DSN_ENOMEM = -2, DSN_EDEVICE = -3 };
+#define DSN_LEVELS 4
+#define DSN_SCALE 100.0f
+
+typedef struct dsn_ctx dsn_ctx;
+
+/* H, W: network grid, multiples of 8 (three poolings), at most 2048;
+ * base: level-0 width, 32 or 64; max_batch >= 1.  Allocates the parameters
+ * (zero), Adam moments, and activations/gradients for max_batch samples.
+ * stream: a hipStream_t (NULL = default stream). */
+int dsn_create(dsn_ctx **out, int H, int W, int base, int max_batch, void *stream);
+int dsn_destroy(dsn_ctx *ctx);
+const char *dsn_last_error(void);
+/* Number of FP32 entries of the flat parameter vector. */
+long long dsn_num_params(const dsn_ctx *ctx);
+/* Load / read the flat FP32 parameters (device [num_params]).  Loading also
+ * refreshes the BF16 working copies and zeroes the Adam moments and step. */
+int dsn_set_params(dsn_ctx *ctx, const float *d_params);
+int dsn_get_params(const dsn_ctx *ctx, float *d_params);
+
+/* Forward pass.  d_x: [B][H][W] FP32 network input; d_out: [B][H][W] FP32
+ * network output (target scale, i.e. phi / 100).  Keeps every activation for
+ * dsn_backward, which also reads d_x and d_out again: both must stay valid
+ * until then.  1 <= B <= max_batch. */
+int dsn_forward(dsn_ctx *ctx, const float *d_x, int B, float *d_out);
+/* Backward pass of L_0 for the last forward (same B).  d_target [B][H][W];
+ * d_loss: device double[1], set to L_0 averaged over the batch; d_grad: NULL
+ * or device FP32 [num_params] receiving the gradient (it is always kept
+ * internally for dsn_adam_step). */
+int dsn_backward(dsn_ctx *ctx, const float *d_target, int B, double *d_loss, float *d_grad);
+/* One Adam step with the gradient of the last backward (step count kept in
+ * the context, starting at 1). */
+int dsn_adam_step(dsn_ctx *ctx, float lr, float beta1, float beta2, float eps);
+
+/* Resampling between the fine grid (4H x 4W) and the network grid.
+ * dsn_prepare: d_target bytes [B][4H][4W] (nonzero = metal) -> d_x
+ * [B][H][W] 4 x 4 means; if d_phi_gt (FP32 [B][4H][4W]) is non-NULL, also
+ * d_t [B][H][W] = 4 x 4 means of phi_gt / 100.
+ * dsn_predict: forward pass of the targets' means, then
+ * d_phi0 [B][4H][4W] = clip(100 x bilinear 4x upsample, d_lower, d_upper). */
+int dsn_prepare(dsn_ctx *ctx, const unsigned char *d_target, const float *d_phi_gt, int B, float *d_x,
+                float *d_t);
+int dsn_predict(dsn_ctx *ctx, const unsigned char *d_target, int B, float d_lower, float d_upper,
+                float *d_phi0);
+
+/* Single operations of the network, for callers composing their own layers
+ * (and for testing each kernel alone).  BF16 tensors channels-last; N images
+ * of H x W output pixels; zero padding 1.  Synchronous; the gradient
+ * operations allocate and free a temporary buffer.
+ * dsn_op_conv3x3: d_y [N][H][W][Cout] = act(d_b + conv(d_x, d_w)), with
+ *   d_x [N][H'][W'][Cin] read through a nearest 2x upsampling when up != 0
+ *   (H' = H/2, W' = W/2; else H' = H, W' = W); d_w [Cout][3][3][Cin]; d_b
+ *   FP32 [Cout] or NULL; relu != 0 applies max(., 0).
+ * dsn_op_conv3x3_dgrad: d_dx [N][H][W][Cin] = gradient of sum(d_dy . conv(x))
+ *   with respect to x (no upsampling), d_dy [N][H][W][Cout].
+ * dsn_op_conv3x3_wgrad: FP32 d_dw [Cout][3][3][Cin] and d_db [Cout], the
+ *   gradients of sum(d_dz . conv(x)) with d_dz [N][H][W][Cout] and x as in
+ *   dsn_op_conv3x3.
+ * Channel counts: multiples of 32 in [32, 1024]. */
+int dsn_op_conv3x3(const void *d_x, int N, int H, int W, int Cin, int up, const void *d_w, const float *d_b,
+                   int Cout, int relu, void *d_y, void *stream);
+int dsn_op_conv3x3_dgrad(const void *d_dy, int N, int H, int W, int Cout, const void *d_w, int Cin, void *d_dx,
+                         void *stream);
+int dsn_op_conv3x3_wgrad(const void *d_dz, const void *d_x, int N, int H, int W, int Cin, int up, int Cout,
+                         float *d_dw, float *d_db, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DSN_H */

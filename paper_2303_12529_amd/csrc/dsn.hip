@@ -1,0 +1,1171 @@
+// DevelSet-Net level-set branch (Sec. III-B): UNet forward, backward of the
+// squared-error loss L_0, Adam, and the resampling between the fine grid and
+// the network grid, on the gfx950 BF16 matrix cores.  The C ABI is in
+// include/dsn.h.
+//
+// Activations are channels-last BF16 views (pointer, channel stride): the
+// encoder's skip outputs are written straight into the upper half of the
+// decoder's concatenation buffers, whose lower half receives the up
+// convolution.  A 3x3 convolution is an implicit GEMM C[co][pixel] =
+// sum_{tap, ci} W[co][tap][ci] X[pixel + tap][ci] on 16x16x32 BF16 matrix
+// instructions (weights as the A operand, so each lane stores four
+// consecutive channels of one pixel); the same kernel computes the input
+// gradient with flipped, transposed weights.  A flag makes a convolution read
+// its input through a nearest 2x upsampling, so the upsampled tensor is never
+// written.  Weight gradients are a GEMM over pixels, split into pixel ranges
+// whose FP32 partials are summed in a fixed order.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdint>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "../../include/dsn.h"
+
+namespace {
+
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf4 __attribute__((ext_vector_type(4)));
+
+thread_local std::string g_err;
+
+int fail(int code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+int fail(int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIPCHK(expr)                                                                             \
+    do {                                                                                         \
+        hipError_t e_ = (expr);                                                                  \
+        if (e_ != hipSuccess) return fail(DSN_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+__device__ __forceinline__ f4 mfma_b(bf8 a, bf8 b, f4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ bf8 bf8_zero() {
+    bf8 z;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) z[e] = (__bf16)0.f;
+    return z;
+}
+
+// Channels-last BF16 tensor view: element (pixel, c) at p[pixel * stride + c].
+struct View {
+    __bf16 *p;
+    int C, stride;
+};
+
+// --------------------------------------------------------------------------
+// First convolution (one input channel), VALU: thread = (pixel, 8 channels).
+// --------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_conv_first(const float *__restrict__ x, int B, int H, int W,
+                                                     const __bf16 *__restrict__ w, const float *__restrict__ bias,
+                                                     View y) {
+    const int groups = y.C / 8;
+    const long long id = (long long)blockIdx.x * 256 + threadIdx.x;
+    const long long npix = (long long)B * H * W;
+    if (id >= npix * groups) return;
+    const long long pix = id / groups;
+    const int g = (int)(id - pix * groups);
+    const int xx = (int)(pix % W);
+    const long long r = pix / W;
+    const int yy = (int)(r % H);
+    const int b = (int)(r / H);
+    float in[9];
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+        const int sy = yy + t / 3 - 1, sx = xx + t % 3 - 1;
+        in[t] = (sy >= 0 && sy < H && sx >= 0 && sx < W) ? x[((size_t)b * H + sy) * W + sx] : 0.f;
+    }
+    bf8 out;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        const int co = 8 * g + e;
+        float acc = bias[co];
+#pragma unroll
+        for (int t = 0; t < 9; ++t) acc = fmaf((float)w[co * 9 + t], in[t], acc);
+        out[e] = (__bf16)fmaxf(acc, 0.f);
+    }
+    *reinterpret_cast<bf8 *>(y.p + pix * y.stride + 8 * g) = out;
+}
+
+// --------------------------------------------------------------------------
+// 3x3 convolution, implicit GEMM on the BF16 matrix cores.
+//   out[pixel][co] = act(bias[co] + sum_{tap, ci} w[co][tap][ci] x[src(pixel, tap)][ci])
+// Block: 4 waves as WPX (pixels) x WCO (channels); wave tile 32 channels x
+// 32 pixels = 2 x 2 matrix blocks.  UP: x has half the resolution and is
+// read through a nearest 2x upsampling.  Requirements (checked on the host):
+// Cin % 32 == 0, Cout % (32 WCO) == 0, 16-byte aligned views.
+// --------------------------------------------------------------------------
+template <int WPX, int WCO, bool UP>
+__global__ __launch_bounds__(256) void k_conv(View x, int B, int H, int W, const __bf16 *__restrict__ w,
+                                              int Cin, const float *__restrict__ bias, int relu, View y) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int l16 = lane & 15, lq = lane >> 4;
+    const int wp = wave % WPX, wc = wave / WPX;
+    const long long npix = (long long)B * H * W;
+    const long long px0 = ((long long)blockIdx.x * WPX + wp) * 32;
+    const int co0 = (blockIdx.y * WCO + wc) * 32;
+    const int Hin = UP ? H / 2 : H, Win = UP ? W / 2 : W;
+    int pb_b[2], pb_y[2], pb_x[2];
+    bool pb_ok[2];
+#pragma unroll
+    for (int pb = 0; pb < 2; ++pb) {
+        const long long pix = px0 + 16 * pb + l16;
+        pb_ok[pb] = pix < npix;
+        const long long pc = pb_ok[pb] ? pix : 0;
+        pb_x[pb] = (int)(pc % W);
+        const long long r = pc / W;
+        pb_y[pb] = (int)(r % H);
+        pb_b[pb] = (int)(r / H);
+    }
+    f4 acc[2][2];
+#pragma unroll
+    for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+        for (int pb = 0; pb < 2; ++pb) acc[cb][pb] = f4{0.f, 0.f, 0.f, 0.f};
+    for (int t = 0; t < 9; ++t) {
+        const int dy = t / 3 - 1, dx = t % 3 - 1;
+        const __bf16 *src[2];
+#pragma unroll
+        for (int pb = 0; pb < 2; ++pb) {
+            const int sy = pb_y[pb] + dy, sx = pb_x[pb] + dx;
+            const bool ok = pb_ok[pb] && sy >= 0 && sy < H && sx >= 0 && sx < W;
+            const int iy = UP ? (sy >> 1) : sy, ix = UP ? (sx >> 1) : sx;
+            src[pb] = ok ? x.p + (((size_t)pb_b[pb] * Hin + iy) * Win + ix) * x.stride + 8 * lq : nullptr;
+        }
+        const __bf16 *wt[2];
+#pragma unroll
+        for (int cb = 0; cb < 2; ++cb) wt[cb] = w + ((size_t)(co0 + 16 * cb + l16) * 9 + t) * Cin + 8 * lq;
+        for (int ci0 = 0; ci0 < Cin; ci0 += 32) {
+            bf8 a[2], bv[2];
+#pragma unroll
+            for (int cb = 0; cb < 2; ++cb) a[cb] = *reinterpret_cast<const bf8 *>(wt[cb] + ci0);
+#pragma unroll
+            for (int pb = 0; pb < 2; ++pb)
+                bv[pb] = src[pb] ? *reinterpret_cast<const bf8 *>(src[pb] + ci0) : bf8_zero();
+#pragma unroll
+            for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+                for (int pb = 0; pb < 2; ++pb) acc[cb][pb] = mfma_b(a[cb], bv[pb], acc[cb][pb]);
+        }
+    }
+    // register i of acc[cb][pb]: channel co0 + 16 cb + 4 lq + i, pixel px0 + 16 pb + l16
+#pragma unroll
+    for (int pb = 0; pb < 2; ++pb) {
+        const long long pix = px0 + 16 * pb + l16;
+        if (pix >= npix) continue;
+#pragma unroll
+        for (int cb = 0; cb < 2; ++cb) {
+            const int c = co0 + 16 * cb + 4 * lq;
+            bf4 o;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                float v = acc[cb][pb][i] + (bias ? bias[c + i] : 0.f);
+                if (relu) v = fmaxf(v, 0.f);
+                o[i] = (__bf16)v;
+            }
+            *reinterpret_cast<bf4 *>(y.p + pix * y.stride + c) = o;
+        }
+    }
+}
+
+// --------------------------------------------------------------------------
+// Weight gradient, split over pixel ranges:
+//   part[s][co][tap][ci] = sum_{pixel in range s} dz[pixel][co] x[src(pixel, tap)][ci]
+// Block tile TCO x TCI channels for one tap; per stage PXC pixels of dz and
+// of the shifted x are staged transposed ([channel][pixel]) in LDS so that
+// each lane reads 8 consecutive pixels as one operand.  Waves: one per
+// 32 x 32 quadrant; with fewer than four quadrants the remaining waves take
+// further 32-pixel slices of the stage and are summed at the end.
+// --------------------------------------------------------------------------
+template <int TCO, int TCI, bool UP>
+__global__ __launch_bounds__(256) void k_wgrad(View dz, View x, int B, int H, int W, int Cin, int Cout,
+                                               long long pix_per_split, float *__restrict__ part) {
+    constexpr int NQ = (TCO / 32) * (TCI / 32);
+    constexpr int KS = 4 / NQ;                 // 32-pixel slices per stage
+    constexpr int PXC = 32 * KS;
+    constexpr int LD = PXC + 8;                // LDS row (bf16), padded
+    __shared__ __attribute__((aligned(16))) __bf16 Zs[TCO][LD];
+    __shared__ __attribute__((aligned(16))) __bf16 Xs[TCI][LD];
+    __shared__ float Red[KS > 1 ? 4 : 1][32][33];   // per wave
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int l16 = lane & 15, lq = lane >> 4;
+    const int q = wave % NQ, ks = wave / NQ;
+    const int qco = (q % (TCO / 32)) * 32, qci = (q / (TCO / 32)) * 32;
+    const int co_t = blockIdx.x * TCO, ci_t = blockIdx.y * TCI;
+    const int t = blockIdx.z % 9, s = blockIdx.z / 9;
+    const int dy = t / 3 - 1, dx = t % 3 - 1;
+    const long long npix = (long long)B * H * W;
+    const long long p_lo = (long long)s * pix_per_split;
+    const long long p_hi = p_lo + pix_per_split < npix ? p_lo + pix_per_split : npix;
+    const int Hin = UP ? H / 2 : H, Win = UP ? W / 2 : W;
+    f4 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+    for (long long p0 = p_lo; p0 < p_hi; p0 += PXC) {
+        __syncthreads();
+        // stage dz: PXC pixels x TCO channels, 8 channels per thread-load
+        for (int e = threadIdx.x; e < PXC * (TCO / 8); e += 256) {
+            const int px = e / (TCO / 8), g = e % (TCO / 8);
+            const long long pix = p0 + px;
+            bf8 v = bf8_zero();
+            if (pix < p_hi) v = *reinterpret_cast<const bf8 *>(dz.p + pix * dz.stride + co_t + 8 * g);
+#pragma unroll
+            for (int k = 0; k < 8; ++k) Zs[8 * g + k][px] = v[k];
+        }
+        // stage x at the tap's source pixel
+        for (int e = threadIdx.x; e < PXC * (TCI / 8); e += 256) {
+            const int px = e / (TCI / 8), g = e % (TCI / 8);
+            const long long pix = p0 + px;
+            bf8 v = bf8_zero();
+            if (pix < p_hi) {
+                const int xx = (int)(pix % W);
+                const long long r = pix / W;
+                const int yy = (int)(r % H), b = (int)(r / H);
+                const int sy = yy + dy, sx = xx + dx;
+                if (sy >= 0 && sy < H && sx >= 0 && sx < W) {
+                    const int iy = UP ? (sy >> 1) : sy, ix = UP ? (sx >> 1) : sx;
+                    v = *reinterpret_cast<const bf8 *>(x.p + (((size_t)b * Hin + iy) * Win + ix) * x.stride + ci_t + 8 * g);
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < 8; ++k) Xs[8 * g + k][px] = v[k];
+        }
+        __syncthreads();
+        const int k0 = 32 * ks + 8 * lq;
+        bf8 a[2], bv[2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) a[i] = *reinterpret_cast<const bf8 *>(&Zs[qco + 16 * i + l16][k0]);
+#pragma unroll
+        for (int j = 0; j < 2; ++j) bv[j] = *reinterpret_cast<const bf8 *>(&Xs[qci + 16 * j + l16][k0]);
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j) acc[i][j] = mfma_b(a[i], bv[j], acc[i][j]);
+    }
+    // register r of acc[i][j]: co = qco + 16 i + 4 lq + r, ci = qci + 16 j + l16
+    if (KS > 1) {
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) Red[wave][16 * i + 4 * lq + r][16 * j + l16] = acc[i][j][r];
+        __syncthreads();
+        if (ks != 0) return;
+        // waves q, q + NQ, q + 2 NQ, ... hold the same quadrant's slices
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    float v = 0.f;
+                    for (int k = 0; k < KS; ++k) v += Red[q + NQ * k][16 * i + 4 * lq + r][16 * j + l16];
+                    acc[i][j][r] = v;
+                }
+    }
+    float *dst = part + (size_t)s * Cout * 9 * Cin;
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int co = co_t + qco + 16 * i + 4 * lq + r, ci = ci_t + qci + 16 * j + l16;
+                dst[((size_t)co * 9 + t) * Cin + ci] = acc[i][j][r];
+            }
+}
+
+// First layer (one input channel): part[s][co][tap] over a pixel range.
+__global__ __launch_bounds__(256) void k_wgrad_first(View dz, const float *__restrict__ x, int B, int H, int W,
+                                                      long long pix_per_split, float *__restrict__ part) {
+    const int C = dz.C;                       // <= 64
+    __shared__ float red[256][10];
+    const int s = blockIdx.x;
+    const long long npix = (long long)B * H * W;
+    const long long p_lo = (long long)s * pix_per_split;
+    const long long p_hi = p_lo + pix_per_split < npix ? p_lo + pix_per_split : npix;
+    const int co = threadIdx.x % C, ph = threadIdx.x / C, nph = 256 / C;
+    float acc[10];
+#pragma unroll
+    for (int k = 0; k < 10; ++k) acc[k] = 0.f;
+    for (long long pix = p_lo + ph; pix < p_hi; pix += nph) {
+        const float d = (float)dz.p[pix * dz.stride + co];
+        const int xx = (int)(pix % W);
+        const long long r = pix / W;
+        const int yy = (int)(r % H), b = (int)(r / H);
+#pragma unroll
+        for (int t = 0; t < 9; ++t) {
+            const int sy = yy + t / 3 - 1, sx = xx + t % 3 - 1;
+            if (sy >= 0 && sy < H && sx >= 0 && sx < W) acc[t] = fmaf(d, x[((size_t)b * H + sy) * W + sx], acc[t]);
+        }
+        acc[9] += d;
+    }
+#pragma unroll
+    for (int k = 0; k < 10; ++k) red[threadIdx.x][k] = acc[k];
+    __syncthreads();
+    if (threadIdx.x < C) {
+        float v[10];
+#pragma unroll
+        for (int k = 0; k < 10; ++k) v[k] = 0.f;
+        for (int h = 0; h < nph; ++h)
+#pragma unroll
+            for (int k = 0; k < 10; ++k) v[k] += red[h * C + threadIdx.x][k];
+        // [s][co][tap] then bias partials [s][co] after all weights
+        for (int k = 0; k < 9; ++k) part[((size_t)s * C + threadIdx.x) * 9 + k] = v[k];
+        part[(size_t)gridDim.x * C * 9 + (size_t)s * C + threadIdx.x] = v[9];
+    }
+}
+
+// Bias gradient partials: part[s][c] = sum_{pixel in range s} dz[pixel][c].
+__global__ __launch_bounds__(256) void k_bias_grad(View dz, long long npix, long long pix_per_split,
+                                                    float *__restrict__ part) {
+    __shared__ float red[256];
+    const int C = dz.C;
+    const int s = blockIdx.x;
+    const int c = threadIdx.x % C, ph = threadIdx.x / C, nph = 256 / C;
+    const long long p_lo = (long long)s * pix_per_split;
+    const long long p_hi = p_lo + pix_per_split < npix ? p_lo + pix_per_split : npix;
+    float acc = 0.f;
+    if (ph < nph)
+        for (long long pix = p_lo + ph; pix < p_hi; pix += nph) acc += (float)dz.p[pix * dz.stride + c];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    if (threadIdx.x < C) {
+        float v = 0.f;
+        for (int h = 0; h < nph; ++h) v += red[h * C + threadIdx.x];
+        part[(size_t)s * C + threadIdx.x] = v;
+    }
+}
+
+// out[j] = sum_s part[s][j] in a fixed order (FP64 accumulation).
+__global__ void k_reduce_splits(const float *__restrict__ part, int S, long long n, float *__restrict__ out) {
+    const long long j = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    double v = 0.0;
+    for (int s = 0; s < S; ++s) v += part[(size_t)s * n + j];
+    out[j] = (float)v;
+}
+
+// --------------------------------------------------------------------------
+// Pooling, upsampling, ReLU gradient (thread = pixel x 8 channels).
+// --------------------------------------------------------------------------
+__global__ void k_maxpool(View x, int B, int H, int W, View y) {
+    const int groups = x.C / 8;
+    const int Ho = H / 2, Wo = W / 2;
+    const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long n = (long long)B * Ho * Wo * groups;
+    if (id >= n) return;
+    const long long po = id / groups;
+    const int g = (int)(id - po * groups);
+    const int xo = (int)(po % Wo);
+    const long long r = po / Wo;
+    const int yo = (int)(r % Ho), b = (int)(r / Ho);
+    bf8 m;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const size_t pi = ((size_t)b * H + 2 * yo + k / 2) * W + 2 * xo + k % 2;
+        const bf8 v = *reinterpret_cast<const bf8 *>(x.p + pi * x.stride + 8 * g);
+        if (k == 0) {
+            m = v;
+        } else {
+#pragma unroll
+            for (int e = 0; e < 8; ++e) m[e] = (float)v[e] > (float)m[e] ? v[e] : m[e];
+        }
+    }
+    *reinterpret_cast<bf8 *>(y.p + po * y.stride + 8 * g) = m;
+}
+
+// dx (view holding the skip gradient) += gradient routed to the first
+// maximum (row-major order) of each 2x2 window.
+__global__ void k_maxpool_bwd(View x, int B, int H, int W, View dy, View dx) {
+    const int groups = x.C / 8;
+    const int Ho = H / 2, Wo = W / 2;
+    const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long n = (long long)B * Ho * Wo * groups;
+    if (id >= n) return;
+    const long long po = id / groups;
+    const int g = (int)(id - po * groups);
+    const int xo = (int)(po % Wo);
+    const long long r = po / Wo;
+    const int yo = (int)(r % Ho), b = (int)(r / Ho);
+    bf8 v[4];
+    size_t pi[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        pi[k] = ((size_t)b * H + 2 * yo + k / 2) * W + 2 * xo + k % 2;
+        v[k] = *reinterpret_cast<const bf8 *>(x.p + pi[k] * x.stride + 8 * g);
+    }
+    int arg[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        int a = 0;
+        float best = (float)v[0][e];
+#pragma unroll
+        for (int k = 1; k < 4; ++k)
+            if ((float)v[k][e] > best) {
+                best = (float)v[k][e];
+                a = k;
+            }
+        arg[e] = a;
+    }
+    const bf8 d = *reinterpret_cast<const bf8 *>(dy.p + po * dy.stride + 8 * g);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        __bf16 *q = dx.p + pi[k] * dx.stride + 8 * g;
+        bf8 cur = *reinterpret_cast<const bf8 *>(q);
+#pragma unroll
+        for (int e = 0; e < 8; ++e)
+            if (arg[e] == k) cur[e] = (__bf16)((float)cur[e] + (float)d[e]);
+        *reinterpret_cast<bf8 *>(q) = cur;
+    }
+}
+
+// Gradient of the nearest 2x upsampling: dx[half pixel] = sum of its 4 children.
+__global__ void k_upsample_bwd(View dy, int B, int H, int W, View dx) {
+    const int groups = dx.C / 8;
+    const int Ho = H / 2, Wo = W / 2;
+    const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long n = (long long)B * Ho * Wo * groups;
+    if (id >= n) return;
+    const long long po = id / groups;
+    const int g = (int)(id - po * groups);
+    const int xo = (int)(po % Wo);
+    const long long r = po / Wo;
+    const int yo = (int)(r % Ho), b = (int)(r / Ho);
+    float s[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) s[e] = 0.f;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const size_t pi = ((size_t)b * H + 2 * yo + k / 2) * W + 2 * xo + k % 2;
+        const bf8 v = *reinterpret_cast<const bf8 *>(dy.p + pi * dy.stride + 8 * g);
+#pragma unroll
+        for (int e = 0; e < 8; ++e) s[e] += (float)v[e];
+    }
+    bf8 o;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) o[e] = (__bf16)s[e];
+    *reinterpret_cast<bf8 *>(dx.p + po * dx.stride + 8 * g) = o;
+}
+
+// d <- d . [y > 0] (in place), same shape views.
+__global__ void k_relu_bwd(View d, View y, long long npix) {
+    const int groups = d.C / 8;
+    const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= npix * groups) return;
+    const long long pix = id / groups;
+    const int g = (int)(id - pix * groups);
+    __bf16 *q = d.p + pix * d.stride + 8 * g;
+    bf8 dv = *reinterpret_cast<const bf8 *>(q);
+    const bf8 yv = *reinterpret_cast<const bf8 *>(y.p + pix * y.stride + 8 * g);
+#pragma unroll
+    for (int e = 0; e < 8; ++e)
+        if (!((float)yv[e] > 0.f)) dv[e] = (__bf16)0.f;
+    *reinterpret_cast<bf8 *>(q) = dv;
+}
+
+// --------------------------------------------------------------------------
+// Head (1x1 convolution to one channel) and the loss.
+// --------------------------------------------------------------------------
+__global__ void k_head(View x, long long npix, const __bf16 *__restrict__ w, const float *__restrict__ bias,
+                       float *__restrict__ out) {
+    const long long pix = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (pix >= npix) return;
+    float acc = bias[0];
+    for (int c = 0; c < x.C; c += 8) {
+        const bf8 v = *reinterpret_cast<const bf8 *>(x.p + pix * x.stride + c);
+#pragma unroll
+        for (int e = 0; e < 8; ++e) acc = fmaf((float)w[c + e], (float)v[e], acc);
+    }
+    out[pix] = acc;
+}
+
+// g = (2/B)(out - t); dx[pixel][c] = g w[c]; per-block partials of the loss
+// (FP64) and of the head gradients sum_p g x[p][c], sum_p g (FP32).
+__global__ __launch_bounds__(256) void k_head_bwd(View x, long long npix, int B, const __bf16 *__restrict__ w,
+                                                   const float *__restrict__ out, const float *__restrict__ tgt,
+                                                   View dx, double *__restrict__ loss_part,
+                                                   float *__restrict__ gpart) {
+    const int C = x.C;                      // <= 64
+    __shared__ double lred[256];
+    __shared__ float gred[256][65];
+    const long long pix = (long long)blockIdx.x * 256 + threadIdx.x;
+    double l = 0.0;
+    for (int c = 0; c <= C; ++c) gred[threadIdx.x][c] = 0.f;
+    if (pix < npix) {
+        const float d = out[pix] - tgt[pix];
+        l = (double)d * d;
+        const float g = 2.f / (float)B * d;
+        for (int c = 0; c < C; c += 8) {
+            const bf8 v = *reinterpret_cast<const bf8 *>(x.p + pix * x.stride + c);
+            bf8 o;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                o[e] = (__bf16)(g * (float)w[c + e]);
+                gred[threadIdx.x][c + e] = g * (float)v[e];
+            }
+            *reinterpret_cast<bf8 *>(dx.p + pix * dx.stride + c) = o;
+        }
+        gred[threadIdx.x][C] = g;
+    }
+    lred[threadIdx.x] = l;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s = 0.0;
+        for (int i = 0; i < 256; ++i) s += lred[i];
+        loss_part[blockIdx.x] = s;
+    }
+    if (threadIdx.x <= C) {
+        float s = 0.f;
+        for (int i = 0; i < 256; ++i) s += gred[i][threadIdx.x];
+        gpart[(size_t)blockIdx.x * (C + 1) + threadIdx.x] = s;
+    }
+}
+
+__global__ void k_loss_finish(const double *__restrict__ part, int n, int B, double *__restrict__ loss) {
+    __shared__ double red[256];
+    double s = 0.0;
+    for (int i = threadIdx.x; i < n; i += 256) s += part[i];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int i = 0; i < 256; ++i) t += red[i];
+        loss[0] = t / B;
+    }
+}
+
+// --------------------------------------------------------------------------
+// Parameters: BF16 working copies, flipped/transposed copies for the input
+// gradient, Adam.
+// --------------------------------------------------------------------------
+__global__ void k_to_bf16(const float *__restrict__ a, long long n, __bf16 *__restrict__ b) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) b[i] = (__bf16)a[i];
+}
+
+// wt[ci][tap][co] = w[co][8 - tap][ci]
+__global__ void k_flip_transpose(const __bf16 *__restrict__ w, int Cout, int Cin, __bf16 *__restrict__ wt) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long n = (long long)Cout * 9 * Cin;
+    if (i >= n) return;
+    const int co = (int)(i % Cout);
+    const long long r = i / Cout;
+    const int t = (int)(r % 9), ci = (int)(r / 9);
+    wt[i] = w[((size_t)co * 9 + (8 - t)) * Cin + ci];
+}
+
+__global__ void k_adam(float *__restrict__ p, float *__restrict__ m, float *__restrict__ v,
+                       const float *__restrict__ g, long long n, float lr, float b1, float b2, float eps,
+                       float c1, float c2, __bf16 *__restrict__ pb) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.f - b1) * gi;
+    const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    const float pi = p[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+    p[i] = pi;
+    pb[i] = (__bf16)pi;
+}
+
+// --------------------------------------------------------------------------
+// Resampling between the fine grid (4H x 4W) and the network grid (H x W).
+// --------------------------------------------------------------------------
+__global__ void k_prepare(const unsigned char *__restrict__ tgt, const float *__restrict__ phi, int B, int H,
+                          int W, float *__restrict__ x, float *__restrict__ t) {
+    const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= (long long)B * H * W) return;
+    const int xx = (int)(id % W);
+    const long long r = id / W;
+    const int yy = (int)(r % H), b = (int)(r / H);
+    const int W4 = 4 * W, H4 = 4 * H;
+    int cnt = 0;
+    double s = 0.0;
+    for (int a = 0; a < 4; ++a)
+        for (int c = 0; c < 4; ++c) {
+            const size_t q = ((size_t)b * H4 + 4 * yy + a) * W4 + 4 * xx + c;
+            cnt += tgt[q] != 0;
+            if (phi) s += phi[q];
+        }
+    x[id] = (float)cnt * (1.f / 16.f);
+    if (phi) t[id] = (float)(s / 16.0 / (double)DSN_SCALE);
+}
+
+// phi0 = clip(100 x bilinear 4x upsampling): fine pixel i samples the network
+// coordinate (i + 1/2)/4 - 1/2, clamped to [0, n - 1].
+__global__ void k_phi0(const float *__restrict__ out, int B, int H, int W, float lo, float hi,
+                       float *__restrict__ phi0) {
+    const int W4 = 4 * W, H4 = 4 * H;
+    const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= (long long)B * H4 * W4) return;
+    const int xx = (int)(id % W4);
+    const long long r = id / W4;
+    const int yy = (int)(r % H4), b = (int)(r / H4);
+    const float ty = fminf(fmaxf((yy + 0.5f) * 0.25f - 0.5f, 0.f), (float)(H - 1));
+    const float tx = fminf(fmaxf((xx + 0.5f) * 0.25f - 0.5f, 0.f), (float)(W - 1));
+    const int y0 = (int)ty, x0 = (int)tx;
+    const int y1 = min(y0 + 1, H - 1), x1 = min(x0 + 1, W - 1);
+    const float fy = ty - y0, fx = tx - x0;
+    const float *o = out + (size_t)b * H * W;
+    const float top = o[(size_t)y0 * W + x0] * (1.f - fx) + o[(size_t)y0 * W + x1] * fx;
+    const float bot = o[(size_t)y1 * W + x0] * (1.f - fx) + o[(size_t)y1 * W + x1] * fx;
+    const float v = DSN_SCALE * (top * (1.f - fy) + bot * fy);
+    phi0[id] = fminf(fmaxf(v, lo), hi);
+}
+
+inline unsigned grid1(long long n, int bs = 256) { return (unsigned)((n + bs - 1) / bs); }
+
+}  // namespace
+
+// ---------------------------------------------------------------- host side
+
+struct dsn_layer {
+    int cin, cout;
+    long long w_off, b_off;   // offsets in the flat parameter vector
+};
+
+struct dsn_ctx {
+    int H, W, base, maxB;
+    hipStream_t stream;
+    int C[DSN_LEVELS], h[DSN_LEVELS], w[DSN_LEVELS];
+    long long np[DSN_LEVELS];          // pixels per level at max batch
+    std::vector<dsn_layer> L;          // parameter order
+    long long n_params;
+    float *p = nullptr, *m = nullptr, *v = nullptr, *grad = nullptr;
+    __bf16 *pb = nullptr, *pt = nullptr;   // BF16 weights, flipped/transposed copies
+    int step = 0;
+    // activations
+    float *x_in = nullptr;                 // forward input [B][H][W] (caller's, kept)
+    __bf16 *act_a[DSN_LEVELS] = {}, *cat[DSN_LEVELS] = {}, *pool[DSN_LEVELS] = {}, *bott = nullptr;
+    __bf16 *dec_a[DSN_LEVELS] = {}, *dec_b[DSN_LEVELS] = {};
+    float *out = nullptr;                  // forward output [B][H][W] (caller's, kept)
+    int fwdB = 0;
+    // gradients
+    __bf16 *gA[DSN_LEVELS] = {}, *gB[DSN_LEVELS] = {}, *gcat[DSN_LEVELS] = {};
+    float *part = nullptr;
+    long long part_cap = 0;
+    double *lpart = nullptr;
+    float *hpart = nullptr;
+    float *net_x = nullptr, *net_out = nullptr;   // predict scratch
+    std::vector<void *> allocs;
+};
+
+namespace {
+
+enum { ENC0A = 0 };   // layer indices: enc l a = 2l, enc l b = 2l + 1; dec l: 8 + 3 (2 - l) + {0 up, 1 a, 2 b}; head 17
+inline int enc_a(int l) { return 2 * l; }
+inline int enc_b(int l) { return 2 * l + 1; }
+inline int dec_up(int l) { return 2 * DSN_LEVELS + 3 * (DSN_LEVELS - 2 - l); }
+inline int dec_a_i(int l) { return dec_up(l) + 1; }
+inline int dec_b_i(int l) { return dec_up(l) + 2; }
+inline int head_i() { return 2 * DSN_LEVELS + 3 * (DSN_LEVELS - 1); }
+
+View view(__bf16 *p, int C, int stride) { return View{p, C, stride}; }
+
+int splits_for(long long npix) {
+    long long s = npix / 4096;
+    return (int)std::max(1LL, std::min(256LL, s));
+}
+
+template <typename T>
+hipError_t dalloc(dsn_ctx *c, T **p, size_t n) {
+    void *q = nullptr;
+    hipError_t e = hipMalloc(&q, std::max<size_t>(n, 1) * sizeof(T));
+    if (e == hipSuccess) {
+        c->allocs.push_back(q);
+        *p = static_cast<T *>(q);
+    }
+    return e;
+}
+
+void free_all(dsn_ctx *c) {
+    for (void *q : c->allocs) (void)hipFree(q);
+    c->allocs.clear();
+}
+
+int conv(dsn_ctx *c, View x, int B, int l, int layer_i, bool up, bool transposed, int relu, View y) {
+    // forward: weights pb[layer] [cout][9][cin]; input gradient: pt[layer] [cin][9][cout]
+    const dsn_layer &ly = c->L[layer_i];
+    const int Cin = transposed ? ly.cout : ly.cin, Cout = transposed ? ly.cin : ly.cout;
+    const __bf16 *w = (transposed ? c->pt : c->pb) + ly.w_off;
+    const float *bias = transposed ? nullptr : c->p + ly.b_off;
+    if (Cin % 32 || Cout % 32 || x.C != Cin || y.C != Cout) return fail(DSN_EINVAL, "conv shape mismatch");
+    const int H = c->h[l], W = c->w[l];
+    const long long npix = (long long)B * H * W;
+    if (Cout % 64 == 0) {
+        dim3 grid(grid1(npix, 64), Cout / 64);
+        if (up) k_conv<2, 2, true><<<grid, 256, 0, c->stream>>>(x, B, H, W, w, Cin, bias, relu, y);
+        else k_conv<2, 2, false><<<grid, 256, 0, c->stream>>>(x, B, H, W, w, Cin, bias, relu, y);
+    } else {
+        dim3 grid(grid1(npix, 128), Cout / 32);
+        if (up) k_conv<4, 1, true><<<grid, 256, 0, c->stream>>>(x, B, H, W, w, Cin, bias, relu, y);
+        else k_conv<4, 1, false><<<grid, 256, 0, c->stream>>>(x, B, H, W, w, Cin, bias, relu, y);
+    }
+    HIPCHK(hipGetLastError());
+    return DSN_OK;
+}
+
+// weight and bias gradients of a 3x3 layer (input view x, output gradient dz)
+int wgrad(dsn_ctx *c, View dz, View x, int B, int l, int layer_i, bool up) {
+    const dsn_layer &ly = c->L[layer_i];
+    const int H = c->h[l], W = c->w[l];
+    const long long npix = (long long)B * H * W;
+    const int S = splits_for(npix);
+    const long long pps = (npix + S - 1) / S;
+    const int Cin = ly.cin, Cout = ly.cout;
+    if ((long long)S * Cout * 9 * Cin > c->part_cap || (long long)S * Cout > c->part_cap)
+        return fail(DSN_EINVAL, "weight-gradient scratch too small");
+    const int tco = Cout % 64 == 0 ? 64 : 32, tci = Cin % 64 == 0 ? 64 : 32;
+    dim3 grid(Cout / tco, Cin / tci, 9 * S);
+#define WG(A, Bq)                                                                                        \
+    if (up) k_wgrad<A, Bq, true><<<grid, 256, 0, c->stream>>>(dz, x, B, H, W, Cin, Cout, pps, c->part); \
+    else k_wgrad<A, Bq, false><<<grid, 256, 0, c->stream>>>(dz, x, B, H, W, Cin, Cout, pps, c->part)
+    if (tco == 64 && tci == 64) WG(64, 64);
+    else if (tco == 64) WG(64, 32);
+    else if (tci == 64) WG(32, 64);
+    else WG(32, 32);
+#undef WG
+    HIPCHK(hipGetLastError());
+    const long long nw = (long long)Cout * 9 * Cin;
+    k_reduce_splits<<<grid1(nw), 256, 0, c->stream>>>(c->part, S, nw, c->grad + ly.w_off);
+    HIPCHK(hipGetLastError());
+    k_bias_grad<<<S, 256, 0, c->stream>>>(dz, npix, pps, c->part);
+    HIPCHK(hipGetLastError());
+    k_reduce_splits<<<grid1(Cout), 256, 0, c->stream>>>(c->part, S, Cout, c->grad + ly.b_off);
+    HIPCHK(hipGetLastError());
+    return DSN_OK;
+}
+
+int relu_bwd(dsn_ctx *c, View d, View y, long long npix) {
+    k_relu_bwd<<<grid1(npix * (d.C / 8)), 256, 0, c->stream>>>(d, y, npix);
+    HIPCHK(hipGetLastError());
+    return DSN_OK;
+}
+
+int check_ctx(const dsn_ctx *c) { return c ? DSN_OK : fail(DSN_EINVAL, "context is NULL"); }
+
+int check_ptr(const void *p, const char *name) {
+    if (!p) return fail(DSN_EINVAL, "%s is NULL", name);
+    if (reinterpret_cast<uintptr_t>(p) % 16) return fail(DSN_EINVAL, "%s is not 16-byte aligned", name);
+    return DSN_OK;
+}
+
+}  // namespace
+
+extern "C" const char *dsn_last_error(void) { return g_err.c_str(); }
+
+extern "C" int dsn_create(dsn_ctx **out, int H, int W, int base, int maxB, void *stream) {
+    if (!out) return fail(DSN_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (H < 8 || W < 8 || H % 8 || W % 8 || H > 2048 || W > 2048)
+        return fail(DSN_EINVAL, "H and W must be multiples of 8 in [8, 2048]");
+    if (base != 32 && base != 64) return fail(DSN_EINVAL, "base must be 32 or 64");
+    if (maxB < 1) return fail(DSN_EINVAL, "max_batch must be >= 1");
+    dsn_ctx *c = new (std::nothrow) dsn_ctx();
+    if (!c) return fail(DSN_ENOMEM, "out of host memory");
+    c->H = H;
+    c->W = W;
+    c->base = base;
+    c->maxB = maxB;
+    c->stream = static_cast<hipStream_t>(stream);
+    for (int l = 0; l < DSN_LEVELS; ++l) {
+        c->C[l] = base << l;
+        c->h[l] = H >> l;
+        c->w[l] = W >> l;
+        c->np[l] = (long long)maxB * c->h[l] * c->w[l];
+    }
+    // parameter table
+    long long off = 0;
+    auto add = [&](int cin, int cout, int taps) {
+        dsn_layer ly{cin, cout, off, off + (long long)cout * taps * cin};
+        off = ly.b_off + cout;
+        c->L.push_back(ly);
+    };
+    int prev = 1;
+    for (int l = 0; l < DSN_LEVELS; ++l) {
+        add(prev, c->C[l], 9);
+        add(c->C[l], c->C[l], 9);
+        prev = c->C[l];
+    }
+    for (int l = DSN_LEVELS - 2; l >= 0; --l) {
+        add(c->C[l + 1], c->C[l], 9);
+        add(2 * c->C[l], c->C[l], 9);
+        add(c->C[l], c->C[l], 9);
+    }
+    add(c->C[0], 1, 1);
+    c->n_params = off;
+    // scratch for split weight gradients: the largest S * Cout * 9 * Cin
+    long long cap = 0;
+    for (size_t i = 0; i + 1 < c->L.size(); ++i) {
+        int l = 0;
+        if (i < 2 * DSN_LEVELS) l = (int)i / 2;
+        else l = DSN_LEVELS - 2 - (int)(i - 2 * DSN_LEVELS) / 3;
+        const long long S = splits_for(c->np[l]);
+        cap = std::max(cap, S * c->L[i].cout * 9 * std::max(c->L[i].cin, 1) + S * c->L[i].cout);
+    }
+    c->part_cap = cap;
+    hipError_t e = hipSuccess;
+    const long long n = c->n_params;
+    if (e == hipSuccess) e = dalloc(c, &c->p, n);
+    if (e == hipSuccess) e = dalloc(c, &c->m, n);
+    if (e == hipSuccess) e = dalloc(c, &c->v, n);
+    if (e == hipSuccess) e = dalloc(c, &c->grad, n);
+    if (e == hipSuccess) e = dalloc(c, &c->pb, n);
+    if (e == hipSuccess) e = dalloc(c, &c->pt, n);
+    if (e == hipSuccess) e = dalloc(c, &c->part, cap);
+    for (int l = 0; l < DSN_LEVELS && e == hipSuccess; ++l) {
+        const long long np = c->np[l];
+        const int C = c->C[l];
+        e = dalloc(c, &c->act_a[l], np * C);
+        if (e == hipSuccess && l < DSN_LEVELS - 1) e = dalloc(c, &c->cat[l], np * 2 * C);
+        if (e == hipSuccess && l < DSN_LEVELS - 1) e = dalloc(c, &c->pool[l], c->np[l + 1] * C);
+        if (e == hipSuccess && l < DSN_LEVELS - 1) e = dalloc(c, &c->dec_a[l], np * C);
+        if (e == hipSuccess && l < DSN_LEVELS - 1) e = dalloc(c, &c->dec_b[l], np * C);
+        if (e == hipSuccess && l < DSN_LEVELS - 1) e = dalloc(c, &c->gcat[l], np * 2 * C);
+        if (e == hipSuccess) e = dalloc(c, &c->gA[l], np * 2 * C);
+        if (e == hipSuccess) e = dalloc(c, &c->gB[l], np * 2 * C);
+    }
+    if (e == hipSuccess) e = dalloc(c, &c->bott, c->np[DSN_LEVELS - 1] * c->C[DSN_LEVELS - 1]);
+    const long long nblk = (c->np[0] + 255) / 256;
+    if (e == hipSuccess) e = dalloc(c, &c->lpart, nblk);
+    if (e == hipSuccess) e = dalloc(c, &c->hpart, nblk * (c->C[0] + 1));
+    if (e == hipSuccess) e = dalloc(c, &c->net_x, c->np[0]);
+    if (e == hipSuccess) e = dalloc(c, &c->net_out, c->np[0]);
+    if (e == hipSuccess) e = hipMemsetAsync(c->p, 0, n * sizeof(float), c->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(c->pb, 0, n * sizeof(__bf16), c->stream);
+    if (e != hipSuccess) {
+        free_all(c);
+        delete c;
+        return fail(e == hipErrorOutOfMemory ? DSN_ENOMEM : DSN_EDEVICE, "dsn_create: %s", hipGetErrorString(e));
+    }
+    *out = c;
+    return DSN_OK;
+}
+
+extern "C" int dsn_destroy(dsn_ctx *c) {
+    if (!c) return fail(DSN_EINVAL, "context is NULL");
+    (void)hipStreamSynchronize(c->stream);
+    free_all(c);
+    delete c;
+    return DSN_OK;
+}
+
+extern "C" long long dsn_num_params(const dsn_ctx *c) { return c ? c->n_params : -1; }
+
+extern "C" int dsn_set_params(dsn_ctx *c, const float *d) {
+    int r;
+    if ((r = check_ctx(c)) || (r = check_ptr(d, "d_params"))) return r;
+    const long long n = c->n_params;
+    HIPCHK(hipMemcpyAsync(c->p, d, n * sizeof(float), hipMemcpyDeviceToDevice, c->stream));
+    k_to_bf16<<<grid1(n), 256, 0, c->stream>>>(c->p, n, c->pb);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemsetAsync(c->m, 0, n * sizeof(float), c->stream));
+    HIPCHK(hipMemsetAsync(c->v, 0, n * sizeof(float), c->stream));
+    c->step = 0;
+    return DSN_OK;
+}
+
+extern "C" int dsn_get_params(const dsn_ctx *c, float *d) {
+    int r;
+    if ((r = check_ctx(c)) || (r = check_ptr(d, "d_params"))) return r;
+    HIPCHK(hipMemcpyAsync(d, c->p, c->n_params * sizeof(float), hipMemcpyDeviceToDevice, c->stream));
+    return DSN_OK;
+}
+
+extern "C" int dsn_forward(dsn_ctx *c, const float *d_x, int B, float *d_out) {
+    int r;
+    if ((r = check_ctx(c)) || (r = check_ptr(d_x, "d_x")) || (r = check_ptr(d_out, "d_out"))) return r;
+    if (B < 1 || B > c->maxB) return fail(DSN_EINVAL, "B must be in [1, %d]", c->maxB);
+    const int NL = DSN_LEVELS;
+    // encoder
+    {
+        const dsn_layer &ly = c->L[enc_a(0)];
+        const long long npix = (long long)B * c->h[0] * c->w[0];
+        k_conv_first<<<grid1(npix * (c->C[0] / 8)), 256, 0, c->stream>>>(
+            d_x, B, c->h[0], c->w[0], c->pb + ly.w_off, c->p + ly.b_off, view(c->act_a[0], c->C[0], c->C[0]));
+        HIPCHK(hipGetLastError());
+    }
+    for (int l = 0; l < NL; ++l) {
+        const int C = c->C[l];
+        if (l > 0) {
+            if ((r = conv(c, view(c->pool[l - 1], c->C[l - 1], c->C[l - 1]), B, l, enc_a(l), false, false, 1,
+                          view(c->act_a[l], C, C))))
+                return r;
+        }
+        View yb = l < NL - 1 ? view(c->cat[l] + C, C, 2 * C) : view(c->bott, C, C);
+        if ((r = conv(c, view(c->act_a[l], C, C), B, l, enc_b(l), false, false, 1, yb))) return r;
+        if (l < NL - 1) {
+            const long long n = (long long)B * c->h[l + 1] * c->w[l + 1] * (C / 8);
+            k_maxpool<<<grid1(n), 256, 0, c->stream>>>(yb, B, c->h[l], c->w[l], view(c->pool[l], C, C));
+            HIPCHK(hipGetLastError());
+        }
+    }
+    // decoder
+    for (int l = NL - 2; l >= 0; --l) {
+        const int C = c->C[l], C1 = c->C[l + 1];
+        View below = l == NL - 2 ? view(c->bott, C1, C1) : view(c->dec_b[l + 1], C1, C1);
+        if ((r = conv(c, below, B, l, dec_up(l), true, false, 1, view(c->cat[l], C, 2 * C)))) return r;
+        if ((r = conv(c, view(c->cat[l], 2 * C, 2 * C), B, l, dec_a_i(l), false, false, 1, view(c->dec_a[l], C, C))))
+            return r;
+        if ((r = conv(c, view(c->dec_a[l], C, C), B, l, dec_b_i(l), false, false, 1, view(c->dec_b[l], C, C))))
+            return r;
+    }
+    const dsn_layer &hd = c->L[head_i()];
+    const long long npix = (long long)B * c->h[0] * c->w[0];
+    k_head<<<grid1(npix), 256, 0, c->stream>>>(view(c->dec_b[0], c->C[0], c->C[0]), npix, c->pb + hd.w_off,
+                                               c->p + hd.b_off, d_out);
+    HIPCHK(hipGetLastError());
+    c->x_in = const_cast<float *>(d_x);
+    c->out = d_out;
+    c->fwdB = B;
+    return DSN_OK;
+}
+
+extern "C" int dsn_backward(dsn_ctx *c, const float *d_target, int B, double *d_loss, float *d_grad) {
+    int r;
+    if ((r = check_ctx(c)) || (r = check_ptr(d_target, "d_target"))) return r;
+    if (!d_loss) return fail(DSN_EINVAL, "d_loss is NULL");
+    if (d_grad && (r = check_ptr(d_grad, "d_grad"))) return r;
+    if (B != c->fwdB || !c->out) return fail(DSN_EINVAL, "backward needs a forward pass with the same batch");
+    const int NL = DSN_LEVELS;
+    // flipped/transposed weights for the input gradients
+    for (size_t i = 0; i + 1 < c->L.size(); ++i) {
+        const dsn_layer &ly = c->L[i];
+        const long long n = (long long)ly.cout * 9 * ly.cin;
+        k_flip_transpose<<<grid1(n), 256, 0, c->stream>>>(c->pb + ly.w_off, ly.cout, ly.cin, c->pt + ly.w_off);
+        HIPCHK(hipGetLastError());
+    }
+    // head and loss
+    const int C0 = c->C[0];
+    const long long np0 = (long long)B * c->h[0] * c->w[0];
+    const dsn_layer &hd = c->L[head_i()];
+    const unsigned nblk = grid1(np0);
+    k_head_bwd<<<nblk, 256, 0, c->stream>>>(view(c->dec_b[0], C0, C0), np0, B, c->pb + hd.w_off, c->out, d_target,
+                                            view(c->gA[0], C0, C0), c->lpart, c->hpart);
+    HIPCHK(hipGetLastError());
+    k_loss_finish<<<1, 256, 0, c->stream>>>(c->lpart, (int)nblk, B, d_loss);
+    HIPCHK(hipGetLastError());
+    // hpart [nblk][C0 + 1] -> weights then bias (contiguous in the flat vector)
+    k_reduce_splits<<<grid1(C0 + 1), 256, 0, c->stream>>>(c->hpart, (int)nblk, C0 + 1, c->grad + hd.w_off);
+    HIPCHK(hipGetLastError());
+    // decoder, bottom-up in the backward order
+    for (int l = 0; l <= NL - 2; ++l) {
+        const int C = c->C[l], C1 = c->C[l + 1];
+        const long long np = (long long)B * c->h[l] * c->w[l];
+        View gy = view(c->gA[l], C, C);                        // d(dec_b output)
+        if ((r = relu_bwd(c, gy, view(c->dec_b[l], C, C), np))) return r;
+        if ((r = wgrad(c, gy, view(c->dec_a[l], C, C), B, l, dec_b_i(l), false))) return r;
+        View ga = view(c->gB[l], C, C);
+        if ((r = conv(c, gy, B, l, dec_b_i(l), false, true, 0, ga))) return r;
+        if ((r = relu_bwd(c, ga, view(c->dec_a[l], C, C), np))) return r;
+        if ((r = wgrad(c, ga, view(c->cat[l], 2 * C, 2 * C), B, l, dec_a_i(l), false))) return r;
+        View gc = view(c->gcat[l], 2 * C, 2 * C);
+        if ((r = conv(c, ga, B, l, dec_a_i(l), false, true, 0, gc))) return r;
+        View gu = view(c->gcat[l], C, 2 * C);                  // d(up-convolution output)
+        if ((r = relu_bwd(c, gu, view(c->cat[l], C, 2 * C), np))) return r;
+        View below = l == NL - 2 ? view(c->bott, C1, C1) : view(c->dec_b[l + 1], C1, C1);
+        if ((r = wgrad(c, gu, below, B, l, dec_up(l), true))) return r;
+        View gfull = view(c->gA[l], C1, C1);                   // gradient of the upsampled input
+        if ((r = conv(c, gu, B, l, dec_up(l), false, true, 0, gfull))) return r;
+        const long long n = (long long)B * c->h[l + 1] * c->w[l + 1] * (C1 / 8);
+        k_upsample_bwd<<<grid1(n), 256, 0, c->stream>>>(gfull, B, c->h[l], c->w[l], view(c->gA[l + 1], C1, C1));
+        HIPCHK(hipGetLastError());
+    }
+    // encoder, top-down
+    for (int l = NL - 1; l >= 0; --l) {
+        const int C = c->C[l];
+        const long long np = (long long)B * c->h[l] * c->w[l];
+        View yb, gyb;
+        if (l == NL - 1) {
+            yb = view(c->bott, C, C);
+            gyb = view(c->gA[l], C, C);
+        } else {
+            yb = view(c->cat[l] + C, C, 2 * C);
+            gyb = view(c->gcat[l] + C, C, 2 * C);
+            // add the pooled path's gradient (held in gA[l + 1]) to the skip's
+            const long long n = (long long)B * c->h[l + 1] * c->w[l + 1] * (C / 8);
+            k_maxpool_bwd<<<grid1(n), 256, 0, c->stream>>>(yb, B, c->h[l], c->w[l], view(c->gA[l + 1], C, C), gyb);
+            HIPCHK(hipGetLastError());
+        }
+        if ((r = relu_bwd(c, gyb, yb, np))) return r;
+        if ((r = wgrad(c, gyb, view(c->act_a[l], C, C), B, l, enc_b(l), false))) return r;
+        View ga = view(c->gB[l], C, C);
+        if ((r = conv(c, gyb, B, l, enc_b(l), false, true, 0, ga))) return r;
+        if ((r = relu_bwd(c, ga, view(c->act_a[l], C, C), np))) return r;
+        if (l > 0) {
+            const int Cp = c->C[l - 1];
+            if ((r = wgrad(c, ga, view(c->pool[l - 1], Cp, Cp), B, l, enc_a(l), false))) return r;
+            // gradient of the pooled input, kept in gA[l] for the level above
+            if ((r = conv(c, ga, B, l, enc_a(l), false, true, 0, view(c->gA[l], Cp, Cp)))) return r;
+        } else {
+            const dsn_layer &ly = c->L[enc_a(0)];
+            const int S = splits_for(np);
+            const long long pps = (np + S - 1) / S;
+            k_wgrad_first<<<S, 256, 0, c->stream>>>(ga, c->x_in, B, c->h[0], c->w[0], pps, c->part);
+            HIPCHK(hipGetLastError());
+            const long long nw = (long long)ly.cout * 9;
+            k_reduce_splits<<<grid1(nw), 256, 0, c->stream>>>(c->part, S, nw, c->grad + ly.w_off);
+            HIPCHK(hipGetLastError());
+            k_reduce_splits<<<grid1(ly.cout), 256, 0, c->stream>>>(c->part + (size_t)S * ly.cout * 9, S, ly.cout,
+                                                                     c->grad + ly.b_off);
+            HIPCHK(hipGetLastError());
+        }
+    }
+    if (d_grad)
+        HIPCHK(hipMemcpyAsync(d_grad, c->grad, c->n_params * sizeof(float), hipMemcpyDeviceToDevice, c->stream));
+    return DSN_OK;
+}
+
+extern "C" int dsn_adam_step(dsn_ctx *c, float lr, float b1, float b2, float eps) {
+    int r;
+    if ((r = check_ctx(c))) return r;
+    if (!(lr >= 0.f) || !(b1 >= 0.f && b1 < 1.f) || !(b2 >= 0.f && b2 < 1.f) || !(eps > 0.f))
+        return fail(DSN_EINVAL, "bad Adam hyperparameters");
+    c->step += 1;
+    const float c1 = 1.f - std::pow(b1, (float)c->step), c2 = 1.f - std::pow(b2, (float)c->step);
+    k_adam<<<grid1(c->n_params), 256, 0, c->stream>>>(c->p, c->m, c->v, c->grad, c->n_params, lr, b1, b2, eps, c1,
+                                                      c2, c->pb);
+    HIPCHK(hipGetLastError());
+    return DSN_OK;
+}
+
+extern "C" int dsn_prepare(dsn_ctx *c, const unsigned char *d_target, const float *d_phi_gt, int B, float *d_x,
+                           float *d_t) {
+    int r;
+    if ((r = check_ctx(c)) || (r = check_ptr(d_target, "d_target")) || (r = check_ptr(d_x, "d_x"))) return r;
+    if (d_phi_gt && ((r = check_ptr(d_phi_gt, "d_phi_gt")) || (r = check_ptr(d_t, "d_t")))) return r;
+    if (B < 1) return fail(DSN_EINVAL, "B must be >= 1");
+    k_prepare<<<grid1((long long)B * c->H * c->W), 256, 0, c->stream>>>(d_target, d_phi_gt, B, c->H, c->W, d_x,
+                                                                        d_t);
+    HIPCHK(hipGetLastError());
+    return DSN_OK;
+}
+
+extern "C" int dsn_predict(dsn_ctx *c, const unsigned char *d_target, int B, float lo, float hi, float *d_phi0) {
+    int r;
+    if ((r = check_ctx(c)) || (r = check_ptr(d_target, "d_target")) || (r = check_ptr(d_phi0, "d_phi0"))) return r;
+    if (B < 1 || B > c->maxB) return fail(DSN_EINVAL, "B must be in [1, %d]", c->maxB);
+    if (!(lo < hi)) return fail(DSN_EINVAL, "d_lower must be below d_upper");
+    if ((r = dsn_prepare(c, d_target, nullptr, B, c->net_x, nullptr))) return r;
+    if ((r = dsn_forward(c, c->net_x, B, c->net_out))) return r;
+    const long long n = (long long)B * 16 * c->H * c->W;
+    k_phi0<<<grid1(n), 256, 0, c->stream>>>(c->net_out, B, c->H, c->W, lo, hi, d_phi0);
+    HIPCHK(hipGetLastError());
+    return DSN_OK;
+}
+
+// ---------------------------------------------------------------- single operations
+
+namespace {
+
+int op_conv(View x, int N, int H, int W, int Cin, bool up, const __bf16 *w, const float *b, int Cout, int relu,
+            View y, hipStream_t st) {
+    const long long npix = (long long)N * H * W;
+    if (Cout % 64 == 0) {
+        dim3 grid(grid1(npix, 64), Cout / 64);
+        if (up) k_conv<2, 2, true><<<grid, 256, 0, st>>>(x, N, H, W, w, Cin, b, relu, y);
+        else k_conv<2, 2, false><<<grid, 256, 0, st>>>(x, N, H, W, w, Cin, b, relu, y);
+    } else {
+        dim3 grid(grid1(npix, 128), Cout / 32);
+        if (up) k_conv<4, 1, true><<<grid, 256, 0, st>>>(x, N, H, W, w, Cin, b, relu, y);
+        else k_conv<4, 1, false><<<grid, 256, 0, st>>>(x, N, H, W, w, Cin, b, relu, y);
+    }
+    HIPCHK(hipGetLastError());
+    return DSN_OK;
+}
+
+int op_check(const void *a, const void *b, int N, int H, int W, int Cin, int Cout, bool up) {
+    if (!a || !b) return fail(DSN_EINVAL, "NULL buffer");
+    if (N < 1 || H < 1 || W < 1) return fail(DSN_EINVAL, "bad N, H, W");
+    if (up && (H % 2 || W % 2)) return fail(DSN_EINVAL, "up needs even H and W");
+    if (Cin % 32 || Cout % 32 || Cin < 32 || Cout < 32 || Cin > 1024 || Cout > 1024)
+        return fail(DSN_EINVAL, "channel counts must be multiples of 32 in [32, 1024]");
+    return DSN_OK;
+}
+
+}  // namespace
+
+extern "C" int dsn_op_conv3x3(const void *d_x, int N, int H, int W, int Cin, int up, const void *d_w,
+                              const float *d_b, int Cout, int relu, void *d_y, void *stream) {
+    int r;
+    if ((r = op_check(d_x, d_w, N, H, W, Cin, Cout, up)) || (r = check_ptr(d_y, "d_y"))) return r;
+    return op_conv(View{(__bf16 *)d_x, Cin, Cin}, N, H, W, Cin, up, (const __bf16 *)d_w, d_b, Cout, relu ? 1 : 0,
+                   View{(__bf16 *)d_y, Cout, Cout}, static_cast<hipStream_t>(stream));
+}
+
+extern "C" int dsn_op_conv3x3_dgrad(const void *d_dy, int N, int H, int W, int Cout, const void *d_w, int Cin,
+                                    void *d_dx, void *stream) {
+    int r;
+    if ((r = op_check(d_dy, d_w, N, H, W, Cin, Cout, false)) || (r = check_ptr(d_dx, "d_dx"))) return r;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    __bf16 *wt = nullptr;
+    const long long n = (long long)Cout * 9 * Cin;
+    HIPCHK(hipMalloc(&wt, n * sizeof(__bf16)));
+    k_flip_transpose<<<grid1(n), 256, 0, st>>>((const __bf16 *)d_w, Cout, Cin, wt);
+    hipError_t e = hipGetLastError();
+    r = e == hipSuccess ? op_conv(View{(__bf16 *)d_dy, Cout, Cout}, N, H, W, Cout, false, wt, nullptr, Cin, 0,
+                                  View{(__bf16 *)d_dx, Cin, Cin}, st)
+                        : fail(DSN_EDEVICE, "k_flip_transpose: %s", hipGetErrorString(e));
+    (void)hipStreamSynchronize(st);
+    (void)hipFree(wt);
+    return r;
+}
+
+extern "C" int dsn_op_conv3x3_wgrad(const void *d_dz, const void *d_x, int N, int H, int W, int Cin, int up,
+                                    int Cout, float *d_dw, float *d_db, void *stream) {
+    int r;
+    if ((r = op_check(d_dz, d_x, N, H, W, Cin, Cout, up)) || (r = check_ptr(d_dw, "d_dw")) ||
+        (r = check_ptr(d_db, "d_db")))
+        return r;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const long long npix = (long long)N * H * W;
+    const int S = splits_for(npix);
+    const long long pps = (npix + S - 1) / S;
+    float *part = nullptr;
+    HIPCHK(hipMalloc(&part, ((size_t)S * Cout * 9 * Cin + (size_t)S * Cout) * sizeof(float)));
+    View dz{(__bf16 *)d_dz, Cout, Cout}, x{(__bf16 *)d_x, Cin, Cin};
+    const int tco = Cout % 64 == 0 ? 64 : 32, tci = Cin % 64 == 0 ? 64 : 32;
+    dim3 grid(Cout / tco, Cin / tci, 9 * S);
+#define WG(A, Bq)                                                                            \
+    if (up) k_wgrad<A, Bq, true><<<grid, 256, 0, st>>>(dz, x, N, H, W, Cin, Cout, pps, part); \
+    else k_wgrad<A, Bq, false><<<grid, 256, 0, st>>>(dz, x, N, H, W, Cin, Cout, pps, part)
+    if (tco == 64 && tci == 64) WG(64, 64);
+    else if (tco == 64) WG(64, 32);
+    else if (tci == 64) WG(32, 64);
+    else WG(32, 32);
+#undef WG
+    hipError_t e = hipGetLastError();
+    const long long nw = (long long)Cout * 9 * Cin;
+    if (e == hipSuccess) {
+        k_reduce_splits<<<grid1(nw), 256, 0, st>>>(part, S, nw, d_dw);
+        k_bias_grad<<<S, 256, 0, st>>>(dz, npix, pps, part);
+        k_reduce_splits<<<grid1(Cout), 256, 0, st>>>(part, S, Cout, d_db);
+        e = hipGetLastError();
+    }
+    (void)hipStreamSynchronize(st);
+    (void)hipFree(part);
+    if (e != hipSuccess) return fail(DSN_EDEVICE, "weight gradient: %s", hipGetErrorString(e));
+    return DSN_OK;
+}

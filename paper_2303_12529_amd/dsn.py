@@ -1,0 +1,238 @@
+"""Python binding of the DevelSet-Net level-set branch (include/dsn.h).
+
+Marshalling only: shapes, dtypes and devices are checked here and every
+computation runs in the HIP kernels of libilt.so (no fallback).
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+
+from . import ilt as _ilt
+
+DSN_OK = 0
+LEVELS = 4
+SCALE = 100.0
+
+_VP = ctypes.c_void_p
+_sigs_done = False
+
+
+def _lib():
+    global _sigs_done
+    lib = _ilt.load_library()
+    if not _sigs_done:
+        sig = {
+            "dsn_create": [ctypes.POINTER(_VP), ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, _VP],
+            "dsn_destroy": [_VP],
+            "dsn_set_params": [_VP, _VP],
+            "dsn_get_params": [_VP, _VP],
+            "dsn_forward": [_VP, _VP, ctypes.c_int, _VP],
+            "dsn_backward": [_VP, _VP, ctypes.c_int, _VP, _VP],
+            "dsn_adam_step": [_VP, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float],
+            "dsn_prepare": [_VP, _VP, _VP, ctypes.c_int, _VP, _VP],
+            "dsn_predict": [_VP, _VP, ctypes.c_int, ctypes.c_float, ctypes.c_float, _VP],
+            "dsn_op_conv3x3": [_VP, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, _VP, _VP,
+                               ctypes.c_int, ctypes.c_int, _VP, _VP],
+            "dsn_op_conv3x3_dgrad": [_VP, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, _VP, ctypes.c_int,
+                                     _VP, _VP],
+            "dsn_op_conv3x3_wgrad": [_VP, _VP, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                     ctypes.c_int, _VP, _VP, _VP],
+        }
+        for name, args in sig.items():
+            fn = getattr(lib, name)
+            fn.argtypes = args
+            fn.restype = ctypes.c_int
+        lib.dsn_num_params.argtypes = [_VP]
+        lib.dsn_num_params.restype = ctypes.c_longlong
+        lib.dsn_last_error.argtypes = []
+        lib.dsn_last_error.restype = ctypes.c_char_p
+        _sigs_done = True
+    return lib
+
+
+class DsnError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("DSN error %d: %s" % (code, msg))
+        self.code = code
+
+
+def _check(rc):
+    if rc != DSN_OK:
+        raise DsnError(rc, _lib().dsn_last_error().decode(errors="replace"))
+
+
+def _ptr(t, dtype, shape, name):
+    import torch
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+        raise TypeError("%s must be a CUDA (HIP) tensor" % name)
+    if t.dtype != dtype:
+        raise TypeError("%s must be %s, got %s" % (name, dtype, t.dtype))
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError("%s must have shape %s, got %s" % (name, tuple(shape), tuple(t.shape)))
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    return _VP(t.data_ptr())
+
+
+def layer_table(base: int = 32):
+    """[(name, weight shape, bias shape, weight offset, bias offset)] in the
+    flat parameter order of include/dsn.h."""
+    ch = [base << i for i in range(LEVELS)]
+    rows = []
+    prev = 1
+    for l in range(LEVELS):
+        rows.append(("enc%d_a" % l, (ch[l], 3, 3, prev)))
+        rows.append(("enc%d_b" % l, (ch[l], 3, 3, ch[l])))
+        prev = ch[l]
+    for l in range(LEVELS - 2, -1, -1):
+        rows.append(("dec%d_up" % l, (ch[l], 3, 3, ch[l + 1])))
+        rows.append(("dec%d_a" % l, (ch[l], 3, 3, 2 * ch[l])))
+        rows.append(("dec%d_b" % l, (ch[l], 3, 3, ch[l])))
+    rows.append(("head", (1, 1, 1, ch[0])))
+    out = []
+    off = 0
+    for name, ws in rows:
+        nw = int(np.prod(ws))
+        out.append((name, ws, (ws[0],), off, off + nw))
+        off += nw + ws[0]
+    return out
+
+
+def he_init(seed: int, base: int = 32) -> np.ndarray:
+    """Flat FP32 parameters: He-normal weights (std sqrt(2 / fan_in)), zero biases."""
+    rng = np.random.default_rng(seed)
+    tab = layer_table(base)
+    n = tab[-1][4] + tab[-1][2][0]
+    flat = np.zeros(n, dtype=np.float32)
+    for name, ws, bs, wo, bo in tab:
+        fan_in = ws[1] * ws[2] * ws[3]
+        flat[wo:bo] = rng.normal(0.0, np.sqrt(2.0 / fan_in), size=int(np.prod(ws))).astype(np.float32)
+    return flat
+
+
+class Net:
+    """The level-set branch on the current device and torch stream."""
+
+    def __init__(self, H: int = 512, W: int = 512, base: int = 32, max_batch: int = 16):
+        import torch
+        lib = _lib()
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        self.stream = torch.cuda.current_stream(self.device)
+        h = _VP()
+        _check(lib.dsn_create(ctypes.byref(h), int(H), int(W), int(base), int(max_batch),
+                              _VP(self.stream.cuda_stream)))
+        self._h = h
+        self.H, self.W, self.base, self.max_batch = int(H), int(W), int(base), int(max_batch)
+        self.n_params = int(lib.dsn_num_params(h))
+        self._keep = None
+        self.loss_buf = torch.zeros(1, dtype=torch.float64, device=self.device)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib().dsn_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, flat):
+        import torch
+        t = torch.as_tensor(flat, dtype=torch.float32).to(self.device).contiguous()
+        _check(_lib().dsn_set_params(self._h, _ptr(t, torch.float32, (self.n_params,), "params")))
+        torch.cuda.current_stream(self.device).synchronize()
+
+    def get_params(self):
+        import torch
+        t = torch.empty(self.n_params, dtype=torch.float32, device=self.device)
+        _check(_lib().dsn_get_params(self._h, _ptr(t, torch.float32, None, "params")))
+        return t
+
+    def forward(self, x, out=None):
+        import torch
+        B = int(x.shape[0])
+        if out is None:
+            out = torch.empty((B, self.H, self.W), dtype=torch.float32, device=self.device)
+        _check(_lib().dsn_forward(self._h, _ptr(x, torch.float32, (B, self.H, self.W), "x"), B,
+                                  _ptr(out, torch.float32, (B, self.H, self.W), "out")))
+        self._keep = (x, out)          # read again by backward
+        return out
+
+    def backward(self, target, grad=None):
+        """Returns the loss tensor (device double[1]); grad: optional FP32 [n_params] out."""
+        import torch
+        B = int(target.shape[0])
+        gp = None if grad is None else _ptr(grad, torch.float32, (self.n_params,), "grad")
+        _check(_lib().dsn_backward(self._h, _ptr(target, torch.float32, (B, self.H, self.W), "target"), B,
+                                   _ptr(self.loss_buf, torch.float64, (1,), "loss"), gp))
+        return self.loss_buf
+
+    def adam_step(self, lr: float, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8):
+        _check(_lib().dsn_adam_step(self._h, float(lr), float(beta1), float(beta2), float(eps)))
+
+    def prepare(self, target, phi_gt=None):
+        import torch
+        B = int(target.shape[0])
+        fine = (B, 4 * self.H, 4 * self.W)
+        x = torch.empty((B, self.H, self.W), dtype=torch.float32, device=self.device)
+        t = None if phi_gt is None else torch.empty_like(x)
+        _check(_lib().dsn_prepare(self._h, _ptr(target, torch.uint8, fine, "target"),
+                                  None if phi_gt is None else _ptr(phi_gt, torch.float32, fine, "phi_gt"), B,
+                                  _ptr(x, torch.float32, None, "x"),
+                                  None if t is None else _ptr(t, torch.float32, None, "t")))
+        return x, t
+
+    def predict(self, target, d_lower: float, d_upper: float, phi0=None):
+        import torch
+        B = int(target.shape[0])
+        fine = (B, 4 * self.H, 4 * self.W)
+        if phi0 is None:
+            phi0 = torch.empty(fine, dtype=torch.float32, device=self.device)
+        _check(_lib().dsn_predict(self._h, _ptr(target, torch.uint8, fine, "target"), B, float(d_lower),
+                                  float(d_upper), _ptr(phi0, torch.float32, fine, "phi0")))
+        return phi0
+
+
+# single operations (BF16 channels-last tensors)
+
+def conv3x3(x, w, b=None, relu=False, up=False):
+    import torch
+    N, Hi, Wi, Cin = x.shape
+    Cout = w.shape[0]
+    H, W = (2 * Hi, 2 * Wi) if up else (Hi, Wi)
+    y = torch.empty((N, H, W, Cout), dtype=torch.bfloat16, device=x.device)
+    _check(_lib().dsn_op_conv3x3(_ptr(x, torch.bfloat16, None, "x"), N, H, W, Cin, 1 if up else 0,
+                                 _ptr(w, torch.bfloat16, (Cout, 3, 3, Cin), "w"),
+                                 None if b is None else _ptr(b, torch.float32, (Cout,), "b"), Cout,
+                                 1 if relu else 0, _ptr(y, torch.bfloat16, None, "y"),
+                                 _VP(torch.cuda.current_stream().cuda_stream)))
+    return y
+
+
+def conv3x3_dgrad(dy, w):
+    import torch
+    N, H, W, Cout = dy.shape
+    Cin = w.shape[3]
+    dx = torch.empty((N, H, W, Cin), dtype=torch.bfloat16, device=dy.device)
+    _check(_lib().dsn_op_conv3x3_dgrad(_ptr(dy, torch.bfloat16, None, "dy"), N, H, W, Cout,
+                                       _ptr(w, torch.bfloat16, (Cout, 3, 3, Cin), "w"), Cin,
+                                       _ptr(dx, torch.bfloat16, None, "dx"),
+                                       _VP(torch.cuda.current_stream().cuda_stream)))
+    return dx
+
+
+def conv3x3_wgrad(dz, x, up=False):
+    import torch
+    N, H, W, Cout = dz.shape
+    Cin = x.shape[3]
+    dw = torch.empty((Cout, 3, 3, Cin), dtype=torch.float32, device=dz.device)
+    db = torch.empty((Cout,), dtype=torch.float32, device=dz.device)
+    _check(_lib().dsn_op_conv3x3_wgrad(_ptr(dz, torch.bfloat16, None, "dz"), _ptr(x, torch.bfloat16, None, "x"),
+                                       N, H, W, Cin, 1 if up else 0, Cout, _ptr(dw, torch.float32, None, "dw"),
+                                       _ptr(db, torch.float32, None, "db"),
+                                       _VP(torch.cuda.current_stream().cuda_stream)))
+    return dw, db

@@ -1,0 +1,219 @@
+"""DevelSet-Net level-set branch on the GPU against the FP64 reference.
+
+* Single operations (3x3 convolution forward with bias/ReLU/upsampled input,
+  input gradient, weight and bias gradients): each GPU result against the
+  FP64 reference evaluated on the same BF16 inputs.  Forward outputs and
+  input gradients are rounded once to BF16 (relative 2^-8); weight
+  gradients are FP32 sums.
+* Whole network: forward output and every layer's gradient against the FP64
+  reference run with the GPU's BF16 weights.  BF16 activations and activation
+  gradients between layers make this a normwise band: measured 1.1e-2 on the
+  output, 0.3-9 % on the layer gradients (largest at the 4 x 4 bottleneck,
+  whose sums have the fewest terms); the bars (4e-2, 0.15) sit above those,
+  while any mis-wired buffer gives an O(1) error.  Each kernel is pinned
+  tightly by the single-operation tests.
+* Adam, the loss reduction, and the resampling between the fine grid and
+  the network grid.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import dsn as ref  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def dsn():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2303_12529_amd import dsn as mod
+    mod._lib()
+    return mod
+
+
+def _bf16(a):
+    return torch.as_tensor(np.asarray(a, dtype=np.float32)).to(torch.bfloat16)
+
+
+def _np(t):
+    return t.float().cpu().numpy().astype(np.float64)
+
+
+CONV_CASES = [
+    # N, H, W, Cin, Cout, up, relu
+    (2, 16, 16, 32, 32, False, True),
+    (1, 8, 12, 64, 32, False, False),
+    (2, 16, 16, 64, 64, True, True),
+    (1, 4, 4, 256, 128, False, True),
+    (1, 10, 6, 32, 64, False, True),      # 60 pixels: ragged tile
+    (3, 6, 10, 128, 256, True, False),
+]
+
+
+@pytest.mark.parametrize("N,H,W,Cin,Cout,up,relu", CONV_CASES)
+def test_conv_forward(dsn, N, H, W, Cin, Cout, up, relu):
+    _say("conv", N, H, W, Cin, Cout, up, relu)
+    rng = np.random.default_rng(N * H + W * Cin + Cout)
+    Hi, Wi = (H // 2, W // 2) if up else (H, W)
+    x = _bf16(rng.normal(size=(N, Hi, Wi, Cin)))
+    w = _bf16(rng.normal(scale=1.0 / np.sqrt(9 * Cin), size=(Cout, 3, 3, Cin)))
+    b = torch.as_tensor(rng.normal(scale=0.1, size=Cout).astype(np.float32))
+    y = dsn.conv3x3(x.cuda(), w.cuda(), b.cuda(), relu=relu, up=up)
+    xr = _np(x)
+    if up:
+        xr = ref.upsample2(xr)
+    yr = ref.conv3x3(xr, _np(w), b.double().numpy())
+    if relu:
+        yr = ref.relu(yr)
+    err = np.abs(_np(y) - yr)
+    bound = 2.0 ** -8 * np.abs(yr) + 1e-5 * np.abs(yr).max()
+    _say("  max err", err.max(), "max |y|", np.abs(yr).max())
+    assert np.all(err <= bound)
+
+
+@pytest.mark.parametrize("N,H,W,Cin,Cout", [(2, 16, 16, 32, 32), (1, 8, 8, 64, 128), (1, 10, 6, 128, 64)])
+def test_conv_input_gradient(dsn, N, H, W, Cin, Cout):
+    rng = np.random.default_rng(7 + Cin)
+    dy = _bf16(rng.normal(size=(N, H, W, Cout)))
+    w = _bf16(rng.normal(scale=0.1, size=(Cout, 3, 3, Cin)))
+    dx = dsn.conv3x3_dgrad(dy.cuda(), w.cuda())
+    dxr, _, _ = ref.conv3x3_backward(np.zeros((N, H, W, Cin)), _np(w), _np(dy))
+    err = np.abs(_np(dx) - dxr)
+    assert np.all(err <= 2.0 ** -8 * np.abs(dxr) + 1e-5 * np.abs(dxr).max())
+
+
+@pytest.mark.parametrize("N,H,W,Cin,Cout,up", [(2, 16, 16, 32, 32, False), (1, 8, 12, 64, 32, False),
+                                               (2, 16, 16, 64, 64, True), (1, 4, 4, 256, 128, False),
+                                               (3, 10, 6, 32, 64, True), (64, 32, 32, 32, 32, False)])
+def test_conv_weight_gradient(dsn, N, H, W, Cin, Cout, up):
+    _say("wgrad", N, H, W, Cin, Cout, up)
+    rng = np.random.default_rng(11 + Cin + Cout + N)
+    Hi, Wi = (H // 2, W // 2) if up else (H, W)
+    x = _bf16(rng.normal(size=(N, Hi, Wi, Cin)))
+    dz = _bf16(rng.normal(size=(N, H, W, Cout)))
+    dw, db = dsn.conv3x3_wgrad(dz.cuda(), x.cuda(), up=up)
+    xr = _np(x)
+    if up:
+        xr = ref.upsample2(xr)
+    _, dwr, dbr = ref.conv3x3_backward(xr, np.zeros((Cout, 3, 3, Cin)), _np(dz))
+    e_w = np.abs(dw.double().cpu().numpy() - dwr).max() / np.abs(dwr).max()
+    e_b = np.abs(db.double().cpu().numpy() - dbr).max() / np.abs(dbr).max()
+    _say("  rel err w", e_w, "b", e_b)
+    assert e_w <= 1e-5 and e_b <= 1e-5
+
+
+def _setup_net(dsn, H=32, W=32, B=2, seed=3):
+    net = dsn.Net(H, W, 32, max_batch=B)
+    flat = dsn.he_init(seed)
+    rng = np.random.default_rng(seed)
+    for name, ws, bs, wo, bo in dsn.layer_table(32):
+        flat[bo:bo + bs[0]] = rng.normal(scale=0.05, size=bs[0]).astype(np.float32)
+    net.set_params(flat)
+    # the reference uses the GPU's working weights (BF16) and FP32 biases
+    params = {}
+    for name, ws, bs, wo, bo in dsn.layer_table(32):
+        w = torch.as_tensor(flat[wo:bo]).to(torch.bfloat16).double().numpy().reshape(ws)
+        params[name] = (w, flat[bo:bo + bs[0]].astype(np.float64))
+    x = rng.integers(0, 17, size=(B, H, W)).astype(np.float32) / 16.0
+    t = rng.normal(scale=0.5, size=(B, H, W)).astype(np.float32)
+    return net, flat, params, x, t
+
+
+def test_network_forward_backward(dsn):
+    net, flat, params, x, t = _setup_net(dsn)
+    xd = torch.as_tensor(x).cuda()
+    td = torch.as_tensor(t).cuda()
+    out = net.forward(xd)
+    grad = torch.empty(net.n_params, dtype=torch.float32, device="cuda")
+    loss = net.backward(td, grad)
+    torch.cuda.synchronize()
+    o = out.double().cpu().numpy()
+    o_ref, cache = ref.forward(params, x[..., None].astype(np.float64))
+    g_ref, _ = ref.backward(params, cache, o_ref, t.astype(np.float64))
+    e_out = np.abs(o - o_ref[..., 0]).max() / np.abs(o_ref).max()
+    l_gpu = float(loss.cpu()[0])
+    _say("forward normwise err", e_out, "loss", l_gpu, ref.loss(o_ref, t))
+    # the loss reduction itself, on the GPU's own output (the GPU forms
+    # out - target in FP32, so each term carries a relative 2^-23)
+    assert abs(l_gpu - ref.loss(o[..., None], t)) <= 2.0 ** -22 * abs(l_gpu)
+    assert e_out <= 4e-2
+    g = grad.double().cpu().numpy()
+    worst = 0.0
+    for name, ws, bs, wo, bo in dsn.layer_table(32):
+        gw, gb = g[wo:bo].reshape(ws), g[bo:bo + bs[0]]
+        rw, rb = g_ref[name]
+        ew = np.abs(gw - rw).max() / max(np.abs(rw).max(), 1e-30)
+        eb = np.abs(gb - rb).max() / max(np.abs(rb).max(), 1e-30)
+        _say("  grad", name, "w", round(ew, 5), "b", round(eb, 5))
+        worst = max(worst, ew, eb)
+    assert worst <= 0.15
+
+
+def test_adam_steps(dsn):
+    net, flat, params, x, t = _setup_net(dsn, seed=5)
+    xd = torch.as_tensor(x).cuda()
+    td = torch.as_tensor(t).cuda()
+    net.forward(xd)
+    grad = torch.empty(net.n_params, dtype=torch.float32, device="cuda")
+    net.backward(td, grad)
+    g = grad.double().cpu().numpy()
+    p = net.get_params().double().cpu().numpy()
+    m = np.zeros_like(p)
+    v = np.zeros_like(p)
+    for step in (1, 2):
+        net.adam_step(1e-3, 0.9, 0.999, 1e-8)
+        p, m, v = ref.adam_step(p, g, m, v, step, 1e-3, 0.9, 0.999, 1e-8)
+        got = net.get_params().double().cpu().numpy()
+        assert np.abs(got - p).max() <= 1e-6
+
+
+def test_resampling_and_predict(dsn):
+    net, flat, params, x, t = _setup_net(dsn, H=16, W=24, B=2, seed=9)
+    rng = np.random.default_rng(2)
+    Z = (rng.uniform(size=(2, 64, 96)) < 0.3).astype(np.uint8)
+    phi = rng.normal(scale=30.0, size=(2, 64, 96)).astype(np.float32)
+    xd, td = net.prepare(torch.as_tensor(Z).cuda(), torch.as_tensor(phi).cuda())
+    for b in range(2):
+        assert np.array_equal(xd[b].cpu().numpy(), ref.net_input(Z[b]).astype(np.float32))
+        np.testing.assert_allclose(td[b].cpu().numpy(), ref.net_target(phi[b].astype(np.float64)), rtol=2e-7,
+                                   atol=1e-9)
+    out = net.forward(xd).double().cpu().numpy()
+    phi0 = net.predict(torch.as_tensor(Z).cuda(), -12.5, 112.5).cpu().numpy()
+    for b in range(2):
+        want = ref.phi0_from_output(out[b], -12.5, 112.5)
+        assert np.abs(phi0[b] - want).max() <= 2e-4
+
+
+def test_training_lowers_the_loss(dsn):
+    net, flat, params, x, t = _setup_net(dsn, B=4, seed=13)
+    xd = torch.as_tensor(x).cuda()
+    td = torch.as_tensor(np.tanh(4 * (x - 0.5)).astype(np.float32)).cuda()
+    losses = []
+    for step in range(40):
+        net.forward(xd)
+        losses.append(float(net.backward(td).cpu()[0]))
+        net.adam_step(2e-3)
+    _say("loss", losses[0], "->", losses[-1])
+    assert losses[-1] < 0.5 * losses[0]
+
+
+def test_bad_arguments(dsn):
+    with pytest.raises(dsn.DsnError):
+        dsn.Net(30, 32, 32, 1)            # not a multiple of 8
+    with pytest.raises(dsn.DsnError):
+        dsn.Net(32, 32, 48, 1)            # base must be 32 or 64
+    net = dsn.Net(16, 16, 32, 1)
+    with pytest.raises(dsn.DsnError):
+        net.backward(torch.zeros((1, 16, 16), device="cuda"))   # no forward yet
+    x = torch.zeros((2, 16, 16), device="cuda")
+    with pytest.raises(dsn.DsnError):
+        net.forward(x)                    # batch above max_batch

@@ -11,18 +11,24 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "ilt.h")
+HEADERS = sorted(os.path.join(ROOT, "include", f) for f in os.listdir(os.path.join(ROOT, "include"))
+                 if f.endswith(".h"))
 
 
 def _declared_functions():
-    src = open(HEADER).read()
-    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(\w+)\s*\(", src, flags=re.M)))
+    names = set()
+    for h in HEADERS:
+        src = re.sub(r"/\*.*?\*/", "", open(h).read(), flags=re.S)
+        names.update(re.findall(r"^\s*(?:const\s+)?(?:long\s+long|unsigned\s+\w+|\w+)\s*\*?\s*(\w+)\s*\(", src,
+                                flags=re.M))
+    return sorted(names)
 
 
 def test_header_declares_the_five_calls():
     names = _declared_functions()
     for n in ("litho_forward", "litho_adjoint", "levelset_step", "edt_reinit", "ilt_solve",
-              "ilt_create", "ilt_destroy", "ilt_last_error", "resist_loss"):
+              "ilt_create", "ilt_destroy", "ilt_last_error", "resist_loss", "ilt_solve_batch", "ilt_autotune",
+              "dsn_create", "dsn_forward", "dsn_backward", "dsn_adam_step", "dsn_predict", "dsn_num_params"):
         assert n in names
 
 
