@@ -170,6 +170,31 @@ def time_to_target(ctxs, workload, seeds, extra_iters=10):
     return out
 
 
+DSN_WEIGHTS = os.path.join(HERE, "paper_2303_12529_amd", "weights", "dsn_c1_fp16.npy")
+
+
+def develset_ttt(seeds):
+    """Time to the plain loop's L2 with the trained network's phi_0 (DevelSet,
+    Sec. III-C) vs from TSDF(target), in both precisions of the loop."""
+    import numpy as np
+    from paper_2303_12529_amd import develset, dsn
+    from paper_2303_12529_amd import ilt
+    if not os.path.exists(DSN_WEIGHTS):
+        return None
+    net = dsn.Net(512, 512, 32, max_batch=1)
+    net.set_params(np.load(DSN_WEIGHTS, allow_pickle=False).astype(np.float32))
+    out = {"weights": os.path.relpath(DSN_WEIGHTS, HERE)}
+    for name, prec in (("fp32", ilt.ILT_FP32), ("bf16x3", ilt.ILT_BF16X3)):
+        ev = develset.evaluate(net, seeds, precision=prec)
+        out[name] = {"median_ms_plain": ev["median_ms_plain"], "median_ms_develset": ev["median_ms_develset"],
+                     "speedup": ev.get("speedup"), "dsn_used": ev["dsn_used"],
+                     "iters_develset": [r["iters_develset"] for r in ev["per_seed"]],
+                     "l2_at_T_plain": [r["l2_at_T_plain"] for r in ev["per_seed"]],
+                     "l2_at_T_develset": [r["l2_at_T_develset"] for r in ev["per_seed"]]}
+    net.close()
+    return out
+
+
 def batched(n_clips, lanes, precision):
     """Batched form on n_clips synthetic clips (N uniform over 512/1024/2048,
     one 2048 nm field): one ilt_solve_batch of the full 50-iteration loop per
@@ -326,6 +351,11 @@ def main():
                 if c is not ctx:
                     c.autotune()
         ttt = time_to_target(ctxs, args.workload, range(args.ttt_seeds))
+        if args.workload == "c1":
+            ttt["develset"] = develset_ttt(range(args.ttt_seeds))
+            if ttt["develset"] and ttt["median_ms"].get("fp32") and ttt["develset"]["bf16x3"]["median_ms_develset"]:
+                ttt["develset_bf16x3_speedup_vs_plain"] = round(
+                    ttt["median_ms"]["fp32"] / ttt["develset"]["bf16x3"]["median_ms_develset"], 3)
 
     bat = None
     if args.batch_clips > 0:
