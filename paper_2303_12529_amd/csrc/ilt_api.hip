@@ -295,7 +295,7 @@ extern "C" int ilt_create(ilt_ctx **out, const ilt_optics *o, int max_batch, voi
     ALLOC(H, H.size());
     ALLOC(coef, coef.size());
     ALLOC(sw, sw.size());
-    ALLOC(Spart, (size_t)(Np / 16) * P * P);
+    ALLOC(Spart, (size_t)(Np / 16) * 4 * P * P);
     const bool b3 = o->precision == ILT_BF16X3;
     if (!b3 && !(o->flags & ILT_FLAG_RECOMPUTE_FIELDS)) ALLOC(Est, (size_t)ns * K * (Np / 16) * (Np / 16) * 512);
     if (b3) {

@@ -76,7 +76,7 @@ struct ilt_ctx {
     __bf16 *Yhl;       // split-BF16 form: window rows [n_sets][K][Np][hi|lo][KP]
 
     // workspaces
-    double2 *Spart;    // spectrum band partials [Np/16][P][P]
+    double2 *Spart;    // spectrum band partials [Np/16][column ranges][P][P]
     float2 *S;         // [P][P]
     float *Est;        // stored fields [n_sets][K][Np/16][Np/16][2][64][4] (null: recompute)
     float *Y;          // [n_sets][K][KP][Np]
@@ -146,6 +146,8 @@ hipError_t launch_split_rows(ilt_ctx *c, int set_lo, int set_hi);
 hipError_t launch_image_b3(ilt_ctx *c, int set_lo, int set_hi, float *out);
 hipError_t launch_adjoint_b3(ilt_ctx *c, const float *G, size_t g_set_stride, int set_lo, int set_hi);
 int adjoint_b3_parts(const ilt_ctx *c, int nsets);
+// column ranges of the spectrum kernel: each wave's share stays a multiple of 16
+inline int spectrum_xsplit(const ilt_ctx *c) { return c->Np >= 512 ? 4 : c->Np / 128; }
 int adjoint_b3_max_parts(const ilt_ctx *c, int nsets);
 #define ILT_B3_MAX_XSPLIT 4
 

@@ -30,7 +30,8 @@ __device__ __forceinline__ float wave_max(float v) {
 }
 
 // --------------------------------------------------------------------------
-// Spectrum.  Block = one 16-row band, 8 waves splitting the columns:
+// Spectrum.  Block = one 16-row band x one of gridDim.y column ranges, 8
+// waves splitting the range:
 //   T1[y][n] = sum_x M[y][x] tb0[x][n]        (matrix cores; M = [phi<=0] or src)
 //   Spart[band][a][b] = sum_{y in band} A[a][y] T1[y][b]   (FP64)
 // Each lane loads four consecutive columns of its row as one float4 and uses
@@ -48,8 +49,8 @@ __global__ __launch_bounds__(512) void k_spectrum_band(const float *__restrict__
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int l16 = lane & 15, lq = lane >> 4;
     const int y0 = blockIdx.x * 16;
-    const int span = Np / 8;
-    const int xa = wave * span;
+    const int span = Np / (8 * gridDim.y);
+    const int xa = blockIdx.y * (Np / gridDim.y) + wave * span;
     f4 acc[NB];
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) acc[nb] = f4{0.f, 0.f, 0.f, 0.f};
@@ -105,21 +106,21 @@ __global__ __launch_bounds__(512) void k_spectrum_band(const float *__restrict__
             sr += c * tr - s * ti;
             si += c * ti + s * tr;
         }
-        Spart[(size_t)blockIdx.x * P * P + e] = make_double2(sr, si);
+        Spart[((size_t)blockIdx.x * gridDim.y + blockIdx.y) * P * P + e] = make_double2(sr, si);
     }
 }
 
 // Deterministic sum of n complex partial arrays: out[e] = sum_p part[p][e].
-// Block = 64 outputs x 16 partial groups; groups combined in a fixed order.
+// Block = 16 outputs x 64 partial groups; groups combined in a fixed order.
 template <typename T2>
 __global__ __launch_bounds__(1024) void k_psum(const T2 *__restrict__ part, int nparts, int n,
                                                float2 *__restrict__ out) {
-    __shared__ double sr[16][64], si[16][64];
-    const int o = threadIdx.x & 63, g = threadIdx.x >> 6;
-    const int e = blockIdx.x * 64 + o;
+    __shared__ double sr[64][17], si[64][17];
+    const int o = threadIdx.x & 15, g = threadIdx.x >> 4;
+    const int e = blockIdx.x * 16 + o;
     double r = 0.0, i = 0.0;
     if (e < n)
-        for (int p = g; p < nparts; p += 16) {
+        for (int p = g; p < nparts; p += 64) {
             const T2 v = part[(size_t)p * n + e];
             r += (double)v.x;
             i += (double)v.y;
@@ -129,8 +130,7 @@ __global__ __launch_bounds__(1024) void k_psum(const T2 *__restrict__ part, int 
     __syncthreads();
     if (g == 0 && e < n) {
         double a = 0.0, b = 0.0;
-#pragma unroll
-        for (int q = 0; q < 16; ++q) {
+        for (int q = 0; q < 64; ++q) {
             a += sr[q][o];
             b += si[q][o];
         }
@@ -141,26 +141,31 @@ __global__ __launch_bounds__(1024) void k_psum(const T2 *__restrict__ part, int 
 // --------------------------------------------------------------------------
 // Window -> rows: out[j][r][x] = scale_j * sum_b U_j[a][b] conj(A[b][x]),
 // U_j = H_j . S (or U = S when H is null); rows r = a (real), P + a (imag).
-// Grid (Np/64, n_j, n_sets); 64 columns x 4 row groups per block; each
-// thread keeps the twiddles of its column in registers.
+// Grid (Np/COLS, ceil(n_j/JB), n_sets); COLS columns x 256/COLS row groups
+// per block, JB kernels per block; each thread keeps the twiddles of its
+// column in registers and reuses them for the block's JB kernels.
 // --------------------------------------------------------------------------
+template <int COLS, int JB>
 __global__ __launch_bounds__(256) void k_window_rows(const float2 *__restrict__ H, const float2 *__restrict__ S,
                                                      const float *__restrict__ scale, float scale_c,
                                                      const float *__restrict__ ar, const float *__restrict__ ai,
                                                      int P, int KP, int Np, int nj, int set_lo,
                                                      float *__restrict__ out) {
-    __shared__ float2 U[ILT_MAX_P * ILT_MAX_P];
-    const int j = blockIdx.y, s = set_lo + blockIdx.z;
-    const int x = blockIdx.x * 64 + (threadIdx.x & 63);
-    const int ag = threadIdx.x >> 6;
-    for (int e = threadIdx.x; e < P * P; e += 256) {
-        float2 u = S[e];
-        if (H) {
-            const float2 h = H[((size_t)s * nj + j) * P * P + e];
-            u = make_float2(h.x * u.x - h.y * u.y, h.x * u.y + h.y * u.x);
+    constexpr int RG = 256 / COLS;
+    __shared__ float2 U[JB][ILT_MAX_P * ILT_MAX_P];
+    const int j0 = blockIdx.y * JB, s = set_lo + blockIdx.z;
+    const int x = blockIdx.x * COLS + (threadIdx.x % COLS);
+    const int ag = threadIdx.x / COLS;
+    const int jn = min(JB, nj - j0);
+    for (int jj = 0; jj < jn; ++jj)
+        for (int e = threadIdx.x; e < P * P; e += 256) {
+            float2 u = S[e];
+            if (H) {
+                const float2 h = H[((size_t)s * nj + j0 + jj) * P * P + e];
+                u = make_float2(h.x * u.x - h.y * u.y, h.x * u.y + h.y * u.x);
+            }
+            U[jj][e] = u;
         }
-        U[e] = u;
-    }
     float cr[ILT_MAX_P], ci[ILT_MAX_P];
 #pragma unroll
     for (int b = 0; b < ILT_MAX_P; ++b) {
@@ -168,21 +173,24 @@ __global__ __launch_bounds__(256) void k_window_rows(const float2 *__restrict__ 
         ci[b] = b < P ? ai[(size_t)b * Np + x] : 0.f;
     }
     __syncthreads();
-    const float sc = scale ? scale[(size_t)s * nj + j] : scale_c;
-    float *o = out + ((size_t)(s * nj + j) * KP) * Np;
-    for (int a = ag; a < P; a += 4) {
-        float yr = 0.f, yi = 0.f;
+    for (int jj = 0; jj < jn; ++jj) {
+        const int j = j0 + jj;
+        const float sc = scale ? scale[(size_t)s * nj + j] : scale_c;
+        float *o = out + ((size_t)(s * nj + j) * KP) * Np;
+        for (int a = ag; a < P; a += RG) {
+            float yr = 0.f, yi = 0.f;
 #pragma unroll
-        for (int b = 0; b < ILT_MAX_P; ++b) {
-            if (b < P) {
-                const float2 u = U[a * P + b];
-                // u * conj(A) = (ur + i ui)(c - i sn)
-                yr = fmaf(u.x, cr[b], fmaf(u.y, ci[b], yr));
-                yi = fmaf(u.y, cr[b], fmaf(-u.x, ci[b], yi));
+            for (int b = 0; b < ILT_MAX_P; ++b) {
+                if (b < P) {
+                    const float2 u = U[jj][a * P + b];
+                    // u * conj(A) = (ur + i ui)(c - i sn)
+                    yr = fmaf(u.x, cr[b], fmaf(u.y, ci[b], yr));
+                    yi = fmaf(u.y, cr[b], fmaf(-u.x, ci[b], yi));
+                }
             }
+            o[(size_t)a * Np + x] = sc * yr;
+            o[(size_t)(P + a) * Np + x] = sc * yi;
         }
-        o[(size_t)a * Np + x] = sc * yr;
-        o[(size_t)(P + a) * Np + x] = sc * yi;
     }
 }
 
@@ -521,9 +529,10 @@ __global__ __launch_bounds__(256, 2) void k_adjoint_rc(const float *__restrict__
 
 hipError_t launch_spectrum(ilt_ctx *c, const float *src, int src_is_phi) {
     const int nband = c->Np / 16;
-#define SPEC(FB_, MIX_)                                                                                          \
-    k_spectrum_band<FB_, MIX_><<<nband, 512, 0, c->stream>>>(src, src_is_phi, c->tb, c->ar, c->ai, c->P, c->N, \
-                                                             c->Np, c->Spart)
+    const int xs = spectrum_xsplit(c);
+#define SPEC(FB_, MIX_)                                                                                         \
+    k_spectrum_band<FB_, MIX_><<<dim3(nband, xs), 512, 0, c->stream>>>(src, src_is_phi, c->tb, c->ar, c->ai,   \
+                                                                      c->P, c->N, c->Np, c->Spart)
     if (c->FB == 0 && c->MIX == 1) SPEC(0, 1);
     else if (c->FB == 1 && c->MIX == 0) SPEC(1, 0);
     else if (c->FB == 1 && c->MIX == 1) SPEC(1, 1);
@@ -532,14 +541,14 @@ hipError_t launch_spectrum(ilt_ctx *c, const float *src, int src_is_phi) {
     else return hipErrorInvalidValue;
 #undef SPEC
     const int n = c->P * c->P;
-    k_psum<double2><<<(n + 63) / 64, 1024, 0, c->stream>>>(c->Spart, nband, n, c->S);
+    k_psum<double2><<<(n + 15) / 16, 1024, 0, c->stream>>>(c->Spart, nband * xs, n, c->S);
     return hipGetLastError();
 }
 
 hipError_t launch_make_Y(ilt_ctx *c, int set_lo, int set_hi) {
-    dim3 grid(c->Np / 64, c->K, set_hi - set_lo);
-    k_window_rows<<<grid, 256, 0, c->stream>>>(c->H, c->S, c->sw, 1.f, c->ar, c->ai, c->P, c->KP, c->Np, c->K,
-                                               set_lo, c->Y);
+    dim3 grid(c->Np / 64, (c->K + 3) / 4, set_hi - set_lo);
+    k_window_rows<64, 4><<<grid, 256, 0, c->stream>>>(c->H, c->S, c->sw, 1.f, c->ar, c->ai, c->P, c->KP, c->Np,
+                                                      c->K, set_lo, c->Y);
     return hipGetLastError();
 }
 
@@ -599,16 +608,17 @@ hipError_t launch_window_sum(ilt_ctx *c, int set_lo, int set_hi) {
     const int nparts = c->precision == ILT_BF16X3 ? adjoint_b3_parts(c, set_hi - set_lo)
                                                   : (set_hi - set_lo) * ((c->N + 31) / 32) * ((c->K + 3) / 4);
     const int n = c->P * c->P;
-    k_psum<float2><<<(n + 63) / 64, 1024, 0, c->stream>>>(reinterpret_cast<const float2 *>(c->Wpart), nparts, n,
+    k_psum<float2><<<(n + 15) / 16, 1024, 0, c->stream>>>(reinterpret_cast<const float2 *>(c->Wpart), nparts, n,
                                                          c->W);
     return hipGetLastError();
 }
 
 hipError_t launch_gradient(ilt_ctx *c, float *g_out, double *maxpart) {
     // Tg = 2 W conj(A) in the row layout, then g = Re(A^H Tg)
-    dim3 grid(c->Np / 64, 1, 1);
-    k_window_rows<<<grid, 256, 0, c->stream>>>(nullptr, c->W, nullptr, 2.f, c->ar, c->ai, c->P, c->KP, c->Np, 1, 0,
-                                               c->Tg);
+    // one transform only: narrow column tiles so that the launch covers the chip
+    dim3 grid(c->Np / 16, 1, 1);
+    k_window_rows<16, 1><<<grid, 256, 0, c->stream>>>(nullptr, c->W, nullptr, 2.f, c->ar, c->ai, c->P, c->KP, c->Np,
+                                                      1, 0, c->Tg);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     return image_dispatch<1, false>(c, c->Tg, 1, 0, 1, g_out, maxpart);

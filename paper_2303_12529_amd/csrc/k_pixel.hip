@@ -41,39 +41,105 @@ __device__ __forceinline__ double block_max(double v, double *sh) {
 // binary print (Sec. II-B) for L2 (corner 0) and PVBand (corners 1, 2).
 // Block b covers a contiguous pixel range; partials {loss, l2, pvb, nonfinite}.
 // --------------------------------------------------------------------------
-__global__ __launch_bounds__(RB) void k_resist(const float *__restrict__ I, size_t set_stride,
+// One pixel of the resist: loss, G contributions and the print decisions.
+__device__ __forceinline__ void resist_pixel(const resist_args &ra, float zt, const float (&ii)[ILT_MAX_SETS],
+                                             float (&gs)[ILT_MAX_SETS], double &loss, double &l2, double &pvb,
+                                             double &bad) {
+    float lp = 0.f;
+    bool print[4] = {false, false, false, false};
+#pragma unroll
+    for (int q = 0; q < ILT_MAX_SETS; ++q) gs[q] = 0.f;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        if (c < ra.n_corners) {
+            const int s = ra.cset[c];
+            const float d = ra.dose[c];
+            float iv = 0.f;
+#pragma unroll
+            for (int q = 0; q < ILT_MAX_SETS; ++q)
+                if (q == s) iv = ii[q];
+            const float di = d * iv;
+            const float z = 1.f / (1.f + expf(-ra.sigma_z * (di - ra.i_th)));
+            const float r = z - zt;
+            lp = fmaf(ra.omega[c] * r, r, lp);
+            const float gv = ra.omega[c] * 2.f * ra.sigma_z * d * r * (z * (1.f - z));
+#pragma unroll
+            for (int q = 0; q < ILT_MAX_SETS; ++q)
+                if (q == s) gs[q] += gv;
+            print[c] = di >= ra.i_th;
+        }
+    }
+    loss += (double)lp;
+    if (!isfinite(lp)) bad += 1.0;
+    l2 += (print[0] != (zt != 0.f)) ? 1.0 : 0.0;
+    if (ra.n_corners >= 3) pvb += (print[1] != print[2]) ? 1.0 : 0.0;
+}
+
+// Four consecutive pixels per thread and step (16-byte loads and stores);
+// block b covers quads [b chunk, (b + 1) chunk).  Needs npix % 4 == 0 (every
+// set's image then starts 16-byte aligned).
+__global__ __launch_bounds__(RB) void k_resist4(const float *__restrict__ I, size_t set_stride,
                                                const uint8_t *__restrict__ target, resist_args ra,
                                                size_t npix, size_t chunk, float *__restrict__ G,
                                                double *__restrict__ part) {
+    __shared__ double sh[RB];
+    const size_t nq = npix / 4;
+    const size_t lo = (size_t)blockIdx.x * chunk;
+    const size_t hi = min(nq, lo + chunk);
+    double loss = 0.0, l2 = 0.0, pvb = 0.0, bad = 0.0;
+    for (size_t q4 = lo + threadIdx.x; q4 < hi; q4 += RB) {
+        const size_t p = 4 * q4;
+        const uchar4 t4 = *reinterpret_cast<const uchar4 *>(target + p);
+        float4 iv[ILT_MAX_SETS];
+#pragma unroll
+        for (int q = 0; q < ILT_MAX_SETS; ++q)
+            iv[q] = ra.set_used[q] ? *reinterpret_cast<const float4 *>(I + (size_t)q * set_stride + p)
+                                   : make_float4(0.f, 0.f, 0.f, 0.f);
+        float g4[ILT_MAX_SETS][4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const unsigned char tb = e == 0 ? t4.x : e == 1 ? t4.y : e == 2 ? t4.z : t4.w;
+            float ii[ILT_MAX_SETS], gs[ILT_MAX_SETS];
+#pragma unroll
+            for (int q = 0; q < ILT_MAX_SETS; ++q)
+                ii[q] = e == 0 ? iv[q].x : e == 1 ? iv[q].y : e == 2 ? iv[q].z : iv[q].w;
+            resist_pixel(ra, tb ? 1.f : 0.f, ii, gs, loss, l2, pvb, bad);
+#pragma unroll
+            for (int q = 0; q < ILT_MAX_SETS; ++q) g4[q][e] = gs[q];
+        }
+#pragma unroll
+        for (int q = 0; q < ILT_MAX_SETS; ++q)
+            if (ra.set_used[q])
+                *reinterpret_cast<float4 *>(G + (size_t)q * set_stride + p) =
+                    make_float4(g4[q][0], g4[q][1], g4[q][2], g4[q][3]);
+    }
+    loss = block_sum(loss, sh);
+    l2 = block_sum(l2, sh);
+    pvb = block_sum(pvb, sh);
+    bad = block_sum(bad, sh);
+    if (threadIdx.x == 0) {
+        part[blockIdx.x * 4 + 0] = loss;
+        part[blockIdx.x * 4 + 1] = l2;
+        part[blockIdx.x * 4 + 2] = pvb;
+        part[blockIdx.x * 4 + 3] = bad;
+    }
+}
+
+// Any npix: one pixel per thread and step; block b covers pixels
+// [b chunk, (b + 1) chunk).
+__global__ __launch_bounds__(RB) void k_resist1(const float *__restrict__ I, size_t set_stride,
+                                                const uint8_t *__restrict__ target, resist_args ra,
+                                                size_t npix, size_t chunk, float *__restrict__ G,
+                                                double *__restrict__ part) {
     __shared__ double sh[RB];
     const size_t lo = (size_t)blockIdx.x * chunk;
     const size_t hi = min(npix, lo + chunk);
     double loss = 0.0, l2 = 0.0, pvb = 0.0, bad = 0.0;
     for (size_t p = lo + threadIdx.x; p < hi; p += RB) {
-        const float zt = target[p] ? 1.f : 0.f;
-        float gs[ILT_MAX_SETS] = {0.f, 0.f, 0.f, 0.f};
-        float lp = 0.f;
-        bool print[4] = {false, false, false, false};
+        float ii[ILT_MAX_SETS], gs[ILT_MAX_SETS];
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            if (c < ra.n_corners) {
-                const int s = ra.cset[c];
-                const float d = ra.dose[c];
-                const float di = d * I[(size_t)s * set_stride + p];
-                const float z = 1.f / (1.f + expf(-ra.sigma_z * (di - ra.i_th)));
-                const float r = z - zt;
-                lp = fmaf(ra.omega[c] * r, r, lp);
-                const float gv = ra.omega[c] * 2.f * ra.sigma_z * d * r * (z * (1.f - z));
-#pragma unroll
-                for (int q = 0; q < ILT_MAX_SETS; ++q)
-                    if (q == s) gs[q] += gv;
-                print[c] = di >= ra.i_th;
-            }
-        }
-        loss += (double)lp;
-        if (!isfinite(lp)) bad += 1.0;
-        l2 += (print[0] != (zt != 0.f)) ? 1.0 : 0.0;
-        if (ra.n_corners >= 3) pvb += (print[1] != print[2]) ? 1.0 : 0.0;
+        for (int q = 0; q < ILT_MAX_SETS; ++q) ii[q] = ra.set_used[q] ? I[(size_t)q * set_stride + p] : 0.f;
+        resist_pixel(ra, target[p] ? 1.f : 0.f, ii, gs, loss, l2, pvb, bad);
 #pragma unroll
         for (int q = 0; q < ILT_MAX_SETS; ++q)
             if (ra.set_used[q]) G[(size_t)q * set_stride + p] = gs[q];
@@ -156,7 +222,7 @@ __global__ __launch_bounds__(256) void k_levelset(const float *__restrict__ phi,
                                                   const double *__restrict__ scal, int N,
                                                   float *__restrict__ out, double *__restrict__ part) {
     __shared__ float t[34][35];
-    __shared__ double sh[RB];
+    __shared__ int wsum[4];
     const int bx = blockIdx.x * 32, by = blockIdx.y * 32;
     for (int e = threadIdx.x; e < 34 * 34; e += 256) {
         const int yy = e / 34, xx = e % 34;
@@ -167,7 +233,7 @@ __global__ __launch_bounds__(256) void k_levelset(const float *__restrict__ phi,
     __syncthreads();
     const float dt = (float)scal[SC_DT];
     const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
-    double flips = 0.0;
+    int flips = 0;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
         const int ly = ty + 8 * j + 1, lx = tx + 1;
@@ -190,11 +256,16 @@ __global__ __launch_bounds__(256) void k_levelset(const float *__restrict__ phi,
             const float m = mod ? mod[p] : 1.f;
             const float nv = c + dt * (vel[p] * sqrtf(g2) + lam * m * kap);
             out[p] = nv;
-            flips += ((nv <= 0.f) != (c <= 0.f)) ? 1.0 : 0.0;
+            flips += ((nv <= 0.f) != (c <= 0.f)) ? 1 : 0;
         }
     }
-    flips = block_sum(flips, sh);
-    if (threadIdx.x == 0) part[blockIdx.y * gridDim.x + blockIdx.x] = flips;
+    // integer count: wave sums, then the four waves in order
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) flips += __shfl_xor(flips, o);
+    if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = flips;
+    __syncthreads();
+    if (threadIdx.x == 0)
+        part[blockIdx.y * gridDim.x + blockIdx.x] = (double)(wsum[0] + wsum[1] + wsum[2] + wsum[3]);
 }
 
 __global__ __launch_bounds__(RB) void k_finish_step(const double *__restrict__ part, int nblk,
@@ -561,7 +632,11 @@ hipError_t launch_resist(ilt_ctx *c, const float *I, const uint8_t *target, cons
                          double *part) {
     const size_t npix = (size_t)c->N * c->N;
     const int nblk = resist_blocks(c);
-    k_resist<<<nblk, RB, 0, c->stream>>>(I, npix, target, ra, npix, chunk_of(npix, nblk), G, part);
+    if (npix % 4 == 0 && reinterpret_cast<uintptr_t>(I) % 16 == 0 && reinterpret_cast<uintptr_t>(G) % 16 == 0 &&
+        reinterpret_cast<uintptr_t>(target) % 4 == 0)
+        k_resist4<<<nblk, RB, 0, c->stream>>>(I, npix, target, ra, npix, chunk_of(npix / 4, nblk), G, part);
+    else
+        k_resist1<<<nblk, RB, 0, c->stream>>>(I, npix, target, ra, npix, chunk_of(npix, nblk), G, part);
     return hipGetLastError();
 }
 
