@@ -100,6 +100,56 @@ def issued_bf16_flops(N, P, K, n_sets, phase):
     return None
 
 
+def gwindow_work(N, P, K, n_sets):
+    """Algorithmic flops of one iteration with the G-window adjoint: the
+    adjoint becomes one pruned (2P-1)^2 transform of G per set plus the
+    window correlation."""
+    Q = 2 * P - 1
+    N2 = float(N) * N
+    w = algorithmic_work(N, P, K, n_sets)
+    w["adjoint"] = dict(flops=n_sets * (4.0 * Q * N2 + 8.0 * Q * Q * N) + n_sets * K * 8.0 * P ** 4)
+    return w
+
+
+def gwindow_forms(Z, H, w, N, prm, steps, autotune):
+    """The loop with the G-window adjoint, in both precisions (its own cost
+    model, so its own figures)."""
+    import torch
+    from paper_2303_12529_amd import ilt
+    n_sets, K, P, _ = H.shape
+    target = torch.as_tensor(Z).to("cuda")
+    out = {"note": "adjoint by the G-window identity (exact): one (2P-1)^2 pruned transform of G per set "
+                   "plus a window correlation, instead of K field transforms; no field store"}
+    work = gwindow_work(N, P, K, n_sets)
+    total = sum(v.get("flops", 0.0) for v in work.values())
+    for name, prec in (("fp32", ilt.ILT_FP32), ("bf16x3", ilt.ILT_BF16X3)):
+        ctx = ilt.Context(H, w, N, precision=prec, flags=ilt.ILT_FLAG_GWINDOW_ADJOINT)
+        if autotune:
+            ctx.autotune()
+        phi = torch.empty((N, N), dtype=torch.float32, device="cuda")
+        ctx.ilt_solve(target, phi, ilt.Params.from_dict(prm, iters=5, init_mode=0))
+        p = ilt.Params.from_dict(prm, iters=steps, init_mode=1)
+        start = phi.clone()
+        ctx.ilt_solve(target, phi, p)
+        phi.copy_(start)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rep = ctx.ilt_solve(target, phi, p)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        phi.copy_(start)
+        ctx.profile(True)
+        ctx.ilt_solve(target, phi, p)
+        prof = ctx.profile_read()
+        ctx.profile(False)
+        out[name] = {"value": round(steps / wall, 3), "unit": "it/s", "ms_per_step": round(1e3 * wall / steps, 4),
+                     "algorithmic_tflops": round(total * steps / wall / 1e12, 2),
+                     "phases_ms_per_step": {k: round(v[0] / steps, 4) for k, v in prof.items()},
+                     "final_l2": rep["l2"]}
+        ctx.close()
+    return out
+
+
 def cpu_baseline(workload, seed, iters):
     """Time the FP64 oracle on `iters` iterations of the same workload."""
     import numpy as np
@@ -247,6 +297,7 @@ def main():
                     help="keep the default launch settings instead of timing the tuning candidates first")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="first copy 256 MiB device to device (the reference kernel for scaling HBM counters)")
+    ap.add_argument("--no-gwindow", action="store_true", help="skip the G-window adjoint line")
     ap.add_argument("--batch-clips", type=int, default=64,
                     help="clips in the batched-form measurement (0: skip)")
     ap.add_argument("--batch-lanes", type=int, default=4)
@@ -357,6 +408,10 @@ def main():
                 ttt["develset_bf16x3_speedup_vs_plain"] = round(
                     ttt["median_ms"]["fp32"] / ttt["develset"]["bf16x3"]["median_ms_develset"], 3)
 
+    gw = None
+    if not args.no_gwindow:
+        gw = gwindow_forms(Z, H, w, N, prm, args.steps, not args.no_autotune)
+
     bat = None
     if args.batch_clips > 0:
         bat = batched(args.batch_clips, args.batch_lanes, prec)
@@ -397,6 +452,7 @@ def main():
                   "l2_first": int(tr[0, 2]), "l2_last_iter": int(tr[-1, 2])},
         "tuning": tuning if tuning is not None else ctx.get_tuning(),
         "time_to_target": ttt,
+        "gwindow_adjoint": gw,
         "batched": bat,
     }
     print(json.dumps(line), flush=True)

@@ -63,7 +63,15 @@ enum {
      * during the forward pass.  Storing needs n_sets * K * N^2 * 8 bytes of
      * device memory (1.6 GB at N = 2048, K = 24, two sets) and halves the
      * adjoint's matrix-core work; recomputing needs no such workspace. */
-    ILT_FLAG_RECOMPUTE_FIELDS = 1
+    ILT_FLAG_RECOMPUTE_FIELDS = 1,
+    /* Compute the adjoint through the G-window identity (the same W, exact
+     * up to rounding): the DFT of G at the (2P-1)^2 difference frequencies,
+     * then V_k(f') = N^-4 sum_f U_k(f) Ghat(f' - f) over the window and
+     * W = sum_k w_k conj(H_k) V_k.  One pruned transform of G per kernel set
+     * replaces the K adjoint field transforms, and no fields are stored or
+     * recomputed.  Implies no field store (ILT_FLAG_RECOMPUTE_FIELDS is
+     * then irrelevant). */
+    ILT_FLAG_GWINDOW_ADJOINT = 2
 };
 
 /* Optical model, read at create time and copied to the device. */

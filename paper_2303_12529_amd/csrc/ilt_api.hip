@@ -99,7 +99,8 @@ void free_ctx(ilt_ctx *c) {
     free_graph(c);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     void *ptrs[] = {c->tl, c->tb, c->ta4, c->ar, c->ai, c->H, c->sw, c->coef, c->tlhl, c->tbhl, c->Yhl, c->Spart, c->S, c->Est, c->Y, c->Tg,
-                    c->I, c->G, c->g, c->phi2, c->Wpart, c->W, c->edtg, c->colbits, c->part, c->scal};
+                    c->I, c->G, c->g, c->phi2, c->Wpart, c->W, c->edtg, c->colbits, c->part, c->scal,
+                    c->tbQ, c->arQ, c->aiQ, c->Ghat, c->Vpart};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     delete c;
@@ -220,7 +221,8 @@ extern "C" int ilt_create(ilt_ctx **out, const ilt_optics *o, int max_batch, voi
     if (ns < 1 || ns > ILT_MAX_SETS) return fail(ILT_EINVAL, "n_sets=%d outside [1, %d]", ns, ILT_MAX_SETS);
     if (o->precision != ILT_FP32 && o->precision != ILT_BF16X3)
         return fail(ILT_EUNSUPPORTED, "precision %d not built", o->precision);
-    if (o->flags & ~ILT_FLAG_RECOMPUTE_FIELDS) return fail(ILT_EINVAL, "unknown flags 0x%x", o->flags);
+    if (o->flags & ~(ILT_FLAG_RECOMPUTE_FIELDS | ILT_FLAG_GWINDOW_ADJOINT))
+        return fail(ILT_EINVAL, "unknown flags 0x%x", o->flags);
     if (!o->h_kernels || !o->h_weights) return fail(ILT_EINVAL, "kernels or weights are null");
     for (int i = 0; i < ns * K; ++i)
         if (!(o->h_weights[i] >= 0.0) || !std::isfinite(o->h_weights[i]))
@@ -238,6 +240,12 @@ extern "C" int ilt_create(ilt_ctx **out, const ilt_optics *o, int max_batch, voi
     if ((P % 16) > 8) c->FB += 1;
     c->NZ = 32 * c->FB + 16 * c->MIX;
     c->AP = round_up(P, 16);
+    c->gwin = (o->flags & ILT_FLAG_GWINDOW_ADJOINT) ? 1 : 0;
+    c->Q = 2 * P - 1;
+    c->FBQ = c->Q / 16;
+    c->MIXQ = (c->Q % 16) != 0 && (c->Q % 16) <= 8;
+    if ((c->Q % 16) > 8) c->FBQ += 1;
+    c->NZQ = 32 * c->FBQ + 16 * c->MIXQ;
     c->stream = static_cast<hipStream_t>(stream);
     if (hipGetDevice(&c->device) != hipSuccess) { free_ctx(c); return fail(ILT_EDEVICE, "hipGetDevice failed"); }
     const int Np = c->Np, KP = c->KP, NZ = c->NZ, FB = c->FB, AP = c->AP;
@@ -295,9 +303,36 @@ extern "C" int ilt_create(ilt_ctx **out, const ilt_optics *o, int max_batch, voi
     ALLOC(H, H.size());
     ALLOC(coef, coef.size());
     ALLOC(sw, sw.size());
-    ALLOC(Spart, (size_t)(Np / 16) * 4 * P * P);
+    ALLOC(Spart, (size_t)(Np / 16) * 4 * (c->gwin ? c->Q * c->Q : P * P));
     const bool b3 = o->precision == ILT_BF16X3;
-    if (!b3 && !(o->flags & ILT_FLAG_RECOMPUTE_FIELDS)) ALLOC(Est, (size_t)ns * K * (Np / 16) * (Np / 16) * 512);
+    if (!b3 && !c->gwin && !(o->flags & ILT_FLAG_RECOMPUTE_FIELDS))
+        ALLOC(Est, (size_t)ns * K * (Np / 16) * (Np / 16) * 512);
+    std::vector<float> tbQ, arQ, aiQ;
+    if (c->gwin) {
+        // tables of the difference window: f_a = a - (P - 1), a in [0, Q)
+        const int Q = c->Q, NZQ = c->NZQ, FBQ = c->FBQ;
+        tbQ.assign((size_t)Np * NZQ, 0.f);
+        arQ.assign((size_t)Q * Np, 0.f);
+        aiQ.assign((size_t)Q * Np, 0.f);
+        for (int a = 0; a < Q; ++a) {
+            const long long f = a - (P - 1);
+            for (int x = 0; x < N; ++x) {
+                long long ph = (f * x) % N;
+                if (ph < 0) ph += N;
+                const double ang = -2.0 * M_PI * (double)ph / (double)N;
+                const float cr = (float)std::cos(ang), sn = (float)std::sin(ang);
+                arQ[(size_t)a * Np + x] = cr;
+                aiQ[(size_t)a * Np + x] = sn;
+                tbQ[(size_t)x * NZQ + win_re(a, FBQ)] = cr;
+                tbQ[(size_t)x * NZQ + win_im(a, FBQ)] = sn;
+            }
+        }
+        ALLOC(tbQ, tbQ.size());
+        ALLOC(arQ, arQ.size());
+        ALLOC(aiQ, aiQ.size());
+        ALLOC(Ghat, (size_t)ns * Q * Q);
+        ALLOC(Vpart, (size_t)ns * K * P * P);
+    }
     if (b3) {
         ALLOC(tlhl, (size_t)2 * Np * 2 * KP);
         ALLOC(tbhl, (size_t)2 * 2 * NZ * Np);
@@ -332,6 +367,11 @@ extern "C" int ilt_create(ilt_ctx **out, const ilt_optics *o, int max_batch, voi
     if (e == hipSuccess) e = hipMemcpy(c->H, H.data(), H.size() * 8, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(c->coef, coef.data(), coef.size() * 8, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(c->sw, sw.data(), sw.size() * 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess && c->gwin) {
+        e = hipMemcpy(c->tbQ, tbQ.data(), tbQ.size() * 4, hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(c->arQ, arQ.data(), arQ.size() * 4, hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(c->aiQ, aiQ.data(), aiQ.size() * 4, hipMemcpyHostToDevice);
+    }
     if (e == hipSuccess && b3) {
         std::vector<uint16_t> lh((size_t)2 * Np * 2 * KP), bh((size_t)2 * 2 * NZ * Np);
         for (int part = 0; part < 2; ++part)
@@ -416,15 +456,18 @@ extern "C" int litho_adjoint(ilt_ctx *c, const float *d_mask, const float *d_G, 
     if (set < 0 || set >= c->n_sets) return fail(ILT_EINVAL, "set %d outside [0, %d)", set, c->n_sets);
     HIPCHK(launch_spectrum(c, d_mask, 0));
     HIPCHK(launch_make_Y(c, set, set + 1));
-    if (c->precision == ILT_BF16X3) {
+    if (c->gwin) {
+        HIPCHK(launch_adjoint_gwindow(c, d_G, 0, set, set + 1));
+    } else if (c->precision == ILT_BF16X3) {
         HIPCHK(launch_split_rows(c, set, set + 1));
         HIPCHK(launch_adjoint_b3(c, d_G, 0, set, set + 1));
+        HIPCHK(launch_window_sum(c, set, set + 1));
     } else {
         const int stored = c->Est != nullptr && c->store_fields;
         if (stored) HIPCHK(launch_image_to(c, set, set + 1, c->I + (size_t)set * c->N * c->N, 1));
         HIPCHK(launch_adjoint(c, d_G, 0, set, set + 1, stored));
+        HIPCHK(launch_window_sum(c, set, set + 1));
     }
-    HIPCHK(launch_window_sum(c, set, set + 1));
     HIPCHK(launch_gradient(c, d_out, c->part + part_max_off(c)));
     return ILT_OK;
 }
@@ -521,12 +564,13 @@ int enqueue_solve(ilt_ctx *c, const unsigned char *d_target, float *d_phi, const
         }
         {
             PhaseTimer t(c, 4);
-            if (b3) HIPCHK(launch_adjoint_b3(c, c->G, npix, slo, shi));
+            if (c->gwin) HIPCHK(launch_adjoint_gwindow(c, c->G, npix, slo, shi));
+            else if (b3) HIPCHK(launch_adjoint_b3(c, c->G, npix, slo, shi));
             else HIPCHK(launch_adjoint(c, c->G, npix, slo, shi, stored));
         }
         {
             PhaseTimer t(c, 5);
-            HIPCHK(launch_window_sum(c, slo, shi));
+            if (!c->gwin) HIPCHK(launch_window_sum(c, slo, shi));
             HIPCHK(launch_gradient(c, c->g, pm));
             HIPCHK(launch_finish_dt(c, pm, (int)n_image_blocks(c), p->dt_mode, p->eta, p->dt_max, c->scal));
         }

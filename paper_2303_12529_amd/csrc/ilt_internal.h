@@ -74,9 +74,15 @@ struct ilt_ctx {
     __bf16 *tlhl;      // split-BF16 form: L operands [2][Np][hi|lo][KP]
     __bf16 *tbhl;      // split-BF16 form: B3 in fragment order [Np/32][2][NZ/16][hi|lo][64][8]
     __bf16 *Yhl;       // split-BF16 form: window rows [n_sets][K][Np][hi|lo][KP]
+    // G-window adjoint (ILT_FLAG_GWINDOW_ADJOINT): difference window Q = 2P - 1
+    int gwin, Q, FBQ, MIXQ, NZQ;
+    float *tbQ;        // [Np][NZQ] window columns of the difference window
+    float *arQ, *aiQ;  // [Q][Np]
+    float2 *Ghat;      // [n_sets][Q][Q]
+    double2 *Vpart;    // [n_sets][K][P][P]
 
     // workspaces
-    double2 *Spart;    // spectrum band partials [Np/16][column ranges][P][P]
+    double2 *Spart;    // spectrum band partials [Np/16][column ranges][P][P] (or [Q][Q])
     float2 *S;         // [P][P]
     float *Est;        // stored fields [n_sets][K][Np/16][Np/16][2][64][4] (null: recompute)
     float *Y;          // [n_sets][K][KP][Np]
@@ -145,6 +151,8 @@ hipError_t launch_gradient(ilt_ctx *c, float *g_out, double *maxpart);
 hipError_t launch_split_rows(ilt_ctx *c, int set_lo, int set_hi);
 hipError_t launch_image_b3(ilt_ctx *c, int set_lo, int set_hi, float *out);
 hipError_t launch_adjoint_b3(ilt_ctx *c, const float *G, size_t g_set_stride, int set_lo, int set_hi);
+// G-window adjoint: W for sets [set_lo, set_hi) directly (no window_sum)
+hipError_t launch_adjoint_gwindow(ilt_ctx *c, const float *G, size_t g_set_stride, int set_lo, int set_hi);
 int adjoint_b3_parts(const ilt_ctx *c, int nsets);
 // column ranges of the spectrum kernel: each wave's share stays a multiple of 16
 inline int spectrum_xsplit(const ilt_ctx *c) { return c->Np >= 512 ? 4 : c->Np / 128; }

@@ -523,26 +523,77 @@ __global__ __launch_bounds__(256, 2) void k_adjoint_rc(const float *__restrict__
     ilt_dev::adjoint_tail<FB, MIX>(accZ, jok, j, s, K, P, Np, AP, y0, ta4, coef, Ws, dst);
 }
 
+// --------------------------------------------------------------------------
+// G-window adjoint (exact): with U_k = H_k . S on the window and Ghat the
+// DFT of G at the difference frequencies D in [-(P-1), P-1]^2,
+//   V_k(f') = sum_f U_k(f) Ghat(f' - f),
+//   Vpart[set][k][f'] = (w_k / N^4) conj(H_k(f')) V_k(f')      (FP64),
+// and W = sum over (set, k) of Vpart (fixed order).  Thread = (f', k, set).
+// --------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_gwindow_V(const float2 *__restrict__ H, const float2 *__restrict__ S,
+                                                   const float2 *__restrict__ Ghat, const float *__restrict__ sw,
+                                                   int P, int K, int set_lo, double2 *__restrict__ Vpart) {
+    __shared__ double2 U[ILT_MAX_P * ILT_MAX_P];
+    const int k = blockIdx.y, srel = blockIdx.z, s = set_lo + srel;
+    const int Q = 2 * P - 1;
+    const float2 *Hk = H + ((size_t)s * K + k) * P * P;
+    for (int e = threadIdx.x; e < P * P; e += 256) {
+        const double hr = Hk[e].x, hi = Hk[e].y, sr = S[e].x, si = S[e].y;
+        U[e] = make_double2(hr * sr - hi * si, hr * si + hi * sr);
+    }
+    __syncthreads();
+    const int fp = blockIdx.x * 256 + threadIdx.x;
+    if (fp >= P * P) return;
+    const int a2 = fp / P, b2 = fp % P;
+    const float2 *G = Ghat + (size_t)s * Q * Q;
+    double vr = 0.0, vi = 0.0;
+    for (int a = 0; a < P; ++a) {
+        const float2 *grow = G + (size_t)(a2 - a + P - 1) * Q + (b2 + P - 1);
+        for (int b = 0; b < P; ++b) {
+            const double2 u = U[a * P + b];
+            const float2 g = grow[-b];
+            vr += u.x * g.x - u.y * g.y;
+            vi += u.x * g.y + u.y * g.x;
+        }
+    }
+    const double sc = (double)sw[(size_t)s * K + k] * (double)sw[(size_t)s * K + k];
+    const double hr = Hk[fp].x, hi = -(double)Hk[fp].y;    // conj(H_k(f'))
+    Vpart[(((size_t)srel * K + k) * P * P) + fp] = make_double2(sc * (hr * vr - hi * vi), sc * (hr * vi + hi * vr));
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------- launchers
 
-hipError_t launch_spectrum(ilt_ctx *c, const float *src, int src_is_phi) {
+// Pruned spectrum of src (or of [src <= 0]) on a window of side Pw with the
+// given column tables, summed into out [Pw][Pw].
+static hipError_t spectrum_to(ilt_ctx *c, const float *src, int src_is_phi, int FBw, int MIXw, const float *tbw,
+                              const float *arw, const float *aiw, int Pw, float2 *out) {
     const int nband = c->Np / 16;
     const int xs = spectrum_xsplit(c);
 #define SPEC(FB_, MIX_)                                                                                         \
-    k_spectrum_band<FB_, MIX_><<<dim3(nband, xs), 512, 0, c->stream>>>(src, src_is_phi, c->tb, c->ar, c->ai,   \
-                                                                      c->P, c->N, c->Np, c->Spart)
-    if (c->FB == 0 && c->MIX == 1) SPEC(0, 1);
-    else if (c->FB == 1 && c->MIX == 0) SPEC(1, 0);
-    else if (c->FB == 1 && c->MIX == 1) SPEC(1, 1);
-    else if (c->FB == 2 && c->MIX == 0) SPEC(2, 0);
-    else if (c->FB == 2 && c->MIX == 1) SPEC(2, 1);
+    k_spectrum_band<FB_, MIX_><<<dim3(nband, xs), 512, 0, c->stream>>>(src, src_is_phi, tbw, arw, aiw, Pw, c->N, \
+                                                                      c->Np, c->Spart)
+    if (FBw == 0 && MIXw == 1) SPEC(0, 1);
+    else if (FBw == 1 && MIXw == 0) SPEC(1, 0);
+    else if (FBw == 1 && MIXw == 1) SPEC(1, 1);
+    else if (FBw == 2 && MIXw == 0) SPEC(2, 0);
+    else if (FBw == 2 && MIXw == 1) SPEC(2, 1);
+    else if (FBw == 3 && MIXw == 0) SPEC(3, 0);
+    else if (FBw == 3 && MIXw == 1) SPEC(3, 1);
+    else if (FBw == 4 && MIXw == 0) SPEC(4, 0);
+    else if (FBw == 4 && MIXw == 1) SPEC(4, 1);
     else return hipErrorInvalidValue;
 #undef SPEC
-    const int n = c->P * c->P;
-    k_psum<double2><<<(n + 15) / 16, 1024, 0, c->stream>>>(c->Spart, nband * xs, n, c->S);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int n = Pw * Pw;
+    k_psum<double2><<<(n + 15) / 16, 1024, 0, c->stream>>>(c->Spart, nband * xs, n, out);
     return hipGetLastError();
+}
+
+hipError_t launch_spectrum(ilt_ctx *c, const float *src, int src_is_phi) {
+    return spectrum_to(c, src, src_is_phi, c->FB, c->MIX, c->tb, c->ar, c->ai, c->P, c->S);
 }
 
 hipError_t launch_make_Y(ilt_ctx *c, int set_lo, int set_hi) {
@@ -622,4 +673,21 @@ hipError_t launch_gradient(ilt_ctx *c, float *g_out, double *maxpart) {
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     return image_dispatch<1, false>(c, c->Tg, 1, 0, 1, g_out, maxpart);
+}
+
+hipError_t launch_adjoint_gwindow(ilt_ctx *c, const float *G, size_t g_set_stride, int set_lo, int set_hi) {
+    if (!c->gwin) return hipErrorInvalidValue;
+    const int Q = c->Q;
+    for (int s = set_lo; s < set_hi; ++s) {
+        hipError_t e = spectrum_to(c, G + (size_t)s * g_set_stride, 0, c->FBQ, c->MIXQ, c->tbQ, c->arQ, c->aiQ, Q,
+                                   c->Ghat + (size_t)s * Q * Q);
+        if (e != hipSuccess) return e;
+    }
+    const int n = c->P * c->P;
+    dim3 grid((n + 255) / 256, c->K, set_hi - set_lo);
+    k_gwindow_V<<<grid, 256, 0, c->stream>>>(c->H, c->S, c->Ghat, c->sw, c->P, c->K, set_lo, c->Vpart);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    k_psum<double2><<<(n + 15) / 16, 1024, 0, c->stream>>>(c->Vpart, (set_hi - set_lo) * c->K, n, c->W);
+    return hipGetLastError();
 }

@@ -21,6 +21,7 @@ ILT_OK, ILT_EINVAL, ILT_ENOMEM, ILT_EDEVICE, ILT_ENUMERIC, ILT_EUNSUPPORTED = 0,
 ILT_FP32 = 0
 ILT_BF16X3 = 1
 ILT_FLAG_RECOMPUTE_FIELDS = 1
+ILT_FLAG_GWINDOW_ADJOINT = 2
 TRACE_W = 8
 TRACE_COLUMNS = ("i", "loss", "l2", "pvb", "flips", "max_g", "dt", "t_ns")
 PHASES = ("spectrum", "window_rows", "image", "resist", "adjoint", "gradient", "levelset_step", "reinit")

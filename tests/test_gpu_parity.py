@@ -117,7 +117,7 @@ ADJ_CASES = [(64, 3, 2), (96, 7, 3), (64, 9, 4), (100, 9, 5), (128, 15, 4), (160
              (67, 9, 3), (150, 35, 5)]   # N % 4 != 0: scalar edge paths
 
 
-@pytest.mark.parametrize("flags", [0, 1, "bf16x3"])
+@pytest.mark.parametrize("flags", [0, 1, 2, "bf16x3"])
 @pytest.mark.parametrize("N,P,K", ADJ_CASES)
 def test_litho_adjoint_parity(ilt, N, P, K, flags):
     _say("adjoint", N, P, K, flags)
