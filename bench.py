@@ -298,6 +298,9 @@ def main():
     ap.add_argument("--traffic-probe", action="store_true",
                     help="first copy 256 MiB device to device (the reference kernel for scaling HBM counters)")
     ap.add_argument("--no-gwindow", action="store_true", help="skip the G-window adjoint line")
+    ap.add_argument("--adjoint", choices=("fields", "gwindow"), default="fields",
+                    help="adjoint of the timed loop: through the K fields (the paper's form, default) or the "
+                         "G-window identity")
     ap.add_argument("--batch-clips", type=int, default=64,
                     help="clips in the batched-form measurement (0: skip)")
     ap.add_argument("--batch-lanes", type=int, default=4)
@@ -325,7 +328,8 @@ def main():
         torch.cuda.synchronize()
         del a, b
     prec = ilt.ILT_BF16X3 if args.precision == "bf16x3" else ilt.ILT_FP32
-    ctx = ilt.Context(H, w, N, precision=prec)
+    flags = ilt.ILT_FLAG_GWINDOW_ADJOINT if args.adjoint == "gwindow" else 0
+    ctx = ilt.Context(H, w, N, precision=prec, flags=flags)
     tuning = None if args.no_autotune else ctx.autotune()
     target = torch.as_tensor(Z).to("cuda")
     phi = torch.empty((N, N), dtype=torch.float32, device="cuda")
@@ -360,7 +364,7 @@ def main():
 
     ms_per_step = 1e3 * wall / args.steps
     value = args.steps / wall
-    work = algorithmic_work(N, P, K, n_sets)
+    work = gwindow_work(N, P, K, n_sets) if args.adjoint == "gwindow" else algorithmic_work(N, P, K, n_sets)
     phase_ms = {k: v[0] for k, v in prof.items()}
     dominant = max(phase_ms, key=lambda k: phase_ms[k])
     launches = prof[dominant][1]
@@ -440,6 +444,7 @@ def main():
                             args.workload, N, N, desc["optics"]["pitch_nm"], K, P, P, n_sets,
                             len(prm["corners"]), prm["reinit_every"]),
             "N": N, "P": P, "K": K, "n_sets": n_sets, "corners": len(prm["corners"]), "seed": args.seed,
+            "adjoint": args.adjoint,
         },
         "roofline": roof,
         "cpu_baseline": cpu,

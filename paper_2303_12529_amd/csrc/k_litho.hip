@@ -45,7 +45,9 @@ __global__ __launch_bounds__(512) void k_spectrum_band(const float *__restrict__
                                                        int Np, double2 *__restrict__ Spart) {
     constexpr int NZ = 32 * FB + 16 * MIX;
     constexpr int NB = NZ / 16;
+    constexpr int PW = (NZ + 1) / 2 + 8;          // >= the window side of this layout
     __shared__ float red[8][16][NZ + 1];
+    __shared__ float twr[PW][17], twi[PW][17];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int l16 = lane & 15, lq = lane >> 4;
     const int y0 = blockIdx.x * 16;
@@ -94,14 +96,21 @@ __global__ __launch_bounds__(512) void k_spectrum_band(const float *__restrict__
         red[0][r][n] = s;
     }
     __syncthreads();
+    // the band's 16 twiddle columns of every window row, once per block
+    for (int e = threadIdx.x; e < P * 16; e += 512) {
+        const int a = e / 16, r = e % 16;
+        const int yy = min(y0 + r, N - 1);
+        twr[a][r] = ar[(size_t)a * Np + yy];
+        twi[a][r] = ai[(size_t)a * Np + yy];
+    }
+    __syncthreads();
+    const int rows = min(16, N - y0);
     // band partial of S = A T1, complex, FP64
     for (int e = threadIdx.x; e < P * P; e += 512) {
         const int a = e / P, b = e % P;
         double sr = 0.0, si = 0.0;
-        for (int r = 0; r < 16; ++r) {
-            const int yy = y0 + r;
-            if (yy >= N) break;
-            const double c = ar[(size_t)a * Np + yy], s = ai[(size_t)a * Np + yy];
+        for (int r = 0; r < rows; ++r) {
+            const double c = twr[a][r], s = twi[a][r];
             const double tr = red[0][r][win_re(b, FB)], ti = red[0][r][win_im(b, FB)];
             sr += c * tr - s * ti;
             si += c * ti + s * tr;
@@ -533,7 +542,10 @@ __global__ __launch_bounds__(256, 2) void k_adjoint_rc(const float *__restrict__
 __global__ __launch_bounds__(256) void k_gwindow_V(const float2 *__restrict__ H, const float2 *__restrict__ S,
                                                    const float2 *__restrict__ Ghat, const float *__restrict__ sw,
                                                    int P, int K, int set_lo, double2 *__restrict__ Vpart) {
+    constexpr int QM = 2 * ILT_MAX_P - 1;
     __shared__ double2 U[ILT_MAX_P * ILT_MAX_P];
+    __shared__ float2 Gs[QM * QM];
+    __shared__ double2 part[4][64];
     const int k = blockIdx.y, srel = blockIdx.z, s = set_lo + srel;
     const int Q = 2 * P - 1;
     const float2 *Hk = H + ((size_t)s * K + k) * P * P;
@@ -541,21 +553,31 @@ __global__ __launch_bounds__(256) void k_gwindow_V(const float2 *__restrict__ H,
         const double hr = Hk[e].x, hi = Hk[e].y, sr = S[e].x, si = S[e].y;
         U[e] = make_double2(hr * sr - hi * si, hr * si + hi * sr);
     }
-    __syncthreads();
-    const int fp = blockIdx.x * 256 + threadIdx.x;
-    if (fp >= P * P) return;
-    const int a2 = fp / P, b2 = fp % P;
     const float2 *G = Ghat + (size_t)s * Q * Q;
+    for (int e = threadIdx.x; e < Q * Q; e += 256) Gs[e] = G[e];
+    __syncthreads();
+    // thread = (output f' of the block's 64, quarter q of the rows a)
+    const int o = threadIdx.x & 63, q = threadIdx.x >> 6;
+    const int fp = blockIdx.x * 64 + o;
     double vr = 0.0, vi = 0.0;
-    for (int a = 0; a < P; ++a) {
-        const float2 *grow = G + (size_t)(a2 - a + P - 1) * Q + (b2 + P - 1);
-        for (int b = 0; b < P; ++b) {
-            const double2 u = U[a * P + b];
-            const float2 g = grow[-b];
-            vr += u.x * g.x - u.y * g.y;
-            vi += u.x * g.y + u.y * g.x;
+    if (fp < P * P) {
+        const int a2 = fp / P, b2 = fp % P;
+        for (int a = q; a < P; a += 4) {
+            const float2 *grow = Gs + (a2 - a + P - 1) * Q + (b2 + P - 1);
+            const double2 *urow = U + a * P;
+            for (int b = 0; b < P; ++b) {
+                const double2 u = urow[b];
+                const float2 g = grow[-b];
+                vr += u.x * g.x - u.y * g.y;
+                vi += u.x * g.y + u.y * g.x;
+            }
         }
     }
+    part[q][o] = make_double2(vr, vi);
+    __syncthreads();
+    if (q != 0 || fp >= P * P) return;
+    vr = ((part[0][o].x + part[1][o].x) + part[2][o].x) + part[3][o].x;
+    vi = ((part[0][o].y + part[1][o].y) + part[2][o].y) + part[3][o].y;
     const double sc = (double)sw[(size_t)s * K + k] * (double)sw[(size_t)s * K + k];
     const double hr = Hk[fp].x, hi = -(double)Hk[fp].y;    // conj(H_k(f'))
     Vpart[(((size_t)srel * K + k) * P * P) + fp] = make_double2(sc * (hr * vr - hi * vi), sc * (hr * vi + hi * vr));
@@ -597,8 +619,8 @@ hipError_t launch_spectrum(ilt_ctx *c, const float *src, int src_is_phi) {
 }
 
 hipError_t launch_make_Y(ilt_ctx *c, int set_lo, int set_hi) {
-    dim3 grid(c->Np / 64, (c->K + 3) / 4, set_hi - set_lo);
-    k_window_rows<64, 4><<<grid, 256, 0, c->stream>>>(c->H, c->S, c->sw, 1.f, c->ar, c->ai, c->P, c->KP, c->Np,
+    dim3 grid(c->Np / 64, c->K, set_hi - set_lo);
+    k_window_rows<64, 1><<<grid, 256, 0, c->stream>>>(c->H, c->S, c->sw, 1.f, c->ar, c->ai, c->P, c->KP, c->Np,
                                                       c->K, set_lo, c->Y);
     return hipGetLastError();
 }
@@ -684,7 +706,7 @@ hipError_t launch_adjoint_gwindow(ilt_ctx *c, const float *G, size_t g_set_strid
         if (e != hipSuccess) return e;
     }
     const int n = c->P * c->P;
-    dim3 grid((n + 255) / 256, c->K, set_hi - set_lo);
+    dim3 grid((n + 63) / 64, c->K, set_hi - set_lo);
     k_gwindow_V<<<grid, 256, 0, c->stream>>>(c->H, c->S, c->Ghat, c->sw, c->P, c->K, set_lo, c->Vpart);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
