@@ -92,3 +92,27 @@ def levelset_step(phi, g, mod, eta: float, lam: float, eps_kappa: float,
     new = phi + dt * (g * gn + lam * m * K)
     flips = int(np.sum((new <= 0) != (phi <= 0)))
     return new, dt, m_v, flips
+
+
+def cg_direction(g, state):
+    """Polak-Ribiere conjugate direction with the non-negative restart (PR+).
+
+    The paper optimises DSO with conjugate gradient (Sec. III-C) without
+    naming the variant.  With g the descent velocity of this step (the same
+    field plain DSO would use) and the previous step's g and direction kept
+    in `state`:
+        beta = max(0, <g, g - g_prev> / <g_prev, g_prev>),   d = g + beta d_prev,
+    and beta = 0 on the first step.  Inner products in FP64.  Returns (d, beta)
+    and updates `state` in place.
+    """
+    g = np.asarray(g, dtype=np.float64)
+    gp = state.get("g_prev")
+    beta = 0.0
+    if gp is not None:
+        den = float(np.sum(gp * gp))
+        if den > 0.0:
+            beta = max(0.0, float(np.sum(g * (g - gp))) / den)
+    d = g if gp is None else g + beta * state["d_prev"]
+    state["g_prev"] = g.copy()
+    state["d_prev"] = d.copy()
+    return d, beta

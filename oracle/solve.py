@@ -29,10 +29,13 @@ def forward_all(M, kernels, weights, corners):
     return I
 
 
-def iteration(phi, target, kernels, weights, params):
+def iteration(phi, target, kernels, weights, params, state=None):
     """One DSO iteration before re-initialisation.
 
-    Returns (phi', row) with row = dict(loss, l2, pvb, flips, m_v, dt).
+    params["optimizer"] = 1 moves phi along the conjugate direction of
+    levelset.cg_direction (Sec. III-C) instead of the gradient itself; its
+    state (previous gradient and direction) lives in `state` across calls.
+    Returns (phi', row) with row = dict(loss, l2, pvb, flips, m_v, dt, beta).
     """
     corners = params["corners"]
     M = levelset.mask_from_phi(phi)
@@ -42,10 +45,13 @@ def iteration(phi, target, kernels, weights, params):
     g = np.zeros(phi.shape)
     for s in sets_used(corners):
         g += litho.litho_adjoint(M, G[s], kernels[s], weights[s])
+    beta = 0.0
+    if params.get("optimizer", 0) == 1:
+        g, beta = levelset.cg_direction(g, state if state is not None else {})
     new, dt, m_v, flips = levelset.levelset_step(
         phi, g, None, params["eta"], params["lam"], params["eps_kappa"],
         params.get("dt_mode", 0), params.get("dt_max", 0.0))
-    return new, dict(loss=L, l2=l2, pvb=pvb, flips=flips, m_v=m_v, dt=dt)
+    return new, dict(loss=L, l2=l2, pvb=pvb, flips=flips, m_v=m_v, dt=dt, beta=beta)
 
 
 def ilt_solve(target, kernels, weights, params, phi0=None):
@@ -59,9 +65,10 @@ def ilt_solve(target, kernels, weights, params, phi0=None):
     else:
         phi = np.asarray(phi0, dtype=np.float64).copy()
     trace = []
+    state = {}
     R = int(params.get("reinit_every", 0))
     for i in range(int(params["iters"])):
-        phi, row = iteration(phi, target, kernels, weights, params)
+        phi, row = iteration(phi, target, kernels, weights, params, state)
         if R > 0 and (i + 1) % R == 0:
             phi, _, _ = edt.tsdf_from_phi(phi, params["d_lower"], params["d_upper"])
         row["i"] = i

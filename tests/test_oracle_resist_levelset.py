@@ -156,3 +156,43 @@ def test_cfl_dt_rules():
     assert levelset.cfl_dt(g, 0.1, 1, 0.0) == (0.1, 2.0)
     assert levelset.cfl_dt(np.zeros((2, 2)), 0.85, 0, 5.0) == (5.0, 0.0)
     assert levelset.cfl_dt(np.zeros((2, 2)), 0.85, 0, 0.0) == (0.0, 0.0)
+
+
+def test_cg_direction_recurrence_and_restart():
+    from oracle import levelset as ls
+    st = {}
+    d, b = ls.cg_direction(np.array([1.0, 0.0]), st)
+    assert b == 0.0 and np.array_equal(d, [1.0, 0.0])
+    st["d_prev"] = np.array([2.0, 0.0])
+    d, b = ls.cg_direction(np.array([1.0, 1.0]), st)
+    # <g, g - g_prev> = <(1,1), (0,1)> = 1, <g_prev, g_prev> = 1
+    assert b == 1.0 and np.array_equal(d, [3.0, 1.0])
+    # a negative Polak-Ribiere coefficient restarts along the gradient
+    # <(0.5, 0.5), (0.5, 0.5) - (1, 1)> = -0.5 < 0
+    d, b = ls.cg_direction(np.array([0.5, 0.5]), st)
+    assert b == 0.0 and np.array_equal(d, [0.5, 0.5])
+
+
+def test_cg_direction_solves_a_quadratic_in_n_steps():
+    """With exact line searches, PR conjugate gradient minimises a strictly
+    convex n-dimensional quadratic in n steps (textbook property)."""
+    from oracle import levelset as ls
+    rng = np.random.default_rng(3)
+    n = 6
+    Q = rng.normal(size=(n, n))
+    A = Q @ Q.T + n * np.eye(n)
+    b = rng.normal(size=n)
+    x = np.zeros(n)
+    st = {}
+    for _ in range(n):
+        g = b - A @ x                  # descent velocity: minus the gradient
+        d, _ = ls.cg_direction(g, st)
+        alpha = float(g @ d) / float(d @ A @ d)
+        x = x + alpha * d
+    assert np.linalg.norm(A @ x - b) <= 1e-9 * np.linalg.norm(b)
+    # plain steepest descent with the same line searches does not get there
+    x = np.zeros(n)
+    for _ in range(n):
+        g = b - A @ x
+        x = x + float(g @ g) / float(g @ A @ g) * g
+    assert np.linalg.norm(A @ x - b) > 1e-6 * np.linalg.norm(b)
