@@ -190,10 +190,11 @@ def time_to_target(ctxs, workload, seeds, extra_iters=10):
         phi = torch.empty((N, N), dtype=torch.float32, device="cuda")
         target_l2 = ctxs["fp32"].ilt_solve(tgt, phi, ilt.Params.from_dict(prm, iters=T, init_mode=0))["l2"]
         row = {"seed": seed, "target_l2": int(target_l2)}
-        for name, ctx in ctxs.items():
+        forms = [(name, ctx, 0) for name, ctx in ctxs.items()] + [("fp32_cg", ctxs["fp32"], 1)]
+        for name, ctx, opt in forms:
             tmax = T + extra_iters
             tr = torch.zeros((tmax, ilt.TRACE_W), dtype=torch.float64, device="cuda")
-            ctx.ilt_solve(tgt, phi, ilt.Params.from_dict(prm, iters=tmax, init_mode=0), trace=tr)
+            ctx.ilt_solve(tgt, phi, ilt.Params.from_dict(prm, iters=tmax, init_mode=0, optimizer=opt), trace=tr)
             l2 = tr[:, 2].cpu().numpy()
             hits = np.nonzero(l2 <= target_l2)[0]
             hits = hits[hits > 0]
@@ -201,7 +202,7 @@ def time_to_target(ctxs, workload, seeds, extra_iters=10):
                 row[name] = None
                 continue
             n_it = int(hits[0])
-            p = ilt.Params.from_dict(prm, iters=n_it, init_mode=0)
+            p = ilt.Params.from_dict(prm, iters=n_it, init_mode=0, optimizer=opt)
             ctx.ilt_solve(tgt, phi, p)          # captures this solve's graph
             torch.cuda.synchronize()
             t0 = time.perf_counter()
@@ -212,7 +213,7 @@ def time_to_target(ctxs, workload, seeds, extra_iters=10):
         per_seed.append(row)
     out = {"target": "L2 of the plain FP32 loop after its configured iterations from TSDF(target)",
            "seeds": list(seeds), "per_seed": per_seed, "median_ms": {}}
-    for name in ctxs:
+    for name in list(ctxs) + ["fp32_cg"]:
         ms = [r[name]["ms"] for r in per_seed if r.get(name)]
         out["median_ms"][name] = round(float(np.median(ms)), 3) if len(ms) == len(per_seed) else None
     if out["median_ms"].get("fp32") and out["median_ms"].get("bf16x3"):

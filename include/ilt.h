@@ -107,6 +107,12 @@ typedef struct {
     int n_corners;          /* 1..4; corner 0 = nominal (L2 metric); with 3
                                corners, 1 and 2 are the PVBand extremes       */
     ilt_corner corners[4];
+    int optimizer;          /* ilt_solve: 0 = move along the gradient g; 1 =
+                               conjugate gradient (Sec. III-C): Polak-Ribiere
+                               with non-negative restart, d = g + beta d_prev,
+                               beta = max(0, <g, g - g_prev>/<g_prev, g_prev>)
+                               (FP64 inner products, beta = 0 on the first
+                               step), CFL step on max|d|                      */
 } ilt_params;
 
 typedef struct {

@@ -100,7 +100,7 @@ void free_ctx(ilt_ctx *c) {
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     void *ptrs[] = {c->tl, c->tb, c->ta4, c->ar, c->ai, c->H, c->sw, c->coef, c->tlhl, c->tbhl, c->Yhl, c->Spart, c->S, c->Est, c->Y, c->Tg,
                     c->I, c->G, c->g, c->phi2, c->Wpart, c->W, c->edtg, c->colbits, c->part, c->scal,
-                    c->tbQ, c->arQ, c->aiQ, c->Ghat, c->Vpart};
+                    c->tbQ, c->arQ, c->aiQ, c->Ghat, c->Vpart, c->g_prev, c->dcg};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     delete c;
@@ -123,6 +123,7 @@ int check_ptr(const void *p, const char *name, size_t align = 4) {
 int check_params(const ilt_ctx *c, const ilt_params *p, bool need_loop) {
     if (!p) return fail(ILT_EINVAL, "params is null");
     if (p->n_corners < 1 || p->n_corners > 4) return fail(ILT_EINVAL, "n_corners must be 1..4");
+    if (p->optimizer != 0 && p->optimizer != 1) return fail(ILT_EINVAL, "optimizer must be 0 or 1");
     for (int i = 0; i < p->n_corners; ++i) {
         const ilt_corner &k = p->corners[i];
         if (k.set < 0 || k.set >= c->n_sets) return fail(ILT_EINVAL, "corner %d uses set %d", i, k.set);
@@ -190,7 +191,8 @@ size_t n_image_blocks(const ilt_ctx *c) { return (size_t)(c->Np / 64) * (c->Np /
 size_t part_step_off(const ilt_ctx *c) {
     return part_max_off(c) + std::max<size_t>(n_image_blocks(c), (size_t)gradmax_blocks(c));
 }
-size_t part_total(const ilt_ctx *c) { return part_step_off(c) + (size_t)step_blocks(c); }
+size_t part_cg_off(const ilt_ctx *c) { return part_step_off(c) + (size_t)step_blocks(c); }
+size_t part_total(const ilt_ctx *c) { return part_cg_off(c) + 3 * (size_t)gradmax_blocks(c); }
 
 }  // namespace
 
@@ -345,6 +347,8 @@ extern "C" int ilt_create(ilt_ctx **out, const ilt_optics *o, int max_batch, voi
     ALLOC(I, (size_t)ns * N * N);
     ALLOC(G, (size_t)ns * N * N);
     ALLOC(g, (size_t)N * N);
+    ALLOC(g_prev, (size_t)N * N);
+    ALLOC(dcg, (size_t)N * N);
     ALLOC(phi2, (size_t)N * N);
     // W partials: one per block of the FP32 adjoint grid, or of the split-BF16 one
     c->n_wpart = std::max(ns * ((N + 31) / 32) * ((K + 3) / 4), adjoint_b3_max_parts(c, ns)) * P * P * 2;
@@ -572,11 +576,18 @@ int enqueue_solve(ilt_ctx *c, const unsigned char *d_target, float *d_phi, const
             PhaseTimer t(c, 5);
             if (!c->gwin) HIPCHK(launch_window_sum(c, slo, shi));
             HIPCHK(launch_gradient(c, c->g, pm));
-            HIPCHK(launch_finish_dt(c, pm, (int)n_image_blocks(c), p->dt_mode, p->eta, p->dt_max, c->scal));
+            int nmax = (int)n_image_blocks(c);
+            if (p->optimizer == 1) {
+                hipError_t e = hipSuccess;
+                nmax = launch_cg(c, i == 0, c->part + part_cg_off(c), pm, &e);
+                HIPCHK(e);
+            }
+            HIPCHK(launch_finish_dt(c, pm, nmax, p->dt_mode, p->eta, p->dt_max, c->scal));
         }
         {
             PhaseTimer t(c, 6);
-            HIPCHK(launch_levelset(c, cur, c->g, nullptr, p->lambda, p->eps_kappa, c->scal, nxt, ps));
+            HIPCHK(launch_levelset(c, cur, p->optimizer == 1 ? c->dcg : c->g, nullptr, p->lambda, p->eps_kappa,
+                                   c->scal, nxt, ps));
             HIPCHK(launch_finish_step(c, ps, step_blocks(c), c->scal, nullptr,
                                       d_trace ? d_trace + (size_t)i * ILT_TRACE_W : nullptr, i));
         }

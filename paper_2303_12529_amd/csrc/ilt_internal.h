@@ -90,6 +90,8 @@ struct ilt_ctx {
     float *I;          // [n_sets][N][N]
     float *G;          // [n_sets][N][N]
     float *g;          // [N][N]
+    float *g_prev;     // [N][N] conjugate gradient: previous gradient
+    float *dcg;        // [N][N] conjugate gradient: direction
     float *phi2;       // [N][N]
     float *Wpart;      // adjoint partials
     float2 *W;         // [P][P]
@@ -125,7 +127,7 @@ struct ilt_ctx {
 // device scalar slots
 enum {
     SC_LOSS = 0, SC_L2 = 1, SC_PVB = 2, SC_NONFIN = 3,
-    SC_MV = 4, SC_DT = 5, SC_FLIPS = 6, SC_ITER = 7,
+    SC_MV = 4, SC_DT = 5, SC_FLIPS = 6, SC_ITER = 7, SC_BETA = 8,
     SC_COUNT = 16
 };
 
@@ -153,6 +155,9 @@ hipError_t launch_image_b3(ilt_ctx *c, int set_lo, int set_hi, float *out);
 hipError_t launch_adjoint_b3(ilt_ctx *c, const float *G, size_t g_set_stride, int set_lo, int set_hi);
 // G-window adjoint: W for sets [set_lo, set_hi) directly (no window_sum)
 hipError_t launch_adjoint_gwindow(ilt_ctx *c, const float *G, size_t g_set_stride, int set_lo, int set_hi);
+// conjugate gradient: d = g + beta d, g_prev = g (beta = 0 when first), and the
+// block maxima of |d| into maxpart for the CFL step; returns that block count
+int launch_cg(ilt_ctx *c, int first, double *part, double *maxpart, hipError_t *err);
 int adjoint_b3_parts(const ilt_ctx *c, int nsets);
 // column ranges of the spectrum kernel: each wave's share stays a multiple of 16
 inline int spectrum_xsplit(const ilt_ctx *c) { return c->Np >= 512 ? 4 : c->Np / 128; }

@@ -217,6 +217,63 @@ __global__ __launch_bounds__(RB) void k_finish_dt(const double *__restrict__ par
 // 32 x 32 output tile per block, staged in LDS with a replicated 1-pixel halo.
 // phi' = phi + dt (v |grad phi| + lambda m K).
 // --------------------------------------------------------------------------
+// --------------------------------------------------------------------------
+// Conjugate gradient (Sec. III-C): Polak-Ribiere with non-negative restart.
+//   k_cg_dots:   block partials of <g,g>, <g,g_prev>, <g_prev,g_prev> (FP64)
+//   k_cg_beta:   beta = max(0, (<g,g> - <g,g_prev>) / <g_prev,g_prev>), 0 when first
+//   k_cg_update: d = g + beta d (d = g when first), g_prev = g, block max |d|
+// --------------------------------------------------------------------------
+__global__ __launch_bounds__(RB) void k_cg_dots(const float *__restrict__ g, const float *__restrict__ gp,
+                                                size_t npix, size_t chunk, double *__restrict__ part) {
+    __shared__ double sh[RB];
+    const size_t lo = (size_t)blockIdx.x * chunk;
+    const size_t hi = min(npix, lo + chunk);
+    double gg = 0.0, ggp = 0.0, gpgp = 0.0;
+    for (size_t p = lo + threadIdx.x; p < hi; p += RB) {
+        const double a = g[p], b = gp[p];
+        gg += a * a;
+        ggp += a * b;
+        gpgp += b * b;
+    }
+    gg = block_sum(gg, sh);
+    ggp = block_sum(ggp, sh);
+    gpgp = block_sum(gpgp, sh);
+    if (threadIdx.x == 0) {
+        part[3 * blockIdx.x + 0] = gg;
+        part[3 * blockIdx.x + 1] = ggp;
+        part[3 * blockIdx.x + 2] = gpgp;
+    }
+}
+
+__global__ __launch_bounds__(RB) void k_cg_beta(const double *__restrict__ part, int nblk, int first,
+                                                double *__restrict__ scal) {
+    __shared__ double sh[RB];
+    double v[3] = {0.0, 0.0, 0.0};
+    for (int b = threadIdx.x; b < nblk; b += RB)
+        for (int q = 0; q < 3; ++q) v[q] += part[3 * b + q];
+    for (int q = 0; q < 3; ++q) v[q] = block_sum(v[q], sh);
+    if (threadIdx.x == 0) scal[SC_BETA] = (first || !(v[2] > 0.0)) ? 0.0 : fmax(0.0, (v[0] - v[1]) / v[2]);
+}
+
+__global__ __launch_bounds__(RB) void k_cg_update(const float *__restrict__ g, float *__restrict__ gp,
+                                                  float *__restrict__ d, size_t npix, size_t chunk, int first,
+                                                  const double *__restrict__ scal, double *__restrict__ maxpart) {
+    __shared__ double sh[RB];
+    const float beta = (float)scal[SC_BETA];
+    const size_t lo = (size_t)blockIdx.x * chunk;
+    const size_t hi = min(npix, lo + chunk);
+    float m = 0.f;
+    for (size_t p = lo + threadIdx.x; p < hi; p += RB) {
+        const float gv = g[p];
+        const float dv = first ? gv : fmaf(beta, d[p], gv);
+        d[p] = dv;
+        gp[p] = gv;
+        m = (dv != dv) ? INFINITY : fmaxf(m, fabsf(dv));
+    }
+    const double r = block_max((double)m, sh);
+    if (threadIdx.x == 0) maxpart[blockIdx.x] = r;
+}
+
 __global__ __launch_bounds__(256) void k_levelset(const float *__restrict__ phi, const float *__restrict__ vel,
                                                   const float *__restrict__ mod, float lam, float eps_kappa,
                                                   const double *__restrict__ scal, int N,
@@ -646,6 +703,17 @@ hipError_t launch_finish_resist(ilt_ctx *c, const double *part, int nblk, double
 }
 
 int gradmax_blocks(const ilt_ctx *c) { return resist_blocks(c); }
+
+int launch_cg(ilt_ctx *c, int first, double *part, double *maxpart, hipError_t *err) {
+    const size_t npix = (size_t)c->N * c->N;
+    const int nblk = gradmax_blocks(c);
+    const size_t chunk = chunk_of(npix, nblk);
+    k_cg_dots<<<nblk, RB, 0, c->stream>>>(c->g, c->g_prev, npix, chunk, part);
+    k_cg_beta<<<1, RB, 0, c->stream>>>(part, nblk, first, c->scal);
+    k_cg_update<<<nblk, RB, 0, c->stream>>>(c->g, c->g_prev, c->dcg, npix, chunk, first, c->scal, maxpart);
+    *err = hipGetLastError();
+    return nblk;
+}
 
 hipError_t launch_absmax(ilt_ctx *c, const float *v, double *part) {
     const size_t npix = (size_t)c->N * c->N;

@@ -48,7 +48,7 @@ class _Params(ctypes.Structure):
                 ("init_mode", ctypes.c_int), ("eta", ctypes.c_float), ("dt_max", ctypes.c_float),
                 ("lambda_", ctypes.c_float), ("sigma_z", ctypes.c_float), ("i_th", ctypes.c_float),
                 ("eps_kappa", ctypes.c_float), ("d_lower", ctypes.c_float), ("d_upper", ctypes.c_float),
-                ("n_corners", ctypes.c_int), ("corners", _Corner * 4)]
+                ("n_corners", ctypes.c_int), ("corners", _Corner * 4), ("optimizer", ctypes.c_int)]
 
 
 class _Report(ctypes.Structure):
@@ -132,6 +132,7 @@ class Params:
     d_lower: float = -100.0
     d_upper: float = 900.0
     corners: tuple = ((0, 1.0, 1.0),)
+    optimizer: int = 0              # 0: gradient, 1: conjugate gradient (Polak-Ribiere+)
 
     @classmethod
     def from_dict(cls, d: dict, **over):
@@ -148,6 +149,7 @@ class Params:
         if not 1 <= len(self.corners) <= 4:
             raise ValueError("1..4 corners")
         p.n_corners = len(self.corners)
+        p.optimizer = int(self.optimizer)
         for i, (s, d, w) in enumerate(self.corners):
             p.corners[i].set, p.corners[i].dose, p.corners[i].omega = int(s), float(d), float(w)
         return p

@@ -173,3 +173,58 @@ def test_gwindow_trajectory_matches_stored_fields(ilt):
     # same method, different rounding order: print counts within near-ties
     assert np.all(np.abs(outs[0][:, 2] - outs[1][:, 2]) <= 2)
     assert np.allclose(outs[0][:, 5], outs[1][:, 5], rtol=1e-3)
+
+
+def test_cg_first_step_equals_plain(ilt):
+    """With beta = 0 on the first step the conjugate direction is the gradient."""
+    Z, H, w, prm = workload_inputs("c0", 7)
+    N = Z.shape[0]
+    ctx = ilt.Context(H, w, N)
+    outs = []
+    for opt in (0, 1):
+        phi = torch.empty((N, N), dtype=torch.float32, device="cuda")
+        ctx.ilt_solve(_dev(Z, torch.uint8), phi, ilt.Params.from_dict(prm, iters=1, optimizer=opt))
+        outs.append(phi.cpu().numpy())
+    assert np.array_equal(outs[0], outs[1])
+
+
+def test_cg_iterations_teacher_forced(ilt):
+    """Three CG iterations (no reinit) from the same phi_0 against the oracle."""
+    Z, H, w, prm = workload_inputs("c0", 8)
+    N = Z.shape[0]
+    phi0, _, _ = o_edt.tsdf_from_mask(Z, prm["d_lower"], prm["d_upper"])
+    phi0 = phi0.astype(np.float32)
+    prm3 = dict(prm, iters=3, reinit_every=0, optimizer=1)
+    ctx = ilt.Context(H, w, N)
+    phi = _dev(phi0)
+    trace = torch.zeros((3, ilt.TRACE_W), dtype=torch.float64, device="cuda")
+    ctx.ilt_solve(_dev(Z, torch.uint8), phi, ilt.Params.from_dict(prm3, init_mode=1), trace=trace)
+    tr = trace.cpu().numpy()
+    ref = phi0.astype(np.float64)
+    state = {}
+    for i in range(3):
+        ref, row = o_solve.iteration(ref, Z, H, w, prm3, state)
+        _say("cg it", i, "loss", tr[i, 1], row["loss"], "m_v", tr[i, 5], row["m_v"], "beta", row["beta"])
+        assert abs(tr[i, 1] - row["loss"]) <= 1e-4 * abs(row["loss"])
+        assert abs(tr[i, 5] - row["m_v"]) <= 1e-3 * row["m_v"]
+    err = np.abs(phi.cpu().numpy().astype(np.float64) - ref).max()
+    _say("cg phi err", err)
+    assert err <= 3e-3 * prm["eta"] + 1e-3
+
+
+def test_cg_trajectory_band(ilt):
+    Z, H, w, prm = workload_inputs("c0", 1)
+    N = Z.shape[0]
+    prm = dict(prm, optimizer=1)
+    ctx = ilt.Context(H, w, N)
+    phi = torch.empty((N, N), dtype=torch.float32, device="cuda")
+    trace = torch.zeros((prm["iters"], ilt.TRACE_W), dtype=torch.float64, device="cuda")
+    rep = ctx.ilt_solve(_dev(Z, torch.uint8), phi, ilt.Params.from_dict(prm), trace=trace)
+    l2g = trace.cpu().numpy()[:, 2]
+    _, otr, ofin = o_solve.ilt_solve(Z, H, w, prm)
+    l2o = np.array([r["l2"] for r in otr])
+    _say("cg gpu l2", l2g.astype(int).tolist())
+    _say("cg ref l2", l2o.tolist())
+    band = 0.02 * l2o[0] + 10
+    assert np.all(np.abs(l2g - l2o) <= band)
+    assert abs(rep["l2"] - ofin["l2"]) <= band
