@@ -22,6 +22,14 @@ by the HIP path) are:
 * loss: L_0 per sample (a sum over pixels), averaged over the batch;
 * optimiser: Adam (Kingma and Ba) on FP32 master weights.
 
+Modulation branch (Sec. III-B, multi-branch pre-training): a second 1x1 head
+on the same backbone output gives phi_m; the branch's map is the
+approximated Heaviside m = H_eps(phi_m) = 1/2 (1 + (2/pi) arctan(phi_m/eps))
+with eps = 0.03, trained with L_m = sum (H_eps(phi_m) - m_gt)^2 (per sample,
+averaged over the batch) next to L_0.  m_gt is the Heaviside of the shifted
+ground-truth level set, H(phi_gt + dh) (H(z) = 1 for z >= 0), for the shift
+dh that gives the lowest L_DSO when [phi_gt + dh <= 0] is printed as a mask.
+
 Layouts: activations [B][H][W][C] (channels last); convolution weights
 [C_out][3][3][C_in]; biases [C_out].
 """
@@ -36,8 +44,12 @@ SCALE = 100.0
 # architecture
 # --------------------------------------------------------------------------
 
-def param_shapes(base: int = 32, levels: int = 4, c_in: int = 1):
-    """Ordered (name, weight shape, bias shape) of the level-set branch."""
+EPS_AHF = 0.03
+
+
+def param_shapes(base: int = 32, levels: int = 4, c_in: int = 1, modulation: bool = False):
+    """Ordered (name, weight shape, bias shape) of the level-set branch (and
+    the modulation head after it)."""
     ch = [base << i for i in range(levels)]
     out = []
     prev = c_in
@@ -50,14 +62,16 @@ def param_shapes(base: int = 32, levels: int = 4, c_in: int = 1):
         out.append(("dec%d_a" % l, (ch[l], 3, 3, 2 * ch[l]), (ch[l],)))
         out.append(("dec%d_b" % l, (ch[l], 3, 3, ch[l]), (ch[l],)))
     out.append(("head", (1, 1, 1, ch[0]), (1,)))
+    if modulation:
+        out.append(("head_m", (1, 1, 1, ch[0]), (1,)))
     return out
 
 
-def init_params(seed: int, base: int = 32, levels: int = 4):
+def init_params(seed: int, base: int = 32, levels: int = 4, modulation: bool = False):
     """He-normal weights, zero biases (dict name -> (w, b))."""
     rng = np.random.default_rng(seed)
     p = {}
-    for name, ws, bs in param_shapes(base, levels):
+    for name, ws, bs in param_shapes(base, levels, modulation=modulation):
         fan_in = ws[1] * ws[2] * ws[3]
         p[name] = (rng.normal(0.0, np.sqrt(2.0 / fan_in), size=ws), np.zeros(bs))
     return p
@@ -156,12 +170,31 @@ def forward(params, x, levels: int = 4):
             h = relu(conv3x3(h, *params[name]))
             cache[name + ":y"] = h
     cache["head"] = h
-    return conv1x1(h, *params["head"]), cache
+    out = conv1x1(h, *params["head"])
+    if "head_m" in params:
+        out = np.concatenate([out, conv1x1(h, *params["head_m"])], axis=-1)
+    return out, cache
+
+
+def ahf(z, eps=EPS_AHF):
+    """Approximated Heaviside 1/2 (1 + (2/pi) arctan(z / eps))."""
+    return 0.5 * (1.0 + (2.0 / np.pi) * np.arctan(np.asarray(z, dtype=np.float64) / eps))
+
+
+def ahf_grad(z, eps=EPS_AHF):
+    z = np.asarray(z, dtype=np.float64)
+    return (1.0 / np.pi) * eps / (eps * eps + z * z)
 
 
 def loss(out, target):
     """L_0 per sample, averaged over the batch: mean_b sum_p (out - target)^2."""
     d = out[..., 0] - target
+    return float(np.sum(d * d)) / out.shape[0]
+
+
+def loss_m(out, target_m):
+    """L_m per sample, averaged over the batch: mean_b sum_p (H_eps(out_m) - m_gt)^2."""
+    d = ahf(out[..., 1]) - target_m
     return float(np.sum(d * d)) / out.shape[0]
 
 
@@ -200,8 +233,9 @@ def upsample2_backward(dy):
     return dy.reshape(n, h // 2, 2, wd // 2, 2, c).sum(axis=(2, 4))
 
 
-def backward(params, cache, out, target, levels: int = 4):
-    """Gradients of loss(out, target) for every parameter: name -> (dw, db)."""
+def backward(params, cache, out, target, levels: int = 4, target_m=None):
+    """Gradients of loss(out, target) (+ loss_m(out, target_m) when given and
+    the network has the modulation head) for every parameter: name -> (dw, db)."""
     B = out.shape[0]
     g = {}
     dout = (2.0 / B) * (out[..., 0] - target)[..., None]
@@ -210,6 +244,13 @@ def backward(params, cache, out, target, levels: int = 4):
     g["head"] = ((dout.reshape(-1, 1).T @ h.reshape(-1, h.shape[-1]))[:, None, None, :],
                  dout.reshape(-1, 1).sum(axis=0))
     dh = dout @ wh[:, 0, 0, :]
+    if "head_m" in params:
+        zm = out[..., 1]
+        dm = np.zeros_like(zm) if target_m is None else (2.0 / B) * (ahf(zm) - target_m) * ahf_grad(zm)
+        dm = dm[..., None]
+        g["head_m"] = ((dm.reshape(-1, 1).T @ h.reshape(-1, h.shape[-1]))[:, None, None, :],
+                       dm.reshape(-1, 1).sum(axis=0))
+        dh = dh + dm @ params["head_m"][0][:, 0, 0, :]
     dskip = {}
     for l in range(0, levels - 1):
         for part in ("b", "a"):
@@ -262,3 +303,15 @@ def net_target(phi_gt_2048):
 def phi0_from_output(out_512, d_lower, d_upper):
     """phi_0 for DSO: 100 x bilinear 4x upsampling, clipped to the TSDF bounds."""
     return np.clip(SCALE * bilinear_up(out_512, 4), d_lower, d_upper)
+
+
+def modulation_target(phi_gt, shifts, loss_of_mask):
+    """m_gt = H(phi_gt + dh) for the shift dh with the lowest loss_of_mask(
+    [phi_gt + dh <= 0]) (ties: the first in `shifts`); returns (m_gt, dh)."""
+    phi_gt = np.asarray(phi_gt, dtype=np.float64)
+    best, best_dh = None, None
+    for dh in shifts:
+        L = loss_of_mask((phi_gt + dh <= 0).astype(np.float64))
+        if best is None or L < best:
+            best, best_dh = L, dh
+    return (phi_gt + best_dh >= 0).astype(np.float64), best_dh

@@ -161,3 +161,52 @@ def test_interface_resampling():
     back = dsn.phi0_from_output(np.full((512, 512), 0.5), -100.0, 900.0)
     assert back.shape == (2048, 2048) and np.all(back == 50.0)
     assert np.all(dsn.phi0_from_output(np.full((4, 4), 20.0), -100.0, 900.0) == 900.0)
+
+
+def test_ahf_closed_forms():
+    assert dsn.ahf(0.0) == 0.5
+    assert abs(dsn.ahf(1e9) - 1.0) < 1e-9 and abs(dsn.ahf(-1e9)) < 1e-9
+    z = np.linspace(-0.2, 0.2, 11)
+    h = 1e-7
+    assert np.allclose((dsn.ahf(z + h) - dsn.ahf(z - h)) / (2 * h), dsn.ahf_grad(z), rtol=1e-6)
+    # at z = eps the map is 3/4 (arctan 1 = pi/4)
+    assert abs(dsn.ahf(dsn.EPS_AHF) - 0.75) < 1e-15
+
+
+def test_modulation_head_backward_matches_finite_differences():
+    rng = np.random.default_rng(21)
+    p = dsn.init_params(9, base=4, levels=3, modulation=True)
+    p = {k: (w, rng.normal(scale=0.1, size=b.shape)) for k, (w, b) in p.items()}
+    x = rng.uniform(size=(2, 16, 16, 1))
+    t = rng.normal(size=(2, 16, 16))
+    tm = (rng.uniform(size=(2, 16, 16)) < 0.5).astype(float)
+    out, cache = dsn.forward(p, x, levels=3)
+    assert out.shape[-1] == 2
+    g, dx = dsn.backward(p, cache, out, t, levels=3, target_m=tm)
+
+    def L(pp):
+        o = dsn.forward(pp, x, levels=3)[0]
+        return dsn.loss(o, t) + dsn.loss_m(o, tm)
+
+    h = 1e-6
+    for name in ("head_m", "head", "dec0_b", "enc1_a"):
+        w, b = p[name]
+        for _ in range(3):
+            idx = tuple(rng.integers(0, s) for s in w.shape)
+            wp, wm = w.copy(), w.copy()
+            wp[idx] += h
+            wm[idx] -= h
+            fd = (L({**p, name: (wp, b)}) - L({**p, name: (wm, b)})) / (2 * h)
+            assert abs(fd - g[name][0][idx]) <= 1e-6 * max(1.0, abs(fd)), (name, idx)
+    bp, bm = p["head_m"][1].copy(), p["head_m"][1].copy()
+    bp[0] += h
+    bm[0] -= h
+    fd = (L({**p, "head_m": (p["head_m"][0], bp)}) - L({**p, "head_m": (p["head_m"][0], bm)})) / (2 * h)
+    assert abs(fd - g["head_m"][1][0]) <= 1e-6 * max(1.0, abs(fd))
+
+
+def test_modulation_target_picks_the_best_shift():
+    phi = np.add.outer(np.arange(10.0), np.zeros(4)) - 4.5      # rows 0..4 inside (phi <= 0)
+    want = (phi + 2 <= 0).astype(float)                          # the mask shifted by dh = 2
+    m, dh = dsn.modulation_target(phi, [-2, 0, 2, 4], lambda M: float(np.sum(M != want)))
+    assert dh == 2 and np.array_equal(m, (phi + 2 >= 0).astype(float))
