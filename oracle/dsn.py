@@ -305,13 +305,17 @@ def phi0_from_output(out_512, d_lower, d_upper):
     return np.clip(SCALE * bilinear_up(out_512, 4), d_lower, d_upper)
 
 
-def modulation_target(phi_gt, shifts, loss_of_mask):
-    """m_gt = H(phi_gt + dh) for the shift dh with the lowest loss_of_mask(
-    [phi_gt + dh <= 0]) (ties: the first in `shifts`); returns (m_gt, dh)."""
+def modulation_target(phi_gt, shifts, loss_of_modulation):
+    """m_gt of the modulation branch (Sec. III-B): each candidate is the
+    Heaviside map m = H(phi_gt + dh) of the shifted ground truth, and m_gt is
+    the candidate with the lowest loss_of_modulation(m), the DSO loss reached
+    when DSO runs with m as its modulation map (ties: the first in `shifts`).
+    Returns (m_gt, dh)."""
     phi_gt = np.asarray(phi_gt, dtype=np.float64)
-    best, best_dh = None, None
+    best, best_dh, best_m = None, None, None
     for dh in shifts:
-        L = loss_of_mask((phi_gt + dh <= 0).astype(np.float64))
+        m = (phi_gt + dh >= 0).astype(np.float64)
+        L = loss_of_modulation(m)
         if best is None or L < best:
-            best, best_dh = L, dh
-    return (phi_gt + best_dh >= 0).astype(np.float64), best_dh
+            best, best_dh, best_m = L, dh, m
+    return best_m, best_dh

@@ -29,12 +29,13 @@ def forward_all(M, kernels, weights, corners):
     return I
 
 
-def iteration(phi, target, kernels, weights, params, state=None):
+def iteration(phi, target, kernels, weights, params, state=None, mod=None):
     """One DSO iteration before re-initialisation.
 
     params["optimizer"] = 1 moves phi along the conjugate direction of
     levelset.cg_direction (Sec. III-C) instead of the gradient itself; its
     state (previous gradient and direction) lives in `state` across calls.
+    mod: the modulation map m of the curvature term (Sec. III-C), None = 1.
     Returns (phi', row) with row = dict(loss, l2, pvb, flips, m_v, dt, beta).
     """
     corners = params["corners"]
@@ -49,13 +50,14 @@ def iteration(phi, target, kernels, weights, params, state=None):
     if params.get("optimizer", 0) == 1:
         g, beta = levelset.cg_direction(g, state if state is not None else {})
     new, dt, m_v, flips = levelset.levelset_step(
-        phi, g, None, params["eta"], params["lam"], params["eps_kappa"],
+        phi, g, mod, params["eta"], params["lam"], params["eps_kappa"],
         params.get("dt_mode", 0), params.get("dt_max", 0.0))
     return new, dict(loss=L, l2=l2, pvb=pvb, flips=flips, m_v=m_v, dt=dt, beta=beta)
 
 
-def ilt_solve(target, kernels, weights, params, phi0=None):
-    """Run params['iters'] DSO iterations; returns (phi_T, trace, final).
+def ilt_solve(target, kernels, weights, params, phi0=None, mod=None):
+    """Run params['iters'] DSO iterations (curvature term weighted by `mod`
+    when given); returns (phi_T, trace, final).
 
     final = dict(l2, pvb, loss) of the mask [phi_T <= 0].
     """
@@ -68,7 +70,7 @@ def ilt_solve(target, kernels, weights, params, phi0=None):
     state = {}
     R = int(params.get("reinit_every", 0))
     for i in range(int(params["iters"])):
-        phi, row = iteration(phi, target, kernels, weights, params, state)
+        phi, row = iteration(phi, target, kernels, weights, params, state, mod)
         if R > 0 and (i + 1) % R == 0:
             phi, _, _ = edt.tsdf_from_phi(phi, params["d_lower"], params["d_upper"])
         row["i"] = i

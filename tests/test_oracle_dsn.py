@@ -207,6 +207,11 @@ def test_modulation_head_backward_matches_finite_differences():
 
 def test_modulation_target_picks_the_best_shift():
     phi = np.add.outer(np.arange(10.0), np.zeros(4)) - 4.5      # rows 0..4 inside (phi <= 0)
-    want = (phi + 2 <= 0).astype(float)                          # the mask shifted by dh = 2
-    m, dh = dsn.modulation_target(phi, [-2, 0, 2, 4], lambda M: float(np.sum(M != want)))
-    assert dh == 2 and np.array_equal(m, (phi + 2 >= 0).astype(float))
+    want = np.zeros_like(phi)
+    want[3:, :] = 1.0                                            # H(phi + 2): rows with r - 2.5 >= 0
+    m, dh = dsn.modulation_target(phi, [-2, 0, 2, 4], lambda mm: float(np.sum(mm != want)))
+    assert dh == 2 and np.array_equal(m, want)
+    # ties go to the first candidate; the loss sees the Heaviside map itself
+    seen = []
+    m, dh = dsn.modulation_target(phi, [4, -2], lambda mm: seen.append(mm.sum()) or 0.0)
+    assert dh == 4 and seen == [4.0 * 9, 4.0 * 3]

@@ -120,6 +120,33 @@ def test_circle_curvature_flow_area_rate():
     assert flips == 0 and np.array_equal(e2 <= 0, edge <= 0)
 
 
+def test_modulated_curvature_flow():
+    """The modulation map scales the curvature term pointwise (Sec. III-C):
+    m = 1/2 everywhere halves the circle's area rate (pi lambda); m = 0 keeps
+    phi unchanged; m = 0 on the left half and 1 on the right leaves the left
+    half of the disc where it was while the right half shrinks."""
+    N, R0, lam, dt, steps = 128, 30.0, 1.0, 0.2, 1000
+    yy, xx = np.mgrid[0:N, 0:N].astype(np.float64)
+    phi0 = np.hypot(yy - 63.5, xx - 63.5) - R0
+    zero = np.zeros((N, N))
+    phi = phi0.copy()
+    half = np.full((N, N), 0.5)
+    for _ in range(steps):
+        phi, _, _, _ = levelset.levelset_step(phi, zero, half, dt, lam, 1e-12, dt_mode=1)
+    rate = (np.sum(phi0 <= 0) - np.sum(phi <= 0)) / (steps * dt)
+    assert abs(rate - np.pi * lam) <= 0.05 * np.pi * lam
+    frozen, _, _, f = levelset.levelset_step(phi0, zero, zero, dt, lam, 1e-12, dt_mode=1)
+    assert f == 0 and np.array_equal(frozen, phi0)
+    side = (xx >= 63.5).astype(np.float64)
+    phi = phi0.copy()
+    for _ in range(200):
+        phi, _, _, _ = levelset.levelset_step(phi, zero, side, dt, lam, 1e-12, dt_mode=1)
+    left = xx < 58.0                    # a few pixels clear of the stencil's reach across the seam
+    assert np.array_equal((phi <= 0) & left, (phi0 <= 0) & left)
+    right = xx > 69.0
+    assert np.sum((phi <= 0) & right) < np.sum((phi0 <= 0) & right)
+
+
 def test_descent_sign_and_loss_decrease():
     """A motion-only step flips only pixels with g * dM < 0, and a small CFL
     step lowers the DSO loss."""
