@@ -232,9 +232,12 @@ def develset_ttt(seeds):
     from paper_2303_12529_amd import ilt
     if not os.path.exists(DSN_WEIGHTS):
         return None
-    net = dsn.Net(512, 512, 32, max_batch=1)
-    net.set_params(np.load(DSN_WEIGHTS, allow_pickle=False).astype(np.float32))
-    out = {"weights": os.path.relpath(DSN_WEIGHTS, HERE)}
+    flat = np.load(DSN_WEIGHTS, allow_pickle=False).astype(np.float32)
+    # the modulation branch adds one 1x1 head (32 weights and a bias)
+    modulation = flat.size == dsn.layer_table(32, True)[-1][4] + 1
+    net = dsn.Net(512, 512, 32, max_batch=1, modulation=modulation)
+    net.set_params(flat)
+    out = {"weights": os.path.relpath(DSN_WEIGHTS, HERE), "modulation": modulation}
     for name, prec in (("fp32", ilt.ILT_FP32), ("bf16x3", ilt.ILT_BF16X3)):
         ev = develset.evaluate(net, seeds, precision=prec)
         out[name] = {"median_ms_plain": ev["median_ms_plain"], "median_ms_develset": ev["median_ms_develset"],
@@ -242,6 +245,10 @@ def develset_ttt(seeds):
                      "iters_develset": [r["iters_develset"] for r in ev["per_seed"]],
                      "l2_at_T_plain": [r["l2_at_T_plain"] for r in ev["per_seed"]],
                      "l2_at_T_develset": [r["l2_at_T_develset"] for r in ev["per_seed"]]}
+        if modulation:
+            out[name].update(median_ms_develset_m=ev.get("median_ms_develset_m"), speedup_m=ev.get("speedup_m"),
+                             iters_develset_m=[r["iters_develset_m"] for r in ev["per_seed"]],
+                             l2_at_T_develset_m=[r["l2_at_T_develset_m"] for r in ev["per_seed"]])
     net.close()
     return out
 

@@ -1,26 +1,36 @@
-/* C ABI of the DevelSet-Net level-set branch on one AMD MI355X (gfx950).
+/* C ABI of DevelSet-Net on one AMD MI355X (gfx950).
  *
  * Sec. III-B of Chen et al., "DevelSet: Deep Neural Level Set for Instant
  * Mask Optimization" (arXiv 2303.12529): a UNet backbone predicts the initial
  * level-set function phi_0 of DSO from the target image and is trained with
  * the squared error L_0 = sum (phi_0,theta - phi_gt)^2 against level-set
- * functions produced by DSO.  The paper leaves the layer sizes, resampling
- * and optimiser open; this library fixes them as follows:
+ * functions produced by DSO.  Its second branch predicts the modulation map
+ * m_theta = H_eps(phi_m), H_eps(z) = 1/2 (1 + (2/pi) atan(z / eps)) the
+ * approximated Heaviside function with the paper's eps = DSN_EPS_AHF (Sec.
+ * III-B, Sec. IV), trained with L_m = sum (m_theta - m_gt)^2 and m_gt a
+ * binary map that the caller derives from phi_gt by a shift search.  The paper leaves the layer sizes, resampling and
+ * optimiser open; this library fixes them as follows:
  *   - network grid H x W (the 2048 clip's 4 x 4 means: 512 x 512); four
  *     levels of width C, 2C, 4C, 8C (C = base, a multiple of 32); per level
  *     two 3x3 convolutions (zero padding 1, bias, ReLU); 2x2 max-pooling
  *     down; up: nearest 2x upsampling, a 3x3 convolution (bias, ReLU) to the
  *     level's width, concatenation [up | skip], the level's two
- *     convolutions; a 1x1 head (bias, no ReLU);
+ *     convolutions; a 1x1 head (bias, no ReLU) giving phi / 100, and with
+ *     the modulation branch a second 1x1 head on the same features giving
+ *     phi_m (the two branches share the backbone);
  *   - input = 4 x 4 mean of the binary target; target = 4 x 4 mean of phi_gt
  *     (pixels of the fine grid) / 100; phi_0 = clip(100 x bilinear 4x
  *     upsample of the output) with half-pixel centres and clamped borders;
- *   - loss L_0 per sample (a sum over pixels) averaged over the batch;
+ *     the modulation target t_m = 4 x 4 mean of m_gt, and the fine-grid
+ *     modulation map m_0 = bilinear 4x upsample of H_eps(phi_m);
+ *   - losses L_0 and L_m per sample (sums over pixels of the network grid)
+ *     averaged over the batch; the trained objective is L_0 + L_m;
  *     Adam on FP32 master weights; BF16 activations, weights and activation
  *     gradients with FP32 accumulation; FP32 weight gradients.
  * Parameters are one flat FP32 vector: for each layer in the order enc0_a,
- * enc0_b, ..., enc3_a, enc3_b, dec2_up, dec2_a, dec2_b, dec1_*, dec0_*, head,
- * the weights [C_out][3][3][C_in] (head: [1][1][1][C]) then the bias [C_out].
+ * enc0_b, ..., enc3_a, enc3_b, dec2_up, dec2_a, dec2_b, dec1_*, dec0_*, head
+ * and, with the modulation branch, head_m: the weights [C_out][3][3][C_in]
+ * (heads: [1][1][1][C]) then the bias [C_out].
  *
  * Buffers are device pointers owned by the caller unless stated; every call
  * is enqueued on the context's stream and returns without waiting.  Errors:
@@ -37,14 +47,16 @@ extern "C" {
 enum { DSN_OK = 0, DSN_EINVAL = -1, DSN_ENOMEM = -2, DSN_EDEVICE = -3 };
 #define DSN_LEVELS 4
 #define DSN_SCALE 100.0f
+#define DSN_EPS_AHF 0.03f
 
 typedef struct dsn_ctx dsn_ctx;
 
 /* H, W: network grid, multiples of 8 (three poolings), at most 2048;
- * base: level-0 width, 32 or 64; max_batch >= 1.  Allocates the parameters
- * (zero), Adam moments, and activations/gradients for max_batch samples.
+ * base: level-0 width, 32 or 64; max_batch >= 1; modulation: 1 adds the
+ * modulation head, 0 leaves it out.  Allocates the parameters (zero), Adam
+ * moments, and activations/gradients for max_batch samples.
  * stream: a hipStream_t (NULL = default stream). */
-int dsn_create(dsn_ctx **out, int H, int W, int base, int max_batch, void *stream);
+int dsn_create(dsn_ctx **out, int H, int W, int base, int max_batch, int modulation, void *stream);
 int dsn_destroy(dsn_ctx *ctx);
 const char *dsn_last_error(void);
 /* Number of FP32 entries of the flat parameter vector. */
@@ -55,15 +67,20 @@ int dsn_set_params(dsn_ctx *ctx, const float *d_params);
 int dsn_get_params(const dsn_ctx *ctx, float *d_params);
 
 /* Forward pass.  d_x: [B][H][W] FP32 network input; d_out: [B][H][W] FP32
- * network output (target scale, i.e. phi / 100).  Keeps every activation for
- * dsn_backward, which also reads d_x and d_out again: both must stay valid
- * until then.  1 <= B <= max_batch. */
-int dsn_forward(dsn_ctx *ctx, const float *d_x, int B, float *d_out);
-/* Backward pass of L_0 for the last forward (same B).  d_target [B][H][W];
- * d_loss: device double[1], set to L_0 averaged over the batch; d_grad: NULL
- * or device FP32 [num_params] receiving the gradient (it is always kept
- * internally for dsn_adam_step). */
-int dsn_backward(dsn_ctx *ctx, const float *d_target, int B, double *d_loss, float *d_grad);
+ * network output (target scale, i.e. phi / 100); d_out_m: NULL, or (only
+ * with the modulation head) [B][H][W] FP32 receiving phi_m before H_eps.
+ * Keeps every activation for dsn_backward, which also reads d_x, d_out and
+ * d_out_m again: they must stay valid until then.  1 <= B <= max_batch. */
+int dsn_forward(dsn_ctx *ctx, const float *d_x, int B, float *d_out, float *d_out_m);
+/* Backward pass for the last forward (same B).  d_target [B][H][W];
+ * d_target_m: NULL (L_m is left out; the modulation head's gradient is
+ * zero) or [B][H][W] modulation targets in [0, 1], which needs a forward
+ * with d_out_m; the gradient is that of L_0 + L_m.  d_loss: device
+ * double[2], set to L_0 and L_m (0 without d_target_m) averaged over the
+ * batch; d_grad: NULL or device FP32 [num_params] receiving the gradient
+ * (it is always kept internally for dsn_adam_step). */
+int dsn_backward(dsn_ctx *ctx, const float *d_target, const float *d_target_m, int B, double *d_loss,
+                 float *d_grad);
 /* One Adam step with the gradient of the last backward (step count kept in
  * the context, starting at 1). */
 int dsn_adam_step(dsn_ctx *ctx, float lr, float beta1, float beta2, float eps);
@@ -71,13 +88,16 @@ int dsn_adam_step(dsn_ctx *ctx, float lr, float beta1, float beta2, float eps);
 /* Resampling between the fine grid (4H x 4W) and the network grid.
  * dsn_prepare: d_target bytes [B][4H][4W] (nonzero = metal) -> d_x
  * [B][H][W] 4 x 4 means; if d_phi_gt (FP32 [B][4H][4W]) is non-NULL, also
- * d_t [B][H][W] = 4 x 4 means of phi_gt / 100.
+ * d_t [B][H][W] = 4 x 4 means of phi_gt / 100; if d_m_gt (FP32
+ * [B][4H][4W]) is non-NULL, also d_t_m [B][H][W] = its 4 x 4 means.
  * dsn_predict: forward pass of the targets' means, then
- * d_phi0 [B][4H][4W] = clip(100 x bilinear 4x upsample, d_lower, d_upper). */
-int dsn_prepare(dsn_ctx *ctx, const unsigned char *d_target, const float *d_phi_gt, int B, float *d_x,
-                float *d_t);
+ * d_phi0 [B][4H][4W] = clip(100 x bilinear 4x upsample, d_lower, d_upper)
+ * and, if d_m0 is non-NULL (modulation head only), d_m0 [B][4H][4W] =
+ * bilinear 4x upsample of H_eps(phi_m), values in [0, 1]. */
+int dsn_prepare(dsn_ctx *ctx, const unsigned char *d_target, const float *d_phi_gt, const float *d_m_gt, int B,
+                float *d_x, float *d_t, float *d_t_m);
 int dsn_predict(dsn_ctx *ctx, const unsigned char *d_target, int B, float d_lower, float d_upper,
-                float *d_phi0);
+                float *d_phi0, float *d_m0);
 
 /* Single operations of the network, for callers composing their own layers
  * (and for testing each kernel alone).  BF16 tensors channels-last; N images

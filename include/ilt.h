@@ -184,6 +184,16 @@ int edt_reinit(ilt_ctx *ctx, const float *d_phi, const unsigned char *d_mask,
 int ilt_solve(ilt_ctx *ctx, const unsigned char *d_target, float *d_phi,
               const ilt_params *params, ilt_report *h_report, double *d_trace);
 
+/* Sec. III-C (DevelSet): ilt_solve with the curvature term of every step
+ * weighted by a modulation map, phi += dt * (v |grad phi| + lambda * m * K)
+ * with m = d_mod [N][N] FP32 (the DSN's modulation branch output upsampled
+ * to the clip, values in [0, 1]; ilt_solve is the case m = 1).  d_mod is
+ * read by every iteration and must stay valid and unchanged for the call;
+ * a replayed graph keys on its address, not its contents.  Same arguments,
+ * errors and synchronisation as ilt_solve. */
+int ilt_solve_modulated(ilt_ctx *ctx, const unsigned char *d_target, float *d_phi, const float *d_mod,
+                        const ilt_params *params, ilt_report *h_report, double *d_trace);
+
 /* Sec. III-A/B, device-resident loop: by default ilt_solve captures its
  * whole launch sequence (init, iterations, final metrics) into a hipGraph on
  * an internal stream the first time it sees a set of arguments, and replays

@@ -1,6 +1,7 @@
-// DevelSet-Net level-set branch (Sec. III-B): UNet forward, backward of the
-// squared-error loss L_0, Adam, and the resampling between the fine grid and
-// the network grid, on the gfx950 BF16 matrix cores.  The C ABI is in
+// DevelSet-Net (Sec. III-B): UNet forward with the level-set head and the
+// optional modulation head, backward of L_0 (and of L_m), Adam, and the
+// resampling between the fine grid and the network grid, on the gfx950 BF16
+// matrix cores.  The C ABI is in
 // include/dsn.h.
 //
 // Activations are channels-last BF16 views (pointer, channel stride): the
@@ -488,70 +489,109 @@ __global__ void k_relu_bwd(View d, View y, long long npix) {
 // Head (1x1 convolution to one channel) and the loss.
 // --------------------------------------------------------------------------
 __global__ void k_head(View x, long long npix, const __bf16 *__restrict__ w, const float *__restrict__ bias,
-                       float *__restrict__ out) {
+                       const __bf16 *__restrict__ wm, const float *__restrict__ bm, float *__restrict__ out,
+                       float *__restrict__ out_m) {
     const long long pix = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (pix >= npix) return;
-    float acc = bias[0];
+    float acc = bias[0], accm = out_m ? bm[0] : 0.f;
     for (int c = 0; c < x.C; c += 8) {
         const bf8 v = *reinterpret_cast<const bf8 *>(x.p + pix * x.stride + c);
 #pragma unroll
-        for (int e = 0; e < 8; ++e) acc = fmaf((float)w[c + e], (float)v[e], acc);
+        for (int e = 0; e < 8; ++e) {
+            acc = fmaf((float)w[c + e], (float)v[e], acc);
+            if (out_m) accm = fmaf((float)wm[c + e], (float)v[e], accm);
+        }
     }
     out[pix] = acc;
+    if (out_m) out_m[pix] = accm;
 }
 
-// g = (2/B)(out - t); dx[pixel][c] = g w[c]; per-block partials of the loss
-// (FP64) and of the head gradients sum_p g x[p][c], sum_p g (FP32).
+// approximated Heaviside of the modulation branch and its derivative
+__device__ __forceinline__ float ahf(float z) { return 0.5f * (1.f + (2.f / 3.14159265358979f) * atanf(z / DSN_EPS_AHF)); }
+__device__ __forceinline__ float ahf_grad(float z) {
+    return (1.f / 3.14159265358979f) * DSN_EPS_AHF / (DSN_EPS_AHF * DSN_EPS_AHF + z * z);
+}
+
+// g = (2/B)(out - t); with the modulation head also gm = (2/B)(H(out_m) - t_m)
+// H'(out_m) (0 without t_m); dx[pixel][c] = g w[c] + gm wm[c]; per-block
+// partials of both losses (FP64) and of both heads' gradients (FP32):
+// gpart[block][h][C + 1] = {sum_p g_h x[p][c], sum_p g_h}.
 __global__ __launch_bounds__(256) void k_head_bwd(View x, long long npix, int B, const __bf16 *__restrict__ w,
-                                                   const float *__restrict__ out, const float *__restrict__ tgt,
-                                                   View dx, double *__restrict__ loss_part,
-                                                   float *__restrict__ gpart) {
+                                                   const __bf16 *__restrict__ wm, const float *__restrict__ out,
+                                                   const float *__restrict__ out_m, const float *__restrict__ tgt,
+                                                   const float *__restrict__ tgt_m, View dx,
+                                                   double *__restrict__ loss_part, float *__restrict__ gpart) {
     const int C = x.C;                      // <= 64
-    __shared__ double lred[256];
+    const int NH = out_m ? 2 : 1;
+    __shared__ double lred[2][256];
     __shared__ float gred[256][65];
     const long long pix = (long long)blockIdx.x * 256 + threadIdx.x;
-    double l = 0.0;
-    for (int c = 0; c <= C; ++c) gred[threadIdx.x][c] = 0.f;
+    double l = 0.0, lm = 0.0;
+    float g = 0.f, gm = 0.f;
+    bf8 v[8];
     if (pix < npix) {
         const float d = out[pix] - tgt[pix];
         l = (double)d * d;
-        const float g = 2.f / (float)B * d;
+        g = 2.f / (float)B * d;
+        if (out_m && tgt_m) {
+            const float z = out_m[pix], hm = ahf(z) - tgt_m[pix];
+            lm = (double)hm * hm;
+            gm = 2.f / (float)B * hm * ahf_grad(z);
+        }
         for (int c = 0; c < C; c += 8) {
-            const bf8 v = *reinterpret_cast<const bf8 *>(x.p + pix * x.stride + c);
+            v[c / 8] = *reinterpret_cast<const bf8 *>(x.p + pix * x.stride + c);
             bf8 o;
 #pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                o[e] = (__bf16)(g * (float)w[c + e]);
-                gred[threadIdx.x][c + e] = g * (float)v[e];
-            }
+            for (int e = 0; e < 8; ++e)
+                o[e] = (__bf16)(g * (float)w[c + e] + (out_m ? gm * (float)wm[c + e] : 0.f));
             *reinterpret_cast<bf8 *>(dx.p + pix * dx.stride + c) = o;
         }
-        gred[threadIdx.x][C] = g;
     }
-    lred[threadIdx.x] = l;
-    __syncthreads();
+    lred[0][threadIdx.x] = l;
+    lred[1][threadIdx.x] = lm;
+    for (int h = 0; h < NH; ++h) {
+        const float gh = h == 0 ? g : gm;
+        for (int c = 0; c < C; c += 8)
+#pragma unroll
+            for (int e = 0; e < 8; ++e) gred[threadIdx.x][c + e] = pix < npix ? gh * (float)v[c / 8][e] : 0.f;
+        gred[threadIdx.x][C] = pix < npix ? gh : 0.f;
+        __syncthreads();
+        if (threadIdx.x <= C) {
+            float sum = 0.f;
+            for (int i = 0; i < 256; ++i) sum += gred[i][threadIdx.x];
+            gpart[((size_t)blockIdx.x * NH + h) * (C + 1) + threadIdx.x] = sum;
+        }
+        __syncthreads();
+    }
     if (threadIdx.x == 0) {
-        double s = 0.0;
-        for (int i = 0; i < 256; ++i) s += lred[i];
-        loss_part[blockIdx.x] = s;
-    }
-    if (threadIdx.x <= C) {
-        float s = 0.f;
-        for (int i = 0; i < 256; ++i) s += gred[i][threadIdx.x];
-        gpart[(size_t)blockIdx.x * (C + 1) + threadIdx.x] = s;
+        double s0 = 0.0, s1 = 0.0;
+        for (int i = 0; i < 256; ++i) {
+            s0 += lred[0][i];
+            s1 += lred[1][i];
+        }
+        loss_part[2 * blockIdx.x] = s0;
+        loss_part[2 * blockIdx.x + 1] = s1;
     }
 }
 
 __global__ void k_loss_finish(const double *__restrict__ part, int n, int B, double *__restrict__ loss) {
-    __shared__ double red[256];
-    double s = 0.0;
-    for (int i = threadIdx.x; i < n; i += 256) s += part[i];
-    red[threadIdx.x] = s;
+    __shared__ double red[2][256];
+    double s0 = 0.0, s1 = 0.0;
+    for (int i = threadIdx.x; i < n; i += 256) {
+        s0 += part[2 * i];
+        s1 += part[2 * i + 1];
+    }
+    red[0][threadIdx.x] = s0;
+    red[1][threadIdx.x] = s1;
     __syncthreads();
     if (threadIdx.x == 0) {
-        double t = 0.0;
-        for (int i = 0; i < 256; ++i) t += red[i];
-        loss[0] = t / B;
+        double t0 = 0.0, t1 = 0.0;
+        for (int i = 0; i < 256; ++i) {
+            t0 += red[0][i];
+            t1 += red[1][i];
+        }
+        loss[0] = t0 / B;
+        loss[1] = t1 / B;
     }
 }
 
@@ -593,8 +633,9 @@ __global__ void k_adam(float *__restrict__ p, float *__restrict__ m, float *__re
 // --------------------------------------------------------------------------
 // Resampling between the fine grid (4H x 4W) and the network grid (H x W).
 // --------------------------------------------------------------------------
-__global__ void k_prepare(const unsigned char *__restrict__ tgt, const float *__restrict__ phi, int B, int H,
-                          int W, float *__restrict__ x, float *__restrict__ t) {
+__global__ void k_prepare(const unsigned char *__restrict__ tgt, const float *__restrict__ phi,
+                          const float *__restrict__ mgt, int B, int H, int W, float *__restrict__ x,
+                          float *__restrict__ t, float *__restrict__ tm) {
     const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (id >= (long long)B * H * W) return;
     const int xx = (int)(id % W);
@@ -602,20 +643,22 @@ __global__ void k_prepare(const unsigned char *__restrict__ tgt, const float *__
     const int yy = (int)(r % H), b = (int)(r / H);
     const int W4 = 4 * W, H4 = 4 * H;
     int cnt = 0;
-    double s = 0.0;
+    double s = 0.0, sm = 0.0;
     for (int a = 0; a < 4; ++a)
         for (int c = 0; c < 4; ++c) {
             const size_t q = ((size_t)b * H4 + 4 * yy + a) * W4 + 4 * xx + c;
             cnt += tgt[q] != 0;
             if (phi) s += phi[q];
+            if (mgt) sm += mgt[q];
         }
     x[id] = (float)cnt * (1.f / 16.f);
     if (phi) t[id] = (float)(s / 16.0 / (double)DSN_SCALE);
+    if (mgt) tm[id] = (float)(sm / 16.0);
 }
 
 // phi0 = clip(100 x bilinear 4x upsampling): fine pixel i samples the network
 // coordinate (i + 1/2)/4 - 1/2, clamped to [0, n - 1].
-__global__ void k_phi0(const float *__restrict__ out, int B, int H, int W, float lo, float hi,
+__global__ void k_phi0(const float *__restrict__ out, int B, int H, int W, float lo, float hi, int is_mod,
                        float *__restrict__ phi0) {
     const int W4 = 4 * W, H4 = 4 * H;
     const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -629,10 +672,16 @@ __global__ void k_phi0(const float *__restrict__ out, int B, int H, int W, float
     const int y1 = min(y0 + 1, H - 1), x1 = min(x0 + 1, W - 1);
     const float fy = ty - y0, fx = tx - x0;
     const float *o = out + (size_t)b * H * W;
-    const float top = o[(size_t)y0 * W + x0] * (1.f - fx) + o[(size_t)y0 * W + x1] * fx;
-    const float bot = o[(size_t)y1 * W + x0] * (1.f - fx) + o[(size_t)y1 * W + x1] * fx;
-    const float v = DSN_SCALE * (top * (1.f - fy) + bot * fy);
-    phi0[id] = fminf(fmaxf(v, lo), hi);
+    // phi_0: 100 x bilinear of the prediction, clipped; modulation: bilinear
+    // of H_eps of the prediction
+    auto val = [&](int yy_, int xx_) {
+        const float v = o[(size_t)yy_ * W + xx_];
+        return is_mod ? ahf(v) : v;
+    };
+    const float top = val(y0, x0) * (1.f - fx) + val(y0, x1) * fx;
+    const float bot = val(y1, x0) * (1.f - fx) + val(y1, x1) * fx;
+    const float v = top * (1.f - fy) + bot * fy;
+    phi0[id] = is_mod ? v : fminf(fmaxf(DSN_SCALE * v, lo), hi);
 }
 
 inline unsigned grid1(long long n, int bs = 256) { return (unsigned)((n + bs - 1) / bs); }
@@ -647,7 +696,7 @@ struct dsn_layer {
 };
 
 struct dsn_ctx {
-    int H, W, base, maxB;
+    int H, W, base, maxB, modulation;
     hipStream_t stream;
     int C[DSN_LEVELS], h[DSN_LEVELS], w[DSN_LEVELS];
     long long np[DSN_LEVELS];          // pixels per level at max batch
@@ -661,6 +710,7 @@ struct dsn_ctx {
     __bf16 *act_a[DSN_LEVELS] = {}, *cat[DSN_LEVELS] = {}, *pool[DSN_LEVELS] = {}, *bott = nullptr;
     __bf16 *dec_a[DSN_LEVELS] = {}, *dec_b[DSN_LEVELS] = {};
     float *out = nullptr;                  // forward output [B][H][W] (caller's, kept)
+    float *out_m = nullptr;                // modulation output of the last forward (caller's) or NULL
     int fwdB = 0;
     // gradients
     __bf16 *gA[DSN_LEVELS] = {}, *gB[DSN_LEVELS] = {}, *gcat[DSN_LEVELS] = {};
@@ -668,19 +718,21 @@ struct dsn_ctx {
     long long part_cap = 0;
     double *lpart = nullptr;
     float *hpart = nullptr;
-    float *net_x = nullptr, *net_out = nullptr;   // predict scratch
+    float *net_x = nullptr, *net_out = nullptr, *net_out_m = nullptr;   // predict scratch
     std::vector<void *> allocs;
 };
 
 namespace {
 
-enum { ENC0A = 0 };   // layer indices: enc l a = 2l, enc l b = 2l + 1; dec l: 8 + 3 (2 - l) + {0 up, 1 a, 2 b}; head 17
+// layer indices: enc l a = 2l, enc l b = 2l + 1; dec l: 8 + 3 (2 - l) + {0 up, 1 a, 2 b}; head 17;
+// modulation head 18.  Only the layers before the heads are 3x3 convolutions.
 inline int enc_a(int l) { return 2 * l; }
 inline int enc_b(int l) { return 2 * l + 1; }
 inline int dec_up(int l) { return 2 * DSN_LEVELS + 3 * (DSN_LEVELS - 2 - l); }
 inline int dec_a_i(int l) { return dec_up(l) + 1; }
 inline int dec_b_i(int l) { return dec_up(l) + 2; }
 inline int head_i() { return 2 * DSN_LEVELS + 3 * (DSN_LEVELS - 1); }
+inline int head_m_i() { return head_i() + 1; }
 
 View view(__bf16 *p, int C, int stride) { return View{p, C, stride}; }
 
@@ -776,19 +828,21 @@ int check_ptr(const void *p, const char *name) {
 
 extern "C" const char *dsn_last_error(void) { return g_err.c_str(); }
 
-extern "C" int dsn_create(dsn_ctx **out, int H, int W, int base, int maxB, void *stream) {
+extern "C" int dsn_create(dsn_ctx **out, int H, int W, int base, int maxB, int modulation, void *stream) {
     if (!out) return fail(DSN_EINVAL, "out is NULL");
     *out = nullptr;
     if (H < 8 || W < 8 || H % 8 || W % 8 || H > 2048 || W > 2048)
         return fail(DSN_EINVAL, "H and W must be multiples of 8 in [8, 2048]");
     if (base != 32 && base != 64) return fail(DSN_EINVAL, "base must be 32 or 64");
     if (maxB < 1) return fail(DSN_EINVAL, "max_batch must be >= 1");
+    if (modulation != 0 && modulation != 1) return fail(DSN_EINVAL, "modulation must be 0 or 1");
     dsn_ctx *c = new (std::nothrow) dsn_ctx();
     if (!c) return fail(DSN_ENOMEM, "out of host memory");
     c->H = H;
     c->W = W;
     c->base = base;
     c->maxB = maxB;
+    c->modulation = modulation;
     c->stream = static_cast<hipStream_t>(stream);
     for (int l = 0; l < DSN_LEVELS; ++l) {
         c->C[l] = base << l;
@@ -815,10 +869,11 @@ extern "C" int dsn_create(dsn_ctx **out, int H, int W, int base, int maxB, void 
         add(c->C[l], c->C[l], 9);
     }
     add(c->C[0], 1, 1);
+    if (modulation) add(c->C[0], 1, 1);
     c->n_params = off;
     // scratch for split weight gradients: the largest S * Cout * 9 * Cin
     long long cap = 0;
-    for (size_t i = 0; i + 1 < c->L.size(); ++i) {
+    for (int i = 0; i < head_i(); ++i) {
         int l = 0;
         if (i < 2 * DSN_LEVELS) l = (int)i / 2;
         else l = DSN_LEVELS - 2 - (int)(i - 2 * DSN_LEVELS) / 3;
@@ -849,10 +904,11 @@ extern "C" int dsn_create(dsn_ctx **out, int H, int W, int base, int maxB, void 
     }
     if (e == hipSuccess) e = dalloc(c, &c->bott, c->np[DSN_LEVELS - 1] * c->C[DSN_LEVELS - 1]);
     const long long nblk = (c->np[0] + 255) / 256;
-    if (e == hipSuccess) e = dalloc(c, &c->lpart, nblk);
-    if (e == hipSuccess) e = dalloc(c, &c->hpart, nblk * (c->C[0] + 1));
+    if (e == hipSuccess) e = dalloc(c, &c->lpart, 2 * nblk);
+    if (e == hipSuccess) e = dalloc(c, &c->hpart, nblk * 2 * (c->C[0] + 1));
     if (e == hipSuccess) e = dalloc(c, &c->net_x, c->np[0]);
     if (e == hipSuccess) e = dalloc(c, &c->net_out, c->np[0]);
+    if (e == hipSuccess && modulation) e = dalloc(c, &c->net_out_m, c->np[0]);
     if (e == hipSuccess) e = hipMemsetAsync(c->p, 0, n * sizeof(float), c->stream);
     if (e == hipSuccess) e = hipMemsetAsync(c->pb, 0, n * sizeof(__bf16), c->stream);
     if (e != hipSuccess) {
@@ -894,9 +950,11 @@ extern "C" int dsn_get_params(const dsn_ctx *c, float *d) {
     return DSN_OK;
 }
 
-extern "C" int dsn_forward(dsn_ctx *c, const float *d_x, int B, float *d_out) {
+extern "C" int dsn_forward(dsn_ctx *c, const float *d_x, int B, float *d_out, float *d_out_m) {
     int r;
     if ((r = check_ctx(c)) || (r = check_ptr(d_x, "d_x")) || (r = check_ptr(d_out, "d_out"))) return r;
+    if (d_out_m && (r = check_ptr(d_out_m, "d_out_m"))) return r;
+    if (d_out_m && !c->modulation) return fail(DSN_EINVAL, "d_out_m given but the network has no modulation head");
     if (B < 1 || B > c->maxB) return fail(DSN_EINVAL, "B must be in [1, %d]", c->maxB);
     const int NL = DSN_LEVELS;
     // encoder
@@ -934,24 +992,29 @@ extern "C" int dsn_forward(dsn_ctx *c, const float *d_x, int B, float *d_out) {
     }
     const dsn_layer &hd = c->L[head_i()];
     const long long npix = (long long)B * c->h[0] * c->w[0];
+    const dsn_layer &hm = c->L[c->modulation ? head_m_i() : head_i()];
     k_head<<<grid1(npix), 256, 0, c->stream>>>(view(c->dec_b[0], c->C[0], c->C[0]), npix, c->pb + hd.w_off,
-                                               c->p + hd.b_off, d_out);
+                                               c->p + hd.b_off, c->pb + hm.w_off, c->p + hm.b_off, d_out, d_out_m);
     HIPCHK(hipGetLastError());
     c->x_in = const_cast<float *>(d_x);
     c->out = d_out;
+    c->out_m = d_out_m;
     c->fwdB = B;
     return DSN_OK;
 }
 
-extern "C" int dsn_backward(dsn_ctx *c, const float *d_target, int B, double *d_loss, float *d_grad) {
+extern "C" int dsn_backward(dsn_ctx *c, const float *d_target, const float *d_target_m, int B, double *d_loss,
+                            float *d_grad) {
     int r;
     if ((r = check_ctx(c)) || (r = check_ptr(d_target, "d_target"))) return r;
+    if (d_target_m && (r = check_ptr(d_target_m, "d_target_m"))) return r;
+    if (d_target_m && !c->out_m) return fail(DSN_EINVAL, "d_target_m needs a forward pass with d_out_m");
     if (!d_loss) return fail(DSN_EINVAL, "d_loss is NULL");
     if (d_grad && (r = check_ptr(d_grad, "d_grad"))) return r;
     if (B != c->fwdB || !c->out) return fail(DSN_EINVAL, "backward needs a forward pass with the same batch");
     const int NL = DSN_LEVELS;
     // flipped/transposed weights for the input gradients
-    for (size_t i = 0; i + 1 < c->L.size(); ++i) {
+    for (int i = 0; i < head_i(); ++i) {
         const dsn_layer &ly = c->L[i];
         const long long n = (long long)ly.cout * 9 * ly.cin;
         k_flip_transpose<<<grid1(n), 256, 0, c->stream>>>(c->pb + ly.w_off, ly.cout, ly.cin, c->pt + ly.w_off);
@@ -962,14 +1025,24 @@ extern "C" int dsn_backward(dsn_ctx *c, const float *d_target, int B, double *d_
     const long long np0 = (long long)B * c->h[0] * c->w[0];
     const dsn_layer &hd = c->L[head_i()];
     const unsigned nblk = grid1(np0);
-    k_head_bwd<<<nblk, 256, 0, c->stream>>>(view(c->dec_b[0], C0, C0), np0, B, c->pb + hd.w_off, c->out, d_target,
+    // the modulation head takes part only when its target is given; otherwise
+    // its gradient is zero and L_m is reported as 0
+    const int with_m = d_target_m != nullptr;
+    const dsn_layer &hm = c->L[c->modulation ? head_m_i() : head_i()];
+    k_head_bwd<<<nblk, 256, 0, c->stream>>>(view(c->dec_b[0], C0, C0), np0, B, c->pb + hd.w_off, c->pb + hm.w_off,
+                                            c->out, with_m ? c->out_m : nullptr, d_target, d_target_m,
                                             view(c->gA[0], C0, C0), c->lpart, c->hpart);
     HIPCHK(hipGetLastError());
     k_loss_finish<<<1, 256, 0, c->stream>>>(c->lpart, (int)nblk, B, d_loss);
     HIPCHK(hipGetLastError());
-    // hpart [nblk][C0 + 1] -> weights then bias (contiguous in the flat vector)
-    k_reduce_splits<<<grid1(C0 + 1), 256, 0, c->stream>>>(c->hpart, (int)nblk, C0 + 1, c->grad + hd.w_off);
+    // hpart [nblk][heads][C0 + 1] -> each head's weights then bias; the two
+    // heads are adjacent in the flat vector
+    const int nh = with_m ? 2 : 1;
+    k_reduce_splits<<<grid1(nh * (C0 + 1)), 256, 0, c->stream>>>(c->hpart, (int)nblk, nh * (C0 + 1),
+                                                                   c->grad + hd.w_off);
     HIPCHK(hipGetLastError());
+    if (c->modulation && !with_m)
+        HIPCHK(hipMemsetAsync(c->grad + hm.w_off, 0, (C0 + 1) * sizeof(float), c->stream));
     // decoder, bottom-up in the backward order
     for (int l = 0; l <= NL - 2; ++l) {
         const int C = c->C[l], C1 = c->C[l + 1];
@@ -1051,28 +1124,36 @@ extern "C" int dsn_adam_step(dsn_ctx *c, float lr, float b1, float b2, float eps
     return DSN_OK;
 }
 
-extern "C" int dsn_prepare(dsn_ctx *c, const unsigned char *d_target, const float *d_phi_gt, int B, float *d_x,
-                           float *d_t) {
+extern "C" int dsn_prepare(dsn_ctx *c, const unsigned char *d_target, const float *d_phi_gt, const float *d_m_gt,
+                           int B, float *d_x, float *d_t, float *d_t_m) {
     int r;
     if ((r = check_ctx(c)) || (r = check_ptr(d_target, "d_target")) || (r = check_ptr(d_x, "d_x"))) return r;
     if (d_phi_gt && ((r = check_ptr(d_phi_gt, "d_phi_gt")) || (r = check_ptr(d_t, "d_t")))) return r;
+    if (d_m_gt && ((r = check_ptr(d_m_gt, "d_m_gt")) || (r = check_ptr(d_t_m, "d_t_m")))) return r;
     if (B < 1) return fail(DSN_EINVAL, "B must be >= 1");
-    k_prepare<<<grid1((long long)B * c->H * c->W), 256, 0, c->stream>>>(d_target, d_phi_gt, B, c->H, c->W, d_x,
-                                                                        d_t);
+    k_prepare<<<grid1((long long)B * c->H * c->W), 256, 0, c->stream>>>(d_target, d_phi_gt, d_m_gt, B, c->H, c->W,
+                                                                        d_x, d_t, d_t_m);
     HIPCHK(hipGetLastError());
     return DSN_OK;
 }
 
-extern "C" int dsn_predict(dsn_ctx *c, const unsigned char *d_target, int B, float lo, float hi, float *d_phi0) {
+extern "C" int dsn_predict(dsn_ctx *c, const unsigned char *d_target, int B, float lo, float hi, float *d_phi0,
+                           float *d_m0) {
     int r;
     if ((r = check_ctx(c)) || (r = check_ptr(d_target, "d_target")) || (r = check_ptr(d_phi0, "d_phi0"))) return r;
+    if (d_m0 && (r = check_ptr(d_m0, "d_m0"))) return r;
+    if (d_m0 && !c->modulation) return fail(DSN_EINVAL, "d_m0 given but the network has no modulation head");
     if (B < 1 || B > c->maxB) return fail(DSN_EINVAL, "B must be in [1, %d]", c->maxB);
     if (!(lo < hi)) return fail(DSN_EINVAL, "d_lower must be below d_upper");
-    if ((r = dsn_prepare(c, d_target, nullptr, B, c->net_x, nullptr))) return r;
-    if ((r = dsn_forward(c, c->net_x, B, c->net_out))) return r;
+    if ((r = dsn_prepare(c, d_target, nullptr, nullptr, B, c->net_x, nullptr, nullptr))) return r;
+    if ((r = dsn_forward(c, c->net_x, B, c->net_out, d_m0 ? c->net_out_m : nullptr))) return r;
     const long long n = (long long)B * 16 * c->H * c->W;
-    k_phi0<<<grid1(n), 256, 0, c->stream>>>(c->net_out, B, c->H, c->W, lo, hi, d_phi0);
+    k_phi0<<<grid1(n), 256, 0, c->stream>>>(c->net_out, B, c->H, c->W, lo, hi, 0, d_phi0);
     HIPCHK(hipGetLastError());
+    if (d_m0) {
+        k_phi0<<<grid1(n), 256, 0, c->stream>>>(c->net_out_m, B, c->H, c->W, 0.f, 1.f, 1, d_m0);
+        HIPCHK(hipGetLastError());
+    }
     return DSN_OK;
 }
 

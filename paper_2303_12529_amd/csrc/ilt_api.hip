@@ -531,8 +531,10 @@ extern "C" int edt_reinit(ilt_ctx *c, const float *d_phi, const unsigned char *d
 
 namespace {
 
-// Enqueue the whole solve (init, T iterations, final metrics) on c->stream.
-int enqueue_solve(ilt_ctx *c, const unsigned char *d_target, float *d_phi, const ilt_params *p, double *d_trace) {
+// Enqueue the whole solve (init, T iterations, final metrics) on c->stream;
+// d_mod: the curvature term's modulation map, or NULL for m = 1.
+int enqueue_solve(ilt_ctx *c, const unsigned char *d_target, float *d_phi, const float *d_mod, const ilt_params *p,
+                  double *d_trace) {
     const resist_args ra = make_resist_args(p);
     int slo, shi;
     used_set_range(p, &slo, &shi);
@@ -586,7 +588,7 @@ int enqueue_solve(ilt_ctx *c, const unsigned char *d_target, float *d_phi, const
         }
         {
             PhaseTimer t(c, 6);
-            HIPCHK(launch_levelset(c, cur, p->optimizer == 1 ? c->dcg : c->g, nullptr, p->lambda, p->eps_kappa,
+            HIPCHK(launch_levelset(c, cur, p->optimizer == 1 ? c->dcg : c->g, d_mod, p->lambda, p->eps_kappa,
                                    c->scal, nxt, ps));
             HIPCHK(launch_finish_step(c, ps, step_blocks(c), c->scal, nullptr,
                                       d_trace ? d_trace + (size_t)i * ILT_TRACE_W : nullptr, i));
@@ -612,20 +614,21 @@ int enqueue_solve(ilt_ctx *c, const unsigned char *d_target, float *d_phi, const
     return ILT_OK;
 }
 
-int graph_key(const unsigned char *d_target, const float *d_phi, const ilt_params *p, const double *d_trace,
-              unsigned char *key) {
+static_assert(4 * sizeof(void *) + sizeof(ilt_params) <= sizeof(ilt_ctx::graph_key), "graph key buffer too small");
+
+int graph_key(const unsigned char *d_target, const float *d_phi, const float *d_mod, const ilt_params *p,
+              const double *d_trace, unsigned char *key) {
     int n = 0;
     std::memcpy(key + n, &d_target, sizeof d_target); n += sizeof d_target;
     std::memcpy(key + n, &d_phi, sizeof d_phi); n += sizeof d_phi;
+    std::memcpy(key + n, &d_mod, sizeof d_mod); n += sizeof d_mod;
     std::memcpy(key + n, &d_trace, sizeof d_trace); n += sizeof d_trace;
     std::memcpy(key + n, p, sizeof *p); n += sizeof *p;
     return n;
 }
 
-}  // namespace
-
-extern "C" int ilt_solve(ilt_ctx *c, const unsigned char *d_target, float *d_phi, const ilt_params *p,
-                         ilt_report *h_report, double *d_trace) {
+int solve(ilt_ctx *c, const unsigned char *d_target, float *d_phi, const float *d_mod, const ilt_params *p,
+          ilt_report *h_report, double *d_trace) {
     int r;
     if ((r = check_ctx(c))) return r;
     if ((r = check_ptr(d_target, "d_target", 1))) return r;
@@ -638,7 +641,7 @@ extern "C" int ilt_solve(ilt_ctx *c, const unsigned char *d_target, float *d_phi
     // solve with the measurement hook on launches directly
     if (c->use_graph && !c->profiling) {
         unsigned char key[sizeof c->graph_key];
-        const int klen = graph_key(d_target, d_phi, p, d_trace, key);
+        const int klen = graph_key(d_target, d_phi, d_mod, p, d_trace, key);
         if (!c->graph_exec || klen != c->graph_key_len || std::memcmp(key, c->graph_key, klen) != 0) {
             free_graph(c);
             hipStream_t user = c->stream;
@@ -648,7 +651,7 @@ extern "C" int ilt_solve(ilt_ctx *c, const unsigned char *d_target, float *d_phi
                 c->stream = user;
                 return fail(ILT_EDEVICE, "hipStreamBeginCapture: %s", hipGetErrorString(e));
             }
-            const int rc = enqueue_solve(c, d_target, d_phi, p, d_trace);
+            const int rc = enqueue_solve(c, d_target, d_phi, d_mod, p, d_trace);
             hipGraph_t g = nullptr;
             e = hipStreamEndCapture(c->cap_stream, &g);
             c->stream = user;
@@ -668,7 +671,7 @@ extern "C" int ilt_solve(ilt_ctx *c, const unsigned char *d_target, float *d_phi
         }
         HIPCHK(hipGraphLaunch(c->graph_exec, c->stream));
     } else {
-        if ((r = enqueue_solve(c, d_target, d_phi, p, d_trace))) return r;
+        if ((r = enqueue_solve(c, d_target, d_phi, d_mod, p, d_trace))) return r;
     }
     double sc[SC_COUNT];
     HIPCHK(hipMemcpyAsync(sc, c->scal, sizeof sc, hipMemcpyDeviceToHost, c->stream));
@@ -684,6 +687,21 @@ extern "C" int ilt_solve(ilt_ctx *c, const unsigned char *d_target, float *d_phi
     if (sc[SC_NONFIN] > 0.0 || !std::isfinite(sc[SC_LOSS]))
         return fail(ILT_ENUMERIC, "non-finite loss or gradient in the loop");
     return ILT_OK;
+}
+
+}  // namespace
+
+extern "C" int ilt_solve(ilt_ctx *c, const unsigned char *d_target, float *d_phi, const ilt_params *p,
+                         ilt_report *h_report, double *d_trace) {
+    return solve(c, d_target, d_phi, nullptr, p, h_report, d_trace);
+}
+
+extern "C" int ilt_solve_modulated(ilt_ctx *c, const unsigned char *d_target, float *d_phi, const float *d_mod,
+                                   const ilt_params *p, ilt_report *h_report, double *d_trace) {
+    int r;
+    if ((r = check_ctx(c))) return r;
+    if ((r = check_ptr(d_mod, "d_mod"))) return r;
+    return solve(c, d_target, d_phi, d_mod, p, h_report, d_trace);
 }
 
 extern "C" int ilt_set_graph(ilt_ctx *c, int enable) {
@@ -863,9 +881,9 @@ extern "C" int ilt_autotune(ilt_ctx *c, const char *cache_path, ilt_tuning *h_be
     best = saved;
     for (size_t i = 0; i < cand.size() && rc == ILT_OK; ++i) {
         if ((rc = ilt_set_tuning(c, &cand[i])) != ILT_OK) break;
-        if ((rc = enqueue_solve(c, d_t, d_phi, &p, nullptr)) != ILT_OK) break;     // warm-up
+        if ((rc = enqueue_solve(c, d_t, d_phi, nullptr, &p, nullptr)) != ILT_OK) break;     // warm-up
         if ((e = hipEventRecord(e0, c->stream)) != hipSuccess) break;
-        for (int rep = 0; rep < 2 && rc == ILT_OK; ++rep) rc = enqueue_solve(c, d_t, d_phi, &p, nullptr);
+        for (int rep = 0; rep < 2 && rc == ILT_OK; ++rep) rc = enqueue_solve(c, d_t, d_phi, nullptr, &p, nullptr);
         if (rc != ILT_OK) break;
         if ((e = hipEventRecord(e1, c->stream)) != hipSuccess) break;
         if ((e = hipEventSynchronize(e1)) != hipSuccess) break;
@@ -991,7 +1009,7 @@ int enqueue_lane(ilt_batch *b, int l, int n, const ilt_clip *clips, const std::v
     for (int i = 0; i < n; ++i) {
         if (lane_of[i] != l) continue;
         ilt_ctx *c = b->ctx[size_index(b, clips[i].N)][l];
-        int r = enqueue_solve(c, clips[i].d_target, clips[i].d_phi, &clips[i].params, clips[i].d_trace);
+        int r = enqueue_solve(c, clips[i].d_target, clips[i].d_phi, nullptr, &clips[i].params, clips[i].d_trace);
         if (r != ILT_OK) return r;
         HIPCHK(launch_copy(c, reinterpret_cast<float *>(b->d_reports + (size_t)i * SC_COUNT),
                            reinterpret_cast<const float *>(c->scal), 2 * SC_COUNT));

@@ -1,4 +1,5 @@
-"""Python binding of the DevelSet-Net level-set branch (include/dsn.h).
+"""Python binding of DevelSet-Net (include/dsn.h): the level-set branch and
+the optional modulation branch.
 
 Marshalling only: shapes, dtypes and devices are checked here and every
 computation runs in the HIP kernels of libilt.so (no fallback).
@@ -14,6 +15,7 @@ from . import ilt as _ilt
 DSN_OK = 0
 LEVELS = 4
 SCALE = 100.0
+EPS_AHF = 0.03
 
 _VP = ctypes.c_void_p
 _sigs_done = False
@@ -24,15 +26,16 @@ def _lib():
     lib = _ilt.load_library()
     if not _sigs_done:
         sig = {
-            "dsn_create": [ctypes.POINTER(_VP), ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, _VP],
+            "dsn_create": [ctypes.POINTER(_VP), ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                           _VP],
             "dsn_destroy": [_VP],
             "dsn_set_params": [_VP, _VP],
             "dsn_get_params": [_VP, _VP],
-            "dsn_forward": [_VP, _VP, ctypes.c_int, _VP],
-            "dsn_backward": [_VP, _VP, ctypes.c_int, _VP, _VP],
+            "dsn_forward": [_VP, _VP, ctypes.c_int, _VP, _VP],
+            "dsn_backward": [_VP, _VP, _VP, ctypes.c_int, _VP, _VP],
             "dsn_adam_step": [_VP, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float],
-            "dsn_prepare": [_VP, _VP, _VP, ctypes.c_int, _VP, _VP],
-            "dsn_predict": [_VP, _VP, ctypes.c_int, ctypes.c_float, ctypes.c_float, _VP],
+            "dsn_prepare": [_VP, _VP, _VP, _VP, ctypes.c_int, _VP, _VP, _VP],
+            "dsn_predict": [_VP, _VP, ctypes.c_int, ctypes.c_float, ctypes.c_float, _VP, _VP],
             "dsn_op_conv3x3": [_VP, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, _VP, _VP,
                                ctypes.c_int, ctypes.c_int, _VP, _VP],
             "dsn_op_conv3x3_dgrad": [_VP, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, _VP, ctypes.c_int,
@@ -76,7 +79,7 @@ def _ptr(t, dtype, shape, name):
     return _VP(t.data_ptr())
 
 
-def layer_table(base: int = 32):
+def layer_table(base: int = 32, modulation: bool = False):
     """[(name, weight shape, bias shape, weight offset, bias offset)] in the
     flat parameter order of include/dsn.h."""
     ch = [base << i for i in range(LEVELS)]
@@ -91,6 +94,8 @@ def layer_table(base: int = 32):
         rows.append(("dec%d_a" % l, (ch[l], 3, 3, 2 * ch[l])))
         rows.append(("dec%d_b" % l, (ch[l], 3, 3, ch[l])))
     rows.append(("head", (1, 1, 1, ch[0])))
+    if modulation:
+        rows.append(("head_m", (1, 1, 1, ch[0])))
     out = []
     off = 0
     for name, ws in rows:
@@ -100,10 +105,12 @@ def layer_table(base: int = 32):
     return out
 
 
-def he_init(seed: int, base: int = 32) -> np.ndarray:
-    """Flat FP32 parameters: He-normal weights (std sqrt(2 / fan_in)), zero biases."""
+def he_init(seed: int, base: int = 32, modulation: bool = False) -> np.ndarray:
+    """Flat FP32 parameters: He-normal weights (std sqrt(2 / fan_in)), zero
+    biases.  The modulation head's weights are drawn after all others, so the
+    shared layers are the same with and without it."""
     rng = np.random.default_rng(seed)
-    tab = layer_table(base)
+    tab = layer_table(base, modulation)
     n = tab[-1][4] + tab[-1][2][0]
     flat = np.zeros(n, dtype=np.float32)
     for name, ws, bs, wo, bo in tab:
@@ -113,21 +120,23 @@ def he_init(seed: int, base: int = 32) -> np.ndarray:
 
 
 class Net:
-    """The level-set branch on the current device and torch stream."""
+    """DevelSet-Net on the current device and torch stream; `modulation`
+    adds the modulation branch's head."""
 
-    def __init__(self, H: int = 512, W: int = 512, base: int = 32, max_batch: int = 16):
+    def __init__(self, H: int = 512, W: int = 512, base: int = 32, max_batch: int = 16, modulation: bool = False):
         import torch
         lib = _lib()
         self.device = torch.device("cuda", torch.cuda.current_device())
         self.stream = torch.cuda.current_stream(self.device)
         h = _VP()
-        _check(lib.dsn_create(ctypes.byref(h), int(H), int(W), int(base), int(max_batch),
+        _check(lib.dsn_create(ctypes.byref(h), int(H), int(W), int(base), int(max_batch), int(bool(modulation)),
                               _VP(self.stream.cuda_stream)))
         self._h = h
         self.H, self.W, self.base, self.max_batch = int(H), int(W), int(base), int(max_batch)
+        self.modulation = bool(modulation)
         self.n_params = int(lib.dsn_num_params(h))
         self._keep = None
-        self.loss_buf = torch.zeros(1, dtype=torch.float64, device=self.device)
+        self.loss_buf = torch.zeros(2, dtype=torch.float64, device=self.device)
 
     def close(self):
         if getattr(self, "_h", None):
@@ -152,49 +161,69 @@ class Net:
         _check(_lib().dsn_get_params(self._h, _ptr(t, torch.float32, None, "params")))
         return t
 
-    def forward(self, x, out=None):
+    def forward(self, x, out=None, out_m=None):
+        """Level-set output [B, H, W]; with the modulation head, the pair
+        (out, out_m), out_m being phi_m before the approximated Heaviside."""
         import torch
         B = int(x.shape[0])
+        shape = (B, self.H, self.W)
         if out is None:
-            out = torch.empty((B, self.H, self.W), dtype=torch.float32, device=self.device)
-        _check(_lib().dsn_forward(self._h, _ptr(x, torch.float32, (B, self.H, self.W), "x"), B,
-                                  _ptr(out, torch.float32, (B, self.H, self.W), "out")))
-        self._keep = (x, out)          # read again by backward
-        return out
+            out = torch.empty(shape, dtype=torch.float32, device=self.device)
+        if self.modulation and out_m is None:
+            out_m = torch.empty(shape, dtype=torch.float32, device=self.device)
+        _check(_lib().dsn_forward(self._h, _ptr(x, torch.float32, shape, "x"), B, _ptr(out, torch.float32, shape, "out"),
+                                  None if out_m is None else _ptr(out_m, torch.float32, shape, "out_m")))
+        self._keep = (x, out, out_m)   # read again by backward
+        return (out, out_m) if self.modulation else out
 
-    def backward(self, target, grad=None):
-        """Returns the loss tensor (device double[1]); grad: optional FP32 [n_params] out."""
+    def backward(self, target, grad=None, target_m=None):
+        """Returns the device double[2] (L_0, L_m) of the last forward; grad:
+        optional FP32 [n_params] out; target_m: modulation targets (L_m is
+        left out without them)."""
         import torch
         B = int(target.shape[0])
+        shape = (B, self.H, self.W)
         gp = None if grad is None else _ptr(grad, torch.float32, (self.n_params,), "grad")
-        _check(_lib().dsn_backward(self._h, _ptr(target, torch.float32, (B, self.H, self.W), "target"), B,
-                                   _ptr(self.loss_buf, torch.float64, (1,), "loss"), gp))
+        _check(_lib().dsn_backward(self._h, _ptr(target, torch.float32, shape, "target"),
+                                   None if target_m is None else _ptr(target_m, torch.float32, shape, "target_m"), B,
+                                   _ptr(self.loss_buf, torch.float64, (2,), "loss"), gp))
         return self.loss_buf
 
     def adam_step(self, lr: float, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8):
         _check(_lib().dsn_adam_step(self._h, float(lr), float(beta1), float(beta2), float(eps)))
 
-    def prepare(self, target, phi_gt=None):
+    def prepare(self, target, phi_gt=None, m_gt=None):
+        """Network-grid input x and, when given the fine-grid phi_gt / m_gt,
+        the targets t and t_m; returns (x, t) or, with m_gt, (x, t, t_m)."""
         import torch
         B = int(target.shape[0])
         fine = (B, 4 * self.H, 4 * self.W)
         x = torch.empty((B, self.H, self.W), dtype=torch.float32, device=self.device)
         t = None if phi_gt is None else torch.empty_like(x)
+        tm = None if m_gt is None else torch.empty_like(x)
         _check(_lib().dsn_prepare(self._h, _ptr(target, torch.uint8, fine, "target"),
-                                  None if phi_gt is None else _ptr(phi_gt, torch.float32, fine, "phi_gt"), B,
+                                  None if phi_gt is None else _ptr(phi_gt, torch.float32, fine, "phi_gt"),
+                                  None if m_gt is None else _ptr(m_gt, torch.float32, fine, "m_gt"), B,
                                   _ptr(x, torch.float32, None, "x"),
-                                  None if t is None else _ptr(t, torch.float32, None, "t")))
-        return x, t
+                                  None if t is None else _ptr(t, torch.float32, None, "t"),
+                                  None if tm is None else _ptr(tm, torch.float32, None, "t_m")))
+        return (x, t) if m_gt is None else (x, t, tm)
 
-    def predict(self, target, d_lower: float, d_upper: float, phi0=None):
+    def predict(self, target, d_lower: float, d_upper: float, phi0=None, m0=None, with_m: bool = False):
+        """phi_0 on the fine grid; with `with_m` (or m0 given) also the
+        modulation map m_0 and returns (phi0, m0)."""
         import torch
         B = int(target.shape[0])
         fine = (B, 4 * self.H, 4 * self.W)
         if phi0 is None:
             phi0 = torch.empty(fine, dtype=torch.float32, device=self.device)
+        with_m = with_m or m0 is not None
+        if with_m and m0 is None:
+            m0 = torch.empty(fine, dtype=torch.float32, device=self.device)
         _check(_lib().dsn_predict(self._h, _ptr(target, torch.uint8, fine, "target"), B, float(d_lower),
-                                  float(d_upper), _ptr(phi0, torch.float32, fine, "phi0")))
-        return phi0
+                                  float(d_upper), _ptr(phi0, torch.float32, fine, "phi0"),
+                                  _ptr(m0, torch.float32, fine, "m0") if with_m else None))
+        return (phi0, m0) if with_m else phi0
 
 
 # single operations (BF16 channels-last tensors)

@@ -89,6 +89,7 @@ def load_library(path: str = LIB_PATH):
         "levelset_step": [_VP, _VP, _VP, _VP, ctypes.POINTER(_Params), _VP],
         "edt_reinit": [_VP, _VP, _VP, _VP, _VP, ctypes.POINTER(_Params)],
         "ilt_solve": [_VP, _VP, _VP, ctypes.POINTER(_Params), ctypes.POINTER(_Report), _VP],
+        "ilt_solve_modulated": [_VP, _VP, _VP, _VP, ctypes.POINTER(_Params), ctypes.POINTER(_Report), _VP],
         "ilt_profile": [_VP, ctypes.c_int],
         "ilt_set_graph": [_VP, ctypes.c_int],
         "ilt_profile_read": [_VP, ctypes.POINTER(ctypes.c_double), ctypes.c_int],
@@ -269,15 +270,22 @@ class Context:
                                          ctypes.byref(pc)))
         return phi_out
 
-    def ilt_solve(self, target, phi, params: Params, trace=None):
+    def ilt_solve(self, target, phi, params: Params, trace=None, mod=None):
+        """The DSO loop in place on phi; mod: optional [N, N] modulation map of
+        the curvature term (ilt_solve_modulated)."""
         import torch
         pc = params.to_c()
         rep = _Report()
         tr = None
         if trace is not None:
             tr = _ptr(trace, torch.float64, (params.iters, TRACE_W), "trace", self.device)
-        rc = load_library().ilt_solve(self._h, self._img(target, "target", torch.uint8), self._img(phi, "phi"),
-                                      ctypes.byref(pc), ctypes.byref(rep), tr)
+        lib = load_library()
+        if mod is None:
+            rc = lib.ilt_solve(self._h, self._img(target, "target", torch.uint8), self._img(phi, "phi"),
+                               ctypes.byref(pc), ctypes.byref(rep), tr)
+        else:
+            rc = lib.ilt_solve_modulated(self._h, self._img(target, "target", torch.uint8), self._img(phi, "phi"),
+                                         self._img(mod, "mod"), ctypes.byref(pc), ctypes.byref(rep), tr)
         _check(rc)
         return dict(iters_done=rep.iters_done, status=rep.status, loss=rep.loss, l2=rep.l2, pvb=rep.pvb,
                     flips=rep.flips)
@@ -401,5 +409,5 @@ def edt_reinit(ctx: Context, params, phi=None, mask=None, phi_out=None, sqdist=N
     return ctx.edt_reinit(params, phi, mask, phi_out, sqdist)
 
 
-def ilt_solve(ctx: Context, target, phi, params, trace=None):
-    return ctx.ilt_solve(target, phi, params, trace)
+def ilt_solve(ctx: Context, target, phi, params, trace=None, mod=None):
+    return ctx.ilt_solve(target, phi, params, trace, mod)

@@ -1,6 +1,10 @@
-"""Train the DSN level-set branch on DSO results and measure DevelSet.
+"""Train DSN on DSO results and measure DevelSet.
 
-    python -m paper_2303_12529_amd.train_dsn --clips 1024 --epochs 10 --out DIR
+    python -m paper_2303_12529_amd.train_dsn --clips 1024 --epochs 10 --out DIR [--modulation]
+
+--modulation adds the modulation branch: its targets come from the shift
+search of develset.make_dataset, it trains on L_0 + L_m, and the evaluation
+adds DevelSet with the network's modulation map.
 
 Writes DIR/dsn_weights.npy (flat FP32 parameters, the layout of
 include/dsn.h) and DIR/dsn_report.json (dataset and training times, the
@@ -38,16 +42,17 @@ def speed(net, batch, steps=10):
     import torch
     x = torch.rand((batch, net.H, net.W), device="cuda")
     t = torch.rand((batch, net.H, net.W), device="cuda")
+    tm = t if net.modulation else None
     for _ in range(2):
         net.forward(x)
-        net.backward(t)
+        net.backward(t, target_m=tm)
         net.adam_step(0.0)
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
     for _ in range(steps):
         net.forward(x)
-        net.backward(t)
+        net.backward(t, target_m=tm)
         net.adam_step(0.0)
     e1.record()
     torch.cuda.synchronize()
@@ -74,6 +79,7 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--out", required=True)
     ap.add_argument("--speed-only", action="store_true")
+    ap.add_argument("--modulation", action="store_true")
     args = ap.parse_args()
 
     import torch
@@ -85,24 +91,32 @@ def main():
 
     os.makedirs(args.out, exist_ok=True)
     torch.cuda.set_device(0)
-    net = dsn.Net(512, 512, 32, max_batch=args.batch)
-    net.set_params(dsn.he_init(args.seed))
-    report = {"network": {"grid": [512, 512], "base": 32, "params": net.n_params,
+    net = dsn.Net(512, 512, 32, max_batch=args.batch, modulation=args.modulation)
+    init = dsn.he_init(args.seed, modulation=args.modulation)
+    net.set_params(init)
+    report = {"network": {"grid": [512, 512], "base": 32, "params": net.n_params, "modulation": args.modulation,
                           "forward_gflop_per_sample": round(develset_flops(net) / 1e9, 2)}}
     report["speed"] = speed(net, args.batch)
     log("speed %s" % report["speed"])
     if args.speed_only:
         print(json.dumps(report), flush=True)
         return
-    net.set_params(dsn.he_init(args.seed))
+    net.set_params(init)
     t0 = time.perf_counter()
-    x, t = develset.make_dataset(args.clips, 100000, net, log=log)
+    data = develset.make_dataset(args.clips, 100000, net, log=log)
+    x, t = data[0], data[1]
+    tm = data[2] if args.modulation else None
     report["dataset"] = {"clips": args.clips, "seconds": round(time.perf_counter() - t0, 1)}
+    if args.modulation:
+        import numpy as np
+        vals, counts = np.unique(data[3], return_counts=True)
+        report["dataset"]["shift_histogram"] = {int(v): int(c) for v, c in zip(vals, counts)}
+        log("shift histogram %s" % report["dataset"]["shift_histogram"])
     t0 = time.perf_counter()
-    hist = develset.train(net, x, t, args.epochs, args.batch, args.lr, seed=args.seed, log=log)
+    hist = develset.train(net, x, t, args.epochs, args.batch, args.lr, seed=args.seed, log=log, tm=tm)
     report["training"] = {"epochs": args.epochs, "batch": args.batch, "lr": args.lr, "loss_per_epoch": hist,
                           "seconds": round(time.perf_counter() - t0, 1)}
-    del x, t
+    del x, t, tm, data
     import numpy as np
     np.save(os.path.join(args.out, "dsn_weights.npy"), net.get_params().cpu().numpy())
     report["evaluation"] = develset.evaluate(net, range(args.eval_seeds), log=log)
@@ -110,8 +124,9 @@ def main():
         json.dump(report, f, indent=1)
     print(json.dumps({k: v for k, v in report.items() if k != "evaluation"}), flush=True)
     ev = report["evaluation"]
-    print(json.dumps({"median_ms_plain": ev["median_ms_plain"], "median_ms_develset": ev["median_ms_develset"],
-                      "speedup": ev.get("speedup"), "dsn_used": ev["dsn_used"]}), flush=True)
+    print(json.dumps({k: ev.get(k) for k in ("median_ms_plain", "median_ms_develset", "speedup", "dsn_used",
+                                              "median_ms_develset_m", "speedup_m", "reached_develset_m")}),
+          flush=True)
 
 
 def develset_flops(net):

@@ -111,16 +111,16 @@ def test_conv_weight_gradient(dsn, N, H, W, Cin, Cout, up):
     assert e_w <= 1e-5 and e_b <= 1e-5
 
 
-def _setup_net(dsn, H=32, W=32, B=2, seed=3):
-    net = dsn.Net(H, W, 32, max_batch=B)
-    flat = dsn.he_init(seed)
+def _setup_net(dsn, H=32, W=32, B=2, seed=3, modulation=False):
+    net = dsn.Net(H, W, 32, max_batch=B, modulation=modulation)
+    flat = dsn.he_init(seed, modulation=modulation)
     rng = np.random.default_rng(seed)
-    for name, ws, bs, wo, bo in dsn.layer_table(32):
+    for name, ws, bs, wo, bo in dsn.layer_table(32, modulation):
         flat[bo:bo + bs[0]] = rng.normal(scale=0.05, size=bs[0]).astype(np.float32)
     net.set_params(flat)
     # the reference uses the GPU's working weights (BF16) and FP32 biases
     params = {}
-    for name, ws, bs, wo, bo in dsn.layer_table(32):
+    for name, ws, bs, wo, bo in dsn.layer_table(32, modulation):
         w = torch.as_tensor(flat[wo:bo]).to(torch.bfloat16).double().numpy().reshape(ws)
         params[name] = (w, flat[bo:bo + bs[0]].astype(np.float64))
     x = rng.integers(0, 17, size=(B, H, W)).astype(np.float32) / 16.0
@@ -217,3 +217,90 @@ def test_bad_arguments(dsn):
     x = torch.zeros((2, 16, 16), device="cuda")
     with pytest.raises(dsn.DsnError):
         net.forward(x)                    # batch above max_batch
+
+
+def test_modulation_head_forward_backward(dsn):
+    """Both heads, both losses and the gradient of L_0 + L_m against the
+    oracle; the modulation targets are binary maps as the shift search gives."""
+    net, flat, params, x, t = _setup_net(dsn, seed=21, modulation=True)
+    assert net.n_params == dsn.layer_table(32, True)[-1][4] + 1
+    B, H, W = x.shape
+    rng = np.random.default_rng(22)
+    tm = (rng.uniform(size=(B, H, W)) < 0.5).astype(np.float32)
+    out, out_m = net.forward(torch.as_tensor(x).cuda())
+    grad = torch.empty(net.n_params, dtype=torch.float32, device="cuda")
+    loss = net.backward(torch.as_tensor(t).cuda(), grad, target_m=torch.as_tensor(tm).cuda())
+    torch.cuda.synchronize()
+    o = np.stack([out.double().cpu().numpy(), out_m.double().cpu().numpy()], axis=-1)
+    o_ref, cache = ref.forward(params, x[..., None].astype(np.float64))
+    assert o_ref.shape[-1] == 2
+    e_out = np.abs(o - o_ref).max() / np.abs(o_ref).max()
+    l0, lm = (float(v) for v in loss.cpu())
+    _say("forward normwise err", e_out, "L0", l0, "Lm", lm, ref.loss_m(o_ref, tm))
+    assert e_out <= 4e-2
+    # both loss reductions on the GPU's own outputs (H_eps in FP32)
+    assert abs(l0 - ref.loss(o, t)) <= 2.0 ** -22 * abs(l0)
+    assert abs(lm - ref.loss_m(o, tm)) <= 1e-5 * abs(lm)
+    g_ref, _ = ref.backward(params, cache, o_ref, t.astype(np.float64), target_m=tm.astype(np.float64))
+    g = grad.double().cpu().numpy()
+    worst = 0.0
+    for name, ws, bs, wo, bo in dsn.layer_table(32, True):
+        gw, gb = g[wo:bo].reshape(ws), g[bo:bo + bs[0]]
+        rw, rb = g_ref[name]
+        ew = np.abs(gw - rw).max() / max(np.abs(rw).max(), 1e-30)
+        eb = np.abs(gb - rb).max() / max(np.abs(rb).max(), 1e-30)
+        _say("  grad", name, "w", round(ew, 5), "b", round(eb, 5))
+        worst = max(worst, ew, eb)
+    assert worst <= 0.15
+
+
+def test_modulation_head_left_out_without_target(dsn):
+    """Without modulation targets the shared layers get the level-set
+    branch's gradient bitwise, the modulation head none, and L_m = 0."""
+    net_m, flat_m, _, x, t = _setup_net(dsn, seed=23, modulation=True)
+    net = dsn.Net(32, 32, 32, max_batch=2)
+    n = net.n_params
+    net.set_params(flat_m[:n])
+    xd, td = torch.as_tensor(x).cuda(), torch.as_tensor(t).cuda()
+    g_m = torch.empty(net_m.n_params, dtype=torch.float32, device="cuda")
+    g = torch.empty(n, dtype=torch.float32, device="cuda")
+    out_a, _ = net_m.forward(xd)
+    loss_m = net_m.backward(td, g_m).clone()
+    out_b = net.forward(xd)
+    loss = net.backward(td, g).clone()
+    assert torch.equal(out_a, out_b)
+    assert torch.equal(g_m[:n], g) and torch.count_nonzero(g_m[n:]) == 0
+    assert float(loss_m[0]) == float(loss[0]) and float(loss_m[1]) == 0.0
+
+
+def test_modulation_resampling_and_predict(dsn):
+    net, flat, params, x, t = _setup_net(dsn, H=16, W=24, B=2, seed=25, modulation=True)
+    rng = np.random.default_rng(4)
+    Z = (rng.uniform(size=(2, 64, 96)) < 0.3).astype(np.uint8)
+    phi = rng.normal(scale=30.0, size=(2, 64, 96)).astype(np.float32)
+    m_gt = (phi >= 5.0).astype(np.float32)
+    xd, td, tmd = net.prepare(torch.as_tensor(Z).cuda(), torch.as_tensor(phi).cuda(), torch.as_tensor(m_gt).cuda())
+    for b in range(2):
+        np.testing.assert_allclose(tmd[b].cpu().numpy(), ref.mean_pool(m_gt[b].astype(np.float64), 4), rtol=0,
+                                   atol=1e-7)
+    out, out_m = net.forward(xd)
+    out, out_m = out.double().cpu().numpy(), out_m.double().cpu().numpy()
+    phi0, m0 = net.predict(torch.as_tensor(Z).cuda(), -12.5, 112.5, with_m=True)
+    phi0, m0 = phi0.cpu().numpy(), m0.cpu().numpy()
+    for b in range(2):
+        assert np.abs(phi0[b] - ref.phi0_from_output(out[b], -12.5, 112.5)).max() <= 2e-4
+        want = ref.bilinear_up(ref.ahf(out_m[b]), 4)
+        assert np.abs(m0[b] - want).max() <= 2e-6
+    assert m0.min() >= 0.0 and m0.max() <= 1.0
+
+
+def test_modulation_bad_arguments(dsn):
+    net = dsn.Net(16, 16, 32, 1)                          # no modulation head
+    x = torch.zeros((1, 16, 16), device="cuda")
+    net.forward(x)
+    with pytest.raises(dsn.DsnError):
+        net.backward(x, target_m=x)                       # no modulation output to train
+    with pytest.raises(dsn.DsnError):
+        net.forward(x, out_m=torch.zeros_like(x))
+    with pytest.raises(dsn.DsnError):
+        net.predict(torch.zeros((1, 64, 64), dtype=torch.uint8, device="cuda"), -1.0, 1.0, with_m=True)

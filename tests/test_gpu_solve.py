@@ -228,3 +228,75 @@ def test_cg_trajectory_band(ilt):
     band = 0.02 * l2o[0] + 10
     assert np.all(np.abs(l2g - l2o) <= band)
     assert abs(rep["l2"] - ofin["l2"]) <= band
+
+
+def _modulation_map(Z, phi0, dh):
+    """A modulation map of the shape the modulation branch learns: the
+    Heaviside map of the target's shifted TSDF."""
+    return (phi0.astype(np.float64) + dh >= 0).astype(np.float32)
+
+
+@pytest.mark.parametrize("dh", [-5.0, -15.0])
+def test_modulated_iterations_teacher_forced(ilt, dh):
+    """Three modulated iterations (no reinit) against the oracle's loop with the
+    same map; the map must change the result."""
+    _say("modulated teacher-forced dh", dh)
+    Z, H, w, prm = workload_inputs("c0", 4)
+    N = Z.shape[0]
+    phi0, _, _ = o_edt.tsdf_from_mask(Z, prm["d_lower"], prm["d_upper"])
+    phi0 = phi0.astype(np.float32)
+    mod = _modulation_map(Z, phi0, dh)
+    prm3 = dict(prm, iters=3, reinit_every=0)
+    ctx = ilt.Context(H, w, N)
+    phi = _dev(phi0)
+    trace = torch.zeros((3, ilt.TRACE_W), dtype=torch.float64, device="cuda")
+    ctx.ilt_solve(_dev(Z, torch.uint8), phi, ilt.Params.from_dict(prm3, init_mode=1), trace=trace, mod=_dev(mod))
+    tr = trace.cpu().numpy()
+    ref = phi0.astype(np.float64)
+    plain = phi0.astype(np.float64)
+    for i in range(3):
+        ref, row = o_solve.iteration(ref, Z, H, w, prm3, mod=mod.astype(np.float64))
+        plain, _ = o_solve.iteration(plain, Z, H, w, prm3)
+        assert abs(tr[i, 1] - row["loss"]) <= 1e-4 * abs(row["loss"])
+        assert abs(tr[i, 5] - row["m_v"]) <= 1e-3 * row["m_v"]
+    out = phi.cpu().numpy().astype(np.float64)
+    err = np.abs(out - ref).max()
+    _say("  phi err", err, "modulation effect", np.abs(ref - plain).max())
+    assert err <= 3e-3 * prm["eta"] + 1e-3
+    assert np.abs(ref - plain).max() > 10 * (3e-3 * prm["eta"] + 1e-3)
+
+
+def test_modulated_with_ones_equals_plain_and_replays(ilt):
+    """m = 1 everywhere reproduces ilt_solve bitwise; a replayed graph reads the
+    map's current contents (new values at the same address)."""
+    Z, H, w, prm = workload_inputs("c0", 6)
+    N = Z.shape[0]
+    ctx = ilt.Context(H, w, N)
+    tgt = _dev(Z, torch.uint8)
+    p = ilt.Params.from_dict(prm, iters=8)
+    phi_a = torch.empty((N, N), dtype=torch.float32, device="cuda")
+    ctx.ilt_solve(tgt, phi_a, p)
+    mod = torch.ones((N, N), dtype=torch.float32, device="cuda")
+    phi_b = torch.empty_like(phi_a)
+    ctx.ilt_solve(tgt, phi_b, p, mod=mod)
+    assert torch.equal(phi_a, phi_b)
+    phi0, _, _ = o_edt.tsdf_from_mask(Z, prm["d_lower"], prm["d_upper"])
+    mod.copy_(_dev(_modulation_map(Z, phi0, 5.0)))
+    ctx.ilt_solve(tgt, phi_b, p, mod=mod)                  # graph replay, new contents
+    ctx.set_graph(False)
+    phi_c = torch.empty_like(phi_a)
+    ctx.ilt_solve(tgt, phi_c, p, mod=mod)                  # direct launches
+    assert torch.equal(phi_b, phi_c) and not torch.equal(phi_a, phi_b)
+
+
+def test_modulated_rejects_null_map(ilt):
+    Z, H, w, prm = workload_inputs("c0", 0)
+    N = Z.shape[0]
+    ctx = ilt.Context(H, w, N)
+    lib = ilt.load_library()
+    phi = torch.empty((N, N), dtype=torch.float32, device="cuda")
+    pc = ilt.Params.from_dict(prm).to_c()
+    import ctypes
+    rc = lib.ilt_solve_modulated(ctx._h, ctypes.c_void_p(_dev(Z, torch.uint8).data_ptr()),
+                                 ctypes.c_void_p(phi.data_ptr()), None, ctypes.byref(pc), None, None)
+    assert rc == ilt.ILT_EINVAL
