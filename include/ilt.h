@@ -224,12 +224,16 @@ int ilt_profile_read(ilt_ctx *ctx, double *h_out, int n);
  *   b3_xsplit     BF16x3 adjoint: column chunks split over this many blocks
  *                 per row tile, 1..4 (0 = chosen by size).
  *   xcd_remap     BF16x3 image: XCD-aware tile order (1) or plain (0).
+ *   st_xsplit     FP32 adjoint from stored fields: column chunks split over
+ *                 this many blocks per row tile, 1..2 (0 = chosen by size:
+ *                 2 when the grid would hold fewer than 512 blocks).
  * ilt_set_tuning drops a captured solve graph (it is re-captured).
  * ilt_autotune: with cache_path non-NULL and a line for this device
  * architecture and problem (N, P, K, n_sets, precision, field buffer) in that
  * text file (one JSON object per line, written by this function), applies
  * it and returns 1.  Otherwise times every candidate with HIP events on a
- * synthetic clip (3-iteration solves on the context's stream; allocates and
+ * synthetic clip (the fastest of three 4-iteration solves after a warm-up,
+ * on the context's stream; allocates and
  * frees two N x N scratch buffers), applies the fastest, appends it to
  * cache_path (if given) and returns 0.  h_best, h_ms_per_iter: NULL or out.
  * Synchronous. */
@@ -237,6 +241,7 @@ typedef struct {
     int store_fields;
     int b3_xsplit;
     int xcd_remap;
+    int st_xsplit;
 } ilt_tuning;
 
 int ilt_get_tuning(const ilt_ctx *ctx, ilt_tuning *h_tuning);
@@ -289,6 +294,54 @@ int ilt_batch_destroy(ilt_batch *batch);
 /* Capture and replay hipGraphs (1, default) or launch directly (0). */
 int ilt_batch_set_graph(ilt_batch *batch, int enable);
 int ilt_solve_batch(ilt_batch *batch, int n, const ilt_clip *clips, ilt_report *h_reports);
+
+/* ------------------------------------------------------------------------
+ * Full layouts (beyond one clip).  The paper optimises clips of a fixed
+ * size (Sec. IV: 2048 x 2048); a larger layout is covered by N x N tiles
+ * whose cores, C = N - 2 halo pixels square, tile the layout at stride C.
+ * Tile (i, j), i < rows, j < cols, spans layout rows [i C - halo,
+ * i C - halo + N) and columns [j C - halo, j C - halo + N); tile pixels
+ * outside the layout are empty.  The halo is optical context: the imaging
+ * kernels reach beyond a core, so each core is solved with its surroundings
+ * and only the core is kept.  Tiles are stored [rows][cols][N][N].
+ *
+ * Layout sides in [1, ILT_LAYOUT_MAX_SIDE], N in [16, 4096], 0 <= halo,
+ * N - 2 halo >= 1, rows x cols <= ILT_LAYOUT_MAX_TILES; ILT_EINVAL otherwise.
+ * ilt_layout_grid: rows and cols of the tiling (host only).
+ * ilt_layout_extract: d_tiles [rows][cols][N][N] bytes from d_layout [H][W]
+ *   bytes.  Async on `stream` (a hipStream_t, NULL = default).
+ * ilt_layout_stitch: d_layout [H][W] FP32, each pixel from the core of the
+ *   tile holding it in d_tiles [rows][cols][N][N] FP32.  Async.
+ * ilt_solve_layout: extract, then the DSO loop of ilt_solve on every tile
+ *   through the batch (N must be one of its sizes; chunks of max_clips),
+ *   then stitch phi.  d_tile_targets [rows][cols][N][N] bytes and
+ *   d_tile_phi [rows][cols][N][N] FP32 are the caller's workspaces (tile
+ *   results stay there); d_layout_phi [H][W] out.  params->init_mode must be
+ *   0 (each tile starts from the TSDF of its own target).  h_reports: NULL
+ *   or host [rows x cols], per tile.  Synchronous; ILT_ENUMERIC if any tile
+ *   went non-finite (the stitched result is still written). */
+#define ILT_LAYOUT_MAX_SIDE (1 << 20)
+#define ILT_LAYOUT_MAX_TILES (1 << 20)
+
+int ilt_layout_grid(int H, int W, int N, int halo, int *rows, int *cols);
+int ilt_layout_extract(const unsigned char *d_layout, int H, int W, int N, int halo, unsigned char *d_tiles,
+                       void *stream);
+int ilt_layout_stitch(const float *d_tiles, int H, int W, int N, int halo, float *d_layout, void *stream);
+int ilt_solve_layout(ilt_batch *batch, const unsigned char *d_layout, int H, int W, int N, int halo,
+                     const ilt_params *params, unsigned char *d_tile_targets, float *d_tile_phi,
+                     float *d_layout_phi, ilt_report *h_reports);
+
+/* Sec. II-C, mask fracturing shot count: the number of rectangles of an
+ * exact fracturing of the mask (the paper's scripts are not given).  The
+ * estimate: every maximal run of ones in a row continues the rectangle of
+ * the identical run (same first and last column) in the row above, or
+ * starts a rectangle; the same with rows and columns exchanged; the smaller
+ * of the two counts.  Exactly one of d_phi (mask [phi <= 0], FP32) and
+ * d_mask (bytes, nonzero = 1) is given, [H][W], sides in
+ * [1, ILT_LAYOUT_MAX_SIDE].  d_counts: device int64 [3] = {row fracturing,
+ * column fracturing, minimum}.  Exact integers.  Async on `stream`. */
+int ilt_shot_count(const float *d_phi, const unsigned char *d_mask, int H, int W, long long *d_counts,
+                   void *stream);
 
 #ifdef __cplusplus
 }

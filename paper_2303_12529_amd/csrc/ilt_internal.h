@@ -109,6 +109,7 @@ struct ilt_ctx {
     // beyond rounding order
     int store_fields;  // FP32: 1 = forward stores the fields, the adjoint streams them
     int b3_xsplit;     // BF16x3 adjoint: column chunks split over this many blocks (0 = by size)
+    int st_xsplit;     // FP32 stored-field adjoint: the same split (0 = by size)
     hipStream_t cap_stream;
     hipGraph_t graph;
     hipGraphExec_t graph_exec;
@@ -163,6 +164,19 @@ int adjoint_b3_parts(const ilt_ctx *c, int nsets);
 inline int spectrum_xsplit(const ilt_ctx *c) { return c->Np >= 512 ? 4 : c->Np / 128; }
 int adjoint_b3_max_parts(const ilt_ctx *c, int nsets);
 #define ILT_B3_MAX_XSPLIT 4
+#define ILT_ST_MAX_XSPLIT 2
+// by size: split the columns in two when the row tiles x kernel groups x sets
+// would not give every CU two blocks
+inline int adjoint_st_xsplit(const ilt_ctx *c) {
+    if (c->st_xsplit > 0) return c->st_xsplit;
+    return ((c->N + 31) / 32) * ((c->K + 3) / 4) * c->n_sets < 512 ? 2 : 1;
+}
+// partial W count of the FP32 adjoint for nsets sets: row tiles x kernel
+// groups, times the column split when the fields are stored
+inline int adjoint_fp32_parts(const ilt_ctx *c, int nsets) {
+    const int base = nsets * ((c->N + 31) / 32) * ((c->K + 3) / 4);
+    return (c->Est && c->store_fields) ? base * adjoint_st_xsplit(c) : base;
+}
 
 // ---- launchers (k_pixel.hip) ----
 int resist_blocks(const ilt_ctx *c);
@@ -183,3 +197,17 @@ hipError_t launch_edt(ilt_ctx *c, const float *phi, const uint8_t *mask, float *
                       float d_lower, float d_upper);
 hipError_t launch_copy(ilt_ctx *c, float *dst, const float *src, size_t n);
 hipError_t launch_fill(ilt_ctx *c, float *dst, float v, size_t n);
+
+// ---- full-layout tiling and shot count (k_layout.hip) ----
+// tiles per column / row of the layout grid (cores of C = N - 2 halo pixels)
+inline void layout_grid_dims(int H, int W, int N, int halo, int *rows, int *cols) {
+    const int C = N - 2 * halo;
+    *rows = (H + C - 1) / C;
+    *cols = (W + C - 1) / C;
+}
+hipError_t launch_layout_extract(const unsigned char *d_layout, int H, int W, int N, int halo,
+                                 unsigned char *d_tiles, hipStream_t st);
+hipError_t launch_layout_stitch(const float *d_tiles, int H, int W, int N, int halo, float *d_out, hipStream_t st);
+// d_counts [3]: row fracturing, column fracturing, their minimum
+hipError_t launch_shot_count(const float *d_phi, const unsigned char *d_mask, int H, int W,
+                             unsigned long long *d_counts, hipStream_t st);

@@ -357,8 +357,8 @@ __global__ __launch_bounds__(256, 2) void k_image(const float *__restrict__ tl, 
 // 32-column chunks:
 //   X = G . E_j    (E_j fragments read in accumulator layout, G from LDS)
 //   Z += X B3      (E fragments are the A-operand as loaded; B3 from LDS)
-// then the shared tail.  G and B3 chunks and the next chunk's fragments are
-// prefetched into registers while the current chunk is multiplied.
+// then the shared tail.  grid.y = kernel groups x column ranges: a block
+// walks its range of chunks only (its partial W is summed with the others').
 // --------------------------------------------------------------------------
 template <int FB, int MIX>
 __global__ __launch_bounds__(256, 2) void k_adjoint_st(const float *__restrict__ tb, const float *__restrict__ ta4,
@@ -374,7 +374,9 @@ __global__ __launch_bounds__(256, 2) void k_adjoint_st(const float *__restrict__
     __shared__ float2 Ws[ILT_MAX_P * ILT_MAX_P];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int l16 = lane & 15, lq = lane >> 4;
-    const int ytile = blockIdx.x, kg = blockIdx.y, srel = blockIdx.z, s = set_lo + srel;
+    const int kgroups = (K + 3) / 4;
+    const int ytile = blockIdx.x, kg = blockIdx.y % kgroups, xs = blockIdx.y / kgroups;
+    const int srel = blockIdx.z, s = set_lo + srel;
     const int y0 = ytile * 32;
     const int j = kg * 4 + wave;
     const bool jok = j < K;
@@ -382,6 +384,8 @@ __global__ __launch_bounds__(256, 2) void k_adjoint_st(const float *__restrict__
     const float *Gsrc = G + (size_t)s * g_set_stride;
     const float *Ej = Est + (size_t)(s * K + (jok ? j : 0)) * NB16 * NB16 * 512;
     const int nchunk = (N + 31) / 32;
+    const int xsplit = gridDim.y / kgroups;
+    const int c_begin = xs * nchunk / xsplit, c_end = (xs + 1) * nchunk / xsplit;
 
     f4 accZ[2][NB];
 #pragma unroll
@@ -389,7 +393,7 @@ __global__ __launch_bounds__(256, 2) void k_adjoint_st(const float *__restrict__
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb) accZ[yb][nb] = f4{0.f, 0.f, 0.f, 0.f};
 
-    for (int c = 0; c < nchunk; ++c) {
+    for (int c = c_begin; c < c_end; ++c) {
         const int x0 = c * 32;
         __syncthreads();
 #pragma unroll
@@ -436,7 +440,7 @@ __global__ __launch_bounds__(256, 2) void k_adjoint_st(const float *__restrict__
             }
         }
     }
-    float *dst = Wpart + ((size_t)(srel * gridDim.x + ytile) * gridDim.y + kg) * P * P * 2;
+    float *dst = Wpart + ((size_t)(srel * gridDim.x + ytile) * gridDim.y + blockIdx.y) * P * P * 2;
     ilt_dev::adjoint_tail<FB, MIX>(accZ, jok, j, s, K, P, Np, AP, y0, ta4, coef, Ws, dst);
 }
 
@@ -647,6 +651,8 @@ hipError_t launch_adjoint(ilt_ctx *c, const float *G, size_t g_set_stride, int s
     dim3 grid((c->N + 31) / 32, (c->K + 3) / 4, set_hi - set_lo);
     if (fields_stored) {
         if (!c->Est) return hipErrorInvalidValue;
+        grid.y *= adjoint_st_xsplit(c);
+        if ((size_t)grid.x * grid.y * grid.z * c->P * c->P * 2 > (size_t)c->n_wpart) return hipErrorInvalidValue;
 #define ADJS(FB_, MIX_)                                                                                       \
     k_adjoint_st<FB_, MIX_><<<grid, 256, 0, c->stream>>>(c->tb, c->ta4, c->Est, G, g_set_stride, c->coef, c->K, \
                                                          c->P, c->N, c->Np, c->AP, set_lo, c->Wpart)
@@ -679,7 +685,7 @@ hipError_t launch_adjoint(ilt_ctx *c, const float *G, size_t g_set_stride, int s
 
 hipError_t launch_window_sum(ilt_ctx *c, int set_lo, int set_hi) {
     const int nparts = c->precision == ILT_BF16X3 ? adjoint_b3_parts(c, set_hi - set_lo)
-                                                  : (set_hi - set_lo) * ((c->N + 31) / 32) * ((c->K + 3) / 4);
+                                                  : adjoint_fp32_parts(c, set_hi - set_lo);
     const int n = c->P * c->P;
     k_psum<float2><<<(n + 15) / 16, 1024, 0, c->stream>>>(reinterpret_cast<const float2 *>(c->Wpart), nparts, n,
                                                          c->W);

@@ -57,7 +57,8 @@ class _Report(ctypes.Structure):
 
 
 class _Tuning(ctypes.Structure):
-    _fields_ = [("store_fields", ctypes.c_int), ("b3_xsplit", ctypes.c_int), ("xcd_remap", ctypes.c_int)]
+    _fields_ = [("store_fields", ctypes.c_int), ("b3_xsplit", ctypes.c_int), ("xcd_remap", ctypes.c_int),
+                ("st_xsplit", ctypes.c_int)]
 
 
 class _Clip(ctypes.Structure):
@@ -101,6 +102,13 @@ def load_library(path: str = LIB_PATH):
         "ilt_batch_destroy": [_VP],
         "ilt_batch_set_graph": [_VP, ctypes.c_int],
         "ilt_solve_batch": [_VP, ctypes.c_int, ctypes.POINTER(_Clip), ctypes.POINTER(_Report)],
+        "ilt_layout_extract": [_VP, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, _VP, _VP],
+        "ilt_layout_stitch": [_VP, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, _VP, _VP],
+        "ilt_layout_grid": [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
+                            ctypes.POINTER(ctypes.c_int)],
+        "ilt_solve_layout": [_VP, _VP, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                             ctypes.POINTER(_Params), _VP, _VP, _VP, ctypes.POINTER(_Report)],
+        "ilt_shot_count": [_VP, _VP, ctypes.c_int, ctypes.c_int, _VP, _VP],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -387,6 +395,87 @@ class Batch:
         _check(load_library().ilt_solve_batch(self._h, n, arr, reps))
         return [dict(iters_done=r.iters_done, status=r.status, loss=r.loss, l2=r.l2, pvb=r.pvb, flips=r.flips)
                 for r in reps]
+
+    def solve_layout(self, layout, N: int, halo: int, params: Params, tile_targets=None, tile_phi=None, out=None):
+        """DSO on every N x N tile of a layout (uint8 [H, W]) and the stitched
+        phi [H, W]; returns (phi, per-tile reports, tile_phi [T, N, N])."""
+        import torch
+        H, W = (int(v) for v in layout.shape)
+        rows, cols = layout_grid(H, W, N, halo)
+        T = rows * cols
+        if tile_targets is None:
+            tile_targets = torch.empty((T, N, N), dtype=torch.uint8, device=self.device)
+        if tile_phi is None:
+            tile_phi = torch.empty((T, N, N), dtype=torch.float32, device=self.device)
+        if out is None:
+            out = torch.empty((H, W), dtype=torch.float32, device=self.device)
+        reps = (_Report * T)()
+        pc = params.to_c()
+        _check(load_library().ilt_solve_layout(
+            self._h, _ptr(layout, torch.uint8, (H, W), "layout", self.device), H, W, int(N), int(halo),
+            ctypes.byref(pc), _ptr(tile_targets, torch.uint8, (T, N, N), "tile_targets", self.device),
+            _ptr(tile_phi, torch.float32, (T, N, N), "tile_phi", self.device),
+            _ptr(out, torch.float32, (H, W), "out", self.device), reps))
+        return out, [dict(iters_done=r.iters_done, status=r.status, loss=r.loss, l2=r.l2, pvb=r.pvb,
+                          flips=r.flips) for r in reps], tile_phi
+
+
+def _stream_of(t):
+    import torch
+    return _VP(torch.cuda.current_stream(t.device).cuda_stream)
+
+
+def layout_grid(H: int, W: int, N: int, halo: int):
+    """(rows, cols) of the tiling of an H x W layout by N x N tiles with
+    cores of N - 2 halo pixels."""
+    r, c = ctypes.c_int(), ctypes.c_int()
+    _check(load_library().ilt_layout_grid(int(H), int(W), int(N), int(halo), ctypes.byref(r), ctypes.byref(c)))
+    return r.value, c.value
+
+
+def layout_extract(layout, N: int, halo: int, out=None):
+    """Tiles [rows * cols, N, N] uint8 of a layout uint8 [H, W]."""
+    import torch
+    H, W = (int(v) for v in layout.shape)
+    rows, cols = layout_grid(H, W, N, halo)
+    if out is None:
+        out = torch.empty((rows * cols, N, N), dtype=torch.uint8, device=layout.device)
+    _check(load_library().ilt_layout_extract(_ptr(layout, torch.uint8, (H, W), "layout", layout.device), H, W,
+                                             int(N), int(halo),
+                                             _ptr(out, torch.uint8, (rows * cols, N, N), "out", layout.device),
+                                             _stream_of(layout)))
+    return out
+
+
+def layout_stitch(tiles, H: int, W: int, N: int, halo: int, out=None):
+    """Layout [H, W] float32 from the cores of tiles [rows * cols, N, N] float32."""
+    import torch
+    rows, cols = layout_grid(H, W, N, halo)
+    if out is None:
+        out = torch.empty((H, W), dtype=torch.float32, device=tiles.device)
+    _check(load_library().ilt_layout_stitch(_ptr(tiles, torch.float32, (rows * cols, N, N), "tiles", tiles.device),
+                                            int(H), int(W), int(N), int(halo),
+                                            _ptr(out, torch.float32, (H, W), "out", tiles.device),
+                                            _stream_of(tiles)))
+    return out
+
+
+def shot_count(phi=None, mask=None, out=None):
+    """Device int64 [3]: rectangles of the row fracturing, of the column
+    fracturing, and the smaller (the shot count) of [phi <= 0] or of a
+    uint8 mask."""
+    import torch
+    if (phi is None) == (mask is None):
+        raise ValueError("give exactly one of phi and mask")
+    t = phi if phi is not None else mask
+    H, W = (int(v) for v in t.shape)
+    if out is None:
+        out = torch.empty(3, dtype=torch.int64, device=t.device)
+    _check(load_library().ilt_shot_count(
+        None if phi is None else _ptr(phi, torch.float32, (H, W), "phi", t.device),
+        None if mask is None else _ptr(mask, torch.uint8, (H, W), "mask", t.device), H, W,
+        _ptr(out, torch.int64, (3,), "out", t.device), _stream_of(t)))
+    return out
 
 
 def litho_forward(ctx: Context, mask, set_=0, out=None):

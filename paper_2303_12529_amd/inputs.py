@@ -332,3 +332,20 @@ def workload_inputs(name: str, seed: int = 0):
     Z = gen_clip(w["clip"], seed)
     k, wt = build_optics(**w["optics"])
     return Z, k, wt, dict(w["params"])
+
+
+# Full-layout workload: a square layout at 1 nm drawn with the 2048^2 clip
+# recipe scaled to its area (polygon count times the area ratio), tiled by
+# 2048^2 tiles with a halo of LAYOUT_HALO pixels.
+LAYOUT_TILE = 2048
+LAYOUT_HALO = 256
+
+
+def layout_inputs(side: int = 6144, seed: int = 0):
+    """(layout uint8 [side, side], kernels, weights, params dict) with the
+    optics and loop parameters of the 2048^2 workload."""
+    scale = (side / C1_CLIP.N) ** 2
+    spec = dataclasses.replace(C1_CLIP, N=side, n_min=int(C1_CLIP.n_min * scale),
+                               n_max=int(C1_CLIP.n_max * scale))
+    _, k, wt, prm = workload_inputs("c1", 0)
+    return gen_clip(spec, seed), k, wt, prm

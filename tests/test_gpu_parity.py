@@ -117,7 +117,7 @@ ADJ_CASES = [(64, 3, 2), (96, 7, 3), (64, 9, 4), (100, 9, 5), (128, 15, 4), (160
              (67, 9, 3), (150, 35, 5)]   # N % 4 != 0: scalar edge paths
 
 
-@pytest.mark.parametrize("flags", [0, 1, 2, "bf16x3"])
+@pytest.mark.parametrize("flags", [0, "xsplit2", 1, 2, "bf16x3"])
 @pytest.mark.parametrize("N,P,K", ADJ_CASES)
 def test_litho_adjoint_parity(ilt, N, P, K, flags):
     _say("adjoint", N, P, K, flags)
@@ -127,6 +127,9 @@ def test_litho_adjoint_parity(ilt, N, P, K, flags):
     G = rng.normal(size=(N, N)).astype(np.float32)
     if flags == "bf16x3":
         ctx = ilt.Context(H, w, N, precision=ilt.ILT_BF16X3)
+    elif flags == "xsplit2":                 # stored fields, columns split over two blocks
+        ctx = ilt.Context(H, w, N)
+        ctx.set_tuning(store_fields=1, st_xsplit=2)
     else:
         ctx = ilt.Context(H, w, N, flags=flags)
     out = ctx.litho_adjoint(_dev(M), _dev(G), 0).cpu().numpy()

@@ -33,7 +33,8 @@ def ilt():
     return mod
 
 
-CANDIDATES = [("fp32", dict(store_fields=1)), ("fp32", dict(store_fields=0))] + \
+CANDIDATES = [("fp32", dict(store_fields=1, st_xsplit=1)), ("fp32", dict(store_fields=1, st_xsplit=2)),
+              ("fp32", dict(store_fields=0))] + \
     [("bf16x3", dict(b3_xsplit=xs, xcd_remap=rm)) for xs in (1, 2, 4) for rm in (0, 1)]
 
 
@@ -72,10 +73,10 @@ def test_autotune_picks_a_candidate_and_caches_it(ilt, prec):
         first = ctx.autotune(path)
         _say(prec, "tuned", first)
         assert not first["from_cache"] and first["ms_per_iter"] > 0
-        picked = {k: first[k] for k in ("store_fields", "b3_xsplit", "xcd_remap")}
+        picked = {k: first[k] for k in ("store_fields", "b3_xsplit", "xcd_remap", "st_xsplit")}
         assert picked == ctx.get_tuning()
         if prec == "fp32":
-            assert picked["store_fields"] in (0, 1)
+            assert picked["store_fields"] in (0, 1) and picked["st_xsplit"] in ((1, 2) if picked["store_fields"] else (0,))
         else:
             assert picked["b3_xsplit"] in (1, 2, 4) and picked["xcd_remap"] in (0, 1)
         lines = open(path).read().strip().splitlines()
@@ -98,4 +99,6 @@ def test_bad_tuning_rejected(ilt):
         ctx.set_tuning(store_fields=1)          # no field buffer
     with pytest.raises(ilt.IltError):
         ctx.set_tuning(b3_xsplit=5)
+    with pytest.raises(ilt.IltError):
+        ctx.set_tuning(st_xsplit=3)
     ctx.close()

@@ -53,7 +53,7 @@ int main(void) {
   printf("%zu %zu\n", offsetof(ilt_optics, h_kernels), offsetof(ilt_report, loss));
   printf("%zu %zu %zu %d %d %d\n", sizeof(ilt_clip), offsetof(ilt_clip, d_trace), offsetof(ilt_clip, params),
          ILT_BATCH_MAX_SIZES, ILT_BATCH_MAX_LANES, ILT_BATCH_MAX_CLIPS);
-  printf("%zu %zu\n", sizeof(ilt_tuning), offsetof(ilt_tuning, xcd_remap));
+  printf("%zu %zu %zu\n", sizeof(ilt_tuning), offsetof(ilt_tuning, xcd_remap), offsetof(ilt_tuning, st_xsplit));
   printf("%zu\n", offsetof(ilt_params, optimizer));
   return 0;
 }
@@ -79,7 +79,8 @@ int main(void) {
     assert vals[11] == ilt._Clip.params.offset
     assert tuple(vals[12:15]) == (ilt.ILT_BATCH_MAX_SIZES, ilt.ILT_BATCH_MAX_LANES, ilt.ILT_BATCH_MAX_CLIPS)
     assert vals[15] == ctypes.sizeof(ilt._Tuning) and vals[16] == ilt._Tuning.xcd_remap.offset
-    assert vals[17] == ilt._Params.optimizer.offset
+    assert vals[17] == ilt._Tuning.st_xsplit.offset
+    assert vals[18] == ilt._Params.optimizer.offset
 
 
 def test_params_roundtrip_and_validation():
