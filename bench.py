@@ -222,35 +222,48 @@ def time_to_target(ctxs, workload, seeds, extra_iters=10):
 
 
 DSN_WEIGHTS = os.path.join(HERE, "paper_2303_12529_amd", "weights", "dsn_c1_fp16.npy")
+DSN_MOD_WEIGHTS = os.path.join(HERE, "paper_2303_12529_amd", "weights", "dsn_c1_mod_fp16.npy")
 
 
 def develset_ttt(seeds):
     """Time to the plain loop's L2 with the trained network's phi_0 (DevelSet,
-    Sec. III-C) vs from TSDF(target), in both precisions of the loop."""
+    Sec. III-C) vs from TSDF(target): the level-set-branch network in both
+    precisions of the loop, and the two-branch network (level set +
+    modulation, whose m_theta weights every step's curvature term) on the
+    FP32 loop."""
     import numpy as np
     from paper_2303_12529_amd import develset, dsn
     from paper_2303_12529_amd import ilt
-    if not os.path.exists(DSN_WEIGHTS):
-        return None
-    flat = np.load(DSN_WEIGHTS, allow_pickle=False).astype(np.float32)
-    # the modulation branch adds one 1x1 head (32 weights and a bias)
-    modulation = flat.size == dsn.layer_table(32, True)[-1][4] + 1
-    net = dsn.Net(512, 512, 32, max_batch=1, modulation=modulation)
-    net.set_params(flat)
-    out = {"weights": os.path.relpath(DSN_WEIGHTS, HERE), "modulation": modulation}
-    for name, prec in (("fp32", ilt.ILT_FP32), ("bf16x3", ilt.ILT_BF16X3)):
-        ev = develset.evaluate(net, seeds, precision=prec)
-        out[name] = {"median_ms_plain": ev["median_ms_plain"], "median_ms_develset": ev["median_ms_develset"],
-                     "speedup": ev.get("speedup"), "dsn_used": ev["dsn_used"],
-                     "iters_develset": [r["iters_develset"] for r in ev["per_seed"]],
-                     "l2_at_T_plain": [r["l2_at_T_plain"] for r in ev["per_seed"]],
-                     "l2_at_T_develset": [r["l2_at_T_develset"] for r in ev["per_seed"]]}
-        if modulation:
-            out[name].update(median_ms_develset_m=ev.get("median_ms_develset_m"), speedup_m=ev.get("speedup_m"),
-                             iters_develset_m=[r["iters_develset_m"] for r in ev["per_seed"]],
-                             l2_at_T_develset_m=[r["l2_at_T_develset_m"] for r in ev["per_seed"]])
-    net.close()
-    return out
+    out = {}
+    runs = [("weights", DSN_WEIGHTS, (("fp32", ilt.ILT_FP32), ("bf16x3", ilt.ILT_BF16X3))),
+            ("modulation_net", DSN_MOD_WEIGHTS, (("fp32", ilt.ILT_FP32),))]
+    for label, path, forms in runs:
+        if not os.path.exists(path):
+            continue
+        flat = np.load(path, allow_pickle=False).astype(np.float32)
+        # the modulation branch adds one 1x1 head (32 weights and a bias)
+        modulation = flat.size == dsn.layer_table(32, True)[-1][4] + 1
+        net = dsn.Net(512, 512, 32, max_batch=1, modulation=modulation)
+        net.set_params(flat)
+        res = {"weights": os.path.relpath(path, HERE), "modulation": modulation}
+        for name, prec in forms:
+            ev = develset.evaluate(net, seeds, precision=prec)
+            r = {"median_ms_plain": ev["median_ms_plain"], "median_ms_develset": ev["median_ms_develset"],
+                 "speedup": ev.get("speedup"), "dsn_used": ev["dsn_used"],
+                 "iters_develset": [x["iters_develset"] for x in ev["per_seed"]],
+                 "l2_at_T_plain": [x["l2_at_T_plain"] for x in ev["per_seed"]],
+                 "l2_at_T_develset": [x["l2_at_T_develset"] for x in ev["per_seed"]]}
+            if modulation:
+                r.update(median_ms_develset_m=ev.get("median_ms_develset_m"), speedup_m=ev.get("speedup_m"),
+                         iters_develset_m=[x["iters_develset_m"] for x in ev["per_seed"]],
+                         l2_at_T_develset_m=[x["l2_at_T_develset_m"] for x in ev["per_seed"]])
+            res[name] = r
+        net.close()
+        if label == "weights":
+            out.update(res)
+        else:
+            out[label] = res
+    return out or None
 
 
 def batched(n_clips, lanes, precision):
@@ -290,6 +303,53 @@ def batched(n_clips, lanes, precision):
     return out
 
 
+def layout_leg(side, lanes, precision):
+    """A side x side layout at 1 nm (the 2048^2 recipe scaled to its area),
+    2048^2 tiles with a 256-pixel halo, every tile through the full loop on
+    `lanes` streams (ilt_solve_layout: extraction, batched DSO, stitching),
+    then the shot count of the stitched mask."""
+    import torch
+    from paper_2303_12529_amd import ilt
+    from paper_2303_12529_amd.inputs import LAYOUT_HALO, LAYOUT_TILE, layout_inputs
+    Z, H, w, prm = layout_inputs(side)
+    N, halo = LAYOUT_TILE, LAYOUT_HALO
+    rows, cols = ilt.layout_grid(side, side, N, halo)
+    T = rows * cols
+    b = ilt.Batch(H, w, [N], max_clips=T, n_lanes=lanes, precision=precision)
+    target = torch.as_tensor(Z).to("cuda")
+    tt = torch.empty((T, N, N), dtype=torch.uint8, device="cuda")
+    tp = torch.empty((T, N, N), dtype=torch.float32, device="cuda")
+    out = torch.empty((side, side), dtype=torch.float32, device="cuda")
+    p = ilt.Params.from_dict(prm, init_mode=0)
+    b.solve_layout(target, N, halo, p, tt, tp, out)          # captures the lanes' graphs
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, reps, _ = b.solve_layout(target, N, halo, p, tt, tp, out)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    b.close()
+    counts = torch.empty(3, dtype=torch.int64, device="cuda")
+    ilt.shot_count(phi=out, out=counts)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        ilt.shot_count(phi=out, out=counts)
+    e1.record()
+    torch.cuda.synchronize()
+    shots = counts.cpu().tolist()
+    tshots = ilt.shot_count(mask=target).cpu().tolist()
+    iters = prm["iters"]
+    return {"layout": "%dx%d at 1 nm, the 2048^2 clip recipe scaled to the area, %.1f %% metal"
+                      % (side, side, 100.0 * float(Z.mean())),
+            "tile": N, "halo": halo, "tiles": T, "lanes": lanes, "iters_per_tile": iters,
+            "s_per_layout": round(dt, 4), "tile_iters_per_s": round(T * iters / dt, 1),
+            "um2_per_s": round(side * side * 1e-6 / dt, 3),
+            "core_fraction": round(side * side / (T * N * N), 4),
+            "shots_mask": shots[2], "shots_rows_cols": shots[:2], "shots_target": tshots[2],
+            "shot_count_ms": round(e0.elapsed_time(e1) / 5, 4),
+            "tile_l2_sum_with_halos": int(sum(r["l2"] for r in reps))}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -312,6 +372,8 @@ def main():
     ap.add_argument("--batch-clips", type=int, default=64,
                     help="clips in the batched-form measurement (0: skip)")
     ap.add_argument("--batch-lanes", type=int, default=4)
+    ap.add_argument("--layout-side", type=int, default=6144,
+                    help="side of the full-layout measurement in pixels (0: skip)")
     ap.add_argument("--ttt-seeds", type=int, default=10,
                     help="seeds 0..n-1 for the time-to-L2-target comparison (0: skip)")
     args = ap.parse_args()
@@ -416,7 +478,8 @@ def main():
         ttt = time_to_target(ctxs, args.workload, range(args.ttt_seeds))
         if args.workload == "c1":
             ttt["develset"] = develset_ttt(range(args.ttt_seeds))
-            if ttt["develset"] and ttt["median_ms"].get("fp32") and ttt["develset"]["bf16x3"]["median_ms_develset"]:
+            if ttt["develset"] and ttt["median_ms"].get("fp32") and \
+                    (ttt["develset"].get("bf16x3") or {}).get("median_ms_develset"):
                 ttt["develset_bf16x3_speedup_vs_plain"] = round(
                     ttt["median_ms"]["fp32"] / ttt["develset"]["bf16x3"]["median_ms_develset"], 3)
 
@@ -427,6 +490,10 @@ def main():
     bat = None
     if args.batch_clips > 0:
         bat = batched(args.batch_clips, args.batch_lanes, prec)
+
+    lay = None
+    if args.layout_side > 0:
+        lay = layout_leg(args.layout_side, args.batch_lanes, prec)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -467,6 +534,7 @@ def main():
         "time_to_target": ttt,
         "gwindow_adjoint": gw,
         "batched": bat,
+        "full_layout": lay,
     }
     print(json.dumps(line), flush=True)
 

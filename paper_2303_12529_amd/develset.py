@@ -37,14 +37,15 @@ MOD_SHIFTS = tuple(range(-20, 21, 5))
 
 
 def make_dataset(n_clips: int, seed0: int, net: "_dsn.Net", precision: int = _ilt.ILT_FP32, log=None,
-                 shifts=MOD_SHIFTS):
+                 shifts=MOD_SHIFTS, flags: int = _ilt.ILT_FLAG_GWINDOW_ADJOINT):
     """(x, t) or, for a net with the modulation head, (x, t, t_m, dh): device
     float32 [n, H, W] network inputs and targets, and the chosen shift per
-    clip (numpy int array)."""
+    clip (numpy int array).  flags: the solves' context flags (by default
+    the G-window adjoint, the fastest exact form of the loop)."""
     import torch
     _, H, w, prm = workload_inputs("c1", 0)
     N = 2048
-    ctx = _ilt.Context(H, w, N, precision=precision)
+    ctx = _ilt.Context(H, w, N, precision=precision, flags=flags)
     ctx.autotune()
     p = _ilt.Params.from_dict(prm, init_mode=0)
     pr = _ilt.Params.from_dict(prm)
