@@ -226,7 +226,8 @@ int ilt_profile_read(ilt_ctx *ctx, double *h_out, int n);
  *   xcd_remap     BF16x3 image: XCD-aware tile order (1) or plain (0).
  *   st_xsplit     FP32 adjoint from stored fields: column chunks split over
  *                 this many blocks per row tile, 1..2 (0 = chosen by size:
- *                 2 when the grid would hold fewer than 512 blocks).
+ *                 2 when the grid would hold fewer than 256 blocks; the
+ *                 autotuner leaves it there).
  * ilt_set_tuning drops a captured solve graph (it is re-captured).
  * ilt_autotune: with cache_path non-NULL and a line for this device
  * architecture and problem (N, P, K, n_sets, precision, field buffer) in that

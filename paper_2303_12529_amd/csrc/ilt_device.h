@@ -5,6 +5,35 @@
 namespace ilt_dev {
 
 // --------------------------------------------------------------------------
+// Global -> LDS copies issued from inline assembly: the compiler neither
+// counts them nor waits for them, so every wave waits for its own copies
+// (wait_copies) and then meets the others at a barrier before reading them.
+// --------------------------------------------------------------------------
+__device__ __forceinline__ unsigned lds_offset(const void *p) {
+    return (unsigned)(size_t)(const __attribute__((address_space(3))) void *)p;
+}
+
+// global -> LDS copy of 16 bytes per lane: lane l's bytes land at
+// lds + 16 l (lds wave-uniform); M0 is restored afterwards
+__device__ __forceinline__ void lds_dma16(const void *g, const void *lds) {
+    const unsigned base = __builtin_amdgcn_readfirstlane(lds_offset(lds));
+    unsigned saved;
+    asm volatile(
+        "s_mov_b32 %0, m0\n\t"
+        "s_mov_b32 m0, %2\n\t"
+        "global_load_lds_dwordx4 %1, off\n\t"
+        "s_mov_b32 m0, %0"
+        : "=&s"(saved)
+        : "v"(g), "s"(base)
+        : "memory");
+}
+
+// wait for every outstanding memory operation of this wave, the copies
+// included; as a compiler-visible wait it also retires the compiler's own
+// pending loads, so that none of its waits land inside the chunk loop
+__device__ __forceinline__ void wait_copies() { __builtin_amdgcn_s_waitcnt(0); }
+
+// --------------------------------------------------------------------------
 // Adjoint, shared tail: (d) V = A4 Z over each wave's 32 rows y0.., then
 // W_part += c_j conj(H_j) . V, summed over the four waves in a fixed order.
 // --------------------------------------------------------------------------
@@ -91,27 +120,36 @@ __device__ __forceinline__ void adjoint_tail(const f4 (&accZ)[2][2 * FB + MIX], 
 }
 
 // (c) for one 16-column block xb of a 32-column chunk: Z += (G . E) B3.
+// The B3 operands of step i + 1 are read from LDS before the products of
+// step i are issued (scheduling barriers keep that order), so each step's
+// 4 NB products cover the next step's LDS latency.
 template <int NB>
 __device__ __forceinline__ void adjoint_rows(f4 (&accZ)[2][NB], const f4 (&er)[2], const f4 (&ei)[2],
                                              const float *Bre, const float *Bim, int ldb, int xb, int lq,
                                              int l16) {
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
+    float br[2][NB], bi[2][NB];
+    auto fetch = [&](int i, float (&r)[NB], float (&m)[NB]) {
         const int xr = 16 * xb + 4 * lq + i;
-        float br[NB], bi[NB];
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb) {
-            br[nb] = Bre[xr * ldb + 16 * nb + l16];
-            bi[nb] = Bim[xr * ldb + 16 * nb + l16];
+            r[nb] = Bre[xr * ldb + 16 * nb + l16];
+            m[nb] = Bim[xr * ldb + 16 * nb + l16];
         }
+    };
+    fetch(0, br[0], bi[0]);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        if (i + 1 < 4) fetch(i + 1, br[(i + 1) & 1], bi[(i + 1) & 1]);
+        __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
-            for (int yb = 0; yb < 2; ++yb) accZ[yb][nb] = mfma4(er[yb][i], br[nb], accZ[yb][nb]);
+            for (int yb = 0; yb < 2; ++yb) accZ[yb][nb] = mfma4(er[yb][i], br[i & 1][nb], accZ[yb][nb]);
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
-            for (int yb = 0; yb < 2; ++yb) accZ[yb][nb] = mfma4(ei[yb][i], bi[nb], accZ[yb][nb]);
+            for (int yb = 0; yb < 2; ++yb) accZ[yb][nb] = mfma4(ei[yb][i], bi[i & 1][nb], accZ[yb][nb]);
+        __builtin_amdgcn_sched_barrier(0);
     }
 }
 

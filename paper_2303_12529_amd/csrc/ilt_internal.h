@@ -166,10 +166,10 @@ int adjoint_b3_max_parts(const ilt_ctx *c, int nsets);
 #define ILT_B3_MAX_XSPLIT 4
 #define ILT_ST_MAX_XSPLIT 2
 // by size: split the columns in two when the row tiles x kernel groups x sets
-// would not give every CU two blocks
+// would leave compute units without a block
 inline int adjoint_st_xsplit(const ilt_ctx *c) {
     if (c->st_xsplit > 0) return c->st_xsplit;
-    return ((c->N + 31) / 32) * ((c->K + 3) / 4) * c->n_sets < 512 ? 2 : 1;
+    return ((c->N + 31) / 32) * ((c->K + 3) / 4) * c->n_sets < 256 ? 2 : 1;
 }
 // partial W count of the FP32 adjoint for nsets sets: row tiles x kernel
 // groups, times the column split when the fields are stored

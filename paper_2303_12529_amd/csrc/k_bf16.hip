@@ -288,29 +288,8 @@ __global__ __launch_bounds__(256, 2) void k_image_b3(const __bf16 *__restrict__ 
 // counts them nor waits for them: every wave waits for its own copies
 // (vmcnt 0) and then meets the others at a barrier before reading them.
 // --------------------------------------------------------------------------
-__device__ __forceinline__ unsigned lds_offset(const void *p) {
-    return (unsigned)(size_t)(const __attribute__((address_space(3))) void *)p;
-}
-
-// global -> LDS copy of 16 bytes per lane: lane l's bytes land at
-// lds + 16 l (lds wave-uniform); M0 is restored afterwards
-__device__ __forceinline__ void lds_dma16(const void *g, const void *lds) {
-    const unsigned base = __builtin_amdgcn_readfirstlane(lds_offset(lds));
-    unsigned saved;
-    asm volatile(
-        "s_mov_b32 %0, m0\n\t"
-        "s_mov_b32 m0, %2\n\t"
-        "global_load_lds_dwordx4 %1, off\n\t"
-        "s_mov_b32 m0, %0"
-        : "=&s"(saved)
-        : "v"(g), "s"(base)
-        : "memory");
-}
-
-// wait for every outstanding memory operation of this wave, the copies
-// included; as a compiler-visible wait it also retires the compiler's own
-// pending loads, so that none of its waits land inside the chunk loop
-__device__ __forceinline__ void wait_copies() { __builtin_amdgcn_s_waitcnt(0); }
+using ilt_dev::lds_dma16;
+using ilt_dev::wait_copies;
 
 // G[y][x..x+3] (x a multiple of 4), zero outside the N x N image, for N % 4 != 0
 __device__ __forceinline__ f4 load_g4_any(const float *__restrict__ G, int N, int y, int x) {
@@ -529,7 +508,7 @@ hipError_t launch_adjoint_b3(ilt_ctx *c, const float *G, size_t g_set_stride, in
     dim3 grid((c->N + 127) / 128 * xsplit, c->K, set_hi - set_lo);
 #define ADJB(KP_, FB_, MIX_)                                                                                   \
     do {                                                                                                       \
-        if ((c->N & 3) == 0)                                                                                   \
+        if ((c->N & 3) == 0 && (reinterpret_cast<uintptr_t>(G) & 15) == 0)                                    \
             k_adjoint_b3<KP_, FB_, MIX_, true><<<grid, 256, 0, c->stream>>>(                                   \
                 c->tlhl, c->tbhl, c->ta4, c->Yhl, G, g_set_stride, c->coef, c->K, c->P, c->N, c->Np, c->AP,     \
                 set_lo, xsplit, c->Wpart);                                                                     \

@@ -353,25 +353,38 @@ __global__ __launch_bounds__(256, 2) void k_image(const float *__restrict__ tl, 
 
 // --------------------------------------------------------------------------
 // Adjoint from stored fields.  Block = (32-row tile, group of 4 kernels,
-// set); wave w handles kernel j = 4*group + w and walks all columns in
+// set); wave w handles kernel j = 4*group + w and walks its columns in
 // 32-column chunks:
 //   X = G . E_j    (E_j fragments read in accumulator layout, G from LDS)
 //   Z += X B3      (E fragments are the A-operand as loaded; B3 from LDS)
 // then the shared tail.  grid.y = kernel groups x column ranges: a block
 // walks its range of chunks only (its partial W is summed with the others').
+//
+// Pipeline, one barrier per chunk: the B3 rows and G tile of chunk c + 1
+// are copied global -> LDS (no registers) into the other half of
+// double-buffered tiles, and the E fragments of the next 16-column half are
+// loaded into registers, while the current half is multiplied.  Both are
+// issued only after the compiler's wait for the current half's fragments,
+// so that its waits never cover them; the chunk ends with a full wait and
+// the barrier.  G tiles are copied with clamped coordinates and masked when
+// read (N % 4 == 0), else staged through registers.  The tail's W
+// accumulator reuses the two B3 tiles.
 // --------------------------------------------------------------------------
-template <int FB, int MIX>
+template <int FB, int MIX, bool A4>
 __global__ __launch_bounds__(256, 2) void k_adjoint_st(const float *__restrict__ tb, const float *__restrict__ ta4,
                                                     const float *__restrict__ Est, const float *__restrict__ G,
                                                     size_t g_set_stride, const float2 *__restrict__ coef, int K,
                                                     int P, int N, int Np, int AP, int set_lo,
                                                     float *__restrict__ Wpart) {
     constexpr int NZ = 32 * FB + 16 * MIX, NB = NZ / 16;
-    constexpr int LDB = NZ + 4;
-    constexpr int NBV = (2 * 32 * NZ / 4 + 255) / 256;    // float4 of B3 per thread per chunk
-    __shared__ float Gs[32][36];
-    __shared__ float Bs[2][32][LDB];
-    __shared__ float2 Ws[ILT_MAX_P * ILT_MAX_P];
+    constexpr int LDB = NZ + 4;                       // row: NZ / 4 data units + 1 pad unit of 16 B
+    constexpr int BU = 2 * 32 * (LDB / 4);            // 16-byte units of one B3 tile (a multiple of 64)
+    constexpr int GU = 320;                           // G tile [32][36] = 288 units, padded to 5 x 64
+    static_assert(BU % 64 == 0, "B3 tile must be whole wave copies");
+    static_assert((size_t)2 * BU * 16 >= sizeof(float2) * ILT_MAX_P * ILT_MAX_P, "W accumulator must fit the B3 tiles");
+    __shared__ __align__(16) float Bs[2][BU * 4];
+    __shared__ __align__(16) float Gs[2][GU * 4];
+    float2 *Ws = reinterpret_cast<float2 *>(&Bs[0][0]);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int l16 = lane & 15, lq = lane >> 4;
     const int kgroups = (K + 3) / 4;
@@ -393,52 +406,105 @@ __global__ __launch_bounds__(256, 2) void k_adjoint_st(const float *__restrict__
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb) accZ[yb][nb] = f4{0.f, 0.f, 0.f, 0.f};
 
-    for (int c = c_begin; c < c_end; ++c) {
+    // B3 rows x0.. of both parts into tile bb (pad units copy a valid row start)
+    auto copy_b = [&](int c, int bb) {
         const int x0 = c * 32;
-        __syncthreads();
-#pragma unroll
-        for (int v = 0; v < NBV; ++v) {
-            const int e = threadIdx.x + 256 * v;
-            if (e < 2 * 32 * NZ / 4) {
-                const int part = e / (32 * NZ / 4), rem = e % (32 * NZ / 4);
-                const int xx = rem / (NZ / 4), c4 = (rem % (NZ / 4)) * 4;
-                *reinterpret_cast<float4 *>(&Bs[part][xx][c4]) =
-                    *reinterpret_cast<const float4 *>(tb + ((size_t)part * Np + x0 + xx) * NZ + c4);
-            }
+        for (int i = wave; i < BU / 64; i += 4) {
+            const int U = 64 * i + lane;
+            const int part = U / (32 * (LDB / 4)), rem = U - part * (32 * (LDB / 4));
+            const int row = rem / (LDB / 4), c4 = rem - row * (LDB / 4);
+            const float *src = tb + ((size_t)part * Np + x0 + row) * NZ + (c4 < NZ / 4 ? 4 * c4 : 0);
+            ilt_dev::lds_dma16(src, &Bs[bb][256 * i]);
         }
+    };
+    // G rows y0.., columns x0.. into tile bb, coordinates clamped into the image
+    auto copy_g = [&](int c, int bb) {
+        const int x0 = c * 32;
+        for (int i = wave; i < GU / 64; i += 4) {
+            const int U = 64 * i + lane;
+            const int row = U / 9, c4 = U - (U / 9) * 9;
+            const bool data = U < 288 && c4 < 8;
+            const int y = min(y0 + (data ? row : 0), N - 1), x = min(x0 + (data ? 4 * c4 : 0), N - 4);
+            ilt_dev::lds_dma16(Gsrc + (size_t)y * N + x, &Gs[bb][256 * i]);
+        }
+    };
+    // N % 4 != 0: G staged through registers, 4 values per thread
+    float gr[4];
+    auto load_g_regs = [&](int c) {
+        const int x0 = c * 32;
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             const int e = threadIdx.x + 256 * v;
-            const int yy = e >> 5, xx = e & 31;
-            const int gy = y0 + yy, gx = x0 + xx;
-            Gs[yy][xx] = (gy < N && gx < N) ? Gsrc[(size_t)gy * N + gx] : 0.f;
+            const int gy = y0 + (e >> 5), gx = x0 + (e & 31);
+            gr[v] = (gy < N && gx < N) ? Gsrc[(size_t)gy * N + gx] : 0.f;
         }
-        f4 e_[2][2][2];
-        if (jok) {
+    };
+    auto store_g_regs = [&](int bb) {
 #pragma unroll
-            for (int yb = 0; yb < 2; ++yb)
-#pragma unroll
-                for (int xb = 0; xb < 2; ++xb) {
-                    const float *src = Ej + (((size_t)(ytile * 2 + yb) * NB16) + (c * 2 + xb)) * 512 + lane * 4;
-                    e_[yb][xb][0] = __builtin_nontemporal_load(reinterpret_cast<const f4 *>(src));
-                    e_[yb][xb][1] = __builtin_nontemporal_load(reinterpret_cast<const f4 *>(src + 256));
-                }
+        for (int v = 0; v < 4; ++v) {
+            const int e = threadIdx.x + 256 * v;
+            Gs[bb][(e >> 5) * 36 + (e & 31)] = gr[v];
         }
-        __syncthreads();
-        if (jok) {
+    };
+    auto load_half = [&](int c, int xb, f4 (&e_)[2][2]) {
 #pragma unroll
-            for (int xb = 0; xb < 2; ++xb) {
-                f4 er[2], ei[2];
+        for (int yb = 0; yb < 2; ++yb) {
+            const float *src = Ej + (((size_t)(ytile * 2 + yb) * NB16) + (c * 2 + xb)) * 512 + lane * 4;
+            e_[yb][0] = __builtin_nontemporal_load(reinterpret_cast<const f4 *>(src));
+            e_[yb][1] = __builtin_nontemporal_load(reinterpret_cast<const f4 *>(src + 256));
+        }
+    };
+    // X = G . E for one 16-column half (G masked outside the image)
+    auto form_x = [&](int c, int bb, int xb, const f4 (&e_)[2][2], f4 (&er)[2], f4 (&ei)[2]) {
+        const int gx = c * 32 + 16 * xb + 4 * lq;
 #pragma unroll
-                for (int yb = 0; yb < 2; ++yb) {
-                    const float4 gv = *reinterpret_cast<const float4 *>(&Gs[16 * yb + l16][16 * xb + 4 * lq]);
-                    const f4 g4 = f4{gv.x, gv.y, gv.z, gv.w};
-                    er[yb] = e_[yb][xb][0] * g4;
-                    ei[yb] = e_[yb][xb][1] * g4;
-                }
-                ilt_dev::adjoint_rows<NB>(accZ, er, ei, &Bs[0][0][0], &Bs[1][0][0], LDB, xb, lq, l16);
+        for (int yb = 0; yb < 2; ++yb) {
+            const float4 gv = *reinterpret_cast<const float4 *>(&Gs[bb][(16 * yb + l16) * 36 + 16 * xb + 4 * lq]);
+            f4 g4 = f4{gv.x, gv.y, gv.z, gv.w};
+            if (A4) {
+                const bool rin = y0 + 16 * yb + l16 < N;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) g4[i] = (rin && gx + i < N) ? g4[i] : 0.f;
             }
+            er[yb] = e_[yb][0] * g4;
+            ei[yb] = e_[yb][1] * g4;
         }
+    };
+
+    f4 ea[2][2], eb[2][2];
+    if (c_begin < c_end) {
+        copy_b(c_begin, 0);
+        if (A4) copy_g(c_begin, 0);
+        else {
+            load_g_regs(c_begin);
+            store_g_regs(0);
+        }
+        if (jok) load_half(c_begin, 0, ea);
+    }
+    ilt_dev::wait_copies();
+    __syncthreads();
+    for (int c = c_begin; c < c_end; ++c) {
+        const int bb = (c - c_begin) & 1;
+        const bool more = c + 1 < c_end;
+        if (jok) load_half(c, 1, eb);
+        if (jok) {
+            f4 er[2], ei[2];
+            form_x(c, bb, 0, ea, er, ei);
+            ilt_dev::adjoint_rows<NB>(accZ, er, ei, &Bs[bb][0], &Bs[bb][BU * 2], LDB, 0, lq, l16);
+        }
+        f4 er[2], ei[2];
+        if (jok) form_x(c, bb, 1, eb, er, ei);
+        ilt_dev::wait_copies();                        // eb has landed; nothing issued later is waited for
+        if (more) {
+            copy_b(c + 1, bb ^ 1);
+            if (A4) copy_g(c + 1, bb ^ 1);
+            else load_g_regs(c + 1);
+            if (jok) load_half(c + 1, 0, ea);
+        }
+        if (jok) ilt_dev::adjoint_rows<NB>(accZ, er, ei, &Bs[bb][0], &Bs[bb][BU * 2], LDB, 1, lq, l16);
+        if (!A4 && more) store_g_regs(bb ^ 1);
+        ilt_dev::wait_copies();
+        __syncthreads();
     }
     float *dst = Wpart + ((size_t)(srel * gridDim.x + ytile) * gridDim.y + blockIdx.y) * P * P * 2;
     ilt_dev::adjoint_tail<FB, MIX>(accZ, jok, j, s, K, P, Np, AP, y0, ta4, coef, Ws, dst);
@@ -653,9 +719,17 @@ hipError_t launch_adjoint(ilt_ctx *c, const float *G, size_t g_set_stride, int s
         if (!c->Est) return hipErrorInvalidValue;
         grid.y *= adjoint_st_xsplit(c);
         if ((size_t)grid.x * grid.y * grid.z * c->P * c->P * 2 > (size_t)c->n_wpart) return hipErrorInvalidValue;
-#define ADJS(FB_, MIX_)                                                                                       \
-    k_adjoint_st<FB_, MIX_><<<grid, 256, 0, c->stream>>>(c->tb, c->ta4, c->Est, G, g_set_stride, c->coef, c->K, \
-                                                         c->P, c->N, c->Np, c->AP, set_lo, c->Wpart)
+#define ADJS(FB_, MIX_)                                                                                        \
+    do {                                                                                                        \
+        if ((c->N & 3) == 0 && (reinterpret_cast<uintptr_t>(G) & 15) == 0)                                     \
+            k_adjoint_st<FB_, MIX_, true><<<grid, 256, 0, c->stream>>>(c->tb, c->ta4, c->Est, G, g_set_stride,   \
+                                                                      c->coef, c->K, c->P, c->N, c->Np, c->AP, \
+                                                                      set_lo, c->Wpart);                       \
+        else                                                                                                    \
+            k_adjoint_st<FB_, MIX_, false><<<grid, 256, 0, c->stream>>>(c->tb, c->ta4, c->Est, G, g_set_stride,  \
+                                                                       c->coef, c->K, c->P, c->N, c->Np, c->AP, \
+                                                                       set_lo, c->Wpart);                       \
+    } while (0)
         if (c->FB == 0 && c->MIX == 1) ADJS(0, 1);
         else if (c->FB == 1 && c->MIX == 0) ADJS(1, 0);
         else if (c->FB == 1 && c->MIX == 1) ADJS(1, 1);
