@@ -216,8 +216,9 @@ def time_to_target(ctxs, workload, seeds, extra_iters=10):
     for name in list(ctxs) + ["fp32_cg"]:
         ms = [r[name]["ms"] for r in per_seed if r.get(name)]
         out["median_ms"][name] = round(float(np.median(ms)), 3) if len(ms) == len(per_seed) else None
-    if out["median_ms"].get("fp32") and out["median_ms"].get("bf16x3"):
-        out["bf16x3_speedup_vs_plain"] = round(out["median_ms"]["fp32"] / out["median_ms"]["bf16x3"], 3)
+    for name in ctxs:
+        if name != "fp32" and out["median_ms"].get("fp32") and out["median_ms"].get(name):
+            out["%s_speedup_vs_plain" % name] = round(out["median_ms"]["fp32"] / out["median_ms"][name], 3)
     return out
 
 
@@ -227,16 +228,18 @@ DSN_MOD_WEIGHTS = os.path.join(HERE, "paper_2303_12529_amd", "weights", "dsn_c1_
 
 def develset_ttt(seeds):
     """Time to the plain loop's L2 with the trained network's phi_0 (DevelSet,
-    Sec. III-C) vs from TSDF(target): the level-set-branch network in both
-    precisions of the loop, and the two-branch network (level set +
-    modulation, whose m_theta weights every step's curvature term) on the
-    FP32 loop."""
+    Sec. III-C) vs from TSDF(target): the level-set-branch network with the
+    loop in FP32, BF16x3, and BF16x3 with the G-window adjoint, and the
+    two-branch network (level set + modulation, whose m_theta weights every
+    step's curvature term) on the FP32 loop."""
     import numpy as np
     from paper_2303_12529_amd import develset, dsn
     from paper_2303_12529_amd import ilt
     out = {}
-    runs = [("weights", DSN_WEIGHTS, (("fp32", ilt.ILT_FP32), ("bf16x3", ilt.ILT_BF16X3))),
-            ("modulation_net", DSN_MOD_WEIGHTS, (("fp32", ilt.ILT_FP32),))]
+    gw = ilt.ILT_FLAG_GWINDOW_ADJOINT
+    runs = [("weights", DSN_WEIGHTS, (("fp32", ilt.ILT_FP32, 0), ("bf16x3", ilt.ILT_BF16X3, 0),
+                                      ("bf16x3_gwindow", ilt.ILT_BF16X3, gw))),
+            ("modulation_net", DSN_MOD_WEIGHTS, (("fp32", ilt.ILT_FP32, 0),))]
     for label, path, forms in runs:
         if not os.path.exists(path):
             continue
@@ -246,8 +249,8 @@ def develset_ttt(seeds):
         net = dsn.Net(512, 512, 32, max_batch=1, modulation=modulation)
         net.set_params(flat)
         res = {"weights": os.path.relpath(path, HERE), "modulation": modulation}
-        for name, prec in forms:
-            ev = develset.evaluate(net, seeds, precision=prec)
+        for name, prec, flags in forms:
+            ev = develset.evaluate(net, seeds, precision=prec, flags=flags)
             r = {"median_ms_plain": ev["median_ms_plain"], "median_ms_develset": ev["median_ms_develset"],
                  "speedup": ev.get("speedup"), "dsn_used": ev["dsn_used"],
                  "iters_develset": [x["iters_develset"] for x in ev["per_seed"]],
@@ -469,8 +472,12 @@ def main():
 
     ttt = None
     if args.ttt_seeds > 0:
-        ctxs = {"fp32": ctx if prec == ilt.ILT_FP32 else ilt.Context(H, w, N, precision=ilt.ILT_FP32),
-                "bf16x3": ctx if prec == ilt.ILT_BF16X3 else ilt.Context(H, w, N, precision=ilt.ILT_BF16X3)}
+        ctxs = {"fp32": ctx if prec == ilt.ILT_FP32 and flags == 0 else ilt.Context(H, w, N, precision=ilt.ILT_FP32),
+                "bf16x3": ctx if prec == ilt.ILT_BF16X3 and flags == 0 else ilt.Context(H, w, N,
+                                                                                      precision=ilt.ILT_BF16X3)}
+        if not args.no_gwindow:
+            ctxs["bf16x3_gwindow"] = ilt.Context(H, w, N, precision=ilt.ILT_BF16X3,
+                                                 flags=ilt.ILT_FLAG_GWINDOW_ADJOINT)
         if not args.no_autotune:
             for c in ctxs.values():
                 if c is not ctx:
@@ -478,10 +485,11 @@ def main():
         ttt = time_to_target(ctxs, args.workload, range(args.ttt_seeds))
         if args.workload == "c1":
             ttt["develset"] = develset_ttt(range(args.ttt_seeds))
-            if ttt["develset"] and ttt["median_ms"].get("fp32") and \
-                    (ttt["develset"].get("bf16x3") or {}).get("median_ms_develset"):
-                ttt["develset_bf16x3_speedup_vs_plain"] = round(
-                    ttt["median_ms"]["fp32"] / ttt["develset"]["bf16x3"]["median_ms_develset"], 3)
+            for form in ("bf16x3", "bf16x3_gwindow"):
+                if ttt["develset"] and ttt["median_ms"].get("fp32") and \
+                        (ttt["develset"].get(form) or {}).get("median_ms_develset"):
+                    ttt["develset_%s_speedup_vs_plain" % form] = round(
+                        ttt["median_ms"]["fp32"] / ttt["develset"][form]["median_ms_develset"], 3)
 
     gw = None
     if not args.no_gwindow:

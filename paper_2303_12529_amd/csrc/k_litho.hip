@@ -33,7 +33,12 @@ __device__ __forceinline__ float wave_max(float v) {
 // Spectrum.  Block = one 16-row band x one of gridDim.y column ranges, 8
 // waves splitting the range:
 //   T1[y][n] = sum_x M[y][x] tb0[x][n]        (matrix cores; M = [phi<=0] or src)
-//   Spart[band][a][b] = sum_{y in band} A[a][y] T1[y][b]   (FP64)
+//   Spart[band][a][b] = sum_{y in band} A[a][y] T1[y][b]
+// The band product is a 16-deep complex GEMM on the matrix cores too: per
+// 16 x 16 output tile, S_re = [Ar | -Ai] [T1_re; T1_im] and
+// S_im = [Ar | Ai] [T1_im; T1_re], the B operands gathered from the band's
+// T1 columns of the window layout.  Band partials are FP32 (16-term sums);
+// they are summed over the bands in FP64.
 // Each lane loads four consecutive columns of its row as one float4 and uses
 // them in four consecutive k-steps; the B-operand rows follow the same
 // (x = 4(l/16) + e) order, so the sum is unchanged.
@@ -42,11 +47,11 @@ template <int FB, int MIX>
 __global__ __launch_bounds__(512) void k_spectrum_band(const float *__restrict__ src, int src_is_phi,
                                                        const float *__restrict__ tb, const float *__restrict__ ar,
                                                        const float *__restrict__ ai, int P, int N,
-                                                       int Np, double2 *__restrict__ Spart) {
+                                                       int Np, float2 *__restrict__ Spart) {
     constexpr int NZ = 32 * FB + 16 * MIX;
     constexpr int NB = NZ / 16;
     constexpr int PW = (NZ + 1) / 2 + 8;          // >= the window side of this layout
-    __shared__ float red[8][16][NZ + 1];
+    __shared__ float red[4][16][NZ + 1];
     __shared__ float twr[PW][17], twi[PW][17];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int l16 = lane & 15, lq = lane >> 4;
@@ -83,17 +88,29 @@ __global__ __launch_bounds__(512) void k_spectrum_band(const float *__restrict__
             for (int nb = 0; nb < NB; ++nb) acc[nb] = mfma4(m[e], brow[nb * 16], acc[nb]);
         }
     }
+    // sum of the 8 waves' partials in a fixed order, through half as much
+    // LDS: waves 4..7 store, waves 0..3 add theirs (w + (w + 4)), then the
+    // four pair sums are added in order
+    if (wave >= 4) {
 #pragma unroll
-    for (int nb = 0; nb < NB; ++nb)
+        for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
-        for (int i = 0; i < 4; ++i) red[wave][4 * lq + i][nb * 16 + l16] = acc[nb][i];
+            for (int i = 0; i < 4; ++i) red[wave - 4][4 * lq + i][nb * 16 + l16] = acc[nb][i];
+    }
+    __syncthreads();
+    if (wave < 4) {
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                float &r = red[wave][4 * lq + i][nb * 16 + l16];
+                r = acc[nb][i] + r;
+            }
+    }
     __syncthreads();
     for (int e = threadIdx.x; e < 16 * NZ; e += 512) {
         const int r = e / NZ, n = e % NZ;
-        float s = 0.f;
-#pragma unroll
-        for (int w = 0; w < 8; ++w) s += red[w][r][n];
-        red[0][r][n] = s;
+        red[0][r][n] = ((red[0][r][n] + red[1][r][n]) + red[2][r][n]) + red[3][r][n];
     }
     __syncthreads();
     // the band's 16 twiddle columns of every window row, once per block
@@ -104,18 +121,30 @@ __global__ __launch_bounds__(512) void k_spectrum_band(const float *__restrict__
         twi[a][r] = ai[(size_t)a * Np + yy];
     }
     __syncthreads();
-    const int rows = min(16, N - y0);
-    // band partial of S = A T1, complex, FP64
-    for (int e = threadIdx.x; e < P * P; e += 512) {
-        const int a = e / P, b = e % P;
-        double sr = 0.0, si = 0.0;
-        for (int r = 0; r < rows; ++r) {
-            const double c = twr[a][r], s = twi[a][r];
-            const double tr = red[0][r][win_re(b, FB)], ti = red[0][r][win_im(b, FB)];
-            sr += c * tr - s * ti;
-            si += c * ti + s * tr;
+    // band partial of S = A T1 (rows of the band beyond the image hold T1 = 0)
+    float2 *dst = Spart + ((size_t)blockIdx.x * gridDim.y + blockIdx.y) * P * P;
+    const int TA = (P + 15) / 16;
+    for (int t = wave; t < TA * TA; t += 8) {
+        const int ta = t / TA, tc = t - (t / TA) * TA;
+        const int a = 16 * ta + l16, b = 16 * tc + l16;
+        const bool aok = a < P, bok = b < P;
+        const int cre = bok ? win_re(b, FB) : 0, cim = bok ? win_im(b, FB) : 0;
+        f4 sre = f4{0.f, 0.f, 0.f, 0.f}, sim = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) {
+            const int r = 4 * ks + lq;
+            const float cw = aok ? twr[a][r] : 0.f, sw = aok ? twi[a][r] : 0.f;
+            const float tre = red[0][r][cre], tim = red[0][r][cim];
+            sre = mfma4(cw, tre, sre);
+            sre = mfma4(-sw, tim, sre);
+            sim = mfma4(cw, tim, sim);
+            sim = mfma4(sw, tre, sim);
         }
-        Spart[((size_t)blockIdx.x * gridDim.y + blockIdx.y) * P * P + e] = make_double2(sr, si);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int ao = 16 * ta + 4 * lq + i;
+            if (ao < P && bok) dst[ao * P + b] = make_float2(sre[i], sim[i]);
+        }
     }
 }
 
@@ -680,7 +709,7 @@ static hipError_t spectrum_to(ilt_ctx *c, const float *src, int src_is_phi, int 
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int n = Pw * Pw;
-    k_psum<double2><<<(n + 15) / 16, 1024, 0, c->stream>>>(c->Spart, nband * xs, n, out);
+    k_psum<float2><<<(n + 15) / 16, 1024, 0, c->stream>>>(c->Spart, nband * xs, n, out);
     return hipGetLastError();
 }
 

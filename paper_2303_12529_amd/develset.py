@@ -125,12 +125,14 @@ def train(net: "_dsn.Net", x, t, epochs: int, batch: int, lr: float = 1e-3, seed
     return hist
 
 
-def evaluate(net: "_dsn.Net", seeds, precision: int = _ilt.ILT_FP32, extra_iters: int = 10, log=None):
-    """Time to the plain loop's L2 from TSDF(target) vs from the network's phi_0."""
+def evaluate(net: "_dsn.Net", seeds, precision: int = _ilt.ILT_FP32, extra_iters: int = 10, log=None,
+             flags: int = 0):
+    """Time to the plain loop's L2 from TSDF(target) vs from the network's
+    phi_0, with the loop in the given precision and context flags."""
     import torch
     _, H, w, prm = workload_inputs("c1", 0)
     N = 2048
-    ctx = _ilt.Context(H, w, N, precision=precision)
+    ctx = _ilt.Context(H, w, N, precision=precision, flags=flags)
     ctx.autotune()
     T = prm["iters"]
     rows = []
