@@ -9,28 +9,26 @@
 namespace {
 
 constexpr int RB = 256;           // threads per reduction block
-constexpr int MAX_RBLK = 1024;    // cap on reduction blocks
+constexpr int MAX_RBLK = 2048;    // cap on reduction blocks
 
+static_assert(RB == 256, "block reductions combine four waves");
+
+// Block reductions in a fixed order: a shuffle tree inside each wave, then
+// the four wave results in wave order; every thread receives the result.
 __device__ __forceinline__ double block_sum(double v, double *sh) {
-    sh[threadIdx.x] = v;
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
     __syncthreads();
-    for (int o = RB / 2; o > 0; o >>= 1) {
-        if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
-        __syncthreads();
-    }
-    const double r = sh[0];
+    const double r = ((sh[0] + sh[1]) + sh[2]) + sh[3];
     __syncthreads();
     return r;
 }
 
 __device__ __forceinline__ double block_max(double v, double *sh) {
-    sh[threadIdx.x] = v;
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_down(v, o, 64));
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
     __syncthreads();
-    for (int o = RB / 2; o > 0; o >>= 1) {
-        if (threadIdx.x < o) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + o]);
-        __syncthreads();
-    }
-    const double r = sh[0];
+    const double r = fmax(fmax(sh[0], sh[1]), fmax(sh[2], sh[3]));
     __syncthreads();
     return r;
 }
@@ -42,42 +40,65 @@ __device__ __forceinline__ double block_max(double v, double *sh) {
 // Block b covers a contiguous pixel range; partials {loss, l2, pvb, nonfinite}.
 // --------------------------------------------------------------------------
 // One pixel of the resist: loss, G contributions and the print decisions.
+// The sigmoid's reciprocal is the hardware one (1 ulp); print counts are
+// integers per thread, the loss an FP64 sum.
+//
+// Corner layouts: CL = 0 any (corners' sets chosen at run time), CL = 1 one
+// corner on set 0, CL = 2 three corners on sets 0, 0, 1 (nominal, outer,
+// inner).  The fixed layouts index the sets at compile time.
+constexpr int corner_count(int CL) { return CL == 1 ? 1 : CL == 2 ? 3 : 4; }
+constexpr int corner_set(int CL, int c) { return CL == 2 ? (c == 2 ? 1 : 0) : 0; }
+
+template <int CL>
 __device__ __forceinline__ void resist_pixel(const resist_args &ra, float zt, const float (&ii)[ILT_MAX_SETS],
-                                             float (&gs)[ILT_MAX_SETS], double &loss, double &l2, double &pvb,
-                                             double &bad) {
+                                             float (&gs)[ILT_MAX_SETS], double &loss, unsigned &l2, unsigned &pvb,
+                                             unsigned &bad) {
     float lp = 0.f;
     bool print[4] = {false, false, false, false};
 #pragma unroll
     for (int q = 0; q < ILT_MAX_SETS; ++q) gs[q] = 0.f;
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
-        if (c < ra.n_corners) {
-            const int s = ra.cset[c];
+    for (int c = 0; c < corner_count(CL); ++c) {
+        if (CL != 0 || c < ra.n_corners) {
             const float d = ra.dose[c];
             float iv = 0.f;
+            if (CL != 0) {
+                iv = ii[corner_set(CL, c)];
+            } else {
 #pragma unroll
-            for (int q = 0; q < ILT_MAX_SETS; ++q)
-                if (q == s) iv = ii[q];
+                for (int q = 0; q < ILT_MAX_SETS; ++q)
+                    if (q == ra.cset[c]) iv = ii[q];
+            }
             const float di = d * iv;
-            const float z = 1.f / (1.f + expf(-ra.sigma_z * (di - ra.i_th)));
+            const float z = __builtin_amdgcn_rcpf(1.f + expf(-ra.sigma_z * (di - ra.i_th)));
             const float r = z - zt;
             lp = fmaf(ra.omega[c] * r, r, lp);
             const float gv = ra.omega[c] * 2.f * ra.sigma_z * d * r * (z * (1.f - z));
+            if (CL != 0) {
+                gs[corner_set(CL, c)] += gv;
+            } else {
 #pragma unroll
-            for (int q = 0; q < ILT_MAX_SETS; ++q)
-                if (q == s) gs[q] += gv;
+                for (int q = 0; q < ILT_MAX_SETS; ++q)
+                    if (q == ra.cset[c]) gs[q] += gv;
+            }
             print[c] = di >= ra.i_th;
         }
     }
     loss += (double)lp;
-    if (!isfinite(lp)) bad += 1.0;
-    l2 += (print[0] != (zt != 0.f)) ? 1.0 : 0.0;
-    if (ra.n_corners >= 3) pvb += (print[1] != print[2]) ? 1.0 : 0.0;
+    bad += !isfinite(lp);
+    l2 += print[0] != (zt != 0.f);
+    if (CL == 2 || (CL == 0 && ra.n_corners >= 3)) pvb += print[1] != print[2];
+}
+
+// sets a corner layout reads
+__device__ __forceinline__ bool layout_uses(int CL, const resist_args &ra, int q) {
+    return CL == 1 ? q == 0 : CL == 2 ? q < 2 : ra.set_used[q] != 0;
 }
 
 // Four consecutive pixels per thread and step (16-byte loads and stores);
 // block b covers quads [b chunk, (b + 1) chunk).  Needs npix % 4 == 0 (every
 // set's image then starts 16-byte aligned).
+template <int CL>
 __global__ __launch_bounds__(RB) void k_resist4(const float *__restrict__ I, size_t set_stride,
                                                const uint8_t *__restrict__ target, resist_args ra,
                                                size_t npix, size_t chunk, float *__restrict__ G,
@@ -86,15 +107,33 @@ __global__ __launch_bounds__(RB) void k_resist4(const float *__restrict__ I, siz
     const size_t nq = npix / 4;
     const size_t lo = (size_t)blockIdx.x * chunk;
     const size_t hi = min(nq, lo + chunk);
-    double loss = 0.0, l2 = 0.0, pvb = 0.0, bad = 0.0;
-    for (size_t q4 = lo + threadIdx.x; q4 < hi; q4 += RB) {
-        const size_t p = 4 * q4;
-        const uchar4 t4 = *reinterpret_cast<const uchar4 *>(target + p);
-        float4 iv[ILT_MAX_SETS];
+    double loss = 0.0;
+    unsigned l2 = 0, pvb = 0, bad = 0;
+    // the loads of RU consecutive steps are issued together
+    constexpr int RU = 4;
+    for (size_t base = lo + threadIdx.x; base < hi; base += (size_t)RB * RU) {
+      uchar4 tq[RU];
+      float4 ivq[RU][ILT_MAX_SETS];
 #pragma unroll
-        for (int q = 0; q < ILT_MAX_SETS; ++q)
-            iv[q] = ra.set_used[q] ? *reinterpret_cast<const float4 *>(I + (size_t)q * set_stride + p)
-                                   : make_float4(0.f, 0.f, 0.f, 0.f);
+      for (int u = 0; u < RU; ++u) {
+        const size_t q4 = base + (size_t)u * RB;
+        tq[u] = make_uchar4(0, 0, 0, 0);
+#pragma unroll
+        for (int q = 0; q < ILT_MAX_SETS; ++q) ivq[u][q] = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (q4 < hi) {
+            tq[u] = *reinterpret_cast<const uchar4 *>(target + 4 * q4);
+#pragma unroll
+            for (int q = 0; q < ILT_MAX_SETS; ++q)
+                if (layout_uses(CL, ra, q)) ivq[u][q] = *reinterpret_cast<const float4 *>(I + (size_t)q * set_stride + 4 * q4);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < RU; ++u) {
+        const size_t q4 = base + (size_t)u * RB;
+        if (q4 >= hi) break;
+        const size_t p = 4 * q4;
+        const uchar4 t4 = tq[u];
+        const float4 (&iv)[ILT_MAX_SETS] = ivq[u];
         float g4[ILT_MAX_SETS][4];
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
@@ -103,25 +142,26 @@ __global__ __launch_bounds__(RB) void k_resist4(const float *__restrict__ I, siz
 #pragma unroll
             for (int q = 0; q < ILT_MAX_SETS; ++q)
                 ii[q] = e == 0 ? iv[q].x : e == 1 ? iv[q].y : e == 2 ? iv[q].z : iv[q].w;
-            resist_pixel(ra, tb ? 1.f : 0.f, ii, gs, loss, l2, pvb, bad);
+            resist_pixel<CL>(ra, tb ? 1.f : 0.f, ii, gs, loss, l2, pvb, bad);
 #pragma unroll
             for (int q = 0; q < ILT_MAX_SETS; ++q) g4[q][e] = gs[q];
         }
 #pragma unroll
         for (int q = 0; q < ILT_MAX_SETS; ++q)
-            if (ra.set_used[q])
+            if (layout_uses(CL, ra, q))
                 *reinterpret_cast<float4 *>(G + (size_t)q * set_stride + p) =
                     make_float4(g4[q][0], g4[q][1], g4[q][2], g4[q][3]);
+      }
     }
     loss = block_sum(loss, sh);
-    l2 = block_sum(l2, sh);
-    pvb = block_sum(pvb, sh);
-    bad = block_sum(bad, sh);
+    const double l2s = block_sum((double)l2, sh);
+    const double pvbs = block_sum((double)pvb, sh);
+    const double bads = block_sum((double)bad, sh);
     if (threadIdx.x == 0) {
         part[blockIdx.x * 4 + 0] = loss;
-        part[blockIdx.x * 4 + 1] = l2;
-        part[blockIdx.x * 4 + 2] = pvb;
-        part[blockIdx.x * 4 + 3] = bad;
+        part[blockIdx.x * 4 + 1] = l2s;
+        part[blockIdx.x * 4 + 2] = pvbs;
+        part[blockIdx.x * 4 + 3] = bads;
     }
 }
 
@@ -134,25 +174,26 @@ __global__ __launch_bounds__(RB) void k_resist1(const float *__restrict__ I, siz
     __shared__ double sh[RB];
     const size_t lo = (size_t)blockIdx.x * chunk;
     const size_t hi = min(npix, lo + chunk);
-    double loss = 0.0, l2 = 0.0, pvb = 0.0, bad = 0.0;
+    double loss = 0.0;
+    unsigned l2 = 0, pvb = 0, bad = 0;
     for (size_t p = lo + threadIdx.x; p < hi; p += RB) {
         float ii[ILT_MAX_SETS], gs[ILT_MAX_SETS];
 #pragma unroll
         for (int q = 0; q < ILT_MAX_SETS; ++q) ii[q] = ra.set_used[q] ? I[(size_t)q * set_stride + p] : 0.f;
-        resist_pixel(ra, target[p] ? 1.f : 0.f, ii, gs, loss, l2, pvb, bad);
+        resist_pixel<0>(ra, target[p] ? 1.f : 0.f, ii, gs, loss, l2, pvb, bad);
 #pragma unroll
         for (int q = 0; q < ILT_MAX_SETS; ++q)
             if (ra.set_used[q]) G[(size_t)q * set_stride + p] = gs[q];
     }
     loss = block_sum(loss, sh);
-    l2 = block_sum(l2, sh);
-    pvb = block_sum(pvb, sh);
-    bad = block_sum(bad, sh);
+    const double l2s = block_sum((double)l2, sh);
+    const double pvbs = block_sum((double)pvb, sh);
+    const double bads = block_sum((double)bad, sh);
     if (threadIdx.x == 0) {
         part[blockIdx.x * 4 + 0] = loss;
-        part[blockIdx.x * 4 + 1] = l2;
-        part[blockIdx.x * 4 + 2] = pvb;
-        part[blockIdx.x * 4 + 3] = bad;
+        part[blockIdx.x * 4 + 1] = l2s;
+        part[blockIdx.x * 4 + 2] = pvbs;
+        part[blockIdx.x * 4 + 3] = bads;
     }
 }
 
@@ -281,6 +322,18 @@ __global__ __launch_bounds__(256) void k_levelset(const float *__restrict__ phi,
     __shared__ float t[34][35];
     __shared__ int wsum[4];
     const int bx = blockIdx.x * 32, by = blockIdx.y * 32;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    // the velocity (and modulation) of this thread's pixels, requested before
+    // the tile so that both loads are in flight together
+    float vv[4], mv[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int y = by + ty + 8 * j, x = bx + tx;
+        const bool ok = y < N && x < N;
+        const size_t p = ok ? (size_t)y * N + x : 0;
+        vv[j] = ok ? vel[p] : 0.f;
+        mv[j] = (ok && mod) ? mod[p] : 1.f;
+    }
     for (int e = threadIdx.x; e < 34 * 34; e += 256) {
         const int yy = e / 34, xx = e % 34;
         const int gy = min(max(by + yy - 1, 0), N - 1);
@@ -289,7 +342,6 @@ __global__ __launch_bounds__(256) void k_levelset(const float *__restrict__ phi,
     }
     __syncthreads();
     const float dt = (float)scal[SC_DT];
-    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
     int flips = 0;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
@@ -308,10 +360,9 @@ __global__ __launch_bounds__(256) void k_levelset(const float *__restrict__ phi,
             const float pxy = 0.25f * ((pp - pm) - (mp - mm));
             const float g2 = px * px + py * py;
             const float num = pxx * py * py - 2.f * px * py * pxy + pyy * px * px;
-            const float kap = num / (g2 + eps_kappa);
+            const float kap = num * __builtin_amdgcn_rcpf(g2 + eps_kappa);
             const size_t p = (size_t)y * N + x;
-            const float m = mod ? mod[p] : 1.f;
-            const float nv = c + dt * (vel[p] * sqrtf(g2) + lam * m * kap);
+            const float nv = c + dt * (vv[j] * sqrtf(g2) + lam * mv[j] * kap);
             out[p] = nv;
             flips += ((nv <= 0.f) != (c <= 0.f)) ? 1 : 0;
         }
@@ -682,7 +733,7 @@ size_t chunk_of(size_t npix, int nblk) { return (npix + nblk - 1) / nblk; }
 
 int resist_blocks(const ilt_ctx *c) {
     const size_t npix = (size_t)c->N * c->N;
-    return (int)std::min<size_t>(MAX_RBLK, (npix + 4095) / 4096);
+    return (int)std::min<size_t>(MAX_RBLK, (npix + 2047) / 2048);
 }
 
 hipError_t launch_resist(ilt_ctx *c, const float *I, const uint8_t *target, const resist_args &ra, float *G,
@@ -691,7 +742,17 @@ hipError_t launch_resist(ilt_ctx *c, const float *I, const uint8_t *target, cons
     const int nblk = resist_blocks(c);
     if (npix % 4 == 0 && reinterpret_cast<uintptr_t>(I) % 16 == 0 && reinterpret_cast<uintptr_t>(G) % 16 == 0 &&
         reinterpret_cast<uintptr_t>(target) % 4 == 0)
-        k_resist4<<<nblk, RB, 0, c->stream>>>(I, npix, target, ra, npix, chunk_of(npix / 4, nblk), G, part);
+    {
+        // the corner layouts of the fixed-layout kernels (set_used must agree)
+        const bool one = ra.n_corners == 1 && ra.cset[0] == 0 && ra.set_used[0] && !ra.set_used[1] &&
+                         !ra.set_used[2] && !ra.set_used[3];
+        const bool three = ra.n_corners == 3 && ra.cset[0] == 0 && ra.cset[1] == 0 && ra.cset[2] == 1 &&
+                           ra.set_used[0] && ra.set_used[1] && !ra.set_used[2] && !ra.set_used[3];
+        const size_t ch = chunk_of(npix / 4, nblk);
+        if (one) k_resist4<1><<<nblk, RB, 0, c->stream>>>(I, npix, target, ra, npix, ch, G, part);
+        else if (three) k_resist4<2><<<nblk, RB, 0, c->stream>>>(I, npix, target, ra, npix, ch, G, part);
+        else k_resist4<0><<<nblk, RB, 0, c->stream>>>(I, npix, target, ra, npix, ch, G, part);
+    }
     else
         k_resist1<<<nblk, RB, 0, c->stream>>>(I, npix, target, ra, npix, chunk_of(npix, nblk), G, part);
     return hipGetLastError();
