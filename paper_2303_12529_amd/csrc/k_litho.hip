@@ -233,6 +233,92 @@ __global__ __launch_bounds__(256) void k_window_rows(const float2 *__restrict__ 
 }
 
 // --------------------------------------------------------------------------
+// Window -> rows for every kernel on the matrix cores.  With U_j = H_j . S
+// and conj(A) = Ar - i Ai, the rows of Y_j are
+//   [Re; Im](U_j conj(A)) = C_j [Ar; Ai],  C_j = [[Ur, Ui], [Ui, -Ur]],
+// a (2P x 2P) x (2P x N) real GEMM whose right operand is the image-side
+// table tl (part 0 holds [Ar; Ai] in rows [0, 2P)).  Block = (128-column
+// range, kernel j, set): the scaled C_j is built in LDS, each wave takes 32
+// columns (two 16-column tiles) of every 16-row tile of C_j.
+// --------------------------------------------------------------------------
+template <int KP>
+__global__ __launch_bounds__(256) void k_make_y(const float2 *__restrict__ H, const float2 *__restrict__ S,
+                                                const float *__restrict__ scale, const float *__restrict__ tl,
+                                                int P, int Np, int nj, int set_lo, float *__restrict__ out) {
+    constexpr int MT = (KP + 15) / 16;            // 16-row tiles of C (>= 2P rows)
+    constexpr int LDC = KP + 4;
+    __shared__ float C[16 * MT][LDC];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int l16 = lane & 15, lq = lane >> 4;
+    const int j = blockIdx.y, s = set_lo + blockIdx.z;
+    const float sc = scale[(size_t)s * nj + j];
+    const int x0 = blockIdx.x * 128 + wave * 32;
+    // all of the wave's tl operands are requested first (2 KP / 4 values),
+    // so that their latency overlaps the construction of C
+    float bt[KP / 4][2];
+#pragma unroll
+    for (int ks = 0; ks < KP / 4; ++ks)
+#pragma unroll
+        for (int nt = 0; nt < 2; ++nt) bt[ks][nt] = tl[(size_t)(4 * ks + lq) * Np + x0 + 16 * nt + l16];
+    const float2 *Hj = H + (size_t)(s * nj + j) * P * P;
+    // pad rows and columns of C are zero
+    for (int e = threadIdx.x; e < 16 * MT * KP; e += 256) {
+        const int m = e / KP, k = e - (e / KP) * KP;
+        if (m >= 2 * P || k >= 2 * P) C[m][k] = 0.f;
+    }
+    // each U entry fills four places of C; the loads of a thread's entries
+    // are issued together (P^2 <= 5 x 256)
+    constexpr int UPT = (ILT_MAX_P * ILT_MAX_P + 255) / 256;
+    float2 hv[UPT], sv[UPT];
+#pragma unroll
+    for (int u = 0; u < UPT; ++u) {
+        const int e = threadIdx.x + 256 * u;
+        hv[u] = e < P * P ? Hj[e] : make_float2(0.f, 0.f);
+        sv[u] = e < P * P ? S[e] : make_float2(0.f, 0.f);
+    }
+#pragma unroll
+    for (int u = 0; u < UPT; ++u) {
+        const int e = threadIdx.x + 256 * u;
+        if (e < P * P) {
+            const int a = e / P, b = e - (e / P) * P;
+            const float ur = sc * (hv[u].x * sv[u].x - hv[u].y * sv[u].y);
+            const float ui = sc * (hv[u].x * sv[u].y + hv[u].y * sv[u].x);
+            C[a][b] = ur;
+            C[a][P + b] = ui;
+            C[P + a][b] = ui;
+            C[P + a][P + b] = -ur;
+        }
+    }
+    __syncthreads();
+    f4 acc[MT][2];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < 2; ++nt) acc[mt][nt] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int ks = 0; ks < KP / 4; ++ks) {
+        const int k = 4 * ks + lq;
+        float b[2] = {bt[ks][0], bt[ks][1]}, a[MT];
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) a[mt] = C[16 * mt + l16][k];
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+            for (int nt = 0; nt < 2; ++nt) acc[mt][nt] = mfma4(a[mt], b[nt], acc[mt][nt]);
+    }
+    float *o = out + ((size_t)(s * nj + j) * KP) * Np;
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < 2; ++nt)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int r = 16 * mt + 4 * lq + i;
+                if (r < 2 * P) o[(size_t)r * Np + x0 + 16 * nt + l16] = acc[mt][nt][i];
+            }
+}
+
+// --------------------------------------------------------------------------
 // Image: per 16x16 block, E_j^T = Y_j^T L^T with Re E = L1 Y, Im E = L2 Y.
 //   MODE 0: out = sum_j |E_j|^2      (aerial image of one kernel set)
 //   MODE 1: out = Re E_0             (gradient back-transform), plus the
@@ -718,9 +804,13 @@ hipError_t launch_spectrum(ilt_ctx *c, const float *src, int src_is_phi) {
 }
 
 hipError_t launch_make_Y(ilt_ctx *c, int set_lo, int set_hi) {
-    dim3 grid(c->Np / 64, c->K, set_hi - set_lo);
-    k_window_rows<64, 1><<<grid, 256, 0, c->stream>>>(c->H, c->S, c->sw, 1.f, c->ar, c->ai, c->P, c->KP, c->Np,
-                                                      c->K, set_lo, c->Y);
+    dim3 grid(c->Np / 128, c->K, set_hi - set_lo);
+    switch (c->KP) {
+#define MKY(KP_) case KP_: k_make_y<KP_><<<grid, 256, 0, c->stream>>>(c->H, c->S, c->sw, c->tl, c->P, c->Np, c->K, set_lo, c->Y); break;
+        MKY(8) MKY(24) MKY(40) MKY(72)
+#undef MKY
+        default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
