@@ -445,7 +445,6 @@ extern "C" int litho_forward(ilt_ctx *c, const float *d_mask, int set, float *d_
     HIPCHK(launch_spectrum(c, d_mask, 0));
     HIPCHK(launch_make_Y(c, set, set + 1));
     if (c->precision == ILT_BF16X3) {
-        HIPCHK(launch_split_rows(c, set, set + 1));
         HIPCHK(launch_image_b3(c, set, set + 1, d_aerial));
     } else {
         HIPCHK(launch_image_to(c, set, set + 1, d_aerial, 0));
@@ -465,7 +464,6 @@ extern "C" int litho_adjoint(ilt_ctx *c, const float *d_mask, const float *d_G, 
     if (c->gwin) {
         HIPCHK(launch_adjoint_gwindow(c, d_G, 0, set, set + 1));
     } else if (c->precision == ILT_BF16X3) {
-        HIPCHK(launch_split_rows(c, set, set + 1));
         HIPCHK(launch_adjoint_b3(c, d_G, 0, set, set + 1));
         HIPCHK(launch_window_sum(c, set, set + 1));
     } else {
@@ -558,7 +556,6 @@ int enqueue_solve(ilt_ctx *c, const unsigned char *d_target, float *d_phi, const
         {
             PhaseTimer t(c, 1);
             HIPCHK(launch_make_Y(c, slo, shi));
-            if (b3) HIPCHK(launch_split_rows(c, slo, shi));
         }
         {
             PhaseTimer t(c, 2);
@@ -606,7 +603,6 @@ int enqueue_solve(ilt_ctx *c, const unsigned char *d_target, float *d_phi, const
     HIPCHK(launch_spectrum(c, d_phi, 1));
     HIPCHK(launch_make_Y(c, slo, shi));
     if (b3) {
-        HIPCHK(launch_split_rows(c, slo, shi));
         HIPCHK(launch_image_b3(c, slo, shi, c->I + (size_t)slo * npix));
     } else {
         HIPCHK(launch_image_to(c, slo, shi, c->I + (size_t)slo * npix, 0));

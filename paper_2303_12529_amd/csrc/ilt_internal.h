@@ -151,7 +151,6 @@ hipError_t launch_window_sum(ilt_ctx *c, int set_lo, int set_hi);  // partial co
 hipError_t launch_gradient(ilt_ctx *c, float *g_out, double *maxpart);
 
 // ---- launchers (k_bf16.hip) ----
-hipError_t launch_split_rows(ilt_ctx *c, int set_lo, int set_hi);
 hipError_t launch_image_b3(ilt_ctx *c, int set_lo, int set_hi, float *out);
 hipError_t launch_adjoint_b3(ilt_ctx *c, const float *G, size_t g_set_stride, int set_lo, int set_hi);
 // G-window adjoint: W for sets [set_lo, set_hi) directly (no window_sum)

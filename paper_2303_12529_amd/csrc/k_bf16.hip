@@ -108,32 +108,6 @@ __device__ __forceinline__ void load_l_operands(const __bf16 *__restrict__ tlhl,
     }
 }
 
-// --------------------------------------------------------------------------
-// Split and transpose the window-row operands:
-//   Y  [set][j][KP][Np] fp32   ->   Yhl [set][j][Np][2][KP] bf16 (hi row, lo row)
-// Block: 64 columns x 4 groups of 8 rows.
-// --------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_split_rows(const float *__restrict__ Y, int KP, int Np, int nj, int set_lo,
-                                                    __bf16 *__restrict__ Yhl) {
-    const int j = blockIdx.y, s = set_lo + blockIdx.z;
-    const int x = blockIdx.x * 64 + (threadIdx.x & 63);
-    const int rg = threadIdx.x >> 6;
-    const float *src = Y + ((size_t)(s * nj + j) * KP) * Np + x;
-    __bf16 *dst = Yhl + (((size_t)(s * nj + j) * Np) + x) * 2 * KP;
-    for (int g = rg; g < KP / 8; g += 4) {
-        bf8 h, l;
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            __bf16 a, b;
-            split(src[(size_t)(8 * g + e) * Np], a, b);
-            h[e] = a;
-            l[e] = b;
-        }
-        *reinterpret_cast<bf8 *>(dst + 8 * g) = h;
-        *reinterpret_cast<bf8 *>(dst + KP + 8 * g) = l;
-    }
-}
-
 // XCD-aware tile order: hardware places consecutive blocks round-robin on the
 // 8 XCDs; remap so that the blocks an XCD receives cover all row tiles of the
 // same column tiles, which then share that XCD's L2 for their Y_j tiles.
@@ -468,12 +442,6 @@ __global__ __launch_bounds__(256, 2) void k_adjoint_b3(const __bf16 *__restrict_
 }  // namespace
 
 // ---------------------------------------------------------------- launchers
-
-hipError_t launch_split_rows(ilt_ctx *c, int set_lo, int set_hi) {
-    dim3 grid(c->Np / 64, c->K, set_hi - set_lo);
-    k_split_rows<<<grid, 256, 0, c->stream>>>(c->Y, c->KP, c->Np, c->K, set_lo, c->Yhl);
-    return hipGetLastError();
-}
 
 hipError_t launch_image_b3(ilt_ctx *c, int set_lo, int set_hi, float *out) {
     const int nblk = (c->Np / 64) * (c->Np / 128) * (set_hi - set_lo);

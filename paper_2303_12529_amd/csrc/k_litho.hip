@@ -240,11 +240,14 @@ __global__ __launch_bounds__(256) void k_window_rows(const float2 *__restrict__ 
 // table tl (part 0 holds [Ar; Ai] in rows [0, 2P)).  Block = (128-column
 // range, kernel j, set): the scaled C_j is built in LDS, each wave takes 32
 // columns (two 16-column tiles) of every 16-row tile of C_j.
+// SPLIT: write the split-BF16 form instead, Yhl [set][j][Np][hi | lo][KP]
+// with hi = bf16(y), lo = bf16(y - hi) (rows [2P, KP) zero).
 // --------------------------------------------------------------------------
-template <int KP>
+template <int KP, bool SPLIT>
 __global__ __launch_bounds__(256) void k_make_y(const float2 *__restrict__ H, const float2 *__restrict__ S,
                                                 const float *__restrict__ scale, const float *__restrict__ tl,
-                                                int P, int Np, int nj, int set_lo, float *__restrict__ out) {
+                                                int P, int Np, int nj, int set_lo, float *__restrict__ out,
+                                                __bf16 *__restrict__ outhl) {
     constexpr int MT = (KP + 15) / 16;            // 16-row tiles of C (>= 2P rows)
     constexpr int LDC = KP + 4;
     __shared__ float C[16 * MT][LDC];
@@ -305,6 +308,30 @@ __global__ __launch_bounds__(256) void k_make_y(const float2 *__restrict__ H, co
         for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
             for (int nt = 0; nt < 2; ++nt) acc[mt][nt] = mfma4(a[mt], b[nt], acc[mt][nt]);
+    }
+    if (SPLIT) {
+        // four consecutive rows per lane: 8 bytes of hi and 8 of lo per column
+        typedef __bf16 bf4 __attribute__((ext_vector_type(4)));
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+            const int r0 = 16 * mt + 4 * lq;
+            if (r0 >= KP) continue;
+#pragma unroll
+            for (int nt = 0; nt < 2; ++nt) {
+                const int x = x0 + 16 * nt + l16;
+                bf4 h, l;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const float v = acc[mt][nt][i];
+                    h[i] = (__bf16)v;
+                    l[i] = (__bf16)(v - (float)h[i]);
+                }
+                __bf16 *d = outhl + (((size_t)(s * nj + j) * Np) + x) * 2 * KP + r0;
+                *reinterpret_cast<bf4 *>(d) = h;
+                *reinterpret_cast<bf4 *>(d + KP) = l;
+            }
+        }
+        return;
     }
     float *o = out + ((size_t)(s * nj + j) * KP) * Np;
 #pragma unroll
@@ -805,8 +832,18 @@ hipError_t launch_spectrum(ilt_ctx *c, const float *src, int src_is_phi) {
 
 hipError_t launch_make_Y(ilt_ctx *c, int set_lo, int set_hi) {
     dim3 grid(c->Np / 128, c->K, set_hi - set_lo);
+    // the split-BF16 form reads only the split rows, written here directly
+    const bool split = c->precision == ILT_BF16X3;
     switch (c->KP) {
-#define MKY(KP_) case KP_: k_make_y<KP_><<<grid, 256, 0, c->stream>>>(c->H, c->S, c->sw, c->tl, c->P, c->Np, c->K, set_lo, c->Y); break;
+#define MKY(KP_)                                                                                               \
+    case KP_:                                                                                                  \
+        if (split)                                                                                             \
+            k_make_y<KP_, true><<<grid, 256, 0, c->stream>>>(c->H, c->S, c->sw, c->tl, c->P, c->Np, c->K, set_lo, \
+                                                             nullptr, c->Yhl);                                 \
+        else                                                                                                   \
+            k_make_y<KP_, false><<<grid, 256, 0, c->stream>>>(c->H, c->S, c->sw, c->tl, c->P, c->Np, c->K,      \
+                                                              set_lo, c->Y, nullptr);                          \
+        break;
         MKY(8) MKY(24) MKY(40) MKY(72)
 #undef MKY
         default: return hipErrorInvalidValue;
