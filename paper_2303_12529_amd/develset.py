@@ -36,12 +36,20 @@ from .inputs import C1_CLIP, WORKLOADS, gen_clip, workload_inputs
 MOD_SHIFTS = tuple(range(-20, 21, 5))
 
 
+def clip_of_seed(seed: int):
+    """The 2048^2 training clip of one seed (a module-level function, so that
+    worker processes can draw clips while the device solves)."""
+    return gen_clip(C1_CLIP, seed)
+
+
 def make_dataset(n_clips: int, seed0: int, net: "_dsn.Net", precision: int = _ilt.ILT_FP32, log=None,
-                 shifts=MOD_SHIFTS, flags: int = _ilt.ILT_FLAG_GWINDOW_ADJOINT):
+                 shifts=MOD_SHIFTS, flags: int = _ilt.ILT_FLAG_GWINDOW_ADJOINT, clips=None):
     """(x, t) or, for a net with the modulation head, (x, t, t_m, dh): device
     float32 [n, H, W] network inputs and targets, and the chosen shift per
     clip (numpy int array).  flags: the solves' context flags (by default
-    the G-window adjoint, the fastest exact form of the loop)."""
+    the G-window adjoint, the fastest exact form of the loop).  clips: an
+    optional iterable yielding the targets of seeds seed0, seed0 + 1, ... in
+    order (e.g. from a process pool); drawn here otherwise."""
     import torch
     _, H, w, prm = workload_inputs("c1", 0)
     N = 2048
@@ -62,7 +70,7 @@ def make_dataset(n_clips: int, seed0: int, net: "_dsn.Net", precision: int = _il
     best = torch.empty((1, N, N), dtype=torch.float32, device="cuda")
     t0 = time.perf_counter()
     for i in range(n_clips):
-        Z = gen_clip(C1_CLIP, seed0 + i)
+        Z = next(clips) if clips is not None else gen_clip(C1_CLIP, seed0 + i)
         tgt[0].copy_(torch.as_tensor(Z))
         mod.fill_(1.0)
         ctx.ilt_solve(tgt[0], work, p, mod=mod)

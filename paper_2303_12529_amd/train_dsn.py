@@ -80,7 +80,17 @@ def main():
     ap.add_argument("--out", required=True)
     ap.add_argument("--speed-only", action="store_true")
     ap.add_argument("--modulation", action="store_true")
+    ap.add_argument("--workers", type=int, default=0,
+                    help="processes drawing the training clips while the device solves (0: draw in line)")
     args = ap.parse_args()
+
+    # the clip-drawing workers start before this process touches the device
+    pool = None
+    if args.workers > 0 and not args.speed_only:
+        import multiprocessing
+        from .develset import clip_of_seed
+        pool = multiprocessing.get_context("spawn").Pool(args.workers)
+        clip_iter = pool.imap(clip_of_seed, range(100000, 100000 + args.clips), chunksize=4)
 
     import torch
     from . import develset
@@ -103,7 +113,10 @@ def main():
         return
     net.set_params(init)
     t0 = time.perf_counter()
-    data = develset.make_dataset(args.clips, 100000, net, log=log)
+    data = develset.make_dataset(args.clips, 100000, net, log=log, clips=clip_iter if pool else None)
+    if pool:
+        pool.close()
+        pool.join()
     x, t = data[0], data[1]
     tm = data[2] if args.modulation else None
     report["dataset"] = {"clips": args.clips, "seconds": round(time.perf_counter() - t0, 1)}
