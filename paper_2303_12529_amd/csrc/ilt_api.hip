@@ -305,7 +305,7 @@ extern "C" int ilt_create(ilt_ctx **out, const ilt_optics *o, int max_batch, voi
     ALLOC(H, H.size());
     ALLOC(coef, coef.size());
     ALLOC(sw, sw.size());
-    ALLOC(Spart, (size_t)(Np / 16) * 4 * (c->gwin ? c->Q * c->Q : P * P));
+    ALLOC(Spart, (size_t)(Np / 16) * 4 * (c->gwin ? (size_t)c->Q * c->Q * ns : (size_t)P * P));
     const bool b3 = o->precision == ILT_BF16X3;
     if (!b3 && !c->gwin && !(o->flags & ILT_FLAG_RECOMPUTE_FIELDS))
         ALLOC(Est, (size_t)ns * K * (Np / 16) * (Np / 16) * 512);

@@ -82,7 +82,7 @@ struct ilt_ctx {
     double2 *Vpart;    // [n_sets][K][P][P]
 
     // workspaces
-    float2 *Spart;     // spectrum band partials [Np/16][column ranges][P][P] (or [Q][Q])
+    float2 *Spart;     // spectrum band partials [Np/16][column ranges][P][P] (G-window: [set][Np/16][ranges][Q][Q])
     float2 *S;         // [P][P]
     float *Est;        // stored fields [n_sets][K][Np/16][Np/16][2][64][4] (null: recompute)
     float *Y;          // [n_sets][K][KP][Np]

@@ -44,10 +44,13 @@ __device__ __forceinline__ float wave_max(float v) {
 // (x = 4(l/16) + e) order, so the sum is unchanged.
 // --------------------------------------------------------------------------
 template <int FB, int MIX>
-__global__ __launch_bounds__(512) void k_spectrum_band(const float *__restrict__ src, int src_is_phi,
-                                                       const float *__restrict__ tb, const float *__restrict__ ar,
-                                                       const float *__restrict__ ai, int P, int N,
-                                                       int Np, float2 *__restrict__ Spart) {
+__global__ __launch_bounds__(512) void k_spectrum_band(const float *__restrict__ src, size_t src_stride,
+                                                       int src_is_phi, const float *__restrict__ tb,
+                                                       const float *__restrict__ ar, const float *__restrict__ ai,
+                                                       int P, int N, int Np, float2 *__restrict__ Spart) {
+    // grid.z: independent images src + z src_stride, partials in their own range
+    src += blockIdx.z * src_stride;
+    Spart += (size_t)blockIdx.z * gridDim.x * gridDim.y * P * P;
     constexpr int NZ = 32 * FB + 16 * MIX;
     constexpr int NB = NZ / 16;
     constexpr int PW = (NZ + 1) / 2 + 8;          // >= the window side of this layout
@@ -150,9 +153,12 @@ __global__ __launch_bounds__(512) void k_spectrum_band(const float *__restrict__
 
 // Deterministic sum of n complex partial arrays: out[e] = sum_p part[p][e].
 // Block = 16 outputs x 64 partial groups; groups combined in a fixed order.
+// grid.y: independent sums (part + y nparts n -> out + y n).
 template <typename T2>
 __global__ __launch_bounds__(1024) void k_psum(const T2 *__restrict__ part, int nparts, int n,
                                                float2 *__restrict__ out) {
+    part += (size_t)blockIdx.y * nparts * n;
+    out += (size_t)blockIdx.y * n;
     __shared__ double sr[64][17], si[64][17];
     const int o = threadIdx.x & 15, g = threadIdx.x >> 4;
     const int e = blockIdx.x * 16 + o;
@@ -802,12 +808,13 @@ __global__ __launch_bounds__(256) void k_gwindow_V(const float2 *__restrict__ H,
 // Pruned spectrum of src (or of [src <= 0]) on a window of side Pw with the
 // given column tables, summed into out [Pw][Pw].
 static hipError_t spectrum_to(ilt_ctx *c, const float *src, int src_is_phi, int FBw, int MIXw, const float *tbw,
-                              const float *arw, const float *aiw, int Pw, float2 *out) {
+                              const float *arw, const float *aiw, int Pw, float2 *out, int nimg = 1,
+                              size_t src_stride = 0) {
     const int nband = c->Np / 16;
     const int xs = spectrum_xsplit(c);
-#define SPEC(FB_, MIX_)                                                                                         \
-    k_spectrum_band<FB_, MIX_><<<dim3(nband, xs), 512, 0, c->stream>>>(src, src_is_phi, tbw, arw, aiw, Pw, c->N, \
-                                                                      c->Np, c->Spart)
+#define SPEC(FB_, MIX_)                                                                                    \
+    k_spectrum_band<FB_, MIX_><<<dim3(nband, xs, nimg), 512, 0, c->stream>>>(src, src_stride, src_is_phi, tbw, \
+                                                                            arw, aiw, Pw, c->N, c->Np, c->Spart)
     if (FBw == 0 && MIXw == 1) SPEC(0, 1);
     else if (FBw == 1 && MIXw == 0) SPEC(1, 0);
     else if (FBw == 1 && MIXw == 1) SPEC(1, 1);
@@ -822,7 +829,7 @@ static hipError_t spectrum_to(ilt_ctx *c, const float *src, int src_is_phi, int 
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int n = Pw * Pw;
-    k_psum<float2><<<(n + 15) / 16, 1024, 0, c->stream>>>(c->Spart, nband * xs, n, out);
+    k_psum<float2><<<dim3((n + 15) / 16, nimg), 1024, 0, c->stream>>>(c->Spart, nband * xs, n, out);
     return hipGetLastError();
 }
 
@@ -936,9 +943,10 @@ hipError_t launch_gradient(ilt_ctx *c, float *g_out, double *maxpart) {
 hipError_t launch_adjoint_gwindow(ilt_ctx *c, const float *G, size_t g_set_stride, int set_lo, int set_hi) {
     if (!c->gwin) return hipErrorInvalidValue;
     const int Q = c->Q;
-    for (int s = set_lo; s < set_hi; ++s) {
-        hipError_t e = spectrum_to(c, G + (size_t)s * g_set_stride, 0, c->FBQ, c->MIXQ, c->tbQ, c->arQ, c->aiQ, Q,
-                                   c->Ghat + (size_t)s * Q * Q);
+    // the spectra of every set's G in one launch (one pass over the tables)
+    {
+        hipError_t e = spectrum_to(c, G + (size_t)set_lo * g_set_stride, 0, c->FBQ, c->MIXQ, c->tbQ, c->arQ, c->aiQ,
+                                   Q, c->Ghat + (size_t)set_lo * Q * Q, set_hi - set_lo, g_set_stride);
         if (e != hipSuccess) return e;
     }
     const int n = c->P * c->P;
