@@ -100,7 +100,7 @@ void free_ctx(ilt_ctx *c) {
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     void *ptrs[] = {c->tl, c->tb, c->ta4, c->ar, c->ai, c->H, c->sw, c->coef, c->tlhl, c->tbhl, c->Yhl, c->Spart, c->S, c->Est, c->Y, c->Tg,
                     c->I, c->G, c->g, c->phi2, c->Wpart, c->W, c->edtg, c->colbits, c->part, c->scal,
-                    c->tbQ, c->arQ, c->aiQ, c->Ghat, c->Vpart, c->g_prev, c->dcg};
+                    c->tbQ, c->arQ, c->aiQ, c->Ghat, c->Ugw, c->Vpart, c->g_prev, c->dcg};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     delete c;
@@ -333,7 +333,18 @@ extern "C" int ilt_create(ilt_ctx **out, const ilt_optics *o, int max_batch, voi
         ALLOC(arQ, arQ.size());
         ALLOC(aiQ, aiQ.size());
         ALLOC(Ghat, (size_t)ns * Q * Q);
-        ALLOC(Vpart, (size_t)ns * K * P * P);
+        // the correlation GEMM: at most two 4-wave blocks per compute unit
+        int ncu = 256;
+        if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device) != hipSuccess || ncu < 1)
+            ncu = 256;
+        // and at least enough ranges that one range's rows of U fit in LDS
+        // beside Ghat
+        const int Fpad = (P * P + 3) / 4 * 4, per_group = (gwin_ftiles(P) + 3) / 4 * ns, nchunk = Fpad / 4;
+        const int cap = (GWIN_LDS_FLOATS - 2 * Q * Q) / (4 * 16 * gwin_ntiles(K));
+        c->gw_groups = std::max(1, std::min(nchunk, 2 * ncu / per_group));
+        c->gw_groups = std::max(c->gw_groups, (nchunk + cap - 1) / cap);
+        ALLOC(Ugw, (size_t)ns * Fpad * 16 * gwin_ntiles(K));
+        ALLOC(Vpart, (size_t)c->gw_groups * ns * P * P);
     }
     if (b3) {
         ALLOC(tlhl, (size_t)2 * Np * 2 * KP);

@@ -79,7 +79,9 @@ struct ilt_ctx {
     float *tbQ;        // [Np][NZQ] window columns of the difference window
     float *arQ, *aiQ;  // [Q][Np]
     float2 *Ghat;      // [n_sets][Q][Q]
-    double2 *Vpart;    // [n_sets][K][P][P]
+    float *Ugw;        // [n_sets][Fpad][NC] U_k = H_k . S as real columns (Fpad = P^2 rounded up to 4, NC = 2K rounded up to 16)
+    double2 *Vpart;    // [gw_groups][n_sets][P][P] partial sums of W over ranges of window rows
+    int gw_groups;     // ranges the window sum is split into (grid.y of the correlation GEMM)
 
     // workspaces
     float2 *Spart;     // spectrum band partials [Np/16][column ranges][P][P] (G-window: [set][Np/16][ranges][Q][Q])
@@ -166,6 +168,13 @@ int adjoint_b3_max_parts(const ilt_ctx *c, int nsets);
 #define ILT_ST_MAX_XSPLIT 2
 // by size: split the columns in two when the row tiles x kernel groups x sets
 // would leave compute units without a block
+// G-window correlation GEMM: column tiles of 16 over [Re U | Im U] and row
+// tiles of 16 over the window frequencies.
+inline int gwin_ntiles(int K) { return (2 * K + 15) / 16; }
+// LDS of one correlation block (floats): Ghat, then the block's rows of U
+#define GWIN_LDS_FLOATS 16384
+inline int gwin_ftiles(int P) { return (P * P + 15) / 16; }
+
 inline int adjoint_st_xsplit(const ilt_ctx *c) {
     if (c->st_xsplit > 0) return c->st_xsplit;
     return ((c->N + 31) / 32) * ((c->K + 3) / 4) * c->n_sets < 256 ? 2 : 1;

@@ -754,51 +754,170 @@ __global__ __launch_bounds__(256, 2) void k_adjoint_rc(const float *__restrict__
 // G-window adjoint (exact): with U_k = H_k . S on the window and Ghat the
 // DFT of G at the difference frequencies D in [-(P-1), P-1]^2,
 //   V_k(f') = sum_f U_k(f) Ghat(f' - f),
-//   Vpart[set][k][f'] = (w_k / N^4) conj(H_k(f')) V_k(f')      (FP64),
-// and W = sum over (set, k) of Vpart (fixed order).  Thread = (f', k, set).
+//   W = sum over (set, k) of (w_k / N^4) conj(H_k(f')) V_k(f').
+// All kernels of a set share Ghat, so the correlation is one GEMM per set,
+// V[f'][k] = sum_f T[f'][f] U[f][k], with the Toeplitz-block-Toeplitz
+// T[f'][f] = Ghat(a' - a, b' - b) read from Ghat in LDS, on the FP32 matrix
+// cores (the precision of the field adjoint); partial sums over ranges of f,
+// the weighting by conj(H_k) and the sums over k and sets are FP64.  U holds
+// real and imaginary parts as separate columns, so the complex product is
+// two real products per operand pair.
 // --------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_gwindow_V(const float2 *__restrict__ H, const float2 *__restrict__ S,
-                                                   const float2 *__restrict__ Ghat, const float *__restrict__ sw,
-                                                   int P, int K, int set_lo, double2 *__restrict__ Vpart) {
-    constexpr int QM = 2 * ILT_MAX_P - 1;
-    __shared__ double2 U[ILT_MAX_P * ILT_MAX_P];
-    __shared__ float2 Gs[QM * QM];
-    __shared__ double2 part[4][64];
-    const int k = blockIdx.y, srel = blockIdx.z, s = set_lo + srel;
-    const int Q = 2 * P - 1;
-    const float2 *Hk = H + ((size_t)s * K + k) * P * P;
-    for (int e = threadIdx.x; e < P * P; e += 256) {
-        const double hr = Hk[e].x, hi = Hk[e].y, sr = S[e].x, si = S[e].y;
-        U[e] = make_double2(hr * sr - hi * si, hr * si + hi * sr);
+
+// U operand: row f of the window (row-major, zero rows up to Fpad, a
+// multiple of 4), columns [Re U_0 .. Re U_{K-1} | Im U_0 .. Im U_{K-1} | 0]
+// (NC = 2K rounded up to 16).
+__global__ __launch_bounds__(256) void k_gwindow_U(const float2 *__restrict__ H, const float2 *__restrict__ S, int P,
+                                                   int K, int NC, int Fpad, int set_lo, float *__restrict__ U) {
+    const int srel = blockIdx.y, s = set_lo + srel;
+    const int id = blockIdx.x * 256 + threadIdx.x;
+    if (id >= Fpad * NC) return;
+    const int f = id / NC, col = id - (id / NC) * NC;
+    double v = 0.0;
+    if (f < P * P && col < 2 * K) {
+        const int k = col < K ? col : col - K;
+        const float2 h = H[((size_t)s * K + k) * P * P + f], sv = S[f];
+        v = col < K ? (double)h.x * sv.x - (double)h.y * sv.y : (double)h.x * sv.y + (double)h.y * sv.x;
     }
-    const float2 *G = Ghat + (size_t)s * Q * Q;
-    for (int e = threadIdx.x; e < Q * Q; e += 256) Gs[e] = G[e];
+    U[(size_t)srel * Fpad * NC + id] = (float)v;
+}
+
+// Block-wide copy global -> LDS with UNR independent loads in flight per
+// thread (a plain copy loop waits for each load before the next).
+template <int UNR, typename T>
+__device__ __forceinline__ void stage_to_lds(T *dst, const T *__restrict__ src, int n) {
+    for (int base = 0; base < n; base += 256 * UNR) {
+        T v[UNR];
+#pragma unroll
+        for (int u = 0; u < UNR; ++u) {
+            const int e = base + u * 256 + (int)threadIdx.x;
+            if (e < n) v[u] = src[e];
+        }
+#pragma unroll
+        for (int u = 0; u < UNR; ++u) {
+            const int e = base + u * 256 + (int)threadIdx.x;
+            if (e < n) dst[e] = v[u];
+        }
+    }
+}
+
+// Block: 4 waves, wave w = a 16-row tile of f' (v_mfma_f32_16x16x4: lane l
+// holds A[l%16][l/16], B[l/16][l%16] and C[4(l/16) + i][l%16] in item i).
+// grid.y splits the sum over f into ranges of 4-row chunks whose rows of U
+// are staged in LDS after Ghat (the host sizes the ranges to fit), grid.z =
+// set.  Epilogue: V_re = T_re U_re - T_im U_im, V_im = T_re U_im + T_im U_re,
+// times (w_k / N^4) conj(H_k(f')), summed over k in a fixed order ->
+// Wpart[range][set][f'].
+template <int NT>
+__global__ __launch_bounds__(256) void k_gwindow_mm(const float2 *__restrict__ Ghat, const float *__restrict__ U,
+                                                    const float2 *__restrict__ H, const float *__restrict__ sw, int P,
+                                                    int K, int Fpad, int set_lo, double2 *__restrict__ Wpart) {
+    constexpr int NC = 16 * NT;
+    constexpr int SMEM = GWIN_LDS_FLOATS;                   // 64 KB
+    constexpr int WPR = (SMEM / (32 * NC)) < 4 ? SMEM / (32 * NC) : 4;   // epilogue waves per round
+    static_assert(2 * (2 * ILT_MAX_P - 1) * (2 * ILT_MAX_P - 1) + 4 * 16 * 8 <= SMEM,
+                  "Ghat and one chunk of U do not fit");
+    static_assert(WPR >= 1, "epilogue tile does not fit");
+    __shared__ float smem[SMEM];
+    const int srel = blockIdx.z, s = set_lo + srel, Q = 2 * P - 1, PP = P * P;
+    float2 *Gs = reinterpret_cast<float2 *>(smem);
+    stage_to_lds<10>(Gs, Ghat + (size_t)s * Q * Q, Q * Q);
+    const int nchunk = Fpad / 4, per = (nchunk + gridDim.y - 1) / gridDim.y;
+    const int t0 = blockIdx.y * per, t1 = min(nchunk, t0 + per);
+    float *Us = smem + 2 * Q * Q;
+    stage_to_lds<12>(Us, U + ((size_t)srel * Fpad + 4 * t0) * NC, (t1 > t0 ? t1 - t0 : 0) * 4 * NC);
     __syncthreads();
-    // thread = (output f' of the block's 64, quarter q of the rows a)
-    const int o = threadIdx.x & 63, q = threadIdx.x >> 6;
-    const int fp = blockIdx.x * 64 + o;
-    double vr = 0.0, vi = 0.0;
-    if (fp < P * P) {
-        const int a2 = fp / P, b2 = fp % P;
-        for (int a = q; a < P; a += 4) {
-            const float2 *grow = Gs + (a2 - a + P - 1) * Q + (b2 + P - 1);
-            const double2 *urow = U + a * P;
-            for (int b = 0; b < P; ++b) {
-                const double2 u = urow[b];
-                const float2 g = grow[-b];
-                vr += u.x * g.x - u.y * g.y;
-                vi += u.x * g.y + u.y * g.x;
+
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int r = lane & 15, kq = lane >> 4;
+    const int m0 = (blockIdx.x * 4 + w) * 16;
+    const int fp = m0 + r;
+    const bool fp_ok = fp < PP;
+    const int a2 = fp_ok ? fp / P : 0, b2 = fp_ok ? fp - (fp / P) * P : 0;
+
+    // the epilogue's conj(H_k(f')) and weights, fetched before the main loop
+    // (lane: row rr of the tile, kernels k = q, q + 4, ...; K <= 8 NT)
+    const int rr = lane >> 2, q = lane & 3, fo = m0 + rr;
+    float2 hv[2 * NT];
+    float sv[2 * NT];
+#pragma unroll
+    for (int u = 0; u < 2 * NT; ++u) {
+        const int k = q + 4 * u;
+        hv[u] = make_float2(0.f, 0.f);
+        sv[u] = 0.f;
+        if (fo < PP && k < K) {
+            hv[u] = H[((size_t)s * K + k) * PP + fo];
+            sv[u] = sw[(size_t)s * K + k];
+        }
+    }
+
+    f4 pre[NT], pim[NT];
+#pragma unroll
+    for (int j = 0; j < NT; ++j) pre[j] = pim[j] = f4{0.f, 0.f, 0.f, 0.f};
+    if (m0 < PP && t0 < t1) {                               // wave-uniform
+        int f = 4 * t0 + kq, a = f / P, b = f - (f / P) * P;
+        const float *urow = Us + kq * NC + r;
+#pragma unroll 2
+        for (int t = t0; t < t1; ++t) {
+            float2 g = make_float2(0.f, 0.f);
+            if (fp_ok && f < PP) g = Gs[(a2 - a + P - 1) * Q + (b2 - b + P - 1)];
+            float bv[NT];
+#pragma unroll
+            for (int j = 0; j < NT; ++j) bv[j] = urow[16 * j];
+#pragma unroll
+            for (int j = 0; j < NT; ++j) {
+                pre[j] = mfma4(g.x, bv[j], pre[j]);
+                pim[j] = mfma4(g.y, bv[j], pim[j]);
+            }
+            f += 4;
+            urow += 4 * NC;
+            b += 4;
+            while (b >= P) {
+                b -= P;
+                ++a;
             }
         }
     }
-    part[q][o] = make_double2(vr, vi);
-    __syncthreads();
-    if (q != 0 || fp >= P * P) return;
-    vr = ((part[0][o].x + part[1][o].x) + part[2][o].x) + part[3][o].x;
-    vi = ((part[0][o].y + part[1][o].y) + part[2][o].y) + part[3][o].y;
-    const double sc = (double)sw[(size_t)s * K + k] * (double)sw[(size_t)s * K + k];
-    const double hr = Hk[fp].x, hi = -(double)Hk[fp].y;    // conj(H_k(f'))
-    Vpart[(((size_t)srel * K + k) * P * P) + fp] = make_double2(sc * (hr * vr - hi * vi), sc * (hr * vi + hi * vr));
+    __syncthreads();                                        // LDS free again
+
+    // epilogue in rounds of WPR waves: E[row][col][re-part, im-part]
+    for (int w0 = 0; w0 < 4; w0 += WPR) {
+        float *E = smem + (size_t)(w - w0) * 32 * NC;
+        const bool mine = w >= w0 && w < w0 + WPR;
+        if (mine) {
+#pragma unroll
+            for (int j = 0; j < NT; ++j) {
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    *reinterpret_cast<float2 *>(E + ((4 * kq + i) * NC + 16 * j + r) * 2) = make_float2(pre[j][i], pim[j][i]);
+            }
+        }
+        __syncthreads();
+        if (mine) {
+            double wr = 0.0, wi = 0.0;
+            if (fo < PP) {
+                const float *er = E + rr * NC * 2;
+#pragma unroll
+                for (int u = 0; u < 2 * NT; ++u) {
+                    const int k = q + 4 * u;
+                    if (k < K) {
+                        const double vre = (double)er[2 * k] - (double)er[2 * (K + k) + 1];
+                        const double vim = (double)er[2 * (K + k)] + (double)er[2 * k + 1];
+                        const double sc = (double)sv[u] * (double)sv[u];
+                        wr += sc * ((double)hv[u].x * vre + (double)hv[u].y * vim);
+                        wi += sc * ((double)hv[u].x * vim - (double)hv[u].y * vre);
+                    }
+                }
+            }
+            wr += __shfl_xor(wr, 1, 64);
+            wi += __shfl_xor(wi, 1, 64);
+            wr += __shfl_xor(wr, 2, 64);
+            wi += __shfl_xor(wi, 2, 64);
+            if (q == 0 && fo < PP)
+                Wpart[((size_t)blockIdx.y * gridDim.z + srel) * PP + fo] = make_double2(wr, wi);
+        }
+        __syncthreads();
+    }
 }
 
 }  // namespace
@@ -949,11 +1068,24 @@ hipError_t launch_adjoint_gwindow(ilt_ctx *c, const float *G, size_t g_set_strid
                                    Q, c->Ghat + (size_t)set_lo * Q * Q, set_hi - set_lo, g_set_stride);
         if (e != hipSuccess) return e;
     }
-    const int n = c->P * c->P;
-    dim3 grid((n + 63) / 64, c->K, set_hi - set_lo);
-    k_gwindow_V<<<grid, 256, 0, c->stream>>>(c->H, c->S, c->Ghat, c->sw, c->P, c->K, set_lo, c->Vpart);
+    const int n = c->P * c->P, ns = set_hi - set_lo, NT = gwin_ntiles(c->K), NC = 16 * NT;
+    const int Fpad = (n + 3) / 4 * 4;
+    k_gwindow_U<<<dim3((Fpad * NC + 255) / 256, ns), 256, 0, c->stream>>>(c->H, c->S, c->P, c->K, NC, Fpad, set_lo,
+                                                                         c->Ugw);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    k_psum<double2><<<(n + 15) / 16, 1024, 0, c->stream>>>(c->Vpart, (set_hi - set_lo) * c->K, n, c->W);
+    const dim3 grid((gwin_ftiles(c->P) + 3) / 4, c->gw_groups, ns);
+    switch (NT) {
+#define GWMM(NT_)                                                                                              \
+    case NT_:                                                                                                  \
+        k_gwindow_mm<NT_><<<grid, 256, 0, c->stream>>>(c->Ghat, c->Ugw, c->H, c->sw, c->P, c->K, Fpad, set_lo, \
+                                                      c->Vpart);                                               \
+        break;
+        GWMM(1) GWMM(2) GWMM(3) GWMM(4) GWMM(5) GWMM(6) GWMM(7) GWMM(8)
+#undef GWMM
+    default: return hipErrorInvalidValue;
+    }
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    k_psum<double2><<<(n + 15) / 16, 1024, 0, c->stream>>>(c->Vpart, c->gw_groups * ns, n, c->W);
     return hipGetLastError();
 }
