@@ -161,20 +161,25 @@ hipError_t launch_adjoint_gwindow(ilt_ctx *c, const float *G, size_t g_set_strid
 // block maxima of |d| into maxpart for the CFL step; returns that block count
 int launch_cg(ilt_ctx *c, int first, double *part, double *maxpart, hipError_t *err);
 int adjoint_b3_parts(const ilt_ctx *c, int nsets);
-// column ranges of the spectrum kernel: each wave's share stays a multiple of 16
-inline int spectrum_xsplit(const ilt_ctx *c) { return c->Np >= 512 ? 4 : c->Np / 128; }
+// column ranges per 16-row band of the spectrum (each wave's share, Np / (8
+// ranges), stays a multiple of 16): every range writes a whole window partial
+// that is summed afterwards, so fewer ranges once the launch has enough blocks
+// (several images fill the device with one range)
+inline int spectrum_xsplit(const ilt_ctx *c, int nimg) {
+    if (c->Np < 512) return c->Np / 128;
+    return nimg >= 2 ? 1 : 2;
+}
 int adjoint_b3_max_parts(const ilt_ctx *c, int nsets);
 #define ILT_B3_MAX_XSPLIT 4
 #define ILT_ST_MAX_XSPLIT 2
-// by size: split the columns in two when the row tiles x kernel groups x sets
-// would leave compute units without a block
 // G-window correlation GEMM: column tiles of 16 over [Re U | Im U] and row
 // tiles of 16 over the window frequencies.
 inline int gwin_ntiles(int K) { return (2 * K + 15) / 16; }
+inline int gwin_ftiles(int P) { return (P * P + 15) / 16; }
 // LDS of one correlation block (floats): Ghat, then the block's rows of U
 #define GWIN_LDS_FLOATS 16384
-inline int gwin_ftiles(int P) { return (P * P + 15) / 16; }
-
+// by size: split the columns in two when the row tiles x kernel groups x sets
+// would leave compute units without a block
 inline int adjoint_st_xsplit(const ilt_ctx *c) {
     if (c->st_xsplit > 0) return c->st_xsplit;
     return ((c->N + 31) / 32) * ((c->K + 3) / 4) * c->n_sets < 256 ? 2 : 1;

@@ -930,7 +930,7 @@ static hipError_t spectrum_to(ilt_ctx *c, const float *src, int src_is_phi, int 
                               const float *arw, const float *aiw, int Pw, float2 *out, int nimg = 1,
                               size_t src_stride = 0) {
     const int nband = c->Np / 16;
-    const int xs = spectrum_xsplit(c);
+    const int xs = spectrum_xsplit(c, nimg);
 #define SPEC(FB_, MIX_)                                                                                    \
     k_spectrum_band<FB_, MIX_><<<dim3(nband, xs, nimg), 512, 0, c->stream>>>(src, src_stride, src_is_phi, tbw, \
                                                                             arw, aiw, Pw, c->N, c->Np, c->Spart)
