@@ -139,6 +139,28 @@ def test_litho_adjoint_parity(ilt, N, P, K, flags):
     assert err <= (2e-2 if flags == "bf16x3" else 1e-4)
 
 
+
+# the G-window correlation GEMM holds 2K real columns in tiles of 16: these
+# cover every tile count beyond the K <= 24 cases above (2K up to 128), with
+# two kernel sets so that the second set's kernels and Ghat are indexed too
+GW_WIDE = [(96, 9, 25), (96, 9, 40), (128, 15, 48), (96, 7, 57), (128, 35, 64)]
+
+
+@pytest.mark.parametrize("N,P,K", GW_WIDE)
+def test_gwindow_adjoint_many_kernels(ilt, N, P, K):
+    _say("gwindow adjoint", N, P, K)
+    H, w = _rand_kernels(2, K, P, seed=K + 7)
+    rng = np.random.default_rng(K)
+    M = random_mask(N, 0.3, seed=K).astype(np.float32)
+    G = rng.normal(size=(N, N)).astype(np.float32)
+    ctx = ilt.Context(H, w, N, flags=ilt.ILT_FLAG_GWINDOW_ADJOINT)
+    for s in range(2):
+        out = ctx.litho_adjoint(_dev(M), _dev(G), s).cpu().numpy()
+        ref = o_litho.litho_adjoint(M.astype(np.float64), G.astype(np.float64), H[s], w[s])
+        err = np.abs(out - ref).max() / np.abs(ref).max()
+        _say("  set", s, "rel err", err)
+        assert err <= 1e-4
+
 def test_resist_loss_parity(ilt):
     N = 256
     H, w = _rand_kernels(2, 2, 5, seed=1)
