@@ -7,7 +7,8 @@ aerial images I_s and the whole-objective gradient g = sum_s dL/dM through
 its own chain (image -> resist -> G_s -> adjoint).  Errors are normwise:
 max|x - x_ref| / max|x_ref| per quantity, against (a) the plain FP32 form and
 (b) the oracle.  One JSON line per step is written to
-$ILT_REPORT_DIR/precision_report.jsonl when that directory exists.
+$ILT_REPORT_DIR/precision_report.jsonl (default: the system temporary
+directory) when that directory exists.
 
 Bars (BF16x3 vs the oracle): I <= 1e-3, g <= 2e-2; FP32: I <= 1e-5, g <= 1e-3.
 End state: both forms run the full loop from TSDF(target); the BF16x3 final
@@ -17,6 +18,7 @@ nominal print) within 0.5 nm of plain.
 import json
 import os
 import sys
+import tempfile
 
 import numpy as np
 import pytest
@@ -74,7 +76,7 @@ def test_precision_report_along_trajectory(ilt):
     plain = ilt.Context(H, w, N, precision=ilt.ILT_FP32)
     b3 = ilt.Context(H, w, N, precision=ilt.ILT_BF16X3)
     params = ilt.Params.from_dict(prm)
-    out_dir = os.environ.get("ILT_REPORT_DIR", "gpurun_out")
+    out_dir = os.environ.get("ILT_REPORT_DIR", tempfile.gettempdir())
     rows = []
     for i in STEPS:
         phi = torch.empty((N, N), dtype=torch.float32, device="cuda")
@@ -128,7 +130,7 @@ def test_final_l2_pvb_epe_match_plain(ilt):
     _say(json.dumps(out))
     assert abs(out["bf16x3"]["l2"] - out["fp32"]["l2"]) <= 0.01 * out["fp32"]["l2"]
     assert abs(out["bf16x3"]["mean_abs_nm"] - out["fp32"]["mean_abs_nm"]) <= 0.5
-    out_dir = os.environ.get("ILT_REPORT_DIR", "gpurun_out")
+    out_dir = os.environ.get("ILT_REPORT_DIR", tempfile.gettempdir())
     if os.path.isdir(out_dir):
         with open(os.path.join(out_dir, "precision_report.jsonl"), "a") as f:
             f.write(json.dumps({"final": out}) + "\n")
