@@ -201,15 +201,29 @@ __global__ __launch_bounds__(256) void k_window_rows(const float2 *__restrict__ 
     const int x = blockIdx.x * COLS + (threadIdx.x % COLS);
     const int ag = threadIdx.x / COLS;
     const int jn = min(JB, nj - j0);
-    for (int jj = 0; jj < jn; ++jj)
-        for (int e = threadIdx.x; e < P * P; e += 256) {
-            float2 u = S[e];
-            if (H) {
-                const float2 h = H[((size_t)s * nj + j0 + jj) * P * P + e];
-                u = make_float2(h.x * u.x - h.y * u.y, h.x * u.y + h.y * u.x);
+    // U_j = H_j . S (or S itself): a thread's loads are issued before any
+    // product is stored
+    constexpr int UPT = (ILT_MAX_P * ILT_MAX_P + 255) / 256;
+    for (int jj = 0; jj < jn; ++jj) {
+        float2 sv[UPT], hv[UPT];
+#pragma unroll
+        for (int u = 0; u < UPT; ++u) {
+            const int e = threadIdx.x + 256 * u;
+            if (e < P * P) {
+                sv[u] = S[e];
+                if (H) hv[u] = H[((size_t)s * nj + j0 + jj) * P * P + e];
             }
-            U[jj][e] = u;
         }
+#pragma unroll
+        for (int u = 0; u < UPT; ++u) {
+            const int e = threadIdx.x + 256 * u;
+            if (e < P * P) {
+                float2 v = sv[u];
+                if (H) v = make_float2(hv[u].x * v.x - hv[u].y * v.y, hv[u].x * v.y + hv[u].y * v.x);
+                U[jj][e] = v;
+            }
+        }
+    }
     float cr[ILT_MAX_P], ci[ILT_MAX_P];
 #pragma unroll
     for (int b = 0; b < ILT_MAX_P; ++b) {

@@ -334,11 +334,24 @@ __global__ __launch_bounds__(256) void k_levelset(const float *__restrict__ phi,
         vv[j] = ok ? vel[p] : 0.f;
         mv[j] = (ok && mod) ? mod[p] : 1.f;
     }
-    for (int e = threadIdx.x; e < 34 * 34; e += 256) {
-        const int yy = e / 34, xx = e % 34;
-        const int gy = min(max(by + yy - 1, 0), N - 1);
-        const int gx = min(max(bx + xx - 1, 0), N - 1);
-        t[yy][xx] = phi[(size_t)gy * N + gx];
+    // the tile with its 1-pixel halo (clamped at the image edge): all of a
+    // thread's loads are issued before any is stored
+    constexpr int TE = 34 * 34, TU = (TE + 255) / 256;
+    float tv[TU];
+#pragma unroll
+    for (int u = 0; u < TU; ++u) {
+        const int e = threadIdx.x + 256 * u;
+        if (e < TE) {
+            const int yy = e / 34, xx = e - (e / 34) * 34;
+            const int gy = min(max(by + yy - 1, 0), N - 1);
+            const int gx = min(max(bx + xx - 1, 0), N - 1);
+            tv[u] = phi[(size_t)gy * N + gx];
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < TU; ++u) {
+        const int e = threadIdx.x + 256 * u;
+        if (e < TE) t[e / 34][e - (e / 34) * 34] = tv[u];
     }
     __syncthreads();
     const float dt = (float)scal[SC_DT];
