@@ -871,7 +871,6 @@ __global__ __launch_bounds__(256) void k_gwindow_mm(const float2 *__restrict__ G
     if (m0 < PP && t0 < t1) {                               // wave-uniform
         int f = 4 * t0 + kq, a = f / P, b = f - (f / P) * P;
         const float *urow = Us + kq * NC + r;
-#pragma unroll 2
         for (int t = t0; t < t1; ++t) {
             float2 g = make_float2(0.f, 0.f);
             if (fp_ok && f < PP) g = Gs[(a2 - a + P - 1) * Q + (b2 - b + P - 1)];

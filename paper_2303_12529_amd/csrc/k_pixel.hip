@@ -24,6 +24,28 @@ __device__ __forceinline__ double block_sum(double v, double *sh) {
     return r;
 }
 
+// Per-thread sums over the partials b = threadIdx.x, +RB, ... (NQ values per
+// partial), with the loads of UNR partials in flight at a time; the additions
+// happen in the order of the plain strided loop, so the sums are the same.
+template <int NQ, int UNR>
+__device__ __forceinline__ void thread_partial_sums(const double *__restrict__ part, int nblk, double (&v)[NQ]) {
+    for (int b0 = threadIdx.x; b0 < nblk; b0 += RB * UNR) {
+        double t[UNR][NQ];
+#pragma unroll
+        for (int u = 0; u < UNR; ++u) {
+            const int b = b0 + RB * u;
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) t[u][q] = b < nblk ? part[(size_t)b * NQ + q] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < UNR; ++u)
+            if (b0 + RB * u < nblk) {
+#pragma unroll
+                for (int q = 0; q < NQ; ++q) v[q] += t[u][q];
+            }
+    }
+}
+
 __device__ __forceinline__ double block_max(double v, double *sh) {
     for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_down(v, o, 64));
     if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
@@ -201,8 +223,7 @@ __global__ __launch_bounds__(RB) void k_finish_resist(const double *__restrict__
                                                       double *__restrict__ scal, double *__restrict__ stats4) {
     __shared__ double sh[RB];
     double v[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int b = threadIdx.x; b < nblk; b += RB)
-        for (int q = 0; q < 4; ++q) v[q] += part[b * 4 + q];
+    thread_partial_sums<4, 8>(part, nblk, v);
     for (int q = 0; q < 4; ++q) v[q] = block_sum(v[q], sh);
     if (threadIdx.x == 0) {
         scal[SC_LOSS] = v[0];
@@ -290,8 +311,7 @@ __global__ __launch_bounds__(RB) void k_cg_beta(const double *__restrict__ part,
                                                 double *__restrict__ scal) {
     __shared__ double sh[RB];
     double v[3] = {0.0, 0.0, 0.0};
-    for (int b = threadIdx.x; b < nblk; b += RB)
-        for (int q = 0; q < 3; ++q) v[q] += part[3 * b + q];
+    thread_partial_sums<3, 8>(part, nblk, v);
     for (int q = 0; q < 3; ++q) v[q] = block_sum(v[q], sh);
     if (threadIdx.x == 0) scal[SC_BETA] = (first || !(v[2] > 0.0)) ? 0.0 : fmax(0.0, (v[0] - v[1]) / v[2]);
 }
@@ -323,8 +343,10 @@ __global__ __launch_bounds__(256) void k_levelset(const float *__restrict__ phi,
     __shared__ int wsum[4];
     const int bx = blockIdx.x * 32, by = blockIdx.y * 32;
     const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
-    // the velocity (and modulation) of this thread's pixels, requested before
-    // the tile so that both loads are in flight together
+    // the time step, and the velocity (and modulation) of this thread's
+    // pixels, requested before the tile so that all loads are in flight
+    // together
+    const float dt = (float)scal[SC_DT];
     float vv[4], mv[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
@@ -354,7 +376,6 @@ __global__ __launch_bounds__(256) void k_levelset(const float *__restrict__ phi,
         if (e < TE) t[e / 34][e - (e / 34) * 34] = tv[u];
     }
     __syncthreads();
-    const float dt = (float)scal[SC_DT];
     int flips = 0;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
@@ -393,9 +414,9 @@ __global__ __launch_bounds__(RB) void k_finish_step(const double *__restrict__ p
                                                     double *__restrict__ scal, double *__restrict__ stats4,
                                                     double *__restrict__ trace_row, int iter, double ns_per_tick) {
     __shared__ double sh[RB];
-    double f = 0.0;
-    for (int b = threadIdx.x; b < nblk; b += RB) f += part[b];
-    f = block_sum(f, sh);
+    double fs[1] = {0.0};
+    thread_partial_sums<1, 16>(part, nblk, fs);
+    const double f = block_sum(fs[0], sh);
     if (threadIdx.x == 0) {
         scal[SC_FLIPS] = f;
         if (stats4) {
