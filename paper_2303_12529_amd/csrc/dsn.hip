@@ -107,25 +107,28 @@ __global__ __launch_bounds__(256) void k_conv_first(const float *__restrict__ x,
 // --------------------------------------------------------------------------
 // 3x3 convolution, implicit GEMM on the BF16 matrix cores.
 //   out[pixel][co] = act(bias[co] + sum_{tap, ci} w[co][tap][ci] x[src(pixel, tap)][ci])
-// Block: 4 waves as WPX (pixels) x WCO (channels); wave tile 32 channels x
-// 32 pixels = 2 x 2 matrix blocks.  UP: x has half the resolution and is
-// read through a nearest 2x upsampling.  Requirements (checked on the host):
-// Cin % 32 == 0, Cout % (32 WCO) == 0, 16-byte aligned views.
+// Block: 4 waves as WPX (pixels) x WCO (channels); wave tile CB x PB matrix
+// blocks of 16 channels x 16 pixels: per 32-deep step a wave loads CB weight
+// and PB input fragments for CB x PB matrix-core steps.  Every output sums
+// taps, then input channels in steps of 32, in the same order for every tile
+// shape.  UP: x has half the resolution and is read through a nearest 2x
+// upsampling.  Requirements (checked on the host): Cin % 32 == 0,
+// Cout % (16 CB WCO) == 0, 16-byte aligned views.
 // --------------------------------------------------------------------------
-template <int WPX, int WCO, bool UP>
+template <int WPX, int WCO, int CB, int PB, bool UP>
 __global__ __launch_bounds__(256) void k_conv(View x, int B, int H, int W, const __bf16 *__restrict__ w,
                                               int Cin, const float *__restrict__ bias, int relu, View y) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int l16 = lane & 15, lq = lane >> 4;
     const int wp = wave % WPX, wc = wave / WPX;
     const long long npix = (long long)B * H * W;
-    const long long px0 = ((long long)blockIdx.x * WPX + wp) * 32;
-    const int co0 = (blockIdx.y * WCO + wc) * 32;
+    const long long px0 = ((long long)blockIdx.x * WPX + wp) * (16 * PB);
+    const int co0 = (blockIdx.y * WCO + wc) * (16 * CB);
     const int Hin = UP ? H / 2 : H, Win = UP ? W / 2 : W;
-    int pb_b[2], pb_y[2], pb_x[2];
-    bool pb_ok[2];
+    int pb_b[PB], pb_y[PB], pb_x[PB];
+    bool pb_ok[PB];
 #pragma unroll
-    for (int pb = 0; pb < 2; ++pb) {
+    for (int pb = 0; pb < PB; ++pb) {
         const long long pix = px0 + 16 * pb + l16;
         pb_ok[pb] = pix < npix;
         const long long pc = pb_ok[pb] ? pix : 0;
@@ -134,44 +137,44 @@ __global__ __launch_bounds__(256) void k_conv(View x, int B, int H, int W, const
         pb_y[pb] = (int)(r % H);
         pb_b[pb] = (int)(r / H);
     }
-    f4 acc[2][2];
+    f4 acc[CB][PB];
 #pragma unroll
-    for (int cb = 0; cb < 2; ++cb)
+    for (int cb = 0; cb < CB; ++cb)
 #pragma unroll
-        for (int pb = 0; pb < 2; ++pb) acc[cb][pb] = f4{0.f, 0.f, 0.f, 0.f};
+        for (int pb = 0; pb < PB; ++pb) acc[cb][pb] = f4{0.f, 0.f, 0.f, 0.f};
     for (int t = 0; t < 9; ++t) {
         const int dy = t / 3 - 1, dx = t % 3 - 1;
-        const __bf16 *src[2];
+        const __bf16 *src[PB];
 #pragma unroll
-        for (int pb = 0; pb < 2; ++pb) {
+        for (int pb = 0; pb < PB; ++pb) {
             const int sy = pb_y[pb] + dy, sx = pb_x[pb] + dx;
             const bool ok = pb_ok[pb] && sy >= 0 && sy < H && sx >= 0 && sx < W;
             const int iy = UP ? (sy >> 1) : sy, ix = UP ? (sx >> 1) : sx;
             src[pb] = ok ? x.p + (((size_t)pb_b[pb] * Hin + iy) * Win + ix) * x.stride + 8 * lq : nullptr;
         }
-        const __bf16 *wt[2];
+        const __bf16 *wt[CB];
 #pragma unroll
-        for (int cb = 0; cb < 2; ++cb) wt[cb] = w + ((size_t)(co0 + 16 * cb + l16) * 9 + t) * Cin + 8 * lq;
+        for (int cb = 0; cb < CB; ++cb) wt[cb] = w + ((size_t)(co0 + 16 * cb + l16) * 9 + t) * Cin + 8 * lq;
         for (int ci0 = 0; ci0 < Cin; ci0 += 32) {
-            bf8 a[2], bv[2];
+            bf8 a[CB], bv[PB];
 #pragma unroll
-            for (int cb = 0; cb < 2; ++cb) a[cb] = *reinterpret_cast<const bf8 *>(wt[cb] + ci0);
+            for (int cb = 0; cb < CB; ++cb) a[cb] = *reinterpret_cast<const bf8 *>(wt[cb] + ci0);
 #pragma unroll
-            for (int pb = 0; pb < 2; ++pb)
+            for (int pb = 0; pb < PB; ++pb)
                 bv[pb] = src[pb] ? *reinterpret_cast<const bf8 *>(src[pb] + ci0) : bf8_zero();
 #pragma unroll
-            for (int cb = 0; cb < 2; ++cb)
+            for (int cb = 0; cb < CB; ++cb)
 #pragma unroll
-                for (int pb = 0; pb < 2; ++pb) acc[cb][pb] = mfma_b(a[cb], bv[pb], acc[cb][pb]);
+                for (int pb = 0; pb < PB; ++pb) acc[cb][pb] = mfma_b(a[cb], bv[pb], acc[cb][pb]);
         }
     }
     // register i of acc[cb][pb]: channel co0 + 16 cb + 4 lq + i, pixel px0 + 16 pb + l16
 #pragma unroll
-    for (int pb = 0; pb < 2; ++pb) {
+    for (int pb = 0; pb < PB; ++pb) {
         const long long pix = px0 + 16 * pb + l16;
         if (pix >= npix) continue;
 #pragma unroll
-        for (int cb = 0; cb < 2; ++cb) {
+        for (int cb = 0; cb < CB; ++cb) {
             const int c = co0 + 16 * cb + 4 * lq;
             bf4 o;
 #pragma unroll
@@ -686,6 +689,33 @@ __global__ void k_phi0(const float *__restrict__ out, int B, int H, int W, float
 
 inline unsigned grid1(long long n, int bs = 256) { return (unsigned)((n + bs - 1) / bs); }
 
+// Tile shape of a 3x3 convolution: wide wave tiles (64 channels x 64 pixels,
+// or 32 channels x 128 pixels when Cout is not a multiple of 64) load fewer
+// operand bytes per matrix-core step; they are used while they still give a
+// block per compute unit (256), the 32 x 32 wave tiles otherwise.
+template <bool UP>
+void launch_conv_tiles(View x, int B, int H, int W, const __bf16 *w, int Cin, const float *bias, int relu, int Cout,
+                       View y, hipStream_t st) {
+    const long long npix = (long long)B * H * W;
+    if (Cout % 64 == 0) {
+        if ((long long)grid1(npix, 256) * (Cout / 64) >= 256)
+            k_conv<4, 1, 4, 4, UP><<<dim3(grid1(npix, 256), Cout / 64), 256, 0, st>>>(x, B, H, W, w, Cin, bias, relu, y);
+        else
+            k_conv<2, 2, 2, 2, UP><<<dim3(grid1(npix, 64), Cout / 64), 256, 0, st>>>(x, B, H, W, w, Cin, bias, relu, y);
+    } else {
+        if ((long long)grid1(npix, 512) * (Cout / 32) >= 256)
+            k_conv<4, 1, 2, 8, UP><<<dim3(grid1(npix, 512), Cout / 32), 256, 0, st>>>(x, B, H, W, w, Cin, bias, relu, y);
+        else
+            k_conv<4, 1, 2, 2, UP><<<dim3(grid1(npix, 128), Cout / 32), 256, 0, st>>>(x, B, H, W, w, Cin, bias, relu, y);
+    }
+}
+
+void launch_conv(View x, int B, int H, int W, const __bf16 *w, int Cin, const float *bias, int relu, int Cout, bool up,
+                 View y, hipStream_t st) {
+    if (up) launch_conv_tiles<true>(x, B, H, W, w, Cin, bias, relu, Cout, y, st);
+    else launch_conv_tiles<false>(x, B, H, W, w, Cin, bias, relu, Cout, y, st);
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------- host side
@@ -764,17 +794,7 @@ int conv(dsn_ctx *c, View x, int B, int l, int layer_i, bool up, bool transposed
     const __bf16 *w = (transposed ? c->pt : c->pb) + ly.w_off;
     const float *bias = transposed ? nullptr : c->p + ly.b_off;
     if (Cin % 32 || Cout % 32 || x.C != Cin || y.C != Cout) return fail(DSN_EINVAL, "conv shape mismatch");
-    const int H = c->h[l], W = c->w[l];
-    const long long npix = (long long)B * H * W;
-    if (Cout % 64 == 0) {
-        dim3 grid(grid1(npix, 64), Cout / 64);
-        if (up) k_conv<2, 2, true><<<grid, 256, 0, c->stream>>>(x, B, H, W, w, Cin, bias, relu, y);
-        else k_conv<2, 2, false><<<grid, 256, 0, c->stream>>>(x, B, H, W, w, Cin, bias, relu, y);
-    } else {
-        dim3 grid(grid1(npix, 128), Cout / 32);
-        if (up) k_conv<4, 1, true><<<grid, 256, 0, c->stream>>>(x, B, H, W, w, Cin, bias, relu, y);
-        else k_conv<4, 1, false><<<grid, 256, 0, c->stream>>>(x, B, H, W, w, Cin, bias, relu, y);
-    }
+    launch_conv(x, B, c->h[l], c->w[l], w, Cin, bias, relu, Cout, up, y, c->stream);
     HIPCHK(hipGetLastError());
     return DSN_OK;
 }
@@ -1163,16 +1183,7 @@ namespace {
 
 int op_conv(View x, int N, int H, int W, int Cin, bool up, const __bf16 *w, const float *b, int Cout, int relu,
             View y, hipStream_t st) {
-    const long long npix = (long long)N * H * W;
-    if (Cout % 64 == 0) {
-        dim3 grid(grid1(npix, 64), Cout / 64);
-        if (up) k_conv<2, 2, true><<<grid, 256, 0, st>>>(x, N, H, W, w, Cin, b, relu, y);
-        else k_conv<2, 2, false><<<grid, 256, 0, st>>>(x, N, H, W, w, Cin, b, relu, y);
-    } else {
-        dim3 grid(grid1(npix, 128), Cout / 32);
-        if (up) k_conv<4, 1, true><<<grid, 256, 0, st>>>(x, N, H, W, w, Cin, b, relu, y);
-        else k_conv<4, 1, false><<<grid, 256, 0, st>>>(x, N, H, W, w, Cin, b, relu, y);
-    }
+    launch_conv(x, N, H, W, w, Cin, b, relu, Cout, up, y, st);
     HIPCHK(hipGetLastError());
     return DSN_OK;
 }

@@ -56,6 +56,11 @@ CONV_CASES = [
     (1, 4, 4, 256, 128, False, True),
     (1, 10, 6, 32, 64, False, True),      # 60 pixels: ragged tile
     (3, 6, 10, 128, 256, True, False),
+    # images large enough for the wide wave tiles (32 x 128 and 64 x 64)
+    (2, 256, 256, 32, 32, False, True),
+    (1, 362, 364, 64, 32, True, True),    # ragged last block
+    (1, 256, 256, 64, 64, True, False),
+    (2, 129, 130, 32, 128, False, True),  # ragged last block
 ]
 
 
@@ -80,7 +85,8 @@ def test_conv_forward(dsn, N, H, W, Cin, Cout, up, relu):
     assert np.all(err <= bound)
 
 
-@pytest.mark.parametrize("N,H,W,Cin,Cout", [(2, 16, 16, 32, 32), (1, 8, 8, 64, 128), (1, 10, 6, 128, 64)])
+@pytest.mark.parametrize("N,H,W,Cin,Cout", [(2, 16, 16, 32, 32), (1, 8, 8, 64, 128), (1, 10, 6, 128, 64),
+                                           (1, 256, 256, 64, 32), (1, 513, 300, 32, 64)])
 def test_conv_input_gradient(dsn, N, H, W, Cin, Cout):
     rng = np.random.default_rng(7 + Cin)
     dy = _bf16(rng.normal(size=(N, H, W, Cout)))
