@@ -109,11 +109,12 @@ __global__ __launch_bounds__(256) void k_conv_first(const float *__restrict__ x,
 //   out[pixel][co] = act(bias[co] + sum_{tap, ci} w[co][tap][ci] x[src(pixel, tap)][ci])
 // Block: 4 waves as WPX (pixels) x WCO (channels); wave tile CB x PB matrix
 // blocks of 16 channels x 16 pixels: per 32-deep step a wave loads CB weight
-// and PB input fragments for CB x PB matrix-core steps.  Every output sums
-// taps, then input channels in steps of 32, in the same order for every tile
-// shape.  UP: x has half the resolution and is read through a nearest 2x
-// upsampling.  Requirements (checked on the host): Cin % 32 == 0,
-// Cout % (16 CB WCO) == 0, 16-byte aligned views.
+// and PB input fragments straight from global memory for CB x PB
+// matrix-core steps (used for small images; larger ones take k_conv_lds).
+// Every output sums taps, then input channels in steps of 32.  UP: x has
+// half the resolution and is read through a nearest 2x upsampling.
+// Requirements (checked on the host): Cin % 32 == 0, Cout % (16 CB WCO) == 0,
+// 16-byte aligned views.
 // --------------------------------------------------------------------------
 template <int WPX, int WCO, int CB, int PB, bool UP>
 __global__ __launch_bounds__(256) void k_conv(View x, int B, int H, int W, const __bf16 *__restrict__ w,
@@ -175,6 +176,120 @@ __global__ __launch_bounds__(256) void k_conv(View x, int B, int H, int W, const
         if (pix >= npix) continue;
 #pragma unroll
         for (int cb = 0; cb < CB; ++cb) {
+            const int c = co0 + 16 * cb + 4 * lq;
+            bf4 o;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                float v = acc[cb][pb][i] + (bias ? bias[c + i] : 0.f);
+                if (relu) v = fmaxf(v, 0.f);
+                o[i] = (__bf16)v;
+            }
+            *reinterpret_cast<bf4 *>(y.p + pix * y.stride + c) = o;
+        }
+    }
+}
+
+// --------------------------------------------------------------------------
+// 3x3 convolution with LDS-staged operands.  Block: an 8 x 32 pixel tile of
+// one image x 32 output channels; per 32-channel input chunk it stages the
+// tile's input pixels with a one-pixel halo (zero outside the image; through
+// the nearest 2x upsampling when UP) and the 32 x 9 x 32 weights in LDS, then
+// each of the nine taps reads its shifted window from LDS.  Wave w: rows 2w
+// and 2w + 1 of the tile (4 matrix blocks of 16 pixels) x 32 channels.  Row
+// strides of 40 and 296 elements make the 16-byte reads of 8 consecutive
+// lanes hit distinct banks.  Every output sums input-channel chunks, then
+// taps.
+// --------------------------------------------------------------------------
+constexpr int CL_TY = 8, CL_TX = 32, CL_TC = 32;
+constexpr int CL_XS = 40;                         // LDS elements per staged pixel
+constexpr int CL_WS = 9 * 32 + 8;                 // LDS elements per staged output channel
+constexpr int CL_NPX = (CL_TY + 2) * (CL_TX + 2);
+
+template <bool UP>
+__global__ __launch_bounds__(256) void k_conv_lds(View x, int B, int H, int W, const __bf16 *__restrict__ w,
+                                                  int Cin, const float *__restrict__ bias, int relu, View y) {
+    __shared__ __attribute__((aligned(16))) __bf16 Xs[CL_NPX * CL_XS];
+    __shared__ __attribute__((aligned(16))) __bf16 Ws[CL_TC * CL_WS];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int l16 = lane & 15, lq = lane >> 4;
+    const int ntx = (W + CL_TX - 1) / CL_TX, nty = (H + CL_TY - 1) / CL_TY;
+    const int tix = blockIdx.x % ntx, rest = blockIdx.x / ntx;
+    const int tiy = rest % nty, b = rest / nty;
+    const int x0 = tix * CL_TX, y0 = tiy * CL_TY, co0 = blockIdx.y * CL_TC;
+    const int Hin = UP ? H / 2 : H, Win = UP ? W / 2 : W;
+    constexpr int XU = (CL_NPX * 4 + 255) / 256;  // 16-byte input units per thread
+    constexpr int WU = (CL_TC * 36 + 255) / 256;  // 16-byte weight units per thread
+    f4 acc[2][4];
+#pragma unroll
+    for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+        for (int pb = 0; pb < 4; ++pb) acc[cb][pb] = f4{0.f, 0.f, 0.f, 0.f};
+    for (int ci0 = 0; ci0 < Cin; ci0 += 32) {
+        bf8 xv[XU], wv[WU];
+#pragma unroll
+        for (int u = 0; u < XU; ++u) {
+            const int e = threadIdx.x + 256 * u;
+            xv[u] = bf8_zero();
+            if (e < CL_NPX * 4) {
+                const int px = e >> 2, seg = e & 3;
+                const int gy = y0 + px / (CL_TX + 2) - 1, gx = x0 + px % (CL_TX + 2) - 1;
+                if (gy >= 0 && gy < H && gx >= 0 && gx < W) {
+                    const int sy = UP ? (gy >> 1) : gy, sx = UP ? (gx >> 1) : gx;
+                    xv[u] = *reinterpret_cast<const bf8 *>(x.p + (((size_t)b * Hin + sy) * Win + sx) * x.stride +
+                                                           ci0 + 8 * seg);
+                }
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < WU; ++u) {
+            const int e = threadIdx.x + 256 * u;
+            if (e < CL_TC * 36) {
+                const int col = e / 36, rem = e % 36;
+                wv[u] = *reinterpret_cast<const bf8 *>(w + ((size_t)(co0 + col) * 9 + rem / 4) * Cin + ci0 +
+                                                       8 * (rem % 4));
+            }
+        }
+        __syncthreads();                              // the previous chunk's reads are done
+#pragma unroll
+        for (int u = 0; u < XU; ++u) {
+            const int e = threadIdx.x + 256 * u;
+            if (e < CL_NPX * 4) *reinterpret_cast<bf8 *>(&Xs[(e >> 2) * CL_XS + 8 * (e & 3)]) = xv[u];
+        }
+#pragma unroll
+        for (int u = 0; u < WU; ++u) {
+            const int e = threadIdx.x + 256 * u;
+            if (e < CL_TC * 36) {
+                const int col = e / 36, rem = e % 36;
+                *reinterpret_cast<bf8 *>(&Ws[col * CL_WS + (rem / 4) * 32 + 8 * (rem % 4)]) = wv[u];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int t = 0; t < 9; ++t) {
+            const int dy = t / 3, dx = t % 3;         // halo offsets 0..2
+            bf8 a[2], bv[4];
+#pragma unroll
+            for (int cb = 0; cb < 2; ++cb)
+                a[cb] = *reinterpret_cast<const bf8 *>(&Ws[(16 * cb + l16) * CL_WS + t * 32 + 8 * lq]);
+#pragma unroll
+            for (int pb = 0; pb < 4; ++pb) {
+                const int r = 2 * wave + (pb >> 1), c = 16 * (pb & 1) + l16;
+                bv[pb] = *reinterpret_cast<const bf8 *>(&Xs[((r + dy) * (CL_TX + 2) + c + dx) * CL_XS + 8 * lq]);
+            }
+#pragma unroll
+            for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+                for (int pb = 0; pb < 4; ++pb) acc[cb][pb] = mfma_b(a[cb], bv[pb], acc[cb][pb]);
+        }
+    }
+    // register i of acc[cb][pb]: channel co0 + 16 cb + 4 lq + i, pixel (row r, column c) of the tile
+#pragma unroll
+    for (int pb = 0; pb < 4; ++pb) {
+        const int gy = y0 + 2 * wave + (pb >> 1), gx = x0 + 16 * (pb & 1) + l16;
+        if (gy >= H || gx >= W) continue;
+        const long long pix = ((long long)b * H + gy) * W + gx;
+#pragma unroll
+        for (int cb = 0; cb < 2; ++cb) {
             const int c = co0 + 16 * cb + 4 * lq;
             bf4 o;
 #pragma unroll
@@ -689,25 +804,22 @@ __global__ void k_phi0(const float *__restrict__ out, int B, int H, int W, float
 
 inline unsigned grid1(long long n, int bs = 256) { return (unsigned)((n + bs - 1) / bs); }
 
-// Tile shape of a 3x3 convolution: wide wave tiles (64 channels x 64 pixels,
-// or 32 channels x 128 pixels when Cout is not a multiple of 64) load fewer
-// operand bytes per matrix-core step; they are used while they still give a
-// block per compute unit (256), the 32 x 32 wave tiles otherwise.
+// Kernel of a 3x3 convolution: the LDS-staged tiles from 8 x 32 pixels up,
+// register tiles of 32 x 32 per wave (operands straight from global memory)
+// for smaller images.
 template <bool UP>
 void launch_conv_tiles(View x, int B, int H, int W, const __bf16 *w, int Cin, const float *bias, int relu, int Cout,
                        View y, hipStream_t st) {
-    const long long npix = (long long)B * H * W;
-    if (Cout % 64 == 0) {
-        if ((long long)grid1(npix, 256) * (Cout / 64) >= 256)
-            k_conv<4, 1, 4, 4, UP><<<dim3(grid1(npix, 256), Cout / 64), 256, 0, st>>>(x, B, H, W, w, Cin, bias, relu, y);
-        else
-            k_conv<2, 2, 2, 2, UP><<<dim3(grid1(npix, 64), Cout / 64), 256, 0, st>>>(x, B, H, W, w, Cin, bias, relu, y);
-    } else {
-        if ((long long)grid1(npix, 512) * (Cout / 32) >= 256)
-            k_conv<4, 1, 2, 8, UP><<<dim3(grid1(npix, 512), Cout / 32), 256, 0, st>>>(x, B, H, W, w, Cin, bias, relu, y);
-        else
-            k_conv<4, 1, 2, 2, UP><<<dim3(grid1(npix, 128), Cout / 32), 256, 0, st>>>(x, B, H, W, w, Cin, bias, relu, y);
+    if (H >= CL_TY && W >= CL_TX) {
+        const long long tiles = (long long)B * ((H + CL_TY - 1) / CL_TY) * ((W + CL_TX - 1) / CL_TX);
+        k_conv_lds<UP><<<dim3((unsigned)tiles, Cout / CL_TC), 256, 0, st>>>(x, B, H, W, w, Cin, bias, relu, y);
+        return;
     }
+    const long long npix = (long long)B * H * W;
+    if (Cout % 64 == 0)
+        k_conv<2, 2, 2, 2, UP><<<dim3(grid1(npix, 64), Cout / 64), 256, 0, st>>>(x, B, H, W, w, Cin, bias, relu, y);
+    else
+        k_conv<4, 1, 2, 2, UP><<<dim3(grid1(npix, 128), Cout / 32), 256, 0, st>>>(x, B, H, W, w, Cin, bias, relu, y);
 }
 
 void launch_conv(View x, int B, int H, int W, const __bf16 *w, int Cin, const float *bias, int relu, int Cout, bool up,

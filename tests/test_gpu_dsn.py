@@ -56,11 +56,13 @@ CONV_CASES = [
     (1, 4, 4, 256, 128, False, True),
     (1, 10, 6, 32, 64, False, True),      # 60 pixels: ragged tile
     (3, 6, 10, 128, 256, True, False),
-    # images large enough for the wide wave tiles (32 x 128 and 64 x 64)
+    # images of 8 x 32 pixels and more take the LDS-staged kernel
     (2, 256, 256, 32, 32, False, True),
     (1, 362, 364, 64, 32, True, True),    # ragged last block
     (1, 256, 256, 64, 64, True, False),
     (2, 129, 130, 32, 128, False, True),  # ragged last block
+    (3, 8, 32, 96, 256, False, True),     # exactly one tile per image
+    (1, 10, 34, 128, 64, True, False),    # one full and one partial tile per row
 ]
 
 
