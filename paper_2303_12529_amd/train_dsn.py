@@ -80,6 +80,9 @@ def main():
     ap.add_argument("--out", required=True)
     ap.add_argument("--speed-only", action="store_true")
     ap.add_argument("--modulation", action="store_true")
+    ap.add_argument("--init", default=None,
+                    help="flat parameters (.npy) to start from, e.g. a trained level-set network for the "
+                         "two-branch one; parameters beyond them (the modulation head) keep their He values")
     ap.add_argument("--workers", type=int, default=0,
                     help="processes drawing the training clips while the device solves (0: draw in line)")
     args = ap.parse_args()
@@ -103,9 +106,17 @@ def main():
     torch.cuda.set_device(0)
     net = dsn.Net(512, 512, 32, max_batch=args.batch, modulation=args.modulation)
     init = dsn.he_init(args.seed, modulation=args.modulation)
+    if args.init:
+        import numpy as np
+        start = np.load(args.init, allow_pickle=False)
+        if start.ndim != 1 or start.size > init.size:
+            raise SystemExit("--init: expected a flat vector of at most %d parameters" % init.size)
+        init[:start.size] = start.astype(np.float32)
     net.set_params(init)
     report = {"network": {"grid": [512, 512], "base": 32, "params": net.n_params, "modulation": args.modulation,
                           "forward_gflop_per_sample": round(develset_flops(net) / 1e9, 2)}}
+    if args.init:
+        report["init"] = os.path.basename(args.init)
     report["speed"] = speed(net, args.batch)
     log("speed %s" % report["speed"])
     if args.speed_only:
