@@ -427,17 +427,32 @@ __global__ __launch_bounds__(256) void k_wgrad_first(View dz, const float *__res
     float acc[10];
 #pragma unroll
     for (int k = 0; k < 10; ++k) acc[k] = 0.f;
-    for (long long pix = p_lo + ph; pix < p_hi; pix += nph) {
-        const float d = (float)dz.p[pix * dz.stride + co];
-        const int xx = (int)(pix % W);
+    // the thread's pixels advance by nph (< W): (b, yy, xx) stepped instead of
+    // divided out per pixel
+    long long pix = p_lo + ph;
+    int xx = 0, yy = 0, b = 0;
+    if (pix < p_hi) {
+        xx = (int)(pix % W);
         const long long r = pix / W;
-        const int yy = (int)(r % H), b = (int)(r / H);
+        yy = (int)(r % H);
+        b = (int)(r / H);
+    }
+    for (; pix < p_hi; pix += nph) {
+        const float d = (float)dz.p[pix * dz.stride + co];
 #pragma unroll
         for (int t = 0; t < 9; ++t) {
             const int sy = yy + t / 3 - 1, sx = xx + t % 3 - 1;
             if (sy >= 0 && sy < H && sx >= 0 && sx < W) acc[t] = fmaf(d, x[((size_t)b * H + sy) * W + sx], acc[t]);
         }
         acc[9] += d;
+        xx += nph;
+        while (xx >= W) {
+            xx -= W;
+            if (++yy == H) {
+                yy = 0;
+                ++b;
+            }
+        }
     }
 #pragma unroll
     for (int k = 0; k < 10; ++k) red[threadIdx.x][k] = acc[k];
@@ -466,7 +481,17 @@ __global__ __launch_bounds__(256) void k_bias_grad(View dz, long long npix, long
     const long long p_hi = p_lo + pix_per_split < npix ? p_lo + pix_per_split : npix;
     float acc = 0.f;
     if (ph < nph)
-        for (long long pix = p_lo + ph; pix < p_hi; pix += nph) acc += (float)dz.p[pix * dz.stride + c];
+        for (long long pix = p_lo + ph; pix < p_hi; pix += 8LL * nph) {
+            // eight pixels' loads in flight, added in pixel order
+            float v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const long long q = pix + (long long)u * nph;
+                v[u] = q < p_hi ? (float)dz.p[q * dz.stride + c] : 0.f;
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) acc += v[u];
+        }
     red[threadIdx.x] = acc;
     __syncthreads();
     if (threadIdx.x < C) {
@@ -476,13 +501,33 @@ __global__ __launch_bounds__(256) void k_bias_grad(View dz, long long npix, long
     }
 }
 
-// out[j] = sum_s part[s][j] in a fixed order (FP64 accumulation).
-__global__ void k_reduce_splits(const float *__restrict__ part, int S, long long n, float *__restrict__ out) {
-    const long long j = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= n) return;
+// out[j] = sum_s part[s][j] in a fixed order (FP64 accumulation).  Block:
+// OUT outputs x (256 / OUT) groups of partials s = g, g + 256/OUT, ...; the
+// group sums are added in group order.
+template <int OUT>
+__global__ __launch_bounds__(256) void k_reduce_splits(const float *__restrict__ part, int S, long long n,
+                                                       float *__restrict__ out) {
+    constexpr int GRP = 256 / OUT;
+    __shared__ double red[GRP][OUT + 1];
+    const int o = threadIdx.x % OUT, g = threadIdx.x / OUT;
+    const long long j = (long long)blockIdx.x * OUT + o;
     double v = 0.0;
-    for (int s = 0; s < S; ++s) v += part[(size_t)s * n + j];
-    out[j] = (float)v;
+    if (j < n)
+        for (int s = g; s < S; s += GRP) v += part[(size_t)s * n + j];
+    red[g][o] = v;
+    __syncthreads();
+    if (g == 0 && j < n) {
+        double t = 0.0;
+        for (int q = 0; q < GRP; ++q) t += red[q][o];
+        out[j] = (float)t;
+    }
+}
+
+// many outputs: 16 per block; few (biases, the head): one per block, all
+// 256 threads on its partials
+void reduce_splits(const float *part, int S, long long n, float *out, hipStream_t st) {
+    if (n >= 4096) k_reduce_splits<16><<<(unsigned)((n + 15) / 16), 256, 0, st>>>(part, S, n, out);
+    else k_reduce_splits<1><<<(unsigned)n, 256, 0, st>>>(part, S, n, out);
 }
 
 // --------------------------------------------------------------------------
@@ -933,11 +978,11 @@ int wgrad(dsn_ctx *c, View dz, View x, int B, int l, int layer_i, bool up) {
 #undef WG
     HIPCHK(hipGetLastError());
     const long long nw = (long long)Cout * 9 * Cin;
-    k_reduce_splits<<<grid1(nw), 256, 0, c->stream>>>(c->part, S, nw, c->grad + ly.w_off);
+    reduce_splits(c->part, S, nw, c->grad + ly.w_off, c->stream);
     HIPCHK(hipGetLastError());
     k_bias_grad<<<S, 256, 0, c->stream>>>(dz, npix, pps, c->part);
     HIPCHK(hipGetLastError());
-    k_reduce_splits<<<grid1(Cout), 256, 0, c->stream>>>(c->part, S, Cout, c->grad + ly.b_off);
+    reduce_splits(c->part, S, Cout, c->grad + ly.b_off, c->stream);
     HIPCHK(hipGetLastError());
     return DSN_OK;
 }
@@ -1170,8 +1215,7 @@ extern "C" int dsn_backward(dsn_ctx *c, const float *d_target, const float *d_ta
     // hpart [nblk][heads][C0 + 1] -> each head's weights then bias; the two
     // heads are adjacent in the flat vector
     const int nh = with_m ? 2 : 1;
-    k_reduce_splits<<<grid1(nh * (C0 + 1)), 256, 0, c->stream>>>(c->hpart, (int)nblk, nh * (C0 + 1),
-                                                                   c->grad + hd.w_off);
+    reduce_splits(c->hpart, (int)nblk, nh * (C0 + 1), c->grad + hd.w_off, c->stream);
     HIPCHK(hipGetLastError());
     if (c->modulation && !with_m)
         HIPCHK(hipMemsetAsync(c->grad + hm.w_off, 0, (C0 + 1) * sizeof(float), c->stream));
@@ -1231,10 +1275,9 @@ extern "C" int dsn_backward(dsn_ctx *c, const float *d_target, const float *d_ta
             k_wgrad_first<<<S, 256, 0, c->stream>>>(ga, c->x_in, B, c->h[0], c->w[0], pps, c->part);
             HIPCHK(hipGetLastError());
             const long long nw = (long long)ly.cout * 9;
-            k_reduce_splits<<<grid1(nw), 256, 0, c->stream>>>(c->part, S, nw, c->grad + ly.w_off);
+            reduce_splits(c->part, S, nw, c->grad + ly.w_off, c->stream);
             HIPCHK(hipGetLastError());
-            k_reduce_splits<<<grid1(ly.cout), 256, 0, c->stream>>>(c->part + (size_t)S * ly.cout * 9, S, ly.cout,
-                                                                     c->grad + ly.b_off);
+            reduce_splits(c->part + (size_t)S * ly.cout * 9, S, ly.cout, c->grad + ly.b_off, c->stream);
             HIPCHK(hipGetLastError());
         }
     }
@@ -1363,9 +1406,9 @@ extern "C" int dsn_op_conv3x3_wgrad(const void *d_dz, const void *d_x, int N, in
     hipError_t e = hipGetLastError();
     const long long nw = (long long)Cout * 9 * Cin;
     if (e == hipSuccess) {
-        k_reduce_splits<<<grid1(nw), 256, 0, st>>>(part, S, nw, d_dw);
+        reduce_splits(part, S, nw, d_dw, st);
         k_bias_grad<<<S, 256, 0, st>>>(dz, npix, pps, part);
-        k_reduce_splits<<<grid1(Cout), 256, 0, st>>>(part, S, Cout, d_db);
+        reduce_splits(part, S, Cout, d_db, st);
         e = hipGetLastError();
     }
     (void)hipStreamSynchronize(st);
