@@ -471,33 +471,40 @@ __global__ __launch_bounds__(256) void k_wgrad_first(View dz, const float *__res
 }
 
 // Bias gradient partials: part[s][c] = sum_{pixel in range s} dz[pixel][c].
+// Thread = (group of 8 channels, pixel lane): 16-byte loads, four pixels'
+// loads in flight; the pixel lanes are added in lane order.  C % 8 == 0,
+// C <= 2048, 16-byte aligned view.
 __global__ __launch_bounds__(256) void k_bias_grad(View dz, long long npix, long long pix_per_split,
                                                     float *__restrict__ part) {
-    __shared__ float red[256];
-    const int C = dz.C;
+    __shared__ float red[256][9];
+    const int C = dz.C, G = C / 8;
     const int s = blockIdx.x;
-    const int c = threadIdx.x % C, ph = threadIdx.x / C, nph = 256 / C;
+    const int g = threadIdx.x % G, ph = threadIdx.x / G, nph = 256 / G;
     const long long p_lo = (long long)s * pix_per_split;
     const long long p_hi = p_lo + pix_per_split < npix ? p_lo + pix_per_split : npix;
-    float acc = 0.f;
-    if (ph < nph)
-        for (long long pix = p_lo + ph; pix < p_hi; pix += 8LL * nph) {
-            // eight pixels' loads in flight, added in pixel order
-            float v[8];
+    float acc[8];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const long long q = pix + (long long)u * nph;
-                v[u] = q < p_hi ? (float)dz.p[q * dz.stride + c] : 0.f;
-            }
+    for (int e = 0; e < 8; ++e) acc[e] = 0.f;
+    for (long long pix = p_lo + ph; ph < nph && pix < p_hi; pix += 4LL * nph) {
+        bf8 v[4];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) acc += v[u];
+        for (int u = 0; u < 4; ++u) {
+            const long long q = pix + (long long)u * nph;
+            v[u] = q < p_hi ? *reinterpret_cast<const bf8 *>(dz.p + q * dz.stride + 8 * g) : bf8_zero();
         }
-    red[threadIdx.x] = acc;
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int e = 0; e < 8; ++e) acc[e] += (float)v[u][e];
+    }
+#pragma unroll
+    for (int e = 0; e < 8; ++e) red[threadIdx.x][e] = acc[e];
     __syncthreads();
-    if (threadIdx.x < C) {
+    for (int c = threadIdx.x; c < C; c += 256) {
+        const int gc = c / 8, e = c % 8;
         float v = 0.f;
-        for (int h = 0; h < nph; ++h) v += red[h * C + threadIdx.x];
-        part[(size_t)s * C + threadIdx.x] = v;
+        for (int h = 0; h < nph; ++h) v += red[h * G + gc][e];
+        part[(size_t)s * C + c] = v;
     }
 }
 

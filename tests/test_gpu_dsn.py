@@ -101,7 +101,10 @@ def test_conv_input_gradient(dsn, N, H, W, Cin, Cout):
 
 @pytest.mark.parametrize("N,H,W,Cin,Cout,up", [(2, 16, 16, 32, 32, False), (1, 8, 12, 64, 32, False),
                                                (2, 16, 16, 64, 64, True), (1, 4, 4, 256, 128, False),
-                                               (3, 10, 6, 32, 64, True), (64, 32, 32, 32, 32, False)])
+                                               (3, 10, 6, 32, 64, True), (64, 32, 32, 32, 32, False),
+                                               # bias sums with channel groups that do not divide the
+                                               # block (96) and more channels than threads (320)
+                                               (2, 12, 10, 32, 96, False), (1, 9, 11, 32, 320, False)])
 def test_conv_weight_gradient(dsn, N, H, W, Cin, Cout, up):
     _say("wgrad", N, H, W, Cin, Cout, up)
     rng = np.random.default_rng(11 + Cin + Cout + N)
