@@ -1277,7 +1277,10 @@ extern "C" int dsn_backward(dsn_ctx *c, const float *d_target, const float *d_ta
             if ((r = conv(c, ga, B, l, enc_a(l), false, true, 0, view(c->gA[l], Cp, Cp)))) return r;
         } else {
             const dsn_layer &ly = c->L[enc_a(0)];
-            const int S = splits_for(np);
+            // one input channel: little work per pixel, so ranges of 512
+            // pixels (up to 4096 blocks) while the partials fit the buffer
+            int S = (int)std::max(1LL, std::min(4096LL, np / 512));
+            if ((long long)S * ly.cout * 10 > c->part_cap) S = splits_for(np);
             const long long pps = (np + S - 1) / S;
             k_wgrad_first<<<S, 256, 0, c->stream>>>(ga, c->x_in, B, c->h[0], c->w[0], pps, c->part);
             HIPCHK(hipGetLastError());
