@@ -691,10 +691,11 @@ __global__ __launch_bounds__(256) void k_head_bwd(View x, long long npix, int B,
                                                    const float *__restrict__ out_m, const float *__restrict__ tgt,
                                                    const float *__restrict__ tgt_m, View dx,
                                                    double *__restrict__ loss_part, float *__restrict__ gpart) {
-    const int C = x.C;                      // <= 64
+    const int C = x.C;                      // <= 64, a multiple of 8
     const int NH = out_m ? 2 : 1;
-    __shared__ double lred[2][256];
-    __shared__ float gred[256][65];
+    __shared__ double lw[2][4];
+    __shared__ float gw[2][4][65];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const long long pix = (long long)blockIdx.x * 256 + threadIdx.x;
     double l = 0.0, lm = 0.0;
     float g = 0.f, gm = 0.f;
@@ -708,8 +709,11 @@ __global__ __launch_bounds__(256) void k_head_bwd(View x, long long npix, int B,
             lm = (double)hm * hm;
             gm = 2.f / (float)B * hm * ahf_grad(z);
         }
-        for (int c = 0; c < C; c += 8) {
-            v[c / 8] = *reinterpret_cast<const bf8 *>(x.p + pix * x.stride + c);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            if (8 * k >= C) break;
+            const int c = 8 * k;
+            v[k] = *reinterpret_cast<const bf8 *>(x.p + pix * x.stride + c);
             bf8 o;
 #pragma unroll
             for (int e = 0; e < 8; ++e)
@@ -717,30 +721,42 @@ __global__ __launch_bounds__(256) void k_head_bwd(View x, long long npix, int B,
             *reinterpret_cast<bf8 *>(dx.p + pix * dx.stride + c) = o;
         }
     }
-    lred[0][threadIdx.x] = l;
-    lred[1][threadIdx.x] = lm;
+    // per-block sums in a fixed order: a shuffle tree in each wave, then the
+    // four waves in wave order
+    double l0 = l, l1 = lm;
+    for (int o = 32; o > 0; o >>= 1) {
+        l0 += __shfl_xor(l0, o, 64);
+        l1 += __shfl_xor(l1, o, 64);
+    }
+    if (lane == 0) {
+        lw[0][wave] = l0;
+        lw[1][wave] = l1;
+    }
     for (int h = 0; h < NH; ++h) {
-        const float gh = h == 0 ? g : gm;
-        for (int c = 0; c < C; c += 8)
+        const float gh = pix < npix ? (h == 0 ? g : gm) : 0.f;
 #pragma unroll
-            for (int e = 0; e < 8; ++e) gred[threadIdx.x][c + e] = pix < npix ? gh * (float)v[c / 8][e] : 0.f;
-        gred[threadIdx.x][C] = pix < npix ? gh : 0.f;
-        __syncthreads();
-        if (threadIdx.x <= C) {
-            float sum = 0.f;
-            for (int i = 0; i < 256; ++i) sum += gred[i][threadIdx.x];
-            gpart[((size_t)blockIdx.x * NH + h) * (C + 1) + threadIdx.x] = sum;
+        for (int k = 0; k < 8; ++k) {
+            if (8 * k >= C) break;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                float t = pix < npix ? gh * (float)v[k][e] : 0.f;
+                for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o, 64);
+                if (lane == 0) gw[h][wave][8 * k + e] = t;
+            }
         }
-        __syncthreads();
+        float t = gh;
+        for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o, 64);
+        if (lane == 0) gw[h][wave][C] = t;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < NH * (C + 1); i += 256) {
+        const int h = i / (C + 1), c = i - (i / (C + 1)) * (C + 1);
+        gpart[((size_t)blockIdx.x * NH + h) * (C + 1) + c] =
+            ((gw[h][0][c] + gw[h][1][c]) + gw[h][2][c]) + gw[h][3][c];
     }
     if (threadIdx.x == 0) {
-        double s0 = 0.0, s1 = 0.0;
-        for (int i = 0; i < 256; ++i) {
-            s0 += lred[0][i];
-            s1 += lred[1][i];
-        }
-        loss_part[2 * blockIdx.x] = s0;
-        loss_part[2 * blockIdx.x + 1] = s1;
+        loss_part[2 * blockIdx.x] = ((lw[0][0] + lw[0][1]) + lw[0][2]) + lw[0][3];
+        loss_part[2 * blockIdx.x + 1] = ((lw[1][0] + lw[1][1]) + lw[1][2]) + lw[1][3];
     }
 }
 
