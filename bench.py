@@ -150,23 +150,57 @@ def gwindow_forms(Z, H, w, N, prm, steps, autotune):
     return out
 
 
-def cpu_baseline(workload, seed, iters):
-    """Time the FP64 oracle on `iters` iterations of the same workload."""
-    import numpy as np
-    from threadpoolctl import threadpool_info
+def cpu_model():
+    """The host CPU's model name (first /proc/cpuinfo entry) and logical CPU count."""
+    name = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    name = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return name, os.cpu_count()
+
+
+def _oracle_iters(workload, seed, iters):
+    """Wall time of `iters` oracle iterations from TSDF(target) (the TSDF
+    itself untimed)."""
     from oracle import edt as o_edt
     from oracle import solve as o_solve
     from paper_2303_12529_amd.inputs import workload_inputs
     Z, H, w, prm = workload_inputs(workload, seed)
     phi, _, _ = o_edt.tsdf_from_mask(Z, prm["d_lower"], prm["d_upper"])
-    threads = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
     t0 = time.perf_counter()
     for _ in range(iters):
         phi, _ = o_solve.iteration(phi, Z, H, w, prm)
-    dt = time.perf_counter() - t0
-    return {"value": iters / dt, "unit": "it/s", "cores": int(threads), "kind": "oracle",
-            "sample": "%d DSO iterations of the same %s clip (seed %d), FP64 numpy/BLAS, %.1f s"
-                      % (iters, workload, seed, dt)}
+    return time.perf_counter() - t0
+
+
+def cpu_baseline(workload, seed, iters, iters_1t=1, c0_iters=20):
+    """The FP64 oracle on the host cores: `iters` iterations of the timed
+    workload with the BLAS threads it finds (the reported value), the same
+    with one thread, and the 256^2 workload's whole loop."""
+    from threadpoolctl import threadpool_info, threadpool_limits
+    threads = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
+    dt = _oracle_iters(workload, seed, iters)
+    model, ncpu = cpu_model()
+    out = {"value": iters / dt, "unit": "it/s", "cores": int(threads), "kind": "oracle",
+           "sample": "%d DSO iterations of the same %s clip (seed %d), FP64 numpy/BLAS on %d threads, %.1f s"
+                     % (iters, workload, seed, threads, dt),
+           "cpu_model": model, "logical_cpus": ncpu}
+    with threadpool_limits(limits=1):
+        if iters_1t > 0:
+            d1 = _oracle_iters(workload, seed, iters_1t)
+            out["one_thread"] = {"value": iters_1t / d1, "unit": "it/s", "cores": 1,
+                                 "sample": "%d iteration(s), %.1f s" % (iters_1t, d1)}
+    if c0_iters > 0 and workload != "c0":
+        d0 = _oracle_iters("c0", seed, c0_iters)
+        out["c0_whole_loop"] = {"value": c0_iters / d0, "unit": "it/s", "cores": int(threads),
+                                "s": round(d0, 3),
+                                "sample": "the 256^2 workload's %d iterations (seed %d)" % (c0_iters, seed)}
+    return out
 
 
 def time_to_target(ctxs, workload, seeds, extra_iters=10):
@@ -361,6 +395,7 @@ def main():
     ap.add_argument("--workload", default="c1")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--cpu-iters", type=int, default=4)
+    ap.add_argument("--cpu-iters-1t", type=int, default=1, help="oracle iterations on one thread (0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--precision", choices=("fp32", "bf16x3"), default="fp32",
                     help="arithmetic of the dense contractions (default: the plain FP32 loop)")
@@ -505,7 +540,7 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(args.workload, args.seed, args.cpu_iters)
+        cpu = cpu_baseline(args.workload, args.seed, args.cpu_iters, args.cpu_iters_1t)
 
     desc = WORKLOADS[args.workload]
     line = {

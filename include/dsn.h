@@ -120,6 +120,50 @@ int dsn_op_conv3x3_dgrad(const void *d_dy, int N, int H, int W, int Cout, const 
 int dsn_op_conv3x3_wgrad(const void *d_dz, const void *d_x, int N, int H, int W, int Cin, int up, int Cout,
                          float *d_dw, float *d_db, void *stream);
 
+/* The network's other layers, one call each (Sec. III-B; the same kernels as
+ * dsn_forward / dsn_backward, with the same work split).  Every pointer
+ * 16-byte aligned; C (channels) as stated per call.
+ * dsn_op_conv_first: the first layer (one input channel, VALU): d_y BF16
+ *   [N][H][W][Cout] = max(0, d_b + conv3x3(d_x)), d_x FP32 [N][H][W], d_w
+ *   BF16 [Cout][3][3][1], d_b FP32 [Cout]; Cout a multiple of 8 in
+ *   [8, 1024].  Async on `stream`.
+ * dsn_op_wgrad_first: its weight and bias gradients, FP32 d_dw [C][3][3][1]
+ *   and d_db [C], for the output gradient d_dz BF16 [N][H][W][C] and input
+ *   d_x FP32 [N][H][W]: sums over pixel ranges (512 pixels each, at most
+ *   4096 ranges; a range may cross image boundaries) in FP32, the ranges
+ *   added in FP64 in a fixed order.  C in {8, 16, 32, 64}.  Synchronous;
+ *   allocates and frees the range partials.
+ * dsn_op_head_bwd: backward of the 1x1 head(s) and the losses for npix
+ *   pixels of features d_x BF16 [npix][C] (C a multiple of 8 in [8, 64]),
+ *   level-set head weights d_w BF16 [C], outputs d_out and targets d_t FP32
+ *   [npix], batch size B (the losses are sums over pixels averaged over B).
+ *   With the modulation head, d_wm BF16 [C], d_out_m (phi_m before H_eps)
+ *   and d_t_m FP32 [npix] (all three or none).  Out: d_dx BF16 [npix][C]
+ *   = g w + g_m w_m with g = (2/B)(out - t), g_m = (2/B)(H_eps(out_m) - t_m)
+ *   H_eps'(out_m); d_loss double[2] = {L_0, L_m (0 without the head)};
+ *   d_gw FP32 [heads][C + 1] = per head the weight gradient sum_p g x[p]
+ *   then the bias gradient sum_p g.  Synchronous; allocates and frees the
+ *   block partials.
+ * dsn_op_maxpool2_bwd: d_dx BF16 [N][H][W][C] += each gradient of d_dy BF16
+ *   [N][H/2][W/2][C] routed to the first maximum (row-major) of its 2x2
+ *   window of d_x BF16 [N][H][W][C]; the sum in FP32, rounded once to BF16.
+ * dsn_op_upsample2_bwd: d_dx BF16 [N][H/2][W/2][C] = the FP32 sum of the
+ *   four children in d_dy BF16 [N][H][W][C] (nearest 2x upsampling's
+ *   gradient), rounded once to BF16.
+ * dsn_op_relu_bwd: d_d BF16 [npix][C] *= [d_y > 0] in place (d_y BF16, the
+ *   layer's output).
+ * The last three: H, W even, C a multiple of 8 in [8, 2048]; async. */
+int dsn_op_conv_first(const float *d_x, int N, int H, int W, const void *d_w, const float *d_b, int Cout, void *d_y,
+                      void *stream);
+int dsn_op_wgrad_first(const void *d_dz, const float *d_x, int N, int H, int W, int C, float *d_dw, float *d_db,
+                       void *stream);
+int dsn_op_head_bwd(const void *d_x, long long npix, int C, int B, const void *d_w, const void *d_wm,
+                    const float *d_out, const float *d_out_m, const float *d_t, const float *d_t_m, void *d_dx,
+                    double *d_loss, float *d_gw, void *stream);
+int dsn_op_maxpool2_bwd(const void *d_x, int N, int H, int W, int C, const void *d_dy, void *d_dx, void *stream);
+int dsn_op_upsample2_bwd(const void *d_dy, int N, int H, int W, int C, void *d_dx, void *stream);
+int dsn_op_relu_bwd(void *d_d, const void *d_y, long long npix, int C, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

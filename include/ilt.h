@@ -46,7 +46,7 @@ enum {
     ILT_EINVAL = -1,       /* bad argument (null, size, range, alignment)     */
     ILT_ENOMEM = -2,       /* device allocation at create time failed         */
     ILT_EDEVICE = -3,      /* a HIP runtime call failed                       */
-    ILT_ENUMERIC = -4,     /* non-finite loss or gradient detected            */
+    ILT_ENUMERIC = -4,     /* non-finite loss, gradient or phi detected       */
     ILT_EUNSUPPORTED = -5  /* valid but not built for (e.g. P too large)      */
 };
 
@@ -54,8 +54,12 @@ enum {
  * ILT_BF16X3: each FP32 operand is split into BF16 hi + lo and products are
  * taken as hi*hi + hi*lo + lo*hi with FP32 accumulation on the BF16 matrix
  * cores; the adjoint then recomputes the fields (no field store).  Every
- * other step is FP32/FP64 as in ILT_FP32. */
-enum { ILT_FP32 = 0, ILT_BF16X3 = 1 };
+ * other step is FP32/FP64 as in ILT_FP32.
+ * ILT_FP64: the context also holds FP64 tables and workspaces for the _f64
+ * entry points below (N <= 2048), which run every step of the loop in FP64;
+ * the FP32 entry points work on it as on an ILT_FP32 context (without the
+ * field store). */
+enum { ILT_FP32 = 0, ILT_BF16X3 = 1, ILT_FP64 = 2 };
 
 /* ilt_optics.flags */
 enum {
@@ -112,7 +116,15 @@ typedef struct {
                                with non-negative restart, d = g + beta d_prev,
                                beta = max(0, <g, g - g_prev>/<g_prev, g_prev>)
                                (FP64 inner products, beta = 0 on the first
-                               step), CFL step on max|d|                      */
+                               step of a call), CFL step on max|d|            */
+    int iter0;              /* ilt_solve: index of the first iteration (>= 0).
+                               The loop's state is phi and this index: a solve
+                               of T1 iterations followed by one from its phi
+                               with init_mode 1 and iter0 = T1 takes the same
+                               steps as one solve of T1 + T2 iterations (the
+                               re-initialisation schedule and the trace's i
+                               column count from iter0); the conjugate
+                               directions restart at a call's first step     */
 } ilt_params;
 
 typedef struct {
@@ -139,6 +151,19 @@ int ilt_get_dims(const ilt_ctx *ctx, int *N, int *P, int *K, int *n_sets);
  * d_mask [N][N] (any real values), d_aerial [N][N] out.  Async. */
 int litho_forward(ilt_ctx *ctx, const float *d_mask, int set, float *d_aerial);
 
+/* Sec. II-A (mask of a level-set function, M = 1 where phi <= 0) and
+ * Sec. II-B: the aerial image of kernel set `set` for the binary mask
+ * [d_phi <= 0], formed as the spectrum's operand is loaded (no mask array is
+ * written).  d_phi, d_aerial [N][N].  Async. */
+int litho_forward_phi(ilt_ctx *ctx, const float *d_phi, int set, float *d_aerial);
+
+/* Sec. III-B (modulation branch target): the Heaviside map of a shifted
+ * level-set function, d_out[i] = 1 if d_phi[i] + dh >= 0 else 0, for n
+ * values (FP32 in and out; the sign of the FP32 sum is that of the exact
+ * one).  n >= 0, dh finite.  No context: async on `stream` (a hipStream_t,
+ * NULL = default). */
+int ilt_shifted_heaviside(const float *d_phi, float dh, long long n, float *d_out, void *stream);
+
 /* Sec. III-A (ILT gradient): dL/dM = 2 sum_k w_k Re T_k^H (G . T_k M) for a
  * loss with dL/dI = G on kernel set `set` (T_k M = field of kernel k).
  * d_mask, d_dL_dI [N][N] in; d_dL_dM [N][N] out (overwritten).  Async. */
@@ -159,7 +184,8 @@ int resist_loss(ilt_ctx *ctx, const float *d_aerial, const unsigned char *d_targ
  * K = (phi_xx phi_y^2 - 2 phi_x phi_y phi_xy + phi_yy phi_x^2)/(phi_x^2+phi_y^2+eps),
  * central differences with replicated borders, v = d_vel = dL/dM (descent
  * sign), m = d_mod or 1 if NULL, dt from params (CFL uses max|v|, computed on
- * the device).  d_stats: NULL or device double[4] = {max|v|, dt, flips, 0}.
+ * the device).  d_stats: NULL or device double[4] = {max|v|, dt, flips, non-finite
+ * phi values after the step}.
  * Async. */
 int levelset_step(ilt_ctx *ctx, float *d_phi, const float *d_vel, const float *d_mod,
                   const ilt_params *params, double *d_stats);
@@ -180,9 +206,28 @@ int edt_reinit(ilt_ctx *ctx, const float *d_phi, const unsigned char *d_mask,
  * and out (final phi).  h_report: final loss / L2 / PVB of [phi_T <= 0].
  * d_trace: NULL or device double [iters][8] rows
  *   {i, loss, l2, pvb, flips, max|g|, dt, device time (ns)}.
- * Synchronous: waits for the stream once at the end. */
+ * Synchronous: waits for the stream once at the end.  Returns ILT_ENUMERIC
+ * (h_report->status likewise) when a non-finite loss, gradient maximum or
+ * phi value after a step occurred at any iteration of the call. */
 int ilt_solve(ilt_ctx *ctx, const unsigned char *d_target, float *d_phi,
               const ilt_params *params, ilt_report *h_report, double *d_trace);
+
+/* The loop and its two transforms in FP64, on an ILT_FP64 context: the
+ * same steps and arguments as litho_forward, litho_adjoint and ilt_solve
+ * with FP64 images (d_mask, d_aerial, d_dL_dI, d_dL_dM, d_phi: double
+ * [N][N], 8-byte aligned) and every operation in double precision: the
+ * pruned transforms, fields and image (Sec. II-B), the resist, L_DSO, G and
+ * the print counts (Sec. III-A, II-C; corner doses and weights, sigma_z and
+ * I_th taken as the FP64 values of the FP32 parameters), the adjoint
+ * (Sec. III-A), the CFL step (Sec. III-C, dt = eta / max|g| in FP64), the
+ * level-set update (Sec. II-A, III-A) and the TSDF (phi = sqrt(D) - 1/2
+ * correctly rounded in FP64).  ilt_solve_f64 supports optimizer 0 only and
+ * no modulation map; its trace rows and report are those of ilt_solve.
+ * ILT_EINVAL on a context that is not ILT_FP64. */
+int litho_forward_f64(ilt_ctx *ctx, const double *d_mask, int set, double *d_aerial);
+int litho_adjoint_f64(ilt_ctx *ctx, const double *d_mask, const double *d_dL_dI, int set, double *d_dL_dM);
+int ilt_solve_f64(ilt_ctx *ctx, const unsigned char *d_target, double *d_phi, const ilt_params *params,
+                  ilt_report *h_report, double *d_trace);
 
 /* Sec. III-C (DevelSet): ilt_solve with the curvature term of every step
  * weighted by a modulation map, phi += dt * (v |grad phi| + lambda * m * K)

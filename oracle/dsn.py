@@ -28,7 +28,9 @@ approximated Heaviside m = H_eps(phi_m) = 1/2 (1 + (2/pi) arctan(phi_m/eps))
 with eps = 0.03, trained with L_m = sum (H_eps(phi_m) - m_gt)^2 (per sample,
 averaged over the batch) next to L_0.  m_gt is the Heaviside of the shifted
 ground-truth level set, H(phi_gt + dh) (H(z) = 1 for z >= 0), for the shift
-dh that gives the lowest L_DSO when [phi_gt + dh <= 0] is printed as a mask.
+dh whose map, used as DSO's modulation map, gives the lowest L_DSO: the DSO
+loss that the loop reaches from TSDF(target) with that map weighting its
+curvature term (see `modulation_target`).
 
 Layouts: activations [B][H][W][C] (channels last); convolution weights
 [C_out][3][3][C_in]; biases [C_out].

@@ -785,6 +785,11 @@ __global__ void k_loss_finish(const double *__restrict__ part, int n, int B, dou
 // Parameters: BF16 working copies, flipped/transposed copies for the input
 // gradient, Adam.
 // --------------------------------------------------------------------------
+__global__ void k_fill_f32(float *__restrict__ a, long long n, float v) {
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        a[i] = v;
+}
+
 __global__ void k_to_bf16(const float *__restrict__ a, long long n, __bf16 *__restrict__ b) {
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) b[i] = (__bf16)a[i];
@@ -989,6 +994,7 @@ int wgrad(dsn_ctx *c, View dz, View x, int B, int l, int layer_i, bool up) {
     const int Cin = ly.cin, Cout = ly.cout;
     if ((long long)S * Cout * 9 * Cin > c->part_cap || (long long)S * Cout > c->part_cap)
         return fail(DSN_EINVAL, "weight-gradient scratch too small");
+    if (Cout % 8 || Cout > 2048) return fail(DSN_EINVAL, "bias gradient needs C %% 8 == 0 and C <= 2048");
     const int tco = Cout % 64 == 0 ? 64 : 32, tci = Cin % 64 == 0 ? 64 : 32;
     dim3 grid(Cout / tco, Cin / tci, 9 * S);
 #define WG(A, Bq)                                                                                        \
@@ -1008,6 +1014,43 @@ int wgrad(dsn_ctx *c, View dz, View x, int B, int l, int layer_i, bool up) {
     reduce_splits(c->part, S, Cout, c->grad + ly.b_off, c->stream);
     HIPCHK(hipGetLastError());
     return DSN_OK;
+}
+
+// First layer's weight gradient: one input channel means little work per
+// pixel, so ranges of 512 pixels (up to 4096 blocks) while the partials
+// (S x C x 10 floats) fit cap; ranges of splits_for() otherwise.
+int first_layer_splits(long long npix, int C, long long cap) {
+    int S = (int)std::max(1LL, std::min(4096LL, npix / 512));
+    if ((long long)S * C * 10 > cap) S = splits_for(npix);
+    return S;
+}
+
+// dw [C][9] and db [C] of the first layer from S range partials in part
+hipError_t launch_wgrad_first(View dz, const float *x, int B, int H, int W, int S, float *part, float *dw, float *db,
+                              hipStream_t st) {
+    const long long np = (long long)B * H * W;
+    const long long pps = (np + S - 1) / S;
+    k_wgrad_first<<<S, 256, 0, st>>>(dz, x, B, H, W, pps, part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    reduce_splits(part, S, (long long)dz.C * 9, dw, st);
+    reduce_splits(part + (size_t)S * dz.C * 9, S, dz.C, db, st);
+    return hipGetLastError();
+}
+
+// Head backward over npix pixels of the features x: the input gradient dx,
+// the losses (d_loss[2], averaged over B) and the heads' weight and bias
+// gradients (gw [heads][C + 1]) from per-block partials in lpart / hpart.
+hipError_t launch_head_bwd(View x, long long npix, int B, const __bf16 *w, const __bf16 *wm, const float *out,
+                           const float *out_m, const float *tgt, const float *tgt_m, View dx, double *lpart,
+                           float *hpart, double *d_loss, float *gw, hipStream_t st) {
+    const unsigned nblk = grid1(npix);
+    k_head_bwd<<<nblk, 256, 0, st>>>(x, npix, B, w, wm, out, out_m, tgt, tgt_m, dx, lpart, hpart);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    k_loss_finish<<<1, 256, 0, st>>>(lpart, (int)nblk, B, d_loss);
+    reduce_splits(hpart, (int)nblk, (out_m ? 2 : 1) * (x.C + 1), gw, st);
+    return hipGetLastError();
 }
 
 int relu_bwd(dsn_ctx *c, View d, View y, long long npix) {
@@ -1224,24 +1267,19 @@ extern "C" int dsn_backward(dsn_ctx *c, const float *d_target, const float *d_ta
     const int C0 = c->C[0];
     const long long np0 = (long long)B * c->h[0] * c->w[0];
     const dsn_layer &hd = c->L[head_i()];
-    const unsigned nblk = grid1(np0);
     // the modulation head takes part only when its target is given; otherwise
     // its gradient is zero and L_m is reported as 0
     const int with_m = d_target_m != nullptr;
     const dsn_layer &hm = c->L[c->modulation ? head_m_i() : head_i()];
-    k_head_bwd<<<nblk, 256, 0, c->stream>>>(view(c->dec_b[0], C0, C0), np0, B, c->pb + hd.w_off, c->pb + hm.w_off,
-                                            c->out, with_m ? c->out_m : nullptr, d_target, d_target_m,
-                                            view(c->gA[0], C0, C0), c->lpart, c->hpart);
-    HIPCHK(hipGetLastError());
-    k_loss_finish<<<1, 256, 0, c->stream>>>(c->lpart, (int)nblk, B, d_loss);
-    HIPCHK(hipGetLastError());
     // hpart [nblk][heads][C0 + 1] -> each head's weights then bias; the two
     // heads are adjacent in the flat vector
-    const int nh = with_m ? 2 : 1;
-    reduce_splits(c->hpart, (int)nblk, nh * (C0 + 1), c->grad + hd.w_off, c->stream);
-    HIPCHK(hipGetLastError());
-    if (c->modulation && !with_m)
-        HIPCHK(hipMemsetAsync(c->grad + hm.w_off, 0, (C0 + 1) * sizeof(float), c->stream));
+    HIPCHK(launch_head_bwd(view(c->dec_b[0], C0, C0), np0, B, c->pb + hd.w_off, c->pb + hm.w_off, c->out,
+                           with_m ? c->out_m : nullptr, d_target, d_target_m, view(c->gA[0], C0, C0), c->lpart,
+                           c->hpart, d_loss, c->grad + hd.w_off, c->stream));
+    if (c->modulation && !with_m) {
+        k_fill_f32<<<1, 256, 0, c->stream>>>(c->grad + hm.w_off, C0 + 1, 0.f);
+        HIPCHK(hipGetLastError());
+    }
     // decoder, bottom-up in the backward order
     for (int l = 0; l <= NL - 2; ++l) {
         const int C = c->C[l], C1 = c->C[l + 1];
@@ -1293,18 +1331,9 @@ extern "C" int dsn_backward(dsn_ctx *c, const float *d_target, const float *d_ta
             if ((r = conv(c, ga, B, l, enc_a(l), false, true, 0, view(c->gA[l], Cp, Cp)))) return r;
         } else {
             const dsn_layer &ly = c->L[enc_a(0)];
-            // one input channel: little work per pixel, so ranges of 512
-            // pixels (up to 4096 blocks) while the partials fit the buffer
-            int S = (int)std::max(1LL, std::min(4096LL, np / 512));
-            if ((long long)S * ly.cout * 10 > c->part_cap) S = splits_for(np);
-            const long long pps = (np + S - 1) / S;
-            k_wgrad_first<<<S, 256, 0, c->stream>>>(ga, c->x_in, B, c->h[0], c->w[0], pps, c->part);
-            HIPCHK(hipGetLastError());
-            const long long nw = (long long)ly.cout * 9;
-            reduce_splits(c->part, S, nw, c->grad + ly.w_off, c->stream);
-            HIPCHK(hipGetLastError());
-            reduce_splits(c->part + (size_t)S * ly.cout * 9, S, ly.cout, c->grad + ly.b_off, c->stream);
-            HIPCHK(hipGetLastError());
+            const int S = first_layer_splits(np, ly.cout, c->part_cap);
+            HIPCHK(launch_wgrad_first(ga, c->x_in, B, c->h[0], c->w[0], S, c->part, c->grad + ly.w_off,
+                                      c->grad + ly.b_off, c->stream));
         }
     }
     if (d_grad)
@@ -1370,7 +1399,9 @@ int op_conv(View x, int N, int H, int W, int Cin, bool up, const __bf16 *w, cons
 }
 
 int op_check(const void *a, const void *b, int N, int H, int W, int Cin, int Cout, bool up) {
-    if (!a || !b) return fail(DSN_EINVAL, "NULL buffer");
+    int r;
+    // the kernels read both operands with 16-byte vector loads
+    if ((r = check_ptr(a, "first operand")) || (r = check_ptr(b, "second operand"))) return r;
     if (N < 1 || H < 1 || W < 1) return fail(DSN_EINVAL, "bad N, H, W");
     if (up && (H % 2 || W % 2)) return fail(DSN_EINVAL, "up needs even H and W");
     if (Cin % 32 || Cout % 32 || Cin < 32 || Cout < 32 || Cin > 1024 || Cout > 1024)
@@ -1440,5 +1471,113 @@ extern "C" int dsn_op_conv3x3_wgrad(const void *d_dz, const void *d_x, int N, in
     (void)hipStreamSynchronize(st);
     (void)hipFree(part);
     if (e != hipSuccess) return fail(DSN_EDEVICE, "weight gradient: %s", hipGetErrorString(e));
+    return DSN_OK;
+}
+
+namespace {
+
+bool c_ok_first(int C) { return C >= 8 && C <= 64 && C % 8 == 0 && 256 % C == 0; }
+
+}  // namespace
+
+extern "C" int dsn_op_conv_first(const float *d_x, int N, int H, int W, const void *d_w, const float *d_b, int Cout,
+                                 void *d_y, void *stream) {
+    int r;
+    if ((r = check_ptr(d_x, "d_x")) || (r = check_ptr(d_w, "d_w")) || (r = check_ptr(d_b, "d_b")) ||
+        (r = check_ptr(d_y, "d_y")))
+        return r;
+    if (N < 1 || H < 1 || W < 1) return fail(DSN_EINVAL, "bad N, H, W");
+    if (Cout < 8 || Cout > 1024 || Cout % 8) return fail(DSN_EINVAL, "Cout must be a multiple of 8 in [8, 1024]");
+    const long long npix = (long long)N * H * W;
+    k_conv_first<<<grid1(npix * (Cout / 8)), 256, 0, static_cast<hipStream_t>(stream)>>>(
+        d_x, N, H, W, (const __bf16 *)d_w, d_b, View{(__bf16 *)d_y, Cout, Cout});
+    HIPCHK(hipGetLastError());
+    return DSN_OK;
+}
+
+extern "C" int dsn_op_wgrad_first(const void *d_dz, const float *d_x, int N, int H, int W, int C, float *d_dw,
+                                  float *d_db, void *stream) {
+    int r;
+    if ((r = check_ptr(d_dz, "d_dz")) || (r = check_ptr(d_x, "d_x")) || (r = check_ptr(d_dw, "d_dw")) ||
+        (r = check_ptr(d_db, "d_db")))
+        return r;
+    if (N < 1 || H < 1 || W < 1) return fail(DSN_EINVAL, "bad N, H, W");
+    if (!c_ok_first(C)) return fail(DSN_EINVAL, "C must be 8, 16, 32 or 64");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const long long npix = (long long)N * H * W;
+    const int S = first_layer_splits(npix, C, 1LL << 62);
+    float *part = nullptr;
+    HIPCHK(hipMalloc(&part, (size_t)S * C * 10 * sizeof(float)));
+    hipError_t e = launch_wgrad_first(View{(__bf16 *)d_dz, C, C}, d_x, N, H, W, S, part, d_dw, d_db, st);
+    (void)hipStreamSynchronize(st);
+    (void)hipFree(part);
+    if (e != hipSuccess) return fail(DSN_EDEVICE, "first-layer weight gradient: %s", hipGetErrorString(e));
+    return DSN_OK;
+}
+
+extern "C" int dsn_op_head_bwd(const void *d_x, long long npix, int C, int B, const void *d_w, const void *d_wm,
+                               const float *d_out, const float *d_out_m, const float *d_t, const float *d_t_m,
+                               void *d_dx, double *d_loss, float *d_gw, void *stream) {
+    int r;
+    if ((r = check_ptr(d_x, "d_x")) || (r = check_ptr(d_w, "d_w")) || (r = check_ptr(d_out, "d_out")) ||
+        (r = check_ptr(d_t, "d_t")) || (r = check_ptr(d_dx, "d_dx")) || (r = check_ptr(d_loss, "d_loss")) ||
+        (r = check_ptr(d_gw, "d_gw")))
+        return r;
+    const int nm = (d_wm != nullptr) + (d_out_m != nullptr) + (d_t_m != nullptr);
+    if (nm != 0 && nm != 3) return fail(DSN_EINVAL, "d_wm, d_out_m and d_t_m are given together or not at all");
+    if (nm == 3 && ((r = check_ptr(d_wm, "d_wm")) || (r = check_ptr(d_out_m, "d_out_m")) ||
+                    (r = check_ptr(d_t_m, "d_t_m"))))
+        return r;
+    if (npix < 1 || B < 1) return fail(DSN_EINVAL, "npix and B must be >= 1");
+    if (C < 8 || C > 64 || C % 8) return fail(DSN_EINVAL, "C must be a multiple of 8 in [8, 64]");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const long long nblk = grid1(npix);
+    double *lpart = nullptr;
+    float *hpart = nullptr;
+    HIPCHK(hipMalloc(&lpart, (size_t)nblk * 2 * sizeof(double)));
+    hipError_t e = hipMalloc(&hpart, (size_t)nblk * 2 * (C + 1) * sizeof(float));
+    if (e == hipSuccess)
+        e = launch_head_bwd(View{(__bf16 *)d_x, C, C}, npix, B, (const __bf16 *)d_w, (const __bf16 *)d_wm, d_out,
+                            d_out_m, d_t, d_t_m, View{(__bf16 *)d_dx, C, C}, lpart, hpart, d_loss, d_gw, st);
+    (void)hipStreamSynchronize(st);
+    (void)hipFree(lpart);
+    if (hpart) (void)hipFree(hpart);
+    if (e != hipSuccess) return fail(DSN_EDEVICE, "head backward: %s", hipGetErrorString(e));
+    return DSN_OK;
+}
+
+extern "C" int dsn_op_maxpool2_bwd(const void *d_x, int N, int H, int W, int C, const void *d_dy, void *d_dx,
+                                   void *stream) {
+    int r;
+    if ((r = check_ptr(d_x, "d_x")) || (r = check_ptr(d_dy, "d_dy")) || (r = check_ptr(d_dx, "d_dx"))) return r;
+    if (N < 1 || H < 2 || W < 2 || H % 2 || W % 2) return fail(DSN_EINVAL, "need N >= 1 and even H, W >= 2");
+    if (C < 8 || C % 8 || C > 2048) return fail(DSN_EINVAL, "C must be a multiple of 8 in [8, 2048]");
+    const long long n = (long long)N * (H / 2) * (W / 2) * (C / 8);
+    k_maxpool_bwd<<<grid1(n), 256, 0, static_cast<hipStream_t>(stream)>>>(
+        View{(__bf16 *)d_x, C, C}, N, H, W, View{(__bf16 *)d_dy, C, C}, View{(__bf16 *)d_dx, C, C});
+    HIPCHK(hipGetLastError());
+    return DSN_OK;
+}
+
+extern "C" int dsn_op_upsample2_bwd(const void *d_dy, int N, int H, int W, int C, void *d_dx, void *stream) {
+    int r;
+    if ((r = check_ptr(d_dy, "d_dy")) || (r = check_ptr(d_dx, "d_dx"))) return r;
+    if (N < 1 || H < 2 || W < 2 || H % 2 || W % 2) return fail(DSN_EINVAL, "need N >= 1 and even H, W >= 2");
+    if (C < 8 || C % 8 || C > 2048) return fail(DSN_EINVAL, "C must be a multiple of 8 in [8, 2048]");
+    const long long n = (long long)N * (H / 2) * (W / 2) * (C / 8);
+    k_upsample_bwd<<<grid1(n), 256, 0, static_cast<hipStream_t>(stream)>>>(View{(__bf16 *)d_dy, C, C}, N, H, W,
+                                                                            View{(__bf16 *)d_dx, C, C});
+    HIPCHK(hipGetLastError());
+    return DSN_OK;
+}
+
+extern "C" int dsn_op_relu_bwd(void *d_d, const void *d_y, long long npix, int C, void *stream) {
+    int r;
+    if ((r = check_ptr(d_d, "d_d")) || (r = check_ptr(d_y, "d_y"))) return r;
+    if (npix < 1) return fail(DSN_EINVAL, "npix must be >= 1");
+    if (C < 8 || C % 8 || C > 2048) return fail(DSN_EINVAL, "C must be a multiple of 8 in [8, 2048]");
+    k_relu_bwd<<<grid1(npix * (C / 8)), 256, 0, static_cast<hipStream_t>(stream)>>>(
+        View{(__bf16 *)d_d, C, C}, View{(__bf16 *)d_y, C, C}, npix);
+    HIPCHK(hipGetLastError());
     return DSN_OK;
 }

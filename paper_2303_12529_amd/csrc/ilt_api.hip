@@ -98,8 +98,10 @@ void free_ctx(ilt_ctx *c) {
     free_events(c);
     free_graph(c);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
-    void *ptrs[] = {c->tl, c->tb, c->ta4, c->ar, c->ai, c->H, c->sw, c->coef, c->tlhl, c->tbhl, c->Yhl, c->Spart, c->S, c->Est, c->Y, c->Tg,
-                    c->I, c->G, c->g, c->phi2, c->Wpart, c->W, c->edtg, c->colbits, c->part, c->scal,
+    void *ptrs[] = {c->A64, c->H64, c->w64, c->T64, c->S64, c->Y64, c->I64, c->G64, c->Q64, c->W64, c->Z64, c->g64,
+                    c->phi64, c->part64,
+                    c->tl, c->tb, c->ta4, c->ar, c->ai, c->H, c->sw, c->coef, c->tlhl, c->tbhl, c->Yhl, c->Spart, c->S, c->Est, c->Y, c->Tg,
+                    c->I, c->G, c->g, c->phi2, c->Wpart, c->W, c->edt_scratch, c->part, c->scal,
                     c->tbQ, c->arQ, c->aiQ, c->Ghat, c->Ugw, c->Vpart, c->g_prev, c->dcg};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
@@ -134,6 +136,7 @@ int check_params(const ilt_ctx *c, const ilt_params *p, bool need_loop) {
     if (need_loop) {
         if (p->iters < 0) return fail(ILT_EINVAL, "iters < 0");
         if (p->reinit_every < 0) return fail(ILT_EINVAL, "reinit_every < 0");
+        if (p->iter0 < 0) return fail(ILT_EINVAL, "iter0 < 0");
     }
     if (p->dt_mode != 0 && p->dt_mode != 1) return fail(ILT_EINVAL, "dt_mode must be 0 or 1");
     if (!std::isfinite(p->eta) || p->eta < 0.f) return fail(ILT_EINVAL, "eta must be finite and >= 0");
@@ -191,7 +194,8 @@ size_t n_image_blocks(const ilt_ctx *c) { return (size_t)(c->Np / 64) * (c->Np /
 size_t part_step_off(const ilt_ctx *c) {
     return part_max_off(c) + std::max<size_t>(n_image_blocks(c), (size_t)gradmax_blocks(c));
 }
-size_t part_cg_off(const ilt_ctx *c) { return part_step_off(c) + (size_t)step_blocks(c); }
+// level-set step partials: {flips, non-finite count} per block
+size_t part_cg_off(const ilt_ctx *c) { return part_step_off(c) + 2 * (size_t)step_blocks(c); }
 size_t part_total(const ilt_ctx *c) { return part_cg_off(c) + 3 * (size_t)gradmax_blocks(c); }
 
 }  // namespace
@@ -221,8 +225,10 @@ extern "C" int ilt_create(ilt_ctx **out, const ilt_optics *o, int max_batch, voi
     if (2 * P - 1 > N) return fail(ILT_EINVAL, "window 2P-1=%d exceeds N=%d", 2 * P - 1, N);
     if (K < 1 || K > ILT_MAX_K) return fail(ILT_EINVAL, "K=%d outside [1, %d]", K, ILT_MAX_K);
     if (ns < 1 || ns > ILT_MAX_SETS) return fail(ILT_EINVAL, "n_sets=%d outside [1, %d]", ns, ILT_MAX_SETS);
-    if (o->precision != ILT_FP32 && o->precision != ILT_BF16X3)
+    if (o->precision != ILT_FP32 && o->precision != ILT_BF16X3 && o->precision != ILT_FP64)
         return fail(ILT_EUNSUPPORTED, "precision %d not built", o->precision);
+    if (o->precision == ILT_FP64 && N > ILT_FP64_MAX_N)
+        return fail(ILT_EUNSUPPORTED, "ILT_FP64 contexts are built for N <= %d", ILT_FP64_MAX_N);
     if (o->flags & ~(ILT_FLAG_RECOMPUTE_FIELDS | ILT_FLAG_GWINDOW_ADJOINT))
         return fail(ILT_EINVAL, "unknown flags 0x%x", o->flags);
     if (!o->h_kernels || !o->h_weights) return fail(ILT_EINVAL, "kernels or weights are null");
@@ -307,8 +313,40 @@ extern "C" int ilt_create(ilt_ctx **out, const ilt_optics *o, int max_batch, voi
     ALLOC(sw, sw.size());
     ALLOC(Spart, (size_t)(Np / 16) * 4 * (c->gwin ? (size_t)c->Q * c->Q * ns : (size_t)P * P));
     const bool b3 = o->precision == ILT_BF16X3;
-    if (!b3 && !c->gwin && !(o->flags & ILT_FLAG_RECOMPUTE_FIELDS))
+    const bool f64 = o->precision == ILT_FP64;
+    if (!b3 && !f64 && !c->gwin && !(o->flags & ILT_FLAG_RECOMPUTE_FIELDS))
         ALLOC(Est, (size_t)ns * K * (Np / 16) * (Np / 16) * 512);
+    std::vector<double2> A64h, H64h;
+    std::vector<double> w64h;
+    if (f64) {
+        A64h.resize((size_t)P * N);
+        for (int a = 0; a < P; ++a) {
+            const long long f = a - (P - 1) / 2;
+            for (int x = 0; x < N; ++x) {
+                long long ph = (f * x) % N;
+                if (ph < 0) ph += N;
+                const double ang = -2.0 * M_PI * (double)ph / (double)N;
+                A64h[(size_t)a * N + x] = make_double2(std::cos(ang), std::sin(ang));
+            }
+        }
+        H64h.resize((size_t)ns * K * P * P);
+        for (size_t i = 0; i < H64h.size(); ++i) H64h[i] = make_double2(o->h_kernels[2 * i], o->h_kernels[2 * i + 1]);
+        w64h.assign(o->h_weights, o->h_weights + (size_t)ns * K);
+        ALLOC(A64, A64h.size());
+        ALLOC(H64, H64h.size());
+        ALLOC(w64, w64h.size());
+        ALLOC(T64, (size_t)N * P);
+        ALLOC(S64, (size_t)P * P);
+        ALLOC(Y64, (size_t)ns * K * P * N);
+        ALLOC(I64, (size_t)ns * N * N);
+        ALLOC(G64, (size_t)ns * N * N);
+        ALLOC(Q64, (size_t)ns * K * N * P);
+        ALLOC(W64, (size_t)P * P);
+        ALLOC(Z64, (size_t)P * N);
+        ALLOC(g64, (size_t)N * N);
+        ALLOC(phi64, (size_t)N * N);
+        ALLOC(part64, (size_t)4 * 2048 + 3 * (size_t)N * ((N + 255) / 256));
+    }
     std::vector<float> tbQ, arQ, aiQ;
     if (c->gwin) {
         // tables of the difference window: f_a = a - (P - 1), a in [0, Q)
@@ -365,8 +403,11 @@ extern "C" int ilt_create(ilt_ctx **out, const ilt_optics *o, int max_batch, voi
     c->n_wpart = std::max(ns * ((N + 31) / 32) * ((K + 3) / 4) * ILT_ST_MAX_XSPLIT, adjoint_b3_max_parts(c, ns)) * P *
                  P * 2;
     ALLOC(Wpart, (size_t)c->n_wpart);
-    ALLOC(edtg, (size_t)N * N);
-    ALLOC(colbits, (size_t)((N + 31) / 32) * N);
+    if (e == hipSuccess) {
+        unsigned char *es = nullptr;
+        e = dalloc(&es, edt_scratch_bytes(N));
+        c->edt_scratch = es;
+    }
     c->n_part = (int)part_total(c);
     ALLOC(part, (size_t)c->n_part);
     ALLOC(scal, (size_t)SC_COUNT);
@@ -383,6 +424,11 @@ extern "C" int ilt_create(ilt_ctx **out, const ilt_optics *o, int max_batch, voi
     if (e == hipSuccess) e = hipMemcpy(c->H, H.data(), H.size() * 8, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(c->coef, coef.data(), coef.size() * 8, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(c->sw, sw.data(), sw.size() * 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess && f64) {
+        e = hipMemcpy(c->A64, A64h.data(), A64h.size() * sizeof(double2), hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(c->H64, H64h.data(), H64h.size() * sizeof(double2), hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(c->w64, w64h.data(), w64h.size() * sizeof(double), hipMemcpyHostToDevice);
+    }
     if (e == hipSuccess && c->gwin) {
         e = hipMemcpy(c->tbQ, tbQ.data(), tbQ.size() * 4, hipMemcpyHostToDevice);
         if (e == hipSuccess) e = hipMemcpy(c->arQ, arQ.data(), arQ.size() * 4, hipMemcpyHostToDevice);
@@ -460,6 +506,33 @@ extern "C" int litho_forward(ilt_ctx *c, const float *d_mask, int set, float *d_
     } else {
         HIPCHK(launch_image_to(c, set, set + 1, d_aerial, 0));
     }
+    return ILT_OK;
+}
+
+extern "C" int litho_forward_phi(ilt_ctx *c, const float *d_phi, int set, float *d_aerial) {
+    int r;
+    if ((r = check_ctx(c))) return r;
+    if ((r = check_ptr(d_phi, "d_phi"))) return r;
+    if ((r = check_ptr(d_aerial, "d_aerial"))) return r;
+    if (set < 0 || set >= c->n_sets) return fail(ILT_EINVAL, "set %d outside [0, %d)", set, c->n_sets);
+    HIPCHK(launch_spectrum(c, d_phi, 1));
+    HIPCHK(launch_make_Y(c, set, set + 1));
+    if (c->precision == ILT_BF16X3) {
+        HIPCHK(launch_image_b3(c, set, set + 1, d_aerial));
+    } else {
+        HIPCHK(launch_image_to(c, set, set + 1, d_aerial, 0));
+    }
+    return ILT_OK;
+}
+
+extern "C" int ilt_shifted_heaviside(const float *d_phi, float dh, long long n, float *d_out, void *stream) {
+    int r;
+    if ((r = check_ptr(d_phi, "d_phi"))) return r;
+    if ((r = check_ptr(d_out, "d_out"))) return r;
+    if (n < 0) return fail(ILT_EINVAL, "n < 0");
+    if (!std::isfinite(dh)) return fail(ILT_EINVAL, "dh is not finite");
+    if (n == 0) return ILT_OK;
+    HIPCHK(launch_heaviside_shift(d_phi, dh, (size_t)n, d_out, static_cast<hipStream_t>(stream)));
     return ILT_OK;
 }
 
@@ -554,12 +627,16 @@ int enqueue_solve(ilt_ctx *c, const unsigned char *d_target, float *d_phi, const
     const int stored = c->Est != nullptr && c->store_fields;
     const bool b3 = c->precision == ILT_BF16X3;
     c->n_ev = 0;
+    HIPCHK(launch_set_scal(c, SC_BAD, 0.0));
     if (p->init_mode == 0) {
         PhaseTimer t(c, 7);
         HIPCHK(launch_edt(c, nullptr, d_target, d_phi, nullptr, p->d_lower, p->d_upper));
     }
     float *cur = d_phi, *nxt = c->phi2;
     for (int i = 0; i < p->iters; ++i) {
+        // the loop's own iteration index: a resumed solve continues the
+        // re-initialisation schedule and the trace numbering of the first
+        const int gi = p->iter0 + i;
         {
             PhaseTimer t(c, 0);
             HIPCHK(launch_spectrum(c, cur, 1));
@@ -601,9 +678,9 @@ int enqueue_solve(ilt_ctx *c, const unsigned char *d_target, float *d_phi, const
             HIPCHK(launch_levelset(c, cur, p->optimizer == 1 ? c->dcg : c->g, d_mod, p->lambda, p->eps_kappa,
                                    c->scal, nxt, ps));
             HIPCHK(launch_finish_step(c, ps, step_blocks(c), c->scal, nullptr,
-                                      d_trace ? d_trace + (size_t)i * ILT_TRACE_W : nullptr, i));
+                                      d_trace ? d_trace + (size_t)i * ILT_TRACE_W : nullptr, gi));
         }
-        if (p->reinit_every > 0 && (i + 1) % p->reinit_every == 0) {
+        if (p->reinit_every > 0 && (gi + 1) % p->reinit_every == 0) {
             PhaseTimer t(c, 7);
             HIPCHK(launch_edt(c, nxt, nullptr, nxt, nullptr, p->d_lower, p->d_upper));
         }
@@ -691,14 +768,113 @@ int solve(ilt_ctx *c, const unsigned char *d_target, float *d_phi, const float *
         h_report->l2 = (long long)sc[SC_L2];
         h_report->pvb = (long long)sc[SC_PVB];
         h_report->flips = (long long)sc[SC_FLIPS];
-        h_report->status = (sc[SC_NONFIN] > 0.0 || !std::isfinite(sc[SC_LOSS])) ? ILT_ENUMERIC : ILT_OK;
+        h_report->status = (sc[SC_BAD] > 0.0 || !std::isfinite(sc[SC_LOSS])) ? ILT_ENUMERIC : ILT_OK;
     }
-    if (sc[SC_NONFIN] > 0.0 || !std::isfinite(sc[SC_LOSS]))
-        return fail(ILT_ENUMERIC, "non-finite loss or gradient in the loop");
+    if (sc[SC_BAD] > 0.0 || !std::isfinite(sc[SC_LOSS]))
+        return fail(ILT_ENUMERIC, "non-finite loss, gradient or phi in the loop (%.0f values)", sc[SC_BAD]);
     return ILT_OK;
 }
 
 }  // namespace
+
+// ---------------------------------------------------------------- FP64 form
+
+namespace {
+
+int check_f64(const ilt_ctx *c) {
+    int r;
+    if ((r = check_ctx(c))) return r;
+    if (c->precision != ILT_FP64) return fail(ILT_EINVAL, "the _f64 entry points need an ILT_FP64 context");
+    return ILT_OK;
+}
+
+// partial-buffer regions of the FP64 form (doubles)
+double *p64_resist(ilt_ctx *c) { return c->part64; }
+double *p64_max(ilt_ctx *c) { return c->part64 + 4 * 2048; }
+double *p64_step(ilt_ctx *c) { return c->part64 + 4 * 2048 + (size_t)c->N * rowblk64(c); }
+
+}  // namespace
+
+extern "C" int litho_forward_f64(ilt_ctx *c, const double *d_mask, int set, double *d_aerial) {
+    int r;
+    if ((r = check_f64(c))) return r;
+    if ((r = check_ptr(d_mask, "d_mask", 8)) || (r = check_ptr(d_aerial, "d_aerial", 8))) return r;
+    if (set < 0 || set >= c->n_sets) return fail(ILT_EINVAL, "set %d outside [0, %d)", set, c->n_sets);
+    HIPCHK(launch64_spectrum(c, d_mask, 0));
+    HIPCHK(launch64_image(c, set, set + 1, d_aerial));
+    return ILT_OK;
+}
+
+extern "C" int litho_adjoint_f64(ilt_ctx *c, const double *d_mask, const double *d_G, int set, double *d_out) {
+    int r;
+    if ((r = check_f64(c))) return r;
+    if ((r = check_ptr(d_mask, "d_mask", 8)) || (r = check_ptr(d_G, "d_dL_dI", 8)) ||
+        (r = check_ptr(d_out, "d_dL_dM", 8)))
+        return r;
+    if (set < 0 || set >= c->n_sets) return fail(ILT_EINVAL, "set %d outside [0, %d)", set, c->n_sets);
+    HIPCHK(launch64_spectrum(c, d_mask, 0));
+    HIPCHK(launch64_make_Y(c, set, set + 1));
+    HIPCHK(launch64_adjoint(c, d_G, set, set + 1));
+    hipError_t e = hipSuccess;
+    (void)launch64_gradient(c, d_out, p64_max(c), &e);
+    HIPCHK(e);
+    return ILT_OK;
+}
+
+extern "C" int ilt_solve_f64(ilt_ctx *c, const unsigned char *d_target, double *d_phi, const ilt_params *p,
+                             ilt_report *h_report, double *d_trace) {
+    int r;
+    if ((r = check_f64(c))) return r;
+    if ((r = check_ptr(d_target, "d_target", 1)) || (r = check_ptr(d_phi, "d_phi", 8))) return r;
+    if (d_trace && !aligned(d_trace, 8)) return fail(ILT_EINVAL, "d_trace is not 8-byte aligned");
+    if ((r = check_params(c, p, true))) return r;
+    if (p->init_mode != 0 && p->init_mode != 1) return fail(ILT_EINVAL, "init_mode must be 0 or 1");
+    if (p->optimizer != 0) return fail(ILT_EUNSUPPORTED, "ilt_solve_f64 runs the gradient optimizer only");
+    int slo, shi;
+    used_set_range(p, &slo, &shi);
+    const size_t npix = (size_t)c->N * c->N;
+    HIPCHK(launch_set_scal(c, SC_BAD, 0.0));
+    if (p->init_mode == 0) HIPCHK(launch_edt64(c, nullptr, d_target, d_phi, nullptr, p->d_lower, p->d_upper));
+    double *cur = d_phi, *nxt = c->phi64;
+    hipError_t e = hipSuccess;
+    for (int i = 0; i < p->iters; ++i) {
+        const int gi = p->iter0 + i;
+        HIPCHK(launch64_spectrum(c, cur, 1));
+        HIPCHK(launch64_image(c, slo, shi, c->I64 + (size_t)slo * npix));
+        HIPCHK(launch64_resist(c, c->I64, d_target, p, c->G64, p64_resist(c)));
+        HIPCHK(launch_finish_resist(c, p64_resist(c), resist64_blocks(c), c->scal, nullptr));
+        HIPCHK(launch64_adjoint(c, c->G64 + (size_t)slo * npix, slo, shi));
+        const int nmax = launch64_gradient(c, c->g64, p64_max(c), &e);
+        HIPCHK(e);
+        HIPCHK(launch64_finish_dt(c, p64_max(c), nmax, p));
+        const int nstep = launch64_levelset(c, cur, c->g64, p, nxt, p64_step(c), &e);
+        HIPCHK(e);
+        HIPCHK(launch_finish_step(c, p64_step(c), nstep, c->scal, nullptr,
+                                  d_trace ? d_trace + (size_t)i * ILT_TRACE_W : nullptr, gi));
+        if (p->reinit_every > 0 && (gi + 1) % p->reinit_every == 0)
+            HIPCHK(launch_edt64(c, nxt, nullptr, nxt, nullptr, p->d_lower, p->d_upper));
+        std::swap(cur, nxt);
+    }
+    if (cur != d_phi) HIPCHK(launch64_copy(c, d_phi, cur, npix));
+    HIPCHK(launch64_spectrum(c, d_phi, 1));
+    HIPCHK(launch64_image(c, slo, shi, c->I64 + (size_t)slo * npix));
+    HIPCHK(launch64_resist(c, c->I64, d_target, p, c->G64, p64_resist(c)));
+    HIPCHK(launch_finish_resist(c, p64_resist(c), resist64_blocks(c), c->scal, nullptr));
+    double sc[SC_COUNT];
+    HIPCHK(hipMemcpyAsync(sc, c->scal, sizeof sc, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    const bool bad = sc[SC_BAD] > 0.0 || !std::isfinite(sc[SC_LOSS]);
+    if (h_report) {
+        h_report->iters_done = p->iters;
+        h_report->loss = sc[SC_LOSS];
+        h_report->l2 = (long long)sc[SC_L2];
+        h_report->pvb = (long long)sc[SC_PVB];
+        h_report->flips = (long long)sc[SC_FLIPS];
+        h_report->status = bad ? ILT_ENUMERIC : ILT_OK;
+    }
+    if (bad) return fail(ILT_ENUMERIC, "non-finite loss, gradient or phi in the FP64 loop");
+    return ILT_OK;
+}
 
 extern "C" int ilt_solve(ilt_ctx *c, const unsigned char *d_target, float *d_phi, const ilt_params *p,
                          ilt_report *h_report, double *d_trace) {
@@ -1180,7 +1356,7 @@ extern "C" int ilt_solve_batch(ilt_batch *b, int n, const ilt_clip *clips, ilt_r
     int status = ILT_OK;
     for (int i = 0; i < n; ++i) {
         const double *sc = b->h_reports + (size_t)i * SC_COUNT;
-        const bool bad = sc[SC_NONFIN] > 0.0 || !std::isfinite(sc[SC_LOSS]);
+        const bool bad = sc[SC_BAD] > 0.0 || !std::isfinite(sc[SC_LOSS]);
         if (h_reports) {
             h_reports[i].iters_done = clips[i].params.iters;
             h_reports[i].loss = sc[SC_LOSS];

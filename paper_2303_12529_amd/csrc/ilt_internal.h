@@ -83,6 +83,20 @@ struct ilt_ctx {
     double2 *Vpart;    // [gw_groups][n_sets][P][P] partial sums of W over ranges of window rows
     int gw_groups;     // ranges the window sum is split into (grid.y of the correlation GEMM)
 
+    // FP64 form (ILT_FP64 contexts only)
+    double2 *A64;      // [P][N]      A in FP64
+    double2 *H64;      // [n_sets][K][P][P]
+    double *w64;       // [n_sets][K]
+    double2 *T64;      // [N][P]      rows of the spectrum (and scratch of the column transform)
+    double2 *S64;      // [P][P]
+    double2 *Y64;      // [n_sets][K][P][N]  N^-2 (H . S) conj(A)
+    double *I64, *G64; // [n_sets][N][N]
+    double2 *Q64;      // [n_sets][K][N][P]  adjoint row transforms
+    double2 *W64;      // [P][P]
+    double2 *Z64;      // [P][N]
+    double *g64, *phi64; // [N][N] gradient, the step's output
+    double *part64;    // partials: resist [4 x 2048], max |g| and the step [3 x rows x row blocks]
+
     // workspaces
     float2 *Spart;     // spectrum band partials [Np/16][column ranges][P][P] (G-window: [set][Np/16][ranges][Q][Q])
     float2 *S;         // [P][P]
@@ -97,8 +111,10 @@ struct ilt_ctx {
     float *phi2;       // [N][N]
     float *Wpart;      // adjoint partials
     float2 *W;         // [P][P]
-    uint32_t *edtg;    // [N][N] packed column distances
-    uint32_t *colbits; // [ceil(N/32)][N] class bits, 32 rows per word
+    // EDT scratch (edt_scratch_bytes): class bits [W][N] u32 (W = ceil(N/32),
+    // 32 rows per word), then the nearest class rows above / below each
+    // word, [4][W][N] int16
+    void *edt_scratch;
     double *part;      // reduction partials (doubles)
     double *scal;      // device scalars (see SC_* below)
     int n_part;        // capacity of part (doubles)
@@ -131,6 +147,9 @@ struct ilt_ctx {
 enum {
     SC_LOSS = 0, SC_L2 = 1, SC_PVB = 2, SC_NONFIN = 3,
     SC_MV = 4, SC_DT = 5, SC_FLIPS = 6, SC_ITER = 7, SC_BETA = 8,
+    // non-finite values met anywhere in the current solve (loss, gradient,
+    // phi after a step); zeroed when a solve starts, never reset inside it
+    SC_BAD = 9,
     SC_COUNT = 16
 };
 
@@ -208,8 +227,34 @@ hipError_t launch_finish_step(ilt_ctx *c, const double *part, int nblk, double *
                               double *trace_row, int iter);
 hipError_t launch_edt(ilt_ctx *c, const float *phi, const uint8_t *mask, float *phi_out, int *sqdist,
                       float d_lower, float d_upper);
+// the EDT on any stream with a caller-given scratch of edt_scratch_bytes(N)
+size_t edt_scratch_bytes(int N);
+hipError_t launch_edt_raw(hipStream_t st, int N, const float *phi, const uint8_t *mask, float *phi_out, int *sqdist,
+                          float d_lower, float d_upper, void *scratch);
 hipError_t launch_copy(ilt_ctx *c, float *dst, const float *src, size_t n);
+// out = H(phi + dh) (0/1) over n values, on stream st
+hipError_t launch_heaviside_shift(const float *phi, float dh, size_t n, float *out, hipStream_t st);
+// scal[slot] = v on the context's stream (a kernel, so that it may be captured)
+hipError_t launch_set_scal(ilt_ctx *c, int slot, double v);
 hipError_t launch_fill(ilt_ctx *c, float *dst, float v, size_t n);
+
+// ---- FP64 form (k_fp64.hip) ----
+int resist64_blocks(const ilt_ctx *c);
+int rowblk64(const ilt_ctx *c);
+hipError_t launch64_spectrum(ilt_ctx *c, const double *src, int src_is_phi);
+hipError_t launch64_make_Y(ilt_ctx *c, int s0, int s1);
+hipError_t launch64_image(ilt_ctx *c, int s0, int s1, double *I);
+hipError_t launch64_resist(ilt_ctx *c, const double *I, const uint8_t *target, const ilt_params *p, double *G,
+                           double *part);
+hipError_t launch64_adjoint(ilt_ctx *c, const double *G, int s0, int s1);
+int launch64_gradient(ilt_ctx *c, double *g, double *maxpart, hipError_t *err);
+hipError_t launch64_finish_dt(ilt_ctx *c, const double *part, int nblk, const ilt_params *p);
+int launch64_levelset(ilt_ctx *c, const double *phi, const double *vel, const ilt_params *p, double *out,
+                      double *part, hipError_t *err);
+hipError_t launch64_copy(ilt_ctx *c, double *dst, const double *src, size_t n);
+hipError_t launch_edt64(ilt_ctx *c, const double *phi, const uint8_t *mask, double *phi_out, int *sqdist,
+                        float d_lower, float d_upper);
+#define ILT_FP64_MAX_N 2048
 
 // ---- full-layout tiling and shot count (k_layout.hip) ----
 // tiles per column / row of the layout grid (cores of C = N - 2 halo pixels)

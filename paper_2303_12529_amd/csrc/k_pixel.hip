@@ -230,6 +230,7 @@ __global__ __launch_bounds__(RB) void k_finish_resist(const double *__restrict__
         scal[SC_L2] = v[1];
         scal[SC_PVB] = v[2];
         scal[SC_NONFIN] = v[3];
+        scal[SC_BAD] += v[3];
         if (stats4)
             for (int q = 0; q < 4; ++q) stats4[q] = v[q];
     }
@@ -270,7 +271,10 @@ __global__ __launch_bounds__(RB) void k_finish_dt(const double *__restrict__ par
         }
         scal[SC_MV] = m;
         scal[SC_DT] = (double)dt;
-        if (!isfinite(mv)) scal[SC_NONFIN] += 1.0;
+        if (!isfinite(mv)) {
+            scal[SC_NONFIN] += 1.0;
+            scal[SC_BAD] += 1.0;
+        }
     }
 }
 
@@ -340,7 +344,7 @@ __global__ __launch_bounds__(256) void k_levelset(const float *__restrict__ phi,
                                                   const double *__restrict__ scal, int N,
                                                   float *__restrict__ out, double *__restrict__ part) {
     __shared__ float t[34][35];
-    __shared__ int wsum[4];
+    __shared__ int wsum[4], wbad[4];
     const int bx = blockIdx.x * 32, by = blockIdx.y * 32;
     const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
     // the time step, and the velocity (and modulation) of this thread's
@@ -376,7 +380,7 @@ __global__ __launch_bounds__(256) void k_levelset(const float *__restrict__ phi,
         if (e < TE) t[e / 34][e - (e / 34) * 34] = tv[u];
     }
     __syncthreads();
-    int flips = 0;
+    int flips = 0, bad = 0;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
         const int ly = ty + 8 * j + 1, lx = tx + 1;
@@ -399,31 +403,43 @@ __global__ __launch_bounds__(256) void k_levelset(const float *__restrict__ phi,
             const float nv = c + dt * (vv[j] * sqrtf(g2) + lam * mv[j] * kap);
             out[p] = nv;
             flips += ((nv <= 0.f) != (c <= 0.f)) ? 1 : 0;
+            bad += isfinite(nv) ? 0 : 1;
         }
     }
-    // integer count: wave sums, then the four waves in order
+    // integer counts: wave sums, then the four waves in order
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) flips += __shfl_xor(flips, o);
-    if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = flips;
+    for (int o = 32; o > 0; o >>= 1) {
+        flips += __shfl_xor(flips, o);
+        bad += __shfl_xor(bad, o);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        wsum[threadIdx.x >> 6] = flips;
+        wbad[threadIdx.x >> 6] = bad;
+    }
     __syncthreads();
-    if (threadIdx.x == 0)
-        part[blockIdx.y * gridDim.x + blockIdx.x] = (double)(wsum[0] + wsum[1] + wsum[2] + wsum[3]);
+    if (threadIdx.x == 0) {
+        const size_t b = (size_t)blockIdx.y * gridDim.x + blockIdx.x;
+        part[2 * b] = (double)(wsum[0] + wsum[1] + wsum[2] + wsum[3]);
+        part[2 * b + 1] = (double)(wbad[0] + wbad[1] + wbad[2] + wbad[3]);
+    }
 }
 
 __global__ __launch_bounds__(RB) void k_finish_step(const double *__restrict__ part, int nblk,
                                                     double *__restrict__ scal, double *__restrict__ stats4,
                                                     double *__restrict__ trace_row, int iter, double ns_per_tick) {
     __shared__ double sh[RB];
-    double fs[1] = {0.0};
-    thread_partial_sums<1, 16>(part, nblk, fs);
+    double fs[2] = {0.0, 0.0};
+    thread_partial_sums<2, 8>(part, nblk, fs);
     const double f = block_sum(fs[0], sh);
+    const double bad = block_sum(fs[1], sh);
     if (threadIdx.x == 0) {
         scal[SC_FLIPS] = f;
+        scal[SC_BAD] += bad;
         if (stats4) {
             stats4[0] = scal[SC_MV];
             stats4[1] = scal[SC_DT];
             stats4[2] = f;
-            stats4[3] = 0.0;
+            stats4[3] = bad;
         }
         if (trace_row) {
             trace_row[0] = (double)iter;
@@ -440,82 +456,133 @@ __global__ __launch_bounds__(RB) void k_finish_step(const double *__restrict__ p
 
 // --------------------------------------------------------------------------
 // Exact squared EDT (Sec. II-A SDF, Sec. III-A TSDF, Alg. 1 CUDA_TSDF).
+// Separable: a column pass gives, for every pixel and class c, the distance
+// g_c along its column to the nearest class-c pixel; a row pass then takes
+// D_c(x) = min_x' g_c(x')^2 + (x - x')^2, the lower envelope of one
+// parabola per column, which is exact integer arithmetic throughout.
 //
 // Column pass, step 1: pack the class bits of every column, 32 rows per word:
-// colbits[w][x] bit b = [pixel (32w + b, x) is inside].
+// colbits[w][x] bit b = [pixel (32w + b, x) is inside].  Block = 32 rows x
+// 256 columns; each lane reads four adjacent columns (one 16-byte load per
+// row when the rows allow it), each wave eight of the 32 rows; the four
+// waves' bits meet in LDS.
 // --------------------------------------------------------------------------
-constexpr uint32_t NONE16 = 0xFFFFu;
-
-__global__ __launch_bounds__(256) void k_edt_pack(const float *__restrict__ phi, const uint8_t *__restrict__ mask,
-                                                  int N, uint32_t *__restrict__ colbits) {
-    const int x = blockIdx.x * 256 + threadIdx.x;
-    const int w = blockIdx.y;
-    if (x >= N) return;
-    uint32_t bits = 0u;
-#pragma unroll 8
-    for (int b = 0; b < 32; ++b) {
-        const int y = 32 * w + b;
-        if (y < N) {
-            const bool in = phi ? (phi[(size_t)y * N + x] <= 0.f) : (mask[(size_t)y * N + x] != 0);
-            bits |= (in ? 1u : 0u) << b;
-        }
-    }
-    colbits[(size_t)w * N + x] = bits;
-}
-
-// Column pass, step 2: for each pixel, the distance along its column to the
-// nearest pixel of each class (0 = outside, 1 = inside), packed as two 16-bit
-// fields (0xFFFF = none).  One thread per (column, 32-row word): the nearest
-// class pixels above and below the word come from a scan over whole words,
-// the rest from clz / ctz of the word itself.
 __device__ __forceinline__ uint32_t valid_bits(int w, int N) {
     const int rows = N - 32 * w;
     return rows >= 32 ? 0xFFFFFFFFu : ((1u << rows) - 1u);
 }
 
-__global__ __launch_bounds__(256) void k_edt_coldist(const uint32_t *__restrict__ colbits, int N,
-                                                     uint32_t *__restrict__ gout) {
-    const int x = blockIdx.x * 256 + threadIdx.x;
+template <bool PHI, typename TP>
+__global__ __launch_bounds__(256) void k_edt_bits(const TP *__restrict__ phi, const uint8_t *__restrict__ mask,
+                                                  int N, int vec, uint32_t *__restrict__ colbits) {
+    __shared__ uint32_t part[4][256];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int w = blockIdx.y;
-    if (x >= N) return;
-    const int W = (N + 31) / 32;
-    const uint32_t vm = valid_bits(w, N);
-    const uint32_t w1 = colbits[(size_t)w * N + x];
-    const uint32_t w0 = ~w1 & vm;
-    // nearest rows of each class strictly above this word / strictly below it
-    int up1 = -1, up0 = -1, dn1 = -1, dn0 = -1;
-    for (int v = w - 1; v >= 0 && (up1 < 0 || up0 < 0); --v) {
-        const uint32_t b1 = colbits[(size_t)v * N + x];
-        const uint32_t b0 = ~b1;                      // words above are full
-        if (up1 < 0 && b1) up1 = 32 * v + 31 - __clz(b1);
-        if (up0 < 0 && b0) up0 = 32 * v + 31 - __clz(b0);
-    }
-    for (int v = w + 1; v < W && (dn1 < 0 || dn0 < 0); ++v) {
-        const uint32_t b1 = colbits[(size_t)v * N + x];
-        const uint32_t b0 = ~b1 & valid_bits(v, N);
-        if (dn1 < 0 && b1) dn1 = 32 * v + __ffs(b1) - 1;
-        if (dn0 < 0 && b0) dn0 = 32 * v + __ffs(b0) - 1;
-    }
-#pragma unroll 4
-    for (int b = 0; b < 32; ++b) {
-        const int y = 32 * w + b;
-        if (y >= N) break;
-        const uint32_t le = (b == 31) ? 0xFFFFFFFFu : ((2u << b) - 1u);   // bits <= b
-        uint32_t d[2];
+    const int x0 = blockIdx.x * 256 + 4 * lane;
+    bool in[8][4];
 #pragma unroll
-        for (int c = 0; c < 2; ++c) {
-            const uint32_t word = c ? w1 : w0;
-            const int up = c ? up1 : up0, dn = c ? dn1 : dn0;
-            const uint32_t a = word & le;
-            const uint32_t bl = word & ~le;
-            int best = 0x7FFFFFFF;
-            if (a) best = min(best, b - (31 - __clz(a)));
-            else if (up >= 0) best = min(best, y - up);
-            if (bl) best = min(best, (__ffs(bl) - 1) - b);
-            else if (dn >= 0) best = min(best, dn - y);
-            d[c] = best == 0x7FFFFFFF ? NONE16 : (uint32_t)best;
+    for (int i = 0; i < 8; ++i) {
+        const int y = 32 * w + wave + 4 * i;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) in[i][e] = false;
+        if (y >= N) continue;
+        const size_t row = (size_t)y * N;
+        if (sizeof(TP) == 4 && vec && x0 + 3 < N) {
+            if (PHI) {
+                const float4 v = *reinterpret_cast<const float4 *>(phi + row + x0);
+                in[i][0] = v.x <= 0.f; in[i][1] = v.y <= 0.f; in[i][2] = v.z <= 0.f; in[i][3] = v.w <= 0.f;
+            } else {
+                const uchar4 v = *reinterpret_cast<const uchar4 *>(mask + row + x0);
+                in[i][0] = v.x != 0; in[i][1] = v.y != 0; in[i][2] = v.z != 0; in[i][3] = v.w != 0;
+            }
+        } else {
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                if (x0 + e < N) in[i][e] = PHI ? (phi[row + x0 + e] <= (TP)0) : (mask[row + x0 + e] != 0);
         }
-        gout[(size_t)y * N + x] = d[0] | (d[1] << 16);
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        uint32_t b = 0u;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) b |= (in[i][e] ? 1u : 0u) << (wave + 4 * i);
+        part[wave][4 * lane + e] = b;
+    }
+    __syncthreads();
+    const int x = blockIdx.x * 256 + threadIdx.x;
+    if (x < N)
+        colbits[(size_t)w * N + x] = ((part[0][threadIdx.x] | part[1][threadIdx.x]) | part[2][threadIdx.x]) |
+                                     part[3][threadIdx.x];
+}
+
+// Column pass, step 2: for every column x and word w, the nearest rows of
+// each class strictly above the word and strictly below it:
+// info[0][w][x] = class 1 above, [1] class 0 above, [2] class 1 below,
+// [3] class 0 below (-1: none).  Block = 64 columns x every word: the
+// words sit in LDS, and per column a bit mask of the words holding each
+// class turns "nearest word above / below" into one bit scan.
+// Up to 128 words (N <= 4096).
+__device__ __forceinline__ int word_below(const unsigned long long (&m)[2], int v) {   // largest u < v, or -1
+    if (v > 64) {
+        const unsigned long long t = m[1] & (v == 128 ? ~0ull : ((1ull << (v - 64)) - 1ull));
+        if (t) return 64 + 63 - __clzll((long long)t);
+        v = 64;
+    }
+    const unsigned long long t = m[0] & (v == 64 ? ~0ull : ((1ull << v) - 1ull));
+    return t ? 63 - __clzll((long long)t) : -1;
+}
+
+__device__ __forceinline__ int word_above(const unsigned long long (&m)[2], int v) {   // smallest u > v, or -1
+    int u = v + 1;
+    if (u < 64) {
+        const unsigned long long t = m[0] & (~0ull << u);
+        if (t) return __ffsll((long long)t) - 1;
+        u = 64;
+    }
+    if (u < 128) {
+        const unsigned long long t = m[1] & (~0ull << (u - 64));
+        if (t) return 64 + __ffsll((long long)t) - 1;
+    }
+    return -1;
+}
+
+__global__ __launch_bounds__(256) void k_edt_colinfo(const uint32_t *__restrict__ colbits, int N,
+                                                     int16_t *__restrict__ info) {
+    extern __shared__ uint32_t wsh[];                       // [W][64]
+    __shared__ unsigned long long any1[64][2], any0[64][2];
+    const int W = (N + 31) / 32;
+    const int c = threadIdx.x & 63, v0 = threadIdx.x >> 6;
+    const int x = blockIdx.x * 64 + c;
+    if (threadIdx.x < 128) {
+        any1[threadIdx.x >> 1][threadIdx.x & 1] = 0ull;
+        any0[threadIdx.x >> 1][threadIdx.x & 1] = 0ull;
+    }
+    __syncthreads();
+    for (int v = v0; v < W; v += 4) {
+        const uint32_t wd = x < N ? colbits[(size_t)v * N + x] : 0u;
+        wsh[v * 64 + c] = wd;
+        if (x < N) {
+            if (wd) atomicOr(&any1[c][v >> 6], 1ull << (v & 63));
+            if (~wd & valid_bits(v, N)) atomicOr(&any0[c][v >> 6], 1ull << (v & 63));
+        }
+    }
+    __syncthreads();
+    if (x >= N) return;
+    const unsigned long long m1[2] = {any1[c][0], any1[c][1]}, m0[2] = {any0[c][0], any0[c][1]};
+    const size_t plane = (size_t)W * N;
+    for (int v = v0; v < W; v += 4) {
+        int r[4];
+        int u = word_below(m1, v);
+        r[0] = u < 0 ? -1 : 32 * u + 31 - __clz(wsh[u * 64 + c]);
+        u = word_below(m0, v);
+        r[1] = u < 0 ? -1 : 32 * u + 31 - __clz(~wsh[u * 64 + c] & valid_bits(u, N));
+        u = word_above(m1, v);
+        r[2] = u < 0 ? -1 : 32 * u + __ffs(wsh[u * 64 + c]) - 1;
+        u = word_above(m0, v);
+        r[3] = u < 0 ? -1 : 32 * u + __ffs(~wsh[u * 64 + c] & valid_bits(u, N)) - 1;
+        const size_t o = (size_t)v * N + x;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) info[q * plane + o] = (int16_t)r[q];
     }
 }
 
@@ -536,224 +603,203 @@ __device__ float sqrt_minus_half(int D) {
     return t;
 }
 
-// Row pass: for each row and class c, D_c(x) = min_x' f(x') + (x - x')^2,
-// f = g_c^2 (2^30 stand-in where the column has no class-c pixel).  The cost
-// matrix is Monge, so the leftmost minimiser is non-decreasing in x; the
-// minimisers are found level by level over x (stride halving), each query
-// searching only between its neighbours' minimisers.  The candidates of all
-// queries of a level are laid end to end and split evenly over the 64 lanes
-// of the row's wave; partial minima meet in LDS through a 64-bit atomic
-// minimum of (value, index), which keeps the leftmost minimiser.
+// Row pass.  One block per row, one wave per class c (0 = outside, 1 =
+// inside): D_c(x) = min over columns x' holding a class-c pixel of
+// g_c(x')^2 + (x - x')^2.  In the dual, column x' is the point
+// (x', x'^2 + g^2) and D_c(x) - x^2 is the minimum of c' - 2 x x' over the
+// points, attained on their lower convex hull; hull vertices are the
+// columns whose parabola is lowest somewhere.
+//   1. each lane builds the hull of its band of m = N/64 columns (a stack:
+//      a vertex is dropped while it lies on or above the chord of its
+//      neighbours; exact in 64-bit integers);
+//   2. six rounds merge adjacent hulls pairwise: the first lane of a pair
+//      drops vertices at the junction while one is on or above the chord of
+//      its neighbours across it (every drop removes a non-vertex of the
+//      union, and once the junction is convex the chain is the union's
+//      hull), then the pair's lanes move the right hull's remainder next to
+//      the left one's;
+//   3. the optimal vertex is non-decreasing in x: each lane finds the one
+//      of its first pixel by bisection (the differences of c' - 2 x x'
+//      along the hull change sign once) and walks forward from there.
+// Every value is an exact integer, so the result is unique.  A class that
+// is absent from the whole image leaves D = FBIG.
 constexpr int FBIG = 1 << 30;
+constexpr uint16_t GNONE = 0xFFFFu;
 
-struct RowLevel {
-    int s;      // stride (0: the two end points)
-    int N;
-    int nq;     // queries per class
-};
-
-// Query q of a level covers class q / nq; returns its pixel, candidate range
-// and the class arrays it reads.
-// arg and f hold both classes back to back: class c at [c * N, (c + 1) * N).
-__device__ __forceinline__ void query_of(const RowLevel &L, const int16_t *arg, int q, int &cls, int &xq,
-                                         int &lo, int &hi) {
-    cls = q >= L.nq;
-    const int qq = q - cls * L.nq;
-    if (L.s == 0) {
-        xq = qq ? L.N - 1 : 0;
-        lo = 0;
-        hi = L.N - 1;
-    } else {
-        xq = L.s * (2 * qq + 1);
-        lo = arg[cls * L.N + xq - L.s];
-        hi = arg[cls * L.N + min(xq + L.s, L.N - 1)];
-    }
+__device__ __forceinline__ long long hull_c(const uint16_t *g, int s) {
+    const long long gs = g[s];
+    return (long long)s * s + gs * gs;
 }
 
-__device__ __forceinline__ void row_level(const RowLevel &L, const int *f, int16_t *arg, int *off,
-                                          unsigned long long *key, int lane) {
-    const int nq = 2 * L.nq;                  // both classes
-    const int qb = (nq + 63) / 64;
-    const int qlo = min(nq, lane * qb), qhi = min(nq, qlo + qb);
-    int sum = 0;
-    for (int q = qlo; q < qhi; ++q) {
-        int cls, xq, lo, hi;
-        query_of(L, arg, q, cls, xq, lo, hi);
-        sum += hi - lo + 1;
-    }
-    int incl = sum;
-    for (int o = 1; o < 64; o <<= 1) {
-        const int t = __shfl_up(incl, o);
-        if (lane >= o) incl += t;
-    }
-    const int T = __shfl(incl, 63);
-    int run = incl - sum;
-    for (int q = qlo; q < qhi; ++q) {
-        int cls, xq, lo, hi;
-        query_of(L, arg, q, cls, xq, lo, hi);
-        off[q] = run;
-        run += hi - lo + 1;
-        key[q] = ~0ull;
-    }
-    __syncthreads();
-    const int C = (T + 63) / 64;
-    const int i0 = lane * C, i1 = min(T, i0 + C);
-    if (i0 < i1) {
-        int a = 0, b = nq - 1;                  // largest q with off[q] <= i0
-        while (a < b) {
-            const int m = (a + b + 1) >> 1;
-            if (off[m] <= i0) a = m; else b = m - 1;
-        }
-        int q = a, i = i0;
-        while (i < i1) {
-            int cls, xq, lo, hi;
-            query_of(L, arg, q, cls, xq, lo, hi);
-            const int *fc = f + cls * L.N;
-            const int cs = lo + (i - off[q]);
-            const int ce = min(hi, lo + (i1 - off[q]) - 1);
-            int bv = 0x7FFFFFFF, bi = 0;
-            int cnd = cs;
-            for (; cnd + 3 <= ce; cnd += 4) {
-                const int f0 = fc[cnd], f1 = fc[cnd + 1], f2 = fc[cnd + 2], f3 = fc[cnd + 3];
-                const int d0 = xq - cnd;
-                const int v0 = f0 + d0 * d0;
-                const int v1 = f1 + (d0 - 1) * (d0 - 1);
-                const int v2 = f2 + (d0 - 2) * (d0 - 2);
-                const int v3 = f3 + (d0 - 3) * (d0 - 3);
-                if (v0 < bv) { bv = v0; bi = cnd; }
-                if (v1 < bv) { bv = v1; bi = cnd + 1; }
-                if (v2 < bv) { bv = v2; bi = cnd + 2; }
-                if (v3 < bv) { bv = v3; bi = cnd + 3; }
-            }
-            for (; cnd <= ce; ++cnd) {
-                const int v = fc[cnd] + (xq - cnd) * (xq - cnd);
-                if (v < bv) { bv = v; bi = cnd; }
-            }
-            atomicMin(&key[q], ((unsigned long long)(unsigned)bv << 32) | (unsigned)bi);
-            i = off[q] + (hi - lo + 1);
-            ++q;
-        }
-    }
-    __syncthreads();
-    for (int q = lane; q < nq; q += 64) {
-        int cls, xq, lo, hi;
-        query_of(L, arg, q, cls, xq, lo, hi);
-        arg[cls * L.N + xq] = (int16_t)(key[q] & 0xFFFFFFFFull);
-    }
-    __syncthreads();
+// is b on or above the chord from a to q (a < b < q)?
+__device__ __forceinline__ bool hull_drop(const uint16_t *g, int a, int b, int q) {
+    const long long ca = hull_c(g, a), cb = hull_c(g, b), cq = hull_c(g, q);
+    return (cb - ca) * (long long)(q - b) >= (cq - cb) * (long long)(b - a);
 }
 
-__device__ __forceinline__ void row_transform(const int *f, int16_t *arg, int *off, unsigned long long *key,
-                                              int N, int lane) {
-    row_level(RowLevel{0, N, N > 1 ? 2 : 1}, f, arg, off, key, lane);
-    int Lp = 1;
-    while (Lp < N - 1) Lp <<= 1;
-    for (int s = Lp >> 1; s >= 1; s >>= 1) {
-        const int nq = (N - 1 > s) ? ((N - 1 - s + 2 * s - 1) / (2 * s)) : 0;
-        if (nq > 0) row_level(RowLevel{s, N, nq}, f, arg, off, key, lane);
-    }
+__device__ __forceinline__ int hull_val(const uint16_t *g, int s, int x) {
+    const int gs = g[s];
+    return gs * gs + (x - s) * (x - s);
 }
 
-// Both classes of one row per 64-lane block.  LDS: packed column distances,
-// f and minimisers for each class, and the level's query offsets and keys.
-__global__ __launch_bounds__(64) void k_edt_rows(const uint32_t *__restrict__ gin, int N, float d_lower,
-                                                 float d_upper, float *__restrict__ phi_out,
-                                                 int *__restrict__ sqdist) {
-    extern __shared__ unsigned long long smem_u64[];
-    const int nqmax = 2 * (N / 2 + 2);
-    unsigned long long *key = smem_u64;                           // [nqmax]
-    uint32_t *gr = reinterpret_cast<uint32_t *>(key + nqmax);     // [N]
-    int *f0 = reinterpret_cast<int *>(gr + N);                    // [N]
-    int *f1 = f0 + N;                                             // [N]
-    int *off = f1 + N;                                            // [nqmax]
-    int16_t *a0 = reinterpret_cast<int16_t *>(off + nqmax);       // [N]
-    int16_t *a1 = a0 + N;                                         // [N]
-    const int y = blockIdx.x, lane = threadIdx.x;
-    const uint32_t *grow = gin + (size_t)y * N;
-    for (int x = lane; x < N; x += 64) {
-        const uint32_t g = grow[x];
-        gr[x] = g;
-        const uint32_t g0 = g & 0xFFFFu, g1 = g >> 16;
-        f0[x] = (g0 == NONE16) ? FBIG : (int)(g0 * g0);
-        f1[x] = (g1 == NONE16) ? FBIG : (int)(g1 * g1);
-    }
-    __syncthreads();
-    row_transform(f0, a0, off, key, N, lane);
-    for (int x = lane; x < N; x += 64) {
-        const bool inside = (gr[x] >> 16) == 0;        // distance 0 to class 1
-        // inside pixels need the distance to class 0 (D_out), outside to class 1 (D_in)
-        const int c0 = a0[x], c1 = a1[x];
-        const int D0 = f0[c0] + (x - c0) * (x - c0);
-        const int D1 = f1[c1] + (x - c1) * (x - c1);
-        if (sqdist) {
-            sqdist[(size_t)y * N + x] = D1 >= FBIG ? 0x7FFFFFFF : D1;
-            sqdist[(size_t)N * N + (size_t)y * N + x] = D0 >= FBIG ? 0x7FFFFFFF : D0;
-        }
-        float v;
-        if (inside) v = D0 >= FBIG ? d_lower : -sqrt_minus_half(D0);
-        else v = D1 >= FBIG ? d_upper : sqrt_minus_half(D1);
-        phi_out[(size_t)y * N + x] = fminf(fmaxf(v, d_lower), d_upper);
-    }
-}
-
-// Row pass for a clipped TSDF only (no squared-distance output).  A pixel
-// needs its exact D only while sqrt(D) - 1/2 stays inside the clip bound B,
-// i.e. D <= Rb^2 with Rb = bound + 1/2.  Each pixel scans candidate columns
-// outward from its own, x' = x +- d: every scanned candidate is an upper
-// bound of D, and the scan stops once d^2 >= best (nothing farther can beat
-// it) or d passes floor(Rb) (a minimiser with D <= Rb^2 lies within that
-// window).  So the result is exact whenever it is at most Rb^2, and above
-// Rb^2 only when D is; such pixels take the clip value.  One block per row.
-__global__ __launch_bounds__(256) void k_edt_rows_clip(const uint32_t *__restrict__ gin, int N, int pad,
-                                                       float d_lower, float d_upper, float *__restrict__ phi_out) {
-    // each class row is stored with `pad` sentinel entries on both sides, so
-    // the scan needs no bounds checks (sentinels never win: FBIG >= any bound)
-    extern __shared__ int fsh[];
-    const int W = N + 2 * pad;
-    int *f0 = fsh + pad;          // squared column distance to class 0 (FBIG: none)
-    int *f1 = fsh + W + pad;      // ... to class 1
+template <typename TP>
+__global__ __launch_bounds__(128) void k_edt_rows_env(const uint32_t *__restrict__ colbits,
+                                                      const int16_t *__restrict__ info, int N, float d_lower,
+                                                      float d_upper, TP *__restrict__ phi_out,
+                                                      int *__restrict__ sqdist) {
+    extern __shared__ int esm[];
+    int *Dout = esm;                                              // [N]
+    uint16_t *gsh = reinterpret_cast<uint16_t *>(Dout + N);        // [2][N]
+    int16_t *env = reinterpret_cast<int16_t *>(gsh + 2 * N);       // [2][N]
+    __shared__ int cnt[2][64], mia[2][64], mib[2][64];
     const int y = blockIdx.x;
-    const uint32_t *grow = gin + (size_t)y * N;
-    for (int i = threadIdx.x; i < 2 * W; i += 256) fsh[i] = FBIG;
-    __syncthreads();
-    for (int x = threadIdx.x; x < N; x += 256) {
-        const uint32_t g = grow[x];
-        const uint32_t g0 = g & 0xFFFFu, g1 = g >> 16;
-        f0[x] = (g0 == NONE16) ? FBIG : (int)(g0 * g0);
-        f1[x] = (g1 == NONE16) ? FBIG : (int)(g1 * g1);
+    const int lane = threadIdx.x & 63, cls = threadIdx.x >> 6;
+    const int W = (N + 31) / 32;
+    const int w = y >> 5, b = y & 31;
+    const uint32_t le = (b == 31) ? 0xFFFFFFFFu : ((2u << b) - 1u);
+    const uint32_t vm = valid_bits(w, N);
+    const size_t plane = (size_t)W * N;
+    // g_c of every column of this row from the column bits and the nearest
+    // class rows above and below this row's word
+    for (int x = threadIdx.x; x < N; x += 128) {
+        const size_t o = (size_t)w * N + x;
+        const uint32_t w1 = colbits[o], w0 = ~w1 & vm;
+        const int up1 = info[o], up0 = info[plane + o], dn1 = info[2 * plane + o], dn0 = info[3 * plane + o];
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            const uint32_t word = c ? w1 : w0;
+            const int up = c ? up1 : up0, dn = c ? dn1 : dn0;
+            const uint32_t a = word & le, bl = word & ~le;
+            int best = 0x7FFFFFFF;
+            if (a) best = b - (31 - __clz(a));
+            else if (up >= 0) best = y - up;
+            if (bl) best = min(best, (__ffs(bl) - 1) - b);
+            else if (dn >= 0) best = min(best, dn - y);
+            gsh[c * N + x] = best == 0x7FFFFFFF ? GNONE : (uint16_t)best;
+        }
     }
     __syncthreads();
-    const int r_out = (int)floorf(d_upper + 0.5f);     // outside pixels: bound d_upper
-    const int r_in = (int)floorf(-d_lower + 0.5f);     // inside pixels: bound |d_lower|
-    for (int x = threadIdx.x; x < N; x += 256) {
-        const bool inside = f1[x] == 0;
-        const int *fc = inside ? f0 : f1;
-        const int R = min(inside ? r_in : r_out, pad - 8);
-        int best = fc[x];
-        int d = 1, q = 1;                               // q = d^2
-        while (d <= R && q < best) {
-#pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                best = min(best, min(fc[x - d], fc[x + d]) + q);
-                q += 2 * d + 1;
-                ++d;
+    const uint16_t *g = gsh + cls * N;
+    int16_t *e = env + cls * N;
+    const int m = (N + 63) / 64;
+    // 1. the hull of this lane's band
+    {
+        const int lo = lane * m, hi = min(N, lo + m);
+        int k = -1;
+        for (int q = lo; q < hi; ++q) {
+            if (g[q] == GNONE) continue;
+            while (k >= 1 && hull_drop(g, e[lo + k - 1], e[lo + k], q)) --k;
+            e[lo + (++k)] = (int16_t)q;
+        }
+        cnt[cls][lane] = k + 1;
+    }
+    __syncthreads();
+    // 2. pairwise merges
+    for (int gs = 1; gs < 64; gs *= 2) {
+        const int A = lane & ~(2 * gs - 1), B = A + gs;
+        if (lane == A) {
+            const int sA = A * m, sB = B * m, nA = cnt[cls][A], nB = cnt[cls][B];
+            int ia = nA - 1, ib = 0;
+            if (nA > 0 && nB > 0) {
+                for (;;) {
+                    if (ia >= 1 && hull_drop(g, e[sA + ia - 1], e[sA + ia], e[sB + ib])) {
+                        --ia;
+                        continue;
+                    }
+                    if (ib + 1 < nB && hull_drop(g, e[sA + ia], e[sB + ib], e[sB + ib + 1])) {
+                        ++ib;
+                        continue;
+                    }
+                    break;
+                }
+            }
+            mia[cls][A] = ia;
+            mib[cls][A] = ib;
+        }
+        __syncthreads();
+        {
+            // the pair's lanes move B's remainder behind A's kept prefix; the
+            // destination never lies above the source, and every load of a
+            // round precedes its stores (one wave), so nothing is overwritten
+            // before it is read
+            const int ia = mia[cls][A], ib = mib[cls][A], nB = cnt[cls][B];
+            const int dst = A * m + ia + 1, src = B * m + ib, n = nB - ib;
+            for (int i = lane - A; i < n; i += 2 * gs) e[dst + i] = e[src + i];
+        }
+        __syncthreads();
+        if (lane == A) cnt[cls][A] = mia[cls][A] + 1 + cnt[cls][B] - mib[cls][A];
+        __syncthreads();
+    }
+    // 3. queries: D_c for every pixel of this lane's band
+    {
+        const int n = cnt[cls][0];
+        const int lo = lane * m, hi = min(N, lo + m);
+        if (lo < hi) {
+            int j = 0;
+            if (n > 0) {
+                int a = 0, bb = n - 1;
+                while (a < bb) {
+                    const int mid = (a + bb) >> 1;
+                    if (hull_val(g, e[mid + 1], lo) >= hull_val(g, e[mid], lo)) bb = mid;
+                    else a = mid + 1;
+                }
+                j = a;
+            }
+            for (int x = lo; x < hi; ++x) {
+                int D = FBIG;
+                if (n > 0) {
+                    int v = hull_val(g, e[j], x);
+                    while (j + 1 < n) {
+                        const int v1 = hull_val(g, e[j + 1], x);
+                        if (v1 >= v) break;
+                        v = v1;
+                        ++j;
+                    }
+                    D = v;
+                }
+                // inside pixels (g_1 = 0) take D_0, outside ones D_1
+                const bool inside = gsh[N + x] == 0;
+                if (inside == (cls == 0)) Dout[x] = D;
+                if (sqdist)
+                    sqdist[(size_t)(1 - cls) * N * N + (size_t)y * N + x] = D >= FBIG ? 0x7FFFFFFF : D;
             }
         }
-        const float rb = inside ? (-d_lower + 0.5f) : (d_upper + 0.5f);
-        float v;
-        if ((double)best > (double)rb * (double)rb) {
-            v = inside ? d_lower : d_upper;
+    }
+    __syncthreads();
+    for (int x = threadIdx.x; x < N; x += 128) {
+        const int D = Dout[x];
+        const bool inside = gsh[N + x] == 0;
+        if (sizeof(TP) == 4) {
+            float v;
+            if (inside) v = D >= FBIG ? d_lower : -sqrt_minus_half(D);
+            else v = D >= FBIG ? d_upper : sqrt_minus_half(D);
+            phi_out[(size_t)y * N + x] = fminf(fmaxf(v, d_lower), d_upper);
         } else {
-            const float t = sqrt_minus_half(best);
-            v = inside ? -t : t;
+            // FP64: the correctly rounded square root less 1/2, which is exact
+            // (sqrt(D) >= 1 has an ulp that divides 1/2)
+            double v;
+            if (inside) v = D >= FBIG ? (double)d_lower : 0.5 - sqrt((double)D);
+            else v = D >= FBIG ? (double)d_upper : sqrt((double)D) - 0.5;
+            phi_out[(size_t)y * N + x] = (TP)fmin(fmax(v, (double)d_lower), (double)d_upper);
         }
-        phi_out[(size_t)y * N + x] = fminf(fmaxf(v, d_lower), d_upper);
     }
 }
 
 __global__ void k_copy(float *__restrict__ dst, const float *__restrict__ src, size_t n) {
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
         dst[i] = src[i];
+}
+
+// H(phi + dh) as 0/1 (H(z) = 1 for z >= 0): the shifted Heaviside maps that
+// are the modulation branch's candidate targets (Sec. III-B).  The FP32 sum
+// has the sign of the exact one (rounding never crosses zero).
+__global__ void k_heaviside_shift(const float *__restrict__ phi, float dh, size_t n, float *__restrict__ out) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        out[i] = (phi[i] + dh >= 0.f) ? 1.f : 0.f;
+}
+
+__global__ void k_set_scal(double *__restrict__ scal, int slot, double v) {
+    if (threadIdx.x == 0) scal[slot] = v;
 }
 
 __global__ void k_fill(float *__restrict__ dst, float v, size_t n) {
@@ -844,32 +890,56 @@ hipError_t launch_finish_step(ilt_ctx *c, const double *part, int nblk, double *
     return hipGetLastError();
 }
 
+size_t edt_scratch_bytes(int N) {
+    const size_t W = (size_t)(N + 31) / 32;
+    return W * N * sizeof(uint32_t) + 4 * W * N * sizeof(int16_t);
+}
+
+template <typename TP>
+hipError_t edt_any(hipStream_t st, int N, const TP *phi, const uint8_t *mask, TP *phi_out, int *sqdist,
+                   float d_lower, float d_upper, void *scratch) {
+    const int W = (N + 31) / 32;
+    uint32_t *colbits = static_cast<uint32_t *>(scratch);
+    int16_t *info = reinterpret_cast<int16_t *>(colbits + (size_t)W * N);
+    const int vec = (N % 4) == 0 && (phi ? reinterpret_cast<uintptr_t>(phi) % 16 == 0
+                                         : reinterpret_cast<uintptr_t>(mask) % 4 == 0);
+    const dim3 g1((N + 255) / 256, W);
+    if (phi) k_edt_bits<true, TP><<<g1, 256, 0, st>>>(phi, nullptr, N, vec, colbits);
+    else k_edt_bits<false, TP><<<g1, 256, 0, st>>>(nullptr, mask, N, vec, colbits);
+    k_edt_colinfo<<<(N + 63) / 64, 256, (size_t)W * 64 * sizeof(uint32_t), st>>>(colbits, N, info);
+    const size_t sm = (size_t)N * (sizeof(int) + 4 * sizeof(uint16_t));
+    k_edt_rows_env<TP><<<N, 128, sm, st>>>(colbits, info, N, d_lower, d_upper, phi_out, sqdist);
+    return hipGetLastError();
+}
+
+hipError_t launch_edt_raw(hipStream_t st, int N, const float *phi, const uint8_t *mask, float *phi_out, int *sqdist,
+                          float d_lower, float d_upper, void *scratch) {
+    return edt_any<float>(st, N, phi, mask, phi_out, sqdist, d_lower, d_upper, scratch);
+}
+
+hipError_t launch_edt64(ilt_ctx *c, const double *phi, const uint8_t *mask, double *phi_out, int *sqdist,
+                        float d_lower, float d_upper) {
+    return edt_any<double>(c->stream, c->N, phi, mask, phi_out, sqdist, d_lower, d_upper, c->edt_scratch);
+}
+
 hipError_t launch_edt(ilt_ctx *c, const float *phi, const uint8_t *mask, float *phi_out, int *sqdist,
                       float d_lower, float d_upper) {
-    const int N = c->N;
-    const dim3 grid((N + 255) / 256, (N + 31) / 32);
-    k_edt_pack<<<grid, 256, 0, c->stream>>>(phi, mask, N, c->colbits);
-    k_edt_coldist<<<grid, 256, 0, c->stream>>>(c->colbits, N, c->edtg);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    if (!sqdist) {
-        // sentinel padding covers the largest clip radius plus one unrolled step
-        const int r = (int)std::ceil(std::max(d_upper, -d_lower) + 0.5f);
-        const int pad = std::min(r, N) + 8;
-        const size_t sm = (size_t)(N + 2 * pad) * 2 * sizeof(int);
-        if (sm <= 160 * 1024) {
-            k_edt_rows_clip<<<N, 256, sm, c->stream>>>(c->edtg, N, pad, d_lower, d_upper, phi_out);
-            return hipGetLastError();
-        }
-    }
-    const int nqmax = 2 * (N / 2 + 2);
-    const size_t sm = (size_t)nqmax * 8 + (size_t)N * 4 * 3 + (size_t)nqmax * 4 + (size_t)N * 2 * 2;
-    k_edt_rows<<<N, 64, sm, c->stream>>>(c->edtg, N, d_lower, d_upper, phi_out, sqdist);
-    return hipGetLastError();
+    return launch_edt_raw(c->stream, c->N, phi, mask, phi_out, sqdist, d_lower, d_upper, c->edt_scratch);
 }
 
 hipError_t launch_copy(ilt_ctx *c, float *dst, const float *src, size_t n) {
     k_copy<<<1024, 256, 0, c->stream>>>(dst, src, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_heaviside_shift(const float *phi, float dh, size_t n, float *out, hipStream_t st) {
+    const int nb = (int)std::min<size_t>(4096, (n + 255) / 256);
+    k_heaviside_shift<<<std::max(nb, 1), 256, 0, st>>>(phi, dh, n, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_set_scal(ilt_ctx *c, int slot, double v) {
+    k_set_scal<<<1, 64, 0, c->stream>>>(c->scal, slot, v);
     return hipGetLastError();
 }
 

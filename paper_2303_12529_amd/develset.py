@@ -78,7 +78,7 @@ def make_dataset(n_clips: int, seed0: int, net: "_dsn.Net", precision: int = _il
         if net.modulation:
             best_loss = None
             for dh in shifts:
-                mod.copy_(phi[0] + float(dh) >= 0)
+                _ilt.shifted_heaviside(phi[0], float(dh), out=mod)
                 loss = ctx.ilt_solve(tgt[0], work, p, mod=mod)["loss"]
                 if best_loss is None or loss < best_loss:
                     best_loss, dhs[i] = loss, dh
@@ -153,9 +153,8 @@ def evaluate(net: "_dsn.Net", seeds, precision: int = _ilt.ILT_FP32, extra_iters
     pr = _ilt.Params.from_dict(prm)
 
     def l2_of(phi_t):
-        m = (phi_t <= 0).to(torch.float32)
         for s in range(ctx.n_sets):
-            ctx.litho_forward(m, s, out=I[s])
+            ctx.litho_forward_phi(phi_t, s, out=I[s])
         _, st = ctx.resist_loss(I, tgt[0], pr)
         return int(st.cpu()[1])
 

@@ -42,6 +42,13 @@ def _lib():
                                      _VP, _VP],
             "dsn_op_conv3x3_wgrad": [_VP, _VP, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                      ctypes.c_int, _VP, _VP, _VP],
+            "dsn_op_conv_first": [_VP, ctypes.c_int, ctypes.c_int, ctypes.c_int, _VP, _VP, ctypes.c_int, _VP, _VP],
+            "dsn_op_wgrad_first": [_VP, _VP, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, _VP, _VP, _VP],
+            "dsn_op_head_bwd": [_VP, ctypes.c_longlong, ctypes.c_int, ctypes.c_int, _VP, _VP, _VP, _VP, _VP, _VP,
+                                _VP, _VP, _VP, _VP],
+            "dsn_op_maxpool2_bwd": [_VP, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, _VP, _VP, _VP],
+            "dsn_op_upsample2_bwd": [_VP, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, _VP, _VP],
+            "dsn_op_relu_bwd": [_VP, _VP, ctypes.c_longlong, ctypes.c_int, _VP],
         }
         for name, args in sig.items():
             fn = getattr(lib, name)
@@ -265,3 +272,86 @@ def conv3x3_wgrad(dz, x, up=False):
                                        _ptr(db, torch.float32, None, "db"),
                                        _VP(torch.cuda.current_stream().cuda_stream)))
     return dw, db
+
+
+def _st():
+    import torch
+    return _VP(torch.cuda.current_stream().cuda_stream)
+
+
+def conv_first(x, w, b):
+    """First layer: x float32 [N, H, W], w bf16 [Cout, 3, 3, 1], b float32
+    [Cout] -> bf16 [N, H, W, Cout] (bias + ReLU)."""
+    import torch
+    N, H, W = x.shape
+    Cout = w.shape[0]
+    y = torch.empty((N, H, W, Cout), dtype=torch.bfloat16, device=x.device)
+    _check(_lib().dsn_op_conv_first(_ptr(x, torch.float32, (N, H, W), "x"), N, H, W,
+                                    _ptr(w, torch.bfloat16, (Cout, 3, 3, 1), "w"),
+                                    _ptr(b, torch.float32, (Cout,), "b"), Cout,
+                                    _ptr(y, torch.bfloat16, None, "y"), _st()))
+    return y
+
+
+def wgrad_first(dz, x):
+    """First layer's (dw float32 [C, 3, 3, 1], db float32 [C]) for dz bf16
+    [N, H, W, C] and x float32 [N, H, W]."""
+    import torch
+    N, H, W, C = dz.shape
+    dw = torch.empty((C, 3, 3, 1), dtype=torch.float32, device=dz.device)
+    db = torch.empty((C,), dtype=torch.float32, device=dz.device)
+    _check(_lib().dsn_op_wgrad_first(_ptr(dz, torch.bfloat16, None, "dz"), _ptr(x, torch.float32, (N, H, W), "x"),
+                                     N, H, W, C, _ptr(dw, torch.float32, None, "dw"),
+                                     _ptr(db, torch.float32, None, "db"), _st()))
+    return dw, db
+
+
+def head_bwd(x, w, out, t, B, wm=None, out_m=None, t_m=None):
+    """Head backward: x bf16 [npix, C] features, w (wm) bf16 [C], out / t
+    (out_m / t_m) float32 [npix].  Returns (dx bf16 [npix, C], loss float64
+    [2], gw float32 [heads, C + 1])."""
+    import torch
+    npix, C = x.shape
+    heads = 2 if wm is not None else 1
+    dx = torch.empty_like(x)
+    loss = torch.zeros(2, dtype=torch.float64, device=x.device)
+    gw = torch.empty((heads, C + 1), dtype=torch.float32, device=x.device)
+    f = torch.float32
+    _check(_lib().dsn_op_head_bwd(
+        _ptr(x, torch.bfloat16, (npix, C), "x"), npix, C, int(B), _ptr(w, torch.bfloat16, (C,), "w"),
+        None if wm is None else _ptr(wm, torch.bfloat16, (C,), "wm"), _ptr(out, f, (npix,), "out"),
+        None if out_m is None else _ptr(out_m, f, (npix,), "out_m"), _ptr(t, f, (npix,), "t"),
+        None if t_m is None else _ptr(t_m, f, (npix,), "t_m"), _ptr(dx, torch.bfloat16, None, "dx"),
+        _ptr(loss, torch.float64, (2,), "loss"), _ptr(gw, f, None, "gw"), _st()))
+    return dx, loss, gw
+
+
+def maxpool2_bwd(x, dy, dx):
+    """dx (bf16 [N, H, W, C]) += dy (bf16 [N, H/2, W/2, C]) routed to the first
+    maximum of each 2x2 window of x; in place, returns dx."""
+    import torch
+    N, H, W, C = x.shape
+    _check(_lib().dsn_op_maxpool2_bwd(_ptr(x, torch.bfloat16, None, "x"), N, H, W, C,
+                                      _ptr(dy, torch.bfloat16, (N, H // 2, W // 2, C), "dy"),
+                                      _ptr(dx, torch.bfloat16, (N, H, W, C), "dx"), _st()))
+    return dx
+
+
+def upsample2_bwd(dy):
+    """bf16 [N, H/2, W/2, C]: the sum of each pixel's four children in dy."""
+    import torch
+    N, H, W, C = dy.shape
+    dx = torch.empty((N, H // 2, W // 2, C), dtype=torch.bfloat16, device=dy.device)
+    _check(_lib().dsn_op_upsample2_bwd(_ptr(dy, torch.bfloat16, None, "dy"), N, H, W, C,
+                                       _ptr(dx, torch.bfloat16, None, "dx"), _st()))
+    return dx
+
+
+def relu_bwd(d, y):
+    """d (bf16 [..., C]) *= [y > 0] in place; returns d."""
+    import torch
+    C = d.shape[-1]
+    npix = d.numel() // C
+    _check(_lib().dsn_op_relu_bwd(_ptr(d, torch.bfloat16, None, "d"), _ptr(y, torch.bfloat16, tuple(d.shape), "y"),
+                                  npix, C, _st()))
+    return d

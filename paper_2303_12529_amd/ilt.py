@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libilt.so")
 ILT_OK, ILT_EINVAL, ILT_ENOMEM, ILT_EDEVICE, ILT_ENUMERIC, ILT_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 ILT_FP32 = 0
 ILT_BF16X3 = 1
+ILT_FP64 = 2
 ILT_FLAG_RECOMPUTE_FIELDS = 1
 ILT_FLAG_GWINDOW_ADJOINT = 2
 TRACE_W = 8
@@ -48,7 +49,8 @@ class _Params(ctypes.Structure):
                 ("init_mode", ctypes.c_int), ("eta", ctypes.c_float), ("dt_max", ctypes.c_float),
                 ("lambda_", ctypes.c_float), ("sigma_z", ctypes.c_float), ("i_th", ctypes.c_float),
                 ("eps_kappa", ctypes.c_float), ("d_lower", ctypes.c_float), ("d_upper", ctypes.c_float),
-                ("n_corners", ctypes.c_int), ("corners", _Corner * 4), ("optimizer", ctypes.c_int)]
+                ("n_corners", ctypes.c_int), ("corners", _Corner * 4), ("optimizer", ctypes.c_int),
+                ("iter0", ctypes.c_int)]
 
 
 class _Report(ctypes.Structure):
@@ -85,6 +87,11 @@ def load_library(path: str = LIB_PATH):
         "ilt_destroy": [_VP],
         "ilt_get_dims": [_VP, ctypes.POINTER(ctypes.c_int)] + [ctypes.POINTER(ctypes.c_int)] * 3,
         "litho_forward": [_VP, _VP, ctypes.c_int, _VP],
+        "litho_forward_phi": [_VP, _VP, ctypes.c_int, _VP],
+        "litho_forward_f64": [_VP, _VP, ctypes.c_int, _VP],
+        "litho_adjoint_f64": [_VP, _VP, _VP, ctypes.c_int, _VP],
+        "ilt_solve_f64": [_VP, _VP, _VP, ctypes.POINTER(_Params), ctypes.POINTER(_Report), _VP],
+        "ilt_shifted_heaviside": [_VP, ctypes.c_float, ctypes.c_longlong, _VP, _VP],
         "litho_adjoint": [_VP, _VP, _VP, ctypes.c_int, _VP],
         "resist_loss": [_VP, _VP, _VP, ctypes.POINTER(_Params), _VP, _VP],
         "levelset_step": [_VP, _VP, _VP, _VP, ctypes.POINTER(_Params), _VP],
@@ -142,6 +149,7 @@ class Params:
     d_upper: float = 900.0
     corners: tuple = ((0, 1.0, 1.0),)
     optimizer: int = 0              # 0: gradient, 1: conjugate gradient (Polak-Ribiere+)
+    iter0: int = 0                  # index of the first iteration (resuming a solve)
 
     @classmethod
     def from_dict(cls, d: dict, **over):
@@ -159,6 +167,7 @@ class Params:
             raise ValueError("1..4 corners")
         p.n_corners = len(self.corners)
         p.optimizer = int(self.optimizer)
+        p.iter0 = int(self.iter0)
         for i, (s, d, w) in enumerate(self.corners):
             p.corners[i].set, p.corners[i].dose, p.corners[i].omega = int(s), float(d), float(w)
         return p
@@ -235,6 +244,14 @@ class Context:
         _check(load_library().litho_forward(self._h, self._img(mask, "mask"), int(set_), self._img(out, "out")))
         return out
 
+    def litho_forward_phi(self, phi, set_: int = 0, out=None):
+        """Aerial image of the mask [phi <= 0] (the mask is formed on the device)."""
+        import torch
+        if out is None:
+            out = torch.empty((self.N, self.N), dtype=torch.float32, device=self.device)
+        _check(load_library().litho_forward_phi(self._h, self._img(phi, "phi"), int(set_), self._img(out, "out")))
+        return out
+
     def litho_adjoint(self, mask, dL_dI, set_: int = 0, out=None):
         import torch
         if out is None:
@@ -298,6 +315,38 @@ class Context:
         return dict(iters_done=rep.iters_done, status=rep.status, loss=rep.loss, l2=rep.l2, pvb=rep.pvb,
                     flips=rep.flips)
 
+
+    # FP64 form (a context created with precision=ILT_FP64)
+    def litho_forward_f64(self, mask, set_: int = 0, out=None):
+        import torch
+        if out is None:
+            out = torch.empty((self.N, self.N), dtype=torch.float64, device=self.device)
+        _check(load_library().litho_forward_f64(self._h, self._img(mask, "mask", torch.float64), int(set_),
+                                                self._img(out, "out", torch.float64)))
+        return out
+
+    def litho_adjoint_f64(self, mask, dL_dI, set_: int = 0, out=None):
+        import torch
+        if out is None:
+            out = torch.empty((self.N, self.N), dtype=torch.float64, device=self.device)
+        _check(load_library().litho_adjoint_f64(self._h, self._img(mask, "mask", torch.float64),
+                                                self._img(dL_dI, "dL_dI", torch.float64), int(set_),
+                                                self._img(out, "out", torch.float64)))
+        return out
+
+    def ilt_solve_f64(self, target, phi, params: Params, trace=None):
+        """The DSO loop in FP64, in place on phi (float64 [N, N])."""
+        import torch
+        pc = params.to_c()
+        rep = _Report()
+        tr = None
+        if trace is not None:
+            tr = _ptr(trace, torch.float64, (params.iters, TRACE_W), "trace", self.device)
+        _check(load_library().ilt_solve_f64(self._h, self._img(target, "target", torch.uint8),
+                                            self._img(phi, "phi", torch.float64), ctypes.byref(pc),
+                                            ctypes.byref(rep), tr))
+        return dict(iters_done=rep.iters_done, status=rep.status, loss=rep.loss, l2=rep.l2, pvb=rep.pvb,
+                    flips=rep.flips)
 
     def get_tuning(self) -> dict:
         t = _Tuning()
@@ -423,6 +472,18 @@ class Batch:
 def _stream_of(t):
     import torch
     return _VP(torch.cuda.current_stream(t.device).cuda_stream)
+
+
+def shifted_heaviside(phi, dh: float, out=None):
+    """H(phi + dh) as float32 0/1 of the same shape (H(z) = 1 for z >= 0)."""
+    import torch
+    if out is None:
+        out = torch.empty_like(phi)
+    shp = tuple(phi.shape)
+    _check(load_library().ilt_shifted_heaviside(_ptr(phi, torch.float32, shp, "phi", phi.device), float(dh),
+                                                int(phi.numel()), _ptr(out, torch.float32, shp, "out", phi.device),
+                                                _stream_of(phi)))
+    return out
 
 
 def layout_grid(H: int, W: int, N: int, halo: int):

@@ -309,20 +309,30 @@ BATCH_SIZES = (512, 1024, 2048)
 BATCH_FIELD_NM = 2048.0
 
 
+def batch_clip(N: int, seed: int):
+    """(target uint8 [N,N], params dict) of one clip of the batched workload:
+    a 2048 nm field at N pixels (pitch 2048/N nm), 50 iterations, three
+    corners, TSDF bounds in that pitch's pixels."""
+    pitch = BATCH_FIELD_NM / N
+    spec = ClipSpec(N=N, pitch_nm=pitch, n_min=1, n_max=1, width_nm=(40.0, 80.0),
+                    length_nm=(80.0, 400.0), spacing_nm=60.0, margin_nm=256.0, manhattan=True,
+                    density=(0.05, 0.25))
+    return gen_clip(spec, seed), _params(pitch, THREE_CORNERS, 50)
+
+
+def batch_optics():
+    """The 35 x 35, K = 24 kernel sets (nominal, 25 nm defocus) of the
+    2048 nm field shared by every clip of the batched workload."""
+    return build_optics(N=2048, pitch_nm=1.0, P=35, K=24, defocus_sets=(0.0, 25.0))
+
+
 def batch_inputs(n_clips: int = 64, seed: int = 1234, sizes=BATCH_SIZES):
     """[(target uint8 [N,N], params dict)] for n_clips clips with N drawn
     uniformly from `sizes`, plus (kernels, weights) shared by all."""
     rng = np.random.default_rng(seed)
     Ns = rng.choice(np.asarray(sizes), size=n_clips)
-    clips = []
-    for i, N in enumerate(Ns):
-        N = int(N)
-        pitch = BATCH_FIELD_NM / N
-        spec = ClipSpec(N=N, pitch_nm=pitch, n_min=1, n_max=1, width_nm=(40.0, 80.0),
-                        length_nm=(80.0, 400.0), spacing_nm=60.0, margin_nm=256.0, manhattan=True,
-                        density=(0.05, 0.25))
-        clips.append((gen_clip(spec, seed * 1000 + i), _params(pitch, THREE_CORNERS, 50)))
-    k, w = build_optics(N=2048, pitch_nm=1.0, P=35, K=24, defocus_sets=(0.0, 25.0))
+    clips = [batch_clip(int(N), seed * 1000 + i) for i, N in enumerate(Ns)]
+    k, w = batch_optics()
     return clips, k, w
 
 

@@ -135,3 +135,53 @@ def test_batch_rejects_bad_clips(ilt):
     with pytest.raises(ilt.IltError):
         ilt.Batch(H, w, (64,), max_clips=2, n_lanes=5)
     batch.close()
+
+
+def test_batch_c3_shapes_against_oracle(ilt):
+    """The batched workload's own shapes: a 512^2 and a 1024^2 clip of one
+    2048 nm field (pitch 4 and 2 nm; 35 x 35 window, K = 24, nominal and
+    defocus kernel sets, three corners, TSDF bounds in each pitch's pixels),
+    one teacher-forced iteration each in one batched call, against the FP64
+    oracle's iteration (Sec. II-B imaging, Sec. III-A DSO step), and bit for
+    bit against per-clip ilt_solve."""
+    from oracle import edt as o_edt
+    from oracle import solve as o_solve
+    from paper_2303_12529_amd.inputs import batch_clip, batch_optics
+    H, w = batch_optics()
+    cases = [(512, 7001), (1024, 7002)]
+    data, ref = [], []
+    for N, seed in cases:
+        Z, prm = batch_clip(N, seed)
+        prm1 = dict(prm, iters=1, reinit_every=0)
+        phi0, _, _ = o_edt.tsdf_from_mask(Z, prm["d_lower"], prm["d_upper"])
+        phi0 = phi0.astype(np.float32)
+        _say("c3 clip", N, seed, "density", float(Z.mean()))
+        data.append((torch.as_tensor(Z).cuda(), torch.as_tensor(phi0).cuda(),
+                     ilt.Params.from_dict(prm1, init_mode=1),
+                     torch.zeros((1, ilt.TRACE_W), dtype=torch.float64, device="cuda")))
+        ref.append((Z, phi0, prm1))
+    batch = ilt.Batch(H, w, (512, 1024), max_clips=2, n_lanes=2)
+    reps = batch.solve(data)
+    for (Z, phi0, prm1), (_, phi, _, tr), rep in zip(ref, data, reps):
+        N = Z.shape[0]
+        out = phi.cpu().numpy().astype(np.float64)
+        row_g = tr.cpu().numpy()[0]
+        phi_r, row = o_solve.iteration(phi0.astype(np.float64), Z, H, w, prm1)
+        err = np.abs(out - phi_r).max()
+        _say("  N", N, "loss", row_g[1], row["loss"], "m_v", row_g[5], row["m_v"], "l2", row_g[2], row["l2"],
+             "pvb", row_g[3], row["pvb"], "phi err", err)
+        assert abs(row_g[1] - row["loss"]) <= 1e-5 * abs(row["loss"])
+        assert abs(row_g[5] - row["m_v"]) <= 1e-4 * row["m_v"]
+        assert abs(row_g[2] - row["l2"]) <= max(2, 1e-4 * row["l2"])
+        assert abs(row_g[3] - row["pvb"]) <= max(2, 1e-4 * max(row["pvb"], 1))
+        assert err <= 1e-3 * prm1["eta"] + 4 * np.spacing(np.float32(np.abs(phi_r).max()))
+        # the same clip alone through ilt_solve: identical bits
+        ctx = ilt.Context(H, w, N)
+        phi1 = torch.as_tensor(phi0).cuda()
+        tr1 = torch.zeros((1, ilt.TRACE_W), dtype=torch.float64, device="cuda")
+        rep1 = ctx.ilt_solve(torch.as_tensor(Z).cuda(), phi1, ilt.Params.from_dict(prm1, init_mode=1), trace=tr1)
+        assert torch.equal(phi1, phi)
+        assert np.array_equal(tr1.cpu().numpy()[:, :7], tr.cpu().numpy()[:, :7])
+        assert (rep1["l2"], rep1["pvb"], rep1["loss"]) == (rep["l2"], rep["pvb"], rep["loss"])
+        ctx.close()
+    batch.close()

@@ -54,7 +54,7 @@ int main(void) {
   printf("%zu %zu %zu %d %d %d\n", sizeof(ilt_clip), offsetof(ilt_clip, d_trace), offsetof(ilt_clip, params),
          ILT_BATCH_MAX_SIZES, ILT_BATCH_MAX_LANES, ILT_BATCH_MAX_CLIPS);
   printf("%zu %zu %zu\n", sizeof(ilt_tuning), offsetof(ilt_tuning, xcd_remap), offsetof(ilt_tuning, st_xsplit));
-  printf("%zu\n", offsetof(ilt_params, optimizer));
+  printf("%zu %zu\n", offsetof(ilt_params, optimizer), offsetof(ilt_params, iter0));
   return 0;
 }
 '''
@@ -81,6 +81,7 @@ int main(void) {
     assert vals[15] == ctypes.sizeof(ilt._Tuning) and vals[16] == ilt._Tuning.xcd_remap.offset
     assert vals[17] == ilt._Tuning.st_xsplit.offset
     assert vals[18] == ilt._Params.optimizer.offset
+    assert vals[19] == ilt._Params.iter0.offset
 
 
 def test_params_roundtrip_and_validation():
