@@ -201,6 +201,20 @@ int levelset_step(ilt_ctx *ctx, float *d_phi, const float *d_vel, const float *d
 int edt_reinit(ilt_ctx *ctx, const float *d_phi, const unsigned char *d_mask,
                float *d_phi_out, int *d_sqdist, const ilt_params *params);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * TSDF as edt_reinit, bit for bit, with no context.  N x N (1 <= N <= 4096;
+ * larger N -> ILT_EINVAL), exactly one of d_phi (device fp32 [N][N], 4-byte
+ * aligned; mask = [phi <= 0]) and d_mask (device bytes [N][N], nonzero =
+ * inside), d_lower < 0 < d_upper (pixels), d_phi_out and d_sqdist as for
+ * edt_reinit.  stream: a HIP stream of the current device (NULL = its null
+ * stream).  Nothing is allocated: the EDT's scratch is a static 6 MiB device
+ * array (one per device, held until the process ends), whose address is
+ * looked up on the first call on each device.  Calls that overlap on one
+ * device share that array and race; order them on one stream.  Async. */
+int edt_reinit_noalloc(int N, const float *d_phi, const unsigned char *d_mask, float d_lower, float d_upper,
+                       float *d_phi_out, int *d_sqdist, void *stream);
+
 /* Sec. III-A/B: the plain DSO loop, params->iters iterations, entirely on the
  * device.  d_target [N][N] bytes; d_phi [N][N] in (used when init_mode = 1)
  * and out (final phi).  h_report: final loss / L2 / PVB of [phi_T <= 0].

@@ -8,6 +8,7 @@
 #include <cstdint>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -610,6 +611,72 @@ extern "C" int edt_reinit(ilt_ctx *c, const float *d_phi, const unsigned char *d
     if (!p) return fail(ILT_EINVAL, "params is null");
     if (!(p->d_lower < 0.f) || !(p->d_upper > 0.f)) return fail(ILT_EINVAL, "need d_lower < 0 < d_upper");
     HIPCHK(launch_edt(c, d_phi, d_mask, d_phi_out, d_sqdist, p->d_lower, p->d_upper));
+    return ILT_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Allocation-free TSDF: the EDT chain of edt_reinit on a scratch area that
+// lives in the code object instead of a context.  The class bits and the
+// per-word nearest rows for the largest side (ILT_MAX_N) take
+// NOALLOC_EDT_BYTES = 6 MiB; each device the library runs on holds its own
+// copy until the process ends.  Every byte the kernels read from it is
+// written earlier in the same call, so nothing needs clearing, but calls that
+// overlap on one device (several streams, several threads) share it and race.
+namespace {
+constexpr size_t NOALLOC_EDT_BYTES =
+    (size_t)((ILT_MAX_N + 31) / 32) * ILT_MAX_N * (sizeof(uint32_t) + 4 * sizeof(int16_t));
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex g_noalloc_mu;
+void *g_noalloc_ptr[NOALLOC_MAX_DEVICES];
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[NOALLOC_EDT_BYTES];
+
+namespace {
+// The device address of this device's copy of `scratch`, looked up once per
+// device (the host-side name is not a device address).
+int noalloc_scratch(void **out) {
+    int dev = -1;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= NOALLOC_MAX_DEVICES)
+        return fail(ILT_EUNSUPPORTED, "device %d is beyond the %d devices the scratch table holds", dev,
+                    NOALLOC_MAX_DEVICES);
+    std::lock_guard<std::mutex> lock(g_noalloc_mu);
+    if (!g_noalloc_ptr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(ILT_EDEVICE, "hipGetSymbolAddress(scratch) on device %d: %s", dev, hipGetErrorString(e));
+        g_noalloc_ptr[dev] = p;
+    }
+    *out = g_noalloc_ptr[dev];
+    return ILT_OK;
+}
+}  // namespace
+
+extern "C" int edt_reinit_noalloc(int N, const float *d_phi, const unsigned char *d_mask, float d_lower,
+                                  float d_upper, float *d_phi_out, int *d_sqdist, void *stream) {
+    int r;
+    if (N < 1 || N > ILT_MAX_N)
+        return fail(ILT_EINVAL, "N=%d outside [1, %d], the largest side the %zu-byte static scratch holds", N,
+                    ILT_MAX_N, NOALLOC_EDT_BYTES);
+    if ((d_phi == nullptr) == (d_mask == nullptr))
+        return fail(ILT_EINVAL, "exactly one of d_phi and d_mask must be given");
+    if (d_phi && (r = check_ptr(d_phi, "d_phi"))) return r;
+    if ((r = check_ptr(d_phi_out, "d_phi_out"))) return r;
+    if (d_sqdist && !aligned(d_sqdist, 4)) return fail(ILT_EINVAL, "d_sqdist is not 4-byte aligned");
+    if (!(d_lower < 0.f) || !(d_upper > 0.f)) return fail(ILT_EINVAL, "need d_lower < 0 < d_upper");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (st) {
+        int cur = -1, sdev = -1;
+        HIPCHK(hipGetDevice(&cur));
+        HIPCHK(hipStreamGetDevice(st, &sdev));
+        if (sdev != cur)
+            return fail(ILT_EINVAL, "stream belongs to device %d but device %d is current", sdev, cur);
+    }
+    void *buf = nullptr;
+    if ((r = noalloc_scratch(&buf))) return r;
+    HIPCHK(launch_edt_raw(st, N, d_phi, d_mask, d_phi_out, d_sqdist, d_lower, d_upper, buf));
     return ILT_OK;
 }
 

@@ -96,6 +96,7 @@ def load_library(path: str = LIB_PATH):
         "resist_loss": [_VP, _VP, _VP, ctypes.POINTER(_Params), _VP, _VP],
         "levelset_step": [_VP, _VP, _VP, _VP, ctypes.POINTER(_Params), _VP],
         "edt_reinit": [_VP, _VP, _VP, _VP, _VP, ctypes.POINTER(_Params)],
+        "edt_reinit_noalloc": [ctypes.c_int, _VP, _VP, ctypes.c_float, ctypes.c_float, _VP, _VP, _VP],
         "ilt_solve": [_VP, _VP, _VP, ctypes.POINTER(_Params), ctypes.POINTER(_Report), _VP],
         "ilt_solve_modulated": [_VP, _VP, _VP, _VP, ctypes.POINTER(_Params), ctypes.POINTER(_Report), _VP],
         "ilt_profile": [_VP, ctypes.c_int],
@@ -484,6 +485,23 @@ def shifted_heaviside(phi, dh: float, out=None):
                                                 int(phi.numel()), _ptr(out, torch.float32, shp, "out", phi.device),
                                                 _stream_of(phi)))
     return out
+
+
+def edt_reinit_noalloc(N: int, d_lower: float, d_upper: float, phi=None, mask=None, phi_out=None, sqdist=None):
+    """TSDF of [phi <= 0] or of mask (N x N) without a context or any device
+    allocation by the library (its scratch is a static device array)."""
+    import torch
+    src = phi if phi is not None else mask
+    if src is None:
+        raise ValueError("give phi or mask")
+    dev = src.device
+    if phi_out is None:
+        phi_out = torch.empty((N, N), dtype=torch.float32, device=dev)
+    _check(load_library().edt_reinit_noalloc(
+        int(N), _ptr(phi, torch.float32, (N, N), "phi", dev), _ptr(mask, torch.uint8, (N, N), "mask", dev),
+        float(d_lower), float(d_upper), _ptr(phi_out, torch.float32, (N, N), "phi_out", dev),
+        _ptr(sqdist, torch.int32, (2, N, N), "sqdist", dev), _stream_of(phi_out)))
+    return phi_out
 
 
 def layout_grid(H: int, W: int, N: int, halo: int):
