@@ -515,10 +515,12 @@ __global__ __launch_bounds__(256) void k_edt_bits(const TP *__restrict__ phi, co
                                      part[3][threadIdx.x];
 }
 
+constexpr int EDT_CB = 16;        // columns per block of the column pass
+
 // Column pass, step 2: for every column x and word w, the nearest rows of
 // each class strictly above the word and strictly below it:
 // info[0][w][x] = class 1 above, [1] class 0 above, [2] class 1 below,
-// [3] class 0 below (-1: none).  Block = 64 columns x every word: the
+// [3] class 0 below (-1: none).  Block = EDT_CB columns x every word: the
 // words sit in LDS, and per column a bit mask of the words holding each
 // class turns "nearest word above / below" into one bit scan.
 // Up to 128 words (N <= 4096).
@@ -548,19 +550,21 @@ __device__ __forceinline__ int word_above(const unsigned long long (&m)[2], int 
 
 __global__ __launch_bounds__(256) void k_edt_colinfo(const uint32_t *__restrict__ colbits, int N,
                                                      int16_t *__restrict__ info) {
-    extern __shared__ uint32_t wsh[];                       // [W][64]
-    __shared__ unsigned long long any1[64][2], any0[64][2];
+    // block = EDT_CB columns; the 256 / EDT_CB thread rows step over the words
+    constexpr int WL = 256 / EDT_CB;
+    extern __shared__ uint32_t wsh[];                       // [W][EDT_CB]
+    __shared__ unsigned long long any1[EDT_CB][2], any0[EDT_CB][2];
     const int W = (N + 31) / 32;
-    const int c = threadIdx.x & 63, v0 = threadIdx.x >> 6;
-    const int x = blockIdx.x * 64 + c;
-    if (threadIdx.x < 128) {
+    const int c = threadIdx.x % EDT_CB, v0 = threadIdx.x / EDT_CB;
+    const int x = blockIdx.x * EDT_CB + c;
+    if (threadIdx.x < 2 * EDT_CB) {
         any1[threadIdx.x >> 1][threadIdx.x & 1] = 0ull;
         any0[threadIdx.x >> 1][threadIdx.x & 1] = 0ull;
     }
     __syncthreads();
-    for (int v = v0; v < W; v += 4) {
+    for (int v = v0; v < W; v += WL) {
         const uint32_t wd = x < N ? colbits[(size_t)v * N + x] : 0u;
-        wsh[v * 64 + c] = wd;
+        wsh[v * EDT_CB + c] = wd;
         if (x < N) {
             if (wd) atomicOr(&any1[c][v >> 6], 1ull << (v & 63));
             if (~wd & valid_bits(v, N)) atomicOr(&any0[c][v >> 6], 1ull << (v & 63));
@@ -570,16 +574,16 @@ __global__ __launch_bounds__(256) void k_edt_colinfo(const uint32_t *__restrict_
     if (x >= N) return;
     const unsigned long long m1[2] = {any1[c][0], any1[c][1]}, m0[2] = {any0[c][0], any0[c][1]};
     const size_t plane = (size_t)W * N;
-    for (int v = v0; v < W; v += 4) {
+    for (int v = v0; v < W; v += WL) {
         int r[4];
         int u = word_below(m1, v);
-        r[0] = u < 0 ? -1 : 32 * u + 31 - __clz(wsh[u * 64 + c]);
+        r[0] = u < 0 ? -1 : 32 * u + 31 - __clz(wsh[u * EDT_CB + c]);
         u = word_below(m0, v);
-        r[1] = u < 0 ? -1 : 32 * u + 31 - __clz(~wsh[u * 64 + c] & valid_bits(u, N));
+        r[1] = u < 0 ? -1 : 32 * u + 31 - __clz(~wsh[u * EDT_CB + c] & valid_bits(u, N));
         u = word_above(m1, v);
-        r[2] = u < 0 ? -1 : 32 * u + __ffs(wsh[u * 64 + c]) - 1;
+        r[2] = u < 0 ? -1 : 32 * u + __ffs(wsh[u * EDT_CB + c]) - 1;
         u = word_above(m0, v);
-        r[3] = u < 0 ? -1 : 32 * u + __ffs(~wsh[u * 64 + c] & valid_bits(u, N)) - 1;
+        r[3] = u < 0 ? -1 : 32 * u + __ffs(~wsh[u * EDT_CB + c] & valid_bits(u, N)) - 1;
         const size_t o = (size_t)v * N + x;
 #pragma unroll
         for (int q = 0; q < 4; ++q) info[q * plane + o] = (int16_t)r[q];
@@ -608,50 +612,90 @@ __device__ float sqrt_minus_half(int D) {
 // g_c(x')^2 + (x - x')^2.  In the dual, column x' is the point
 // (x', x'^2 + g^2) and D_c(x) - x^2 is the minimum of c' - 2 x x' over the
 // points, attained on their lower convex hull; hull vertices are the
-// columns whose parabola is lowest somewhere.
-//   1. each lane builds the hull of its band of m = N/64 columns (a stack:
-//      a vertex is dropped while it lies on or above the chord of its
-//      neighbours; exact in 64-bit integers);
-//   2. six rounds merge adjacent hulls pairwise: the first lane of a pair
-//      drops vertices at the junction while one is on or above the chord of
-//      its neighbours across it (every drop removes a non-vertex of the
-//      union, and once the junction is convex the chain is the union's
-//      hull), then the pair's lanes move the right hull's remainder next to
-//      the left one's;
-//   3. the optimal vertex is non-decreasing in x: each lane finds the one
-//      of its first pixel by bisection (the differences of c' - 2 x x'
-//      along the hull change sign once) and walks forward from there.
+// columns whose parabola is lowest somewhere.  Lane l owns the band of M
+// columns [l M, l M + M) (64 M >= N).
+//   1. each lane builds the hull of its band as a stack (the top vertex is
+//      dropped while it lies on or above the chord from the one below it to
+//      the new column; exact in 64-bit integers) and keeps it as a chain in
+//      LDS; a range [r0, r1) of the chain stays alive;
+//   2. six rounds merge adjacent groups of bands pairwise.  The merged
+//      hull is the left group's chain up to a vertex a and the right
+//      group's from a vertex b on (the bridge).  From a = the left group's
+//      last vertex, b = the right group's first one, alternately b becomes
+//      the tangent point from a on the right group (least slope, the
+//      farthest on ties) and a the tangent point from b on the left group
+//      (greatest slope, the nearest on ties) until neither moves: each lane
+//      finds its own chain's tangent point by bisection and the pair's lanes
+//      reduce over their group; a only moves left and b only right, so the
+//      iteration ends, at the bridge.  Lanes then trim their ranges;
+//   3. each surviving vertex s marks, at the first pixel where it is at
+//      least as low as its predecessor p on the hull (the exact integer
+//      ceiling of (c_s - c_p) / 2 (s - p)), itself; along the hull these
+//      pixels do not decrease, so the owner of pixel x is the marked vertex
+//      of largest column at or before x: a prefix maximum over the row.
 // Every value is an exact integer, so the result is unique.  A class that
 // is absent from the whole image leaves D = FBIG.
 constexpr int FBIG = 1 << 30;
-constexpr uint16_t GNONE = 0xFFFFu;
+constexpr int GNONE = 0xFFFF;
 
-__device__ __forceinline__ long long hull_c(const uint16_t *g, int s) {
-    const long long gs = g[s];
-    return (long long)s * s + gs * gs;
+// a vertex as one word: column << 16 | g (so that comparing words compares
+// columns); -1: none
+__device__ __forceinline__ int vx(int e) { return e >> 16; }
+__device__ __forceinline__ int vg(int e) { return e & 0xFFFF; }
+__device__ __forceinline__ int vc(int e) { return vx(e) * vx(e) + vg(e) * vg(e); }
+
+// is the point (b, cb) on or above the chord from (a, ca) to (q, cq), a < b < q?
+__device__ __forceinline__ bool hull_above(int a, int ca, int b, int cb, int q, int cq) {
+    return (long long)(cb - ca) * (q - b) >= (long long)(cq - cb) * (b - a);
+}
+// slope(P, U) <= slope(P, V) for U, V right of P
+__device__ __forceinline__ bool slope_le_from(int xp, int cp, int u, int v) {
+    return (long long)(vc(u) - cp) * (vx(v) - xp) <= (long long)(vc(v) - cp) * (vx(u) - xp);
+}
+// slope(U, Q) >= slope(V, Q) for U, V left of Q
+__device__ __forceinline__ bool slope_ge_to(int u, int v, int xq, int cq) {
+    return (long long)(cq - vc(u)) * (xq - vx(v)) >= (long long)(cq - vc(v)) * (xq - vx(u));
+}
+// tangent candidates: from P on the right (least slope, larger column on
+// ties) and to Q on the left (greatest slope, smaller column on ties)
+__device__ __forceinline__ bool better_from(int xp, int cp, int u, int v) {
+    if (u < 0) return false;
+    if (v < 0) return true;
+    const long long l = (long long)(vc(u) - cp) * (vx(v) - xp), r = (long long)(vc(v) - cp) * (vx(u) - xp);
+    return l < r || (l == r && vx(u) > vx(v));
+}
+__device__ __forceinline__ bool better_to(int xq, int cq, int u, int v) {
+    if (u < 0) return false;
+    if (v < 0) return true;
+    const long long l = (long long)(cq - vc(u)) * (xq - vx(v)), r = (long long)(cq - vc(v)) * (xq - vx(u));
+    return l > r || (l == r && vx(u) < vx(v));
 }
 
-// is b on or above the chord from a to q (a < b < q)?
-__device__ __forceinline__ bool hull_drop(const uint16_t *g, int a, int b, int q) {
-    const long long ca = hull_c(g, a), cb = hull_c(g, b), cq = hull_c(g, q);
-    return (cb - ca) * (long long)(q - b) >= (cq - cb) * (long long)(b - a);
+// exclusive prefix maximum over the 64 lanes of a wave (lane 0 gets -1)
+__device__ __forceinline__ int wave_excl_max(int v) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int d = 1; d < 64; d *= 2) {
+        const int u = __shfl_up(v, d, 64);
+        if (lane >= d) v = max(v, u);
+    }
+    const int ex = __shfl_up(v, 1, 64);
+    return lane == 0 ? -1 : ex;
 }
 
-__device__ __forceinline__ int hull_val(const uint16_t *g, int s, int x) {
-    const int gs = g[s];
-    return gs * gs + (x - s) * (x - s);
-}
-
-template <typename TP>
+template <int M, typename TP>
 __global__ __launch_bounds__(128) void k_edt_rows_env(const uint32_t *__restrict__ colbits,
                                                       const int16_t *__restrict__ info, int N, float d_lower,
                                                       float d_upper, TP *__restrict__ phi_out,
                                                       int *__restrict__ sqdist) {
-    extern __shared__ int esm[];
-    int *Dout = esm;                                              // [N]
-    uint16_t *gsh = reinterpret_cast<uint16_t *>(Dout + N);        // [2][N]
-    int16_t *env = reinterpret_cast<int16_t *>(gsh + 2 * N);       // [2][N]
-    __shared__ int cnt[2][64], mia[2][64], mib[2][64];
+    // per class: g of every column (halfwords, M + 2 per band) and the band
+    // chains, later the hull marks and then D in the same storage (words,
+    // M + 1 per band).  The pads put the 64 lanes' equal band offsets in
+    // different banks.
+    constexpr int S16 = 64 * (M + 2), S32 = 64 * (M + 1);
+    __shared__ uint16_t gsh[2 * S16];
+    __shared__ int chn[2][S32];
+    __shared__ int need[2];
     const int y = blockIdx.x;
     const int lane = threadIdx.x & 63, cls = threadIdx.x >> 6;
     const int W = (N + 31) / 32;
@@ -659,116 +703,244 @@ __global__ __launch_bounds__(128) void k_edt_rows_env(const uint32_t *__restrict
     const uint32_t le = (b == 31) ? 0xFFFFFFFFu : ((2u << b) - 1u);
     const uint32_t vm = valid_bits(w, N);
     const size_t plane = (size_t)W * N;
-    // g_c of every column of this row from the column bits and the nearest
-    // class rows above and below this row's word
-    for (int x = threadIdx.x; x < N; x += 128) {
-        const size_t o = (size_t)w * N + x;
-        const uint32_t w1 = colbits[o], w0 = ~w1 & vm;
-        const int up1 = info[o], up0 = info[plane + o], dn1 = info[2 * plane + o], dn0 = info[3 * plane + o];
+    // (positions are never negative)
+    constexpr int LM = M >= 64 ? 6 : M >= 32 ? 5 : M >= 16 ? 4 : M >= 8 ? 3 : M >= 4 ? 2 : M >= 2 ? 1 : 0;
+    auto a16 = [](int p) { return p + 2 * (p >> LM); };
+    auto a32 = [](int p) { return p + (p >> LM); };
+    // 0. g_c of every column of this row from the column bits and the
+    // nearest class rows above and below this row's word (all loads issued
+    // first).  Class c is needed where pixels of the other class lie (or
+    // everywhere when squared distances are written).
+    if (threadIdx.x < 2) need[threadIdx.x] = sqdist != nullptr;
+    __syncthreads();
+    {
+        bool any_in = false, any_out = false;
+        constexpr int R = (64 * M + 127) / 128;
+        uint32_t wv[R];
+        int16_t iv[R][4];
 #pragma unroll
-        for (int c = 0; c < 2; ++c) {
-            const uint32_t word = c ? w1 : w0;
-            const int up = c ? up1 : up0, dn = c ? dn1 : dn0;
-            const uint32_t a = word & le, bl = word & ~le;
-            int best = 0x7FFFFFFF;
-            if (a) best = b - (31 - __clz(a));
-            else if (up >= 0) best = y - up;
-            if (bl) best = min(best, (__ffs(bl) - 1) - b);
-            else if (dn >= 0) best = min(best, dn - y);
-            gsh[c * N + x] = best == 0x7FFFFFFF ? GNONE : (uint16_t)best;
+        for (int r = 0; r < R; ++r) {
+            const int x = threadIdx.x + 128 * r;
+            if (x < N) {
+                const size_t o = (size_t)w * N + x;
+                wv[r] = colbits[o];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) iv[r][q] = info[q * plane + o];
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int x = threadIdx.x + 128 * r;
+            if (x >= N) continue;
+            const uint32_t w1 = wv[r], w0 = ~w1 & vm;
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                const uint32_t word = c ? w1 : w0;
+                const int up = iv[r][c ? 0 : 1], dn = iv[r][c ? 2 : 3];
+                const uint32_t a = word & le, bl = word & ~le;
+                int best = 0x7FFFFFFF;
+                if (a) best = b - (31 - __clz(a));
+                else if (up >= 0) best = y - up;
+                if (bl) best = min(best, (__ffs(bl) - 1) - b);
+                else if (dn >= 0) best = min(best, dn - y);
+                gsh[c * S16 + a16(x)] = best == 0x7FFFFFFF ? (uint16_t)GNONE : (uint16_t)best;
+                if (c == 1) {
+                    any_in |= best == 0;
+                    any_out |= best != 0;
+                }
+            }
+        }
+        if (any_in) need[0] = 1;
+        if (any_out) need[1] = 1;
+    }
+    __syncthreads();
+    const bool work = need[cls] != 0;      // uniform over the wave
+    const int lo = lane * M;
+    int *ch = chn[cls];
+    int r0 = 0, r1 = 0;
+    // 1. the hull of this lane's band, as a chain at ch[a32(lo + k)]
+    if (work) {
+        // one event per step (skip an empty column, drop the top, or push),
+        // so that a wave runs at most 2 M steps however its lanes' drops fall
+        const uint16_t *g = gsh + cls * S16;
+        const int hi = min(N, lo + M);
+        int k = 0, s1 = 0, s2 = 0, c1 = 0, c2 = 0;
+        int q = lo, gq = q < hi ? (int)g[a16(q)] : GNONE;
+        while (q < hi) {
+            const int cq = q * q + gq * gq;
+            if (gq != GNONE && k >= 2 && hull_above(s2, c2, s1, c1, q, cq)) {
+                s1 = s2;
+                c1 = c2;
+                --k;
+                if (k >= 2) {
+                    const int e = ch[a32(lo + k - 2)];
+                    s2 = vx(e);
+                    c2 = vc(e);
+                }
+                continue;
+            }
+            if (gq != GNONE) {
+                ch[a32(lo + k)] = (q << 16) | gq;
+                s2 = s1;
+                c2 = c1;
+                s1 = q;
+                c1 = cq;
+                ++k;
+            }
+            ++q;
+            gq = q < hi ? (int)g[a16(q)] : GNONE;
+        }
+        r1 = k;
+    }
+    __syncthreads();
+    // 2. pairwise merges; chains are read-only from here and every lane's
+    // range lives in its registers, so no barrier is needed between rounds
+    for (int gs = 1; gs < 64 && work; gs *= 2) {
+        const bool left = (lane & gs) == 0;
+        const bool ne = r1 > r0;
+        int a = (left && ne) ? ch[a32(lo + r1 - 1)] : -1;
+        int bb = (!left && ne) ? ch[a32(lo + r0)] : 0x7FFFFFFF;
+#pragma unroll
+        for (int d = 1; d < 64; d *= 2) {
+            if (d < 2 * gs) {
+                a = max(a, __shfl_xor(a, d, 64));
+                bb = min(bb, __shfl_xor(bb, d, 64));
+            }
+        }
+        if (a < 0 || bb == 0x7FFFFFFF) continue;      // uniform over the pair's lanes
+        for (int it = 0; it < 4096; ++it) {
+            // b: tangent point from a on the right group
+            const int xa = vx(a), ca = vc(a);
+            int cand = -1;
+            if (!left && ne) {
+                int l = r0, h = r1 - 1;
+                while (l < h) {
+                    const int mid = (l + h + 1) >> 1;
+                    if (slope_le_from(xa, ca, ch[a32(lo + mid)], ch[a32(lo + mid - 1)])) l = mid;
+                    else h = mid - 1;
+                }
+                cand = ch[a32(lo + l)];
+            }
+#pragma unroll
+            for (int d = 1; d < 64; d *= 2) {
+                if (d < 2 * gs) {
+                    const int o = __shfl_xor(cand, d, 64);
+                    if (better_from(xa, ca, o, cand)) cand = o;
+                }
+            }
+            const int nb = cand;
+            // a: tangent point from b on the left group
+            const int xb = vx(nb), cb = vc(nb);
+            cand = -1;
+            if (left && ne) {
+                int l = r0, h = r1 - 1;
+                while (l < h) {
+                    const int mid = (l + h) >> 1;
+                    if (slope_ge_to(ch[a32(lo + mid)], ch[a32(lo + mid + 1)], xb, cb)) h = mid;
+                    else l = mid + 1;
+                }
+                cand = ch[a32(lo + l)];
+            }
+#pragma unroll
+            for (int d = 1; d < 64; d *= 2) {
+                if (d < 2 * gs) {
+                    const int o = __shfl_xor(cand, d, 64);
+                    if (better_to(xb, cb, o, cand)) cand = o;
+                }
+            }
+            const int na = cand;
+            const bool done = na == a && nb == bb;
+            a = na;
+            bb = nb;
+            if (done) break;
+        }
+        // trim: the left group keeps columns <= a, the right one >= b
+        if (ne) {
+            if (left) {
+                const int xa = vx(a);
+                if (vx(ch[a32(lo + r0)]) > xa) {
+                    r1 = r0;
+                } else if (vx(ch[a32(lo + r1 - 1)]) > xa) {
+                    int l = r0, h = r1 - 1;                  // last entry <= xa
+                    while (l < h) {
+                        const int mid = (l + h + 1) >> 1;
+                        if (vx(ch[a32(lo + mid)]) <= xa) l = mid;
+                        else h = mid - 1;
+                    }
+                    r1 = l + 1;
+                }
+            } else {
+                const int xb = vx(bb);
+                if (vx(ch[a32(lo + r1 - 1)]) < xb) {
+                    r0 = r1;
+                } else if (vx(ch[a32(lo + r0)]) < xb) {
+                    int l = r0, h = r1 - 1;                  // first entry >= xb
+                    while (l < h) {
+                        const int mid = (l + h) >> 1;
+                        if (vx(ch[a32(lo + mid)]) >= xb) h = mid;
+                        else l = mid + 1;
+                    }
+                    r0 = l;
+                }
+            }
+        }
+    }
+    // 3. marks, then the owner of every pixel and its D, in the chain
+    // storage once every lane holds its surviving vertices in registers
+    int alive[M];
+#pragma unroll
+    for (int i = 0; i < M; ++i) alive[i] = (work && r0 + i < r1) ? ch[a32(lo + r0 + i)] : -1;
+    const int pred = wave_excl_max(r1 > r0 ? ch[a32(lo + r1 - 1)] : -1);
+    __syncthreads();
+    if (work) {
+#pragma unroll
+        for (int i = 0; i < M; ++i) ch[a32(lo + i)] = -1;
+    }
+    __syncthreads();
+    if (work) {
+        int p = pred;
+#pragma unroll
+        for (int i = 0; i < M; ++i) {
+            const int e = alive[i];
+            if (e < 0) break;
+            int start = 0;
+            if (p >= 0) {
+                const int num = vc(e) - vc(p), den = 2 * (vx(e) - vx(p));
+                start = num >= 0 ? (num + den - 1) / den : -((-num) / den);
+                start = max(start, 0);
+            }
+            if (start < N) atomicMax(&ch[a32(start)], e);
+            p = e;
         }
     }
     __syncthreads();
-    const uint16_t *g = gsh + cls * N;
-    int16_t *e = env + cls * N;
-    const int m = (N + 63) / 64;
-    // 1. the hull of this lane's band
-    {
-        const int lo = lane * m, hi = min(N, lo + m);
-        int k = -1;
-        for (int q = lo; q < hi; ++q) {
-            if (g[q] == GNONE) continue;
-            while (k >= 1 && hull_drop(g, e[lo + k - 1], e[lo + k], q)) --k;
-            e[lo + (++k)] = (int16_t)q;
+    if (work) {
+        int pre[M];
+        int r = -1;
+#pragma unroll
+        for (int i = 0; i < M; ++i) {
+            r = max(r, ch[a32(lo + i)]);
+            pre[i] = r;
         }
-        cnt[cls][lane] = k + 1;
-    }
-    __syncthreads();
-    // 2. pairwise merges
-    for (int gs = 1; gs < 64; gs *= 2) {
-        const int A = lane & ~(2 * gs - 1), B = A + gs;
-        if (lane == A) {
-            const int sA = A * m, sB = B * m, nA = cnt[cls][A], nB = cnt[cls][B];
-            int ia = nA - 1, ib = 0;
-            if (nA > 0 && nB > 0) {
-                for (;;) {
-                    if (ia >= 1 && hull_drop(g, e[sA + ia - 1], e[sA + ia], e[sB + ib])) {
-                        --ia;
-                        continue;
-                    }
-                    if (ib + 1 < nB && hull_drop(g, e[sA + ia], e[sB + ib], e[sB + ib + 1])) {
-                        ++ib;
-                        continue;
-                    }
-                    break;
-                }
-            }
-            mia[cls][A] = ia;
-            mib[cls][A] = ib;
-        }
-        __syncthreads();
-        {
-            // the pair's lanes move B's remainder behind A's kept prefix; the
-            // destination never lies above the source, and every load of a
-            // round precedes its stores (one wave), so nothing is overwritten
-            // before it is read
-            const int ia = mia[cls][A], ib = mib[cls][A], nB = cnt[cls][B];
-            const int dst = A * m + ia + 1, src = B * m + ib, n = nB - ib;
-            for (int i = lane - A; i < n; i += 2 * gs) e[dst + i] = e[src + i];
-        }
-        __syncthreads();
-        if (lane == A) cnt[cls][A] = mia[cls][A] + 1 + cnt[cls][B] - mib[cls][A];
-        __syncthreads();
-    }
-    // 3. queries: D_c for every pixel of this lane's band
-    {
-        const int n = cnt[cls][0];
-        const int lo = lane * m, hi = min(N, lo + m);
-        if (lo < hi) {
-            int j = 0;
-            if (n > 0) {
-                int a = 0, bb = n - 1;
-                while (a < bb) {
-                    const int mid = (a + bb) >> 1;
-                    if (hull_val(g, e[mid + 1], lo) >= hull_val(g, e[mid], lo)) bb = mid;
-                    else a = mid + 1;
-                }
-                j = a;
-            }
-            for (int x = lo; x < hi; ++x) {
-                int D = FBIG;
-                if (n > 0) {
-                    int v = hull_val(g, e[j], x);
-                    while (j + 1 < n) {
-                        const int v1 = hull_val(g, e[j + 1], x);
-                        if (v1 >= v) break;
-                        v = v1;
-                        ++j;
-                    }
-                    D = v;
-                }
-                // inside pixels (g_1 = 0) take D_0, outside ones D_1
-                const bool inside = gsh[N + x] == 0;
-                if (inside == (cls == 0)) Dout[x] = D;
-                if (sqdist)
-                    sqdist[(size_t)(1 - cls) * N * N + (size_t)y * N + x] = D >= FBIG ? 0x7FFFFFFF : D;
-            }
+        const int base = wave_excl_max(r);
+#pragma unroll
+        for (int i = 0; i < M; ++i) {
+            const int x = lo + i, o = max(base, pre[i]);
+            int D = FBIG;
+            if (o >= 0) D = vg(o) * vg(o) + (x - vx(o)) * (x - vx(o));
+            ch[a32(x)] = D;
         }
     }
     __syncthreads();
     for (int x = threadIdx.x; x < N; x += 128) {
-        const int D = Dout[x];
-        const bool inside = gsh[N + x] == 0;
+        // inside pixels (g_1 = 0) take D_0, outside ones D_1
+        const bool inside = gsh[S16 + a16(x)] == 0;
+        const int D = chn[inside ? 0 : 1][a32(x)];
+        if (sqdist) {
+            const int d1 = chn[1][a32(x)], d0 = chn[0][a32(x)];
+            sqdist[(size_t)y * N + x] = d1 >= FBIG ? 0x7FFFFFFF : d1;
+            sqdist[(size_t)N * N + (size_t)y * N + x] = d0 >= FBIG ? 0x7FFFFFFF : d0;
+        }
         if (sizeof(TP) == 4) {
             float v;
             if (inside) v = D >= FBIG ? d_lower : -sqrt_minus_half(D);
@@ -890,6 +1062,13 @@ hipError_t launch_finish_step(ilt_ctx *c, const double *part, int nblk, double *
     return hipGetLastError();
 }
 
+// columns per lane of the row pass: the smallest power of two M with 64 M >= N
+static int edt_band(int N) {
+    int M = 1;
+    while (64 * M < N) M *= 2;
+    return M;
+}
+
 size_t edt_scratch_bytes(int N) {
     const size_t W = (size_t)(N + 31) / 32;
     return W * N * sizeof(uint32_t) + 4 * W * N * sizeof(int16_t);
@@ -906,9 +1085,17 @@ hipError_t edt_any(hipStream_t st, int N, const TP *phi, const uint8_t *mask, TP
     const dim3 g1((N + 255) / 256, W);
     if (phi) k_edt_bits<true, TP><<<g1, 256, 0, st>>>(phi, nullptr, N, vec, colbits);
     else k_edt_bits<false, TP><<<g1, 256, 0, st>>>(nullptr, mask, N, vec, colbits);
-    k_edt_colinfo<<<(N + 63) / 64, 256, (size_t)W * 64 * sizeof(uint32_t), st>>>(colbits, N, info);
-    const size_t sm = (size_t)N * (sizeof(int) + 4 * sizeof(uint16_t));
-    k_edt_rows_env<TP><<<N, 128, sm, st>>>(colbits, info, N, d_lower, d_upper, phi_out, sqdist);
+    k_edt_colinfo<<<(N + EDT_CB - 1) / EDT_CB, 256, (size_t)W * EDT_CB * sizeof(uint32_t), st>>>(colbits, N, info);
+    // row pass: bands of M >= N / 64 columns per lane (a power of two)
+    switch (edt_band(N)) {
+    case 1: k_edt_rows_env<1, TP><<<N, 128, 0, st>>>(colbits, info, N, d_lower, d_upper, phi_out, sqdist); break;
+    case 2: k_edt_rows_env<2, TP><<<N, 128, 0, st>>>(colbits, info, N, d_lower, d_upper, phi_out, sqdist); break;
+    case 4: k_edt_rows_env<4, TP><<<N, 128, 0, st>>>(colbits, info, N, d_lower, d_upper, phi_out, sqdist); break;
+    case 8: k_edt_rows_env<8, TP><<<N, 128, 0, st>>>(colbits, info, N, d_lower, d_upper, phi_out, sqdist); break;
+    case 16: k_edt_rows_env<16, TP><<<N, 128, 0, st>>>(colbits, info, N, d_lower, d_upper, phi_out, sqdist); break;
+    case 32: k_edt_rows_env<32, TP><<<N, 128, 0, st>>>(colbits, info, N, d_lower, d_upper, phi_out, sqdist); break;
+    default: k_edt_rows_env<64, TP><<<N, 128, 0, st>>>(colbits, info, N, d_lower, d_upper, phi_out, sqdist); break;
+    }
     return hipGetLastError();
 }
 

@@ -198,7 +198,7 @@ def test_resist_unused_set_zero(ilt):
 
 
 EDT_CASES = [(16, 0.5), (64, 0.02), (64, 0.5), (64, 0.97), (100, 0.1), (257, 0.3), (256, "clip0"),
-             (1000, 0.001), (2048, "clip1")]
+             (1000, 0.001), (2048, "clip1"), (3000, 0.002)]
 
 
 @pytest.mark.parametrize("N,dens", EDT_CASES)
