@@ -102,7 +102,8 @@ void free_ctx(ilt_ctx *c) {
     void *ptrs[] = {c->A64, c->H64, c->w64, c->T64, c->S64, c->Y64, c->I64, c->G64, c->Q64, c->W64, c->Z64, c->g64,
                     c->phi64, c->part64,
                     c->tl, c->tb, c->ta4, c->ar, c->ai, c->H, c->sw, c->coef, c->tlhl, c->tbhl, c->Yhl, c->Spart, c->S, c->Est, c->Y, c->Tg,
-                    c->I, c->G, c->g, c->phi2, c->Wpart, c->W, c->edt_scratch, c->part, c->scal,
+                    c->I, c->G, c->g, c->phi2, c->Wpart, c->W, c->edt_scratch, c->part, c->scal, c->phib,
+                    c->tgtb,
                     c->tbQ, c->arQ, c->aiQ, c->Ghat, c->Ugw, c->Vpart, c->g_prev, c->dcg};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
@@ -218,7 +219,10 @@ extern "C" int ilt_create(ilt_ctx **out, const ilt_optics *o, int max_batch, voi
     if (!out) return fail(ILT_EINVAL, "out is null");
     *out = nullptr;
     if (!o) return fail(ILT_EINVAL, "optics is null");
-    if (max_batch != 1) return fail(ILT_EUNSUPPORTED, "max_batch must be 1");
+    if (max_batch < 1 || max_batch > ILT_MAX_BATCH)
+        return fail(ILT_EINVAL, "max_batch=%d outside [1, %d]", max_batch, ILT_MAX_BATCH);
+    if (max_batch > 1 && (o->precision != ILT_FP32 || (o->flags & ILT_FLAG_GWINDOW_ADJOINT)))
+        return fail(ILT_EUNSUPPORTED, "several clips per context need ILT_FP32 without the G-window adjoint");
     const int N = o->N, P = o->P, K = o->K, ns = o->n_sets;
     if (N < 16 || N > ILT_MAX_N) return fail(ILT_EINVAL, "N=%d outside [16, %d]", N, ILT_MAX_N);
     if (P < 1 || P % 2 == 0) return fail(ILT_EINVAL, "P=%d must be odd and positive", P);
@@ -242,6 +246,8 @@ extern "C" int ilt_create(ilt_ctx **out, const ilt_optics *o, int max_batch, voi
     ilt_ctx *c = new ilt_ctx();
     std::memset(c, 0, sizeof *c);
     c->N = N; c->P = P; c->K = K; c->n_sets = ns; c->precision = o->precision;
+    c->nb = max_batch;
+    c->ncur = 1;
     c->Np = round_up(N, 128);
     c->KP = pick_kp(P);
     c->FB = P / 16;
@@ -312,11 +318,12 @@ extern "C" int ilt_create(ilt_ctx **out, const ilt_optics *o, int max_batch, voi
     ALLOC(H, H.size());
     ALLOC(coef, coef.size());
     ALLOC(sw, sw.size());
-    ALLOC(Spart, (size_t)(Np / 16) * 4 * (c->gwin ? (size_t)c->Q * c->Q * ns : (size_t)P * P));
+    const size_t nb = (size_t)max_batch;
+    ALLOC(Spart, (size_t)(Np / 16) * 4 * (c->gwin ? (size_t)c->Q * c->Q * ns : (size_t)P * P) * nb);
     const bool b3 = o->precision == ILT_BF16X3;
     const bool f64 = o->precision == ILT_FP64;
     if (!b3 && !f64 && !c->gwin && !(o->flags & ILT_FLAG_RECOMPUTE_FIELDS))
-        ALLOC(Est, (size_t)ns * K * (Np / 16) * (Np / 16) * 512);
+        ALLOC(Est, (size_t)ns * K * (Np / 16) * (Np / 16) * 512 * nb);
     std::vector<double2> A64h, H64h;
     std::vector<double> w64h;
     if (f64) {
@@ -390,28 +397,32 @@ extern "C" int ilt_create(ilt_ctx **out, const ilt_optics *o, int max_batch, voi
         ALLOC(tbhl, (size_t)2 * 2 * NZ * Np);
         ALLOC(Yhl, (size_t)ns * K * Np * 2 * KP);
     }
-    ALLOC(S, (size_t)P * P);
-    ALLOC(W, (size_t)P * P);
-    ALLOC(Y, (size_t)ns * K * KP * Np);
-    ALLOC(Tg, (size_t)KP * Np);
-    ALLOC(I, (size_t)ns * N * N);
-    ALLOC(G, (size_t)ns * N * N);
-    ALLOC(g, (size_t)N * N);
+    ALLOC(S, (size_t)P * P * nb);
+    ALLOC(W, (size_t)P * P * nb);
+    ALLOC(Y, (size_t)ns * K * KP * Np * nb);
+    ALLOC(Tg, (size_t)KP * Np * nb);
+    ALLOC(I, (size_t)ns * N * N * nb);
+    ALLOC(G, (size_t)ns * N * N * nb);
+    ALLOC(g, (size_t)N * N * nb);
     ALLOC(g_prev, (size_t)N * N);
     ALLOC(dcg, (size_t)N * N);
-    ALLOC(phi2, (size_t)N * N);
+    ALLOC(phi2, (size_t)N * N * nb);
+    if (nb > 1) {
+        ALLOC(phib, (size_t)N * N * nb);
+        ALLOC(tgtb, (size_t)N * N * nb);
+    }
     // W partials: one per block of the FP32 adjoint grid, or of the split-BF16 one
     c->n_wpart = std::max(ns * ((N + 31) / 32) * ((K + 3) / 4) * ILT_ST_MAX_XSPLIT, adjoint_b3_max_parts(c, ns)) * P *
                  P * 2;
-    ALLOC(Wpart, (size_t)c->n_wpart);
+    ALLOC(Wpart, (size_t)c->n_wpart * nb);
     if (e == hipSuccess) {
         unsigned char *es = nullptr;
-        e = dalloc(&es, edt_scratch_bytes(N));
+        e = dalloc(&es, edt_scratch_bytes(N) * nb);
         c->edt_scratch = es;
     }
     c->n_part = (int)part_total(c);
-    ALLOC(part, (size_t)c->n_part);
-    ALLOC(scal, (size_t)SC_COUNT);
+    ALLOC(part, (size_t)c->n_part * nb);
+    ALLOC(scal, (size_t)SC_COUNT * nb);
 #undef ALLOC
     if (e != hipSuccess) {
         free_ctx(c);
@@ -745,7 +756,8 @@ int enqueue_solve(ilt_ctx *c, const unsigned char *d_target, float *d_phi, const
             HIPCHK(launch_levelset(c, cur, p->optimizer == 1 ? c->dcg : c->g, d_mod, p->lambda, p->eps_kappa,
                                    c->scal, nxt, ps));
             HIPCHK(launch_finish_step(c, ps, step_blocks(c), c->scal, nullptr,
-                                      d_trace ? d_trace + (size_t)i * ILT_TRACE_W : nullptr, gi));
+                                      d_trace ? d_trace + (size_t)i * ILT_TRACE_W : nullptr, gi,
+                                      c->ncur > 1 ? c->trace_tab : nullptr, i));
         }
         if (p->reinit_every > 0 && (gi + 1) % p->reinit_every == 0) {
             PhaseTimer t(c, 7);
@@ -753,7 +765,7 @@ int enqueue_solve(ilt_ctx *c, const unsigned char *d_target, float *d_phi, const
         }
         std::swap(cur, nxt);
     }
-    if (cur != d_phi) HIPCHK(launch_copy(c, d_phi, cur, npix));
+    if (cur != d_phi) HIPCHK(launch_copy(c, d_phi, cur, npix * c->ncur));
     // final metrics of [phi_T <= 0]
     HIPCHK(launch_spectrum(c, d_phi, 1));
     HIPCHK(launch_make_Y(c, slo, shi));
@@ -1208,11 +1220,21 @@ struct ilt_batch {
     hipEvent_t ev_lane[ILT_BATCH_MAX_LANES] = {};
     double *d_reports = nullptr;            // [max_clips][SC_COUNT]
     double *h_reports = nullptr;            // pinned mirror
+    double **d_ttab = nullptr;              // [max_clips] the clips' trace pointers, in chunk order
+    double **h_ttab = nullptr;              // pinned mirror
     hipGraph_t graph[ILT_BATCH_MAX_LANES] = {};
     hipGraphExec_t exec[ILT_BATCH_MAX_LANES] = {};
     std::vector<unsigned char> key;
-    std::vector<int> lane_of;               // clip -> lane of the captured plan
     int use_graph = 1;
+};
+
+// A chunk: clips of one size with identical parameters that one context
+// runs as one sequence of launches (the clip index is a grid dimension).
+struct batch_chunk {
+    int size = 0;                           // index into sizes
+    std::vector<int> clips;                 // clip indices, in clip order
+    int tab_off = 0;                        // first slot in the trace table
+    double cost = 0.0;
 };
 
 namespace {
@@ -1244,6 +1266,8 @@ void batch_free(ilt_batch *b) {
     if (b->ev_start) (void)hipEventDestroy(b->ev_start);
     if (b->d_reports) (void)hipFree(b->d_reports);
     if (b->h_reports) (void)hipHostFree(b->h_reports);
+    if (b->d_ttab) (void)hipFree(b->d_ttab);
+    if (b->h_ttab) (void)hipHostFree(b->h_ttab);
     delete b;
 }
 
@@ -1253,33 +1277,104 @@ int size_index(const ilt_batch *b, int N) {
     return -1;
 }
 
-// Longest-processing-time-first assignment of clips to lanes (cost ~ N^2);
-// ties keep the clip order, so the plan is a pure function of the clip list.
-void plan_lanes(const ilt_batch *b, int n, const ilt_clip *clips, std::vector<int> &lane_of) {
-    std::vector<int> order(n);
-    for (int i = 0; i < n; ++i) order[i] = i;
-    std::stable_sort(order.begin(), order.end(),
-                     [&](int a, int c) { return (long long)clips[a].N * clips[a].N > (long long)clips[c].N * clips[c].N; });
+// clips of side N per chunk: as many as make up the pixels of one 2048^2
+// clip (at most 16), so that a chunk's launches fill the chip as a 2048^2
+// clip's do
+int chunk_capacity(int N) {
+    const long long cap = (2048LL * 2048LL) / ((long long)N * N);
+    return (int)std::max(1LL, std::min(16LL, cap));
+}
+
+// Chunks: clips in clip order join the last chunk of their size and
+// parameters (compared byte for byte) while it has room; a conjugate-gradient
+// solve runs alone.  Every chunk gets its slots of the trace table.  The
+// plan is a pure function of the clip list.
+void plan_chunks(const ilt_batch *b, int n, const ilt_clip *clips, std::vector<batch_chunk> &chunks) {
+    chunks.clear();
+    for (int i = 0; i < n; ++i) {
+        const int s = size_index(b, clips[i].N);
+        const int cap = clips[i].params.optimizer == 1 ? 1 : b->ctx[s][0]->nb;
+        batch_chunk *into = nullptr;
+        for (int k = (int)chunks.size() - 1; k >= 0 && !into; --k) {
+            batch_chunk &ch = chunks[k];
+            if (ch.size == s && (int)ch.clips.size() < cap &&
+                std::memcmp(&clips[ch.clips[0]].params, &clips[i].params, sizeof(ilt_params)) == 0)
+                into = &ch;
+        }
+        if (!into) {
+            chunks.emplace_back();
+            into = &chunks.back();
+            into->size = s;
+        }
+        into->clips.push_back(i);
+        into->cost += (double)clips[i].N * clips[i].N * (clips[i].params.iters + 1);
+    }
+    int off = 0;
+    for (batch_chunk &ch : chunks) {
+        ch.tab_off = off;
+        off += (int)ch.clips.size();
+    }
+}
+
+// Longest-processing-time-first assignment of chunks to lanes; ties keep
+// the chunk order.
+void plan_lanes(const ilt_batch *b, const std::vector<batch_chunk> &chunks, std::vector<int> &lane_of) {
+    const int m = (int)chunks.size();
+    std::vector<int> order(m);
+    for (int i = 0; i < m; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return chunks[a].cost > chunks[c].cost; });
     std::vector<double> load(b->n_lanes, 0.0);
-    lane_of.assign(n, 0);
+    lane_of.assign(m, 0);
     for (int i : order) {
         int best = 0;
         for (int l = 1; l < b->n_lanes; ++l)
             if (load[l] < load[best]) best = l;
         lane_of[i] = best;
-        load[best] += (double)clips[i].N * clips[i].N * (clips[i].params.iters + 1);
+        load[best] += chunks[i].cost;
     }
 }
 
-// Enqueue the clips of lane l, in clip order, on each context's current stream.
-int enqueue_lane(ilt_batch *b, int l, int n, const ilt_clip *clips, const std::vector<int> &lane_of) {
-    for (int i = 0; i < n; ++i) {
-        if (lane_of[i] != l) continue;
-        ilt_ctx *c = b->ctx[size_index(b, clips[i].N)][l];
-        int r = enqueue_solve(c, clips[i].d_target, clips[i].d_phi, nullptr, &clips[i].params, clips[i].d_trace);
+// Enqueue the chunks of lane l, in chunk order, on each context's current
+// stream.  A chunk of one clip runs on the clip's own buffers; a larger one
+// copies its clips' targets (and initial phi) into the context's clip
+// buffers, runs them together and copies every phi back.
+int enqueue_lane(ilt_batch *b, int l, const ilt_clip *clips, const std::vector<batch_chunk> &chunks,
+                 const std::vector<int> &lane_of) {
+    for (size_t k = 0; k < chunks.size(); ++k) {
+        if (lane_of[k] != l) continue;
+        const batch_chunk &ch = chunks[k];
+        ilt_ctx *c = b->ctx[ch.size][l];
+        const ilt_params &p = clips[ch.clips[0]].params;
+        if (ch.clips.size() == 1) {
+            const int i = ch.clips[0];
+            int r = enqueue_solve(c, clips[i].d_target, clips[i].d_phi, nullptr, &p, clips[i].d_trace);
+            if (r != ILT_OK) return r;
+            HIPCHK(launch_copy(c, reinterpret_cast<float *>(b->d_reports + (size_t)i * SC_COUNT),
+                               reinterpret_cast<const float *>(c->scal), 2 * SC_COUNT));
+            continue;
+        }
+        const int nc = (int)ch.clips.size();
+        const size_t npix = cs_npix(c);
+        for (int j = 0; j < nc; ++j) {
+            const ilt_clip &q = clips[ch.clips[j]];
+            HIPCHK(hipMemcpyAsync(c->tgtb + j * npix, q.d_target, npix, hipMemcpyDeviceToDevice, c->stream));
+            if (p.init_mode == 1)
+                HIPCHK(hipMemcpyAsync(c->phib + j * npix, q.d_phi, npix * sizeof(float), hipMemcpyDeviceToDevice,
+                                      c->stream));
+        }
+        c->ncur = nc;
+        c->trace_tab = b->d_ttab + ch.tab_off;
+        const int r = enqueue_solve(c, c->tgtb, c->phib, nullptr, &p, nullptr);
+        c->ncur = 1;
+        c->trace_tab = nullptr;
         if (r != ILT_OK) return r;
-        HIPCHK(launch_copy(c, reinterpret_cast<float *>(b->d_reports + (size_t)i * SC_COUNT),
-                           reinterpret_cast<const float *>(c->scal), 2 * SC_COUNT));
+        for (int j = 0; j < nc; ++j) {
+            const int i = ch.clips[j];
+            HIPCHK(hipMemcpyAsync(clips[i].d_phi, c->phib + j * npix, npix * sizeof(float), hipMemcpyDeviceToDevice,
+                                  c->stream));
+            HIPCHK(launch_copy(c, reinterpret_cast<float *>(b->d_reports + (size_t)i * SC_COUNT),
+                               reinterpret_cast<const float *>(c->scal + (size_t)j * SC_COUNT), 2 * SC_COUNT));
+        }
     }
     return ILT_OK;
 }
@@ -1319,6 +1414,8 @@ extern "C" int ilt_batch_create(ilt_batch **out, const ilt_optics *o, const int 
     if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_start, hipEventDisableTiming);
     if (e == hipSuccess) e = hipMalloc(&b->d_reports, (size_t)max_clips * SC_COUNT * sizeof(double));
     if (e == hipSuccess) e = hipHostMalloc(&b->h_reports, (size_t)max_clips * SC_COUNT * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc(&b->d_ttab, (size_t)max_clips * sizeof(double *));
+    if (e == hipSuccess) e = hipHostMalloc(&b->h_ttab, (size_t)max_clips * sizeof(double *));
     if (e != hipSuccess) {
         batch_free(b);
         return fail(ILT_EDEVICE, "batch set-up failed: %s", hipGetErrorString(e));
@@ -1327,8 +1424,11 @@ extern "C" int ilt_batch_create(ilt_batch **out, const ilt_optics *o, const int 
         b->sizes[s] = sizes[s];
         ilt_optics os = *o;
         os.N = sizes[s];
+        // FP32 contexts run chunks of several clips of this size
+        const bool multi = os.precision == ILT_FP32 && !(os.flags & ILT_FLAG_GWINDOW_ADJOINT);
+        const int cap = multi ? std::min(chunk_capacity(sizes[s]), max_clips) : 1;
         for (int l = 0; l < n_lanes; ++l) {
-            const int r = ilt_create(&b->ctx[s][l], &os, 1, b->lane[l]);
+            const int r = ilt_create(&b->ctx[s][l], &os, cap, b->lane[l]);
             if (r != ILT_OK) {
                 batch_free(b);
                 return r;   // message set by ilt_create
@@ -1370,12 +1470,21 @@ extern "C" int ilt_solve_batch(ilt_batch *b, int n, const ilt_clip *clips, ilt_r
         for (int t = 0; t < i; ++t)
             if (clips[t].d_phi == k.d_phi) return fail(ILT_EINVAL, "clips %d and %d share d_phi", t, i);
     }
+    std::vector<batch_chunk> chunks;
+    plan_chunks(b, n, clips, chunks);
     std::vector<int> lane_of;
-    plan_lanes(b, n, clips, lane_of);
+    plan_lanes(b, chunks, lane_of);
     std::vector<unsigned char> key(sizeof n + (size_t)n * sizeof(ilt_clip));
     std::memcpy(key.data(), &n, sizeof n);
     std::memcpy(key.data() + sizeof n, clips, (size_t)n * sizeof(ilt_clip));
 
+    if (!b->use_graph || key != b->key) {
+        // the trace table of this clip list (read by the chunks' launches;
+        // unchanged while the captured plan is replayed)
+        for (const batch_chunk &ch : chunks)
+            for (size_t j = 0; j < ch.clips.size(); ++j) b->h_ttab[ch.tab_off + j] = clips[ch.clips[j]].d_trace;
+        HIPCHK(hipMemcpy(b->d_ttab, b->h_ttab, (size_t)n * sizeof(double *), hipMemcpyHostToDevice));
+    }
     if (b->use_graph && key != b->key) {
         batch_free_graphs(b);
         for (int l = 0; l < b->n_lanes; ++l) {
@@ -1387,7 +1496,7 @@ extern "C" int ilt_solve_batch(ilt_batch *b, int n, const ilt_clip *clips, ilt_r
                 batch_free_graphs(b);
                 return fail(ILT_EDEVICE, "hipStreamBeginCapture: %s", hipGetErrorString(e));
             }
-            const int rc = enqueue_lane(b, l, n, clips, lane_of);
+            const int rc = enqueue_lane(b, l, clips, chunks, lane_of);
             hipGraph_t g = nullptr;
             e = hipStreamEndCapture(b->cap[l], &g);
             set_lane_streams(b, l, b->lane[l]);
@@ -1403,7 +1512,6 @@ extern "C" int ilt_solve_batch(ilt_batch *b, int n, const ilt_clip *clips, ilt_r
             }
         }
         b->key = key;
-        b->lane_of = lane_of;
     }
     HIPCHK(hipEventRecord(b->ev_start, b->user));
     for (int l = 0; l < b->n_lanes; ++l) {
@@ -1411,7 +1519,7 @@ extern "C" int ilt_solve_batch(ilt_batch *b, int n, const ilt_clip *clips, ilt_r
         HIPCHK(hipStreamWaitEvent(b->lane[l], b->ev_start, 0));
         if (b->use_graph) {
             HIPCHK(hipGraphLaunch(b->exec[l], b->lane[l]));
-        } else if ((r = enqueue_lane(b, l, n, clips, lane_of))) {
+        } else if ((r = enqueue_lane(b, l, clips, chunks, lane_of))) {
             return r;
         }
         HIPCHK(hipEventRecord(b->ev_lane[l], b->lane[l]));

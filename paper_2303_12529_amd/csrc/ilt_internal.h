@@ -42,6 +42,8 @@
 #define ILT_MAX_K 64
 #define ILT_MAX_SETS 4
 #define ILT_TRACE_W 8
+// clips of one size that a context runs in one launch per phase
+#define ILT_MAX_BATCH 64
 
 typedef float f4 __attribute__((ext_vector_type(4)));
 
@@ -62,6 +64,14 @@ struct ilt_ctx {
     int Np, KP, FB, MIX, NZ, AP;
     int device;
     hipStream_t stream;
+    // clips: a context created for nb > 1 clips holds every per-clip
+    // workspace nb times, one after another (strides cs_*), and runs the
+    // ncur clips of the current sequence in one launch per phase (the clip
+    // index is a grid dimension); ncur = 1 outside such a sequence
+    int nb, ncur;
+    float *phib;            // [nb][N][N] the clips' phi (nb > 1 only)
+    unsigned char *tgtb;    // [nb][N][N] the clips' targets (nb > 1 only)
+    double **trace_tab;     // [nb] device pointers of the clips' traces (or NULL)
 
     // tables
     float *tl;         // [2][KP][Np]
@@ -143,6 +153,13 @@ struct ilt_ctx {
     int *ev_phase;            // [ev_cap]
 };
 
+// per-clip strides (elements) of the workspaces of a context with nb > 1
+inline size_t cs_npix(const ilt_ctx *c) { return (size_t)c->N * c->N; }
+inline size_t cs_y(const ilt_ctx *c) { return (size_t)c->n_sets * c->K * c->KP * c->Np; }
+inline size_t cs_est(const ilt_ctx *c) { return (size_t)c->n_sets * c->K * (c->Np / 16) * (c->Np / 16) * 512; }
+inline size_t cs_tg(const ilt_ctx *c) { return (size_t)c->KP * c->Np; }
+inline size_t cs_spart(const ilt_ctx *c) { return (size_t)(c->Np / 16) * 4 * c->P * c->P; }
+
 // device scalar slots
 enum {
     SC_LOSS = 0, SC_L2 = 1, SC_PVB = 2, SC_NONFIN = 3,
@@ -223,8 +240,10 @@ int step_blocks(const ilt_ctx *c);
 hipError_t launch_levelset(ilt_ctx *c, const float *phi, const float *vel, const float *mod,
                            float lam, float eps_kappa, const double *scal, float *phi_out,
                            double *part);
+// trace rows: trace_row (one clip), or with trace_tab row `row` of each
+// clip's trace trace_tab[clip] (NULL entries skipped)
 hipError_t launch_finish_step(ilt_ctx *c, const double *part, int nblk, double *scal, double *stats4,
-                              double *trace_row, int iter);
+                              double *trace_row, int iter, double *const *trace_tab = nullptr, int row = 0);
 hipError_t launch_edt(ilt_ctx *c, const float *phi, const uint8_t *mask, float *phi_out, int *sqdist,
                       float d_lower, float d_upper);
 // the EDT on any stream with a caller-given scratch of edt_scratch_bytes(N)

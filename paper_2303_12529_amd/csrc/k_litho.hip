@@ -194,10 +194,14 @@ __global__ __launch_bounds__(256) void k_window_rows(const float2 *__restrict__ 
                                                      const float *__restrict__ scale, float scale_c,
                                                      const float *__restrict__ ar, const float *__restrict__ ai,
                                                      int P, int KP, int Np, int nj, int set_lo,
-                                                     float *__restrict__ out) {
+                                                     float *__restrict__ out, int zs, size_t s_cs, size_t out_cs) {
     constexpr int RG = 256 / COLS;
     __shared__ float2 U[JB][ILT_MAX_P * ILT_MAX_P];
-    const int j0 = blockIdx.y * JB, s = set_lo + blockIdx.z;
+    // grid.z = clips x zs window slices; every clip has its own S and out
+    const int clip = blockIdx.z / zs;
+    S += clip * s_cs;
+    out += clip * out_cs;
+    const int j0 = blockIdx.y * JB, s = set_lo + (blockIdx.z - clip * zs);
     const int x = blockIdx.x * COLS + (threadIdx.x % COLS);
     const int ag = threadIdx.x / COLS;
     const int jn = min(JB, nj - j0);
@@ -267,13 +271,17 @@ template <int KP, bool SPLIT>
 __global__ __launch_bounds__(256) void k_make_y(const float2 *__restrict__ H, const float2 *__restrict__ S,
                                                 const float *__restrict__ scale, const float *__restrict__ tl,
                                                 int P, int Np, int nj, int set_lo, float *__restrict__ out,
-                                                __bf16 *__restrict__ outhl) {
+                                                __bf16 *__restrict__ outhl, int zs, size_t s_cs, size_t y_cs) {
     constexpr int MT = (KP + 15) / 16;            // 16-row tiles of C (>= 2P rows)
     constexpr int LDC = KP + 4;
     __shared__ float C[16 * MT][LDC];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int l16 = lane & 15, lq = lane >> 4;
-    const int j = blockIdx.y, s = set_lo + blockIdx.z;
+    // grid.z = clips x sets; every clip has its own S and Y (FP32 form)
+    const int clip = blockIdx.z / zs;
+    S += clip * s_cs;
+    if (out) out += clip * y_cs;
+    const int j = blockIdx.y, s = set_lo + (blockIdx.z - clip * zs);
     const float sc = scale[(size_t)s * nj + j];
     const int x0 = blockIdx.x * 128 + wave * 32;
     // all of the wave's tl operands are requested first (2 KP / 4 values),
@@ -380,7 +388,8 @@ __global__ __launch_bounds__(256) void k_make_y(const float2 *__restrict__ H, co
 template <int KP, int MODE, bool STORE>
 __global__ __launch_bounds__(256, 2) void k_image(const float *__restrict__ tl, const float *__restrict__ Y,
                                                int nj, int N, int Np, int set_lo, float *__restrict__ out,
-                                               double *__restrict__ maxpart, float *__restrict__ Est) {
+                                               double *__restrict__ maxpart, float *__restrict__ Est, int zs,
+                                               size_t y_cs, size_t out_cs, size_t max_cs, size_t est_cs) {
     constexpr int KS = KP / 4;
     constexpr int LDW = 64 + 16;
     constexpr int NV = (KP * 16 + 255) / 256;      // float4 per thread per tile
@@ -388,7 +397,13 @@ __global__ __launch_bounds__(256, 2) void k_image(const float *__restrict__ tl, 
     __shared__ float wmax[4];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int l16 = lane & 15, lq = lane >> 4;
-    const int s = set_lo + blockIdx.z;
+    // grid.z = clips x sets; every clip has its own Y, output, maxima and fields
+    const int clip = blockIdx.z / zs, zr = blockIdx.z - clip * zs;
+    Y += clip * y_cs;
+    out += clip * out_cs;
+    if (MODE == 1) maxpart += clip * max_cs;
+    if (STORE) Est += clip * est_cs;
+    const int s = set_lo + zr;
     const int x0 = blockIdx.x * 64;
     const int yw = blockIdx.y * 128 + wave * 32;
     const int NB16 = Np / 16;
@@ -478,7 +493,7 @@ __global__ __launch_bounds__(256, 2) void k_image(const float *__restrict__ tl, 
 #undef IMG_FETCH
 #undef IMG_STASH
     float m = 0.f;
-    float *o = out + (size_t)blockIdx.z * N * N;
+    float *o = out + (size_t)zr * N * N;
 #pragma unroll
     for (int xb = 0; xb < 4; ++xb)
 #pragma unroll
@@ -537,7 +552,8 @@ __global__ __launch_bounds__(256, 2) void k_adjoint_st(const float *__restrict__
                                                     const float *__restrict__ Est, const float *__restrict__ G,
                                                     size_t g_set_stride, const float2 *__restrict__ coef, int K,
                                                     int P, int N, int Np, int AP, int set_lo,
-                                                    float *__restrict__ Wpart) {
+                                                    float *__restrict__ Wpart, int zs, size_t est_cs, size_t g_cs,
+                                                    size_t wp_cs) {
     constexpr int NZ = 32 * FB + 16 * MIX, NB = NZ / 16;
     constexpr int LDB = NZ + 4;                       // row: NZ / 4 data units + 1 pad unit of 16 B
     constexpr int BU = 2 * 32 * (LDB / 4);            // 16-byte units of one B3 tile (a multiple of 64)
@@ -551,7 +567,12 @@ __global__ __launch_bounds__(256, 2) void k_adjoint_st(const float *__restrict__
     const int l16 = lane & 15, lq = lane >> 4;
     const int kgroups = (K + 3) / 4;
     const int ytile = blockIdx.x, kg = blockIdx.y % kgroups, xs = blockIdx.y / kgroups;
-    const int srel = blockIdx.z, s = set_lo + srel;
+    // grid.z = clips x sets; every clip has its own fields, G and partials
+    const int clip = blockIdx.z / zs;
+    Est += clip * est_cs;
+    G += clip * g_cs;
+    Wpart += clip * wp_cs;
+    const int srel = blockIdx.z - clip * zs, s = set_lo + srel;
     const int y0 = ytile * 32;
     const int j = kg * 4 + wave;
     const bool jok = j < K;
@@ -684,7 +705,8 @@ __global__ __launch_bounds__(256, 2) void k_adjoint_rc(const float *__restrict__
                                                     const float *__restrict__ ta4, const float *__restrict__ Y,
                                                     const float *__restrict__ G, size_t g_set_stride,
                                                     const float2 *__restrict__ coef, int K, int P, int N, int Np,
-                                                    int AP, int set_lo, float *__restrict__ Wpart) {
+                                                    int AP, int set_lo, float *__restrict__ Wpart, int zs,
+                                                    size_t y_cs, size_t g_cs, size_t wp_cs) {
     constexpr int NZ = 32 * FB + 16 * MIX, NB = NZ / 16, KS = KP / 4;
     constexpr int LDB = NZ + 4;
     __shared__ float Gs[32][33];
@@ -692,7 +714,12 @@ __global__ __launch_bounds__(256, 2) void k_adjoint_rc(const float *__restrict__
     __shared__ float2 Ws[ILT_MAX_P * ILT_MAX_P];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int l16 = lane & 15, lq = lane >> 4;
-    const int ytile = blockIdx.x, kg = blockIdx.y, srel = blockIdx.z, s = set_lo + srel;
+    // grid.z = clips x sets; every clip has its own Y, G and partials
+    const int clip = blockIdx.z / zs;
+    Y += clip * y_cs;
+    G += clip * g_cs;
+    Wpart += clip * wp_cs;
+    const int ytile = blockIdx.x, kg = blockIdx.y, srel = blockIdx.z - clip * zs, s = set_lo + srel;
     const int y0 = ytile * 32;
     const int j = kg * 4 + wave;
     const bool jok = j < K;
@@ -941,9 +968,12 @@ __global__ __launch_bounds__(256) void k_gwindow_mm(const float2 *__restrict__ G
 // given column tables, summed into out [Pw][Pw].
 static hipError_t spectrum_to(ilt_ctx *c, const float *src, int src_is_phi, int FBw, int MIXw, const float *tbw,
                               const float *arw, const float *aiw, int Pw, float2 *out, int nimg = 1,
-                              size_t src_stride = 0) {
+                              size_t src_stride = 0, int xs_nimg = 0) {
+    // xs_nimg: the image count whose column split to use (0: nimg); the
+    // clips of one sequence keep the single-image split, so that each
+    // clip's sums group exactly as in a solve of that clip alone
     const int nband = c->Np / 16;
-    const int xs = spectrum_xsplit(c, nimg);
+    const int xs = spectrum_xsplit(c, xs_nimg > 0 ? xs_nimg : nimg);
 #define SPEC(FB_, MIX_)                                                                                    \
     k_spectrum_band<FB_, MIX_><<<dim3(nband, xs, nimg), 512, 0, c->stream>>>(src, src_stride, src_is_phi, tbw, \
                                                                             arw, aiw, Pw, c->N, c->Np, c->Spart)
@@ -966,11 +996,13 @@ static hipError_t spectrum_to(ilt_ctx *c, const float *src, int src_is_phi, int 
 }
 
 hipError_t launch_spectrum(ilt_ctx *c, const float *src, int src_is_phi) {
-    return spectrum_to(c, src, src_is_phi, c->FB, c->MIX, c->tb, c->ar, c->ai, c->P, c->S);
+    return spectrum_to(c, src, src_is_phi, c->FB, c->MIX, c->tb, c->ar, c->ai, c->P, c->S, c->ncur, cs_npix(c), 1);
 }
 
 hipError_t launch_make_Y(ilt_ctx *c, int set_lo, int set_hi) {
-    dim3 grid(c->Np / 128, c->K, set_hi - set_lo);
+    const int zs = set_hi - set_lo;
+    dim3 grid(c->Np / 128, c->K, zs * c->ncur);
+    const size_t scs = (size_t)c->P * c->P, ycs = cs_y(c);
     // the split-BF16 form reads only the split rows, written here directly
     const bool split = c->precision == ILT_BF16X3;
     switch (c->KP) {
@@ -978,10 +1010,10 @@ hipError_t launch_make_Y(ilt_ctx *c, int set_lo, int set_hi) {
     case KP_:                                                                                                  \
         if (split)                                                                                             \
             k_make_y<KP_, true><<<grid, 256, 0, c->stream>>>(c->H, c->S, c->sw, c->tl, c->P, c->Np, c->K, set_lo, \
-                                                             nullptr, c->Yhl);                                 \
+                                                             nullptr, c->Yhl, zs, scs, ycs);                   \
         else                                                                                                   \
             k_make_y<KP_, false><<<grid, 256, 0, c->stream>>>(c->H, c->S, c->sw, c->tl, c->P, c->Np, c->K,      \
-                                                              set_lo, c->Y, nullptr);                          \
+                                                              set_lo, c->Y, nullptr, zs, scs, ycs);            \
         break;
         MKY(8) MKY(24) MKY(40) MKY(72)
 #undef MKY
@@ -990,12 +1022,15 @@ hipError_t launch_make_Y(ilt_ctx *c, int set_lo, int set_hi) {
     return hipGetLastError();
 }
 
+// y_cs, out_cs: the clip strides of Y and out; maxima and fields step by the
+// clip's partials and field store
 template <int MODE, bool STORE>
 static hipError_t image_dispatch(ilt_ctx *c, const float *Y, int nj, int set_lo, int nsets, float *out,
-                                 double *maxpart) {
-    dim3 grid(c->Np / 64, c->Np / 128, nsets);
+                                 double *maxpart, size_t y_cs, size_t out_cs) {
+    dim3 grid(c->Np / 64, c->Np / 128, nsets * c->ncur);
+    const size_t mcs = (size_t)c->n_part, ecs = cs_est(c);
     switch (c->KP) {
-#define IMG(KP_) case KP_: k_image<KP_, MODE, STORE><<<grid, 256, 0, c->stream>>>(c->tl, Y, nj, c->N, c->Np, set_lo, out, maxpart, c->Est); break;
+#define IMG(KP_) case KP_: k_image<KP_, MODE, STORE><<<grid, 256, 0, c->stream>>>(c->tl, Y, nj, c->N, c->Np, set_lo, out, maxpart, c->Est, nsets, y_cs, out_cs, mcs, ecs); break;
         IMG(8) IMG(24) IMG(40) IMG(72)
 #undef IMG
         default: return hipErrorInvalidValue;
@@ -1004,26 +1039,34 @@ static hipError_t image_dispatch(ilt_ctx *c, const float *Y, int nj, int set_lo,
 }
 
 hipError_t launch_image_to(ilt_ctx *c, int set_lo, int set_hi, float *out, int store_fields) {
-    if (store_fields && c->Est) return image_dispatch<0, true>(c, c->Y, c->K, set_lo, set_hi - set_lo, out, nullptr);
-    return image_dispatch<0, false>(c, c->Y, c->K, set_lo, set_hi - set_lo, out, nullptr);
+    // out: the sets' images of the first clip; clips step by n_sets images
+    const size_t ocs = (size_t)c->n_sets * cs_npix(c);
+    if (store_fields && c->Est)
+        return image_dispatch<0, true>(c, c->Y, c->K, set_lo, set_hi - set_lo, out, nullptr, cs_y(c), ocs);
+    return image_dispatch<0, false>(c, c->Y, c->K, set_lo, set_hi - set_lo, out, nullptr, cs_y(c), ocs);
 }
 
 hipError_t launch_adjoint(ilt_ctx *c, const float *G, size_t g_set_stride, int set_lo, int set_hi, int fields_stored) {
-    dim3 grid((c->N + 31) / 32, (c->K + 3) / 4, set_hi - set_lo);
+    // grid.z = clips x sets; G steps by n_sets images per clip, the W
+    // partials by the clip's share
+    const int zs = set_hi - set_lo;
+    dim3 grid((c->N + 31) / 32, (c->K + 3) / 4, zs * c->ncur);
+    const size_t gcs = (size_t)c->n_sets * cs_npix(c);
     if (fields_stored) {
         if (!c->Est) return hipErrorInvalidValue;
         grid.y *= adjoint_st_xsplit(c);
-        if ((size_t)grid.x * grid.y * grid.z * c->P * c->P * 2 > (size_t)c->n_wpart) return hipErrorInvalidValue;
+        const size_t wcs = (size_t)grid.x * grid.y * zs * c->P * c->P * 2;
+        if (wcs * c->ncur > (size_t)c->n_wpart * c->nb) return hipErrorInvalidValue;
 #define ADJS(FB_, MIX_)                                                                                        \
     do {                                                                                                        \
         if ((c->N & 3) == 0 && (reinterpret_cast<uintptr_t>(G) & 15) == 0)                                     \
             k_adjoint_st<FB_, MIX_, true><<<grid, 256, 0, c->stream>>>(c->tb, c->ta4, c->Est, G, g_set_stride,   \
                                                                       c->coef, c->K, c->P, c->N, c->Np, c->AP, \
-                                                                      set_lo, c->Wpart);                       \
+                                                                      set_lo, c->Wpart, zs, cs_est(c), gcs, wcs); \
         else                                                                                                    \
             k_adjoint_st<FB_, MIX_, false><<<grid, 256, 0, c->stream>>>(c->tb, c->ta4, c->Est, G, g_set_stride,  \
                                                                        c->coef, c->K, c->P, c->N, c->Np, c->AP, \
-                                                                       set_lo, c->Wpart);                       \
+                                                                       set_lo, c->Wpart, zs, cs_est(c), gcs, wcs); \
     } while (0)
         if (c->FB == 0 && c->MIX == 1) ADJS(0, 1);
         else if (c->FB == 1 && c->MIX == 0) ADJS(1, 0);
@@ -1034,10 +1077,12 @@ hipError_t launch_adjoint(ilt_ctx *c, const float *G, size_t g_set_stride, int s
 #undef ADJS
         return hipGetLastError();
     }
+    const size_t wcs = (size_t)grid.x * grid.y * zs * c->P * c->P * 2;
+    if (wcs * c->ncur > (size_t)c->n_wpart * c->nb) return hipErrorInvalidValue;
 #define ADJ(KP_, FB_, MIX_)                                                                                 \
     k_adjoint_rc<KP_, FB_, MIX_><<<grid, 256, 0, c->stream>>>(c->tl, c->tb, c->ta4, c->Y, G, g_set_stride,  \
                                                               c->coef, c->K, c->P, c->N, c->Np, c->AP, set_lo, \
-                                                              c->Wpart)
+                                                              c->Wpart, zs, cs_y(c), gcs, wcs)
     const int KPv = c->KP, FBv = c->FB, MIXv = c->MIX;
     if (KPv == 8 && FBv == 0 && MIXv == 1) ADJ(8, 0, 1);
     else if (KPv == 24 && FBv == 0 && MIXv == 1) ADJ(24, 0, 1);
@@ -1056,20 +1101,21 @@ hipError_t launch_window_sum(ilt_ctx *c, int set_lo, int set_hi) {
     const int nparts = c->precision == ILT_BF16X3 ? adjoint_b3_parts(c, set_hi - set_lo)
                                                   : adjoint_fp32_parts(c, set_hi - set_lo);
     const int n = c->P * c->P;
-    k_psum<float2><<<(n + 15) / 16, 1024, 0, c->stream>>>(reinterpret_cast<const float2 *>(c->Wpart), nparts, n,
-                                                         c->W);
+    // one sum per clip (the clips' partials lie one after another)
+    k_psum<float2><<<dim3((n + 15) / 16, c->ncur), 1024, 0, c->stream>>>(
+        reinterpret_cast<const float2 *>(c->Wpart), nparts, n, c->W);
     return hipGetLastError();
 }
 
 hipError_t launch_gradient(ilt_ctx *c, float *g_out, double *maxpart) {
     // Tg = 2 W conj(A) in the row layout, then g = Re(A^H Tg)
     // one transform only: narrow column tiles so that the launch covers the chip
-    dim3 grid(c->Np / 16, 1, 1);
+    dim3 grid(c->Np / 16, 1, c->ncur);
     k_window_rows<16, 1><<<grid, 256, 0, c->stream>>>(nullptr, c->W, nullptr, 2.f, c->ar, c->ai, c->P, c->KP, c->Np,
-                                                      1, 0, c->Tg);
+                                                      1, 0, c->Tg, 1, (size_t)c->P * c->P, cs_tg(c));
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    return image_dispatch<1, false>(c, c->Tg, 1, 0, 1, g_out, maxpart);
+    return image_dispatch<1, false>(c, c->Tg, 1, 0, 1, g_out, maxpart, cs_tg(c), cs_npix(c));
 }
 
 hipError_t launch_adjoint_gwindow(ilt_ctx *c, const float *G, size_t g_set_stride, int set_lo, int set_hi) {

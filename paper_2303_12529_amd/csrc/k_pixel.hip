@@ -124,8 +124,13 @@ template <int CL>
 __global__ __launch_bounds__(RB) void k_resist4(const float *__restrict__ I, size_t set_stride,
                                                const uint8_t *__restrict__ target, resist_args ra,
                                                size_t npix, size_t chunk, float *__restrict__ G,
-                                               double *__restrict__ part) {
+                                               double *__restrict__ part, size_t i_cs, size_t t_cs, size_t p_cs) {
     __shared__ double sh[RB];
+    // grid.y: clips, each with its own images, target, G and partials
+    I += blockIdx.y * i_cs;
+    G += blockIdx.y * i_cs;
+    target += blockIdx.y * t_cs;
+    part += blockIdx.y * p_cs;
     const size_t nq = npix / 4;
     const size_t lo = (size_t)blockIdx.x * chunk;
     const size_t hi = min(nq, lo + chunk);
@@ -192,8 +197,12 @@ __global__ __launch_bounds__(RB) void k_resist4(const float *__restrict__ I, siz
 __global__ __launch_bounds__(RB) void k_resist1(const float *__restrict__ I, size_t set_stride,
                                                 const uint8_t *__restrict__ target, resist_args ra,
                                                 size_t npix, size_t chunk, float *__restrict__ G,
-                                                double *__restrict__ part) {
+                                                double *__restrict__ part, size_t i_cs, size_t t_cs, size_t p_cs) {
     __shared__ double sh[RB];
+    I += blockIdx.y * i_cs;
+    G += blockIdx.y * i_cs;
+    target += blockIdx.y * t_cs;
+    part += blockIdx.y * p_cs;
     const size_t lo = (size_t)blockIdx.x * chunk;
     const size_t hi = min(npix, lo + chunk);
     double loss = 0.0;
@@ -220,8 +229,12 @@ __global__ __launch_bounds__(RB) void k_resist1(const float *__restrict__ I, siz
 }
 
 __global__ __launch_bounds__(RB) void k_finish_resist(const double *__restrict__ part, int nblk,
-                                                      double *__restrict__ scal, double *__restrict__ stats4) {
+                                                      double *__restrict__ scal, double *__restrict__ stats4,
+                                                      size_t p_cs) {
     __shared__ double sh[RB];
+    // block = clip
+    part += blockIdx.x * p_cs;
+    scal += blockIdx.x * SC_COUNT;
     double v[4] = {0.0, 0.0, 0.0, 0.0};
     thread_partial_sums<4, 8>(part, nblk, v);
     for (int q = 0; q < 4; ++q) v[q] = block_sum(v[q], sh);
@@ -253,8 +266,11 @@ __global__ __launch_bounds__(RB) void k_absmax(const float *__restrict__ v, size
 
 // CFL time step (Sec. III-C): dt = eta / max|v|, capped at dt_max; or fixed.
 __global__ __launch_bounds__(RB) void k_finish_dt(const double *__restrict__ part, int nblk, int dt_mode,
-                                                  float eta, float dt_max, double *__restrict__ scal) {
+                                                  float eta, float dt_max, double *__restrict__ scal, size_t p_cs) {
     __shared__ double sh[RB];
+    // block = clip
+    part += blockIdx.x * p_cs;
+    scal += blockIdx.x * SC_COUNT;
     double m = 0.0;
     for (int b = threadIdx.x; b < nblk; b += RB) m = fmax(m, part[b]);
     m = block_max(m, sh);
@@ -342,9 +358,18 @@ __global__ __launch_bounds__(RB) void k_cg_update(const float *__restrict__ g, f
 __global__ __launch_bounds__(256) void k_levelset(const float *__restrict__ phi, const float *__restrict__ vel,
                                                   const float *__restrict__ mod, float lam, float eps_kappa,
                                                   const double *__restrict__ scal, int N,
-                                                  float *__restrict__ out, double *__restrict__ part) {
+                                                  float *__restrict__ out, double *__restrict__ part, size_t p_cs) {
     __shared__ float t[34][35];
     __shared__ int wsum[4], wbad[4];
+    // grid.z: clips, each with its own phi, velocity, output, scalars and partials
+    {
+        const size_t o = (size_t)blockIdx.z * N * N;
+        phi += o;
+        vel += o;
+        out += o;
+        scal += blockIdx.z * SC_COUNT;
+        part += blockIdx.z * p_cs;
+    }
     const int bx = blockIdx.x * 32, by = blockIdx.y * 32;
     const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
     // the time step, and the velocity (and modulation) of this thread's
@@ -426,8 +451,13 @@ __global__ __launch_bounds__(256) void k_levelset(const float *__restrict__ phi,
 
 __global__ __launch_bounds__(RB) void k_finish_step(const double *__restrict__ part, int nblk,
                                                     double *__restrict__ scal, double *__restrict__ stats4,
-                                                    double *__restrict__ trace_row, int iter, double ns_per_tick) {
+                                                    double *__restrict__ trace_row, int iter, double ns_per_tick,
+                                                    size_t p_cs, double *const *__restrict__ trace_tab, int row) {
     __shared__ double sh[RB];
+    // block = clip; with a table, clip b's row goes to trace_tab[b] (if set)
+    part += blockIdx.x * p_cs;
+    scal += blockIdx.x * SC_COUNT;
+    if (trace_tab) trace_row = trace_tab[blockIdx.x] ? trace_tab[blockIdx.x] + (size_t)row * ILT_TRACE_W : nullptr;
     double fs[2] = {0.0, 0.0};
     thread_partial_sums<2, 8>(part, nblk, fs);
     const double f = block_sum(fs[0], sh);
@@ -474,8 +504,12 @@ __device__ __forceinline__ uint32_t valid_bits(int w, int N) {
 
 template <bool PHI, typename TP>
 __global__ __launch_bounds__(256) void k_edt_bits(const TP *__restrict__ phi, const uint8_t *__restrict__ mask,
-                                                  int N, int vec, uint32_t *__restrict__ colbits) {
+                                                  int N, int vec, uint32_t *__restrict__ colbits, size_t scr_words) {
     __shared__ uint32_t part[4][256];
+    // grid.z: clips, each with its own image and scratch
+    if (PHI) phi += (size_t)blockIdx.z * N * N;
+    else mask += (size_t)blockIdx.z * N * N;
+    colbits += blockIdx.z * scr_words;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int w = blockIdx.y;
     const int x0 = blockIdx.x * 256 + 4 * lane;
@@ -549,7 +583,10 @@ __device__ __forceinline__ int word_above(const unsigned long long (&m)[2], int 
 }
 
 __global__ __launch_bounds__(256) void k_edt_colinfo(const uint32_t *__restrict__ colbits, int N,
-                                                     int16_t *__restrict__ info) {
+                                                     int16_t *__restrict__ info, size_t scr_words) {
+    // grid.y: clips, each with its own scratch
+    colbits += blockIdx.y * scr_words;
+    info += blockIdx.y * 2 * scr_words;
     // block = EDT_CB columns; the 256 / EDT_CB thread rows step over the words
     constexpr int WL = 256 / EDT_CB;
     extern __shared__ uint32_t wsh[];                       // [W][EDT_CB]
@@ -687,7 +724,7 @@ template <int M, typename TP>
 __global__ __launch_bounds__(128) void k_edt_rows_env(const uint32_t *__restrict__ colbits,
                                                       const int16_t *__restrict__ info, int N, float d_lower,
                                                       float d_upper, TP *__restrict__ phi_out,
-                                                      int *__restrict__ sqdist) {
+                                                      int *__restrict__ sqdist, size_t scr_words) {
     // per class: g of every column (halfwords, M + 2 per band) and the band
     // chains, later the hull marks and then D in the same storage (words,
     // M + 1 per band).  The pads put the 64 lanes' equal band offsets in
@@ -696,6 +733,10 @@ __global__ __launch_bounds__(128) void k_edt_rows_env(const uint32_t *__restrict
     __shared__ uint16_t gsh[2 * S16];
     __shared__ int chn[2][S32];
     __shared__ int need[2];
+    // grid.y: clips, each with its own scratch and output
+    colbits += blockIdx.y * scr_words;
+    info += blockIdx.y * 2 * scr_words;
+    phi_out += (size_t)blockIdx.y * N * N;
     const int y = blockIdx.x;
     const int lane = threadIdx.x & 63, cls = threadIdx.x >> 6;
     const int W = (N + 31) / 32;
@@ -971,6 +1012,7 @@ __global__ void k_heaviside_shift(const float *__restrict__ phi, float dh, size_
 }
 
 __global__ void k_set_scal(double *__restrict__ scal, int slot, double v) {
+    scal += blockIdx.x * SC_COUNT;      // block = clip
     if (threadIdx.x == 0) scal[slot] = v;
 }
 
@@ -992,6 +1034,8 @@ hipError_t launch_resist(ilt_ctx *c, const float *I, const uint8_t *target, cons
                          double *part) {
     const size_t npix = (size_t)c->N * c->N;
     const int nblk = resist_blocks(c);
+    // clips (c->ncur) step by n_sets images, one target and their partials
+    const size_t ics = (size_t)c->n_sets * npix, pcs = (size_t)c->n_part;
     if (npix % 4 == 0 && reinterpret_cast<uintptr_t>(I) % 16 == 0 && reinterpret_cast<uintptr_t>(G) % 16 == 0 &&
         reinterpret_cast<uintptr_t>(target) % 4 == 0)
     {
@@ -1001,17 +1045,18 @@ hipError_t launch_resist(ilt_ctx *c, const float *I, const uint8_t *target, cons
         const bool three = ra.n_corners == 3 && ra.cset[0] == 0 && ra.cset[1] == 0 && ra.cset[2] == 1 &&
                            ra.set_used[0] && ra.set_used[1] && !ra.set_used[2] && !ra.set_used[3];
         const size_t ch = chunk_of(npix / 4, nblk);
-        if (one) k_resist4<1><<<nblk, RB, 0, c->stream>>>(I, npix, target, ra, npix, ch, G, part);
-        else if (three) k_resist4<2><<<nblk, RB, 0, c->stream>>>(I, npix, target, ra, npix, ch, G, part);
-        else k_resist4<0><<<nblk, RB, 0, c->stream>>>(I, npix, target, ra, npix, ch, G, part);
+        if (one) k_resist4<1><<<dim3(nblk, c->ncur), RB, 0, c->stream>>>(I, npix, target, ra, npix, ch, G, part, ics, npix, pcs);
+        else if (three) k_resist4<2><<<dim3(nblk, c->ncur), RB, 0, c->stream>>>(I, npix, target, ra, npix, ch, G, part, ics, npix, pcs);
+        else k_resist4<0><<<dim3(nblk, c->ncur), RB, 0, c->stream>>>(I, npix, target, ra, npix, ch, G, part, ics, npix, pcs);
     }
     else
-        k_resist1<<<nblk, RB, 0, c->stream>>>(I, npix, target, ra, npix, chunk_of(npix, nblk), G, part);
+        k_resist1<<<dim3(nblk, c->ncur), RB, 0, c->stream>>>(I, npix, target, ra, npix, chunk_of(npix, nblk), G, part,
+                                                              ics, npix, pcs);
     return hipGetLastError();
 }
 
 hipError_t launch_finish_resist(ilt_ctx *c, const double *part, int nblk, double *scal, double *stats4) {
-    k_finish_resist<<<1, RB, 0, c->stream>>>(part, nblk, scal, stats4);
+    k_finish_resist<<<c->ncur, RB, 0, c->stream>>>(part, nblk, scal, stats4, (size_t)c->n_part);
     return hipGetLastError();
 }
 
@@ -1037,7 +1082,7 @@ hipError_t launch_absmax(ilt_ctx *c, const float *v, double *part) {
 
 hipError_t launch_finish_dt(ilt_ctx *c, const double *part, int nblk, int dt_mode, float eta, float dt_max,
                             double *scal) {
-    k_finish_dt<<<1, RB, 0, c->stream>>>(part, nblk, dt_mode, eta, dt_max, scal);
+    k_finish_dt<<<c->ncur, RB, 0, c->stream>>>(part, nblk, dt_mode, eta, dt_max, scal, (size_t)c->n_part);
     return hipGetLastError();
 }
 
@@ -1049,7 +1094,8 @@ int step_blocks(const ilt_ctx *c) {
 hipError_t launch_levelset(ilt_ctx *c, const float *phi, const float *vel, const float *mod, float lam,
                            float eps_kappa, const double *scal, float *phi_out, double *part) {
     const int nb = (c->N + 31) / 32;
-    k_levelset<<<dim3(nb, nb), 256, 0, c->stream>>>(phi, vel, mod, lam, eps_kappa, scal, c->N, phi_out, part);
+    k_levelset<<<dim3(nb, nb, c->ncur), 256, 0, c->stream>>>(phi, vel, mod, lam, eps_kappa, scal, c->N, phi_out, part,
+                                                             (size_t)c->n_part);
     return hipGetLastError();
 }
 
@@ -1057,8 +1103,9 @@ static double g_ns_per_tick = 10.0;
 void set_ns_per_tick(double v) { g_ns_per_tick = v; }
 
 hipError_t launch_finish_step(ilt_ctx *c, const double *part, int nblk, double *scal, double *stats4,
-                              double *trace_row, int iter) {
-    k_finish_step<<<1, RB, 0, c->stream>>>(part, nblk, scal, stats4, trace_row, iter, g_ns_per_tick);
+                              double *trace_row, int iter, double *const *trace_tab, int row) {
+    k_finish_step<<<c->ncur, RB, 0, c->stream>>>(part, nblk, scal, stats4, trace_row, iter, g_ns_per_tick,
+                                                 (size_t)c->n_part, trace_tab, row);
     return hipGetLastError();
 }
 
@@ -1076,25 +1123,31 @@ size_t edt_scratch_bytes(int N) {
 
 template <typename TP>
 hipError_t edt_any(hipStream_t st, int N, const TP *phi, const uint8_t *mask, TP *phi_out, int *sqdist,
-                   float d_lower, float d_upper, void *scratch) {
+                   float d_lower, float d_upper, void *scratch, int nclip = 1) {
+    // nclip images one after another (and as many scratch areas); squared
+    // distances only for one
+    if (nclip > 1 && sqdist) return hipErrorInvalidValue;
     const int W = (N + 31) / 32;
+    const size_t scr_words = edt_scratch_bytes(N) / sizeof(uint32_t);
     uint32_t *colbits = static_cast<uint32_t *>(scratch);
     int16_t *info = reinterpret_cast<int16_t *>(colbits + (size_t)W * N);
     const int vec = (N % 4) == 0 && (phi ? reinterpret_cast<uintptr_t>(phi) % 16 == 0
                                          : reinterpret_cast<uintptr_t>(mask) % 4 == 0);
-    const dim3 g1((N + 255) / 256, W);
-    if (phi) k_edt_bits<true, TP><<<g1, 256, 0, st>>>(phi, nullptr, N, vec, colbits);
-    else k_edt_bits<false, TP><<<g1, 256, 0, st>>>(nullptr, mask, N, vec, colbits);
-    k_edt_colinfo<<<(N + EDT_CB - 1) / EDT_CB, 256, (size_t)W * EDT_CB * sizeof(uint32_t), st>>>(colbits, N, info);
+    const dim3 g1((N + 255) / 256, W, nclip);
+    if (phi) k_edt_bits<true, TP><<<g1, 256, 0, st>>>(phi, nullptr, N, vec, colbits, scr_words);
+    else k_edt_bits<false, TP><<<g1, 256, 0, st>>>(nullptr, mask, N, vec, colbits, scr_words);
+    k_edt_colinfo<<<dim3((N + EDT_CB - 1) / EDT_CB, nclip), 256, (size_t)W * EDT_CB * sizeof(uint32_t), st>>>(
+        colbits, N, info, scr_words);
     // row pass: bands of M >= N / 64 columns per lane (a power of two)
+    const dim3 gr(N, nclip);
     switch (edt_band(N)) {
-    case 1: k_edt_rows_env<1, TP><<<N, 128, 0, st>>>(colbits, info, N, d_lower, d_upper, phi_out, sqdist); break;
-    case 2: k_edt_rows_env<2, TP><<<N, 128, 0, st>>>(colbits, info, N, d_lower, d_upper, phi_out, sqdist); break;
-    case 4: k_edt_rows_env<4, TP><<<N, 128, 0, st>>>(colbits, info, N, d_lower, d_upper, phi_out, sqdist); break;
-    case 8: k_edt_rows_env<8, TP><<<N, 128, 0, st>>>(colbits, info, N, d_lower, d_upper, phi_out, sqdist); break;
-    case 16: k_edt_rows_env<16, TP><<<N, 128, 0, st>>>(colbits, info, N, d_lower, d_upper, phi_out, sqdist); break;
-    case 32: k_edt_rows_env<32, TP><<<N, 128, 0, st>>>(colbits, info, N, d_lower, d_upper, phi_out, sqdist); break;
-    default: k_edt_rows_env<64, TP><<<N, 128, 0, st>>>(colbits, info, N, d_lower, d_upper, phi_out, sqdist); break;
+    case 1: k_edt_rows_env<1, TP><<<gr, 128, 0, st>>>(colbits, info, N, d_lower, d_upper, phi_out, sqdist, scr_words); break;
+    case 2: k_edt_rows_env<2, TP><<<gr, 128, 0, st>>>(colbits, info, N, d_lower, d_upper, phi_out, sqdist, scr_words); break;
+    case 4: k_edt_rows_env<4, TP><<<gr, 128, 0, st>>>(colbits, info, N, d_lower, d_upper, phi_out, sqdist, scr_words); break;
+    case 8: k_edt_rows_env<8, TP><<<gr, 128, 0, st>>>(colbits, info, N, d_lower, d_upper, phi_out, sqdist, scr_words); break;
+    case 16: k_edt_rows_env<16, TP><<<gr, 128, 0, st>>>(colbits, info, N, d_lower, d_upper, phi_out, sqdist, scr_words); break;
+    case 32: k_edt_rows_env<32, TP><<<gr, 128, 0, st>>>(colbits, info, N, d_lower, d_upper, phi_out, sqdist, scr_words); break;
+    default: k_edt_rows_env<64, TP><<<gr, 128, 0, st>>>(colbits, info, N, d_lower, d_upper, phi_out, sqdist, scr_words); break;
     }
     return hipGetLastError();
 }
@@ -1111,7 +1164,7 @@ hipError_t launch_edt64(ilt_ctx *c, const double *phi, const uint8_t *mask, doub
 
 hipError_t launch_edt(ilt_ctx *c, const float *phi, const uint8_t *mask, float *phi_out, int *sqdist,
                       float d_lower, float d_upper) {
-    return launch_edt_raw(c->stream, c->N, phi, mask, phi_out, sqdist, d_lower, d_upper, c->edt_scratch);
+    return edt_any<float>(c->stream, c->N, phi, mask, phi_out, sqdist, d_lower, d_upper, c->edt_scratch, c->ncur);
 }
 
 hipError_t launch_copy(ilt_ctx *c, float *dst, const float *src, size_t n) {
@@ -1126,7 +1179,7 @@ hipError_t launch_heaviside_shift(const float *phi, float dh, size_t n, float *o
 }
 
 hipError_t launch_set_scal(ilt_ctx *c, int slot, double v) {
-    k_set_scal<<<1, 64, 0, c->stream>>>(c->scal, slot, v);
+    k_set_scal<<<c->ncur, 64, 0, c->stream>>>(c->scal, slot, v);
     return hipGetLastError();
 }
 

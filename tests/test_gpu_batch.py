@@ -88,6 +88,58 @@ def test_batch_equals_single_clip_solves(ilt, prec, lanes):
     batch.close()
 
 
+@pytest.mark.parametrize("lanes,init_mode,graph", [(2, 0, True), (1, 1, True), (3, 0, False)])
+def test_batch_chunks_equal_single_clip_solves(ilt, lanes, init_mode, graph):
+    """Clips of one size with identical parameters run as one chunk (one
+    launch per phase for all of them); every clip must still equal, bit for
+    bit, its own ilt_solve: 5 clips of 64^2, 3 of 128^2, 2 of 256^2 with
+    one parameter set, and a 64^2 clip with another (a chunk of its own)."""
+    H, w = build_optics(256, 8.0, 9, 8)
+    sizes = (64, 128, 256)
+    spec = [(64, 21), (128, 22), (64, 23), (256, 24), (64, 25), (128, 26), (64, 27), (256, 28), (64, 29),
+            (128, 30), (64, 31)]
+    clips = []
+    for k, (N, seed) in enumerate(spec):
+        Z, pitch = _clip(N, seed)
+        clips.append((Z, pitch, 5 if k < len(spec) - 1 else 6))
+    _say("chunks", "lanes", lanes, "init", init_mode, "graph", graph)
+    batch = ilt.Batch(H, w, sizes, max_clips=16, n_lanes=lanes)
+    batch.set_graph(graph)
+    data = []
+    phi0s = []
+    for (Z, pitch, iters) in clips:
+        N = Z.shape[0]
+        phi0 = torch.as_tensor(np.where(Z != 0, -2.5, 2.5).astype(np.float32)).cuda()
+        phi0s.append(phi0.clone())
+        data.append((torch.as_tensor(Z).cuda(), phi0,
+                     ilt.Params.from_dict(dict(WORKLOADS["c0"]["params"], iters=iters, d_lower=-100.0 / pitch,
+                                               d_upper=900.0 / pitch), init_mode=init_mode),
+                     torch.zeros((iters, ilt.TRACE_W), dtype=torch.float64, device="cuda")))
+    reps = batch.solve(data)
+    got = [(d[1].clone(), d[3].clone()) for d in data]
+    if graph:
+        for d, p0 in zip(data, phi0s):
+            d[1].copy_(p0)
+            d[3].zero_()
+        reps2 = batch.solve(data)                  # replay
+        assert reps2 == reps
+        for d, (g_phi, g_tr) in zip(data, got):
+            assert torch.equal(d[1], g_phi)
+            assert torch.equal(d[3][:, :7], g_tr[:, :7])
+    for i, (Z, pitch, iters) in enumerate(clips):
+        N = Z.shape[0]
+        ctx = ilt.Context(H, w, N)
+        phi = phi0s[i].clone()
+        tr = torch.zeros((iters, ilt.TRACE_W), dtype=torch.float64, device="cuda")
+        rep = ctx.ilt_solve(torch.as_tensor(Z).cuda(), phi, data[i][2], trace=tr)
+        assert torch.equal(got[i][0], phi), i
+        assert torch.equal(got[i][1][:, :7], tr[:, :7]), i
+        assert (reps[i]["l2"], reps[i]["pvb"], reps[i]["loss"], reps[i]["flips"]) == \
+            (rep["l2"], rep["pvb"], rep["loss"], rep["flips"]), i
+        ctx.close()
+    batch.close()
+
+
 def test_batch_graph_replay_with_interleaved_work(ilt):
     H, w = build_optics(256, 8.0, 9, 8)
     batch = ilt.Batch(H, w, (64, 128), max_clips=4, n_lanes=2)
@@ -138,9 +190,10 @@ def test_batch_rejects_bad_clips(ilt):
 
 
 def test_batch_c3_shapes_against_oracle(ilt):
-    """The batched workload's own shapes: a 512^2 and a 1024^2 clip of one
+    """The batched workload's own shapes: 512^2 and 1024^2 clips of one
     2048 nm field (pitch 4 and 2 nm; 35 x 35 window, K = 24, nominal and
     defocus kernel sets, three corners, TSDF bounds in each pitch's pixels),
+    several of each size (so that they run as chunks, one launch per phase),
     one teacher-forced iteration each in one batched call, against the FP64
     oracle's iteration (Sec. II-B imaging, Sec. III-A DSO step), and bit for
     bit against per-clip ilt_solve."""
@@ -148,7 +201,8 @@ def test_batch_c3_shapes_against_oracle(ilt):
     from oracle import solve as o_solve
     from paper_2303_12529_amd.inputs import batch_clip, batch_optics
     H, w = batch_optics()
-    cases = [(512, 7001), (1024, 7002)]
+    # three 512^2 clips share one chunk, two 1024^2 clips another
+    cases = [(512, 7001), (1024, 7002), (512, 7003), (1024, 7004), (512, 7005)]
     data, ref = [], []
     for N, seed in cases:
         Z, prm = batch_clip(N, seed)
@@ -160,7 +214,7 @@ def test_batch_c3_shapes_against_oracle(ilt):
                      ilt.Params.from_dict(prm1, init_mode=1),
                      torch.zeros((1, ilt.TRACE_W), dtype=torch.float64, device="cuda")))
         ref.append((Z, phi0, prm1))
-    batch = ilt.Batch(H, w, (512, 1024), max_clips=2, n_lanes=2)
+    batch = ilt.Batch(H, w, (512, 1024), max_clips=len(cases), n_lanes=2)
     reps = batch.solve(data)
     for (Z, phi0, prm1), (_, phi, _, tr), rep in zip(ref, data, reps):
         N = Z.shape[0]
