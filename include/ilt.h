@@ -139,7 +139,11 @@ typedef struct {
 /* Create a context on the current HIP device.  Copies the kernels, builds
  * the DFT tables (FP64 on the host, rounded once to FP32) and allocates all
  * workspaces; nothing is allocated after this.  stream: a hipStream_t
- * (NULL = the default stream).  max_batch: reserved, pass 1. */
+ * (NULL = the default stream).  max_batch in [1, 64]: the clips of one size
+ * that the batched form (ilt_solve_batch) runs together in one launch per
+ * phase; the per-clip workspaces are allocated that many times.  Above 1
+ * only for ILT_FP32 without ILT_FLAG_GWINDOW_ADJOINT (else ILT_EUNSUPPORTED).
+ * The single-clip entry points below use the first clip's workspaces. */
 int ilt_create(ilt_ctx **out, const ilt_optics *optics, int max_batch, void *stream);
 int ilt_destroy(ilt_ctx *ctx);
 /* Thread-local message for the last non-OK status of this thread. */
@@ -320,10 +324,18 @@ int ilt_autotune(ilt_ctx *ctx, const char *cache_path, ilt_tuning *h_best, doubl
  * caller passes kernels whose frequency samples suit all of them (clips of
  * one physical field width at different pixel pitches).  n_lanes in
  * [1, ILT_BATCH_MAX_LANES]: clips are spread over that many internal streams
- * and run side by side; device memory grows with n_sizes x n_lanes contexts.
+ * and run side by side; device memory grows with n_sizes x n_lanes contexts, each
+ * holding the workspaces of one chunk of clips (below).
  * max_clips: largest n accepted by ilt_solve_batch.  stream: the caller's
  * stream (NULL = default); ilt_solve_batch orders its work after what is
  * already queued there and returns when every clip is done.
+ *
+ * The clips of one size and identical parameters (compared byte for byte)
+ * are run in chunks of up to (2048 / N)^2 clips (at most 16; one for
+ * conjugate-gradient solves and in the split-BF16 and G-window forms): one
+ * launch per phase covers every clip of a chunk, whose targets and phi are
+ * copied into the context's clip buffers and phi back at the end.  Chunks
+ * are spread over the lanes, longest first.
  *
  * ilt_solve_batch: clips[i] names a listed size N, its device target
  * [N][N] bytes, its phi [N][N] (in when params.init_mode = 1, out always;
