@@ -324,6 +324,7 @@ def batched(n_clips, lanes, precision):
            "iters_per_clip": clips[0][1]["iters"], "dtype": "f32" if precision == ilt.ILT_FP32 else "bf16x3"}
     for nl in sorted({lanes, 1}, reverse=True):
         b = ilt.Batch(H, w, BATCH_SIZES, max_clips=n_clips, n_lanes=nl, precision=precision)
+        tuned = b.autotune()               # clips per chunk and tuning per size
         b.solve(data)                      # captures the lanes' graphs
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -334,9 +335,32 @@ def batched(n_clips, lanes, precision):
         out["lanes_%d" % nl] = {"s_per_batch": round(dt, 4),
                                 "clip_iters_per_s": round(n_clips * clips[0][1]["iters"] / dt, 1),
                                 "algorithmic_tflops": round(flops / dt / 1e12, 2),
-                                "l2_sum": int(sum(r["l2"] for r in reps))}
+                                "l2_sum": int(sum(r["l2"] for r in reps)),
+                                "autotune": tuned}
     if lanes > 1:
         out["speedup_vs_one_lane"] = round(out["lanes_1"]["s_per_batch"] / out["lanes_%d" % lanes]["s_per_batch"], 3)
+    # the plain form: every clip alone through ilt_solve (a context per size,
+    # each clip's graph captured by a first call and its replay timed), the
+    # clips strictly one after another; same results bit for bit
+    ctxs = {N: ilt.Context(H, w, N, precision=precision) for N in BATCH_SIZES}
+    total, l2_plain = 0.0, 0
+    for (tgt, phi, prm, _), (Z, _p) in zip(data, clips):
+        ctx = ctxs[Z.shape[0]]
+        ctx.ilt_solve(tgt, phi, prm)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rep = ctx.ilt_solve(tgt, phi, prm)
+        torch.cuda.synchronize()
+        total += time.perf_counter() - t0
+        l2_plain += int(rep["l2"])
+    for c in ctxs.values():
+        c.close()
+    best = out["lanes_%d" % lanes]["s_per_batch"]
+    out["plain_one_clip_at_a_time"] = {"s_total": round(total, 4), "algorithmic_tflops": round(flops / total / 1e12, 2),
+                                       "l2_sum": l2_plain}
+    out["time_to_result_vs_plain"] = {"batched_s": best, "plain_s": round(total, 4),
+                                      "speedup": round(total / best, 3),
+                                      "same_final_l2": l2_plain == out["lanes_%d" % lanes]["l2_sum"]}
     return out
 
 

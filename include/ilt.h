@@ -367,6 +367,20 @@ int ilt_batch_destroy(ilt_batch *batch);
 int ilt_batch_set_graph(ilt_batch *batch, int enable);
 int ilt_solve_batch(ilt_batch *batch, int n, const ilt_clip *clips, ilt_report *h_reports);
 
+/* Project autotuner of the batched form.  For every listed size, times
+ * (HIP events, best of three after a warm-up, per clip and iteration, on
+ * chunks of a synthetic clip) the clips per chunk (the contexts' whole
+ * capacity, half of it, a quarter) crossed with the FP32 adjoint's field
+ * store and column split, and applies the fastest to every lane of that
+ * size; sizes run one clip per chunk get ilt_autotune's choice.  cache_path:
+ * NULL or a JSON-lines file; a line keyed by (arch, N, P, K, n_sets,
+ * precision, field buffer, chunk capacity) is reused, a new choice
+ * appended.  Outputs (each NULL or host [n_sizes]): the clips per chunk,
+ * the tuning and its time per clip and iteration (us).  Results of every
+ * clip stay those of ilt_solve with the same tuning.  Synchronous. */
+int ilt_batch_autotune(ilt_batch *batch, const char *cache_path, int *h_chunk, ilt_tuning *h_tuning,
+                       double *h_us_per_clip_iter);
+
 /* ------------------------------------------------------------------------
  * Full layouts (beyond one clip).  The paper optimises clips of a fixed
  * size (Sec. IV: 2048 x 2048); a larger layout is covered by N x N tiles

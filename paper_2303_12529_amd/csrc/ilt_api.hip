@@ -1226,6 +1226,7 @@ struct ilt_batch {
     hipGraphExec_t exec[ILT_BATCH_MAX_LANES] = {};
     std::vector<unsigned char> key;
     int use_graph = 1;
+    int chunk[ILT_BATCH_MAX_SIZES] = {};    // clips per chunk of each size (<= its contexts' nb)
 };
 
 // A chunk: clips of one size with identical parameters that one context
@@ -1293,7 +1294,7 @@ void plan_chunks(const ilt_batch *b, int n, const ilt_clip *clips, std::vector<b
     chunks.clear();
     for (int i = 0; i < n; ++i) {
         const int s = size_index(b, clips[i].N);
-        const int cap = clips[i].params.optimizer == 1 ? 1 : b->ctx[s][0]->nb;
+        const int cap = clips[i].params.optimizer == 1 ? 1 : b->chunk[s];
         batch_chunk *into = nullptr;
         for (int k = (int)chunks.size() - 1; k >= 0 && !into; --k) {
             batch_chunk &ch = chunks[k];
@@ -1427,6 +1428,7 @@ extern "C" int ilt_batch_create(ilt_batch **out, const ilt_optics *o, const int 
         // FP32 contexts run chunks of several clips of this size
         const bool multi = os.precision == ILT_FP32 && !(os.flags & ILT_FLAG_GWINDOW_ADJOINT);
         const int cap = multi ? std::min(chunk_capacity(sizes[s]), max_clips) : 1;
+        b->chunk[s] = cap;
         for (int l = 0; l < n_lanes; ++l) {
             const int r = ilt_create(&b->ctx[s][l], &os, cap, b->lane[l]);
             if (r != ILT_OK) {
@@ -1543,6 +1545,151 @@ extern "C" int ilt_solve_batch(ilt_batch *b, int n, const ilt_clip *clips, ilt_r
         if (bad) status = ILT_ENUMERIC;
     }
     if (status != ILT_OK) return fail(ILT_ENUMERIC, "non-finite loss or gradient in a clip of the batch");
+    return ILT_OK;
+}
+
+extern "C" int ilt_batch_autotune(ilt_batch *b, const char *cache_path, int *h_chunk, ilt_tuning *h_tuning,
+                                  double *h_us_per_clip_iter) {
+    if (!b) return fail(ILT_EINVAL, "batch is NULL");
+    batch_free_graphs(b);   // captured with the old settings
+    for (int s = 0; s < b->n_sizes; ++s) {
+        ilt_ctx *c = b->ctx[s][0];
+        ilt_tuning best{};
+        int best_nc = 1;
+        double best_us = 0.0;
+        if (c->nb == 1) {
+            // one clip per chunk: the single-clip tuner
+            double ms = 0.0;
+            const int r = ilt_autotune(c, cache_path, &best, &ms);
+            if (r < 0) return r;
+            best_us = 1e3 * ms;
+        } else {
+            // several clips per chunk: clips per chunk (the whole capacity,
+            // half, a quarter) x field store and adjoint column split, timed
+            // per clip and iteration on chunks of a synthetic clip
+            char extra[64];
+            std::snprintf(extra, sizeof extra, "\"chunk_capacity\": %d, ", c->nb);
+            const std::string key = tune_key(c) + extra;
+            bool cached = false;
+            if (cache_path) {
+                FILE *f = std::fopen(cache_path, "r");
+                if (f) {
+                    char line[1024];
+                    while (std::fgets(line, sizeof line, f)) {
+                        if (std::strncmp(line, key.c_str(), key.size()) != 0) continue;
+                        ilt_tuning v;
+                        int nc = 0;
+                        double us = 0.0;
+                        if (std::sscanf(line + key.size(),
+                                        "\"chunk\": %d, \"store_fields\": %d, \"st_xsplit\": %d, "
+                                        "\"us_per_clip_iter\": %lf",
+                                        &nc, &v.store_fields, &v.st_xsplit, &us) == 4 &&
+                            nc >= 1 && nc <= c->nb) {
+                            v.b3_xsplit = 0;
+                            v.xcd_remap = 1;
+                            best = v;
+                            best_nc = nc;
+                            best_us = us;
+                            cached = true;
+                        }
+                    }
+                    std::fclose(f);
+                }
+            }
+            if (!cached) {
+                std::vector<int> ncs;
+                for (int nc : {c->nb, c->nb / 2, c->nb / 4})
+                    if (nc >= 1 && std::find(ncs.begin(), ncs.end(), nc) == ncs.end()) ncs.push_back(nc);
+                std::vector<ilt_tuning> tun;
+                if (c->Est) {
+                    tun.push_back(ilt_tuning{1, 0, 1, 1});
+                    tun.push_back(ilt_tuning{1, 0, 1, 2});
+                }
+                tun.push_back(ilt_tuning{0, 0, 1, 0});
+                // the synthetic clip of ilt_autotune, in every clip slot
+                const int N = c->N;
+                const size_t npix = cs_npix(c);
+                std::vector<unsigned char> h_t(npix, 0);
+                const int w = std::max(1, N / 32), pitch = std::max(2, N / 8), m = N / 8;
+                for (int y = m; y < N - m; ++y)
+                    for (int x = m; x < N - m; ++x)
+                        h_t[(size_t)y * N + x] = ((y - m) % pitch < w) || ((x - m) % (2 * pitch) < w);
+                for (int j = 0; j < c->nb; ++j)
+                    HIPCHK(hipMemcpy(c->tgtb + j * npix, h_t.data(), npix, hipMemcpyHostToDevice));
+                ilt_params p{};
+                p.iters = 4;
+                p.reinit_every = 5;
+                p.eta = 0.85f;
+                p.dt_max = 5.0f;
+                p.lambda = 0.05f;
+                p.sigma_z = 50.0f;
+                p.i_th = 0.225f;
+                p.eps_kappa = 1e-12f;
+                p.d_lower = -100.0f;
+                p.d_upper = 900.0f;
+                p.n_corners = 1;
+                p.corners[0] = ilt_corner{0, 1.0f, 1.0f};
+                if (c->n_sets > 1) {
+                    p.n_corners = 3;
+                    p.corners[1] = ilt_corner{0, 1.02f, 7.5f};
+                    p.corners[2] = ilt_corner{1, 0.98f, 7.5f};
+                }
+                hipEvent_t e0 = nullptr, e1 = nullptr;
+                HIPCHK(hipEventCreate(&e0));
+                hipError_t e = hipEventCreate(&e1);
+                int rc = e == hipSuccess ? ILT_OK : fail(ILT_EDEVICE, "batch autotune: %s", hipGetErrorString(e));
+                const int saved_prof = c->profiling;
+                c->profiling = 0;
+                best_us = 1e30;
+                for (size_t ti = 0; ti < tun.size() && rc == ILT_OK; ++ti) {
+                    if ((rc = ilt_set_tuning(c, &tun[ti])) != ILT_OK) break;
+                    for (size_t ni = 0; ni < ncs.size() && rc == ILT_OK; ++ni) {
+                        c->ncur = ncs[ni];
+                        double us = 1e30;
+                        // one warm-up solve, then the fastest of three
+                        for (int rep = 0; rep < 4 && rc == ILT_OK && e == hipSuccess; ++rep) {
+                            if ((e = hipEventRecord(e0, c->stream)) != hipSuccess) break;
+                            if ((rc = enqueue_solve(c, c->tgtb, c->phib, nullptr, &p, nullptr)) != ILT_OK) break;
+                            if ((e = hipEventRecord(e1, c->stream)) != hipSuccess) break;
+                            if ((e = hipEventSynchronize(e1)) != hipSuccess) break;
+                            float ms = 0.f;
+                            if ((e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) break;
+                            if (rep > 0) us = std::min(us, 1e3 * ms / (p.iters * ncs[ni]));
+                        }
+                        c->ncur = 1;
+                        if (rc == ILT_OK && e == hipSuccess && us < best_us) {
+                            best_us = us;
+                            best = tun[ti];
+                            best_nc = ncs[ni];
+                        }
+                    }
+                }
+                c->ncur = 1;
+                c->profiling = saved_prof;
+                if (rc == ILT_OK && e != hipSuccess) rc = fail(ILT_EDEVICE, "batch autotune: %s", hipGetErrorString(e));
+                (void)hipEventDestroy(e0);
+                if (e1) (void)hipEventDestroy(e1);
+                if (rc != ILT_OK) return rc;
+                if (cache_path) {
+                    FILE *f = std::fopen(cache_path, "a");
+                    if (!f) return fail(ILT_EINVAL, "cannot append to the tuning cache %s", cache_path);
+                    std::fprintf(f, "%s\"chunk\": %d, \"store_fields\": %d, \"st_xsplit\": %d, "
+                                    "\"us_per_clip_iter\": %.4f}\n",
+                                 key.c_str(), best_nc, best.store_fields, best.st_xsplit, best_us);
+                    std::fclose(f);
+                }
+            }
+        }
+        for (int l = 0; l < b->n_lanes; ++l) {
+            const int r = ilt_set_tuning(b->ctx[s][l], &best);
+            if (r != ILT_OK) return r;
+        }
+        b->chunk[s] = best_nc;
+        if (h_chunk) h_chunk[s] = best_nc;
+        if (h_tuning) h_tuning[s] = best;
+        if (h_us_per_clip_iter) h_us_per_clip_iter[s] = best_us;
+    }
+    b->key.clear();
     return ILT_OK;
 }
 

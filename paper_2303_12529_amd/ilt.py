@@ -110,6 +110,8 @@ def load_library(path: str = LIB_PATH):
         "ilt_batch_destroy": [_VP],
         "ilt_batch_set_graph": [_VP, ctypes.c_int],
         "ilt_solve_batch": [_VP, ctypes.c_int, ctypes.POINTER(_Clip), ctypes.POINTER(_Report)],
+        "ilt_batch_autotune": [_VP, ctypes.c_char_p, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(_Tuning),
+                               ctypes.POINTER(ctypes.c_double)],
         "ilt_layout_extract": [_VP, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, _VP, _VP],
         "ilt_layout_stitch": [_VP, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, _VP, _VP],
         "ilt_layout_grid": [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
@@ -428,6 +430,18 @@ class Batch:
 
     def set_graph(self, enable: bool = True):
         _check(load_library().ilt_batch_set_graph(self._h, 1 if enable else 0))
+
+    def autotune(self, cache_path=None):
+        """Clips per chunk and tuning per size (ilt_batch_autotune)."""
+        n = len(self.sizes)
+        chunk = (ctypes.c_int * n)()
+        tun = (_Tuning * n)()
+        us = (ctypes.c_double * n)()
+        _check(load_library().ilt_batch_autotune(self._h, cache_path.encode() if cache_path else None, chunk, tun,
+                                                 us))
+        return [dict(N=self.sizes[i], chunk=int(chunk[i]), store_fields=int(tun[i].store_fields),
+                     st_xsplit=int(tun[i].st_xsplit), b3_xsplit=int(tun[i].b3_xsplit),
+                     xcd_remap=int(tun[i].xcd_remap), us_per_clip_iter=round(float(us[i]), 3)) for i in range(n)]
 
     def solve(self, clips):
         import torch

@@ -140,6 +140,44 @@ def test_batch_chunks_equal_single_clip_solves(ilt, lanes, init_mode, graph):
     batch.close()
 
 
+def test_batch_autotune_keeps_results(ilt, tmp_path):
+    """The batch autotuner picks clips per chunk and a tuning per size; the
+    chunked solve then equals, bit for bit, per-clip ilt_solve with that
+    size's tuning, and a second tuner call reads its choice from the cache."""
+    H, w = build_optics(256, 8.0, 9, 8)
+    sizes = (64, 128)
+    batch = ilt.Batch(H, w, sizes, max_clips=16, n_lanes=2)
+    cache = str(tmp_path / "tune.jsonl")
+    choice = batch.autotune(cache)
+    _say("batch autotune", choice)
+    for c in choice:
+        assert 1 <= c["chunk"] <= 16
+        assert c["us_per_clip_iter"] > 0
+    again = batch.autotune(cache)                   # from the cache
+    keys = ("N", "chunk", "store_fields", "st_xsplit", "b3_xsplit", "xcd_remap")
+    assert [{k: c[k] for k in keys} for c in again] == [{k: c[k] for k in keys} for c in choice]
+    clips = []
+    for k, (N, seed) in enumerate([(64, 41), (64, 42), (128, 43), (64, 44), (128, 45), (64, 46)]):
+        Z, pitch = _clip(N, seed)
+        clips.append((Z, pitch, 5))
+    got, reps = _run_batch(ilt, batch, clips)
+    by_size = {c["N"]: c for c in choice}
+    for i, (Z, pitch, iters) in enumerate(clips):
+        N = Z.shape[0]
+        ctx = ilt.Context(H, w, N)
+        c = by_size[N]
+        ctx.set_tuning(store_fields=c["store_fields"], b3_xsplit=c["b3_xsplit"], xcd_remap=c["xcd_remap"],
+                       st_xsplit=c["st_xsplit"])
+        phi = torch.empty((N, N), dtype=torch.float32, device="cuda")
+        tr = torch.zeros((iters, ilt.TRACE_W), dtype=torch.float64, device="cuda")
+        rep = ctx.ilt_solve(torch.as_tensor(Z).cuda(), phi, _params(ilt, pitch, iters), trace=tr)
+        assert np.array_equal(got[i][0], phi.cpu().numpy()), i
+        assert np.array_equal(got[i][1][:, :7], tr.cpu().numpy()[:, :7]), i
+        assert (reps[i]["l2"], reps[i]["pvb"], reps[i]["loss"]) == (rep["l2"], rep["pvb"], rep["loss"])
+        ctx.close()
+    batch.close()
+
+
 def test_batch_graph_replay_with_interleaved_work(ilt):
     H, w = build_optics(256, 8.0, 9, 8)
     batch = ilt.Batch(H, w, (64, 128), max_clips=4, n_lanes=2)
