@@ -31,7 +31,7 @@ def _edges(Z):
     for orient in ("h", "v"):
         A = P if orient == "h" else P.T
         n_lines = A.shape[0] - 1
-        for line in range(1, n_lines):
+        for line in range(1, n_lines + 1):
             above, below = A[line - 1, 1:-1], A[line, 1:-1]
             for sign, mask in ((+1, above & ~below), (-1, ~above & below)):
                 idx = np.flatnonzero(mask)

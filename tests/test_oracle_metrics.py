@@ -50,3 +50,17 @@ def test_l_shape_edges_are_split_at_corners():
     lengths = sorted(b - a for _, _, a, b, _ in edges)
     # an L has six straight edges: outer 40 and 40, inner 30 and 30, ends 10 and 10 px
     assert lengths == [10, 10, 30, 30, 40, 40]
+
+
+def test_edges_on_the_image_border_are_sampled():
+    # a rectangle touching the last row and the last column: its bottom and
+    # right edges lie on the image border and are target edges like the rest
+    Z = _rect((32, 48), 12, 32, 20, 48)
+    edges = metrics._edges(Z)
+    assert sorted((o, line, a, b, s) for o, line, a, b, s in edges) == sorted([
+        ("h", 12, 20, 48, -1), ("h", 32, 20, 48, +1), ("v", 20, 12, 32, -1), ("v", 48, 12, 32, +1)])
+    v = metrics.epe(Z, Z, 1.0)
+    # 28 px edges: samples at 5, 15 nm (the last at most 23); 20 px edges: 5, 15
+    assert v.size == 2 * 2 + 2 * 2 and np.all(v == 0.0)
+    # nothing printed beyond the border: outward search finds the boundary at once
+    assert np.all(metrics.epe(Z, np.zeros_like(Z), 1.0) == -40.0)
