@@ -242,14 +242,21 @@ def time_to_target(ctxs, workload, seeds, extra_iters=10):
             t0 = time.perf_counter()
             ctx.ilt_solve(tgt, phi, p)
             torch.cuda.synchronize()
-            row[name] = {"iters": n_it, "ms": round(1e3 * (time.perf_counter() - t0), 3),
-                         "l2_at_T": int(l2[T]) if T < tmax else None}
+            ms = round(1e3 * (time.perf_counter() - t0), 3)
+            # the mask at the hit: edge placement error of its nominal print
+            aerial = ctx.litho_forward_phi(phi, 0)
+            e = ilt.epe(tgt, aerial, prm["i_th"], 2048.0 / N)
+            row[name] = {"iters": n_it, "ms": ms, "l2_at_T": int(l2[T]) if T < tmax else None,
+                         "epe_nm_at_hit": round(e["mean_abs_nm"], 3)}
         per_seed.append(row)
     out = {"target": "L2 of the plain FP32 loop after its configured iterations from TSDF(target)",
            "seeds": list(seeds), "per_seed": per_seed, "median_ms": {}}
+    out["median_epe_nm_at_hit"] = {}
     for name in list(ctxs) + ["fp32_cg"]:
         ms = [r[name]["ms"] for r in per_seed if r.get(name)]
         out["median_ms"][name] = round(float(np.median(ms)), 3) if len(ms) == len(per_seed) else None
+        ep = [r[name]["epe_nm_at_hit"] for r in per_seed if r.get(name)]
+        out["median_epe_nm_at_hit"][name] = round(float(np.median(ep)), 3) if ep else None
     for name in ctxs:
         if name != "fp32" and out["median_ms"].get("fp32") and out["median_ms"].get(name):
             out["%s_speedup_vs_plain" % name] = round(out["median_ms"]["fp32"] / out["median_ms"][name], 3)
@@ -287,6 +294,8 @@ def develset_ttt(seeds):
             ev = develset.evaluate(net, seeds, precision=prec, flags=flags)
             r = {"median_ms_plain": ev["median_ms_plain"], "median_ms_develset": ev["median_ms_develset"],
                  "speedup": ev.get("speedup"), "dsn_used": ev["dsn_used"],
+                 "median_epe_nm_at_hit": {"plain": ev["median_epe_nm_plain"], "develset": ev["median_epe_nm_develset"],
+                                          "develset_m": ev.get("median_epe_nm_develset_m")},
                  "iters_develset": [x["iters_develset"] for x in ev["per_seed"]],
                  "l2_at_T_plain": [x["l2_at_T_plain"] for x in ev["per_seed"]],
                  "l2_at_T_develset": [x["l2_at_T_develset"] for x in ev["per_seed"]]}
@@ -295,6 +304,25 @@ def develset_ttt(seeds):
                          iters_develset_m=[x["iters_develset_m"] for x in ev["per_seed"]],
                          l2_at_T_develset_m=[x["l2_at_T_develset_m"] for x in ev["per_seed"]])
             res[name] = r
+        if modulation:
+            # the paper's own curvature weight (lambda = 0.9, eta = 0.85; the
+            # CFL cap of the curvature term scaled with it): where curvature
+            # drives the loop, what the modulation map gains
+            ov = {"eta": 0.85, "lam": 0.9, "dt_max": 0.25 / 0.9}
+            ev = develset.evaluate(net, seeds, precision=ilt.ILT_FP32, overrides=ov)
+            res["fp32_lambda_0.9"] = {
+                "settings": ov, "median_ms_plain": ev["median_ms_plain"],
+                "median_epe_nm_at_hit": {"plain": ev["median_epe_nm_plain"], "develset": ev["median_epe_nm_develset"],
+                                         "develset_m": ev.get("median_epe_nm_develset_m")},
+                "median_ms_develset": ev["median_ms_develset"], "speedup": ev.get("speedup"),
+                "median_ms_develset_m": ev.get("median_ms_develset_m"), "speedup_m": ev.get("speedup_m"),
+                "dsn_used": ev["dsn_used"],
+                "iters_plain": [x["iters_plain"] for x in ev["per_seed"]],
+                "iters_develset": [x["iters_develset"] for x in ev["per_seed"]],
+                "iters_develset_m": [x["iters_develset_m"] for x in ev["per_seed"]],
+                "l2_at_T_plain": [x["l2_at_T_plain"] for x in ev["per_seed"]],
+                "l2_at_T_develset": [x["l2_at_T_develset"] for x in ev["per_seed"]],
+                "l2_at_T_develset_m": [x["l2_at_T_develset_m"] for x in ev["per_seed"]]}
         net.close()
         if label == "weights":
             out.update(res)

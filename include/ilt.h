@@ -230,6 +230,21 @@ int edt_reinit_noalloc(int N, const float *d_phi, const unsigned char *d_mask, f
 int ilt_solve(ilt_ctx *ctx, const unsigned char *d_target, float *d_phi,
               const ilt_params *params, ilt_report *h_report, double *d_trace);
 
+/* Edge placement error of the print [I >= I_th] (the hard threshold of
+ * Sec. II-C) against the target; the paper scores masks by L2 and PVBand
+ * and defines no EPE, so this is the library's own reading: sample points
+ * every step along each straight edge of the (Manhattan) target, from
+ * `end` after its ends; at each, the signed pixel distance along the
+ * edge's outward normal from the target edge to the print's boundary
+ * (positive: the print extends beyond the target), searched within
+ * ceil(search / pitch) pixels and clipped to +-search.  d_target [N][N]
+ * bytes, d_aerial [N][N] FP32 on the device; pitch_nm > 0; h_sampling: NULL
+ * (10, 5, 40, 15 nm) or host float[4] {step, end, search, limit} in nm.
+ * d_out: device double[4] = {samples, mean |EPE| nm, max |EPE| nm, samples
+ * with |EPE| > limit}.  Async on stream (NULL = default); no context. */
+int ilt_epe(const unsigned char *d_target, const float *d_aerial, float i_th, int N, float pitch_nm,
+            const float *h_sampling, double *d_out, void *stream);
+
 /* The loop and its two transforms in FP64, on an ILT_FP64 context: the
  * same steps and arguments as litho_forward, litho_adjoint and ilt_solve
  * with FP64 images (d_mask, d_aerial, d_dL_dI, d_dL_dM, d_phi: double

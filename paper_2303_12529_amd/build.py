@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libilt.so")
-SOURCES = ["ilt_api.hip", "k_litho.hip", "k_pixel.hip", "k_bf16.hip", "k_layout.hip", "k_fp64.hip", "dsn.hip"]
+SOURCES = ["ilt_api.hip", "k_litho.hip", "k_pixel.hip", "k_bf16.hip", "k_layout.hip", "k_fp64.hip", "k_metrics.hip", "dsn.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -1693,6 +1693,25 @@ extern "C" int ilt_batch_autotune(ilt_batch *b, const char *cache_path, int *h_c
     return ILT_OK;
 }
 
+extern "C" int ilt_epe(const unsigned char *d_target, const float *d_aerial, float i_th, int N, float pitch_nm,
+                       const float *h_sampling, double *d_out, void *stream) {
+    int r;
+    if (N < 1 || N > ILT_MAX_N) return fail(ILT_EINVAL, "N=%d outside [1, %d]", N, ILT_MAX_N);
+    if ((r = check_ptr(d_target, "d_target", 1)) || (r = check_ptr(d_aerial, "d_aerial")) ||
+        (r = check_ptr(d_out, "d_out", 8)))
+        return r;
+    if (!(pitch_nm > 0.f) || !std::isfinite(pitch_nm)) return fail(ILT_EINVAL, "pitch_nm must be positive");
+    if (!std::isfinite(i_th)) return fail(ILT_EINVAL, "i_th is not finite");
+    double smp[4] = {10.0, 5.0, 40.0, 15.0};
+    if (h_sampling)
+        for (int q = 0; q < 4; ++q) smp[q] = h_sampling[q];
+    if (!(smp[0] > 0.0) || !(smp[1] >= 0.0) || !(smp[2] > 0.0) || !(smp[3] >= 0.0))
+        return fail(ILT_EINVAL, "need step > 0, end >= 0, search > 0, limit >= 0");
+    HIPCHK(launch_epe(d_target, d_aerial, i_th, N, (double)pitch_nm, smp[0], smp[1], smp[2], smp[3], d_out,
+                      static_cast<hipStream_t>(stream)));
+    return ILT_OK;
+}
+
 // ---------------------------------------------------------------- full layouts
 
 namespace {

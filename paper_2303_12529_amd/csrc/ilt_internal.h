@@ -275,6 +275,11 @@ hipError_t launch_edt64(ilt_ctx *c, const double *phi, const uint8_t *mask, doub
                         float d_lower, float d_upper);
 #define ILT_FP64_MAX_N 2048
 
+// ---- edge placement error (k_metrics.hip): out[4] = samples, mean |EPE| (nm),
+// max |EPE| (nm), samples with |EPE| > limit ----
+hipError_t launch_epe(const unsigned char *Z, const float *I, float i_th, int N, double pitch, double step_nm,
+                      double end_nm, double search_nm, double limit_nm, double *out, hipStream_t st);
+
 // ---- full-layout tiling and shot count (k_layout.hip) ----
 // tiles per column / row of the layout grid (cores of C = N - 2 halo pixels)
 inline void layout_grid_dims(int H, int W, int N, int halo, int *rows, int *cols) {

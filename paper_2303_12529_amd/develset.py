@@ -134,11 +134,15 @@ def train(net: "_dsn.Net", x, t, epochs: int, batch: int, lr: float = 1e-3, seed
 
 
 def evaluate(net: "_dsn.Net", seeds, precision: int = _ilt.ILT_FP32, extra_iters: int = 10, log=None,
-             flags: int = 0):
+             flags: int = 0, overrides: dict | None = None):
     """Time to the plain loop's L2 from TSDF(target) vs from the network's
-    phi_0, with the loop in the given precision and context flags."""
+    phi_0, with the loop in the given precision and context flags;
+    overrides: loop settings that replace the 2048^2 workload's (e.g. the
+    curvature weight)."""
     import torch
     _, H, w, prm = workload_inputs("c1", 0)
+    if overrides:
+        prm = dict(prm, **overrides)
     N = 2048
     ctx = _ilt.Context(H, w, N, precision=precision, flags=flags)
     ctx.autotune()
@@ -205,6 +209,9 @@ def evaluate(net: "_dsn.Net", seeds, precision: int = _ilt.ILT_FP32, extra_iters
                 torch.cuda.synchronize()
                 dt = time.perf_counter() - t0
             row["ms_" + name] = round(1e3 * dt, 3)
+            # the mask at the hit: edge placement error of its nominal print
+            ctx.litho_forward_phi(phi[0], 0, out=I[0])
+            row["epe_" + name] = round(_ilt.epe(tgt[0], I[0], prm["i_th"], C1_CLIP.pitch_nm)["mean_abs_nm"], 3)
         rows.append(row)
         if log:
             log("eval seed %d: %s" % (seed, row))
@@ -213,12 +220,15 @@ def evaluate(net: "_dsn.Net", seeds, precision: int = _ilt.ILT_FP32, extra_iters
     out = {"per_seed": rows,
            "median_ms_plain": float(np.median([r["ms_plain"] for r in ok])) if ok else None,
            "median_ms_develset": float(np.median([r["ms_develset"] for r in ok])) if ok else None,
+           "median_epe_nm_plain": float(np.median([r["epe_plain"] for r in ok])) if ok else None,
+           "median_epe_nm_develset": float(np.median([r["epe_develset"] for r in ok])) if ok else None,
            "dsn_used": sum(r["dsn_used"] for r in rows)}
     if ok:
         out["speedup"] = round(out["median_ms_plain"] / out["median_ms_develset"], 3)
     if net.modulation:
         okm = [r for r in rows if r["ms_plain"] and r.get("ms_develset_m")]
         out["median_ms_develset_m"] = float(np.median([r["ms_develset_m"] for r in okm])) if okm else None
+        out["median_epe_nm_develset_m"] = float(np.median([r["epe_develset_m"] for r in okm])) if okm else None
         out["reached_develset_m"] = len(okm)
         if okm:
             out["speedup_m"] = round(float(np.median([r["ms_plain"] for r in okm])) / out["median_ms_develset_m"], 3)

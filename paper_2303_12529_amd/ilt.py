@@ -92,6 +92,7 @@ def load_library(path: str = LIB_PATH):
         "litho_adjoint_f64": [_VP, _VP, _VP, ctypes.c_int, _VP],
         "ilt_solve_f64": [_VP, _VP, _VP, ctypes.POINTER(_Params), ctypes.POINTER(_Report), _VP],
         "ilt_shifted_heaviside": [_VP, ctypes.c_float, ctypes.c_longlong, _VP, _VP],
+        "ilt_epe": [_VP, _VP, ctypes.c_float, ctypes.c_int, ctypes.c_float, ctypes.POINTER(ctypes.c_float), _VP, _VP],
         "litho_adjoint": [_VP, _VP, _VP, ctypes.c_int, _VP],
         "resist_loss": [_VP, _VP, _VP, ctypes.POINTER(_Params), _VP, _VP],
         "levelset_step": [_VP, _VP, _VP, _VP, ctypes.POINTER(_Params), _VP],
@@ -516,6 +517,23 @@ def edt_reinit_noalloc(N: int, d_lower: float, d_upper: float, phi=None, mask=No
         float(d_lower), float(d_upper), _ptr(phi_out, torch.float32, (N, N), "phi_out", dev),
         _ptr(sqdist, torch.int32, (2, N, N), "sqdist", dev), _stream_of(phi_out)))
     return phi_out
+
+
+def epe(target, aerial, i_th: float, pitch_nm: float, sampling=None):
+    """Edge placement error of the print [aerial >= i_th] against target
+    (both [N, N] on the device): {samples, mean_abs_nm, max_abs_nm,
+    over_limit}; sampling: None or (step, end, search, limit) in nm."""
+    import torch
+    N = int(target.shape[0])
+    dev = target.device
+    out = torch.zeros(4, dtype=torch.float64, device=dev)
+    smp = None if sampling is None else (ctypes.c_float * 4)(*[float(v) for v in sampling])
+    _check(load_library().ilt_epe(_ptr(target, torch.uint8, (N, N), "target", dev),
+                                  _ptr(aerial, torch.float32, (N, N), "aerial", dev), float(i_th), N,
+                                  float(pitch_nm), smp, _ptr(out, torch.float64, (4,), "out", dev),
+                                  _stream_of(target)))
+    v = out.cpu().tolist()
+    return {"samples": int(v[0]), "mean_abs_nm": v[1], "max_abs_nm": v[2], "over_limit": int(v[3])}
 
 
 def layout_grid(H: int, W: int, N: int, halo: int):
