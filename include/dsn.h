@@ -52,9 +52,10 @@ enum { DSN_OK = 0, DSN_EINVAL = -1, DSN_ENOMEM = -2, DSN_EDEVICE = -3 };
 typedef struct dsn_ctx dsn_ctx;
 
 /* H, W: network grid, multiples of 8 (three poolings), at most 2048;
- * base: level-0 width, 32 or 64; max_batch >= 1; modulation: 1 adds the
- * modulation head, 0 leaves it out.  Allocates the parameters (zero), Adam
- * moments, and activations/gradients for max_batch samples.
+ * base: level-0 width, 32 or 64; max_batch >= 1 with max_batch H W below
+ * 2^31; modulation: 1 adds the modulation head, 0 leaves it out.  Allocates
+ * the parameters (zero), Adam moments, and activations/gradients for
+ * max_batch samples.
  * stream: a hipStream_t (NULL = default stream). */
 int dsn_create(dsn_ctx **out, int H, int W, int base, int max_batch, int modulation, void *stream);
 int dsn_destroy(dsn_ctx *ctx);
@@ -108,15 +109,19 @@ int dsn_predict(dsn_ctx *ctx, const unsigned char *d_target, int B, float d_lowe
  *   (H' = H/2, W' = W/2; else H' = H, W' = W); d_w [Cout][3][3][Cin]; d_b
  *   FP32 [Cout] or NULL; relu != 0 applies max(., 0).
  * dsn_op_conv3x3_dgrad: d_dx [N][H][W][Cin] = gradient of sum(d_dy . conv(x))
- *   with respect to x (no upsampling), d_dy [N][H][W][Cout].
+ *   with respect to x (no upsampling), d_dy [N][H][W][Cout]; with d_mask
+ *   (BF16 [N][H][W][Cin], or NULL) d_dx is zeroed where d_mask <= 0: the
+ *   backward of the ReLU whose output is d_mask, fused.
  * dsn_op_conv3x3_wgrad: FP32 d_dw [Cout][3][3][Cin] and d_db [Cout], the
  *   gradients of sum(d_dz . conv(x)) with d_dz [N][H][W][Cout] and x as in
- *   dsn_op_conv3x3.
+ *   dsn_op_conv3x3: per split of whole 8 x 32 pixel tiles FP32 partials of
+ *   all nine taps (the bias from the same staged d_dz), the splits added in
+ *   FP64 in a fixed order.
  * Channel counts: multiples of 32 in [32, 1024]. */
 int dsn_op_conv3x3(const void *d_x, int N, int H, int W, int Cin, int up, const void *d_w, const float *d_b,
                    int Cout, int relu, void *d_y, void *stream);
-int dsn_op_conv3x3_dgrad(const void *d_dy, int N, int H, int W, int Cout, const void *d_w, int Cin, void *d_dx,
-                         void *stream);
+int dsn_op_conv3x3_dgrad(const void *d_dy, int N, int H, int W, int Cout, const void *d_w, int Cin,
+                         const void *d_mask, void *d_dx, void *stream);
 int dsn_op_conv3x3_wgrad(const void *d_dz, const void *d_x, int N, int H, int W, int Cin, int up, int Cout,
                          float *d_dw, float *d_db, void *stream);
 
@@ -129,8 +134,8 @@ int dsn_op_conv3x3_wgrad(const void *d_dz, const void *d_x, int N, int H, int W,
  *   [8, 1024].  Async on `stream`.
  * dsn_op_wgrad_first: its weight and bias gradients, FP32 d_dw [C][3][3][1]
  *   and d_db [C], for the output gradient d_dz BF16 [N][H][W][C] and input
- *   d_x FP32 [N][H][W]: sums over pixel ranges (512 pixels each, at most
- *   4096 ranges; a range may cross image boundaries) in FP32, the ranges
+ *   d_x FP32 [N][H][W]: sums over pixel ranges (4096 pixels each, at most
+ *   2048 ranges; a range may cross image boundaries) in FP32, the ranges
  *   added in FP64 in a fixed order.  C in {8, 16, 32, 64}.  Synchronous;
  *   allocates and frees the range partials.
  * dsn_op_head_bwd: backward of the 1x1 head(s) and the losses for npix
@@ -142,14 +147,18 @@ int dsn_op_conv3x3_wgrad(const void *d_dz, const void *d_x, int N, int H, int W,
  *   = g w + g_m w_m with g = (2/B)(out - t), g_m = (2/B)(H_eps(out_m) - t_m)
  *   H_eps'(out_m); d_loss double[2] = {L_0, L_m (0 without the head)};
  *   d_gw FP32 [heads][C + 1] = per head the weight gradient sum_p g x[p]
- *   then the bias gradient sum_p g.  Synchronous; allocates and frees the
- *   block partials.
+ *   then the bias gradient sum_p g.  relu_mask != 0 also zeroes d_dx where
+ *   d_x <= 0 (the backward of the ReLU that produced the features).
+ *   Synchronous; allocates and frees the block partials.
  * dsn_op_maxpool2_bwd: d_dx BF16 [N][H][W][C] += each gradient of d_dy BF16
  *   [N][H/2][W/2][C] routed to the first maximum (row-major) of its 2x2
  *   window of d_x BF16 [N][H][W][C]; the sum in FP32, rounded once to BF16.
+ *   relu_mask != 0 then zeroes every element of the windows where d_x <= 0
+ *   (d_x a ReLU output: the ReLU's backward, fused).
  * dsn_op_upsample2_bwd: d_dx BF16 [N][H/2][W/2][C] = the FP32 sum of the
  *   four children in d_dy BF16 [N][H][W][C] (nearest 2x upsampling's
- *   gradient), rounded once to BF16.
+ *   gradient), rounded once to BF16; with d_mask (BF16 [N][H/2][W/2][C], or
+ *   NULL) zeroed where d_mask <= 0.
  * dsn_op_relu_bwd: d_d BF16 [npix][C] *= [d_y > 0] in place (d_y BF16, the
  *   layer's output).
  * The last three: H, W even, C a multiple of 8 in [8, 2048]; async. */
@@ -158,10 +167,12 @@ int dsn_op_conv_first(const float *d_x, int N, int H, int W, const void *d_w, co
 int dsn_op_wgrad_first(const void *d_dz, const float *d_x, int N, int H, int W, int C, float *d_dw, float *d_db,
                        void *stream);
 int dsn_op_head_bwd(const void *d_x, long long npix, int C, int B, const void *d_w, const void *d_wm,
-                    const float *d_out, const float *d_out_m, const float *d_t, const float *d_t_m, void *d_dx,
-                    double *d_loss, float *d_gw, void *stream);
-int dsn_op_maxpool2_bwd(const void *d_x, int N, int H, int W, int C, const void *d_dy, void *d_dx, void *stream);
-int dsn_op_upsample2_bwd(const void *d_dy, int N, int H, int W, int C, void *d_dx, void *stream);
+                    const float *d_out, const float *d_out_m, const float *d_t, const float *d_t_m, int relu_mask,
+                    void *d_dx, double *d_loss, float *d_gw, void *stream);
+int dsn_op_maxpool2_bwd(const void *d_x, int N, int H, int W, int C, const void *d_dy, int relu_mask, void *d_dx,
+                        void *stream);
+int dsn_op_upsample2_bwd(const void *d_dy, int N, int H, int W, int C, const void *d_mask, void *d_dx,
+                         void *stream);
 int dsn_op_relu_bwd(void *d_d, const void *d_y, long long npix, int C, void *stream);
 
 #ifdef __cplusplus

@@ -71,37 +71,44 @@ struct View {
 };
 
 // --------------------------------------------------------------------------
-// First convolution (one input channel), VALU: thread = (pixel, 8 channels).
+// First convolution (one input channel), VALU: thread = pixel, all output
+// channels in groups of 8 (one 16-byte store each); the weights and biases
+// as FP32 in LDS (dynamic, Cout x 10 floats), read as broadcasts.  Pixel
+// coordinates from 32-bit divisions (npix < 2^31, checked on the host).
 // --------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_conv_first(const float *__restrict__ x, int B, int H, int W,
                                                      const __bf16 *__restrict__ w, const float *__restrict__ bias,
                                                      View y) {
-    const int groups = y.C / 8;
-    const long long id = (long long)blockIdx.x * 256 + threadIdx.x;
-    const long long npix = (long long)B * H * W;
-    if (id >= npix * groups) return;
-    const long long pix = id / groups;
-    const int g = (int)(id - pix * groups);
-    const int xx = (int)(pix % W);
-    const long long r = pix / W;
-    const int yy = (int)(r % H);
-    const int b = (int)(r / H);
+    extern __shared__ float wsh[];                 // [Cout][9] then [Cout] biases
+    const int C = y.C;
+    for (int i = threadIdx.x; i < C * 10; i += 256) wsh[i] = i < C * 9 ? (float)w[i] : bias[i - C * 9];
+    __syncthreads();
+    const unsigned npix = (unsigned)B * H * W;
+    const unsigned pix = blockIdx.x * 256u + threadIdx.x;
+    if (pix >= npix) return;
+    const unsigned r = pix / (unsigned)W;
+    const int xx = (int)(pix - r * W);
+    const unsigned b = r / (unsigned)H;
+    const int yy = (int)(r - b * H);
     float in[9];
 #pragma unroll
     for (int t = 0; t < 9; ++t) {
         const int sy = yy + t / 3 - 1, sx = xx + t % 3 - 1;
         in[t] = (sy >= 0 && sy < H && sx >= 0 && sx < W) ? x[((size_t)b * H + sy) * W + sx] : 0.f;
     }
-    bf8 out;
+    __bf16 *dst = y.p + (size_t)pix * y.stride;
+    for (int g = 0; g < C / 8; ++g) {
+        bf8 out;
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-        const int co = 8 * g + e;
-        float acc = bias[co];
+        for (int e = 0; e < 8; ++e) {
+            const int co = 8 * g + e;
+            float acc = wsh[C * 9 + co];
 #pragma unroll
-        for (int t = 0; t < 9; ++t) acc = fmaf((float)w[co * 9 + t], in[t], acc);
-        out[e] = (__bf16)fmaxf(acc, 0.f);
+            for (int t = 0; t < 9; ++t) acc = fmaf(wsh[co * 9 + t], in[t], acc);
+            out[e] = (__bf16)fmaxf(acc, 0.f);
+        }
+        *reinterpret_cast<bf8 *>(dst + 8 * g) = out;
     }
-    *reinterpret_cast<bf8 *>(y.p + pix * y.stride + 8 * g) = out;
 }
 
 // --------------------------------------------------------------------------
@@ -118,7 +125,8 @@ __global__ __launch_bounds__(256) void k_conv_first(const float *__restrict__ x,
 // --------------------------------------------------------------------------
 template <int WPX, int WCO, int CB, int PB, bool UP>
 __global__ __launch_bounds__(256) void k_conv(View x, int B, int H, int W, const __bf16 *__restrict__ w,
-                                              int Cin, const float *__restrict__ bias, int relu, View y) {
+                                              int Cin, const float *__restrict__ bias, int relu, View y,
+                                              View mask) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int l16 = lane & 15, lq = lane >> 4;
     const int wp = wave % WPX, wc = wave / WPX;
@@ -184,6 +192,12 @@ __global__ __launch_bounds__(256) void k_conv(View x, int B, int H, int W, const
                 if (relu) v = fmaxf(v, 0.f);
                 o[i] = (__bf16)v;
             }
+            if (mask.p) {
+                const bf4 m = *reinterpret_cast<const bf4 *>(mask.p + pix * mask.stride + c);
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    if (!((float)m[i] > 0.f)) o[i] = (__bf16)0.f;
+            }
             *reinterpret_cast<bf4 *>(y.p + pix * y.stride + c) = o;
         }
     }
@@ -191,39 +205,44 @@ __global__ __launch_bounds__(256) void k_conv(View x, int B, int H, int W, const
 
 // --------------------------------------------------------------------------
 // 3x3 convolution with LDS-staged operands.  Block: an 8 x 32 pixel tile of
-// one image x 32 output channels; per 32-channel input chunk it stages the
-// tile's input pixels with a one-pixel halo (zero outside the image; through
-// the nearest 2x upsampling when UP) and the 32 x 9 x 32 weights in LDS, then
-// each of the nine taps reads its shifted window from LDS.  Wave w: rows 2w
-// and 2w + 1 of the tile (4 matrix blocks of 16 pixels) x 32 channels.  Row
-// strides of 40 and 296 elements make the 16-byte reads of 8 consecutive
-// lanes hit distinct banks.  Every output sums input-channel chunks, then
-// taps.
+// one image x TC (64 or 32) output channels; per 32-channel input chunk it
+// stages the tile's input pixels with a one-pixel halo (zero outside the
+// image; through the nearest 2x upsampling when UP) and the TC x 9 x 32
+// weights in LDS.  Wave w: the 16-pixel column strip w & 1 of the tile x 32
+// output channels, over all 8 rows (TC = 64: channels 32 (w >> 1) on) or
+// over rows 4 (w >> 1) .. + 3 (TC = 32).  Per chunk the wave keeps its 9 x 2
+// weight operands in registers and walks down its rows: each halo row's
+// three shifted input operands are read once and serve the three output
+// rows whose taps touch it.  Pixel and channel strides of 40 and 296
+// elements make the 16-byte reads of 8 consecutive lanes hit distinct
+// banks.  Every output sums input-channel chunks, then taps in order.
 // --------------------------------------------------------------------------
-constexpr int CL_TY = 8, CL_TX = 32, CL_TC = 32;
+constexpr int CL_TY = 8, CL_TX = 32;
 constexpr int CL_XS = 40;                         // LDS elements per staged pixel
 constexpr int CL_WS = 9 * 32 + 8;                 // LDS elements per staged output channel
 constexpr int CL_NPX = (CL_TY + 2) * (CL_TX + 2);
 
-template <bool UP>
-__global__ __launch_bounds__(256) void k_conv_lds(View x, int B, int H, int W, const __bf16 *__restrict__ w,
-                                                  int Cin, const float *__restrict__ bias, int relu, View y) {
+template <bool UP, int TC>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_conv_lds(
+    View x, int B, int H, int W, const __bf16 *__restrict__ w, int Cin, const float *__restrict__ bias, int relu,
+    View y, View mask) {
+    constexpr int RW = TC == 64 ? 8 : 4;          // output rows per wave
     __shared__ __attribute__((aligned(16))) __bf16 Xs[CL_NPX * CL_XS];
-    __shared__ __attribute__((aligned(16))) __bf16 Ws[CL_TC * CL_WS];
+    __shared__ __attribute__((aligned(16))) __bf16 Ws[TC * CL_WS];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int l16 = lane & 15, lq = lane >> 4;
+    const int strip = wave & 1;
+    const int cw = TC == 64 ? 32 * (wave >> 1) : 0, row0 = TC == 64 ? 0 : 4 * (wave >> 1);
     const int ntx = (W + CL_TX - 1) / CL_TX, nty = (H + CL_TY - 1) / CL_TY;
     const int tix = blockIdx.x % ntx, rest = blockIdx.x / ntx;
     const int tiy = rest % nty, b = rest / nty;
-    const int x0 = tix * CL_TX, y0 = tiy * CL_TY, co0 = blockIdx.y * CL_TC;
+    const int x0 = tix * CL_TX, y0 = tiy * CL_TY, co0 = blockIdx.y * TC;
     const int Hin = UP ? H / 2 : H, Win = UP ? W / 2 : W;
     constexpr int XU = (CL_NPX * 4 + 255) / 256;  // 16-byte input units per thread
-    constexpr int WU = (CL_TC * 36 + 255) / 256;  // 16-byte weight units per thread
-    f4 acc[2][4];
+    constexpr int WU = (TC * 36 + 255) / 256;     // 16-byte weight units per thread
+    f4 acc[RW][2];
 #pragma unroll
-    for (int cb = 0; cb < 2; ++cb)
-#pragma unroll
-        for (int pb = 0; pb < 4; ++pb) acc[cb][pb] = f4{0.f, 0.f, 0.f, 0.f};
+    for (int r = 0; r < RW; ++r) acc[r][0] = acc[r][1] = f4{0.f, 0.f, 0.f, 0.f};
     for (int ci0 = 0; ci0 < Cin; ci0 += 32) {
         bf8 xv[XU], wv[WU];
 #pragma unroll
@@ -243,7 +262,7 @@ __global__ __launch_bounds__(256) void k_conv_lds(View x, int B, int H, int W, c
 #pragma unroll
         for (int u = 0; u < WU; ++u) {
             const int e = threadIdx.x + 256 * u;
-            if (e < CL_TC * 36) {
+            if (e < TC * 36) {
                 const int col = e / 36, rem = e % 36;
                 wv[u] = *reinterpret_cast<const bf8 *>(w + ((size_t)(co0 + col) * 9 + rem / 4) * Cin + ci0 +
                                                        8 * (rem % 4));
@@ -258,45 +277,61 @@ __global__ __launch_bounds__(256) void k_conv_lds(View x, int B, int H, int W, c
 #pragma unroll
         for (int u = 0; u < WU; ++u) {
             const int e = threadIdx.x + 256 * u;
-            if (e < CL_TC * 36) {
+            if (e < TC * 36) {
                 const int col = e / 36, rem = e % 36;
                 *reinterpret_cast<bf8 *>(&Ws[col * CL_WS + (rem / 4) * 32 + 8 * (rem % 4)]) = wv[u];
             }
         }
         __syncthreads();
+        bf8 a[9][2];
 #pragma unroll
-        for (int t = 0; t < 9; ++t) {
-            const int dy = t / 3, dx = t % 3;         // halo offsets 0..2
-            bf8 a[2], bv[4];
-#pragma unroll
-            for (int cb = 0; cb < 2; ++cb)
-                a[cb] = *reinterpret_cast<const bf8 *>(&Ws[(16 * cb + l16) * CL_WS + t * 32 + 8 * lq]);
-#pragma unroll
-            for (int pb = 0; pb < 4; ++pb) {
-                const int r = 2 * wave + (pb >> 1), c = 16 * (pb & 1) + l16;
-                bv[pb] = *reinterpret_cast<const bf8 *>(&Xs[((r + dy) * (CL_TX + 2) + c + dx) * CL_XS + 8 * lq]);
-            }
+        for (int t = 0; t < 9; ++t)
 #pragma unroll
             for (int cb = 0; cb < 2; ++cb)
+                a[t][cb] = *reinterpret_cast<const bf8 *>(&Ws[(cw + 16 * cb + l16) * CL_WS + t * 32 + 8 * lq]);
+        // the three column shifts of halo row hr (of the wave's rows)
+        const __bf16 *xcol = Xs + (16 * strip + l16) * CL_XS + 8 * lq;
+        bf8 bw[3][3];
+        auto load_row = [&](int hr, bf8(&o)[3]) {
 #pragma unroll
-                for (int pb = 0; pb < 4; ++pb) acc[cb][pb] = mfma_b(a[cb], bv[pb], acc[cb][pb]);
+            for (int dx = 0; dx < 3; ++dx)
+                o[dx] = *reinterpret_cast<const bf8 *>(xcol + ((row0 + hr) * (CL_TX + 2) + dx) * CL_XS);
+        };
+        load_row(0, bw[0]);
+        load_row(1, bw[1]);
+#pragma unroll
+        for (int r = 0; r < RW; ++r) {
+            load_row(r + 2, bw[(r + 2) % 3]);
+#pragma unroll
+            for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+                for (int dx = 0; dx < 3; ++dx)
+#pragma unroll
+                    for (int cb = 0; cb < 2; ++cb)
+                        acc[r][cb] = mfma_b(a[3 * dy + dx][cb], bw[(r + dy) % 3][dx], acc[r][cb]);
         }
     }
-    // register i of acc[cb][pb]: channel co0 + 16 cb + 4 lq + i, pixel (row r, column c) of the tile
+    // register i of acc[r][cb]: channel co0 + cw + 16 cb + 4 lq + i, pixel (row row0 + r, column 16 strip + l16)
 #pragma unroll
-    for (int pb = 0; pb < 4; ++pb) {
-        const int gy = y0 + 2 * wave + (pb >> 1), gx = x0 + 16 * (pb & 1) + l16;
+    for (int r = 0; r < RW; ++r) {
+        const int gy = y0 + row0 + r, gx = x0 + 16 * strip + l16;
         if (gy >= H || gx >= W) continue;
         const long long pix = ((long long)b * H + gy) * W + gx;
 #pragma unroll
         for (int cb = 0; cb < 2; ++cb) {
-            const int c = co0 + 16 * cb + 4 * lq;
+            const int c = co0 + cw + 16 * cb + 4 * lq;
             bf4 o;
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                float v = acc[cb][pb][i] + (bias ? bias[c + i] : 0.f);
+                float v = acc[r][cb][i] + (bias ? bias[c + i] : 0.f);
                 if (relu) v = fmaxf(v, 0.f);
                 o[i] = (__bf16)v;
+            }
+            if (mask.p) {
+                const bf4 m = *reinterpret_cast<const bf4 *>(mask.p + pix * mask.stride + c);
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    if (!((float)m[i] > 0.f)) o[i] = (__bf16)0.f;
             }
             *reinterpret_cast<bf4 *>(y.p + pix * y.stride + c) = o;
         }
@@ -304,130 +339,214 @@ __global__ __launch_bounds__(256) void k_conv_lds(View x, int B, int H, int W, c
 }
 
 // --------------------------------------------------------------------------
-// Weight gradient, split over pixel ranges:
-//   part[s][co][tap][ci] = sum_{pixel in range s} dz[pixel][co] x[src(pixel, tap)][ci]
-// Block tile TCO x TCI channels for one tap; per stage PXC pixels of dz and
-// of the shifted x are staged transposed ([channel][pixel]) in LDS so that
-// each lane reads 8 consecutive pixels as one operand.  Waves: one per
-// 32 x 32 quadrant; with fewer than four quadrants the remaining waves take
-// further 32-pixel slices of the stage and are summed at the end.
+// Weight gradient over spatial tiles, all nine taps per block:
+//   part[s][co][tap][ci] = sum over the pixels of split s of
+//                          dz[pixel][co] x[pixel + tap offset][ci]
+// A block owns TCO output x TCI input channels and a range of 8 x 32 pixel
+// tiles of the batch.  Per tile, dz is staged channel-major (Zs[co][pixel])
+// and x as the tile plus a one-pixel halo (Xs[ci][halo row][7 + halo
+// column], zero outside the image, through the nearest 2x upsampling when
+// UP), by 16-byte loads of 8 channels scattered into LDS; the next tile's
+// loads are in flight while the current one is multiplied.  A GEMM over
+// pixels: each wave owns 32 co x 16 ci and, per output row, reads its two dz
+// operands (8 consecutive pixels of one channel per lane) once and takes
+// them against the x operands of the three halo rows that the row's taps
+// touch, at the three column shifts.  The shifted operands come from three
+// aligned 16-byte reads per halo row and lane plus 32-bit funnel shifts; a
+// halo row's operands stay in registers for the three output rows that use
+// it.  Channel strides padded to 264 and 488 elements keep the lanes'
+// 16-byte reads on distinct banks.  FP32 accumulation; the partials of the
+// splits are summed in a fixed order afterwards.
+// With bpart, the blocks of the first input-channel tile also sum dz over
+// their pixels (the bias gradient) by products with a vector of ones: the
+// waves of a row of the block take the output rows in turn and write
+// bpart[split][wave column][co].
 // --------------------------------------------------------------------------
+constexpr int WT_TY = 8, WT_TX = 32, WT_HR = WT_TY + 2, WT_HC = WT_TX + 2, WT_XS = 48;
+constexpr int WT_ZST = WT_TY * WT_TX + 8;        // dz channel stride (elements)
+constexpr int WT_XST = WT_HR * WT_XS + 8;        // x channel stride (elements)
+
+// elements 1..8 of the 16-element sequence lo | hi
+__device__ __forceinline__ bf8 bf8_next(bf8 lo, bf8 hi) {
+    const u4 a = *reinterpret_cast<const u4 *>(&lo), b = *reinterpret_cast<const u4 *>(&hi);
+    u4 o;
+    o[0] = __builtin_amdgcn_alignbit(a[1], a[0], 16);
+    o[1] = __builtin_amdgcn_alignbit(a[2], a[1], 16);
+    o[2] = __builtin_amdgcn_alignbit(a[3], a[2], 16);
+    o[3] = __builtin_amdgcn_alignbit(b[0], a[3], 16);
+    return *reinterpret_cast<const bf8 *>(&o);
+}
+
+// elements 7..14 of the 16-element sequence lo | hi
+__device__ __forceinline__ bf8 bf8_prev(bf8 lo, bf8 hi) {
+    const u4 a = *reinterpret_cast<const u4 *>(&lo), b = *reinterpret_cast<const u4 *>(&hi);
+    u4 o;
+    o[0] = __builtin_amdgcn_alignbit(b[0], a[3], 16);
+    o[1] = __builtin_amdgcn_alignbit(b[1], b[0], 16);
+    o[2] = __builtin_amdgcn_alignbit(b[2], b[1], 16);
+    o[3] = __builtin_amdgcn_alignbit(b[3], b[2], 16);
+    return *reinterpret_cast<const bf8 *>(&o);
+}
+
 template <int TCO, int TCI, bool UP>
-__global__ __launch_bounds__(256) void k_wgrad(View dz, View x, int B, int H, int W, int Cin, int Cout,
-                                               long long pix_per_split, float *__restrict__ part) {
-    constexpr int NQ = (TCO / 32) * (TCI / 32);
-    constexpr int KS = 4 / NQ;                 // 32-pixel slices per stage
-    constexpr int PXC = 32 * KS;
-    constexpr int LD = PXC + 8;                // LDS row (bf16), padded
-    __shared__ __attribute__((aligned(16))) __bf16 Zs[TCO][LD];
-    __shared__ __attribute__((aligned(16))) __bf16 Xs[TCI][LD];
-    __shared__ float Red[KS > 1 ? 4 : 1][32][33];   // per wave
+__global__ __launch_bounds__((TCO / 32) * (TCI / 16) * 64) __attribute__((amdgpu_waves_per_eu(TCO * TCI > 1024 ? 2 : 1))) void k_wgrad_tile(View dz, View x, int B, int H, int W,
+                                                                          int Cin, int Cout, int tiles_per_split,
+                                                                          float *__restrict__ part,
+                                                                          float *__restrict__ bpart) {
+    constexpr int NWC = TCI / 16, NT = (TCO / 32) * NWC * 64;
+    constexpr int ZE = WT_TY * WT_TX * (TCO / 8), XE = WT_HR * WT_HC * (TCI / 8);
+    constexpr int ZL = (ZE + NT - 1) / NT, XL = (XE + NT - 1) / NT;     // 16-byte loads per thread
+    __shared__ __attribute__((aligned(16))) __bf16 Zs[TCO * WT_ZST];
+    __shared__ __attribute__((aligned(16))) __bf16 Xs[TCI * WT_XST];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int l16 = lane & 15, lq = lane >> 4;
-    const int q = wave % NQ, ks = wave / NQ;
-    const int qco = (q % (TCO / 32)) * 32, qci = (q / (TCO / 32)) * 32;
+    const int wco = (wave / NWC) * 32, wci = (wave % NWC) * 16;
     const int co_t = blockIdx.x * TCO, ci_t = blockIdx.y * TCI;
-    const int t = blockIdx.z % 9, s = blockIdx.z / 9;
-    const int dy = t / 3 - 1, dx = t % 3 - 1;
-    const long long npix = (long long)B * H * W;
-    const long long p_lo = (long long)s * pix_per_split;
-    const long long p_hi = p_lo + pix_per_split < npix ? p_lo + pix_per_split : npix;
+    const int ntx = (W + WT_TX - 1) / WT_TX, nty = (H + WT_TY - 1) / WT_TY;
+    const long long ntiles = (long long)B * nty * ntx;
+    const long long t0 = (long long)blockIdx.z * tiles_per_split;
+    const long long t1 = t0 + tiles_per_split < ntiles ? t0 + tiles_per_split : ntiles;
     const int Hin = UP ? H / 2 : H, Win = UP ? W / 2 : W;
-    f4 acc[2][2];
+    bf8 zv[ZL], xv[XL];
+    auto fetch = [&](long long tile) {
+        const int tx = (int)(tile % ntx);
+        const long long rest = tile / ntx;
+        const int ty = (int)(rest % nty), b = (int)(rest / nty);
+        const int x0 = tx * WT_TX, y0 = ty * WT_TY;
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
-    for (long long p0 = p_lo; p0 < p_hi; p0 += PXC) {
-        __syncthreads();
-        // stage dz: PXC pixels x TCO channels, 8 channels per thread-load
-        for (int e = threadIdx.x; e < PXC * (TCO / 8); e += 256) {
-            const int px = e / (TCO / 8), g = e % (TCO / 8);
-            const long long pix = p0 + px;
-            bf8 v = bf8_zero();
-            if (pix < p_hi) v = *reinterpret_cast<const bf8 *>(dz.p + pix * dz.stride + co_t + 8 * g);
-#pragma unroll
-            for (int k = 0; k < 8; ++k) Zs[8 * g + k][px] = v[k];
+        for (int u = 0; u < ZL; ++u) {
+            const int e = threadIdx.x + NT * u;
+            zv[u] = bf8_zero();
+            if (ZE % NT == 0 || e < ZE) {
+                const int p = e % (WT_TY * WT_TX), g = e / (WT_TY * WT_TX);
+                const int yy = y0 + p / WT_TX, xx = x0 + p % WT_TX;
+                if (yy < H && xx < W)
+                    zv[u] = *reinterpret_cast<const bf8 *>(dz.p + (((size_t)b * H + yy) * W + xx) * dz.stride +
+                                                           co_t + 8 * g);
+            }
         }
-        // stage x at the tap's source pixel
-        for (int e = threadIdx.x; e < PXC * (TCI / 8); e += 256) {
-            const int px = e / (TCI / 8), g = e % (TCI / 8);
-            const long long pix = p0 + px;
-            bf8 v = bf8_zero();
-            if (pix < p_hi) {
-                const int xx = (int)(pix % W);
-                const long long r = pix / W;
-                const int yy = (int)(r % H), b = (int)(r / H);
-                const int sy = yy + dy, sx = xx + dx;
-                if (sy >= 0 && sy < H && sx >= 0 && sx < W) {
-                    const int iy = UP ? (sy >> 1) : sy, ix = UP ? (sx >> 1) : sx;
-                    v = *reinterpret_cast<const bf8 *>(x.p + (((size_t)b * Hin + iy) * Win + ix) * x.stride + ci_t + 8 * g);
+#pragma unroll
+        for (int u = 0; u < XL; ++u) {
+            const int e = threadIdx.x + NT * u;
+            xv[u] = bf8_zero();
+            if (XE % NT == 0 || e < XE) {
+                const int hp = e % (WT_HR * WT_HC), g = e / (WT_HR * WT_HC);
+                const int gy = y0 + hp / WT_HC - 1, gx = x0 + hp % WT_HC - 1;
+                if (gy >= 0 && gy < H && gx >= 0 && gx < W) {
+                    const int sy = UP ? (gy >> 1) : gy, sx = UP ? (gx >> 1) : gx;
+                    xv[u] = *reinterpret_cast<const bf8 *>(x.p + (((size_t)b * Hin + sy) * Win + sx) * x.stride +
+                                                           ci_t + 8 * g);
                 }
             }
+        }
+    };
+    f4 acc[9][2], accb[2] = {f4{0.f, 0.f, 0.f, 0.f}, f4{0.f, 0.f, 0.f, 0.f}};
 #pragma unroll
-            for (int k = 0; k < 8; ++k) Xs[8 * g + k][px] = v[k];
+    for (int t = 0; t < 9; ++t) acc[t][0] = acc[t][1] = f4{0.f, 0.f, 0.f, 0.f};
+    const bool with_b = bpart != nullptr && blockIdx.y == 0;
+    bf8 ones;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) ones[k] = (__bf16)1.f;
+    if (t0 < t1) fetch(t0);
+    const __bf16 *xrow = Xs + (wci + l16) * WT_XST + 8 * lq;
+    const __bf16 *zrow0 = Zs + (wco + l16) * WT_ZST + 8 * lq;
+    const __bf16 *zrow1 = zrow0 + 16 * WT_ZST;
+    for (long long tile = t0; tile < t1; ++tile) {
+        __syncthreads();                                   // the previous tile's reads are done
+#pragma unroll
+        for (int u = 0; u < ZL; ++u) {
+            const int e = threadIdx.x + NT * u;
+            if (ZE % NT == 0 || e < ZE) {
+                const int p = e % (WT_TY * WT_TX), g = e / (WT_TY * WT_TX);
+#pragma unroll
+                for (int k = 0; k < 8; ++k) Zs[(8 * g + k) * WT_ZST + p] = zv[u][k];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < XL; ++u) {
+            const int e = threadIdx.x + NT * u;
+            if (XE % NT == 0 || e < XE) {
+                const int hp = e % (WT_HR * WT_HC), g = e / (WT_HR * WT_HC);
+                const int pos = (hp / WT_HC) * WT_XS + hp % WT_HC + 7;
+#pragma unroll
+                for (int k = 0; k < 8; ++k) Xs[(8 * g + k) * WT_XST + pos] = xv[u][k];
+            }
         }
         __syncthreads();
-        const int k0 = 32 * ks + 8 * lq;
-        bf8 a[2], bv[2];
+        if (tile + 1 < t1) fetch(tile + 1);
+        // x operands of halo row hr at the column shifts -1, 0, +1
+        bf8 rows[3][3];
+        auto load_row = [&](int hr, bf8(&op)[3]) {
+            const bf8 c0 = *reinterpret_cast<const bf8 *>(xrow + hr * WT_XS);
+            const bf8 c1 = *reinterpret_cast<const bf8 *>(xrow + hr * WT_XS + 8);
+            const bf8 c2 = *reinterpret_cast<const bf8 *>(xrow + hr * WT_XS + 16);
+            op[0] = bf8_prev(c0, c1);
+            op[1] = c1;
+            op[2] = bf8_next(c1, c2);
+        };
+        load_row(0, rows[0]);
+        load_row(1, rows[1]);
 #pragma unroll
-        for (int i = 0; i < 2; ++i) a[i] = *reinterpret_cast<const bf8 *>(&Zs[qco + 16 * i + l16][k0]);
+        for (int r = 0; r < WT_TY; ++r) {
+            load_row(r + 2, rows[(r + 2) % 3]);
+            const bf8 a0 = *reinterpret_cast<const bf8 *>(zrow0 + r * WT_TX);
+            const bf8 a1 = *reinterpret_cast<const bf8 *>(zrow1 + r * WT_TX);
 #pragma unroll
-        for (int j = 0; j < 2; ++j) bv[j] = *reinterpret_cast<const bf8 *>(&Xs[qci + 16 * j + l16][k0]);
+            for (int dy = 0; dy < 3; ++dy)
 #pragma unroll
-        for (int i = 0; i < 2; ++i)
-#pragma unroll
-            for (int j = 0; j < 2; ++j) acc[i][j] = mfma_b(a[i], bv[j], acc[i][j]);
-    }
-    // register r of acc[i][j]: co = qco + 16 i + 4 lq + r, ci = qci + 16 j + l16
-    if (KS > 1) {
-        __syncthreads();
-#pragma unroll
-        for (int i = 0; i < 2; ++i)
-#pragma unroll
-            for (int j = 0; j < 2; ++j)
-#pragma unroll
-                for (int r = 0; r < 4; ++r) Red[wave][16 * i + 4 * lq + r][16 * j + l16] = acc[i][j][r];
-        __syncthreads();
-        if (ks != 0) return;
-        // waves q, q + NQ, q + 2 NQ, ... hold the same quadrant's slices
-#pragma unroll
-        for (int i = 0; i < 2; ++i)
-#pragma unroll
-            for (int j = 0; j < 2; ++j)
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    float v = 0.f;
-                    for (int k = 0; k < KS; ++k) v += Red[q + NQ * k][16 * i + 4 * lq + r][16 * j + l16];
-                    acc[i][j][r] = v;
+                for (int dx = 0; dx < 3; ++dx) {
+                    const bf8 bo = rows[(r + dy) % 3][dx];
+                    acc[3 * dy + dx][0] = mfma_b(a0, bo, acc[3 * dy + dx][0]);
+                    acc[3 * dy + dx][1] = mfma_b(a1, bo, acc[3 * dy + dx][1]);
                 }
+            if (with_b && r % NWC == wave % NWC) {
+                accb[0] = mfma_b(a0, ones, accb[0]);
+                accb[1] = mfma_b(a1, ones, accb[1]);
+            }
+        }
     }
-    float *dst = part + (size_t)s * Cout * 9 * Cin;
+    if (with_b && l16 == 0) {
+        float *bd = bpart + ((size_t)blockIdx.z * NWC + wave % NWC) * Cout;
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+        for (int h = 0; h < 2; ++h)
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
+            for (int i = 0; i < 4; ++i) bd[co_t + wco + 16 * h + 4 * lq + i] = accb[h][i];
+    }
+    // register i of acc[t][h]: co = wco + 16 h + 4 lq + i, ci = wci + l16
+    float *dst = part + (size_t)blockIdx.z * Cout * 9 * Cin;
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int co = co_t + qco + 16 * i + 4 * lq + r, ci = ci_t + qci + 16 * j + l16;
-                dst[((size_t)co * 9 + t) * Cin + ci] = acc[i][j][r];
+    for (int t = 0; t < 9; ++t)
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int co = co_t + wco + 16 * h + 4 * lq + i, ci = ci_t + wci + l16;
+                dst[((size_t)co * 9 + t) * Cin + ci] = acc[t][h][i];
             }
 }
 
-// First layer (one input channel): part[s][co][tap] over a pixel range.
+// First layer (one input channel): part[s][co][tap] over a pixel range and,
+// after the S x C x 9 weight partials, the bias partials part[S C 9 + s C +
+// co].  Thread = (8 channels, pixel): one 16-byte dz load and the nine
+// neighbouring inputs (FP32, cached reads) per pixel, 80 FMAs into FP32
+// registers; then a shuffle tree over the wave's pixel lanes and the four
+// waves in order.  C in {8, 16, 32, 64}.
 __global__ __launch_bounds__(256) void k_wgrad_first(View dz, const float *__restrict__ x, int B, int H, int W,
                                                       long long pix_per_split, float *__restrict__ part) {
-    const int C = dz.C;                       // <= 64
-    __shared__ float red[256][10];
+    const int C = dz.C, G = C / 8;
+    __shared__ float red[4][8][81];
     const int s = blockIdx.x;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int g = threadIdx.x % G, ph = threadIdx.x / G, nph = 256 / G;
     const long long npix = (long long)B * H * W;
     const long long p_lo = (long long)s * pix_per_split;
     const long long p_hi = p_lo + pix_per_split < npix ? p_lo + pix_per_split : npix;
-    const int co = threadIdx.x % C, ph = threadIdx.x / C, nph = 256 / C;
-    float acc[10];
+    float acc[8][10];
 #pragma unroll
-    for (int k = 0; k < 10; ++k) acc[k] = 0.f;
-    // the thread's pixels advance by nph (< W): (b, yy, xx) stepped instead of
+    for (int e = 0; e < 8; ++e)
+#pragma unroll
+        for (int k = 0; k < 10; ++k) acc[e][k] = 0.f;
+    // the thread's pixels advance by nph: (b, yy, xx) stepped instead of
     // divided out per pixel
     long long pix = p_lo + ph;
     int xx = 0, yy = 0, b = 0;
@@ -438,13 +557,20 @@ __global__ __launch_bounds__(256) void k_wgrad_first(View dz, const float *__res
         b = (int)(r / H);
     }
     for (; pix < p_hi; pix += nph) {
-        const float d = (float)dz.p[pix * dz.stride + co];
+        const bf8 d = *reinterpret_cast<const bf8 *>(dz.p + pix * dz.stride + 8 * g);
+        float xv[9];
 #pragma unroll
         for (int t = 0; t < 9; ++t) {
             const int sy = yy + t / 3 - 1, sx = xx + t % 3 - 1;
-            if (sy >= 0 && sy < H && sx >= 0 && sx < W) acc[t] = fmaf(d, x[((size_t)b * H + sy) * W + sx], acc[t]);
+            xv[t] = (sy >= 0 && sy < H && sx >= 0 && sx < W) ? x[((size_t)b * H + sy) * W + sx] : 0.f;
         }
-        acc[9] += d;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const float de = (float)d[e];
+#pragma unroll
+            for (int t = 0; t < 9; ++t) acc[e][t] = fmaf(de, xv[t], acc[e][t]);
+            acc[e][9] += de;
+        }
         xx += nph;
         while (xx >= W) {
             xx -= W;
@@ -454,57 +580,29 @@ __global__ __launch_bounds__(256) void k_wgrad_first(View dz, const float *__res
             }
         }
     }
+    // lanes lane, lane ^ G, ... hold the same channels
 #pragma unroll
-    for (int k = 0; k < 10; ++k) red[threadIdx.x][k] = acc[k];
-    __syncthreads();
-    if (threadIdx.x < C) {
-        float v[10];
+    for (int e = 0; e < 8; ++e)
 #pragma unroll
-        for (int k = 0; k < 10; ++k) v[k] = 0.f;
-        for (int h = 0; h < nph; ++h)
-#pragma unroll
-            for (int k = 0; k < 10; ++k) v[k] += red[h * C + threadIdx.x][k];
-        // [s][co][tap] then bias partials [s][co] after all weights
-        for (int k = 0; k < 9; ++k) part[((size_t)s * C + threadIdx.x) * 9 + k] = v[k];
-        part[(size_t)gridDim.x * C * 9 + (size_t)s * C + threadIdx.x] = v[9];
-    }
-}
-
-// Bias gradient partials: part[s][c] = sum_{pixel in range s} dz[pixel][c].
-// Thread = (group of 8 channels, pixel lane): 16-byte loads, four pixels'
-// loads in flight; the pixel lanes are added in lane order.  C % 8 == 0,
-// C <= 2048, 16-byte aligned view.
-__global__ __launch_bounds__(256) void k_bias_grad(View dz, long long npix, long long pix_per_split,
-                                                    float *__restrict__ part) {
-    __shared__ float red[256][9];
-    const int C = dz.C, G = C / 8;
-    const int s = blockIdx.x;
-    const int g = threadIdx.x % G, ph = threadIdx.x / G, nph = 256 / G;
-    const long long p_lo = (long long)s * pix_per_split;
-    const long long p_hi = p_lo + pix_per_split < npix ? p_lo + pix_per_split : npix;
-    float acc[8];
-#pragma unroll
-    for (int e = 0; e < 8; ++e) acc[e] = 0.f;
-    for (long long pix = p_lo + ph; ph < nph && pix < p_hi; pix += 4LL * nph) {
-        bf8 v[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const long long q = pix + (long long)u * nph;
-            v[u] = q < p_hi ? *reinterpret_cast<const bf8 *>(dz.p + q * dz.stride + 8 * g) : bf8_zero();
+        for (int k = 0; k < 10; ++k) {
+            float v = acc[e][k];
+            for (int o = G; o < 64; o <<= 1) v += __shfl_xor(v, o, 64);
+            acc[e][k] = v;
         }
+    if (lane < G) {
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
+        for (int e = 0; e < 8; ++e)
 #pragma unroll
-            for (int e = 0; e < 8; ++e) acc[e] += (float)v[u][e];
+            for (int k = 0; k < 10; ++k) red[wave][lane][e * 10 + k] = acc[e][k];
     }
-#pragma unroll
-    for (int e = 0; e < 8; ++e) red[threadIdx.x][e] = acc[e];
     __syncthreads();
-    for (int c = threadIdx.x; c < C; c += 256) {
-        const int gc = c / 8, e = c % 8;
-        float v = 0.f;
-        for (int h = 0; h < nph; ++h) v += red[h * G + gc][e];
-        part[(size_t)s * C + c] = v;
+    for (int i = threadIdx.x; i < C * 10; i += 256) {
+        const int co = i / 10, k = i % 10;
+        const int gg = co / 8, e = co % 8;
+        const float v = ((red[0][gg][e * 10 + k] + red[1][gg][e * 10 + k]) + red[2][gg][e * 10 + k]) +
+                        red[3][gg][e * 10 + k];
+        if (k < 9) part[((size_t)s * C + co) * 9 + k] = v;
+        else part[(size_t)gridDim.x * C * 9 + (size_t)s * C + co] = v;
     }
 }
 
@@ -532,9 +630,54 @@ __global__ __launch_bounds__(256) void k_reduce_splits(const float *__restrict__
 
 // many outputs: 16 per block; few (biases, the head): one per block, all
 // 256 threads on its partials
+// The same sums for n % 4 == 0 and 16-byte aligned partials: a block of 1024
+// threads takes QB consecutive 4-float groups (16-byte loads) x 1024 / QB
+// phases over the splits; each thread adds its splits in order in FP64, then
+// the phases are added by a halving tree.  QB shrinks for short vectors so that the
+// splits spread over more threads (and more blocks).
+__global__ __launch_bounds__(1024) void k_reduce_splits4(const float *__restrict__ part, int S, long long n, int QB,
+                                                         float *__restrict__ out) {
+    __shared__ double red[4096];
+    const long long nq = n / 4;
+    const int qi = threadIdx.x % QB, ph = threadIdx.x / QB, P = 1024 / QB;
+    const long long q = (long long)blockIdx.x * QB + qi;
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    if (q < nq) {
+#pragma unroll 4
+        for (int s = ph; s < S; s += P) {
+            const float4 f = *reinterpret_cast<const float4 *>(part + (size_t)s * n + 4 * q);
+            v[0] += f.x;
+            v[1] += f.y;
+            v[2] += f.z;
+            v[3] += f.w;
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) red[threadIdx.x * 4 + k] = v[k];
+    // phases: a halving tree (P is a power of two)
+    for (int h = P / 2; h > 0; h >>= 1) {
+        __syncthreads();
+        if (ph < h)
+#pragma unroll
+            for (int k = 0; k < 4; ++k) red[threadIdx.x * 4 + k] += red[(threadIdx.x + h * QB) * 4 + k];
+    }
+    __syncthreads();
+    if (ph == 0 && q < nq)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) out[4 * q + k] = (float)red[qi * 4 + k];
+}
+
 void reduce_splits(const float *part, int S, long long n, float *out, hipStream_t st) {
-    if (n >= 4096) k_reduce_splits<16><<<(unsigned)((n + 15) / 16), 256, 0, st>>>(part, S, n, out);
-    else k_reduce_splits<1><<<(unsigned)n, 256, 0, st>>>(part, S, n, out);
+    if (n % 4 == 0 && reinterpret_cast<uintptr_t>(part) % 16 == 0) {
+        const long long nq = n / 4;
+        int QB = 64;
+        while (QB > 1 && (nq + QB - 1) / QB < 512) QB /= 2;
+        k_reduce_splits4<<<(unsigned)((nq + QB - 1) / QB), 1024, 0, st>>>(part, S, n, QB, out);
+    } else if (n >= 4096) {
+        k_reduce_splits<16><<<(unsigned)((n + 15) / 16), 256, 0, st>>>(part, S, n, out);
+    } else {
+        k_reduce_splits<1><<<(unsigned)n, 256, 0, st>>>(part, S, n, out);
+    }
 }
 
 // --------------------------------------------------------------------------
@@ -568,6 +711,7 @@ __global__ void k_maxpool(View x, int B, int H, int W, View y) {
 
 // dx (view holding the skip gradient) += gradient routed to the first
 // maximum (row-major order) of each 2x2 window.
+template <bool MASK>
 __global__ void k_maxpool_bwd(View x, int B, int H, int W, View dy, View dx) {
     const int groups = x.C / 8;
     const int Ho = H / 2, Wo = W / 2;
@@ -605,14 +749,16 @@ __global__ void k_maxpool_bwd(View x, int B, int H, int W, View dy, View dx) {
         __bf16 *q = dx.p + pi[k] * dx.stride + 8 * g;
         bf8 cur = *reinterpret_cast<const bf8 *>(q);
 #pragma unroll
-        for (int e = 0; e < 8; ++e)
+        for (int e = 0; e < 8; ++e) {
             if (arg[e] == k) cur[e] = (__bf16)((float)cur[e] + (float)d[e]);
+            if (MASK && !((float)v[k][e] > 0.f)) cur[e] = (__bf16)0.f;
+        }
         *reinterpret_cast<bf8 *>(q) = cur;
     }
 }
 
 // Gradient of the nearest 2x upsampling: dx[half pixel] = sum of its 4 children.
-__global__ void k_upsample_bwd(View dy, int B, int H, int W, View dx) {
+__global__ void k_upsample_bwd(View dy, int B, int H, int W, View dx, View mask) {
     const int groups = dx.C / 8;
     const int Ho = H / 2, Wo = W / 2;
     const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -636,6 +782,12 @@ __global__ void k_upsample_bwd(View dy, int B, int H, int W, View dx) {
     bf8 o;
 #pragma unroll
     for (int e = 0; e < 8; ++e) o[e] = (__bf16)s[e];
+    if (mask.p) {
+        const bf8 m = *reinterpret_cast<const bf8 *>(mask.p + po * mask.stride + 8 * g);
+#pragma unroll
+        for (int e = 0; e < 8; ++e)
+            if (!((float)m[e] > 0.f)) o[e] = (__bf16)0.f;
+    }
     *reinterpret_cast<bf8 *>(dx.p + po * dx.stride + 8 * g) = o;
 }
 
@@ -689,7 +841,7 @@ __device__ __forceinline__ float ahf_grad(float z) {
 __global__ __launch_bounds__(256) void k_head_bwd(View x, long long npix, int B, const __bf16 *__restrict__ w,
                                                    const __bf16 *__restrict__ wm, const float *__restrict__ out,
                                                    const float *__restrict__ out_m, const float *__restrict__ tgt,
-                                                   const float *__restrict__ tgt_m, View dx,
+                                                   const float *__restrict__ tgt_m, View dx, int relu_mask,
                                                    double *__restrict__ loss_part, float *__restrict__ gpart) {
     const int C = x.C;                      // <= 64, a multiple of 8
     const int NH = out_m ? 2 : 1;
@@ -716,8 +868,10 @@ __global__ __launch_bounds__(256) void k_head_bwd(View x, long long npix, int B,
             v[k] = *reinterpret_cast<const bf8 *>(x.p + pix * x.stride + c);
             bf8 o;
 #pragma unroll
-            for (int e = 0; e < 8; ++e)
+            for (int e = 0; e < 8; ++e) {
                 o[e] = (__bf16)(g * (float)w[c + e] + (out_m ? gm * (float)wm[c + e] : 0.f));
+                if (relu_mask && !((float)v[k][e] > 0.f)) o[e] = (__bf16)0.f;
+            }
             *reinterpret_cast<bf8 *>(dx.p + pix * dx.stride + c) = o;
         }
     }
@@ -882,23 +1036,32 @@ inline unsigned grid1(long long n, int bs = 256) { return (unsigned)((n + bs - 1
 // for smaller images.
 template <bool UP>
 void launch_conv_tiles(View x, int B, int H, int W, const __bf16 *w, int Cin, const float *bias, int relu, int Cout,
-                       View y, hipStream_t st) {
+                       View y, View mask, hipStream_t st) {
     if (H >= CL_TY && W >= CL_TX) {
         const long long tiles = (long long)B * ((H + CL_TY - 1) / CL_TY) * ((W + CL_TX - 1) / CL_TX);
-        k_conv_lds<UP><<<dim3((unsigned)tiles, Cout / CL_TC), 256, 0, st>>>(x, B, H, W, w, Cin, bias, relu, y);
+        if (Cout % 64 == 0)
+            k_conv_lds<UP, 64><<<dim3((unsigned)tiles, Cout / 64), 256, 0, st>>>(x, B, H, W, w, Cin, bias, relu, y,
+                                                                                mask);
+        else
+            k_conv_lds<UP, 32><<<dim3((unsigned)tiles, Cout / 32), 256, 0, st>>>(x, B, H, W, w, Cin, bias, relu, y,
+                                                                                mask);
         return;
     }
     const long long npix = (long long)B * H * W;
     if (Cout % 64 == 0)
-        k_conv<2, 2, 2, 2, UP><<<dim3(grid1(npix, 64), Cout / 64), 256, 0, st>>>(x, B, H, W, w, Cin, bias, relu, y);
+        k_conv<2, 2, 2, 2, UP><<<dim3(grid1(npix, 64), Cout / 64), 256, 0, st>>>(x, B, H, W, w, Cin, bias, relu, y,
+                                                                                mask);
     else
-        k_conv<4, 1, 2, 2, UP><<<dim3(grid1(npix, 128), Cout / 32), 256, 0, st>>>(x, B, H, W, w, Cin, bias, relu, y);
+        k_conv<4, 1, 2, 2, UP><<<dim3(grid1(npix, 128), Cout / 32), 256, 0, st>>>(x, B, H, W, w, Cin, bias, relu, y,
+                                                                                 mask);
 }
 
+// mask (or a NULL view): the output is zeroed where mask <= 0, the backward
+// of a ReLU whose output is mask, fused into the producer of the gradient
 void launch_conv(View x, int B, int H, int W, const __bf16 *w, int Cin, const float *bias, int relu, int Cout, bool up,
-                 View y, hipStream_t st) {
-    if (up) launch_conv_tiles<true>(x, B, H, W, w, Cin, bias, relu, Cout, y, st);
-    else launch_conv_tiles<false>(x, B, H, W, w, Cin, bias, relu, Cout, y, st);
+                 View y, View mask, hipStream_t st) {
+    if (up) launch_conv_tiles<true>(x, B, H, W, w, Cin, bias, relu, Cout, y, mask, st);
+    else launch_conv_tiles<false>(x, B, H, W, w, Cin, bias, relu, Cout, y, mask, st);
 }
 
 }  // namespace
@@ -956,6 +1119,62 @@ int splits_for(long long npix) {
     return (int)std::max(1LL, std::min(256LL, s));
 }
 
+// Splits of the tiled weight gradient: about 1024 blocks in all, each over
+// a range of whole 8 x 32 tiles, with at most WG_PART_MAX floats of partials.
+constexpr long long WG_PART_MAX = 32LL << 20;
+
+long long wgrad_tiles(int B, int H, int W) {
+    return (long long)B * ((H + WT_TY - 1) / WT_TY) * ((W + WT_TX - 1) / WT_TX);
+}
+
+// at most this many splits for B images (and so for any smaller batch)
+long long wgrad_tile_split_bound(int B, int H, int W, int Cin, int Cout) {
+    const int tco = Cout % 64 == 0 ? 64 : 32, tci = Cin % 64 == 0 ? 64 : 32;
+    const long long gxy = (long long)(Cout / tco) * (Cin / tci);
+    long long S = (1024 + gxy - 1) / gxy;
+    S = std::min(S, std::max(1LL, WG_PART_MAX / ((long long)Cout * 9 * Cin)));
+    return std::max(1LL, std::min(S, wgrad_tiles(B, H, W)));
+}
+
+int wgrad_tile_splits(int B, int H, int W, int Cin, int Cout, long long *tiles_per_split) {
+    const long long ntiles = wgrad_tiles(B, H, W);
+    const long long tps = (ntiles + wgrad_tile_split_bound(B, H, W, Cin, Cout) - 1) /
+                          wgrad_tile_split_bound(B, H, W, Cin, Cout);
+    *tiles_per_split = tps;
+    return (int)((ntiles + tps - 1) / tps);
+}
+
+// dW (cout x 9 x cin) and db (cout) of a 3x3 layer, through cap floats of
+// partials at part.  hipErrorInvalidValue when the partials do not fit.
+long long wgrad_part_floats(long long S, int Cin, int Cout) {
+    const int nwc = (Cin % 64 == 0 ? 64 : 32) / 16;
+    return S * Cout * 9 * Cin + S * nwc * Cout;
+}
+
+hipError_t launch_wgrad_tile(View dz, View x, int B, int H, int W, int Cin, int Cout, bool up, float *part,
+                             long long cap, float *dw, float *db, hipStream_t st) {
+    long long tps = 0;
+    const int S = wgrad_tile_splits(B, H, W, Cin, Cout, &tps);
+    if (wgrad_part_floats(S, Cin, Cout) > cap) return hipErrorInvalidValue;
+    const int tco = Cout % 64 == 0 ? 64 : 32, tci = Cin % 64 == 0 ? 64 : 32;
+    const dim3 grid(Cout / tco, Cin / tci, S);
+    const int tp = (int)tps;
+    float *bpart = part + (size_t)S * Cout * 9 * Cin;
+#define WG(A, Bq)                                                                                        \
+    if (up) k_wgrad_tile<A, Bq, true><<<grid, (A / 32) * (Bq / 16) * 64, 0, st>>>(dz, x, B, H, W, Cin, Cout, tp, part, bpart); \
+    else k_wgrad_tile<A, Bq, false><<<grid, (A / 32) * (Bq / 16) * 64, 0, st>>>(dz, x, B, H, W, Cin, Cout, tp, part, bpart)
+    if (tco == 64 && tci == 64) WG(64, 64);
+    else if (tco == 64) WG(64, 32);
+    else if (tci == 64) WG(32, 64);
+    else WG(32, 32);
+#undef WG
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    reduce_splits(part, S, (long long)Cout * 9 * Cin, dw, st);
+    reduce_splits(bpart, S * (tci / 16), Cout, db, st);
+    return hipGetLastError();
+}
+
 template <typename T>
 hipError_t dalloc(dsn_ctx *c, T **p, size_t n) {
     void *q = nullptr;
@@ -972,14 +1191,15 @@ void free_all(dsn_ctx *c) {
     c->allocs.clear();
 }
 
-int conv(dsn_ctx *c, View x, int B, int l, int layer_i, bool up, bool transposed, int relu, View y) {
+int conv(dsn_ctx *c, View x, int B, int l, int layer_i, bool up, bool transposed, int relu, View y,
+         View mask = View{}) {
     // forward: weights pb[layer] [cout][9][cin]; input gradient: pt[layer] [cin][9][cout]
     const dsn_layer &ly = c->L[layer_i];
     const int Cin = transposed ? ly.cout : ly.cin, Cout = transposed ? ly.cin : ly.cout;
     const __bf16 *w = (transposed ? c->pt : c->pb) + ly.w_off;
     const float *bias = transposed ? nullptr : c->p + ly.b_off;
     if (Cin % 32 || Cout % 32 || x.C != Cin || y.C != Cout) return fail(DSN_EINVAL, "conv shape mismatch");
-    launch_conv(x, B, c->h[l], c->w[l], w, Cin, bias, relu, Cout, up, y, c->stream);
+    launch_conv(x, B, c->h[l], c->w[l], w, Cin, bias, relu, Cout, up, y, mask, c->stream);
     HIPCHK(hipGetLastError());
     return DSN_OK;
 }
@@ -987,40 +1207,18 @@ int conv(dsn_ctx *c, View x, int B, int l, int layer_i, bool up, bool transposed
 // weight and bias gradients of a 3x3 layer (input view x, output gradient dz)
 int wgrad(dsn_ctx *c, View dz, View x, int B, int l, int layer_i, bool up) {
     const dsn_layer &ly = c->L[layer_i];
-    const int H = c->h[l], W = c->w[l];
-    const long long npix = (long long)B * H * W;
-    const int S = splits_for(npix);
-    const long long pps = (npix + S - 1) / S;
-    const int Cin = ly.cin, Cout = ly.cout;
-    if ((long long)S * Cout * 9 * Cin > c->part_cap || (long long)S * Cout > c->part_cap)
-        return fail(DSN_EINVAL, "weight-gradient scratch too small");
-    if (Cout % 8 || Cout > 2048) return fail(DSN_EINVAL, "bias gradient needs C %% 8 == 0 and C <= 2048");
-    const int tco = Cout % 64 == 0 ? 64 : 32, tci = Cin % 64 == 0 ? 64 : 32;
-    dim3 grid(Cout / tco, Cin / tci, 9 * S);
-#define WG(A, Bq)                                                                                        \
-    if (up) k_wgrad<A, Bq, true><<<grid, 256, 0, c->stream>>>(dz, x, B, H, W, Cin, Cout, pps, c->part); \
-    else k_wgrad<A, Bq, false><<<grid, 256, 0, c->stream>>>(dz, x, B, H, W, Cin, Cout, pps, c->part)
-    if (tco == 64 && tci == 64) WG(64, 64);
-    else if (tco == 64) WG(64, 32);
-    else if (tci == 64) WG(32, 64);
-    else WG(32, 32);
-#undef WG
-    HIPCHK(hipGetLastError());
-    const long long nw = (long long)Cout * 9 * Cin;
-    reduce_splits(c->part, S, nw, c->grad + ly.w_off, c->stream);
-    HIPCHK(hipGetLastError());
-    k_bias_grad<<<S, 256, 0, c->stream>>>(dz, npix, pps, c->part);
-    HIPCHK(hipGetLastError());
-    reduce_splits(c->part, S, Cout, c->grad + ly.b_off, c->stream);
-    HIPCHK(hipGetLastError());
+    const hipError_t e = launch_wgrad_tile(dz, x, B, c->h[l], c->w[l], ly.cin, ly.cout, up, c->part, c->part_cap,
+                                           c->grad + ly.w_off, c->grad + ly.b_off, c->stream);
+    if (e == hipErrorInvalidValue) return fail(DSN_EINVAL, "weight-gradient scratch too small");
+    HIPCHK(e);
     return DSN_OK;
 }
 
-// First layer's weight gradient: one input channel means little work per
-// pixel, so ranges of 512 pixels (up to 4096 blocks) while the partials
-// (S x C x 10 floats) fit cap; ranges of splits_for() otherwise.
+// First layer's weight gradient: ranges of 4096 pixels (up to 2048 blocks)
+// while the partials (S x C x 10 floats) fit cap; ranges of splits_for()
+// otherwise.
 int first_layer_splits(long long npix, int C, long long cap) {
-    int S = (int)std::max(1LL, std::min(4096LL, npix / 512));
+    int S = (int)std::max(1LL, std::min(2048LL, npix / 4096));
     if ((long long)S * C * 10 > cap) S = splits_for(npix);
     return S;
 }
@@ -1041,22 +1239,18 @@ hipError_t launch_wgrad_first(View dz, const float *x, int B, int H, int W, int 
 // Head backward over npix pixels of the features x: the input gradient dx,
 // the losses (d_loss[2], averaged over B) and the heads' weight and bias
 // gradients (gw [heads][C + 1]) from per-block partials in lpart / hpart.
+// relu_mask: dx is also zeroed where x <= 0 (the backward of the ReLU that
+// produced x)
 hipError_t launch_head_bwd(View x, long long npix, int B, const __bf16 *w, const __bf16 *wm, const float *out,
-                           const float *out_m, const float *tgt, const float *tgt_m, View dx, double *lpart,
-                           float *hpart, double *d_loss, float *gw, hipStream_t st) {
+                           const float *out_m, const float *tgt, const float *tgt_m, View dx, int relu_mask,
+                           double *lpart, float *hpart, double *d_loss, float *gw, hipStream_t st) {
     const unsigned nblk = grid1(npix);
-    k_head_bwd<<<nblk, 256, 0, st>>>(x, npix, B, w, wm, out, out_m, tgt, tgt_m, dx, lpart, hpart);
+    k_head_bwd<<<nblk, 256, 0, st>>>(x, npix, B, w, wm, out, out_m, tgt, tgt_m, dx, relu_mask, lpart, hpart);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     k_loss_finish<<<1, 256, 0, st>>>(lpart, (int)nblk, B, d_loss);
     reduce_splits(hpart, (int)nblk, (out_m ? 2 : 1) * (x.C + 1), gw, st);
     return hipGetLastError();
-}
-
-int relu_bwd(dsn_ctx *c, View d, View y, long long npix) {
-    k_relu_bwd<<<grid1(npix * (d.C / 8)), 256, 0, c->stream>>>(d, y, npix);
-    HIPCHK(hipGetLastError());
-    return DSN_OK;
 }
 
 int check_ctx(const dsn_ctx *c) { return c ? DSN_OK : fail(DSN_EINVAL, "context is NULL"); }
@@ -1078,6 +1272,7 @@ extern "C" int dsn_create(dsn_ctx **out, int H, int W, int base, int maxB, int m
         return fail(DSN_EINVAL, "H and W must be multiples of 8 in [8, 2048]");
     if (base != 32 && base != 64) return fail(DSN_EINVAL, "base must be 32 or 64");
     if (maxB < 1) return fail(DSN_EINVAL, "max_batch must be >= 1");
+    if ((long long)maxB * H * W >= (1LL << 31)) return fail(DSN_EINVAL, "max_batch H W must be below 2^31");
     if (modulation != 0 && modulation != 1) return fail(DSN_EINVAL, "modulation must be 0 or 1");
     dsn_ctx *c = new (std::nothrow) dsn_ctx();
     if (!c) return fail(DSN_ENOMEM, "out of host memory");
@@ -1122,6 +1317,10 @@ extern "C" int dsn_create(dsn_ctx **out, int H, int W, int base, int maxB, int m
         else l = DSN_LEVELS - 2 - (int)(i - 2 * DSN_LEVELS) / 3;
         const long long S = splits_for(c->np[l]);
         cap = std::max(cap, S * c->L[i].cout * 9 * std::max(c->L[i].cin, 1) + S * c->L[i].cout);
+        if (c->L[i].cin % 32 == 0 && c->L[i].cout % 32 == 0) {
+            const long long St = wgrad_tile_split_bound(maxB, c->h[l], c->w[l], c->L[i].cin, c->L[i].cout);
+            cap = std::max(cap, wgrad_part_floats(St, c->L[i].cin, c->L[i].cout));
+        }
     }
     c->part_cap = cap;
     hipError_t e = hipSuccess;
@@ -1204,7 +1403,7 @@ extern "C" int dsn_forward(dsn_ctx *c, const float *d_x, int B, float *d_out, fl
     {
         const dsn_layer &ly = c->L[enc_a(0)];
         const long long npix = (long long)B * c->h[0] * c->w[0];
-        k_conv_first<<<grid1(npix * (c->C[0] / 8)), 256, 0, c->stream>>>(
+        k_conv_first<<<grid1(npix), 256, (size_t)c->C[0] * 10 * sizeof(float), c->stream>>>(
             d_x, B, c->h[0], c->w[0], c->pb + ly.w_off, c->p + ly.b_off, view(c->act_a[0], c->C[0], c->C[0]));
         HIPCHK(hipGetLastError());
     }
@@ -1273,8 +1472,10 @@ extern "C" int dsn_backward(dsn_ctx *c, const float *d_target, const float *d_ta
     const dsn_layer &hm = c->L[c->modulation ? head_m_i() : head_i()];
     // hpart [nblk][heads][C0 + 1] -> each head's weights then bias; the two
     // heads are adjacent in the flat vector
+    // every ReLU's backward is fused into the kernel that produces the
+    // gradient of its output (a mask by the stored activation)
     HIPCHK(launch_head_bwd(view(c->dec_b[0], C0, C0), np0, B, c->pb + hd.w_off, c->pb + hm.w_off, c->out,
-                           with_m ? c->out_m : nullptr, d_target, d_target_m, view(c->gA[0], C0, C0), c->lpart,
+                           with_m ? c->out_m : nullptr, d_target, d_target_m, view(c->gA[0], C0, C0), 1, c->lpart,
                            c->hpart, d_loss, c->grad + hd.w_off, c->stream));
     if (c->modulation && !with_m) {
         k_fill_f32<<<1, 256, 0, c->stream>>>(c->grad + hm.w_off, C0 + 1, 0.f);
@@ -1283,24 +1484,23 @@ extern "C" int dsn_backward(dsn_ctx *c, const float *d_target, const float *d_ta
     // decoder, bottom-up in the backward order
     for (int l = 0; l <= NL - 2; ++l) {
         const int C = c->C[l], C1 = c->C[l + 1];
-        const long long np = (long long)B * c->h[l] * c->w[l];
-        View gy = view(c->gA[l], C, C);                        // d(dec_b output)
-        if ((r = relu_bwd(c, gy, view(c->dec_b[l], C, C), np))) return r;
+        View gy = view(c->gA[l], C, C);                        // d(dec_b pre-activation)
         if ((r = wgrad(c, gy, view(c->dec_a[l], C, C), B, l, dec_b_i(l), false))) return r;
         View ga = view(c->gB[l], C, C);
-        if ((r = conv(c, gy, B, l, dec_b_i(l), false, true, 0, ga))) return r;
-        if ((r = relu_bwd(c, ga, view(c->dec_a[l], C, C), np))) return r;
+        if ((r = conv(c, gy, B, l, dec_b_i(l), false, true, 0, ga, view(c->dec_a[l], C, C)))) return r;
         if ((r = wgrad(c, ga, view(c->cat[l], 2 * C, 2 * C), B, l, dec_a_i(l), false))) return r;
+        // both halves of the concatenation are ReLU outputs (up-convolution,
+        // skip): the mask covers all 2C channels
         View gc = view(c->gcat[l], 2 * C, 2 * C);
-        if ((r = conv(c, ga, B, l, dec_a_i(l), false, true, 0, gc))) return r;
-        View gu = view(c->gcat[l], C, 2 * C);                  // d(up-convolution output)
-        if ((r = relu_bwd(c, gu, view(c->cat[l], C, 2 * C), np))) return r;
+        if ((r = conv(c, ga, B, l, dec_a_i(l), false, true, 0, gc, view(c->cat[l], 2 * C, 2 * C)))) return r;
+        View gu = view(c->gcat[l], C, 2 * C);                  // d(up-convolution pre-activation)
         View below = l == NL - 2 ? view(c->bott, C1, C1) : view(c->dec_b[l + 1], C1, C1);
         if ((r = wgrad(c, gu, below, B, l, dec_up(l), true))) return r;
         View gfull = view(c->gA[l], C1, C1);                   // gradient of the upsampled input
         if ((r = conv(c, gu, B, l, dec_up(l), false, true, 0, gfull))) return r;
         const long long n = (long long)B * c->h[l + 1] * c->w[l + 1] * (C1 / 8);
-        k_upsample_bwd<<<grid1(n), 256, 0, c->stream>>>(gfull, B, c->h[l], c->w[l], view(c->gA[l + 1], C1, C1));
+        k_upsample_bwd<<<grid1(n), 256, 0, c->stream>>>(gfull, B, c->h[l], c->w[l], view(c->gA[l + 1], C1, C1),
+                                                        below);
         HIPCHK(hipGetLastError());
     }
     // encoder, top-down
@@ -1315,15 +1515,15 @@ extern "C" int dsn_backward(dsn_ctx *c, const float *d_target, const float *d_ta
             yb = view(c->cat[l] + C, C, 2 * C);
             gyb = view(c->gcat[l] + C, C, 2 * C);
             // add the pooled path's gradient (held in gA[l + 1]) to the skip's
+            // (already masked) and mask the sum by yb
             const long long n = (long long)B * c->h[l + 1] * c->w[l + 1] * (C / 8);
-            k_maxpool_bwd<<<grid1(n), 256, 0, c->stream>>>(yb, B, c->h[l], c->w[l], view(c->gA[l + 1], C, C), gyb);
+            k_maxpool_bwd<true><<<grid1(n), 256, 0, c->stream>>>(yb, B, c->h[l], c->w[l], view(c->gA[l + 1], C, C),
+                                                               gyb);
             HIPCHK(hipGetLastError());
         }
-        if ((r = relu_bwd(c, gyb, yb, np))) return r;
         if ((r = wgrad(c, gyb, view(c->act_a[l], C, C), B, l, enc_b(l), false))) return r;
         View ga = view(c->gB[l], C, C);
-        if ((r = conv(c, gyb, B, l, enc_b(l), false, true, 0, ga))) return r;
-        if ((r = relu_bwd(c, ga, view(c->act_a[l], C, C), np))) return r;
+        if ((r = conv(c, gyb, B, l, enc_b(l), false, true, 0, ga, view(c->act_a[l], C, C)))) return r;
         if (l > 0) {
             const int Cp = c->C[l - 1];
             if ((r = wgrad(c, ga, view(c->pool[l - 1], Cp, Cp), B, l, enc_a(l), false))) return r;
@@ -1392,8 +1592,8 @@ extern "C" int dsn_predict(dsn_ctx *c, const unsigned char *d_target, int B, flo
 namespace {
 
 int op_conv(View x, int N, int H, int W, int Cin, bool up, const __bf16 *w, const float *b, int Cout, int relu,
-            View y, hipStream_t st) {
-    launch_conv(x, N, H, W, w, Cin, b, relu, Cout, up, y, st);
+            View y, hipStream_t st, View mask = View{}) {
+    launch_conv(x, N, H, W, w, Cin, b, relu, Cout, up, y, mask, st);
     HIPCHK(hipGetLastError());
     return DSN_OK;
 }
@@ -1420,9 +1620,10 @@ extern "C" int dsn_op_conv3x3(const void *d_x, int N, int H, int W, int Cin, int
 }
 
 extern "C" int dsn_op_conv3x3_dgrad(const void *d_dy, int N, int H, int W, int Cout, const void *d_w, int Cin,
-                                    void *d_dx, void *stream) {
+                                    const void *d_mask, void *d_dx, void *stream) {
     int r;
     if ((r = op_check(d_dy, d_w, N, H, W, Cin, Cout, false)) || (r = check_ptr(d_dx, "d_dx"))) return r;
+    if (d_mask && (r = check_ptr(d_mask, "d_mask"))) return r;
     hipStream_t st = static_cast<hipStream_t>(stream);
     __bf16 *wt = nullptr;
     const long long n = (long long)Cout * 9 * Cin;
@@ -1430,7 +1631,7 @@ extern "C" int dsn_op_conv3x3_dgrad(const void *d_dy, int N, int H, int W, int C
     k_flip_transpose<<<grid1(n), 256, 0, st>>>((const __bf16 *)d_w, Cout, Cin, wt);
     hipError_t e = hipGetLastError();
     r = e == hipSuccess ? op_conv(View{(__bf16 *)d_dy, Cout, Cout}, N, H, W, Cout, false, wt, nullptr, Cin, 0,
-                                  View{(__bf16 *)d_dx, Cin, Cin}, st)
+                                  View{(__bf16 *)d_dx, Cin, Cin}, st, View{(__bf16 *)d_mask, Cin, Cin})
                         : fail(DSN_EDEVICE, "k_flip_transpose: %s", hipGetErrorString(e));
     (void)hipStreamSynchronize(st);
     (void)hipFree(wt);
@@ -1444,30 +1645,12 @@ extern "C" int dsn_op_conv3x3_wgrad(const void *d_dz, const void *d_x, int N, in
         (r = check_ptr(d_db, "d_db")))
         return r;
     hipStream_t st = static_cast<hipStream_t>(stream);
-    const long long npix = (long long)N * H * W;
-    const int S = splits_for(npix);
-    const long long pps = (npix + S - 1) / S;
+    long long tps = 0;
+    const long long cap = wgrad_part_floats(wgrad_tile_splits(N, H, W, Cin, Cout, &tps), Cin, Cout);
     float *part = nullptr;
-    HIPCHK(hipMalloc(&part, ((size_t)S * Cout * 9 * Cin + (size_t)S * Cout) * sizeof(float)));
+    HIPCHK(hipMalloc(&part, (size_t)cap * sizeof(float)));
     View dz{(__bf16 *)d_dz, Cout, Cout}, x{(__bf16 *)d_x, Cin, Cin};
-    const int tco = Cout % 64 == 0 ? 64 : 32, tci = Cin % 64 == 0 ? 64 : 32;
-    dim3 grid(Cout / tco, Cin / tci, 9 * S);
-#define WG(A, Bq)                                                                            \
-    if (up) k_wgrad<A, Bq, true><<<grid, 256, 0, st>>>(dz, x, N, H, W, Cin, Cout, pps, part); \
-    else k_wgrad<A, Bq, false><<<grid, 256, 0, st>>>(dz, x, N, H, W, Cin, Cout, pps, part)
-    if (tco == 64 && tci == 64) WG(64, 64);
-    else if (tco == 64) WG(64, 32);
-    else if (tci == 64) WG(32, 64);
-    else WG(32, 32);
-#undef WG
-    hipError_t e = hipGetLastError();
-    const long long nw = (long long)Cout * 9 * Cin;
-    if (e == hipSuccess) {
-        reduce_splits(part, S, nw, d_dw, st);
-        k_bias_grad<<<S, 256, 0, st>>>(dz, npix, pps, part);
-        reduce_splits(part, S, Cout, d_db, st);
-        e = hipGetLastError();
-    }
+    hipError_t e = launch_wgrad_tile(dz, x, N, H, W, Cin, Cout, up != 0, part, cap, d_dw, d_db, st);
     (void)hipStreamSynchronize(st);
     (void)hipFree(part);
     if (e != hipSuccess) return fail(DSN_EDEVICE, "weight gradient: %s", hipGetErrorString(e));
@@ -1489,7 +1672,8 @@ extern "C" int dsn_op_conv_first(const float *d_x, int N, int H, int W, const vo
     if (N < 1 || H < 1 || W < 1) return fail(DSN_EINVAL, "bad N, H, W");
     if (Cout < 8 || Cout > 1024 || Cout % 8) return fail(DSN_EINVAL, "Cout must be a multiple of 8 in [8, 1024]");
     const long long npix = (long long)N * H * W;
-    k_conv_first<<<grid1(npix * (Cout / 8)), 256, 0, static_cast<hipStream_t>(stream)>>>(
+    if (npix >= (1LL << 31)) return fail(DSN_EINVAL, "N H W must be below 2^31");
+    k_conv_first<<<grid1(npix), 256, (size_t)Cout * 10 * sizeof(float), static_cast<hipStream_t>(stream)>>>(
         d_x, N, H, W, (const __bf16 *)d_w, d_b, View{(__bf16 *)d_y, Cout, Cout});
     HIPCHK(hipGetLastError());
     return DSN_OK;
@@ -1517,7 +1701,7 @@ extern "C" int dsn_op_wgrad_first(const void *d_dz, const float *d_x, int N, int
 
 extern "C" int dsn_op_head_bwd(const void *d_x, long long npix, int C, int B, const void *d_w, const void *d_wm,
                                const float *d_out, const float *d_out_m, const float *d_t, const float *d_t_m,
-                               void *d_dx, double *d_loss, float *d_gw, void *stream) {
+                               int relu_mask, void *d_dx, double *d_loss, float *d_gw, void *stream) {
     int r;
     if ((r = check_ptr(d_x, "d_x")) || (r = check_ptr(d_w, "d_w")) || (r = check_ptr(d_out, "d_out")) ||
         (r = check_ptr(d_t, "d_t")) || (r = check_ptr(d_dx, "d_dx")) || (r = check_ptr(d_loss, "d_loss")) ||
@@ -1538,7 +1722,8 @@ extern "C" int dsn_op_head_bwd(const void *d_x, long long npix, int C, int B, co
     hipError_t e = hipMalloc(&hpart, (size_t)nblk * 2 * (C + 1) * sizeof(float));
     if (e == hipSuccess)
         e = launch_head_bwd(View{(__bf16 *)d_x, C, C}, npix, B, (const __bf16 *)d_w, (const __bf16 *)d_wm, d_out,
-                            d_out_m, d_t, d_t_m, View{(__bf16 *)d_dx, C, C}, lpart, hpart, d_loss, d_gw, st);
+                            d_out_m, d_t, d_t_m, View{(__bf16 *)d_dx, C, C}, relu_mask != 0, lpart, hpart, d_loss,
+                            d_gw, st);
     (void)hipStreamSynchronize(st);
     (void)hipFree(lpart);
     if (hpart) (void)hipFree(hpart);
@@ -1546,27 +1731,32 @@ extern "C" int dsn_op_head_bwd(const void *d_x, long long npix, int C, int B, co
     return DSN_OK;
 }
 
-extern "C" int dsn_op_maxpool2_bwd(const void *d_x, int N, int H, int W, int C, const void *d_dy, void *d_dx,
-                                   void *stream) {
+extern "C" int dsn_op_maxpool2_bwd(const void *d_x, int N, int H, int W, int C, const void *d_dy, int relu_mask,
+                                   void *d_dx, void *stream) {
     int r;
     if ((r = check_ptr(d_x, "d_x")) || (r = check_ptr(d_dy, "d_dy")) || (r = check_ptr(d_dx, "d_dx"))) return r;
     if (N < 1 || H < 2 || W < 2 || H % 2 || W % 2) return fail(DSN_EINVAL, "need N >= 1 and even H, W >= 2");
     if (C < 8 || C % 8 || C > 2048) return fail(DSN_EINVAL, "C must be a multiple of 8 in [8, 2048]");
     const long long n = (long long)N * (H / 2) * (W / 2) * (C / 8);
-    k_maxpool_bwd<<<grid1(n), 256, 0, static_cast<hipStream_t>(stream)>>>(
-        View{(__bf16 *)d_x, C, C}, N, H, W, View{(__bf16 *)d_dy, C, C}, View{(__bf16 *)d_dx, C, C});
+    const View x{(__bf16 *)d_x, C, C}, dy{(__bf16 *)d_dy, C, C}, dx{(__bf16 *)d_dx, C, C};
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (relu_mask) k_maxpool_bwd<true><<<grid1(n), 256, 0, st>>>(x, N, H, W, dy, dx);
+    else k_maxpool_bwd<false><<<grid1(n), 256, 0, st>>>(x, N, H, W, dy, dx);
     HIPCHK(hipGetLastError());
     return DSN_OK;
 }
 
-extern "C" int dsn_op_upsample2_bwd(const void *d_dy, int N, int H, int W, int C, void *d_dx, void *stream) {
+extern "C" int dsn_op_upsample2_bwd(const void *d_dy, int N, int H, int W, int C, const void *d_mask, void *d_dx,
+                                    void *stream) {
     int r;
     if ((r = check_ptr(d_dy, "d_dy")) || (r = check_ptr(d_dx, "d_dx"))) return r;
+    if (d_mask && (r = check_ptr(d_mask, "d_mask"))) return r;
     if (N < 1 || H < 2 || W < 2 || H % 2 || W % 2) return fail(DSN_EINVAL, "need N >= 1 and even H, W >= 2");
     if (C < 8 || C % 8 || C > 2048) return fail(DSN_EINVAL, "C must be a multiple of 8 in [8, 2048]");
     const long long n = (long long)N * (H / 2) * (W / 2) * (C / 8);
     k_upsample_bwd<<<grid1(n), 256, 0, static_cast<hipStream_t>(stream)>>>(View{(__bf16 *)d_dy, C, C}, N, H, W,
-                                                                            View{(__bf16 *)d_dx, C, C});
+                                                                            View{(__bf16 *)d_dx, C, C},
+                                                                            View{(__bf16 *)d_mask, C, C});
     HIPCHK(hipGetLastError());
     return DSN_OK;
 }

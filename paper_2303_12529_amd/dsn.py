@@ -39,15 +39,16 @@ def _lib():
             "dsn_op_conv3x3": [_VP, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, _VP, _VP,
                                ctypes.c_int, ctypes.c_int, _VP, _VP],
             "dsn_op_conv3x3_dgrad": [_VP, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, _VP, ctypes.c_int,
-                                     _VP, _VP],
+                                     _VP, _VP, _VP],
             "dsn_op_conv3x3_wgrad": [_VP, _VP, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                      ctypes.c_int, _VP, _VP, _VP],
             "dsn_op_conv_first": [_VP, ctypes.c_int, ctypes.c_int, ctypes.c_int, _VP, _VP, ctypes.c_int, _VP, _VP],
             "dsn_op_wgrad_first": [_VP, _VP, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, _VP, _VP, _VP],
             "dsn_op_head_bwd": [_VP, ctypes.c_longlong, ctypes.c_int, ctypes.c_int, _VP, _VP, _VP, _VP, _VP, _VP,
-                                _VP, _VP, _VP, _VP],
-            "dsn_op_maxpool2_bwd": [_VP, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, _VP, _VP, _VP],
-            "dsn_op_upsample2_bwd": [_VP, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, _VP, _VP],
+                                ctypes.c_int, _VP, _VP, _VP, _VP],
+            "dsn_op_maxpool2_bwd": [_VP, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, _VP, ctypes.c_int,
+                                    _VP, _VP],
+            "dsn_op_upsample2_bwd": [_VP, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, _VP, _VP, _VP],
             "dsn_op_relu_bwd": [_VP, _VP, ctypes.c_longlong, ctypes.c_int, _VP],
         }
         for name, args in sig.items():
@@ -249,13 +250,16 @@ def conv3x3(x, w, b=None, relu=False, up=False):
     return y
 
 
-def conv3x3_dgrad(dy, w):
+def conv3x3_dgrad(dy, w, mask=None):
+    """Input gradient of a 3x3 convolution; with mask (bf16 [N, H, W, Cin],
+    a ReLU output) zeroed where mask <= 0."""
     import torch
     N, H, W, Cout = dy.shape
     Cin = w.shape[3]
     dx = torch.empty((N, H, W, Cin), dtype=torch.bfloat16, device=dy.device)
     _check(_lib().dsn_op_conv3x3_dgrad(_ptr(dy, torch.bfloat16, None, "dy"), N, H, W, Cout,
                                        _ptr(w, torch.bfloat16, (Cout, 3, 3, Cin), "w"), Cin,
+                                       None if mask is None else _ptr(mask, torch.bfloat16, (N, H, W, Cin), "mask"),
                                        _ptr(dx, torch.bfloat16, None, "dx"),
                                        _VP(torch.cuda.current_stream().cuda_stream)))
     return dx
@@ -306,10 +310,10 @@ def wgrad_first(dz, x):
     return dw, db
 
 
-def head_bwd(x, w, out, t, B, wm=None, out_m=None, t_m=None):
+def head_bwd(x, w, out, t, B, wm=None, out_m=None, t_m=None, relu_mask=False):
     """Head backward: x bf16 [npix, C] features, w (wm) bf16 [C], out / t
     (out_m / t_m) float32 [npix].  Returns (dx bf16 [npix, C], loss float64
-    [2], gw float32 [heads, C + 1])."""
+    [2], gw float32 [heads, C + 1]); relu_mask zeroes dx where x <= 0."""
     import torch
     npix, C = x.shape
     heads = 2 if wm is not None else 1
@@ -321,28 +325,33 @@ def head_bwd(x, w, out, t, B, wm=None, out_m=None, t_m=None):
         _ptr(x, torch.bfloat16, (npix, C), "x"), npix, C, int(B), _ptr(w, torch.bfloat16, (C,), "w"),
         None if wm is None else _ptr(wm, torch.bfloat16, (C,), "wm"), _ptr(out, f, (npix,), "out"),
         None if out_m is None else _ptr(out_m, f, (npix,), "out_m"), _ptr(t, f, (npix,), "t"),
-        None if t_m is None else _ptr(t_m, f, (npix,), "t_m"), _ptr(dx, torch.bfloat16, None, "dx"),
+        None if t_m is None else _ptr(t_m, f, (npix,), "t_m"), int(bool(relu_mask)),
+        _ptr(dx, torch.bfloat16, None, "dx"),
         _ptr(loss, torch.float64, (2,), "loss"), _ptr(gw, f, None, "gw"), _st()))
     return dx, loss, gw
 
 
-def maxpool2_bwd(x, dy, dx):
+def maxpool2_bwd(x, dy, dx, relu_mask=False):
     """dx (bf16 [N, H, W, C]) += dy (bf16 [N, H/2, W/2, C]) routed to the first
-    maximum of each 2x2 window of x; in place, returns dx."""
+    maximum of each 2x2 window of x; in place, returns dx.  relu_mask then
+    zeroes the windows' elements where x <= 0."""
     import torch
     N, H, W, C = x.shape
     _check(_lib().dsn_op_maxpool2_bwd(_ptr(x, torch.bfloat16, None, "x"), N, H, W, C,
-                                      _ptr(dy, torch.bfloat16, (N, H // 2, W // 2, C), "dy"),
+                                      _ptr(dy, torch.bfloat16, (N, H // 2, W // 2, C), "dy"), int(bool(relu_mask)),
                                       _ptr(dx, torch.bfloat16, (N, H, W, C), "dx"), _st()))
     return dx
 
 
-def upsample2_bwd(dy):
-    """bf16 [N, H/2, W/2, C]: the sum of each pixel's four children in dy."""
+def upsample2_bwd(dy, mask=None):
+    """bf16 [N, H/2, W/2, C]: the sum of each pixel's four children in dy;
+    with mask (bf16 [N, H/2, W/2, C], a ReLU output) zeroed where mask <= 0."""
     import torch
     N, H, W, C = dy.shape
     dx = torch.empty((N, H // 2, W // 2, C), dtype=torch.bfloat16, device=dy.device)
     _check(_lib().dsn_op_upsample2_bwd(_ptr(dy, torch.bfloat16, None, "dy"), N, H, W, C,
+                                       None if mask is None else _ptr(mask, torch.bfloat16, (N, H // 2, W // 2, C),
+                                                                      "mask"),
                                        _ptr(dx, torch.bfloat16, None, "dx"), _st()))
     return dx
 

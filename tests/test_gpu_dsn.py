@@ -87,14 +87,25 @@ def test_conv_forward(dsn, N, H, W, Cin, Cout, up, relu):
     assert np.all(err <= bound)
 
 
+@pytest.mark.parametrize("masked", [False, True])
 @pytest.mark.parametrize("N,H,W,Cin,Cout", [(2, 16, 16, 32, 32), (1, 8, 8, 64, 128), (1, 10, 6, 128, 64),
                                            (1, 256, 256, 64, 32), (1, 513, 300, 32, 64)])
-def test_conv_input_gradient(dsn, N, H, W, Cin, Cout):
+def test_conv_input_gradient(dsn, N, H, W, Cin, Cout, masked):
+    """With a mask (a ReLU output), the ReLU's backward fused into the
+    epilogue: zero where the mask is, otherwise the unmasked result."""
     rng = np.random.default_rng(7 + Cin)
     dy = _bf16(rng.normal(size=(N, H, W, Cout)))
     w = _bf16(rng.normal(scale=0.1, size=(Cout, 3, 3, Cin)))
-    dx = dsn.conv3x3_dgrad(dy.cuda(), w.cuda())
+    mask = _bf16(np.maximum(rng.normal(size=(N, H, W, Cin)), 0)) if masked else None
+    dx = dsn.conv3x3_dgrad(dy.cuda(), w.cuda(), None if mask is None else mask.cuda())
     dxr, _, _ = ref.conv3x3_backward(np.zeros((N, H, W, Cin)), _np(w), _np(dy))
+    if masked:
+        keep = _np(mask) > 0
+        dxr = np.where(keep, dxr, 0.0)
+        assert np.all(_np(dx)[~keep] == 0.0)
+        plain = dsn.conv3x3_dgrad(dy.cuda(), w.cuda())
+        want = torch.where(mask.cuda() > 0, plain, torch.zeros_like(plain))
+        assert torch.equal(dx.view(torch.int16), want.view(torch.int16))
     err = np.abs(_np(dx) - dxr)
     assert np.all(err <= 2.0 ** -8 * np.abs(dxr) + 1e-5 * np.abs(dxr).max())
 
@@ -104,7 +115,10 @@ def test_conv_input_gradient(dsn, N, H, W, Cin, Cout):
                                                (3, 10, 6, 32, 64, True), (64, 32, 32, 32, 32, False),
                                                # bias sums with channel groups that do not divide the
                                                # block (96) and more channels than threads (320)
-                                               (2, 12, 10, 32, 96, False), (1, 9, 11, 32, 320, False)])
+                                               (2, 12, 10, 32, 96, False), (1, 9, 11, 32, 320, False),
+                                               # several 8 x 32 tiles with ragged tails; splits of two tiles
+                                               (2, 19, 70, 64, 64, False), (1, 34, 66, 64, 96, True),
+                                               (4, 64, 96, 256, 256, False)])
 def test_conv_weight_gradient(dsn, N, H, W, Cin, Cout, up):
     _say("wgrad", N, H, W, Cin, Cout, up)
     rng = np.random.default_rng(11 + Cin + Cout + N)

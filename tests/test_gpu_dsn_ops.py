@@ -1,7 +1,9 @@
 """Single-layer parity of the DevelSet-Net kernels that the whole-network test
 only holds in a band (Sec. III-B): the first convolution and its weight
 gradient, the head backward with and without the modulation head (L_0,
-L_m and their gradients), max-pooling, upsampling and ReLU backward.
+L_m and their gradients), max-pooling, upsampling and ReLU backward, and the
+ReLU backward fused into the head, pooling and upsampling backward (the
+training step's form).
 
 Each call runs the same kernel, with the same work split, as the training
 step.  FP32 results are compared with the FP64 oracle (dsn.py) evaluated on
@@ -67,10 +69,12 @@ def test_conv_first(dsn, N, H, W, C):
     assert np.all(err <= 2.0 ** -8 * np.abs(yr) + 1e-6 * np.abs(yr).max()), err.max()
 
 
-# (B, H, W, C): pixel ranges of 576 crossing image boundaries; ranges of 519
-# pixels that start mid-row; rows narrower than a thread's pixel stride;
-# the training shape (512^2, batch 16: 4096 ranges of 1024 pixels)
-@pytest.mark.parametrize("N,H,W,C", [(3, 40, 24, 32), (2, 100, 70, 64), (1, 7, 5, 8), (16, 512, 512, 32)])
+# (B, H, W, C): one range over three images; ranges of 4667 pixels that start
+# mid-row; ranges of 6000 pixels that start mid-image and cross image
+# boundaries; rows narrower than a thread's pixel stride; the training shape
+# (512^2, batch 16: 1024 ranges of 4096 pixels)
+@pytest.mark.parametrize("N,H,W,C", [(3, 40, 24, 32), (2, 100, 70, 64), (5, 40, 60, 16), (1, 7, 5, 8),
+                                     (16, 512, 512, 32)])
 def test_wgrad_first(dsn, N, H, W, C):
     _say("wgrad_first", N, H, W, C)
     rng = np.random.default_rng(3 * N + W + C)
@@ -83,10 +87,11 @@ def test_wgrad_first(dsn, N, H, W, C):
     assert e_w <= 1e-5 and e_b <= 1e-5
 
 
+@pytest.mark.parametrize("relu_mask", [False, True])
 @pytest.mark.parametrize("mod", [False, True])
 @pytest.mark.parametrize("B,H,W,C", [(3, 40, 24, 32), (2, 64, 70, 64), (16, 256, 256, 32)])
-def test_head_backward(dsn, mod, B, H, W, C):
-    _say("head_bwd", mod, B, H, W, C)
+def test_head_backward(dsn, mod, relu_mask, B, H, W, C):
+    _say("head_bwd", mod, relu_mask, B, H, W, C)
     rng = np.random.default_rng(B + H + C + mod)
     npix = B * H * W
     x = _bf16(np.maximum(rng.standard_normal((npix, C), dtype=np.float32), 0))
@@ -99,7 +104,8 @@ def test_head_backward(dsn, mod, B, H, W, C):
         out_m = rng.normal(scale=0.05, size=npix).astype(np.float32)
         t_m = (rng.random(npix) < 0.5).astype(np.float32)
         kw = dict(wm=wm.cuda(), out_m=torch.as_tensor(out_m).cuda(), t_m=torch.as_tensor(t_m).cuda())
-    dx, loss, gw = dsn.head_bwd(x.cuda(), w.cuda(), torch.as_tensor(out).cuda(), torch.as_tensor(t).cuda(), B, **kw)
+    dx, loss, gw = dsn.head_bwd(x.cuda(), w.cuda(), torch.as_tensor(out).cuda(), torch.as_tensor(t).cuda(), B,
+                                relu_mask=relu_mask, **kw)
     # oracle: the head is a 1x1 convolution; its loss gradient and L_0 / L_m
     xr = _np(x)
     d0 = out.astype(np.float64) - t
@@ -124,34 +130,50 @@ def test_head_backward(dsn, mod, B, H, W, C):
         e = _rel(gwg[h], r)
         _say("  head", h, "grad err", e)
         assert e <= 1e-5
+    if relu_mask:
+        # the features are ReLU outputs: half of them exactly zero
+        keep = xr > 0
+        assert 0 < np.count_nonzero(keep) < keep.size
+        dxr = np.where(keep, dxr, 0.0)
+        assert np.all(_np(dx)[~keep] == 0.0)
     err = np.abs(_np(dx) - dxr)
     assert np.all(err <= 2.0 ** -8 * np.abs(dxr) + 1e-5 * np.abs(dxr).max())
 
 
+@pytest.mark.parametrize("relu_mask", [False, True])
 @pytest.mark.parametrize("N,H,W,C", [(2, 16, 24, 32), (3, 40, 24, 64), (1, 128, 130, 256)])
-def test_maxpool_backward_bit_exact(dsn, N, H, W, C):
+def test_maxpool_backward_bit_exact(dsn, N, H, W, C, relu_mask):
     rng = np.random.default_rng(N + C)
     # coarse values so that windows hold ties (the first maximum wins)
     x = _bf16(rng.integers(-3, 4, size=(N, H, W, C)).astype(np.float32) * 0.5)
     dy = _bf16(rng.standard_normal((N, H // 2, W // 2, C), dtype=np.float32))
     dx0 = _bf16(rng.standard_normal((N, H, W, C), dtype=np.float32))
     dx = dx0.cuda()
-    dsn.maxpool2_bwd(x.cuda(), dy.cuda(), dx)
+    dsn.maxpool2_bwd(x.cuda(), dy.cuda(), dx, relu_mask=relu_mask)
     routed = ref.maxpool2_backward(_np(x), _np(dy))
     want = _round_bf16(dx0.float().numpy() + routed.astype(np.float32))
+    if relu_mask:
+        want = torch.where(x.float() > 0, want, torch.zeros_like(want))
     assert np.array_equal(_bits(dx), _bits(want))
 
 
+@pytest.mark.parametrize("masked", [False, True])
 @pytest.mark.parametrize("N,H,W,C", [(2, 16, 24, 32), (3, 40, 24, 64), (1, 256, 130, 128)])
-def test_upsample_backward_bit_exact(dsn, N, H, W, C):
+def test_upsample_backward_bit_exact(dsn, N, H, W, C, masked):
     rng = np.random.default_rng(2 * N + C)
     dy = _bf16(rng.standard_normal((N, H, W, C), dtype=np.float32))
-    dx = dsn.upsample2_bwd(dy.cuda())
+    mask = _bf16(np.maximum(rng.standard_normal((N, H // 2, W // 2, C), dtype=np.float32), 0)) if masked else None
+    dx = dsn.upsample2_bwd(dy.cuda(), None if mask is None else mask.cuda())
     v = dy.float().numpy().reshape(N, H // 2, 2, W // 2, 2, C)
     s = np.zeros((N, H // 2, W // 2, C), dtype=np.float32)
     for k in range(4):                                  # the kernel's order: row-major children
         s = s + v[:, :, k // 2, :, k % 2, :]
-    assert np.array_equal(_bits(dx), _bits(_round_bf16(s)))
+    want = _round_bf16(s)
+    if masked:
+        want = torch.where(mask.float() > 0, want, torch.zeros_like(want))
+    assert np.array_equal(_bits(dx), _bits(want))
+    if masked:
+        return
     # and the sum is the oracle's (FP64) within one BF16 rounding
     r = ref.upsample2_backward(_np(dy))
     assert np.all(np.abs(_np(dx) - r) <= 2.0 ** -8 * np.abs(r))
