@@ -1031,6 +1031,120 @@ __global__ void k_phi0(const float *__restrict__ out, int B, int H, int W, float
 
 inline unsigned grid1(long long n, int bs = 256) { return (unsigned)((n + bs - 1) / bs); }
 
+// The same convolution for 32 input channels (one chunk), persistent: the
+// block's weights are staged once and kept in registers, and the block walks
+// tiles blockIdx.x, blockIdx.x + gridDim.x, ... with the next tile's input
+// loads in flight while the current tile is multiplied.
+template <bool UP, int TC>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_conv_lds32(
+    View x, int B, int H, int W, const __bf16 *__restrict__ w, const float *__restrict__ bias, int relu, View y,
+    View mask) {
+    constexpr int RW = TC == 64 ? 8 : 4;
+    __shared__ __attribute__((aligned(16))) __bf16 Xs[CL_NPX * CL_XS];
+    __shared__ __attribute__((aligned(16))) __bf16 Ws[TC * CL_WS];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int l16 = lane & 15, lq = lane >> 4;
+    const int strip = wave & 1;
+    const int cw = TC == 64 ? 32 * (wave >> 1) : 0, row0 = TC == 64 ? 0 : 4 * (wave >> 1);
+    const int ntx = (W + CL_TX - 1) / CL_TX, nty = (H + CL_TY - 1) / CL_TY;
+    const int ntiles = B * nty * ntx;
+    const int co0 = blockIdx.y * TC;
+    const int Hin = UP ? H / 2 : H, Win = UP ? W / 2 : W;
+    constexpr int XU = (CL_NPX * 4 + 255) / 256;
+    for (int e = threadIdx.x; e < TC * 36; e += 256) {
+        const int col = e / 36, rem = e % 36;
+        *reinterpret_cast<bf8 *>(&Ws[col * CL_WS + (rem / 4) * 32 + 8 * (rem % 4)]) =
+            *reinterpret_cast<const bf8 *>(w + ((size_t)(co0 + col) * 9 + rem / 4) * 32 + 8 * (rem % 4));
+    }
+    __syncthreads();
+    bf8 a[9][2];
+#pragma unroll
+    for (int t = 0; t < 9; ++t)
+#pragma unroll
+        for (int cb = 0; cb < 2; ++cb)
+            a[t][cb] = *reinterpret_cast<const bf8 *>(&Ws[(cw + 16 * cb + l16) * CL_WS + t * 32 + 8 * lq]);
+    bf8 xv[XU];
+    auto fetch = [&](int tile) {
+        const int tix = tile % ntx, rest = tile / ntx;
+        const int tiy = rest % nty, b = rest / nty;
+        const int x0 = tix * CL_TX, y0 = tiy * CL_TY;
+#pragma unroll
+        for (int u = 0; u < XU; ++u) {
+            const int e = threadIdx.x + 256 * u;
+            xv[u] = bf8_zero();
+            if (e < CL_NPX * 4) {
+                const int px = e >> 2, seg = e & 3;
+                const int gy = y0 + px / (CL_TX + 2) - 1, gx = x0 + px % (CL_TX + 2) - 1;
+                if (gy >= 0 && gy < H && gx >= 0 && gx < W) {
+                    const int sy = UP ? (gy >> 1) : gy, sx = UP ? (gx >> 1) : gx;
+                    xv[u] = *reinterpret_cast<const bf8 *>(x.p + (((size_t)b * Hin + sy) * Win + sx) * x.stride +
+                                                           8 * seg);
+                }
+            }
+        }
+    };
+    if ((int)blockIdx.x < ntiles) fetch(blockIdx.x);
+    const __bf16 *xcol = Xs + (16 * strip + l16) * CL_XS + 8 * lq;
+    for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        __syncthreads();                              // the previous tile's reads are done
+#pragma unroll
+        for (int u = 0; u < XU; ++u) {
+            const int e = threadIdx.x + 256 * u;
+            if (e < CL_NPX * 4) *reinterpret_cast<bf8 *>(&Xs[(e >> 2) * CL_XS + 8 * (e & 3)]) = xv[u];
+        }
+        __syncthreads();
+        if (tile + (int)gridDim.x < ntiles) fetch(tile + gridDim.x);
+        f4 acc[RW][2];
+#pragma unroll
+        for (int r = 0; r < RW; ++r) acc[r][0] = acc[r][1] = f4{0.f, 0.f, 0.f, 0.f};
+        bf8 bw[3][3];
+        auto load_row = [&](int hr, bf8(&o)[3]) {
+#pragma unroll
+            for (int dx = 0; dx < 3; ++dx)
+                o[dx] = *reinterpret_cast<const bf8 *>(xcol + ((row0 + hr) * (CL_TX + 2) + dx) * CL_XS);
+        };
+        load_row(0, bw[0]);
+        load_row(1, bw[1]);
+#pragma unroll
+        for (int r = 0; r < RW; ++r) {
+            load_row(r + 2, bw[(r + 2) % 3]);
+#pragma unroll
+            for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+                for (int dx = 0; dx < 3; ++dx)
+#pragma unroll
+                    for (int cb = 0; cb < 2; ++cb)
+                        acc[r][cb] = mfma_b(a[3 * dy + dx][cb], bw[(r + dy) % 3][dx], acc[r][cb]);
+        }
+        const int tix = tile % ntx, rest = tile / ntx;
+        const int tiy = rest % nty, b = rest / nty;
+#pragma unroll
+        for (int r = 0; r < RW; ++r) {
+            const int gy = tiy * CL_TY + row0 + r, gx = tix * CL_TX + 16 * strip + l16;
+            if (gy >= H || gx >= W) continue;
+            const long long pix = ((long long)b * H + gy) * W + gx;
+#pragma unroll
+            for (int cb = 0; cb < 2; ++cb) {
+                const int c = co0 + cw + 16 * cb + 4 * lq;
+                bf4 o;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    float v = acc[r][cb][i] + (bias ? bias[c + i] : 0.f);
+                    if (relu) v = fmaxf(v, 0.f);
+                    o[i] = (__bf16)v;
+                }
+                if (mask.p) {
+                    const bf4 m = *reinterpret_cast<const bf4 *>(mask.p + pix * mask.stride + c);
+#pragma unroll
+                    for (int i = 0; i < 4; ++i)
+                        if (!((float)m[i] > 0.f)) o[i] = (__bf16)0.f;
+                }
+                *reinterpret_cast<bf4 *>(y.p + pix * y.stride + c) = o;
+            }
+        }
+    }
+}
+
 // Kernel of a 3x3 convolution: the LDS-staged tiles from 8 x 32 pixels up,
 // register tiles of 32 x 32 per wave (operands straight from global memory)
 // for smaller images.
@@ -1039,6 +1153,15 @@ void launch_conv_tiles(View x, int B, int H, int W, const __bf16 *w, int Cin, co
                        View y, View mask, hipStream_t st) {
     if (H >= CL_TY && W >= CL_TX) {
         const long long tiles = (long long)B * ((H + CL_TY - 1) / CL_TY) * ((W + CL_TX - 1) / CL_TX);
+        if (Cin == 32) {
+            // two resident blocks per compute unit
+            const unsigned nb = (unsigned)std::min<long long>(tiles, 512);
+            if (Cout % 64 == 0)
+                k_conv_lds32<UP, 64><<<dim3(nb, Cout / 64), 256, 0, st>>>(x, B, H, W, w, bias, relu, y, mask);
+            else
+                k_conv_lds32<UP, 32><<<dim3(nb, Cout / 32), 256, 0, st>>>(x, B, H, W, w, bias, relu, y, mask);
+            return;
+        }
         if (Cout % 64 == 0)
             k_conv_lds<UP, 64><<<dim3((unsigned)tiles, Cout / 64), 256, 0, st>>>(x, B, H, W, w, Cin, bias, relu, y,
                                                                                 mask);

@@ -197,13 +197,14 @@ hipError_t launch_adjoint_gwindow(ilt_ctx *c, const float *G, size_t g_set_strid
 // block maxima of |d| into maxpart for the CFL step; returns that block count
 int launch_cg(ilt_ctx *c, int first, double *part, double *maxpart, hipError_t *err);
 int adjoint_b3_parts(const ilt_ctx *c, int nsets);
-// column ranges per 16-row band of the spectrum (each wave's share, Np / (8
-// ranges), stays a multiple of 16): every range writes a whole window partial
-// that is summed afterwards, so fewer ranges once the launch has enough blocks
-// (several images fill the device with one range)
+// column ranges per 16-row band of the spectrum: every range writes a whole
+// window partial that is summed afterwards, so fewer ranges once the launch
+// has enough blocks (several images fill the device with one range); each
+// wave's share, Np / (8 ranges), must stay a multiple of 16, so Np (a
+// multiple of 128) is split only where 128 x ranges divides it
 inline int spectrum_xsplit(const ilt_ctx *c, int nimg) {
     if (c->Np < 512) return c->Np / 128;
-    return nimg >= 2 ? 1 : 2;
+    return (nimg >= 2 || c->Np % 256 != 0) ? 1 : 2;
 }
 int adjoint_b3_max_parts(const ilt_ctx *c, int nsets);
 #define ILT_B3_MAX_XSPLIT 4

@@ -63,6 +63,10 @@ CONV_CASES = [
     (2, 129, 130, 32, 128, False, True),  # ragged last block
     (3, 8, 32, 96, 256, False, True),     # exactly one tile per image
     (1, 10, 34, 128, 64, True, False),    # one full and one partial tile per row
+    # 32 input channels, more tiles than resident blocks: each block walks
+    # several tiles (ragged last tile column)
+    (2, 512, 200, 32, 32, False, False),
+    (3, 264, 300, 32, 64, True, True),
 ]
 
 

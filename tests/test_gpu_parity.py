@@ -64,6 +64,7 @@ FWD_CASES = [
     (128, 27, 4, "rand"),
     (160, 15, 3, "binary"),
     (512, 35, 24, "optics"),
+    (600, 21, 6, "binary"),      # padded side 640: spectrum waves of 5 column steps
     (150, 35, 5, "rand"),       # N % 4 != 0: scalar edge paths
 ]
 
@@ -114,7 +115,8 @@ def test_litho_forward_two_sets_select(ilt):
 # 9-12, 13-16, 17-20, 21-24, 25-32, 33-35
 ADJ_CASES = [(64, 3, 2), (96, 7, 3), (64, 9, 4), (100, 9, 5), (128, 15, 4), (160, 19, 5), (256, 21, 9),
              (200, 27, 6), (200, 35, 6), (384, 35, 24),
-             (67, 9, 3), (150, 35, 5)]   # N % 4 != 0: scalar edge paths
+             (67, 9, 3), (150, 35, 5),   # N % 4 != 0: scalar edge paths
+             (600, 21, 6)]               # padded side 640
 
 
 @pytest.mark.parametrize("flags", [0, "xsplit2", 1, 2, "bf16x3"])
