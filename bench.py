@@ -267,12 +267,12 @@ DSN_WEIGHTS = os.path.join(HERE, "paper_2303_12529_amd", "weights", "dsn_c1_fp16
 DSN_MOD_WEIGHTS = os.path.join(HERE, "paper_2303_12529_amd", "weights", "dsn_c1_mod_fp16.npy")
 
 
-def develset_ttt(seeds):
+def develset_ttt(seeds, wide_seeds=None):
     """Time to the plain loop's L2 with the trained network's phi_0 (DevelSet,
     Sec. III-C) vs from TSDF(target): the level-set-branch network with the
-    loop in FP32, BF16x3, and BF16x3 with the G-window adjoint, and the
-    two-branch network (level set + modulation, whose m_theta weights every
-    step's curvature term) on the FP32 loop."""
+    loop in FP32 (on wide_seeds when given), BF16x3, and BF16x3 with the
+    G-window adjoint, and the two-branch network (level set + modulation,
+    whose m_theta weights every step's curvature term) on the FP32 loop."""
     import numpy as np
     from paper_2303_12529_amd import develset, dsn
     from paper_2303_12529_amd import ilt
@@ -291,8 +291,10 @@ def develset_ttt(seeds):
         net.set_params(flat)
         res = {"weights": os.path.relpath(path, HERE), "modulation": modulation}
         for name, prec, flags in forms:
-            ev = develset.evaluate(net, seeds, precision=prec, flags=flags)
-            r = {"median_ms_plain": ev["median_ms_plain"], "median_ms_develset": ev["median_ms_develset"],
+            sd = wide_seeds if (wide_seeds is not None and label == "weights" and name == "fp32") else seeds
+            ev = develset.evaluate(net, sd, precision=prec, flags=flags)
+            r = {"seeds": "%d-%d" % (min(sd), max(sd)),
+                 "median_ms_plain": ev["median_ms_plain"], "median_ms_develset": ev["median_ms_develset"],
                  "speedup": ev.get("speedup"), "dsn_used": ev["dsn_used"],
                  "median_epe_nm_at_hit": {"plain": ev["median_epe_nm_plain"], "develset": ev["median_epe_nm_develset"],
                                           "develset_m": ev.get("median_epe_nm_develset_m")},
@@ -466,6 +468,9 @@ def main():
                     help="side of the full-layout measurement in pixels (0: skip)")
     ap.add_argument("--ttt-seeds", type=int, default=10,
                     help="seeds 0..n-1 for the time-to-L2-target comparison (0: skip)")
+    ap.add_argument("--develset-seeds", type=int, default=100,
+                    help="seeds 0..n-1 for DevelSet (level-set network, FP32 loop) against plain (0: the "
+                         "time-to-target seeds)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the path runs on a single MI355X "
@@ -571,7 +576,8 @@ def main():
                     c.autotune()
         ttt = time_to_target(ctxs, args.workload, range(args.ttt_seeds))
         if args.workload == "c1":
-            ttt["develset"] = develset_ttt(range(args.ttt_seeds))
+            ttt["develset"] = develset_ttt(range(args.ttt_seeds),
+                                           range(args.develset_seeds) if args.develset_seeds > 0 else None)
             for form in ("bf16x3", "bf16x3_gwindow"):
                 if ttt["develset"] and ttt["median_ms"].get("fp32") and \
                         (ttt["develset"].get(form) or {}).get("median_ms_develset"):

@@ -370,7 +370,17 @@ __global__ __launch_bounds__(256) void k_levelset(const float *__restrict__ phi,
         scal += blockIdx.z * SC_COUNT;
         part += blockIdx.z * p_cs;
     }
-    const int bx = blockIdx.x * 32, by = blockIdx.y * 32;
+    // tiles in dispatch order go round the eight XCDs; give each XCD a
+    // contiguous range of tiles (whole tile rows) instead, so that the
+    // sectors of a tile's halo that its neighbours also read are fetched
+    // into that XCD's L2 once
+    int tile;
+    {
+        const int nblk = gridDim.x * gridDim.y, b = blockIdx.y * gridDim.x + blockIdx.x;
+        const int q = nblk >> 3, r = nblk & 7, xcd = b & 7, k = b >> 3;
+        tile = (xcd < r ? xcd * (q + 1) : r * (q + 1) + (xcd - r) * q) + k;
+    }
+    const int bx = (tile % gridDim.x) * 32, by = (tile / gridDim.x) * 32;
     const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
     // the time step, and the velocity (and modulation) of this thread's
     // pixels, requested before the tile so that all loads are in flight
@@ -385,25 +395,47 @@ __global__ __launch_bounds__(256) void k_levelset(const float *__restrict__ phi,
         vv[j] = ok ? vel[p] : 0.f;
         mv[j] = (ok && mod) ? mod[p] : 1.f;
     }
-    // the tile with its 1-pixel halo (clamped at the image edge): all of a
-    // thread's loads are issued before any is stored
-    constexpr int TE = 34 * 34, TU = (TE + 255) / 256;
-    float tv[TU];
+    // the tile with its 1-pixel halo (clamped at the image edge): the 32
+    // interior columns of each of the 34 rows as aligned 16-byte loads, the
+    // two halo columns as single words; all of a thread's loads are issued
+    // before any is stored
+    const bool vec = (N & 3) == 0;
+    float4 iv[2];
+    float hv = 0.f;
 #pragma unroll
-    for (int u = 0; u < TU; ++u) {
+    for (int u = 0; u < 2; ++u) {
         const int e = threadIdx.x + 256 * u;
-        if (e < TE) {
-            const int yy = e / 34, xx = e - (e / 34) * 34;
-            const int gy = min(max(by + yy - 1, 0), N - 1);
-            const int gx = min(max(bx + xx - 1, 0), N - 1);
-            tv[u] = phi[(size_t)gy * N + gx];
+        if (e < 34 * 8) {
+            const int row = e >> 3, q = e & 7;
+            const size_t rb = (size_t)min(max(by + row - 1, 0), N - 1) * N;
+            const int gx = bx + 4 * q;
+            if (vec && gx + 3 < N) {
+                iv[u] = *reinterpret_cast<const float4 *>(phi + rb + gx);
+            } else {
+                iv[u].x = phi[rb + min(gx, N - 1)];
+                iv[u].y = phi[rb + min(gx + 1, N - 1)];
+                iv[u].z = phi[rb + min(gx + 2, N - 1)];
+                iv[u].w = phi[rb + min(gx + 3, N - 1)];
+            }
         }
     }
-#pragma unroll
-    for (int u = 0; u < TU; ++u) {
-        const int e = threadIdx.x + 256 * u;
-        if (e < TE) t[e / 34][e - (e / 34) * 34] = tv[u];
+    if (threadIdx.x < 68) {
+        const int row = threadIdx.x >> 1, side = threadIdx.x & 1;
+        const size_t rb = (size_t)min(max(by + row - 1, 0), N - 1) * N;
+        hv = phi[rb + (side ? min(bx + 32, N - 1) : max(bx - 1, 0))];
     }
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+        const int e = threadIdx.x + 256 * u;
+        if (e < 34 * 8) {
+            const int row = e >> 3, q = e & 7;
+            t[row][1 + 4 * q] = iv[u].x;
+            t[row][2 + 4 * q] = iv[u].y;
+            t[row][3 + 4 * q] = iv[u].z;
+            t[row][4 + 4 * q] = iv[u].w;
+        }
+    }
+    if (threadIdx.x < 68) t[threadIdx.x >> 1][(threadIdx.x & 1) ? 33 : 0] = hv;
     __syncthreads();
     int flips = 0, bad = 0;
 #pragma unroll
@@ -443,7 +475,7 @@ __global__ __launch_bounds__(256) void k_levelset(const float *__restrict__ phi,
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        const size_t b = (size_t)blockIdx.y * gridDim.x + blockIdx.x;
+        const size_t b = (size_t)tile;
         part[2 * b] = (double)(wsum[0] + wsum[1] + wsum[2] + wsum[3]);
         part[2 * b + 1] = (double)(wbad[0] + wbad[1] + wbad[2] + wbad[3]);
     }
