@@ -243,8 +243,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     f4 acc[RW][2];
 #pragma unroll
     for (int r = 0; r < RW; ++r) acc[r][0] = acc[r][1] = f4{0.f, 0.f, 0.f, 0.f};
-    for (int ci0 = 0; ci0 < Cin; ci0 += 32) {
-        bf8 xv[XU], wv[WU];
+    // the input chunk's loads: the next chunk's are in flight while the
+    // current one is multiplied
+    bf8 xv[XU];
+    auto fetch_x = [&](int ci0) {
 #pragma unroll
         for (int u = 0; u < XU; ++u) {
             const int e = threadIdx.x + 256 * u;
@@ -259,6 +261,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
                 }
             }
         }
+    };
+    fetch_x(0);
+    for (int ci0 = 0; ci0 < Cin; ci0 += 32) {
+        bf8 wv[WU];
 #pragma unroll
         for (int u = 0; u < WU; ++u) {
             const int e = threadIdx.x + 256 * u;
@@ -283,6 +289,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
             }
         }
         __syncthreads();
+        if (ci0 + 32 < Cin) fetch_x(ci0 + 32);
         bf8 a[9][2];
 #pragma unroll
         for (int t = 0; t < 9; ++t)
