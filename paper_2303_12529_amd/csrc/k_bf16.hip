@@ -416,18 +416,28 @@ __global__ __launch_bounds__(256, 2) void k_adjoint_b3(const __bf16 *__restrict_
                     xh[yb][4 + i] = h;
                     xl[yb][4 + i] = l;
                 }
-            // (c) Z[y][n] += sum_x X[y][x] B3[x][n]
+            // (c) Z[y][n] += sum_x X[y][x] B3[x][n]: every column block's B3
+            // operands first, then the three split products pass by pass, so
+            // that 2 NB independent accumulators separate dependent steps
+            // (each accumulator still adds hi.hi, hi.lo, lo.hi in that order)
+            bf8 bh[NB], bl[NB];
 #pragma unroll
             for (int nb = 0; nb < NB; ++nb) {
-                const bf8 bh = __builtin_bit_cast(bf8, Bb[((part * NB + nb) * 2 + 0) * 64 + lane]);
-                const bf8 bl = __builtin_bit_cast(bf8, Bb[((part * NB + nb) * 2 + 1) * 64 + lane]);
-#pragma unroll
-                for (int yb = 0; yb < 2; ++yb) {
-                    accZ[yb][nb] = mfma_b(xh[yb], bh, accZ[yb][nb]);
-                    accZ[yb][nb] = mfma_b(xh[yb], bl, accZ[yb][nb]);
-                    accZ[yb][nb] = mfma_b(xl[yb], bh, accZ[yb][nb]);
-                }
+                bh[nb] = __builtin_bit_cast(bf8, Bb[((part * NB + nb) * 2 + 0) * 64 + lane]);
+                bl[nb] = __builtin_bit_cast(bf8, Bb[((part * NB + nb) * 2 + 1) * 64 + lane]);
             }
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+                for (int yb = 0; yb < 2; ++yb) accZ[yb][nb] = mfma_b(xh[yb], bh[nb], accZ[yb][nb]);
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+                for (int yb = 0; yb < 2; ++yb) accZ[yb][nb] = mfma_b(xh[yb], bl[nb], accZ[yb][nb]);
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+                for (int yb = 0; yb < 2; ++yb) accZ[yb][nb] = mfma_b(xl[yb], bh[nb], accZ[yb][nb]);
         }
         // the next chunk's copies have landed (this wave's), and every wave is
         // done with buffer bb before it is refilled
