@@ -270,16 +270,17 @@ DSN_MOD_WEIGHTS = os.path.join(HERE, "paper_2303_12529_amd", "weights", "dsn_c1_
 def develset_ttt(seeds, wide_seeds=None):
     """Time to the plain loop's L2 with the trained network's phi_0 (DevelSet,
     Sec. III-C) vs from TSDF(target): the level-set-branch network with the
-    loop in FP32 (on wide_seeds when given), BF16x3, and BF16x3 with the
-    G-window adjoint, and the two-branch network (level set + modulation,
-    whose m_theta weights every step's curvature term) on the FP32 loop."""
+    loop in FP32 (on wide_seeds when given), FP32 with the G-window adjoint,
+    BF16x3, and BF16x3 with the G-window adjoint, and the two-branch network
+    (level set + modulation, whose m_theta weights every step's curvature
+    term) on the FP32 loop."""
     import numpy as np
     from paper_2303_12529_amd import develset, dsn
     from paper_2303_12529_amd import ilt
     out = {}
     gw = ilt.ILT_FLAG_GWINDOW_ADJOINT
-    runs = [("weights", DSN_WEIGHTS, (("fp32", ilt.ILT_FP32, 0), ("bf16x3", ilt.ILT_BF16X3, 0),
-                                      ("bf16x3_gwindow", ilt.ILT_BF16X3, gw))),
+    runs = [("weights", DSN_WEIGHTS, (("fp32", ilt.ILT_FP32, 0), ("fp32_gwindow", ilt.ILT_FP32, gw),
+                                      ("bf16x3", ilt.ILT_BF16X3, 0), ("bf16x3_gwindow", ilt.ILT_BF16X3, gw))),
             ("modulation_net", DSN_MOD_WEIGHTS, (("fp32", ilt.ILT_FP32, 0),))]
     for label, path, forms in runs:
         if not os.path.exists(path):
@@ -568,6 +569,8 @@ def main():
                 "bf16x3": ctx if prec == ilt.ILT_BF16X3 and flags == 0 else ilt.Context(H, w, N,
                                                                                       precision=ilt.ILT_BF16X3)}
         if not args.no_gwindow:
+            ctxs["fp32_gwindow"] = ilt.Context(H, w, N, precision=ilt.ILT_FP32,
+                                               flags=ilt.ILT_FLAG_GWINDOW_ADJOINT)
             ctxs["bf16x3_gwindow"] = ilt.Context(H, w, N, precision=ilt.ILT_BF16X3,
                                                  flags=ilt.ILT_FLAG_GWINDOW_ADJOINT)
         if not args.no_autotune:
@@ -578,7 +581,7 @@ def main():
         if args.workload == "c1":
             ttt["develset"] = develset_ttt(range(args.ttt_seeds),
                                            range(args.develset_seeds) if args.develset_seeds > 0 else None)
-            for form in ("bf16x3", "bf16x3_gwindow"):
+            for form in ("fp32_gwindow", "bf16x3", "bf16x3_gwindow"):
                 if ttt["develset"] and ttt["median_ms"].get("fp32") and \
                         (ttt["develset"].get(form) or {}).get("median_ms_develset"):
                     ttt["develset_%s_speedup_vs_plain" % form] = round(
