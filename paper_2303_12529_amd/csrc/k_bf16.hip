@@ -321,29 +321,46 @@ __global__ __launch_bounds__(256, 2) void k_adjoint_b3(const __bf16 *__restrict_
     const float *Gsrc = G + (size_t)s * g_set_stride;
     // Y_j and B3 of chunk c_ -> buffer bb; pad units and rows past the chunk
     // copy a valid in-chunk unit (never read back)
+    // The copies' per-lane source offsets within a chunk do not depend on
+    // the chunk: they are formed once (wave w copies the 64-unit groups
+    // w, w + 4, ...).
+    constexpr int NYT = (NYI + 3) / 4, NGT = (NGI + 3) / 4;
+    int yoff[NYT], goff[NGT];
+#pragma unroll
+    for (int t = 0; t < NYT; ++t) {
+        const int U = 64 * (wave + 4 * t) + lane;
+        int row = U / RWU, col = U - row * RWU;
+        if (row > 31) row = 31;
+        if (col >= RWU - 1) col = 0;
+        yoff[t] = row * 2 * KP + col * 8;
+    }
+    auto g_unit = [&](int U, int x0_) {         // G element offset of unit U for chunk column x0_
+        const int row = U / GRU, col = U - row * GRU;
+        const int y = min(yt0 + row, N - 1);
+        return y * N + min(x0_ + 4 * (col < GRU - 1 ? col : 0), N - 4);
+    };
+#pragma unroll
+    for (int t = 0; t < NGT; ++t) goff[t] = g_unit(64 * (wave + 4 * t) + lane, 0);
     auto copy_yb = [&](int c_, int bb) {
-        const int x0_ = c_ * 32;
-        for (int i = wave; i < NYI; i += 4) {
-            const int U = 64 * i + lane;
-            int row = U / RWU, col = U - row * RWU;
-            if (row > 31) row = 31;
-            if (col >= RWU - 1) col = 0;
-            lds_dma16(Yj + (size_t)(x0_ + row) * 2 * KP + col * 8, &Yc[bb][64 * i]);
-        }
+        const __bf16 *src = Yj + (size_t)c_ * 32 * 2 * KP;
+#pragma unroll
+        for (int t = 0; t < NYT; ++t)
+            if (wave + 4 * t < NYI) lds_dma16(src + yoff[t], &Yc[bb][64 * (wave + 4 * t)]);
         for (int i = wave; i < NBI; i += 4)
             lds_dma16(tbf + ((size_t)c_ * NBI * 64 + 64 * i + lane) * 8, &Bc[bb][64 * i]);
     };
     // G rows yt0.., columns 32 c_.. (clamped into the image; values outside it
-    // are masked when read)
+    // are masked when read).  Only a chunk that reaches past the image needs
+    // the clamp of the column.
     auto copy_g = [&](int c_) {
         const int x0_ = c_ * 32;
-        for (int i = wave; i < NGI; i += 4) {
-            const int U = 64 * i + lane;
-            const int row = U / GRU, col = U - row * GRU;
-            const int y = min(yt0 + row, N - 1);
-            const int x = min(x0_ + 4 * (col < GRU - 1 ? col : 0), N - 4);
-            lds_dma16(Gsrc + (size_t)y * N + x, &GWs[64 * i]);
-        }
+        const bool inside = x0_ + 32 <= N;
+#pragma unroll
+        for (int t = 0; t < NGT; ++t)
+            if (wave + 4 * t < NGI) {
+                const int U = 64 * (wave + 4 * t) + lane;
+                lds_dma16(Gsrc + (inside ? goff[t] + x0_ : g_unit(U, x0_)), &GWs[64 * (wave + 4 * t)]);
+            }
     };
     if (c_lo < c_hi) {
         copy_yb(c_lo, 0);

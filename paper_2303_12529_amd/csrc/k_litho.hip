@@ -589,27 +589,39 @@ __global__ __launch_bounds__(256, 2) void k_adjoint_st(const float *__restrict__
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb) accZ[yb][nb] = f4{0.f, 0.f, 0.f, 0.f};
 
+    // The copies' per-lane source offsets do not depend on the chunk: they
+    // are formed once (wave w copies the 64-unit groups w, w + 4, ...).
+    constexpr int NBI = (BU / 64 + 3) / 4, NGI = (GU / 64 + 3) / 4;
+    int boff[NBI], grow[NGI], gcol[NGI];
+#pragma unroll
+    for (int t = 0; t < NBI; ++t) {
+        const int U = 64 * (wave + 4 * t) + lane;
+        const int part = U / (32 * (LDB / 4)), rem = U - part * (32 * (LDB / 4));
+        const int row = rem / (LDB / 4), c4 = rem - row * (LDB / 4);
+        boff[t] = (part * Np + row) * NZ + (c4 < NZ / 4 ? 4 * c4 : 0);
+    }
+#pragma unroll
+    for (int t = 0; t < NGI; ++t) {
+        const int U = 64 * (wave + 4 * t) + lane;
+        const int row = U / 9, c4 = U - (U / 9) * 9;
+        const bool data = U < 288 && c4 < 8;
+        grow[t] = min(y0 + (data ? row : 0), N - 1) * N;
+        gcol[t] = data ? 4 * c4 : 0;
+    }
     // B3 rows x0.. of both parts into tile bb (pad units copy a valid row start)
     auto copy_b = [&](int c, int bb) {
-        const int x0 = c * 32;
-        for (int i = wave; i < BU / 64; i += 4) {
-            const int U = 64 * i + lane;
-            const int part = U / (32 * (LDB / 4)), rem = U - part * (32 * (LDB / 4));
-            const int row = rem / (LDB / 4), c4 = rem - row * (LDB / 4);
-            const float *src = tb + ((size_t)part * Np + x0 + row) * NZ + (c4 < NZ / 4 ? 4 * c4 : 0);
-            ilt_dev::lds_dma16(src, &Bs[bb][256 * i]);
-        }
+        const float *src = tb + (size_t)c * 32 * NZ;
+#pragma unroll
+        for (int t = 0; t < NBI; ++t)
+            if (wave + 4 * t < BU / 64) ilt_dev::lds_dma16(src + boff[t], &Bs[bb][256 * (wave + 4 * t)]);
     };
     // G rows y0.., columns x0.. into tile bb, coordinates clamped into the image
     auto copy_g = [&](int c, int bb) {
         const int x0 = c * 32;
-        for (int i = wave; i < GU / 64; i += 4) {
-            const int U = 64 * i + lane;
-            const int row = U / 9, c4 = U - (U / 9) * 9;
-            const bool data = U < 288 && c4 < 8;
-            const int y = min(y0 + (data ? row : 0), N - 1), x = min(x0 + (data ? 4 * c4 : 0), N - 4);
-            ilt_dev::lds_dma16(Gsrc + (size_t)y * N + x, &Gs[bb][256 * i]);
-        }
+#pragma unroll
+        for (int t = 0; t < NGI; ++t)
+            if (wave + 4 * t < GU / 64)
+                ilt_dev::lds_dma16(Gsrc + grow[t] + min(x0 + gcol[t], N - 4), &Gs[bb][256 * (wave + 4 * t)]);
     };
     // N % 4 != 0: G staged through registers, 4 values per thread
     float gr[4];
