@@ -29,9 +29,15 @@ __device__ __forceinline__ f4 mfma_b(bf8 a, bf8 b, f4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
 }
 
-__device__ __forceinline__ void split(float x, __bf16 &hi, __bf16 &lo) {
-    hi = (__bf16)x;
-    lo = (__bf16)(x - (float)hi);
+// Two products a b split at once: the packed hi pair is rounded once, the
+// FP32 values of its halves are read back by shifts of the packed word, and
+// lo = bf16(a b - hi) takes the residual of the exact product (one FMA).
+typedef float f2v __attribute__((ext_vector_type(2)));
+typedef __bf16 bf2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ void split2(float a0, float b0, float a1, float b1, unsigned &hp, unsigned &lp) {
+    hp = __builtin_bit_cast(unsigned, __builtin_convertvector(f2v{a0 * b0, a1 * b1}, bf2));
+    const float h0 = __builtin_bit_cast(float, hp << 16), h1 = __builtin_bit_cast(float, hp & 0xFFFF0000u);
+    lp = __builtin_bit_cast(unsigned, __builtin_convertvector(f2v{fmaf(a0, b0, -h0), fmaf(a1, b1, -h1)}, bf2));
 }
 
 __device__ __forceinline__ bf8 bf8_zero() {
@@ -178,42 +184,55 @@ __global__ __launch_bounds__(256, 2) void k_image_b3(const __bf16 *__restrict__ 
     for (int j = 0; j < nj; ++j) {
         const int buf = j & 1;
         if (j + 1 < nj) B3_FETCH(j + 1);
-        // two halves of the 64 columns keep only half the field accumulators live
+        // two halves of the 64 columns keep only half the field accumulators
+        // live; the Y operands of step t + 1 are read from LDS before the
+        // products of step t issue (scheduling barriers keep that order)
+        auto read_a = [&](int t, bf8 (&a)[2]) {
+            const int xh = t / NS, st = t - (t / NS) * NS;
+            int p, r0;
+            kmap<KP>::group(st, lq, p, r0);
+            const int off = (p == 2 ? KP : 0) + r0;
 #pragma unroll
-        for (int xh = 0; xh < 2; ++xh) {
-            f4 er[2][2], ei[2][2];
+            for (int xl = 0; xl < 2; ++xl)
+                a[xl] = (p >= 3) ? bf8_zero() : *reinterpret_cast<const bf8 *>(&Ys[buf][16 * (2 * xh + xl) + l16][off]);
+        };
+        f4 er[2][2], ei[2][2];
+        bf8 an[2];
+        read_a(0, an);
+#pragma unroll
+        for (int t = 0; t < 2 * NS; ++t) {
+            const int xh = t / NS, st = t - (t / NS) * NS;
+            if (st == 0) {
+#pragma unroll
+                for (int xl = 0; xl < 2; ++xl)
+#pragma unroll
+                    for (int yb = 0; yb < 2; ++yb) {
+                        er[xl][yb] = f4{0.f, 0.f, 0.f, 0.f};
+                        ei[xl][yb] = f4{0.f, 0.f, 0.f, 0.f};
+                    }
+            }
+            const bf8 a[2] = {an[0], an[1]};
+            if (t + 1 < 2 * NS) read_a(t + 1, an);
+            __builtin_amdgcn_sched_barrier(0);
+            const int sl = kmap<KP>::slot(st);
 #pragma unroll
             for (int xl = 0; xl < 2; ++xl)
 #pragma unroll
                 for (int yb = 0; yb < 2; ++yb) {
-                    er[xl][yb] = f4{0.f, 0.f, 0.f, 0.f};
-                    ei[xl][yb] = f4{0.f, 0.f, 0.f, 0.f};
+                    er[xl][yb] = mfma_b(a[xl], b1[yb][sl], er[xl][yb]);
+                    ei[xl][yb] = mfma_b(a[xl], b2[yb][sl], ei[xl][yb]);
                 }
+            __builtin_amdgcn_sched_barrier(0);
+            if (st == NS - 1) {
 #pragma unroll
-            for (int st = 0; st < NS; ++st) {
-                int p, r0;
-                kmap<KP>::group(st, lq, p, r0);
-                const int sl = kmap<KP>::slot(st);
-                const int off = (p == 2 ? KP : 0) + r0;
+                for (int xl = 0; xl < 2; ++xl)
 #pragma unroll
-                for (int xl = 0; xl < 2; ++xl) {
-                    const int xb = 2 * xh + xl;
-                    bf8 a = (p >= 3) ? bf8_zero() : *reinterpret_cast<const bf8 *>(&Ys[buf][16 * xb + l16][off]);
+                    for (int yb = 0; yb < 2; ++yb)
 #pragma unroll
-                    for (int yb = 0; yb < 2; ++yb) {
-                        er[xl][yb] = mfma_b(a, b1[yb][sl], er[xl][yb]);
-                        ei[xl][yb] = mfma_b(a, b2[yb][sl], ei[xl][yb]);
-                    }
-                }
+                        for (int i = 0; i < 4; ++i)
+                            accI[2 * xh + xl][yb][i] = fmaf(er[xl][yb][i], er[xl][yb][i],
+                                                            fmaf(ei[xl][yb][i], ei[xl][yb][i], accI[2 * xh + xl][yb][i]));
             }
-#pragma unroll
-            for (int xl = 0; xl < 2; ++xl)
-#pragma unroll
-                for (int yb = 0; yb < 2; ++yb)
-#pragma unroll
-                    for (int i = 0; i < 4; ++i)
-                        accI[2 * xh + xl][yb][i] = fmaf(er[xl][yb][i], er[xl][yb][i],
-                                                        fmaf(ei[xl][yb][i], ei[xl][yb][i], accI[2 * xh + xl][yb][i]));
         }
         if (j + 1 < nj) B3_STASH(buf ^ 1);
         __syncthreads();
@@ -420,19 +439,19 @@ __global__ __launch_bounds__(256, 2) void k_adjoint_b3(const __bf16 *__restrict_
                 }
             }
             // (b) X = G . E, split
+            // (element 2 m + q of a row's 8 values: column block m / 2, register 2 (m % 2) + q)
             bf8 xh[2], xl[2];
 #pragma unroll
-            for (int yb = 0; yb < 2; ++yb)
+            for (int yb = 0; yb < 2; ++yb) {
+                unsigned hw[4], lw[4];
 #pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    __bf16 h, l;
-                    split(e[0][yb][i] * gv[0][yb][i], h, l);
-                    xh[yb][i] = h;
-                    xl[yb][i] = l;
-                    split(e[1][yb][i] * gv[1][yb][i], h, l);
-                    xh[yb][4 + i] = h;
-                    xl[yb][4 + i] = l;
+                for (int m = 0; m < 4; ++m) {
+                    const int xb = m >> 1, i = 2 * (m & 1);
+                    split2(e[xb][yb][i], gv[xb][yb][i], e[xb][yb][i + 1], gv[xb][yb][i + 1], hw[m], lw[m]);
                 }
+                xh[yb] = __builtin_bit_cast(bf8, u4{hw[0], hw[1], hw[2], hw[3]});
+                xl[yb] = __builtin_bit_cast(bf8, u4{lw[0], lw[1], lw[2], lw[3]});
+            }
             // (c) Z[y][n] += sum_x X[y][x] B3[x][n]: every column block's B3
             // operands first, then the three split products pass by pass, so
             // that 2 NB independent accumulators separate dependent steps
