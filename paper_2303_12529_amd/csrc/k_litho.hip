@@ -471,8 +471,8 @@ __global__ __launch_bounds__(256, 2) void k_image(const float *__restrict__ tl, 
                 for (int yb = 0; yb < 2; ++yb) {
                     const size_t blk = (((size_t)(s * nj + j) * NB16 + (yw / 16 + yb)) * NB16 + (x0 / 16 + xb));
                     float *dst = Est + blk * 512 + lane * 4;
-                    *reinterpret_cast<f4 *>(dst) = er[xb][yb];
-                    *reinterpret_cast<f4 *>(dst + 256) = ei[xb][yb];
+                    __builtin_nontemporal_store(er[xb][yb], reinterpret_cast<f4 *>(dst));
+                    __builtin_nontemporal_store(ei[xb][yb], reinterpret_cast<f4 *>(dst + 256));
                 }
         }
 #pragma unroll
