@@ -757,13 +757,14 @@ __global__ __launch_bounds__(128) void k_edt_rows_env(const uint32_t *__restrict
                                                       const int16_t *__restrict__ info, int N, float d_lower,
                                                       float d_upper, TP *__restrict__ phi_out,
                                                       int *__restrict__ sqdist, size_t scr_words) {
-    // per class: g of every column (halfwords, M + 2 per band) and the band
-    // chains, later the hull marks and then D in the same storage (words,
-    // M + 1 per band).  The pads put the 64 lanes' equal band offsets in
-    // different banks.
-    constexpr int S16 = 64 * (M + 2), S32 = 64 * (M + 1);
-    __shared__ uint16_t gsh[2 * S16];
+    // per class: g of every column, then (in place: a band's chain never
+    // gets ahead of the column it has read) the band chains, later the hull
+    // marks and then D, M + 1 words per band; the pad puts the 64 lanes'
+    // equal band offsets in different banks.  Plus the row's inside bits.
+    // About 17 KB, so that 8 blocks of 2 waves share a CU.
+    constexpr int S32 = 64 * (M + 1);
     __shared__ int chn[2][S32];
+    __shared__ uint32_t insb[2 * M];
     __shared__ int need[2];
     // grid.y: clips, each with its own scratch and output
     colbits += blockIdx.y * scr_words;
@@ -778,7 +779,6 @@ __global__ __launch_bounds__(128) void k_edt_rows_env(const uint32_t *__restrict
     const size_t plane = (size_t)W * N;
     // (positions are never negative)
     constexpr int LM = M >= 64 ? 6 : M >= 32 ? 5 : M >= 16 ? 4 : M >= 8 ? 3 : M >= 4 ? 2 : M >= 2 ? 1 : 0;
-    auto a16 = [](int p) { return p + 2 * (p >> LM); };
     auto a32 = [](int p) { return p + (p >> LM); };
     // 0. g_c of every column of this row from the column bits and the
     // nearest class rows above and below this row's word (all loads issued
@@ -804,6 +804,12 @@ __global__ __launch_bounds__(128) void k_edt_rows_env(const uint32_t *__restrict
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const int x = threadIdx.x + 128 * r;
+            // inside bits of columns 128 r + 64 cls .. + 63, one ballot per wave
+            const unsigned long long ib = __ballot(x < N && ((wv[r] >> b) & 1u));
+            if (lane == 0 && 128 * r + 64 * cls < 64 * M) {
+                insb[(128 * r + 64 * cls) / 32] = (uint32_t)ib;
+                insb[(128 * r + 64 * cls) / 32 + 1] = (uint32_t)(ib >> 32);
+            }
             if (x >= N) continue;
             const uint32_t w1 = wv[r], w0 = ~w1 & vm;
 #pragma unroll
@@ -816,7 +822,7 @@ __global__ __launch_bounds__(128) void k_edt_rows_env(const uint32_t *__restrict
                 else if (up >= 0) best = y - up;
                 if (bl) best = min(best, (__ffs(bl) - 1) - b);
                 else if (dn >= 0) best = min(best, dn - y);
-                gsh[c * S16 + a16(x)] = best == 0x7FFFFFFF ? (uint16_t)GNONE : (uint16_t)best;
+                chn[c][a32(x)] = best == 0x7FFFFFFF ? GNONE : best;
                 if (c == 1) {
                     any_in |= best == 0;
                     any_out |= best != 0;
@@ -835,10 +841,9 @@ __global__ __launch_bounds__(128) void k_edt_rows_env(const uint32_t *__restrict
     if (work) {
         // one event per step (skip an empty column, drop the top, or push),
         // so that a wave runs at most 2 M steps however its lanes' drops fall
-        const uint16_t *g = gsh + cls * S16;
         const int hi = min(N, lo + M);
         int k = 0, s1 = 0, s2 = 0, c1 = 0, c2 = 0;
-        int q = lo, gq = q < hi ? (int)g[a16(q)] : GNONE;
+        int q = lo, gq = q < hi ? ch[a32(q)] : GNONE;
         while (q < hi) {
             const int cq = q * q + gq * gq;
             if (gq != GNONE && k >= 2 && hull_above(s2, c2, s1, c1, q, cq)) {
@@ -861,7 +866,7 @@ __global__ __launch_bounds__(128) void k_edt_rows_env(const uint32_t *__restrict
                 ++k;
             }
             ++q;
-            gq = q < hi ? (int)g[a16(q)] : GNONE;
+            gq = q < hi ? ch[a32(q)] : GNONE;
         }
         r1 = k;
     }
@@ -1007,7 +1012,7 @@ __global__ __launch_bounds__(128) void k_edt_rows_env(const uint32_t *__restrict
     __syncthreads();
     for (int x = threadIdx.x; x < N; x += 128) {
         // inside pixels (g_1 = 0) take D_0, outside ones D_1
-        const bool inside = gsh[S16 + a16(x)] == 0;
+        const bool inside = (insb[x >> 5] >> (x & 31)) & 1u;
         const int D = chn[inside ? 0 : 1][a32(x)];
         if (sqdist) {
             const int d1 = chn[1][a32(x)], d0 = chn[0][a32(x)];
