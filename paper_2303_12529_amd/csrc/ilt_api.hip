@@ -58,6 +58,23 @@ float bf2f(uint16_t h) {
     std::memcpy(&f, &u, 4);
     return f;
 }
+// A [Np][NZ] column table in the spectrum kernel's fragment order: for each
+// 16-row group g and 16-column block nb, lane 16 q + r holds rows
+// 16 g + 4 q .. + 3 of column 16 nb + r as four consecutive floats, the B
+// operands of four consecutive matrix-core steps in one 16-byte load.
+std::vector<float> spectrum_fragments(const float *t, int Np, int NZ) {
+    std::vector<float> f((size_t)Np * NZ);
+    const int NB = NZ / 16;
+    for (int g = 0; g < Np / 16; ++g)
+        for (int nb = 0; nb < NB; ++nb)
+            for (int lane = 0; lane < 64; ++lane)
+                for (int e = 0; e < 4; ++e) {
+                    const int x = 16 * g + 4 * (lane >> 4) + e, n = 16 * nb + (lane & 15);
+                    f[(((size_t)g * NB + nb) * 64 + lane) * 4 + e] = t[(size_t)x * NZ + n];
+                }
+    return f;
+}
+
 void split_bf(float x, uint16_t &hi, uint16_t &lo) {
     hi = f2bf(x);
     lo = f2bf(x - bf2f(hi));
@@ -101,7 +118,7 @@ void free_ctx(ilt_ctx *c) {
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     void *ptrs[] = {c->A64, c->H64, c->w64, c->T64, c->S64, c->Y64, c->I64, c->G64, c->Q64, c->W64, c->Z64, c->g64,
                     c->phi64, c->part64,
-                    c->tl, c->tb, c->ta4, c->ar, c->ai, c->H, c->sw, c->coef, c->tlhl, c->tbhl, c->Yhl, c->Spart, c->S, c->Est, c->Y, c->Tg,
+                    c->tl, c->tb, c->tbs, c->ta4, c->ar, c->ai, c->H, c->sw, c->coef, c->tlhl, c->tbhl, c->Yhl, c->Spart, c->S, c->Est, c->Y, c->Tg,
                     c->I, c->G, c->g, c->phi2, c->Wpart, c->W, c->edt_scratch, c->part, c->scal, c->phib,
                     c->tgtb,
                     c->tbQ, c->arQ, c->aiQ, c->Ghat, c->Ugw, c->Vpart, c->g_prev, c->dcg};
@@ -312,6 +329,7 @@ extern "C" int ilt_create(ilt_ctx **out, const ilt_optics *o, int max_batch, voi
     if (e == hipSuccess) e = dalloc(&c->ptr, (n))
     ALLOC(tl, tl.size());
     ALLOC(tb, tb.size());
+    ALLOC(tbs, (size_t)Np * NZ);
     ALLOC(ta4, ta4.size());
     ALLOC(ar, ar.size());
     ALLOC(ai, ai.size());
@@ -430,6 +448,10 @@ extern "C" int ilt_create(ilt_ctx **out, const ilt_optics *o, int max_batch, voi
     }
     if (e == hipSuccess) e = hipMemcpy(c->tl, tl.data(), tl.size() * 4, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(c->tb, tb.data(), tb.size() * 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess) {
+        const std::vector<float> f = spectrum_fragments(tb.data(), Np, NZ);
+        e = hipMemcpy(c->tbs, f.data(), f.size() * 4, hipMemcpyHostToDevice);
+    }
     if (e == hipSuccess) e = hipMemcpy(c->ta4, ta4.data(), ta4.size() * 4, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(c->ar, ar.data(), ar.size() * 4, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(c->ai, ai.data(), ai.size() * 4, hipMemcpyHostToDevice);
@@ -442,7 +464,8 @@ extern "C" int ilt_create(ilt_ctx **out, const ilt_optics *o, int max_batch, voi
         if (e == hipSuccess) e = hipMemcpy(c->w64, w64h.data(), w64h.size() * sizeof(double), hipMemcpyHostToDevice);
     }
     if (e == hipSuccess && c->gwin) {
-        e = hipMemcpy(c->tbQ, tbQ.data(), tbQ.size() * 4, hipMemcpyHostToDevice);
+        const std::vector<float> f = spectrum_fragments(tbQ.data(), Np, c->NZQ);
+        e = hipMemcpy(c->tbQ, f.data(), f.size() * 4, hipMemcpyHostToDevice);
         if (e == hipSuccess) e = hipMemcpy(c->arQ, arQ.data(), arQ.size() * 4, hipMemcpyHostToDevice);
         if (e == hipSuccess) e = hipMemcpy(c->aiQ, aiQ.data(), aiQ.size() * 4, hipMemcpyHostToDevice);
     }

@@ -76,6 +76,7 @@ struct ilt_ctx {
     // tables
     float *tl;         // [2][KP][Np]
     float *tb;         // [2][Np][NZ]
+    float *tbs;        // part 0 of tb in the spectrum's fragment order [Np/16][NZ/16][64][4]
     float *ta4;        // [2][Np][AP]
     float *ar, *ai;    // [P][Np]
     float2 *H;         // [n_sets][K][P][P]   kernels (FP32)
@@ -86,7 +87,7 @@ struct ilt_ctx {
     __bf16 *Yhl;       // split-BF16 form: window rows [n_sets][K][Np][hi|lo][KP]
     // G-window adjoint (ILT_FLAG_GWINDOW_ADJOINT): difference window Q = 2P - 1
     int gwin, Q, FBQ, MIXQ, NZQ;
-    float *tbQ;        // [Np][NZQ] window columns of the difference window
+    float *tbQ;        // window columns of the difference window, fragment order [Np/16][NZQ/16][64][4]
     float *arQ, *aiQ;  // [Q][Np]
     float2 *Ghat;      // [n_sets][Q][Q]
     float *Ugw;        // [n_sets][Fpad][NC] U_k = H_k . S as real columns (Fpad = P^2 rounded up to 4, NC = 2K rounded up to 16)

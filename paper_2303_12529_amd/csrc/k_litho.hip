@@ -41,7 +41,9 @@ __device__ __forceinline__ float wave_max(float v) {
 // they are summed over the bands in FP64.
 // Each lane loads four consecutive columns of its row as one float4 and uses
 // them in four consecutive k-steps; the B-operand rows follow the same
-// (x = 4(l/16) + e) order, so the sum is unchanged.
+// (x = 4(l/16) + e) order, so the sum is unchanged.  The column table comes
+// in fragment order ([x/16][NZ/16][lane][e]): one 16-byte load per column
+// block gives a lane its B operands of those four steps.
 // --------------------------------------------------------------------------
 template <int FB, int MIX>
 __global__ __launch_bounds__(512) void k_spectrum_band(const float *__restrict__ src, size_t src_stride,
@@ -84,11 +86,14 @@ __global__ __launch_bounds__(512) void k_spectrum_band(const float *__restrict__
                 for (int e = 0; e < 4; ++e) m[e] = m[e] <= 0.f ? 1.f : 0.f;
             }
         }
+        f4 bv[NB];
+        const f4 *bsrc = reinterpret_cast<const f4 *>(tb) + (size_t)(x / 16) * NB * 64 + lane;
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) bv[nb] = bsrc[nb * 64];
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-            const float *brow = tb + (size_t)(xx + e) * NZ + l16;
 #pragma unroll
-            for (int nb = 0; nb < NB; ++nb) acc[nb] = mfma4(m[e], brow[nb * 16], acc[nb]);
+            for (int nb = 0; nb < NB; ++nb) acc[nb] = mfma4(m[e], bv[nb][e], acc[nb]);
         }
     }
     // sum of the 8 waves' partials in a fixed order, through half as much
@@ -1008,7 +1013,7 @@ static hipError_t spectrum_to(ilt_ctx *c, const float *src, int src_is_phi, int 
 }
 
 hipError_t launch_spectrum(ilt_ctx *c, const float *src, int src_is_phi) {
-    return spectrum_to(c, src, src_is_phi, c->FB, c->MIX, c->tb, c->ar, c->ai, c->P, c->S, c->ncur, cs_npix(c), 1);
+    return spectrum_to(c, src, src_is_phi, c->FB, c->MIX, c->tbs, c->ar, c->ai, c->P, c->S, c->ncur, cs_npix(c), 1);
 }
 
 hipError_t launch_make_Y(ilt_ctx *c, int set_lo, int set_hi) {
