@@ -139,7 +139,6 @@ __global__ __launch_bounds__(256, 2) void k_image_b3(const __bf16 *__restrict__ 
                                                       float *__restrict__ out) {
     constexpr int NS = kmap<KP>::NS, NSL = kmap<KP>::NSL;
     constexpr int RW = 2 * KP + 8;                 // LDS row (one column x), bf16
-    constexpr int NV = (64 * 2 * KP / 8 + 255) / 256;
     __shared__ __attribute__((aligned(16))) __bf16 Ys[2][64][RW];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int l16 = lane & 15, lq = lane >> 4;
@@ -159,31 +158,31 @@ __global__ __launch_bounds__(256, 2) void k_image_b3(const __bf16 *__restrict__ 
 #pragma unroll
         for (int yb = 0; yb < 2; ++yb) accI[xb][yb] = f4{0.f, 0.f, 0.f, 0.f};
 
-    u4 pre[NV];
-#define B3_FETCH(jj)                                                                                     \
-    do {                                                                                                 \
-        const __bf16 *src_ = Yhl + (((size_t)(s * nj + (jj)) * Np) + x0) * 2 * KP;                     \
-        _Pragma("unroll") for (int v = 0; v < NV; ++v) {                                                 \
-            const int e = threadIdx.x + 256 * v;                                                         \
-            if (e < 64 * 2 * KP / 8) pre[v] = *reinterpret_cast<const u4 *>(src_ + (size_t)e * 8);       \
-        }                                                                                                \
-    } while (0)
-#define B3_STASH(bb)                                                                                     \
-    do {                                                                                                 \
-        _Pragma("unroll") for (int v = 0; v < NV; ++v) {                                                 \
-            const int e = threadIdx.x + 256 * v;                                                         \
-            if (e < 64 * 2 * KP / 8) {                                                                   \
-                const int xx = e / (2 * KP / 8), q = e % (2 * KP / 8);                                   \
-                *reinterpret_cast<u4 *>(&Ys[(bb)][xx][q * 8]) = pre[v];                                  \
-            }                                                                                            \
-        }                                                                                                \
-    } while (0)
-    B3_FETCH(0);
-    B3_STASH(0);
+    // Y_j tile: rows x0 .. x0 + 63 of [hi|lo] (2 KP / 8 units of 16 bytes,
+    // one pad unit per LDS row), copied global -> LDS by the memory unit; the
+    // copy of Y_{j+1} runs while Y_j is contracted.  Per-lane source offsets
+    // are formed once (wave w copies the 64-unit groups w, w + 4, ...; a pad
+    // unit copies its row's first unit, never read).
+    constexpr int RWU = RW / 8, NYI = RWU, NYT = (NYI + 3) / 4;
+    int yoff[NYT];
+#pragma unroll
+    for (int t = 0; t < NYT; ++t) {
+        const int U = 64 * (wave + 4 * t) + lane;
+        const int row = U / RWU, col = U - (U / RWU) * RWU;
+        yoff[t] = (x0 + row) * 2 * KP + (col < RWU - 1 ? col : 0) * 8;
+    }
+    auto copy_y = [&](int jj, int bb) {
+        const __bf16 *src = Yhl + (size_t)(s * nj + jj) * Np * 2 * KP;
+#pragma unroll
+        for (int t = 0; t < NYT; ++t)
+            if (wave + 4 * t < NYI) ilt_dev::lds_dma16(src + yoff[t], &Ys[bb][0][0] + 512 * (wave + 4 * t));
+    };
+    copy_y(0, 0);
+    ilt_dev::wait_copies();
     __syncthreads();
     for (int j = 0; j < nj; ++j) {
         const int buf = j & 1;
-        if (j + 1 < nj) B3_FETCH(j + 1);
+        if (j + 1 < nj) copy_y(j + 1, buf ^ 1);
         // two halves of the 64 columns keep only half the field accumulators
         // live; the Y operands of step t + 1 are read from LDS before the
         // products of step t issue (scheduling barriers keep that order)
@@ -234,11 +233,11 @@ __global__ __launch_bounds__(256, 2) void k_image_b3(const __bf16 *__restrict__ 
                                                             fmaf(ei[xl][yb][i], ei[xl][yb][i], accI[2 * xh + xl][yb][i]));
             }
         }
-        if (j + 1 < nj) B3_STASH(buf ^ 1);
+        // this wave's copy of Y_{j+1} has landed, and every wave is done with
+        // buffer buf before it is refilled
+        ilt_dev::wait_copies();
         __syncthreads();
     }
-#undef B3_FETCH
-#undef B3_STASH
     float *o = out + (size_t)ts * N * N;
 #pragma unroll
     for (int xb = 0; xb < 4; ++xb)
