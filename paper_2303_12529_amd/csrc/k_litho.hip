@@ -387,8 +387,9 @@ __global__ __launch_bounds__(256) void k_make_y(const float2 *__restrict__ H, co
 //           [set][j][y/16][x/16][re|im][lane][4].
 // Block = 4 waves; block tile = 128 rows x 64 columns; wave tile = 32 x 64.
 // The image-side operands (L rows of the wave's 32 y) stay in registers as
-// B-operands; each Y_j tile (KP x 64) is staged through LDS, double-buffered
-// with a register prefetch of the next j, and shared by the four waves.
+// B-operands; each Y_j tile (KP x 64) is staged in LDS, double-buffered
+// (the next j copied global -> LDS by the memory unit), and shared by the
+// four waves.
 // --------------------------------------------------------------------------
 template <int KP, int MODE, bool STORE>
 __global__ __launch_bounds__(256, 2) void k_image(const float *__restrict__ tl, const float *__restrict__ Y,
@@ -397,8 +398,10 @@ __global__ __launch_bounds__(256, 2) void k_image(const float *__restrict__ tl, 
                                                size_t y_cs, size_t out_cs, size_t max_cs, size_t est_cs) {
     constexpr int KS = KP / 4;
     constexpr int LDW = 64 + 16;
-    constexpr int NV = (KP * 16 + 255) / 256;      // float4 per thread per tile
-    __shared__ float Ys[2][KP][LDW];
+    // Y_j tiles, KP rows of LDW floats (16 data units of 16 bytes + 4 pad
+    // units), rounded up to whole 64-unit copies
+    constexpr int RU = LDW / 4, NYI = (KP * RU + 63) / 64, NYT = (NYI + 3) / 4;
+    __shared__ __align__(16) float Ysm[2][NYI * 256];
     __shared__ float wmax[4];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int l16 = lane & 15, lq = lane >> 4;
@@ -427,28 +430,29 @@ __global__ __launch_bounds__(256, 2) void k_image(const float *__restrict__ tl, 
 #pragma unroll
         for (int yb = 0; yb < 2; ++yb) accI[xb][yb] = f4{0.f, 0.f, 0.f, 0.f};
 
-    f4 pre[NV];
-#define IMG_FETCH(jj)                                                                                     \
-    do {                                                                                                  \
-        const float *Yj_ = Y + ((size_t)(s * nj + (jj)) * KP) * Np + x0;                                 \
-        _Pragma("unroll") for (int v = 0; v < NV; ++v) {                                                  \
-            const int e = threadIdx.x + 256 * v;                                                          \
-            if (e < KP * 16) pre[v] = *reinterpret_cast<const f4 *>(Yj_ + (size_t)(e >> 4) * Np + (e & 15) * 4); \
-        }                                                                                                 \
-    } while (0)
-#define IMG_STASH(bb)                                                                                     \
-    do {                                                                                                  \
-        _Pragma("unroll") for (int v = 0; v < NV; ++v) {                                                  \
-            const int e = threadIdx.x + 256 * v;                                                          \
-            if (e < KP * 16) *reinterpret_cast<f4 *>(&Ys[(bb)][e >> 4][(e & 15) * 4]) = pre[v];       \
-        }                                                                                                 \
-    } while (0)
-    IMG_FETCH(0);
-    IMG_STASH(0);
+    // copied global -> LDS by the memory unit, the copy of Y_{j+1} in flight
+    // while Y_j is contracted; per-lane source offsets formed once (wave w
+    // copies the 64-unit groups w, w + 4, ...; pad units and the units past
+    // the last row copy a valid unit and are never read)
+    int yoff[NYT];
+#pragma unroll
+    for (int t = 0; t < NYT; ++t) {
+        const int U = 64 * (wave + 4 * t) + lane;
+        const int row = min(U / RU, KP - 1), col = U - (U / RU) * RU;
+        yoff[t] = row * Np + (col < 16 ? 4 * col : 0);
+    }
+    auto copy_y = [&](int jj, int bb) {
+        const float *src = Y + ((size_t)(s * nj + jj) * KP) * Np + x0;
+#pragma unroll
+        for (int t = 0; t < NYT; ++t)
+            if (wave + 4 * t < NYI) ilt_dev::lds_dma16(src + yoff[t], &Ysm[bb][256 * (wave + 4 * t)]);
+    };
+    copy_y(0, 0);
+    ilt_dev::wait_copies();
     __syncthreads();
     for (int j = 0; j < nj; ++j) {
         const int buf = j & 1;
-        if (j + 1 < nj) IMG_FETCH(j + 1);
+        if (j + 1 < nj) copy_y(j + 1, buf ^ 1);
         f4 er[4][2], ei[4][2];
 #pragma unroll
         for (int xb = 0; xb < 4; ++xb)
@@ -461,7 +465,7 @@ __global__ __launch_bounds__(256, 2) void k_image(const float *__restrict__ tl, 
         for (int ks = 0; ks < KS; ++ks) {
 #pragma unroll
             for (int xb = 0; xb < 4; ++xb) {
-                const float a = Ys[buf][4 * ks + lq][16 * xb + l16];
+                const float a = Ysm[buf][(4 * ks + lq) * LDW + 16 * xb + l16];
 #pragma unroll
                 for (int yb = 0; yb < 2; ++yb) {
                     er[xb][yb] = mfma4(a, b1[yb][ks], er[xb][yb]);
@@ -469,6 +473,9 @@ __global__ __launch_bounds__(256, 2) void k_image(const float *__restrict__ tl, 
                 }
             }
         }
+        // this wave's copy of Y_{j+1} has landed (waited for before the field
+        // stores are issued, so that the wait does not cover them)
+        ilt_dev::wait_copies();
         if (STORE) {
 #pragma unroll
             for (int xb = 0; xb < 4; ++xb)
@@ -492,11 +499,9 @@ __global__ __launch_bounds__(256, 2) void k_image(const float *__restrict__ tl, 
                     else
                         accI[xb][yb][i] += er[xb][yb][i];
                 }
-        if (j + 1 < nj) IMG_STASH(buf ^ 1);
+        // every wave is done with buffer buf before it is refilled
         __syncthreads();
     }
-#undef IMG_FETCH
-#undef IMG_STASH
     float m = 0.f;
     float *o = out + (size_t)zr * N * N;
 #pragma unroll
