@@ -75,6 +75,26 @@ std::vector<float> spectrum_fragments(const float *t, int Np, int NZ) {
     return f;
 }
 
+// tb ([2][Np][NZ]) in the stored-field adjoint's fragment order: per
+// 32-column chunk c, 16-column half xb, column block nb and part, lane
+// 16 q + r holds rows 32 c + 16 xb + 4 q .. + 3 of column 16 nb + r as four
+// consecutive floats.
+std::vector<float> adjoint_fragments(const float *tb, int Np, int NZ) {
+    std::vector<float> f((size_t)2 * Np * NZ);
+    const int NB = NZ / 16;
+    size_t o = 0;
+    for (int c = 0; c < Np / 32; ++c)
+        for (int xb = 0; xb < 2; ++xb)
+            for (int nb = 0; nb < NB; ++nb)
+                for (int part = 0; part < 2; ++part)
+                    for (int lane = 0; lane < 64; ++lane)
+                        for (int i = 0; i < 4; ++i) {
+                            const int x = 32 * c + 16 * xb + 4 * (lane >> 4) + i, n = 16 * nb + (lane & 15);
+                            f[o++] = tb[((size_t)part * Np + x) * NZ + n];
+                        }
+    return f;
+}
+
 void split_bf(float x, uint16_t &hi, uint16_t &lo) {
     hi = f2bf(x);
     lo = f2bf(x - bf2f(hi));
@@ -118,7 +138,7 @@ void free_ctx(ilt_ctx *c) {
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     void *ptrs[] = {c->A64, c->H64, c->w64, c->T64, c->S64, c->Y64, c->I64, c->G64, c->Q64, c->W64, c->Z64, c->g64,
                     c->phi64, c->part64,
-                    c->tl, c->tb, c->tbs, c->ta4, c->ar, c->ai, c->H, c->sw, c->coef, c->tlhl, c->tbhl, c->Yhl, c->Spart, c->S, c->Est, c->Y, c->Tg,
+                    c->tl, c->tb, c->tbs, c->tba, c->ta4, c->ar, c->ai, c->H, c->sw, c->coef, c->tlhl, c->tbhl, c->Yhl, c->Spart, c->S, c->Est, c->Y, c->Tg,
                     c->I, c->G, c->g, c->phi2, c->Wpart, c->W, c->edt_scratch, c->part, c->scal, c->phib,
                     c->tgtb,
                     c->tbQ, c->arQ, c->aiQ, c->Ghat, c->Ugw, c->Vpart, c->g_prev, c->dcg};
@@ -330,6 +350,7 @@ extern "C" int ilt_create(ilt_ctx **out, const ilt_optics *o, int max_batch, voi
     ALLOC(tl, tl.size());
     ALLOC(tb, tb.size());
     ALLOC(tbs, (size_t)Np * NZ);
+    ALLOC(tba, tb.size());
     ALLOC(ta4, ta4.size());
     ALLOC(ar, ar.size());
     ALLOC(ai, ai.size());
@@ -451,6 +472,10 @@ extern "C" int ilt_create(ilt_ctx **out, const ilt_optics *o, int max_batch, voi
     if (e == hipSuccess) {
         const std::vector<float> f = spectrum_fragments(tb.data(), Np, NZ);
         e = hipMemcpy(c->tbs, f.data(), f.size() * 4, hipMemcpyHostToDevice);
+    }
+    if (e == hipSuccess) {
+        const std::vector<float> f = adjoint_fragments(tb.data(), Np, NZ);
+        e = hipMemcpy(c->tba, f.data(), f.size() * 4, hipMemcpyHostToDevice);
     }
     if (e == hipSuccess) e = hipMemcpy(c->ta4, ta4.data(), ta4.size() * 4, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(c->ar, ar.data(), ar.size() * 4, hipMemcpyHostToDevice);

@@ -154,4 +154,30 @@ __device__ __forceinline__ void adjoint_rows(f4 (&accZ)[2][NB], const f4 (&er)[2
 }
 
 
+// (c) as above with the B3 operands in fragment order: the tile holds, per
+// 16-column half xb, column block nb and part (re, im), 64 lanes x 4 rows,
+// so one 16-byte read gives a lane its operands of all four steps; the
+// products are issued in the same order, so the sums are the same.
+template <int NB>
+__device__ __forceinline__ void adjoint_rows_frag(f4 (&accZ)[2][NB], const f4 (&er)[2], const f4 (&ei)[2],
+                                                  const float *Bt, int xb, int lane) {
+    f4 br[NB], bi[NB];
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+        br[nb] = *reinterpret_cast<const f4 *>(Bt + ((((xb * NB + nb) * 2 + 0) * 64 + lane) * 4));
+        bi[nb] = *reinterpret_cast<const f4 *>(Bt + ((((xb * NB + nb) * 2 + 1) * 64 + lane) * 4));
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+            for (int yb = 0; yb < 2; ++yb) accZ[yb][nb] = mfma4(er[yb][i], br[nb][i], accZ[yb][nb]);
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+            for (int yb = 0; yb < 2; ++yb) accZ[yb][nb] = mfma4(ei[yb][i], bi[nb][i], accZ[yb][nb]);
+    }
+}
+
 }  // namespace ilt_dev

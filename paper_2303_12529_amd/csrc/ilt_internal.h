@@ -77,6 +77,7 @@ struct ilt_ctx {
     float *tl;         // [2][KP][Np]
     float *tb;         // [2][Np][NZ]
     float *tbs;        // part 0 of tb in the spectrum's fragment order [Np/16][NZ/16][64][4]
+    float *tba;        // tb in the stored-field adjoint's fragment order [Np/32][2][NZ/16][2][64][4]
     float *ta4;        // [2][Np][AP]
     float *ar, *ai;    // [P][Np]
     float2 *H;         // [n_sets][K][P][P]   kernels (FP32)

@@ -547,7 +547,11 @@ __global__ __launch_bounds__(256, 2) void k_image(const float *__restrict__ tl, 
 // then the shared tail.  grid.y = kernel groups x column ranges: a block
 // walks its range of chunks only (its partial W is summed with the others').
 //
-// Pipeline, one barrier per chunk: the B3 rows and G tile of chunk c + 1
+// The B3 operands come from a table in fragment order ([chunk][16-column
+// half][column block][re|im][lane][4 rows]), so that one 16-byte LDS read
+// gives a lane its operands of four matrix-core steps.
+//
+// Pipeline, one barrier per chunk: the B3 operands and G tile of chunk c + 1
 // are copied global -> LDS (no registers) into the other half of
 // double-buffered tiles, and the E fragments of the next 16-column half are
 // loaded into registers, while the current half is multiplied.  Both are
@@ -558,19 +562,20 @@ __global__ __launch_bounds__(256, 2) void k_image(const float *__restrict__ tl, 
 // accumulator reuses the two B3 tiles.
 // --------------------------------------------------------------------------
 template <int FB, int MIX, bool A4>
-__global__ __launch_bounds__(256, 2) void k_adjoint_st(const float *__restrict__ tb, const float *__restrict__ ta4,
+__global__ __launch_bounds__(256, 2) void k_adjoint_st(const float *__restrict__ tba, const float *__restrict__ ta4,
                                                     const float *__restrict__ Est, const float *__restrict__ G,
                                                     size_t g_set_stride, const float2 *__restrict__ coef, int K,
                                                     int P, int N, int Np, int AP, int set_lo,
                                                     float *__restrict__ Wpart, int zs, size_t est_cs, size_t g_cs,
                                                     size_t wp_cs) {
     constexpr int NZ = 32 * FB + 16 * MIX, NB = NZ / 16;
-    constexpr int LDB = NZ + 4;                       // row: NZ / 4 data units + 1 pad unit of 16 B
-    constexpr int BU = 2 * 32 * (LDB / 4);            // 16-byte units of one B3 tile (a multiple of 64)
+    constexpr int BU = 4 * NB * 64;                   // 16-byte units of one B3 tile, fragment order
+    constexpr int WU = (int)((sizeof(float2) * ILT_MAX_P * ILT_MAX_P + 2047) / 2048) * 64;   // W: 16-byte units per tile
+    constexpr int BUA = BU > WU ? BU : WU;            // tile size in LDS
     constexpr int GU = 320;                           // G tile [32][36] = 288 units, padded to 5 x 64
     static_assert(BU % 64 == 0, "B3 tile must be whole wave copies");
-    static_assert((size_t)2 * BU * 16 >= sizeof(float2) * ILT_MAX_P * ILT_MAX_P, "W accumulator must fit the B3 tiles");
-    __shared__ __align__(16) float Bs[2][BU * 4];
+    static_assert((size_t)2 * BUA * 16 >= sizeof(float2) * ILT_MAX_P * ILT_MAX_P, "W accumulator must fit the B3 tiles");
+    __shared__ __align__(16) float Bs[2][BUA * 4];
     __shared__ __align__(16) float Gs[2][GU * 4];
     float2 *Ws = reinterpret_cast<float2 *>(&Bs[0][0]);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -599,17 +604,10 @@ __global__ __launch_bounds__(256, 2) void k_adjoint_st(const float *__restrict__
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb) accZ[yb][nb] = f4{0.f, 0.f, 0.f, 0.f};
 
-    // The copies' per-lane source offsets do not depend on the chunk: they
+    // The G copies' per-lane source offsets do not depend on the chunk: they
     // are formed once (wave w copies the 64-unit groups w, w + 4, ...).
     constexpr int NBI = (BU / 64 + 3) / 4, NGI = (GU / 64 + 3) / 4;
-    int boff[NBI], grow[NGI], gcol[NGI];
-#pragma unroll
-    for (int t = 0; t < NBI; ++t) {
-        const int U = 64 * (wave + 4 * t) + lane;
-        const int part = U / (32 * (LDB / 4)), rem = U - part * (32 * (LDB / 4));
-        const int row = rem / (LDB / 4), c4 = rem - row * (LDB / 4);
-        boff[t] = (part * Np + row) * NZ + (c4 < NZ / 4 ? 4 * c4 : 0);
-    }
+    int grow[NGI], gcol[NGI];
 #pragma unroll
     for (int t = 0; t < NGI; ++t) {
         const int U = 64 * (wave + 4 * t) + lane;
@@ -618,12 +616,13 @@ __global__ __launch_bounds__(256, 2) void k_adjoint_st(const float *__restrict__
         grow[t] = min(y0 + (data ? row : 0), N - 1) * N;
         gcol[t] = data ? 4 * c4 : 0;
     }
-    // B3 rows x0.. of both parts into tile bb (pad units copy a valid row start)
+    // B3 operands of chunk c (contiguous in the fragment-ordered table) into tile bb
     auto copy_b = [&](int c, int bb) {
-        const float *src = tb + (size_t)c * 32 * NZ;
+        const float *src = tba + (size_t)c * BU * 4;
 #pragma unroll
         for (int t = 0; t < NBI; ++t)
-            if (wave + 4 * t < BU / 64) ilt_dev::lds_dma16(src + boff[t], &Bs[bb][256 * (wave + 4 * t)]);
+            if (wave + 4 * t < BU / 64)
+                ilt_dev::lds_dma16(src + (size_t)(64 * (wave + 4 * t) + lane) * 4, &Bs[bb][256 * (wave + 4 * t)]);
     };
     // G rows y0.., columns x0.. into tile bb, coordinates clamped into the image
     auto copy_g = [&](int c, int bb) {
@@ -695,7 +694,7 @@ __global__ __launch_bounds__(256, 2) void k_adjoint_st(const float *__restrict__
         if (jok) {
             f4 er[2], ei[2];
             form_x(c, bb, 0, ea, er, ei);
-            ilt_dev::adjoint_rows<NB>(accZ, er, ei, &Bs[bb][0], &Bs[bb][BU * 2], LDB, 0, lq, l16);
+            ilt_dev::adjoint_rows_frag<NB>(accZ, er, ei, &Bs[bb][0], 0, lane);
         }
         f4 er[2], ei[2];
         if (jok) form_x(c, bb, 1, eb, er, ei);
@@ -706,7 +705,7 @@ __global__ __launch_bounds__(256, 2) void k_adjoint_st(const float *__restrict__
             else load_g_regs(c + 1);
             if (jok) load_half(c + 1, 0, ea);
         }
-        if (jok) ilt_dev::adjoint_rows<NB>(accZ, er, ei, &Bs[bb][0], &Bs[bb][BU * 2], LDB, 1, lq, l16);
+        if (jok) ilt_dev::adjoint_rows_frag<NB>(accZ, er, ei, &Bs[bb][0], 1, lane);
         if (!A4 && more) store_g_regs(bb ^ 1);
         ilt_dev::wait_copies();
         __syncthreads();
@@ -1082,11 +1081,11 @@ hipError_t launch_adjoint(ilt_ctx *c, const float *G, size_t g_set_stride, int s
 #define ADJS(FB_, MIX_)                                                                                        \
     do {                                                                                                        \
         if ((c->N & 3) == 0 && (reinterpret_cast<uintptr_t>(G) & 15) == 0)                                     \
-            k_adjoint_st<FB_, MIX_, true><<<grid, 256, 0, c->stream>>>(c->tb, c->ta4, c->Est, G, g_set_stride,   \
+            k_adjoint_st<FB_, MIX_, true><<<grid, 256, 0, c->stream>>>(c->tba, c->ta4, c->Est, G, g_set_stride,   \
                                                                       c->coef, c->K, c->P, c->N, c->Np, c->AP, \
                                                                       set_lo, c->Wpart, zs, cs_est(c), gcs, wcs); \
         else                                                                                                    \
-            k_adjoint_st<FB_, MIX_, false><<<grid, 256, 0, c->stream>>>(c->tb, c->ta4, c->Est, G, g_set_stride,  \
+            k_adjoint_st<FB_, MIX_, false><<<grid, 256, 0, c->stream>>>(c->tba, c->ta4, c->Est, G, g_set_stride,  \
                                                                        c->coef, c->K, c->P, c->N, c->Np, c->AP, \
                                                                        set_lo, c->Wpart, zs, cs_est(c), gcs, wcs); \
     } while (0)
