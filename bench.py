@@ -111,6 +111,19 @@ def gwindow_work(N, P, K, n_sets):
     return w
 
 
+def hopkins_work(N, P, K, n_sets):
+    """Algorithmic flops of one iteration with the TCC-form image and the
+    G-window adjoint: the image spectrum on the difference window (sum over
+    D of the window overlap is P^4 per kernel), its window rows and one
+    pruned inverse transform per set, instead of K field transforms."""
+    Q = 2 * P - 1
+    N2 = float(N) * N
+    w = gwindow_work(N, P, K, n_sets)
+    w["window_rows"] = dict(flops=n_sets * K * 8.0 * P ** 4)
+    w["image"] = dict(flops=n_sets * (4.0 * Q * N2 + 8.0 * Q * Q * N))
+    return w
+
+
 def gwindow_forms(Z, H, w, N, prm, steps, autotune):
     """The loop with the G-window adjoint, in both precisions (its own cost
     model, so its own figures)."""
@@ -119,11 +132,14 @@ def gwindow_forms(Z, H, w, N, prm, steps, autotune):
     n_sets, K, P, _ = H.shape
     target = torch.as_tensor(Z).to("cuda")
     out = {"note": "adjoint by the G-window identity (exact): one (2P-1)^2 pruned transform of G per set "
-                   "plus a window correlation, instead of K field transforms; no field store"}
-    work = gwindow_work(N, P, K, n_sets)
-    total = sum(v.get("flops", 0.0) for v in work.values())
-    for name, prec in (("fp32", ilt.ILT_FP32), ("bf16x3", ilt.ILT_BF16X3)):
-        ctx = ilt.Context(H, w, N, precision=prec, flags=ilt.ILT_FLAG_GWINDOW_ADJOINT)
+                   "plus a window correlation, instead of K field transforms; no field store; fp32_hopkins: "
+                   "the image as well through its (2P-1)^2 spectrum (TCC form, exact), no field at all"}
+    gw, hop = ilt.ILT_FLAG_GWINDOW_ADJOINT, ilt.ILT_FLAG_HOPKINS_FORWARD
+    for name, prec, flags in (("fp32", ilt.ILT_FP32, gw), ("bf16x3", ilt.ILT_BF16X3, gw),
+                              ("fp32_hopkins", ilt.ILT_FP32, gw | hop)):
+        work = (hopkins_work if flags & hop else gwindow_work)(N, P, K, n_sets)
+        total = sum(v.get("flops", 0.0) for v in work.values())
+        ctx = ilt.Context(H, w, N, precision=prec, flags=flags)
         if autotune:
             ctx.autotune()
         phi = torch.empty((N, N), dtype=torch.float32, device="cuda")
@@ -279,8 +295,10 @@ def develset_ttt(seeds, wide_seeds=None):
     from paper_2303_12529_amd import ilt
     out = {}
     gw = ilt.ILT_FLAG_GWINDOW_ADJOINT
+    hop = gw | ilt.ILT_FLAG_HOPKINS_FORWARD
     runs = [("weights", DSN_WEIGHTS, (("fp32", ilt.ILT_FP32, 0), ("fp32_gwindow", ilt.ILT_FP32, gw),
-                                      ("bf16x3", ilt.ILT_BF16X3, 0), ("bf16x3_gwindow", ilt.ILT_BF16X3, gw))),
+                                      ("bf16x3", ilt.ILT_BF16X3, 0), ("bf16x3_gwindow", ilt.ILT_BF16X3, gw),
+                                      ("fp32_hopkins", ilt.ILT_FP32, hop))),
             ("modulation_net", DSN_MOD_WEIGHTS, (("fp32", ilt.ILT_FP32, 0),))]
     for label, path, forms in runs:
         if not os.path.exists(path):
@@ -462,6 +480,9 @@ def main():
     ap.add_argument("--adjoint", choices=("fields", "gwindow"), default="fields",
                     help="adjoint of the timed loop: through the K fields (the paper's form, default) or the "
                          "G-window identity")
+    ap.add_argument("--forward", choices=("fields", "hopkins"), default="fields",
+                    help="image of the timed loop: through the K fields (default) or its difference-window "
+                         "spectrum (TCC form; needs --adjoint gwindow and --precision fp32)")
     ap.add_argument("--batch-clips", type=int, default=64,
                     help="clips in the batched-form measurement (0: skip)")
     ap.add_argument("--batch-lanes", type=int, default=4)
@@ -494,7 +515,12 @@ def main():
         torch.cuda.synchronize()
         del a, b
     prec = ilt.ILT_BF16X3 if args.precision == "bf16x3" else ilt.ILT_FP32
+    if args.forward == "hopkins" and (args.adjoint != "gwindow" or args.precision != "fp32"):
+        print("--forward hopkins needs --adjoint gwindow and --precision fp32", file=sys.stderr)
+        sys.exit(2)
     flags = ilt.ILT_FLAG_GWINDOW_ADJOINT if args.adjoint == "gwindow" else 0
+    if args.forward == "hopkins":
+        flags |= ilt.ILT_FLAG_HOPKINS_FORWARD
     ctx = ilt.Context(H, w, N, precision=prec, flags=flags)
     tuning = None if args.no_autotune else ctx.autotune()
     target = torch.as_tensor(Z).to("cuda")
@@ -530,7 +556,12 @@ def main():
 
     ms_per_step = 1e3 * wall / args.steps
     value = args.steps / wall
-    work = gwindow_work(N, P, K, n_sets) if args.adjoint == "gwindow" else algorithmic_work(N, P, K, n_sets)
+    if args.forward == "hopkins":
+        work = hopkins_work(N, P, K, n_sets)
+    elif args.adjoint == "gwindow":
+        work = gwindow_work(N, P, K, n_sets)
+    else:
+        work = algorithmic_work(N, P, K, n_sets)
     phase_ms = {k: v[0] for k, v in prof.items()}
     dominant = max(phase_ms, key=lambda k: phase_ms[k])
     launches = prof[dominant][1]
@@ -550,6 +581,9 @@ def main():
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None}
     dtype = "f32" if args.precision == "fp32" else "bf16x3"
     kname, ksrc = KERNELS.get((dominant, dtype), (dominant, ()))
+    if (dominant == "adjoint" and args.adjoint == "gwindow") or (dominant == "image" and args.forward == "hopkins"):
+        # other kernels than the field forms': the phase is named, no counter summary applies
+        kname, ksrc = dominant, ()
     roof["kernel"] = kname
     roof["phase"] = dominant
     roof["avg_launch_ms"] = round(avg_ms, 4)
@@ -573,6 +607,8 @@ def main():
                                                flags=ilt.ILT_FLAG_GWINDOW_ADJOINT)
             ctxs["bf16x3_gwindow"] = ilt.Context(H, w, N, precision=ilt.ILT_BF16X3,
                                                  flags=ilt.ILT_FLAG_GWINDOW_ADJOINT)
+            ctxs["fp32_hopkins"] = ilt.Context(H, w, N, precision=ilt.ILT_FP32,
+                                               flags=ilt.ILT_FLAG_GWINDOW_ADJOINT | ilt.ILT_FLAG_HOPKINS_FORWARD)
         if not args.no_autotune:
             for c in ctxs.values():
                 if c is not ctx:
@@ -581,7 +617,7 @@ def main():
         if args.workload == "c1":
             ttt["develset"] = develset_ttt(range(args.ttt_seeds),
                                            range(args.develset_seeds) if args.develset_seeds > 0 else None)
-            for form in ("fp32_gwindow", "bf16x3", "bf16x3_gwindow"):
+            for form in ("fp32_gwindow", "bf16x3", "bf16x3_gwindow", "fp32_hopkins"):
                 if ttt["develset"] and ttt["median_ms"].get("fp32") and \
                         (ttt["develset"].get(form) or {}).get("median_ms_develset"):
                     ttt["develset_%s_speedup_vs_plain" % form] = round(
@@ -623,7 +659,7 @@ def main():
                             args.workload, N, N, desc["optics"]["pitch_nm"], K, P, P, n_sets,
                             len(prm["corners"]), prm["reinit_every"]),
             "N": N, "P": P, "K": K, "n_sets": n_sets, "corners": len(prm["corners"]), "seed": args.seed,
-            "adjoint": args.adjoint,
+            "adjoint": args.adjoint, "forward": args.forward,
         },
         "roofline": roof,
         "cpu_baseline": cpu,

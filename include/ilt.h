@@ -75,7 +75,15 @@ enum {
      * replaces the K adjoint field transforms, and no fields are stored or
      * recomputed.  Implies no field store (ILT_FLAG_RECOMPUTE_FIELDS is
      * then irrelevant). */
-    ILT_FLAG_GWINDOW_ADJOINT = 2
+    ILT_FLAG_GWINDOW_ADJOINT = 2,
+    /* Compute the aerial image through its spectrum on the (2P-1)^2
+     * difference window (the TCC form of the SOCS sum, Sec. II-B; exact up to
+     * rounding): Ihat(D) = sum_k w_k N^-4 sum_f U_k(f + D) conj(U_k(f)) with
+     * U_k = H_k . S, then I(r) = sum_D Ihat(D) exp(+2 pi i D.r / N).  One
+     * pruned inverse transform per kernel set replaces the K field
+     * transforms.  Requires ILT_FLAG_GWINDOW_ADJOINT (no fields are formed)
+     * and ILT_FP32; ILT_EINVAL otherwise. */
+    ILT_FLAG_HOPKINS_FORWARD = 4
 };
 
 /* Optical model, read at create time and copied to the device. */

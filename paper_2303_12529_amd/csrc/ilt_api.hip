@@ -141,7 +141,8 @@ void free_ctx(ilt_ctx *c) {
                     c->tl, c->tb, c->tbs, c->tba, c->ta4, c->ar, c->ai, c->H, c->sw, c->coef, c->tlhl, c->tbhl, c->Yhl, c->Spart, c->S, c->Est, c->Y, c->Tg,
                     c->I, c->G, c->g, c->phi2, c->Wpart, c->W, c->edt_scratch, c->part, c->scal, c->phib,
                     c->tgtb,
-                    c->tbQ, c->arQ, c->aiQ, c->Ghat, c->Ugw, c->Vpart, c->g_prev, c->dcg};
+                    c->tbQ, c->arQ, c->aiQ, c->Ghat, c->Ugw, c->Vpart, c->g_prev, c->dcg,
+                    c->tlQ, c->Tq, c->Ipart, c->Ihat};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     delete c;
@@ -271,8 +272,11 @@ extern "C" int ilt_create(ilt_ctx **out, const ilt_optics *o, int max_batch, voi
         return fail(ILT_EUNSUPPORTED, "precision %d not built", o->precision);
     if (o->precision == ILT_FP64 && N > ILT_FP64_MAX_N)
         return fail(ILT_EUNSUPPORTED, "ILT_FP64 contexts are built for N <= %d", ILT_FP64_MAX_N);
-    if (o->flags & ~(ILT_FLAG_RECOMPUTE_FIELDS | ILT_FLAG_GWINDOW_ADJOINT))
+    if (o->flags & ~(ILT_FLAG_RECOMPUTE_FIELDS | ILT_FLAG_GWINDOW_ADJOINT | ILT_FLAG_HOPKINS_FORWARD))
         return fail(ILT_EINVAL, "unknown flags 0x%x", o->flags);
+    if ((o->flags & ILT_FLAG_HOPKINS_FORWARD) &&
+        (!(o->flags & ILT_FLAG_GWINDOW_ADJOINT) || o->precision != ILT_FP32))
+        return fail(ILT_EINVAL, "ILT_FLAG_HOPKINS_FORWARD needs ILT_FLAG_GWINDOW_ADJOINT and ILT_FP32");
     if (!o->h_kernels || !o->h_weights) return fail(ILT_EINVAL, "kernels or weights are null");
     for (int i = 0; i < ns * K; ++i)
         if (!(o->h_weights[i] >= 0.0) || !std::isfinite(o->h_weights[i]))
@@ -293,6 +297,7 @@ extern "C" int ilt_create(ilt_ctx **out, const ilt_optics *o, int max_batch, voi
     c->NZ = 32 * c->FB + 16 * c->MIX;
     c->AP = round_up(P, 16);
     c->gwin = (o->flags & ILT_FLAG_GWINDOW_ADJOINT) ? 1 : 0;
+    c->hop = (o->flags & ILT_FLAG_HOPKINS_FORWARD) ? 1 : 0;
     c->Q = 2 * P - 1;
     c->FBQ = c->Q / 16;
     c->MIXQ = (c->Q % 16) != 0 && (c->Q % 16) <= 8;
@@ -417,6 +422,12 @@ extern "C" int ilt_create(ilt_ctx **out, const ilt_optics *o, int max_batch, voi
         ALLOC(tbQ, tbQ.size());
         ALLOC(arQ, arQ.size());
         ALLOC(aiQ, aiQ.size());
+        if (c->hop) {
+            ALLOC(tlQ, (size_t)HOP_KP * Np);
+            ALLOC(Tq, (size_t)ns * HOP_KP * Np);
+            ALLOC(Ipart, (size_t)ns * K * P * Q);
+            ALLOC(Ihat, (size_t)ns * Q * Q + (size_t)ns * P * Q);
+        }
         ALLOC(Ghat, (size_t)ns * Q * Q);
         // the correlation GEMM: at most two 4-wave blocks per compute unit
         int ncu = 256;
@@ -491,6 +502,18 @@ extern "C" int ilt_create(ilt_ctx **out, const ilt_optics *o, int max_batch, voi
     if (e == hipSuccess && c->gwin) {
         const std::vector<float> f = spectrum_fragments(tbQ.data(), Np, c->NZQ);
         e = hipMemcpy(c->tbQ, f.data(), f.size() * 4, hipMemcpyHostToDevice);
+        if (e == hipSuccess && c->hop) {
+            // image-side table of the difference window: rows Re A_Q, Im A_Q, zero
+            std::vector<float> tq((size_t)HOP_KP * Np, 0.f);
+            for (int a = 0; a < c->Q; ++a)
+                for (int y = 0; y < Np; ++y) {
+                    tq[(size_t)a * Np + y] = arQ[(size_t)a * Np + y];
+                    tq[(size_t)(c->Q + a) * Np + y] = aiQ[(size_t)a * Np + y];
+                }
+            e = hipMemcpy(c->tlQ, tq.data(), tq.size() * 4, hipMemcpyHostToDevice);
+            // the window rows past 2Q are read as zero by the image kernel
+            if (e == hipSuccess) e = hipMemset(c->Tq, 0, (size_t)ns * HOP_KP * Np * 4);
+        }
         if (e == hipSuccess) e = hipMemcpy(c->arQ, arQ.data(), arQ.size() * 4, hipMemcpyHostToDevice);
         if (e == hipSuccess) e = hipMemcpy(c->aiQ, aiQ.data(), aiQ.size() * 4, hipMemcpyHostToDevice);
     }
@@ -560,6 +583,11 @@ extern "C" int litho_forward(ilt_ctx *c, const float *d_mask, int set, float *d_
     if ((r = check_ptr(d_aerial, "d_aerial"))) return r;
     if (set < 0 || set >= c->n_sets) return fail(ILT_EINVAL, "set %d outside [0, %d)", set, c->n_sets);
     HIPCHK(launch_spectrum(c, d_mask, 0));
+    if (c->hop) {
+        HIPCHK(launch_hopkins_spectrum(c, set, set + 1));
+        HIPCHK(launch_hopkins_image(c, set, set + 1, d_aerial));
+        return ILT_OK;
+    }
     HIPCHK(launch_make_Y(c, set, set + 1));
     if (c->precision == ILT_BF16X3) {
         HIPCHK(launch_image_b3(c, set, set + 1, d_aerial));
@@ -576,6 +604,11 @@ extern "C" int litho_forward_phi(ilt_ctx *c, const float *d_phi, int set, float 
     if ((r = check_ptr(d_aerial, "d_aerial"))) return r;
     if (set < 0 || set >= c->n_sets) return fail(ILT_EINVAL, "set %d outside [0, %d)", set, c->n_sets);
     HIPCHK(launch_spectrum(c, d_phi, 1));
+    if (c->hop) {
+        HIPCHK(launch_hopkins_spectrum(c, set, set + 1));
+        HIPCHK(launch_hopkins_image(c, set, set + 1, d_aerial));
+        return ILT_OK;
+    }
     HIPCHK(launch_make_Y(c, set, set + 1));
     if (c->precision == ILT_BF16X3) {
         HIPCHK(launch_image_b3(c, set, set + 1, d_aerial));
@@ -769,11 +802,13 @@ int enqueue_solve(ilt_ctx *c, const unsigned char *d_target, float *d_phi, const
         }
         {
             PhaseTimer t(c, 1);
-            HIPCHK(launch_make_Y(c, slo, shi));
+            if (c->hop) HIPCHK(launch_hopkins_spectrum(c, slo, shi));
+            else HIPCHK(launch_make_Y(c, slo, shi));
         }
         {
             PhaseTimer t(c, 2);
-            if (b3) HIPCHK(launch_image_b3(c, slo, shi, c->I + (size_t)slo * npix));
+            if (c->hop) HIPCHK(launch_hopkins_image(c, slo, shi, c->I + (size_t)slo * npix));
+            else if (b3) HIPCHK(launch_image_b3(c, slo, shi, c->I + (size_t)slo * npix));
             else HIPCHK(launch_image_to(c, slo, shi, c->I + (size_t)slo * npix, stored));
         }
         {
@@ -816,11 +851,16 @@ int enqueue_solve(ilt_ctx *c, const unsigned char *d_target, float *d_phi, const
     if (cur != d_phi) HIPCHK(launch_copy(c, d_phi, cur, npix * c->ncur));
     // final metrics of [phi_T <= 0]
     HIPCHK(launch_spectrum(c, d_phi, 1));
-    HIPCHK(launch_make_Y(c, slo, shi));
-    if (b3) {
-        HIPCHK(launch_image_b3(c, slo, shi, c->I + (size_t)slo * npix));
+    if (c->hop) {
+        HIPCHK(launch_hopkins_spectrum(c, slo, shi));
+        HIPCHK(launch_hopkins_image(c, slo, shi, c->I + (size_t)slo * npix));
     } else {
-        HIPCHK(launch_image_to(c, slo, shi, c->I + (size_t)slo * npix, 0));
+        HIPCHK(launch_make_Y(c, slo, shi));
+        if (b3) {
+            HIPCHK(launch_image_b3(c, slo, shi, c->I + (size_t)slo * npix));
+        } else {
+            HIPCHK(launch_image_to(c, slo, shi, c->I + (size_t)slo * npix, 0));
+        }
     }
     HIPCHK(launch_resist(c, c->I, d_target, ra, c->G, pr));
     HIPCHK(launch_finish_resist(c, pr, resist_blocks(c), c->scal, nullptr));

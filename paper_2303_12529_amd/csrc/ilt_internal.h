@@ -39,6 +39,9 @@
 
 #define ILT_MAX_N 4096
 #define ILT_MAX_P 35
+// rows of the difference window's image-side table and window rows (the TCC
+// form of the image): 2 (2 ILT_MAX_P - 1) = 138 rounded up to 16
+#define HOP_KP 144
 #define ILT_MAX_K 64
 #define ILT_MAX_SETS 4
 #define ILT_TRACE_W 8
@@ -93,6 +96,11 @@ struct ilt_ctx {
     float2 *Ghat;      // [n_sets][Q][Q]
     float *Ugw;        // [n_sets][Fpad][NC] U_k = H_k . S as real columns (Fpad = P^2 rounded up to 4, NC = 2K rounded up to 16)
     double2 *Vpart;    // [gw_groups][n_sets][P][P] partial sums of W over ranges of window rows
+    int hop;           // ILT_FLAG_HOPKINS_FORWARD: the image through its difference-window spectrum
+    float *tlQ;        // [HOP_KP][Np] image-side table of the difference window (rows Re, Im, zero)
+    float *Tq;         // [n_sets][HOP_KP][Np] window rows of each set's image (rows >= 2Q stay zero)
+    double2 *Ipart;    // [n_sets][K][P][Q] per-kernel image spectra, rows Da >= 0
+    float2 *Ihat;      // [n_sets][Q][Q] image spectra on the difference window, then [n_sets][P][Q] scratch
     int gw_groups;     // ranges the window sum is split into (grid.y of the correlation GEMM)
 
     // FP64 form (ILT_FP64 contexts only)
@@ -195,6 +203,8 @@ hipError_t launch_image_b3(ilt_ctx *c, int set_lo, int set_hi, float *out);
 hipError_t launch_adjoint_b3(ilt_ctx *c, const float *G, size_t g_set_stride, int set_lo, int set_hi);
 // G-window adjoint: W for sets [set_lo, set_hi) directly (no window_sum)
 hipError_t launch_adjoint_gwindow(ilt_ctx *c, const float *G, size_t g_set_stride, int set_lo, int set_hi);
+hipError_t launch_hopkins_spectrum(ilt_ctx *c, int set_lo, int set_hi);
+hipError_t launch_hopkins_image(ilt_ctx *c, int set_lo, int set_hi, float *out);
 // conjugate gradient: d = g + beta d, g_prev = g (beta = 0 when first), and the
 // block maxima of |d| into maxpart for the CFL step; returns that block count
 int launch_cg(ilt_ctx *c, int first, double *part, double *maxpart, hipError_t *err);

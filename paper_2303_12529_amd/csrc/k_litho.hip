@@ -194,14 +194,14 @@ __global__ __launch_bounds__(1024) void k_psum(const T2 *__restrict__ part, int 
 // per block, JB kernels per block; each thread keeps the twiddles of its
 // column in registers and reuses them for the block's JB kernels.
 // --------------------------------------------------------------------------
-template <int COLS, int JB>
+template <int COLS, int JB, int WS = ILT_MAX_P>
 __global__ __launch_bounds__(256) void k_window_rows(const float2 *__restrict__ H, const float2 *__restrict__ S,
                                                      const float *__restrict__ scale, float scale_c,
                                                      const float *__restrict__ ar, const float *__restrict__ ai,
                                                      int P, int KP, int Np, int nj, int set_lo,
                                                      float *__restrict__ out, int zs, size_t s_cs, size_t out_cs) {
     constexpr int RG = 256 / COLS;
-    __shared__ float2 U[JB][ILT_MAX_P * ILT_MAX_P];
+    __shared__ float2 U[JB][WS * WS];
     // grid.z = clips x zs window slices; every clip has its own S and out
     const int clip = blockIdx.z / zs;
     S += clip * s_cs;
@@ -212,7 +212,7 @@ __global__ __launch_bounds__(256) void k_window_rows(const float2 *__restrict__ 
     const int jn = min(JB, nj - j0);
     // U_j = H_j . S (or S itself): a thread's loads are issued before any
     // product is stored
-    constexpr int UPT = (ILT_MAX_P * ILT_MAX_P + 255) / 256;
+    constexpr int UPT = (WS * WS + 255) / 256;
     for (int jj = 0; jj < jn; ++jj) {
         float2 sv[UPT], hv[UPT];
 #pragma unroll
@@ -233,9 +233,9 @@ __global__ __launch_bounds__(256) void k_window_rows(const float2 *__restrict__ 
             }
         }
     }
-    float cr[ILT_MAX_P], ci[ILT_MAX_P];
+    float cr[WS], ci[WS];
 #pragma unroll
-    for (int b = 0; b < ILT_MAX_P; ++b) {
+    for (int b = 0; b < WS; ++b) {
         cr[b] = b < P ? ar[(size_t)b * Np + x] : 0.f;
         ci[b] = b < P ? ai[(size_t)b * Np + x] : 0.f;
     }
@@ -247,7 +247,7 @@ __global__ __launch_bounds__(256) void k_window_rows(const float2 *__restrict__ 
         for (int a = ag; a < P; a += RG) {
             float yr = 0.f, yi = 0.f;
 #pragma unroll
-            for (int b = 0; b < ILT_MAX_P; ++b) {
+            for (int b = 0; b < WS; ++b) {
                 if (b < P) {
                     const float2 u = U[jj][a * P + b];
                     // u * conj(A) = (ur + i ui)(c - i sn)
@@ -381,6 +381,7 @@ __global__ __launch_bounds__(256) void k_make_y(const float2 *__restrict__ H, co
 // --------------------------------------------------------------------------
 // Image: per 16x16 block, E_j^T = Y_j^T L^T with Re E = L1 Y, Im E = L2 Y.
 //   MODE 0: out = sum_j |E_j|^2      (aerial image of one kernel set)
+//   MODE 2: out = Re E_0             (an image from its window rows)
 //   MODE 1: out = Re E_0             (gradient back-transform), plus the
 //           block maximum of |out| into maxpart[block].
 //   STORE:  also write every E_j fragment to Est in the accumulator layout
@@ -401,7 +402,8 @@ __global__ __launch_bounds__(256, 2) void k_image(const float *__restrict__ tl, 
     // Y_j tiles, KP rows of LDW floats (16 data units of 16 bytes + 4 pad
     // units), rounded up to whole 64-unit copies
     constexpr int RU = LDW / 4, NYI = (KP * RU + 63) / 64, NYT = (NYI + 3) / 4;
-    __shared__ __align__(16) float Ysm[2][NYI * 256];
+    constexpr int NBUF = MODE == 0 ? 2 : 1;        // MODE 1, 2: one tile (nj = 1)
+    __shared__ __align__(16) float Ysm[NBUF][NYI * 256];
     __shared__ float wmax[4];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int l16 = lane & 15, lq = lane >> 4;
@@ -451,8 +453,8 @@ __global__ __launch_bounds__(256, 2) void k_image(const float *__restrict__ tl, 
     ilt_dev::wait_copies();
     __syncthreads();
     for (int j = 0; j < nj; ++j) {
-        const int buf = j & 1;
-        if (j + 1 < nj) copy_y(j + 1, buf ^ 1);
+        const int buf = NBUF == 2 ? (j & 1) : 0;
+        if (NBUF == 2 && j + 1 < nj) copy_y(j + 1, buf ^ 1);
         f4 er[4][2], ei[4][2];
 #pragma unroll
         for (int xb = 0; xb < 4; ++xb)
@@ -844,6 +846,81 @@ __global__ __launch_bounds__(256) void k_gwindow_U(const float2 *__restrict__ H,
     U[(size_t)srel * Fpad * NC + id] = (float)v;
 }
 
+// --------------------------------------------------------------------------
+// Image spectrum on the difference window, the TCC form of the SOCS sum:
+//   Ihat[D] = sum_k sw_k^2 sum_f U_k[f + D] conj(U_k[f]),  U_k = H_k . S,
+// D = (Da, Db) in [-(P-1), P-1]^2 (stored at D + P - 1), sw_k^2 = w_k / N^4,
+// so that I(r) = sum_D Ihat[D] exp(+2 pi i D.r / N) is the SOCS image.
+// Ihat[-D] = conj(Ihat[D]) (I is real), so only the rows Da >= 0 are formed
+// (k_hopkins_fill mirrors the others).  Block = (four rows Da, one per
+// wave; kernel k; set); lane l takes the columns Db = 2 l - (P-1) and the
+// next one.  U_k sits in LDS with P - 1 zero columns on each side, so that
+// every shifted read is in range and the lanes run the same loop; the
+// unshifted factor is the same for all lanes (one broadcast read), and the
+// shifted one slides along the row in registers.  Each window row's
+// products (<= P terms) are summed in FP32, the rows in FP64; the kernels'
+// partials are summed in FP64 afterwards, in a fixed order.
+// --------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_hopkins_ihat(const float2 *__restrict__ H, const float2 *__restrict__ S,
+                                                      const float *__restrict__ sw, int P, int K, int set_lo,
+                                                      double2 *__restrict__ part) {
+    constexpr int WMAX = 3 * ILT_MAX_P - 1;
+    __shared__ float2 U[ILT_MAX_P * WMAX];
+    const int Q = 2 * P - 1, PP = P * P, W = 3 * P - 1;   // one more zero column for the pair's second
+    const int lane = threadIdx.x & 63, da = 4 * blockIdx.x + (threadIdx.x >> 6);
+    const int k = blockIdx.y, srel = blockIdx.z, s = set_lo + srel;
+    for (int e = threadIdx.x; e < P * W; e += 256) U[e] = make_float2(0.f, 0.f);
+    __syncthreads();
+    const float2 *Hk = H + ((size_t)s * K + k) * PP;
+    for (int f = threadIdx.x; f < PP; f += 256) {
+        const int a = f / P, b = f - (f / P) * P;
+        const float2 h = Hk[f], sv = S[f];
+        U[a * W + (P - 1) + b] = make_float2(h.x * sv.x - h.y * sv.y, h.x * sv.y + h.y * sv.x);
+    }
+    __syncthreads();
+    if (da >= P || 2 * lane >= Q) return;                   // no barrier follows
+    const double w2 = (double)sw[(size_t)s * K + k] * (double)sw[(size_t)s * K + k];
+    // column pair t0 = 2 lane, t0 + 1 (index Db + P - 1); the read of
+    // U[a + Da][b + Db] is at column b + t0 of the padded row
+    const int t0 = 2 * lane;
+    double r0 = 0.0, i0 = 0.0, r1 = 0.0, i1 = 0.0;
+    for (int a = 0; a + da < P; ++a) {
+        const float2 *xs = &U[(a + da) * W + t0], *ys = &U[a * W + (P - 1)];
+        float re0 = 0.f, im0 = 0.f, re1 = 0.f, im1 = 0.f;
+        float2 x0 = xs[0];
+        for (int b = 0; b < P; ++b) {
+            const float2 x1 = xs[b + 1], y = ys[b];        // x conj(y)
+            re0 = fmaf(x0.x, y.x, fmaf(x0.y, y.y, re0));
+            im0 = fmaf(x0.y, y.x, fmaf(-x0.x, y.y, im0));
+            re1 = fmaf(x1.x, y.x, fmaf(x1.y, y.y, re1));
+            im1 = fmaf(x1.y, y.x, fmaf(-x1.x, y.y, im1));
+            x0 = x1;
+        }
+        r0 += (double)re0; i0 += (double)im0;
+        r1 += (double)re1; i1 += (double)im1;
+    }
+    double2 *dst = part + (((size_t)srel * K + k) * P + da) * Q;
+    dst[t0] = make_double2(w2 * r0, w2 * i0);
+    if (t0 + 1 < Q) dst[t0 + 1] = make_double2(w2 * r1, w2 * i1);
+}
+
+// Full difference-window spectra from the rows Da >= 0:
+// Ihat[Da][Db] = conj(Ihat[-Da][-Db]) for Da < 0.  Grid (Q, n_sets).
+__global__ __launch_bounds__(128) void k_hopkins_fill(const float2 *__restrict__ half, int P,
+                                                      float2 *__restrict__ ihat) {
+    const int Q = 2 * P - 1, r = blockIdx.x, c = threadIdx.x;
+    if (c >= Q) return;
+    const float2 *h = half + (size_t)blockIdx.y * P * Q;
+    float2 v;
+    if (r >= P - 1) {
+        v = h[(size_t)(r - (P - 1)) * Q + c];
+    } else {
+        v = h[(size_t)(P - 1 - r) * Q + (Q - 1 - c)];
+        v.y = -v.y;
+    }
+    ihat[(size_t)blockIdx.y * Q * Q + (size_t)r * Q + c] = v;
+}
+
 // Block-wide copy global -> LDS with UNR independent loads in flight per
 // thread (a plain copy loop waits for each load before the next).
 template <int UNR, typename T>
@@ -1137,6 +1214,40 @@ hipError_t launch_gradient(ilt_ctx *c, float *g_out, double *maxpart) {
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     return image_dispatch<1, false>(c, c->Tg, 1, 0, 1, g_out, maxpart, cs_tg(c), cs_npix(c));
+}
+
+// TCC-form image (ILT_FLAG_HOPKINS_FORWARD): the sets' spectra on the
+// difference window, then for each set its window rows T = Ihat conj(A_Q)
+// and the image Re(A_Q^H T) on the matrix cores (the rows of a set are one
+// window slice of the row kernel and one image of the image kernel).
+hipError_t launch_hopkins_spectrum(ilt_ctx *c, int set_lo, int set_hi) {
+    if (!c->hop) return hipErrorInvalidValue;
+    const int P = c->P, Q = c->Q, ns = set_hi - set_lo;
+    k_hopkins_ihat<<<dim3((P + 3) / 4, c->K, ns), 256, 0, c->stream>>>(c->H, c->S, c->sw, P, c->K, set_lo,
+                                                                          c->Ipart);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    // rows Da >= 0 summed over the kernels into the second half of Ihat's
+    // storage as scratch, then both halves written in place of the first
+    float2 *half = c->Ihat + (size_t)ns * Q * Q;
+    k_psum<double2><<<dim3((P * Q + 15) / 16, ns), 1024, 0, c->stream>>>(c->Ipart, c->K, P * Q, half);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    k_hopkins_fill<<<dim3(Q, ns), 128, 0, c->stream>>>(half, P, c->Ihat);
+    return hipGetLastError();
+}
+
+hipError_t launch_hopkins_image(ilt_ctx *c, int set_lo, int set_hi, float *out) {
+    if (!c->hop) return hipErrorInvalidValue;
+    const int Q = c->Q, ns = set_hi - set_lo;
+    k_window_rows<16, 1, 2 * ILT_MAX_P - 1><<<dim3(c->Np / 16, 1, ns), 256, 0, c->stream>>>(
+        nullptr, c->Ihat, nullptr, 1.f, c->arQ, c->aiQ, Q, HOP_KP, c->Np, 1, 0, c->Tq, 1, (size_t)Q * Q,
+        (size_t)HOP_KP * c->Np);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    (void)set_lo;
+    k_image<HOP_KP, 2, false><<<dim3(c->Np / 64, c->Np / 128, ns), 256, 0, c->stream>>>(
+        c->tlQ, c->Tq, 1, c->N, c->Np, 0, out, nullptr, nullptr, ns, 0, 0, 0, 0);
+    return hipGetLastError();
 }
 
 hipError_t launch_adjoint_gwindow(ilt_ctx *c, const float *G, size_t g_set_stride, int set_lo, int set_hi) {

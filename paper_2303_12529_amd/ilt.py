@@ -23,6 +23,7 @@ ILT_BF16X3 = 1
 ILT_FP64 = 2
 ILT_FLAG_RECOMPUTE_FIELDS = 1
 ILT_FLAG_GWINDOW_ADJOINT = 2
+ILT_FLAG_HOPKINS_FORWARD = 4
 TRACE_W = 8
 TRACE_COLUMNS = ("i", "loss", "l2", "pvb", "flips", "max_g", "dt", "t_ns")
 PHASES = ("spectrum", "window_rows", "image", "resist", "adjoint", "gradient", "levelset_step", "reinit")

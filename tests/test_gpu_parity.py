@@ -69,7 +69,7 @@ FWD_CASES = [
 ]
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3", "hopkins"])
 @pytest.mark.parametrize("N,P,K,kind", FWD_CASES)
 def test_litho_forward_parity(ilt, N, P, K, kind, prec):
     _say("forward", N, P, K, kind, prec)
@@ -82,7 +82,10 @@ def test_litho_forward_parity(ilt, N, P, K, kind, prec):
         M = rng.uniform(size=(N, N)).astype(np.float32)
     else:
         M = random_mask(N, 0.3, seed=N).astype(np.float32)
-    ctx = ilt.Context(H, w, N, precision=ilt.ILT_BF16X3 if prec == "bf16x3" else ilt.ILT_FP32)
+    if prec == "hopkins":        # the image through its difference-window spectrum
+        ctx = ilt.Context(H, w, N, flags=ilt.ILT_FLAG_GWINDOW_ADJOINT | ilt.ILT_FLAG_HOPKINS_FORWARD)
+    else:
+        ctx = ilt.Context(H, w, N, precision=ilt.ILT_BF16X3 if prec == "bf16x3" else ilt.ILT_FP32)
     out = ctx.litho_forward(_dev(M), 0).cpu().numpy()
     torch.cuda.synchronize()
     ref = o_litho.aerial_image(M.astype(np.float64), H[0], w[0])
@@ -140,6 +143,31 @@ def test_litho_adjoint_parity(ilt, N, P, K, flags):
     _say("  rel err", err)
     assert err <= (2e-2 if flags == "bf16x3" else 1e-4)
 
+
+
+# the TCC-form image sums kernels in groups of four: every group count up to
+# K = 64, two kernel sets (each set its own spectrum, rows and image)
+@pytest.mark.parametrize("N,P,K", [(96, 9, 25), (128, 15, 48), (128, 35, 64), (67, 9, 3)])
+def test_hopkins_forward_many_kernels_two_sets(ilt, N, P, K):
+    _say("hopkins forward", N, P, K)
+    H, w = _rand_kernels(2, K, P, seed=K + 11)
+    M = random_mask(N, 0.3, seed=K + 1).astype(np.float32)
+    ctx = ilt.Context(H, w, N, flags=ilt.ILT_FLAG_GWINDOW_ADJOINT | ilt.ILT_FLAG_HOPKINS_FORWARD)
+    for s in range(2):
+        out = ctx.litho_forward(_dev(M), s).cpu().numpy()
+        ref = o_litho.hopkins_aerial_image(M.astype(np.float64), H[s], w[s])
+        err = np.abs(out - ref).max() / np.abs(ref).max()
+        _say("  set", s, "rel err", err)
+        assert err <= 1e-5
+
+
+def test_hopkins_flag_needs_gwindow_fp32(ilt):
+    H, w = _rand_kernels(1, 2, 3, seed=1)
+    for prec, flags in ((ilt.ILT_FP32, ilt.ILT_FLAG_HOPKINS_FORWARD),
+                        (ilt.ILT_BF16X3, ilt.ILT_FLAG_HOPKINS_FORWARD | ilt.ILT_FLAG_GWINDOW_ADJOINT)):
+        with pytest.raises(ilt.IltError) as ei:
+            ilt.Context(H, w, 64, precision=prec, flags=flags)
+        assert ei.value.code == ilt.ILT_EINVAL
 
 
 # the G-window correlation GEMM holds 2K real columns in tiles of 16: these
