@@ -423,10 +423,10 @@ extern "C" int ilt_create(ilt_ctx **out, const ilt_optics *o, int max_batch, voi
         ALLOC(arQ, arQ.size());
         ALLOC(aiQ, aiQ.size());
         if (c->hop) {
-            ALLOC(tlQ, (size_t)HOP_KP * Np);
-            ALLOC(Tq, (size_t)ns * HOP_KP * Np);
+            ALLOC(tlQ, (size_t)KP * Np);
+            ALLOC(Tq, (size_t)ns * KP * Np);
             ALLOC(Ipart, (size_t)ns * K * P * Q);
-            ALLOC(Ihat, (size_t)ns * Q * Q + (size_t)ns * P * Q);
+            ALLOC(Ihat, (size_t)ns * P * Q);
         }
         ALLOC(Ghat, (size_t)ns * Q * Q);
         // the correlation GEMM: at most two 4-wave blocks per compute unit
@@ -503,16 +503,20 @@ extern "C" int ilt_create(ilt_ctx **out, const ilt_optics *o, int max_batch, voi
         const std::vector<float> f = spectrum_fragments(tbQ.data(), Np, c->NZQ);
         e = hipMemcpy(c->tbQ, f.data(), f.size() * 4, hipMemcpyHostToDevice);
         if (e == hipSuccess && c->hop) {
-            // image-side table of the difference window: rows Re A_Q, Im A_Q, zero
-            std::vector<float> tq((size_t)HOP_KP * Np, 0.f);
-            for (int a = 0; a < c->Q; ++a)
+            // image-side table of the rows Da >= 0 of the difference window:
+            // rows Re A_Q, Im A_Q at frequency Da, doubled for Da > 0 (the
+            // rows Da < 0 contribute the conjugates), then zero rows
+            std::vector<float> tq((size_t)KP * Np, 0.f);
+            for (int d = 0; d < P; ++d) {
+                const float f = d ? 2.f : 1.f;
                 for (int y = 0; y < Np; ++y) {
-                    tq[(size_t)a * Np + y] = arQ[(size_t)a * Np + y];
-                    tq[(size_t)(c->Q + a) * Np + y] = aiQ[(size_t)a * Np + y];
+                    tq[(size_t)d * Np + y] = f * arQ[(size_t)(P - 1 + d) * Np + y];
+                    tq[(size_t)(P + d) * Np + y] = f * aiQ[(size_t)(P - 1 + d) * Np + y];
                 }
+            }
             e = hipMemcpy(c->tlQ, tq.data(), tq.size() * 4, hipMemcpyHostToDevice);
-            // the window rows past 2Q are read as zero by the image kernel
-            if (e == hipSuccess) e = hipMemset(c->Tq, 0, (size_t)ns * HOP_KP * Np * 4);
+            // the window rows past 2P are read as zero by the image kernel
+            if (e == hipSuccess) e = hipMemset(c->Tq, 0, (size_t)ns * KP * Np * 4);
         }
         if (e == hipSuccess) e = hipMemcpy(c->arQ, arQ.data(), arQ.size() * 4, hipMemcpyHostToDevice);
         if (e == hipSuccess) e = hipMemcpy(c->aiQ, aiQ.data(), aiQ.size() * 4, hipMemcpyHostToDevice);

@@ -39,9 +39,6 @@
 
 #define ILT_MAX_N 4096
 #define ILT_MAX_P 35
-// rows of the difference window's image-side table and window rows (the TCC
-// form of the image): 2 (2 ILT_MAX_P - 1) = 138 rounded up to 16
-#define HOP_KP 144
 #define ILT_MAX_K 64
 #define ILT_MAX_SETS 4
 #define ILT_TRACE_W 8
@@ -97,10 +94,10 @@ struct ilt_ctx {
     float *Ugw;        // [n_sets][Fpad][NC] U_k = H_k . S as real columns (Fpad = P^2 rounded up to 4, NC = 2K rounded up to 16)
     double2 *Vpart;    // [gw_groups][n_sets][P][P] partial sums of W over ranges of window rows
     int hop;           // ILT_FLAG_HOPKINS_FORWARD: the image through its difference-window spectrum
-    float *tlQ;        // [HOP_KP][Np] image-side table of the difference window (rows Re, Im, zero)
-    float *Tq;         // [n_sets][HOP_KP][Np] window rows of each set's image (rows >= 2Q stay zero)
+    float *tlQ;        // [KP][Np] image-side table of the rows Da >= 0 of the difference window
+    float *Tq;         // [n_sets][KP][Np] window rows of each set's image (rows >= 2P stay zero)
     double2 *Ipart;    // [n_sets][K][P][Q] per-kernel image spectra, rows Da >= 0
-    float2 *Ihat;      // [n_sets][Q][Q] image spectra on the difference window, then [n_sets][P][Q] scratch
+    float2 *Ihat;      // [n_sets][P][Q] image spectra, rows Da >= 0 of the difference window
     int gw_groups;     // ranges the window sum is split into (grid.y of the correlation GEMM)
 
     // FP64 form (ILT_FP64 contexts only)

@@ -189,7 +189,9 @@ __global__ __launch_bounds__(1024) void k_psum(const T2 *__restrict__ part, int 
 
 // --------------------------------------------------------------------------
 // Window -> rows: out[j][r][x] = scale_j * sum_b U_j[a][b] conj(A[b][x]),
-// U_j = H_j . S (or U = S when H is null); rows r = a (real), P + a (imag).
+// U_j = H_j . S (or U = S when H is null); rows r = a (real), PR + a (imag).
+// The window has PR rows of P columns (PR = P but for the image spectrum's
+// half window; H is used only with PR = P).
 // Grid (Np/COLS, ceil(n_j/JB), n_sets); COLS columns x 256/COLS row groups
 // per block, JB kernels per block; each thread keeps the twiddles of its
 // column in registers and reuses them for the block's JB kernels.
@@ -198,7 +200,7 @@ template <int COLS, int JB, int WS = ILT_MAX_P>
 __global__ __launch_bounds__(256) void k_window_rows(const float2 *__restrict__ H, const float2 *__restrict__ S,
                                                      const float *__restrict__ scale, float scale_c,
                                                      const float *__restrict__ ar, const float *__restrict__ ai,
-                                                     int P, int KP, int Np, int nj, int set_lo,
+                                                     int P, int PR, int KP, int Np, int nj, int set_lo,
                                                      float *__restrict__ out, int zs, size_t s_cs, size_t out_cs) {
     constexpr int RG = 256 / COLS;
     __shared__ float2 U[JB][WS * WS];
@@ -218,7 +220,7 @@ __global__ __launch_bounds__(256) void k_window_rows(const float2 *__restrict__ 
 #pragma unroll
         for (int u = 0; u < UPT; ++u) {
             const int e = threadIdx.x + 256 * u;
-            if (e < P * P) {
+            if (e < PR * P) {
                 sv[u] = S[e];
                 if (H) hv[u] = H[((size_t)s * nj + j0 + jj) * P * P + e];
             }
@@ -226,7 +228,7 @@ __global__ __launch_bounds__(256) void k_window_rows(const float2 *__restrict__ 
 #pragma unroll
         for (int u = 0; u < UPT; ++u) {
             const int e = threadIdx.x + 256 * u;
-            if (e < P * P) {
+            if (e < PR * P) {
                 float2 v = sv[u];
                 if (H) v = make_float2(hv[u].x * v.x - hv[u].y * v.y, hv[u].x * v.y + hv[u].y * v.x);
                 U[jj][e] = v;
@@ -244,7 +246,7 @@ __global__ __launch_bounds__(256) void k_window_rows(const float2 *__restrict__ 
         const int j = j0 + jj;
         const float sc = scale ? scale[(size_t)s * nj + j] : scale_c;
         float *o = out + ((size_t)(s * nj + j) * KP) * Np;
-        for (int a = ag; a < P; a += RG) {
+        for (int a = ag; a < PR; a += RG) {
             float yr = 0.f, yi = 0.f;
 #pragma unroll
             for (int b = 0; b < WS; ++b) {
@@ -256,7 +258,7 @@ __global__ __launch_bounds__(256) void k_window_rows(const float2 *__restrict__ 
                 }
             }
             o[(size_t)a * Np + x] = sc * yr;
-            o[(size_t)(P + a) * Np + x] = sc * yi;
+            o[(size_t)(PR + a) * Np + x] = sc * yi;
         }
     }
 }
@@ -852,7 +854,7 @@ __global__ __launch_bounds__(256) void k_gwindow_U(const float2 *__restrict__ H,
 // D = (Da, Db) in [-(P-1), P-1]^2 (stored at D + P - 1), sw_k^2 = w_k / N^4,
 // so that I(r) = sum_D Ihat[D] exp(+2 pi i D.r / N) is the SOCS image.
 // Ihat[-D] = conj(Ihat[D]) (I is real), so only the rows Da >= 0 are formed
-// (k_hopkins_fill mirrors the others).  Block = (four rows Da, one per
+// (the image uses them alone).  Block = (four rows Da, one per
 // wave; kernel k; set); lane l takes the columns Db = 2 l - (P-1) and the
 // next one.  U_k sits in LDS with P - 1 zero columns on each side, so that
 // every shifted read is in range and the lanes run the same loop; the
@@ -902,23 +904,6 @@ __global__ __launch_bounds__(256) void k_hopkins_ihat(const float2 *__restrict__
     double2 *dst = part + (((size_t)srel * K + k) * P + da) * Q;
     dst[t0] = make_double2(w2 * r0, w2 * i0);
     if (t0 + 1 < Q) dst[t0 + 1] = make_double2(w2 * r1, w2 * i1);
-}
-
-// Full difference-window spectra from the rows Da >= 0:
-// Ihat[Da][Db] = conj(Ihat[-Da][-Db]) for Da < 0.  Grid (Q, n_sets).
-__global__ __launch_bounds__(128) void k_hopkins_fill(const float2 *__restrict__ half, int P,
-                                                      float2 *__restrict__ ihat) {
-    const int Q = 2 * P - 1, r = blockIdx.x, c = threadIdx.x;
-    if (c >= Q) return;
-    const float2 *h = half + (size_t)blockIdx.y * P * Q;
-    float2 v;
-    if (r >= P - 1) {
-        v = h[(size_t)(r - (P - 1)) * Q + c];
-    } else {
-        v = h[(size_t)(P - 1 - r) * Q + (Q - 1 - c)];
-        v.y = -v.y;
-    }
-    ihat[(size_t)blockIdx.y * Q * Q + (size_t)r * Q + c] = v;
 }
 
 // Block-wide copy global -> LDS with UNR independent loads in flight per
@@ -1209,17 +1194,21 @@ hipError_t launch_gradient(ilt_ctx *c, float *g_out, double *maxpart) {
     // Tg = 2 W conj(A) in the row layout, then g = Re(A^H Tg)
     // one transform only: narrow column tiles so that the launch covers the chip
     dim3 grid(c->Np / 16, 1, c->ncur);
-    k_window_rows<16, 1><<<grid, 256, 0, c->stream>>>(nullptr, c->W, nullptr, 2.f, c->ar, c->ai, c->P, c->KP, c->Np,
+    k_window_rows<16, 1><<<grid, 256, 0, c->stream>>>(nullptr, c->W, nullptr, 2.f, c->ar, c->ai, c->P, c->P, c->KP, c->Np,
                                                       1, 0, c->Tg, 1, (size_t)c->P * c->P, cs_tg(c));
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     return image_dispatch<1, false>(c, c->Tg, 1, 0, 1, g_out, maxpart, cs_tg(c), cs_npix(c));
 }
 
-// TCC-form image (ILT_FLAG_HOPKINS_FORWARD): the sets' spectra on the
-// difference window, then for each set its window rows T = Ihat conj(A_Q)
-// and the image Re(A_Q^H T) on the matrix cores (the rows of a set are one
-// window slice of the row kernel and one image of the image kernel).
+// TCC-form image (ILT_FLAG_HOPKINS_FORWARD): the sets' spectra on the rows
+// Da >= 0 of the difference window, then for each set its window rows
+// R = Ihat conj(A_Q) over those rows and the image
+//   I = Re R_0 + 2 Re sum_{Da > 0} exp(+2 pi i Da y / N) R_Da,
+// since R_{-Da} = conj(R_Da) (Ihat(-D) = conj(Ihat(D))): the image-side
+// table tlH holds the rows Da >= 0 with the factor 2, so the image kernel
+// contracts 2P rows, not 2(2P-1) (a set's rows are one window slice of the
+// row kernel and one image of the image kernel).
 hipError_t launch_hopkins_spectrum(ilt_ctx *c, int set_lo, int set_hi) {
     if (!c->hop) return hipErrorInvalidValue;
     const int P = c->P, Q = c->Q, ns = set_hi - set_lo;
@@ -1227,26 +1216,26 @@ hipError_t launch_hopkins_spectrum(ilt_ctx *c, int set_lo, int set_hi) {
                                                                           c->Ipart);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    // rows Da >= 0 summed over the kernels into the second half of Ihat's
-    // storage as scratch, then both halves written in place of the first
-    float2 *half = c->Ihat + (size_t)ns * Q * Q;
-    k_psum<double2><<<dim3((P * Q + 15) / 16, ns), 1024, 0, c->stream>>>(c->Ipart, c->K, P * Q, half);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    k_hopkins_fill<<<dim3(Q, ns), 128, 0, c->stream>>>(half, P, c->Ihat);
+    k_psum<double2><<<dim3((P * Q + 15) / 16, ns), 1024, 0, c->stream>>>(c->Ipart, c->K, P * Q, c->Ihat);
     return hipGetLastError();
 }
 
 hipError_t launch_hopkins_image(ilt_ctx *c, int set_lo, int set_hi, float *out) {
     if (!c->hop) return hipErrorInvalidValue;
-    const int Q = c->Q, ns = set_hi - set_lo;
+    const int P = c->P, Q = c->Q, ns = set_hi - set_lo;
+    (void)set_lo;
     k_window_rows<16, 1, 2 * ILT_MAX_P - 1><<<dim3(c->Np / 16, 1, ns), 256, 0, c->stream>>>(
-        nullptr, c->Ihat, nullptr, 1.f, c->arQ, c->aiQ, Q, HOP_KP, c->Np, 1, 0, c->Tq, 1, (size_t)Q * Q,
-        (size_t)HOP_KP * c->Np);
+        nullptr, c->Ihat, nullptr, 1.f, c->arQ, c->aiQ, Q, P,
+        c->KP, c->Np, 1, 0, c->Tq, 1, (size_t)P * Q, (size_t)c->KP * c->Np);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    (void)set_lo;
-    k_image<HOP_KP, 2, false><<<dim3(c->Np / 64, c->Np / 128, ns), 256, 0, c->stream>>>(
-        c->tlQ, c->Tq, 1, c->N, c->Np, 0, out, nullptr, nullptr, ns, 0, 0, 0, 0);
+    const dim3 grid(c->Np / 64, c->Np / 128, ns);
+    switch (c->KP) {
+#define HIMG(KP_) case KP_: k_image<KP_, 2, false><<<grid, 256, 0, c->stream>>>(c->tlQ, c->Tq, 1, c->N, c->Np, 0, out, nullptr, nullptr, ns, 0, 0, 0, 0); break;
+        HIMG(8) HIMG(24) HIMG(40) HIMG(72)
+#undef HIMG
+        default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
