@@ -141,7 +141,7 @@ void free_ctx(ilt_ctx *c) {
                     c->tl, c->tb, c->tbs, c->tba, c->ta4, c->ar, c->ai, c->H, c->sw, c->coef, c->tlhl, c->tbhl, c->Yhl, c->Spart, c->S, c->Est, c->Y, c->Tg,
                     c->I, c->G, c->g, c->phi2, c->Wpart, c->W, c->edt_scratch, c->part, c->scal, c->phib,
                     c->tgtb,
-                    c->tbQ, c->arQ, c->aiQ, c->Ghat, c->Ugw, c->Vpart, c->g_prev, c->dcg,
+                    c->tbQ, c->arQ, c->aiQ, c->Ghat, c->Ghalf, c->Ugw, c->Vpart, c->g_prev, c->dcg,
                     c->tlQ, c->Tq, c->Ipart, c->Ihat};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
@@ -299,10 +299,6 @@ extern "C" int ilt_create(ilt_ctx **out, const ilt_optics *o, int max_batch, voi
     c->gwin = (o->flags & ILT_FLAG_GWINDOW_ADJOINT) ? 1 : 0;
     c->hop = (o->flags & ILT_FLAG_HOPKINS_FORWARD) ? 1 : 0;
     c->Q = 2 * P - 1;
-    c->FBQ = c->Q / 16;
-    c->MIXQ = (c->Q % 16) != 0 && (c->Q % 16) <= 8;
-    if ((c->Q % 16) > 8) c->FBQ += 1;
-    c->NZQ = 32 * c->FBQ + 16 * c->MIXQ;
     c->stream = static_cast<hipStream_t>(stream);
     if (hipGetDevice(&c->device) != hipSuccess) { free_ctx(c); return fail(ILT_EDEVICE, "hipGetDevice failed"); }
     const int Np = c->Np, KP = c->KP, NZ = c->NZ, FB = c->FB, AP = c->AP;
@@ -401,9 +397,11 @@ extern "C" int ilt_create(ilt_ctx **out, const ilt_optics *o, int max_batch, voi
     }
     std::vector<float> tbQ, arQ, aiQ;
     if (c->gwin) {
-        // tables of the difference window: f_a = a - (P - 1), a in [0, Q)
-        const int Q = c->Q, NZQ = c->NZQ, FBQ = c->FBQ;
-        tbQ.assign((size_t)Np * NZQ, 0.f);
+        // tables of the difference window: f_a = a - (P - 1), a in [0, Q);
+        // the column table holds the columns f >= 0 only (G is real, so its
+        // spectrum's other columns are conjugates), in the layout of P
+        const int Q = c->Q;
+        tbQ.assign((size_t)Np * NZ, 0.f);
         arQ.assign((size_t)Q * Np, 0.f);
         aiQ.assign((size_t)Q * Np, 0.f);
         for (int a = 0; a < Q; ++a) {
@@ -415,8 +413,10 @@ extern "C" int ilt_create(ilt_ctx **out, const ilt_optics *o, int max_batch, voi
                 const float cr = (float)std::cos(ang), sn = (float)std::sin(ang);
                 arQ[(size_t)a * Np + x] = cr;
                 aiQ[(size_t)a * Np + x] = sn;
-                tbQ[(size_t)x * NZQ + win_re(a, FBQ)] = cr;
-                tbQ[(size_t)x * NZQ + win_im(a, FBQ)] = sn;
+                if (f >= 0) {
+                    tbQ[(size_t)x * NZ + win_re((int)f, FB)] = cr;
+                    tbQ[(size_t)x * NZ + win_im((int)f, FB)] = sn;
+                }
             }
         }
         ALLOC(tbQ, tbQ.size());
@@ -429,6 +429,7 @@ extern "C" int ilt_create(ilt_ctx **out, const ilt_optics *o, int max_batch, voi
             ALLOC(Ihat, (size_t)ns * P * Q);
         }
         ALLOC(Ghat, (size_t)ns * Q * Q);
+        ALLOC(Ghalf, (size_t)ns * Q * P);
         // the correlation GEMM: at most two 4-wave blocks per compute unit
         int ncu = 256;
         if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device) != hipSuccess || ncu < 1)
@@ -500,7 +501,7 @@ extern "C" int ilt_create(ilt_ctx **out, const ilt_optics *o, int max_batch, voi
         if (e == hipSuccess) e = hipMemcpy(c->w64, w64h.data(), w64h.size() * sizeof(double), hipMemcpyHostToDevice);
     }
     if (e == hipSuccess && c->gwin) {
-        const std::vector<float> f = spectrum_fragments(tbQ.data(), Np, c->NZQ);
+        const std::vector<float> f = spectrum_fragments(tbQ.data(), Np, NZ);
         e = hipMemcpy(c->tbQ, f.data(), f.size() * 4, hipMemcpyHostToDevice);
         if (e == hipSuccess && c->hop) {
             // image-side table of the rows Da >= 0 of the difference window:

@@ -87,10 +87,11 @@ struct ilt_ctx {
     __bf16 *tbhl;      // split-BF16 form: B3 in fragment order [Np/32][2][NZ/16][hi|lo][64][8]
     __bf16 *Yhl;       // split-BF16 form: window rows [n_sets][K][Np][hi|lo][KP]
     // G-window adjoint (ILT_FLAG_GWINDOW_ADJOINT): difference window Q = 2P - 1
-    int gwin, Q, FBQ, MIXQ, NZQ;
-    float *tbQ;        // window columns of the difference window, fragment order [Np/16][NZQ/16][64][4]
+    int gwin, Q;
+    float *tbQ;        // columns f >= 0 of the difference window (layout of P), fragment order [Np/16][NZ/16][64][4]
     float *arQ, *aiQ;  // [Q][Np]
     float2 *Ghat;      // [n_sets][Q][Q]
+    float2 *Ghalf;     // [n_sets][Q][P]: the columns f >= 0 of Ghat
     float *Ugw;        // [n_sets][Fpad][NC] U_k = H_k . S as real columns (Fpad = P^2 rounded up to 4, NC = 2K rounded up to 16)
     double2 *Vpart;    // [gw_groups][n_sets][P][P] partial sums of W over ranges of window rows
     int hop;           // ILT_FLAG_HOPKINS_FORWARD: the image through its difference-window spectrum

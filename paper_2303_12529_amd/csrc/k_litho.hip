@@ -45,17 +45,20 @@ __device__ __forceinline__ float wave_max(float v) {
 // in fragment order ([x/16][NZ/16][lane][e]): one 16-byte load per column
 // block gives a lane its B operands of those four steps.
 // --------------------------------------------------------------------------
+// PR: window rows (the twiddles ar, ai), P: window columns (the table tb);
+// PR = P but for the difference window of a real image, whose columns
+// Db >= 0 suffice (the others are conjugates, k_conj_fill).
 template <int FB, int MIX>
 __global__ __launch_bounds__(512) void k_spectrum_band(const float *__restrict__ src, size_t src_stride,
                                                        int src_is_phi, const float *__restrict__ tb,
                                                        const float *__restrict__ ar, const float *__restrict__ ai,
-                                                       int P, int N, int Np, float2 *__restrict__ Spart) {
+                                                       int PR, int P, int N, int Np, float2 *__restrict__ Spart) {
     // grid.z: independent images src + z src_stride, partials in their own range
     src += blockIdx.z * src_stride;
-    Spart += (size_t)blockIdx.z * gridDim.x * gridDim.y * P * P;
+    Spart += (size_t)blockIdx.z * gridDim.x * gridDim.y * PR * P;
     constexpr int NZ = 32 * FB + 16 * MIX;
     constexpr int NB = NZ / 16;
-    constexpr int PW = (NZ + 1) / 2 + 8;          // >= the window side of this layout
+    constexpr int PW = 2 * ILT_MAX_P - 1;          // >= every window's row count
     __shared__ float red[4][16][NZ + 1];
     __shared__ float twr[PW][17], twi[PW][17];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -122,7 +125,7 @@ __global__ __launch_bounds__(512) void k_spectrum_band(const float *__restrict__
     }
     __syncthreads();
     // the band's 16 twiddle columns of every window row, once per block
-    for (int e = threadIdx.x; e < P * 16; e += 512) {
+    for (int e = threadIdx.x; e < PR * 16; e += 512) {
         const int a = e / 16, r = e % 16;
         const int yy = min(y0 + r, N - 1);
         twr[a][r] = ar[(size_t)a * Np + yy];
@@ -130,12 +133,12 @@ __global__ __launch_bounds__(512) void k_spectrum_band(const float *__restrict__
     }
     __syncthreads();
     // band partial of S = A T1 (rows of the band beyond the image hold T1 = 0)
-    float2 *dst = Spart + ((size_t)blockIdx.x * gridDim.y + blockIdx.y) * P * P;
-    const int TA = (P + 15) / 16;
-    for (int t = wave; t < TA * TA; t += 8) {
-        const int ta = t / TA, tc = t - (t / TA) * TA;
+    float2 *dst = Spart + ((size_t)blockIdx.x * gridDim.y + blockIdx.y) * PR * P;
+    const int TA = (PR + 15) / 16, TC = (P + 15) / 16;
+    for (int t = wave; t < TA * TC; t += 8) {
+        const int ta = t / TC, tc = t - (t / TC) * TC;
         const int a = 16 * ta + l16, b = 16 * tc + l16;
-        const bool aok = a < P, bok = b < P;
+        const bool aok = a < PR, bok = b < P;
         const int cre = bok ? win_re(b, FB) : 0, cim = bok ? win_im(b, FB) : 0;
         f4 sre = f4{0.f, 0.f, 0.f, 0.f}, sim = f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
@@ -151,7 +154,7 @@ __global__ __launch_bounds__(512) void k_spectrum_band(const float *__restrict__
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const int ao = 16 * ta + 4 * lq + i;
-            if (ao < P && bok) dst[ao * P + b] = make_float2(sre[i], sim[i]);
+            if (ao < PR && bok) dst[ao * P + b] = make_float2(sre[i], sim[i]);
         }
     }
 }
@@ -1050,7 +1053,7 @@ __global__ __launch_bounds__(256) void k_gwindow_mm(const float2 *__restrict__ G
 // Pruned spectrum of src (or of [src <= 0]) on a window of side Pw with the
 // given column tables, summed into out [Pw][Pw].
 static hipError_t spectrum_to(ilt_ctx *c, const float *src, int src_is_phi, int FBw, int MIXw, const float *tbw,
-                              const float *arw, const float *aiw, int Pw, float2 *out, int nimg = 1,
+                              const float *arw, const float *aiw, int PRw, int Pw, float2 *out, int nimg = 1,
                               size_t src_stride = 0, int xs_nimg = 0) {
     // xs_nimg: the image count whose column split to use (0: nimg); the
     // clips of one sequence keep the single-image split, so that each
@@ -1059,7 +1062,7 @@ static hipError_t spectrum_to(ilt_ctx *c, const float *src, int src_is_phi, int 
     const int xs = spectrum_xsplit(c, xs_nimg > 0 ? xs_nimg : nimg);
 #define SPEC(FB_, MIX_)                                                                                    \
     k_spectrum_band<FB_, MIX_><<<dim3(nband, xs, nimg), 512, 0, c->stream>>>(src, src_stride, src_is_phi, tbw, \
-                                                                            arw, aiw, Pw, c->N, c->Np, c->Spart)
+                                                                            arw, aiw, PRw, Pw, c->N, c->Np, c->Spart)
     if (FBw == 0 && MIXw == 1) SPEC(0, 1);
     else if (FBw == 1 && MIXw == 0) SPEC(1, 0);
     else if (FBw == 1 && MIXw == 1) SPEC(1, 1);
@@ -1073,13 +1076,30 @@ static hipError_t spectrum_to(ilt_ctx *c, const float *src, int src_is_phi, int 
 #undef SPEC
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const int n = Pw * Pw;
+    const int n = PRw * Pw;
     k_psum<float2><<<dim3((n + 15) / 16, nimg), 1024, 0, c->stream>>>(c->Spart, nband * xs, n, out);
     return hipGetLastError();
 }
 
+// Spectrum of a real image on the (2P-1)^2 difference window from its
+// columns Db >= 0 (half [img][Q][P]): S(Da, Db) = conj(S(-Da, -Db)).
+__global__ __launch_bounds__(128) void k_conj_fill(const float2 *__restrict__ half, int P, float2 *__restrict__ full) {
+    const int Q = 2 * P - 1, r = blockIdx.x, cix = threadIdx.x;
+    if (cix >= Q) return;
+    const float2 *h = half + (size_t)blockIdx.y * Q * P;
+    float2 v;
+    if (cix >= P - 1) {
+        v = h[(size_t)r * P + (cix - (P - 1))];
+    } else {
+        v = h[(size_t)(Q - 1 - r) * P + (Q - 1 - cix - (P - 1))];
+        v.y = -v.y;
+    }
+    full[(size_t)blockIdx.y * Q * Q + (size_t)r * Q + cix] = v;
+}
+
 hipError_t launch_spectrum(ilt_ctx *c, const float *src, int src_is_phi) {
-    return spectrum_to(c, src, src_is_phi, c->FB, c->MIX, c->tbs, c->ar, c->ai, c->P, c->S, c->ncur, cs_npix(c), 1);
+    return spectrum_to(c, src, src_is_phi, c->FB, c->MIX, c->tbs, c->ar, c->ai, c->P, c->P, c->S, c->ncur,
+                       cs_npix(c), 1);
 }
 
 hipError_t launch_make_Y(ilt_ctx *c, int set_lo, int set_hi) {
@@ -1244,9 +1264,13 @@ hipError_t launch_adjoint_gwindow(ilt_ctx *c, const float *G, size_t g_set_strid
     const int Q = c->Q;
     // the spectra of every set's G in one launch (one pass over the tables)
     {
-        hipError_t e = spectrum_to(c, G + (size_t)set_lo * g_set_stride, 0, c->FBQ, c->MIXQ, c->tbQ, c->arQ, c->aiQ,
-                                   Q, c->Ghat + (size_t)set_lo * Q * Q, set_hi - set_lo, g_set_stride);
+        // the columns f >= 0 (the layout of P), then the others by symmetry
+        hipError_t e = spectrum_to(c, G + (size_t)set_lo * g_set_stride, 0, c->FB, c->MIX, c->tbQ, c->arQ, c->aiQ,
+                                   Q, c->P, c->Ghalf + (size_t)set_lo * Q * c->P, set_hi - set_lo, g_set_stride);
         if (e != hipSuccess) return e;
+        k_conj_fill<<<dim3(Q, set_hi - set_lo), 128, 0, c->stream>>>(c->Ghalf + (size_t)set_lo * Q * c->P, c->P,
+                                                                     c->Ghat + (size_t)set_lo * Q * Q);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     const int n = c->P * c->P, ns = set_hi - set_lo, NT = gwin_ntiles(c->K), NC = 16 * NT;
     const int Fpad = (n + 3) / 4 * 4;
