@@ -59,9 +59,11 @@ def _run_batch(ilt, batch, clips):
     return [(o[1].cpu().numpy(), o[3].cpu().numpy()) for o in outs], reps
 
 
-@pytest.mark.parametrize("prec,lanes", [("fp32", 3), ("fp32", 1), ("bf16x3", 2)])
+@pytest.mark.parametrize("prec,lanes", [("fp32", 3), ("fp32", 1), ("bf16x3", 2), ("tcc", 2)])
 def test_batch_equals_single_clip_solves(ilt, prec, lanes):
     precision = ilt.ILT_BF16X3 if prec == "bf16x3" else ilt.ILT_FP32
+    # "tcc": the TCC-form image with the G-window adjoint (one clip per context)
+    flags = ilt.ILT_FLAG_GWINDOW_ADJOINT | ilt.ILT_FLAG_HOPKINS_FORWARD if prec == "tcc" else 0
     H, w = build_optics(256, 8.0, 9, 8)
     sizes = (64, 128, 256)
     spec = [(256, 1, 7), (64, 2, 9), (128, 3, 6), (64, 4, 5), (256, 5, 8), (128, 6, 7)]
@@ -70,12 +72,12 @@ def test_batch_equals_single_clip_solves(ilt, prec, lanes):
         Z, pitch = _clip(N, seed)
         clips.append((Z, pitch, iters))
     _say("batch", prec, "lanes", lanes, [(c[0].shape[0], c[2]) for c in clips])
-    batch = ilt.Batch(H, w, sizes, max_clips=8, n_lanes=lanes, precision=precision)
+    batch = ilt.Batch(H, w, sizes, max_clips=8, n_lanes=lanes, precision=precision, flags=flags)
     got, reps = _run_batch(ilt, batch, clips)
     got2, reps2 = _run_batch(ilt, batch, clips)     # new buffers: a second capture
     for i, (Z, pitch, iters) in enumerate(clips):
         N = Z.shape[0]
-        ctx = ilt.Context(H, w, N, precision=precision)
+        ctx = ilt.Context(H, w, N, precision=precision, flags=flags)
         phi = torch.empty((N, N), dtype=torch.float32, device="cuda")
         tr = torch.zeros((iters, ilt.TRACE_W), dtype=torch.float64, device="cuda")
         rep = ctx.ilt_solve(torch.as_tensor(Z).cuda(), phi, _params(ilt, pitch, iters), trace=tr)
