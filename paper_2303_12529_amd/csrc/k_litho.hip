@@ -857,9 +857,10 @@ __global__ __launch_bounds__(256) void k_gwindow_U(const float2 *__restrict__ H,
 // D = (Da, Db) in [-(P-1), P-1]^2 (stored at D + P - 1), sw_k^2 = w_k / N^4,
 // so that I(r) = sum_D Ihat[D] exp(+2 pi i D.r / N) is the SOCS image.
 // Ihat[-D] = conj(Ihat[D]) (I is real), so only the rows Da >= 0 are formed
-// (the image uses them alone).  Block = (four rows Da, one per
-// wave; kernel k; set); lane l takes the columns Db = 2 l - (P-1) and the
-// next one.  U_k sits in LDS with P - 1 zero columns on each side, so that
+// (the image uses them alone).  Block = (row Da, kernel k, set); wave w
+// sums the window rows a in [w C, w C + C) (C = ceil(P / 4), so that every
+// wave has about the same work whatever Da), lane l the columns
+// Db = 2 l - (P-1) and the next one.  U_k sits in LDS with P - 1 zero columns on each side, so that
 // every shifted read is in range and the lanes run the same loop; the
 // unshifted factor is the same for all lanes (one broadcast read), and the
 // shifted one slides along the row in registers.  Each window row's
@@ -872,8 +873,9 @@ __global__ __launch_bounds__(256) void k_hopkins_ihat(const float2 *__restrict__
     constexpr int WMAX = 3 * ILT_MAX_P - 1;
     __shared__ float2 U[ILT_MAX_P * WMAX];
     const int Q = 2 * P - 1, PP = P * P, W = 3 * P - 1;   // one more zero column for the pair's second
-    const int lane = threadIdx.x & 63, da = 4 * blockIdx.x + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, da = blockIdx.x;
     const int k = blockIdx.y, srel = blockIdx.z, s = set_lo + srel;
+    const int C = (P + 3) / 4, a_lo = wave * C, a_hi = min(P - da, a_lo + C);
     for (int e = threadIdx.x; e < P * W; e += 256) U[e] = make_float2(0.f, 0.f);
     __syncthreads();
     const float2 *Hk = H + ((size_t)s * K + k) * PP;
@@ -883,13 +885,13 @@ __global__ __launch_bounds__(256) void k_hopkins_ihat(const float2 *__restrict__
         U[a * W + (P - 1) + b] = make_float2(h.x * sv.x - h.y * sv.y, h.x * sv.y + h.y * sv.x);
     }
     __syncthreads();
-    if (da >= P || 2 * lane >= Q) return;                   // no barrier follows
+    if (2 * lane >= Q) return;                              // no barrier follows
     const double w2 = (double)sw[(size_t)s * K + k] * (double)sw[(size_t)s * K + k];
     // column pair t0 = 2 lane, t0 + 1 (index Db + P - 1); the read of
     // U[a + Da][b + Db] is at column b + t0 of the padded row
     const int t0 = 2 * lane;
     double r0 = 0.0, i0 = 0.0, r1 = 0.0, i1 = 0.0;
-    for (int a = 0; a + da < P; ++a) {
+    for (int a = a_lo; a < a_hi; ++a) {
         const float2 *xs = &U[(a + da) * W + t0], *ys = &U[a * W + (P - 1)];
         float re0 = 0.f, im0 = 0.f, re1 = 0.f, im1 = 0.f;
         float2 x0 = xs[0];
@@ -904,7 +906,8 @@ __global__ __launch_bounds__(256) void k_hopkins_ihat(const float2 *__restrict__
         r0 += (double)re0; i0 += (double)im0;
         r1 += (double)re1; i1 += (double)im1;
     }
-    double2 *dst = part + (((size_t)srel * K + k) * P + da) * Q;
+    // (a wave whose range is empty writes zeros)
+    double2 *dst = part + ((((size_t)srel * K + k) * 4 + wave) * P + da) * Q;
     dst[t0] = make_double2(w2 * r0, w2 * i0);
     if (t0 + 1 < Q) dst[t0 + 1] = make_double2(w2 * r1, w2 * i1);
 }
@@ -1232,11 +1235,10 @@ hipError_t launch_gradient(ilt_ctx *c, float *g_out, double *maxpart) {
 hipError_t launch_hopkins_spectrum(ilt_ctx *c, int set_lo, int set_hi) {
     if (!c->hop) return hipErrorInvalidValue;
     const int P = c->P, Q = c->Q, ns = set_hi - set_lo;
-    k_hopkins_ihat<<<dim3((P + 3) / 4, c->K, ns), 256, 0, c->stream>>>(c->H, c->S, c->sw, P, c->K, set_lo,
-                                                                          c->Ipart);
+    k_hopkins_ihat<<<dim3(P, c->K, ns), 256, 0, c->stream>>>(c->H, c->S, c->sw, P, c->K, set_lo, c->Ipart);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    k_psum<double2><<<dim3((P * Q + 15) / 16, ns), 1024, 0, c->stream>>>(c->Ipart, c->K, P * Q, c->Ihat);
+    k_psum<double2><<<dim3((P * Q + 15) / 16, ns), 1024, 0, c->stream>>>(c->Ipart, 4 * c->K, P * Q, c->Ihat);
     return hipGetLastError();
 }
 
