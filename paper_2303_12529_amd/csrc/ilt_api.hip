@@ -425,7 +425,7 @@ extern "C" int ilt_create(ilt_ctx **out, const ilt_optics *o, int max_batch, voi
         if (c->hop) {
             ALLOC(tlQ, (size_t)KP * Np);
             ALLOC(Tq, (size_t)ns * KP * Np);
-            ALLOC(Ipart, (size_t)ns * K * 4 * P * Q);
+            ALLOC(Ipart, (size_t)ns * K * P * Q);
             ALLOC(Ihat, (size_t)ns * P * Q);
         }
         ALLOC(Ghat, (size_t)ns * Q * Q);

@@ -97,7 +97,7 @@ struct ilt_ctx {
     int hop;           // ILT_FLAG_HOPKINS_FORWARD: the image through its difference-window spectrum
     float *tlQ;        // [KP][Np] image-side table of the rows Da >= 0 of the difference window
     float *Tq;         // [n_sets][KP][Np] window rows of each set's image (rows >= 2P stay zero)
-    double2 *Ipart;    // [n_sets][K][4][P][Q] image spectra per kernel and range of window rows, rows Da >= 0
+    double2 *Ipart;    // [n_sets][K][P][Q] image spectra per kernel, rows Da >= 0
     float2 *Ihat;      // [n_sets][P][Q] image spectra, rows Da >= 0 of the difference window
     int gw_groups;     // ranges the window sum is split into (grid.y of the correlation GEMM)
 

@@ -857,25 +857,31 @@ __global__ __launch_bounds__(256) void k_gwindow_U(const float2 *__restrict__ H,
 // D = (Da, Db) in [-(P-1), P-1]^2 (stored at D + P - 1), sw_k^2 = w_k / N^4,
 // so that I(r) = sum_D Ihat[D] exp(+2 pi i D.r / N) is the SOCS image.
 // Ihat[-D] = conj(Ihat[D]) (I is real), so only the rows Da >= 0 are formed
-// (the image uses them alone).  Block = (row Da, kernel k, set); wave w
-// sums the window rows a in [w C, w C + C) (C = ceil(P / 4), so that every
-// wave has about the same work whatever Da), lane l the columns
-// Db = 2 l - (P-1) and the next one.  U_k sits in LDS with P - 1 zero columns on each side, so that
-// every shifted read is in range and the lanes run the same loop; the
-// unshifted factor is the same for all lanes (one broadcast read), and the
-// shifted one slides along the row in registers.  Each window row's
-// products (<= P terms) are summed in FP32, the rows in FP64; the kernels'
-// partials are summed in FP64 afterwards, in a fixed order.
+// (the image uses them alone).  Block = (pair of rows Da and P - 1 - Da,
+// kernel k, set), so that every block sums P + 1 window rows whatever Da
+// (the middle row of an odd P is alone).  The work items (Da, window row a,
+// column pair Db = 2 j - (P-1) and the next one) are spread over all 256
+// threads; U_k sits in LDS with P - 1 zero columns on each side, so that
+// every shifted read is in range and the items run the same loop, the
+// shifted factor sliding along the row in registers.  Each item's products
+// (P terms per column) are summed in FP32 and kept in registers until U
+// is read no more, then stored in U's place in LDS (29 KB per block, five
+// blocks per CU); the rows of a column are then summed in FP64 in the
+// order a = 0, 1, ..., and the kernels' partials in FP64 afterwards, in a
+// fixed order.
 // --------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_hopkins_ihat(const float2 *__restrict__ H, const float2 *__restrict__ S,
                                                       const float *__restrict__ sw, int P, int K, int set_lo,
                                                       double2 *__restrict__ part) {
-    constexpr int WMAX = 3 * ILT_MAX_P - 1;
-    __shared__ float2 U[ILT_MAX_P * WMAX];
-    const int Q = 2 * P - 1, PP = P * P, W = 3 * P - 1;   // one more zero column for the pair's second
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, da = blockIdx.x;
+    constexpr int WMAX = 3 * ILT_MAX_P - 1, NI = (ILT_MAX_P + 1) * ILT_MAX_P, NQ = (NI + 255) / 256;
+    static_assert(2 * NI <= ILT_MAX_P * WMAX, "the item sums must fit in the U storage");
+    __shared__ float4 L4[(ILT_MAX_P * WMAX + 1) / 2];
+    float2 *U = reinterpret_cast<float2 *>(L4);
+    float4 *R = L4;                                        // after U: [item row][pair], (re, im) of both columns
+    const int Q = 2 * P - 1, PP = P * P, W = 3 * P - 1;    // one more zero column for the pair's second
     const int k = blockIdx.y, srel = blockIdx.z, s = set_lo + srel;
-    const int C = (P + 3) / 4, a_lo = wave * C, a_hi = min(P - da, a_lo + C);
+    const int da0 = blockIdx.x, da1 = P - 1 - blockIdx.x;  // da1 >= da0 (grid.x = ceil(P / 2))
+    const int n0 = P - da0, n1 = da1 > da0 ? P - da1 : 0;  // window rows of each Da
     for (int e = threadIdx.x; e < P * W; e += 256) U[e] = make_float2(0.f, 0.f);
     __syncthreads();
     const float2 *Hk = H + ((size_t)s * K + k) * PP;
@@ -885,13 +891,16 @@ __global__ __launch_bounds__(256) void k_hopkins_ihat(const float2 *__restrict__
         U[a * W + (P - 1) + b] = make_float2(h.x * sv.x - h.y * sv.y, h.x * sv.y + h.y * sv.x);
     }
     __syncthreads();
-    if (2 * lane >= Q) return;                              // no barrier follows
-    const double w2 = (double)sw[(size_t)s * K + k] * (double)sw[(size_t)s * K + k];
-    // column pair t0 = 2 lane, t0 + 1 (index Db + P - 1); the read of
+    // item i = r P + j: r < n0 is window row a = r of Da = da0, else a = r - n0
+    // of da1; columns t0 = 2 j, t0 + 1 (index Db + P - 1), whose read of
     // U[a + Da][b + Db] is at column b + t0 of the padded row
-    const int t0 = 2 * lane;
-    double r0 = 0.0, i0 = 0.0, r1 = 0.0, i1 = 0.0;
-    for (int a = a_lo; a < a_hi; ++a) {
+    float4 acc[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        const int i = (int)threadIdx.x + 256 * q;
+        if (i >= (n0 + n1) * P) break;
+        const int r = i / P, j = i - (i / P) * P;
+        const int a = r < n0 ? r : r - n0, da = r < n0 ? da0 : da1, t0 = 2 * j;
         const float2 *xs = &U[(a + da) * W + t0], *ys = &U[a * W + (P - 1)];
         float re0 = 0.f, im0 = 0.f, re1 = 0.f, im1 = 0.f;
         float2 x0 = xs[0];
@@ -903,13 +912,26 @@ __global__ __launch_bounds__(256) void k_hopkins_ihat(const float2 *__restrict__
             im1 = fmaf(x1.y, y.x, fmaf(-x1.x, y.y, im1));
             x0 = x1;
         }
-        r0 += (double)re0; i0 += (double)im0;
-        r1 += (double)re1; i1 += (double)im1;
+        acc[q] = make_float4(re0, im0, re1, im1);
     }
-    // (a wave whose range is empty writes zeros)
-    double2 *dst = part + ((((size_t)srel * K + k) * 4 + wave) * P + da) * Q;
-    dst[t0] = make_double2(w2 * r0, w2 * i0);
-    if (t0 + 1 < Q) dst[t0 + 1] = make_double2(w2 * r1, w2 * i1);
+    __syncthreads();                                       // U is read no more
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        const int i = (int)threadIdx.x + 256 * q;
+        if (i < (n0 + n1) * P) R[i] = acc[q];
+    }
+    __syncthreads();
+    const int t = threadIdx.x < Q ? threadIdx.x : threadIdx.x - Q, half = threadIdx.x < Q ? 0 : 1;
+    if (threadIdx.x >= 2 * Q || (half && n1 == 0)) return;
+    const int r0 = half ? n0 : 0, nr = half ? n1 : n0, j = t >> 1;
+    double re = 0.0, im = 0.0;
+    for (int a = 0; a < nr; ++a) {
+        const float4 v = R[(r0 + a) * P + j];
+        re += (double)(t & 1 ? v.z : v.x);
+        im += (double)(t & 1 ? v.w : v.y);
+    }
+    const double w2 = (double)sw[(size_t)s * K + k] * (double)sw[(size_t)s * K + k];
+    part[(((size_t)srel * K + k) * P + (half ? da1 : da0)) * Q + t] = make_double2(w2 * re, w2 * im);
 }
 
 // Block-wide copy global -> LDS with UNR independent loads in flight per
@@ -1235,10 +1257,10 @@ hipError_t launch_gradient(ilt_ctx *c, float *g_out, double *maxpart) {
 hipError_t launch_hopkins_spectrum(ilt_ctx *c, int set_lo, int set_hi) {
     if (!c->hop) return hipErrorInvalidValue;
     const int P = c->P, Q = c->Q, ns = set_hi - set_lo;
-    k_hopkins_ihat<<<dim3(P, c->K, ns), 256, 0, c->stream>>>(c->H, c->S, c->sw, P, c->K, set_lo, c->Ipart);
+    k_hopkins_ihat<<<dim3((P + 1) / 2, c->K, ns), 256, 0, c->stream>>>(c->H, c->S, c->sw, P, c->K, set_lo, c->Ipart);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    k_psum<double2><<<dim3((P * Q + 15) / 16, ns), 1024, 0, c->stream>>>(c->Ipart, 4 * c->K, P * Q, c->Ihat);
+    k_psum<double2><<<dim3((P * Q + 15) / 16, ns), 1024, 0, c->stream>>>(c->Ipart, c->K, P * Q, c->Ihat);
     return hipGetLastError();
 }
 
